@@ -1,0 +1,12 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This package only *produces inputs*: surface meshes, material/incidence
+settings and seeded random vectors.  It holds none of the discretisation's
+arithmetic (no quadrature, no kernels, no frames), so the oracle and the HIP
+path can both consume it without sharing any computation.
+"""
+from .meshes import icosphere_p2, mesh_counts
+from .configs import CONFIGS, get_config, planewaves, random_directions
+
+__all__ = ["icosphere_p2", "mesh_counts", "CONFIGS", "get_config",
+           "planewaves", "random_directions"]

@@ -1,0 +1,101 @@
+"""Closed P2 (6-node) triangle meshes of spheres, spheroids and ellipsoids.
+
+Recipe (used for every workload):
+  1. the regular icosahedron with vertices (0,+-1,+-phi), (+-1,+-phi,0),
+     (+-phi,0,+-1), phi = (1+sqrt 5)/2, projected to the unit sphere;
+  2. L rounds of 1->4 midpoint subdivision, new vertices projected to the
+     unit sphere after each round (F = 20 * 4**L triangles);
+  3. one P2 mid-edge node per edge at normalize((x_p + x_q)/2);
+  4. every triangle oriented counter-clockwise seen from outside;
+  5. all nodes scaled by diag(a, b, c) for spheroids and ellipsoids.
+
+Node order is the generation order (vertices first, then edge nodes); it is
+deliberately *not* spatially sorted, so that the library's own reordering is
+exercised.  Local node order of a triangle is (v0, v1, v2, m01, m12, m20).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def _icosahedron():
+    p = (1.0 + math.sqrt(5.0)) / 2.0
+    v = np.array([
+        [-1, p, 0], [1, p, 0], [-1, -p, 0], [1, -p, 0],
+        [0, -1, p], [0, 1, p], [0, -1, -p], [0, 1, -p],
+        [p, 0, -1], [p, 0, 1], [-p, 0, -1], [-p, 0, 1],
+    ], dtype=np.float64)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    f = np.array([
+        [0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
+        [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
+        [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+        [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1],
+    ], dtype=np.int64)
+    return v, f
+
+
+def _orient_outward(v, f):
+    a, b, c = v[f[:, 0]], v[f[:, 1]], v[f[:, 2]]
+    s = np.einsum("ij,ij->i", np.cross(b - a, c - a), a + b + c)
+    f = f.copy()
+    bad = s < 0
+    f[bad] = f[bad][:, [0, 2, 1]]
+    return f
+
+
+def _subdivide(v, f):
+    verts = [row for row in v]
+    cache = {}
+
+    def mid(i, j):
+        key = (min(i, j), max(i, j))
+        if key not in cache:
+            m = verts[i] + verts[j]
+            verts.append(m / np.linalg.norm(m))
+            cache[key] = len(verts) - 1
+        return cache[key]
+
+    out = []
+    for a, b, c in f:
+        ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+        out += [[a, ab, ca], [ab, b, bc], [ca, bc, c], [ab, bc, ca]]
+    return np.array(verts), np.array(out, dtype=np.int64)
+
+
+def mesh_counts(n_tris: int):
+    """(n_nodes, n_unknowns) of a closed P2 surface with n_tris triangles."""
+    n_nodes = 2 * n_tris + 2
+    return n_nodes, 4 * n_nodes
+
+
+def icosphere_p2(n_tris: int, axes=(1.0, 1.0, 1.0)):
+    """Return (xyz[n_nodes,3] float64, tri6[n_tris,6] int64)."""
+    levels = 0
+    while 20 * 4 ** levels < n_tris:
+        levels += 1
+    if 20 * 4 ** levels != n_tris:
+        raise ValueError(f"n_tris must be 20*4**L, got {n_tris}")
+    v, f = _icosahedron()
+    for _ in range(levels):
+        v, f = _subdivide(v, f)
+    f = _orient_outward(v, f)
+    nv = v.shape[0]
+    edge_id = {}
+    mids = []
+    tri6 = np.zeros((f.shape[0], 6), dtype=np.int64)
+    for t, (a, b, c) in enumerate(f):
+        tri6[t, :3] = (a, b, c)
+        for k, (p, q) in enumerate(((a, b), (b, c), (c, a))):
+            key = (min(p, q), max(p, q))
+            if key not in edge_id:
+                m = v[p] + v[q]
+                mids.append(m / np.linalg.norm(m))
+                edge_id[key] = nv + len(mids) - 1
+            tri6[t, 3 + k] = edge_id[key]
+    xyz = np.concatenate([v, np.array(mids)], axis=0)
+    xyz = xyz * np.asarray(axes, dtype=np.float64)[None, :]
+    assert xyz.shape[0] == mesh_counts(n_tris)[0]
+    return np.ascontiguousarray(xyz), np.ascontiguousarray(tri6)
