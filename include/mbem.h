@@ -1,0 +1,229 @@
+/*
+ * mbem -- MI355X (gfx950) library for the nodal P2 Mueller boundary-element
+ * method of Y. Luo, "A High-Order Nodal Galerkin Formulation for the Mueller
+ * Equation: Bypassing Divergence Conformity via Kernel Cancellation"
+ * (arXiv 2604.21181).
+ *
+ * The library fills the dense complex Galerkin matrix Z of the global
+ * system (Sec. 4.3, eq. global_system)
+ *
+ *        [ (i/w) K1             (eps_i+eps_a)/2 M + K2^eps ] [ c_j  ]   [ b_E ]
+ *        [ (mu_i+mu_a)/2 M + K2^mu       -(i/w) K1         ] [ c_jm ] = [ b_H ]
+ *
+ * over every pair of curved P2 triangles (regular pairs by a 7-point rule,
+ * coincident / common-edge / common-vertex pairs by Sauter-Schwab
+ * quadrature, Sec. 4.1-4.2 and 6.1), applies it, and solves it with GMRES
+ * right-preconditioned by the Morton block-Jacobi matrix (Sec. 5).
+ *
+ * Conventions
+ *  - Every function returns MBEM_OK (0) or a negative mbem_status; the
+ *    message of the last failure on the calling thread is mbem_last_error().
+ *    No C++ exception crosses this interface.
+ *  - Units: exterior medium vacuum, eps_a = mu_a = 1, eta_a = 1,
+ *    omega = k_a = k0; k_i = k0 sqrt(eps_r mu_r) with Im k_i >= 0.
+ *  - Ownership: the library owns the handles and everything they allocate;
+ *    the caller owns every pointer argument and the library never frees
+ *    caller memory.  "device" pointers are HIP device memory on the
+ *    context's device (e.g. torch tensor data pointers), "host" pointers are
+ *    ordinary host memory.
+ *  - Streams: all device work is enqueued on the context's stream (borrowed,
+ *    never destroyed by the library).  Functions that write host outputs
+ *    synchronise that stream before returning.
+ *  - Ordering: the library renumbers nodes and triangles in Morton (Z-order)
+ *    order (Sec. 5).  All device vectors (right-hand sides, solutions) are
+ *    in that order: x = [c_j ; c_jm], each block of length 2 n_nodes with
+ *    index 2 m + alpha, m the Morton position of the node and alpha in {0,1}
+ *    selecting the tangent t_1 or t_2.  mbem_mesh_permutation() maps the
+ *    caller's numbering to Morton positions.  N = 4 n_nodes unknowns.
+ *  - Complex numbers are interleaved (re, im) pairs: mbem_c128 is two
+ *    doubles (C99 double _Complex, torch.complex128); "c64" buffers are two
+ *    floats (torch.complex64).
+ */
+#ifndef MBEM_H
+#define MBEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } mbem_c128;
+
+typedef enum {
+    MBEM_OK = 0,
+    MBEM_EINVAL = -1,     /* bad argument, size or handle                 */
+    MBEM_ENOMEM = -2,     /* device or host allocation failed             */
+    MBEM_EDEVICE = -3,    /* HIP runtime error                             */
+    MBEM_ENOCONV = -4,    /* iteration limit reached; outputs still valid  */
+    MBEM_ESINGULAR = -5,  /* zero pivot in a preconditioner block          */
+    MBEM_EMESH = -6       /* mesh is not a closed, oriented P2 2-manifold  */
+} mbem_status;
+
+typedef enum {
+    MBEM_FP64 = 0,   /* all pairs in FP64, Z stored complex128             */
+    MBEM_MIXED = 1   /* far regular pairs in FP32, near and singular pairs
+                        in FP64, Z stored complex64; FP64 Arnoldi and an
+                        FP64-accumulated refinement residual              */
+} mbem_precision;
+
+typedef struct mbem_ctx mbem_ctx;    /* device ordinal + borrowed stream      */
+typedef struct mbem_mesh mbem_mesh;  /* Morton-ordered mesh, device tables    */
+typedef struct mbem_op mbem_op;      /* filled operator + preconditioner      */
+
+typedef struct {
+    double k0;                  /* vacuum wavenumber = omega                 */
+    double eps_r_re, eps_r_im;  /* interior relative permittivity            */
+    double mu_r_re, mu_r_im;    /* interior relative permeability            */
+    int32_t ssq_order;          /* Gauss points per dimension of the
+                                   Sauter-Schwab rule (0 -> 4, Sec. 6.1)     */
+    int32_t precision;          /* mbem_precision                            */
+    double near_radius;         /* MIXED: element pairs whose gap is below
+                                   this are computed in FP64; <= 0 selects
+                                   1.89 / sqrt|k_a^2 - k_i^2|                */
+} mbem_params;
+
+typedef struct {
+    double tol;          /* relative residual target |b - Z x| / |b|        */
+    int32_t maxit;       /* GMRES iteration limit (Krylov dimension)         */
+    int32_t max_refine;  /* MIXED: outer refinement sweeps (0 -> 8)          */
+    double inner_tol;    /* MIXED: inner GMRES tolerance (0 -> 1e-4)          */
+} mbem_solve_opts;
+
+typedef struct {
+    int32_t iters;        /* GMRES iterations (sum over refinement sweeps)   */
+    int32_t outer_iters;  /* refinement sweeps (MIXED), 1 otherwise          */
+    double rel_resid;     /* final |b - Z x| / |b| (FP64 accumulation)       */
+    double t_fill_ms;     /* geometry tables + all pair classes + mass       */
+    double t_setup_ms;    /* preconditioner gather + LU + inverse             */
+    double t_solve_ms;    /* GMRES wall time                                 */
+    int64_t n_near_pairs; /* MIXED: regular pairs computed in FP64           */
+    /* device time of single launches, from HIP events on the context stream */
+    double t_geom_ms;     /* nodal frames + quadrature-point tables           */
+    double t_regular_ms;  /* regular-pair kernel (FP64 path: all regular
+                             pairs; MIXED: the FP32 far-pair launch)         */
+    double t_near_ms;     /* MIXED: the FP64 near-pair launch                 */
+    double t_ssq_ms;      /* Sauter-Schwab kernel                            */
+    double t_mass_ms;     /* mass matrix                                     */
+    double t_matvec_ms;   /* solve: sum of dense GEMV kernel times            */
+    int32_t n_matvec;     /* solve: number of GEMV launches                   */
+    int64_t n_regular_pairs; /* regular element pairs (all launches)          */
+} mbem_stats;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Bind a context to HIP device `device` and the caller's stream
+ * (hipStream_t passed as void*, NULL = the null stream).                    */
+int mbem_ctx_create(int device, void *hip_stream, mbem_ctx **out);
+void mbem_ctx_destroy(mbem_ctx *ctx);
+
+/* ---- mesh (Sec. 3 and 5) ------------------------------------------------ */
+
+/* Host preprocessing: validates that the triangles form a closed, oriented
+ * P2 2-manifold (every edge shared by exactly two triangles with opposite
+ * orientation and the same mid-edge node), applies the double Morton
+ * permutation (nodes, then triangles by vertex centroid; Sec. 5), builds
+ * the singular-pair lists (coincident, common edge, common vertex;
+ * Sec. 4.2) and copies the mesh to the device.
+ *   xyz   host [n_nodes*3] float64, node coordinates
+ *   tri6  host [n_tris*6] int64, nodes (v0 v1 v2 m01 m12 m20), counter-
+ *         clockwise seen from outside
+ * Errors: MBEM_EINVAL (sizes, indices), MBEM_EMESH (topology).            */
+int mbem_mesh_create(mbem_ctx *ctx, const double *xyz, int64_t n_nodes,
+                     const int64_t *tri6, int64_t n_tris, mbem_mesh **out);
+void mbem_mesh_destroy(mbem_mesh *mesh);
+
+/* host outputs: node_order[m] = caller's node at Morton position m,
+ * tri_order[t] = caller's triangle at Morton position t (either may be
+ * NULL).                                                                    */
+int mbem_mesh_permutation(const mbem_mesh *mesh, int64_t *node_order,
+                          int64_t *tri_order);
+
+/* host output info[8] = {n_nodes, n_tris, n_unknowns, coincident pairs,
+ * common-edge ordered pairs, common-vertex ordered pairs, 0, 0}.            */
+int mbem_mesh_info(const mbem_mesh *mesh, int64_t *info);
+
+/* The Morton permutation alone, on the host, without a device (Sec. 5):
+ * keys from the bounding box's largest side, 21 bits per axis, x in bit 3b,
+ * y in 3b+1, z in 3b+2; stable sort.  Same outputs as
+ * mbem_mesh_permutation().                                                  */
+int mbem_morton_order(const double *xyz, int64_t n_nodes, const int64_t *tri6,
+                      int64_t n_tris, int64_t *node_order, int64_t *tri_order);
+
+/* ---- fill (Sec. 4, 6.1) ---------------------------------------------------- */
+
+/* Geometry tables (metric-weighted nodal normals and frames, Sec. 3;
+ * quadrature-point frames), every element pair (K1, K2^eps, K2^mu; eqs.
+ * K1_matrix_entry, K2_matrix_entry) and the mass matrix (eq. mass_matrix).
+ * stats may be NULL; t_fill_ms and n_near_pairs are written.               */
+int mbem_fill(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *params,
+              mbem_op **out, mbem_stats *stats);
+void mbem_op_destroy(mbem_op *op);
+
+/* Copy the operator blocks K1, K2^eps, K2^mu ((2 n_nodes)^2 each,
+ * row-major, Morton order) to device buffers of complex128.  Any pointer
+ * may be NULL.                                                              */
+int mbem_op_export_blocks(mbem_ctx *ctx, const mbem_op *op, mbem_c128 *K1,
+                          mbem_c128 *K2e, mbem_c128 *K2m);
+
+/* Dense Z (N x N, row-major, Morton order) into a device complex128 buffer. */
+int mbem_op_export_dense(mbem_ctx *ctx, const mbem_op *op, mbem_c128 *Z);
+
+/* y = Z x for nrhs column-major device vectors of length N (complex128).   */
+int mbem_matvec(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *x,
+                int32_t nrhs, mbem_c128 *y);
+
+/* ---- preconditioner (Sec. 5, eq. precond_block) --------------------------- */
+
+/* Morton block-Jacobi: clusters of `block` consecutive indices of one
+ * current's vector; each block is the 2 block x 2 block restriction of Z,
+ * LU-factorised with partial pivoting and inverted.  MBEM_ESINGULAR on a
+ * zero pivot.  block <= 0 removes the preconditioner.                      */
+int mbem_precond_setup(mbem_ctx *ctx, mbem_op *op, int32_t block,
+                       mbem_stats *stats);
+
+/* z = P^-1 v (device, length N, complex128).                               */
+int mbem_precond_apply(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *v,
+                       mbem_c128 *z);
+
+/* ---- excitation, solve, post-processing ------------------------------------ */
+
+/* b = [b_E ; b_H] (eqs. rhs_E, rhs_H) for plane waves
+ * E = pol e^{i k_a khat.x}, H = khat x E.
+ *   khat  host [nrhs*3] unit directions;  pol host [nrhs*3] complex
+ *   b     device [N*nrhs] complex128, column-major                         */
+int mbem_rhs_planewave(mbem_ctx *ctx, const mbem_mesh *mesh,
+                       const mbem_params *params, const double *khat,
+                       const mbem_c128 *pol, int32_t nrhs, mbem_c128 *b);
+
+/* Solve Z x = b by GMRES (x0 = 0, classical Gram-Schmidt twice in FP64,
+ * right-preconditioned by the Morton block-Jacobi matrix if set up).  For a
+ * MIXED operator the inner GMRES applies the complex64 matrix and an outer
+ * FP64-accumulated residual refines x.  b, x: device [N*nrhs] complex128.
+ * MBEM_ENOCONV if the tolerance was not reached (x holds the last iterate). */
+int mbem_solve(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs,
+               const mbem_solve_opts *opts, mbem_c128 *x, mbem_stats *stats);
+
+/* Far-field amplitude F(r) of the solution currents, E_s ~ F e^{ik r}/r:
+ * F = (i k_a / 4 pi) r x sum_qp w J e^{-i k_a r.y} (eta_a j x r - j_m).
+ *   x device [N*nrhs]; rhat device [ndir*3]; F device [nrhs][ndir][3]
+ *   complex128.                                                            */
+int mbem_farfield(mbem_ctx *ctx, const mbem_mesh *mesh,
+                  const mbem_params *params, const mbem_c128 *x, int32_t nrhs,
+                  const double *rhat, int64_t ndir, mbem_c128 *F);
+
+/* Cross sections of one solution for unit incidence (khat, pol host [3]):
+ * out[0] = C_ext (optical theorem), out[1] = C_sca (Gauss-Legendre in
+ * cos theta x trapezoid in phi, ntheta x 2 ntheta directions),
+ * out[2] = C_abs = Re int n.(j_m x conj j).  out host [3].                 */
+int mbem_cross_sections(mbem_ctx *ctx, const mbem_mesh *mesh,
+                        const mbem_params *params, const mbem_c128 *x,
+                        const double *khat, const mbem_c128 *pol,
+                        int32_t ntheta, double *out);
+
+const char *mbem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBEM_H */

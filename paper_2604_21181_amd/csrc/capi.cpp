@@ -1,0 +1,542 @@
+// The C ABI of include/mbem.h: handle management, orchestration of the
+// device kernels, and the GMRES driver.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+
+#include "mbem_internal.h"
+
+namespace mbem {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+template <typename T>
+static int dalloc(T **p, size_t n) {
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * n);
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+        return MBEM_ENOMEM;
+    }
+    return MBEM_OK;
+}
+
+template <typename T>
+static int upload(T **p, const std::vector<T> &v, hipStream_t s) {
+    MBEM_TRY(dalloc(p, v.size()));
+    if (!v.empty()) MBEM_HIP(hipMemcpyAsync(*p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+    return MBEM_OK;
+}
+
+static void dfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+// Elapsed milliseconds between two events recorded on the stream.
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer() { (void)hipEventCreate(&a); (void)hipEventCreate(&b); }
+    ~Timer() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    void start(hipStream_t s) { (void)hipEventRecord(a, s); }
+    double stop(hipStream_t s) {
+        float ms = 0.f;
+        (void)hipEventRecord(b, s);
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&ms, a, b);
+        return ms;
+    }
+};
+
+static int set_device(const mbem_ctx *ctx) {
+    if (!ctx) { set_error("null context"); return MBEM_EINVAL; }
+    MBEM_HIP(hipSetDevice(ctx->device));
+    return MBEM_OK;
+}
+
+static void mesh_free_device(mbem_mesh *m) {
+    void *ps[] = {m->d_xyz, m->d_tri, m->d_inc_ptr, m->d_inc, m->d_spairs, m->d_frames,
+                  m->d_qp, m->d_qp32, m->d_elem, m->d_mptr, m->d_mcol, m->d_mslot};
+    for (void *p : ps) dfree(p);
+}
+
+static void op_free_device(mbem_op *op) {
+    for (int o = 0; o < 3; ++o) dfree(op->K[o]);
+    dfree(op->d_mval);
+    dfree(op->d_minv);
+    dfree(op->d_lu);
+    dfree(op->d_work);
+}
+
+// ---------------------------------------------------------------- GMRES --
+struct Gmres {
+    const mbem_op *op;
+    hipStream_t s;
+    int64_t N;
+    int m;              // Krylov dimension limit
+    double2 *V, *w, *z, *tmp, *hdev;
+    double *ndev;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // bracket every matvec launch
+    double t_matvec = 0.0;
+    int n_matvec = 0;
+    ~Gmres() {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+    int timed_matvec(const double2 *x, double2 *y) {
+        (void)hipEventRecord(ev0, s);
+        MBEM_TRY(matvec_run(op, x, y, tmp, s));
+        (void)hipEventRecord(ev1, s);
+        return MBEM_OK;
+    }
+    void collect() {   // after a synchronisation of the stream
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev0, ev1) == hipSuccess) { t_matvec += t; ++n_matvec; }
+    }
+};
+
+static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
+    g.op = op;
+    g.s = s;
+    g.N = 2 * op->n2;
+    g.m = maxit;
+    const size_t need = (size_t)(maxit + 1) * g.N + 2 * g.N + 2 * op->n2 + 4 * op->n2 + 2 * (maxit + 2) + 1;
+    if (op->work_elems < need) {
+        mbem_op *mop = const_cast<mbem_op *>(op);
+        dfree(mop->d_work);
+        mop->d_work = nullptr;
+        mop->work_elems = 0;
+        MBEM_TRY(dalloc(&mop->d_work, need));
+        mop->work_elems = need;
+    }
+    g.V = op->d_work;
+    g.w = g.V + (size_t)(maxit + 1) * g.N;
+    g.z = g.w + g.N;
+    g.tmp = g.z + g.N;                 // 4 n2 for the matvec partials
+    g.hdev = g.tmp + 4 * op->n2;       // 2 (maxit + 2)
+    g.ndev = (double *)(g.hdev + 2 * (maxit + 2));
+    if (!g.ev0) MBEM_HIP(hipEventCreate(&g.ev0));
+    if (!g.ev1) MBEM_HIP(hipEventCreate(&g.ev1));
+    return MBEM_OK;
+}
+
+static inline std::complex<double> C(double2 v) { return {v.x, v.y}; }
+
+// Right-preconditioned GMRES on Z P^-1, x0 = 0, CGS2 Arnoldi in FP64.
+// Solves Z x = b to |r_k| <= tol |b| (Arnoldi estimate).  x, b device.
+static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *iters,
+                       double *est) {
+    const hipStream_t s = g.s;
+    const int64_t N = g.N;
+    MBEM_TRY(vec_norm2(b, N, g.ndev, s));
+    double beta = 0;
+    MBEM_HIP(hipMemcpyAsync(&beta, g.ndev, sizeof(double), hipMemcpyDeviceToHost, s));
+    MBEM_HIP(hipStreamSynchronize(s));
+    if (!(beta > 0)) {
+        MBEM_HIP(hipMemsetAsync(x, 0, sizeof(double2) * N, s));
+        *iters = 0;
+        *est = 0;
+        return MBEM_OK;
+    }
+    MBEM_TRY(vec_scale_copy(g.V, b, double2{1.0 / beta, 0.0}, N, s));
+    const int m = g.m;
+    std::vector<std::complex<double>> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1);
+    std::vector<double2> hbuf(2 * (m + 1) + 1);
+    gv[0] = beta;
+    int k = 0;
+    double res = 1.0;
+    bool conv = false;
+    for (k = 0; k < m; ++k) {
+        double2 *vk = g.V + (size_t)k * N;
+        MBEM_TRY(mbj_apply_run(g.op, vk, g.z, s));
+        MBEM_TRY(g.timed_matvec(g.z, g.w));
+        MBEM_TRY(vec_dots(g.V, N, k + 1, g.w, N, g.hdev, s));
+        MBEM_TRY(vec_update(g.w, g.V, N, k + 1, g.hdev, N, s));
+        MBEM_TRY(vec_dots(g.V, N, k + 1, g.w, N, g.hdev + (k + 1), s));
+        MBEM_TRY(vec_update(g.w, g.V, N, k + 1, g.hdev + (k + 1), N, s));
+        MBEM_TRY(vec_norm2(g.w, N, g.ndev, s));
+        MBEM_HIP(hipMemcpyAsync(hbuf.data(), g.hdev, sizeof(double2) * 2 * (k + 1), hipMemcpyDeviceToHost, s));
+        double hn = 0;
+        MBEM_HIP(hipMemcpyAsync(&hn, g.ndev, sizeof(double), hipMemcpyDeviceToHost, s));
+        MBEM_HIP(hipStreamSynchronize(s));
+        g.collect();
+        auto Hc = [&](int i) -> std::complex<double> & { return H[(size_t)i * m + k]; };
+        for (int i = 0; i <= k; ++i) Hc(i) = C(hbuf[i]) + C(hbuf[k + 1 + i]);
+        Hc(k + 1) = hn;
+        if (hn > 0) MBEM_TRY(vec_scale_copy(g.V + (size_t)(k + 1) * N, g.w, double2{1.0 / hn, 0.0}, N, s));
+        for (int i = 0; i < k; ++i) {
+            const std::complex<double> t = cs[i] * Hc(i) + sn[i] * Hc(i + 1);
+            Hc(i + 1) = -std::conj(sn[i]) * Hc(i) + cs[i] * Hc(i + 1);
+            Hc(i) = t;
+        }
+        const std::complex<double> a = Hc(k), bb = Hc(k + 1);
+        const double r = std::hypot(std::abs(a), std::abs(bb));
+        if (r == 0) { cs[k] = 1; sn[k] = 0; }
+        else if (std::abs(a) == 0) { cs[k] = 0; sn[k] = std::conj(bb) / std::abs(bb); }
+        else { cs[k] = std::abs(a) / r; sn[k] = (a / std::abs(a)) * std::conj(bb) / r; }
+        Hc(k) = cs[k] * a + sn[k] * bb;
+        Hc(k + 1) = 0;
+        gv[k + 1] = -std::conj(sn[k]) * gv[k];
+        gv[k] = cs[k] * gv[k];
+        res = std::abs(gv[k + 1]) / beta;
+        if (res <= tol || hn == 0) { ++k; conv = true; break; }
+    }
+    // back substitution H y = g
+    std::vector<std::complex<double>> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+        std::complex<double> t = gv[i];
+        for (int j = i + 1; j < k; ++j) t -= H[(size_t)i * m + j] * y[j];
+        y[i] = t / H[(size_t)i * m + i];
+    }
+    std::vector<double2> yd(k);
+    for (int i = 0; i < k; ++i) yd[i] = {y[i].real(), y[i].imag()};
+    MBEM_HIP(hipMemcpyAsync(g.hdev, yd.data(), sizeof(double2) * k, hipMemcpyHostToDevice, s));
+    MBEM_TRY(vec_combine(g.w, g.V, N, k, g.hdev, N, s));
+    MBEM_TRY(mbj_apply_run(g.op, g.w, x, s));
+    MBEM_HIP(hipStreamSynchronize(s));
+    *iters = k;
+    *est = res;
+    return conv ? MBEM_OK : MBEM_ENOCONV;
+}
+
+}  // namespace mbem
+
+using namespace mbem;
+
+extern "C" {
+
+const char *mbem_last_error(void) { return g_err.c_str(); }
+
+int mbem_ctx_create(int device, void *hip_stream, mbem_ctx **out) {
+    if (!out) { set_error("null output"); return MBEM_EINVAL; }
+    int n = 0;
+    MBEM_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) { set_error("device ordinal out of range"); return MBEM_EINVAL; }
+    mbem_ctx *c = new (std::nothrow) mbem_ctx;
+    if (!c) { set_error("host allocation"); return MBEM_ENOMEM; }
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return MBEM_OK;
+}
+
+void mbem_ctx_destroy(mbem_ctx *ctx) { delete ctx; }
+
+int mbem_morton_order(const double *xyz, int64_t n_nodes, const int64_t *tri6, int64_t n_tris,
+                      int64_t *node_order, int64_t *tri_order) {
+    if (!xyz || !tri6 || n_nodes <= 0 || n_tris <= 0) { set_error("bad arguments"); return MBEM_EINVAL; }
+    for (int64_t i = 0; i < 6 * n_tris; ++i)
+        if (tri6[i] < 0 || tri6[i] >= n_nodes) { set_error("node index out of range"); return MBEM_EINVAL; }
+    std::vector<int64_t> no, to;
+    MBEM_TRY(morton_order_host(xyz, n_nodes, tri6, n_tris, no, to));
+    if (node_order) std::copy(no.begin(), no.end(), node_order);
+    if (tri_order) std::copy(to.begin(), to.end(), tri_order);
+    return MBEM_OK;
+}
+
+int mbem_mesh_create(mbem_ctx *ctx, const double *xyz, int64_t n_nodes, const int64_t *tri6,
+                     int64_t n_tris, mbem_mesh **out) {
+    if (!out || !xyz || !tri6) { set_error("null argument"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    mbem_mesh *m = new (std::nothrow) mbem_mesh;
+    if (!m) { set_error("host allocation"); return MBEM_ENOMEM; }
+    m->ctx = ctx;
+    int st = build_mesh_host(xyz, n_nodes, tri6, n_tris, m);
+    MeshTables T;
+    if (st == MBEM_OK) st = build_tables(m, T);
+    const hipStream_t s = ctx->stream;
+    auto fail = [&](int code) { mesh_free_device(m); delete m; return code; };
+    if (st != MBEM_OK) return fail(st);
+    m->n_spairs = (int64_t)T.spairs.size() / 4;
+    for (int c = 0; c < 4; ++c) m->n_single[c] = T.n_single[c];
+    m->m_ptr = T.m_ptr;
+    m->m_col = T.m_col;
+    const int64_t nq = m->nt * kQP;
+    if ((st = upload(&m->d_xyz, m->xyz, s)) || (st = upload(&m->d_tri, m->tri, s)) ||
+        (st = upload(&m->d_inc_ptr, T.inc_ptr, s)) || (st = upload(&m->d_inc, T.inc, s)) ||
+        (st = upload(&m->d_spairs, T.spairs, s)) || (st = upload(&m->d_mptr, T.m_ptr, s)) ||
+        (st = upload(&m->d_mcol, T.m_col, s)) || (st = upload(&m->d_mslot, T.m_slot, s)) ||
+        (st = dalloc(&m->d_frames, 9 * m->nn)) || (st = dalloc(&m->d_qp, kQPF * nq)) ||
+        (st = dalloc(&m->d_qp32, kQPF * nq)) || (st = dalloc(&m->d_elem, 4 * m->nt)))
+        return fail(st);
+    if ((st = geom_build(m, s))) return fail(st);
+    if (hipStreamSynchronize(s) != hipSuccess) { set_error("mesh upload failed"); return fail(MBEM_EDEVICE); }
+    *out = m;
+    return MBEM_OK;
+}
+
+void mbem_mesh_destroy(mbem_mesh *m) {
+    if (!m) return;
+    if (m->ctx) (void)hipSetDevice(m->ctx->device);
+    if (m->ctx) (void)hipStreamSynchronize(m->ctx->stream);
+    mesh_free_device(m);
+    delete m;
+}
+
+int mbem_mesh_permutation(const mbem_mesh *m, int64_t *node_order, int64_t *tri_order) {
+    if (!m) { set_error("null mesh"); return MBEM_EINVAL; }
+    if (node_order) std::copy(m->node_order.begin(), m->node_order.end(), node_order);
+    if (tri_order) std::copy(m->tri_order.begin(), m->tri_order.end(), tri_order);
+    return MBEM_OK;
+}
+
+int mbem_mesh_info(const mbem_mesh *m, int64_t *info) {
+    if (!m || !info) { set_error("null argument"); return MBEM_EINVAL; }
+    info[0] = m->nn; info[1] = m->nt; info[2] = 4 * m->nn;
+    info[3] = m->n_single[3]; info[4] = m->n_single[2]; info[5] = m->n_single[1];
+    info[6] = 0; info[7] = 0;
+    return MBEM_OK;
+}
+
+int mbem_fill(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_op **out,
+              mbem_stats *stats) {
+    if (!mesh || !p || !out) { set_error("null argument"); return MBEM_EINVAL; }
+    if (p->precision != MBEM_FP64 && p->precision != MBEM_MIXED) { set_error("bad precision"); return MBEM_EINVAL; }
+    if (!(p->k0 > 0)) { set_error("k0 must be positive"); return MBEM_EINVAL; }
+    if (p->ssq_order < 0 || p->ssq_order > kMaxSSQ) { set_error("ssq_order out of range"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    mbem_op *op = new (std::nothrow) mbem_op;
+    if (!op) { set_error("host allocation"); return MBEM_ENOMEM; }
+    op->ctx = ctx;
+    op->mesh = mesh;
+    op->p = *p;
+    op->prec = p->precision;
+    op->n2 = 2 * mesh->nn;
+    derive_constants(p, &op->ka, &op->ki, &op->eps_i, &op->mu_i);
+    op->iw = {0.0, 1.0 / p->k0};
+    op->ce = {(op->eps_i.x + 1.0) / 2.0, op->eps_i.y / 2.0};
+    op->cm = {(op->mu_i.x + 1.0) / 2.0, op->mu_i.y / 2.0};
+    const size_t esz = op->prec == MBEM_FP64 ? 16 : 8;
+    int st = MBEM_OK;
+    for (int o = 0; o < 3 && st == MBEM_OK; ++o) {
+        hipError_t e = hipMalloc(&op->K[o], esz * op->n2 * op->n2);
+        if (e != hipSuccess) { set_error(std::string("operator allocation: ") + hipGetErrorString(e)); st = MBEM_ENOMEM; }
+    }
+    if (st == MBEM_OK) st = dalloc(&op->d_mval, mesh->m_col.size());
+    if (st != MBEM_OK) { op_free_device(op); delete op; return st; }
+    Timer t;
+    t.start(ctx->stream);
+    st = fill_run(op, ctx->stream);
+    const double ms = t.stop(ctx->stream);
+    if (st == MBEM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) { set_error("fill failed"); st = MBEM_EDEVICE; }
+    if (st != MBEM_OK) { op_free_device(op); delete op; return st; }
+    if (stats) {
+        stats->t_fill_ms = ms;
+        stats->n_near_pairs = op->n_near;
+        stats->t_geom_ms = op->t_phase[0];
+        stats->t_regular_ms = op->t_phase[1];
+        stats->t_near_ms = op->t_phase[2];
+        stats->t_ssq_ms = op->t_phase[3];
+        stats->t_mass_ms = op->t_phase[4];
+        stats->n_regular_pairs = mesh->nt * mesh->nt - mesh->n_spairs;
+    }
+    *out = op;
+    return MBEM_OK;
+}
+
+void mbem_op_destroy(mbem_op *op) {
+    if (!op) return;
+    if (op->ctx) { (void)hipSetDevice(op->ctx->device); (void)hipStreamSynchronize(op->ctx->stream); }
+    op_free_device(op);
+    delete op;
+}
+
+int mbem_op_export_blocks(mbem_ctx *ctx, const mbem_op *op, mbem_c128 *K1, mbem_c128 *K2e, mbem_c128 *K2m) {
+    if (!op) { set_error("null operator"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    return export_blocks_run(op, (double2 *)K1, (double2 *)K2e, (double2 *)K2m, ctx->stream);
+}
+
+int mbem_op_export_dense(mbem_ctx *ctx, const mbem_op *op, mbem_c128 *Z) {
+    if (!op || !Z) { set_error("null argument"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    return export_dense_run(op, (double2 *)Z, ctx->stream);
+}
+
+int mbem_matvec(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *x, int32_t nrhs, mbem_c128 *y) {
+    if (!op || !x || !y || nrhs < 1) { set_error("bad argument"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    double2 *tmp = nullptr;
+    MBEM_TRY(dalloc(&tmp, 4 * op->n2));
+    const int64_t N = 2 * op->n2;
+    int st = MBEM_OK;
+    for (int r = 0; r < nrhs && st == MBEM_OK; ++r)
+        st = matvec_run(op, (const double2 *)x + r * N, (double2 *)y + r * N, tmp, ctx->stream);
+    (void)hipStreamSynchronize(ctx->stream);
+    dfree(tmp);
+    return st;
+}
+
+int mbem_precond_setup(mbem_ctx *ctx, mbem_op *op, int32_t block, mbem_stats *stats) {
+    if (!op) { set_error("null operator"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    Timer t;
+    t.start(ctx->stream);
+    int st = mbj_setup_run(op, block, ctx->stream);
+    const double ms = t.stop(ctx->stream);
+    if (stats) stats->t_setup_ms = ms;
+    return st;
+}
+
+int mbem_precond_apply(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *v, mbem_c128 *z) {
+    if (!op || !v || !z) { set_error("null argument"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    return mbj_apply_run(op, (const double2 *)v, (double2 *)z, ctx->stream);
+}
+
+int mbem_rhs_planewave(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const double *khat,
+                       const mbem_c128 *pol, int32_t nrhs, mbem_c128 *b) {
+    if (!mesh || !p || !khat || !pol || !b || nrhs < 1) { set_error("bad argument"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    double *dk = nullptr;
+    double2 *dp = nullptr;
+    MBEM_TRY(dalloc(&dk, 3 * nrhs));
+    MBEM_TRY(dalloc(&dp, 3 * nrhs));
+    const hipStream_t s = ctx->stream;
+    MBEM_HIP(hipMemcpyAsync(dk, khat, sizeof(double) * 3 * nrhs, hipMemcpyHostToDevice, s));
+    MBEM_HIP(hipMemcpyAsync(dp, pol, sizeof(double2) * 3 * nrhs, hipMemcpyHostToDevice, s));
+    int st = rhs_run(mesh, p, dk, dp, nrhs, (double2 *)b, s);
+    (void)hipStreamSynchronize(s);
+    dfree(dk);
+    dfree(dp);
+    return st;
+}
+
+int mbem_solve(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs, const mbem_solve_opts *o,
+               mbem_c128 *x, mbem_stats *stats) {
+    if (!op || !b || !x || !o || nrhs < 1 || o->maxit < 1 || !(o->tol > 0)) {
+        set_error("bad argument");
+        return MBEM_EINVAL;
+    }
+    MBEM_TRY(set_device(ctx));
+    const hipStream_t s = ctx->stream;
+    Gmres g;
+    MBEM_TRY(gmres_alloc(g, op, o->maxit, s));
+    const int64_t N = g.N;
+    double2 *r = nullptr, *d = nullptr;
+    MBEM_TRY(dalloc(&r, N));
+    MBEM_TRY(dalloc(&d, N));
+    Timer t;
+    t.start(s);
+    int total_it = 0, sweeps = 0, status = MBEM_OK;
+    double worst = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+        const double2 *bc = (const double2 *)b + c * N;
+        double2 *xc = (double2 *)x + c * N;
+        double bn = 0, rn = 0;
+        MBEM_TRY(vec_norm2(bc, N, g.ndev, s));
+        MBEM_HIP(hipMemcpyAsync(&bn, g.ndev, sizeof(double), hipMemcpyDeviceToHost, s));
+        MBEM_HIP(hipStreamSynchronize(s));
+        int it = 0;
+        double est = 0;
+        if (op->prec == MBEM_FP64) {
+            int st = gmres_solve(g, bc, o->tol, xc, &it, &est);
+            if (st != MBEM_OK && st != MBEM_ENOCONV) return st;
+            total_it += it;
+            sweeps += 1;
+        } else {
+            // iterative refinement: x += GMRES(Z, b - Z x), residual in FP64
+            const int maxref = o->max_refine > 0 ? o->max_refine : 8;
+            const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
+            MBEM_HIP(hipMemsetAsync(xc, 0, sizeof(double2) * N, s));
+            MBEM_HIP(hipMemcpyAsync(r, bc, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
+            for (int sw = 0; sw < maxref; ++sw) {
+                int st = gmres_solve(g, r, std::max(itol, o->tol), d, &it, &est);
+                if (st != MBEM_OK && st != MBEM_ENOCONV) return st;
+                total_it += it;
+                sweeps += 1;
+                MBEM_TRY(vec_axpy(xc, d, double2{1.0, 0.0}, N, s));
+                MBEM_TRY(matvec_run(op, xc, r, g.tmp, s));
+                MBEM_TRY(vec_scale_copy(r, r, double2{-1.0, 0.0}, N, s));
+                MBEM_TRY(vec_axpy(r, bc, double2{1.0, 0.0}, N, s));
+                MBEM_TRY(vec_norm2(r, N, g.ndev, s));
+                MBEM_HIP(hipMemcpyAsync(&rn, g.ndev, sizeof(double), hipMemcpyDeviceToHost, s));
+                MBEM_HIP(hipStreamSynchronize(s));
+                if (bn == 0 || rn <= o->tol * bn) break;
+            }
+        }
+        // explicit residual of the final iterate
+        MBEM_TRY(matvec_run(op, xc, r, g.tmp, s));
+        MBEM_TRY(vec_scale_copy(r, r, double2{-1.0, 0.0}, N, s));
+        MBEM_TRY(vec_axpy(r, bc, double2{1.0, 0.0}, N, s));
+        MBEM_TRY(vec_norm2(r, N, g.ndev, s));
+        MBEM_HIP(hipMemcpyAsync(&rn, g.ndev, sizeof(double), hipMemcpyDeviceToHost, s));
+        MBEM_HIP(hipStreamSynchronize(s));
+        const double rel = bn > 0 ? rn / bn : 0.0;
+        worst = std::max(worst, rel);
+        if (!(rel <= 10 * o->tol)) status = MBEM_ENOCONV;
+    }
+    const double ms = t.stop(s);
+    dfree(r);
+    dfree(d);
+    if (stats) {
+        stats->iters = total_it;
+        stats->outer_iters = sweeps;
+        stats->rel_resid = worst;
+        stats->t_solve_ms = ms;
+        stats->t_matvec_ms = g.t_matvec;
+        stats->n_matvec = g.n_matvec;
+    }
+    if (status == MBEM_ENOCONV) set_error("GMRES did not reach the tolerance");
+    return status;
+}
+
+int mbem_farfield(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const mbem_c128 *x,
+                  int32_t nrhs, const double *rhat, int64_t ndir, mbem_c128 *F) {
+    if (!mesh || !p || !x || !rhat || !F || nrhs < 1 || ndir < 1) { set_error("bad argument"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    int st = farfield_run(mesh, p, (const double2 *)x, nrhs, rhat, ndir, (double2 *)F, ctx->stream);
+    (void)hipStreamSynchronize(ctx->stream);
+    return st;
+}
+
+int mbem_cross_sections(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const mbem_c128 *x,
+                        const double *khat, const mbem_c128 *pol, int32_t ntheta, double *out) {
+    if (!mesh || !p || !x || !khat || !pol || !out) { set_error("null argument"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    const hipStream_t s = ctx->stream;
+    if (ntheta <= 0) ntheta = (int32_t)std::ceil(2.0 * p->k0 * mesh->amax) + 20;
+    const int nphi = 2 * ntheta;
+    const int64_t ndir = (int64_t)ntheta * nphi + 1;   // last one: khat
+    std::vector<double> dirs(3 * ndir), w(ndir, 0.0), u(ntheta), wu(ntheta);
+    gauss_legendre(ntheta, u.data(), wu.data());
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < ntheta; ++i)
+        for (int j = 0; j < nphi; ++j) {
+            const double ph = 2.0 * pi * j / nphi, st = std::sqrt(std::max(0.0, 1.0 - u[i] * u[i]));
+            const int64_t d = (int64_t)i * nphi + j;
+            dirs[3 * d] = st * std::cos(ph);
+            dirs[3 * d + 1] = st * std::sin(ph);
+            dirs[3 * d + 2] = u[i];
+            w[d] = wu[i] * 2.0 * pi / nphi;
+        }
+    for (int k = 0; k < 3; ++k) dirs[3 * (ndir - 1) + k] = khat[k];
+    double *dd = nullptr, *dw = nullptr, *dacc = nullptr;
+    double2 *dF = nullptr;
+    MBEM_TRY(dalloc(&dd, 3 * ndir));
+    MBEM_TRY(dalloc(&dw, ndir));
+    MBEM_TRY(dalloc(&dacc, 2));
+    MBEM_TRY(dalloc(&dF, 3 * ndir));
+    MBEM_HIP(hipMemcpyAsync(dd, dirs.data(), sizeof(double) * 3 * ndir, hipMemcpyHostToDevice, s));
+    MBEM_HIP(hipMemcpyAsync(dw, w.data(), sizeof(double) * ndir, hipMemcpyHostToDevice, s));
+    MBEM_TRY(farfield_run(mesh, p, (const double2 *)x, 1, dd, ndir, dF, s));
+    MBEM_TRY(weighted_norm_run(ndir, dF, dw, dacc, s));
+    MBEM_TRY(absorbed_run(mesh, (const double2 *)x, dacc + 1, s));
+    double acc[2];
+    double2 Ff[3];
+    MBEM_HIP(hipMemcpyAsync(acc, dacc, sizeof(acc), hipMemcpyDeviceToHost, s));
+    MBEM_HIP(hipMemcpyAsync(Ff, dF + 3 * (ndir - 1), sizeof(Ff), hipMemcpyDeviceToHost, s));
+    MBEM_HIP(hipStreamSynchronize(s));
+    std::complex<double> pe(0.0, 0.0);
+    for (int k = 0; k < 3; ++k) pe += std::conj(std::complex<double>(pol[k].re, pol[k].im)) * C(Ff[k]);
+    out[0] = 4.0 * pi / p->k0 * pe.imag();
+    out[1] = acc[0];
+    out[2] = acc[1];
+    dfree(dd); dfree(dw); dfree(dacc); dfree(dF);
+    return MBEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,510 @@
+// Galerkin fill of K1, K2^eps, K2^mu (Sec. 4.1-4.2, fused as in Sec. 6.1)
+// and of the mass matrix (eq. mass_matrix).
+//
+//  * regular pairs: 7 x 7 quadrature-point pairs per element pair, one
+//    wavefront per pair; the twelve weighted kernel values of every point
+//    pair go to LDS and are contracted with the shape-function table in two
+//    steps (trial side, then test side) before being added to Z;
+//  * singular pairs (coincident, common edge, common vertex): Sauter-Schwab
+//    quadrature, 6 / 5 / 2 regions x n^4 Gauss points, one wavefront per
+//    pair, FP64;
+//  * MIXED precision: far regular pairs in FP32, near regular pairs and all
+//    singular pairs in FP64, everything accumulated into complex64 Z.
+#include <complex>
+
+#include "mbem_internal.h"
+#include "p2_device.h"
+
+namespace mbem {
+
+constexpr int kWave = 64;
+
+// -------------------------------------------------------------- helpers --
+__device__ inline void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ inline void atomic_add(float *p, double v) { unsafeAtomicAdd(p, (float)v); }
+__device__ inline void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+// Map a linear workgroup id so that each of the 8 XCDs (which receive
+// workgroups round-robin) works on one contiguous range of tiles.
+__device__ inline int64_t xcd_remap(int64_t bid, int64_t total) {
+    const int64_t q = total / 8, r = total % 8;
+    const int64_t xcd = bid % 8, local = bid / 8;
+    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+// Twelve weighted kernel values (eqs. kappa1_alphabeta, kappa2_alpha_beta)
+// at a test point (x, n, t_a, s_a) and a trial point (y, t_b):
+//   kappa1_ab = (D0 - dg)(s_a.t_b) + df (s_a.R)(R.t_b)
+//   kappa2_ab = G_chi [(t_a.t_b)(n.R) - (t_a.R)(n.t_b)],  R = (x - y)/|x - y|
+// output order c = 4 op + 2 a + b, op: K1, K2^eps, K2^mu.
+template <typename T>
+__device__ inline void kappa12(const KernelConst &K, vec3<T> x, vec3<T> n,
+                               const vec3<T> ta[2], const vec3<T> sa[2],
+                               vec3<T> y, const vec3<T> tb[2], T ww,
+                               cx<T> out[12]) {
+    vec3<T> Rv = x - y;
+    const T R = sqrt(dot(Rv, Rv));
+    const vec3<T> Rh = ((T)1 / R) * Rv;
+    const KScal<T> s = kernel_scalars<T>(K, R);
+    const cx<T> A = s.D0 - s.dg;
+    const T nR = dot(n, Rh);
+    T tRy[2], ntb[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) { tRy[b] = dot(tb[b], Rh); ntb[b] = dot(n, tb[b]); }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const T sR = dot(sa[a], Rh), tR = dot(ta[a], Rh);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const T st = dot(sa[a], tb[b]);
+            const T g2 = dot(ta[a], tb[b]) * nR - tR * ntb[b];
+            const cx<T> k1 = st * A + (sR * tRy[b]) * s.df;
+            out[0 + 2 * a + b] = ww * k1;
+            out[4 + 2 * a + b] = (ww * g2) * s.Ge;
+            out[8 + 2 * a + b] = (ww * g2) * s.Gm;
+        }
+    }
+}
+
+// ---------------------------------------------------- regular pairs ---
+template <typename T, typename TS>
+struct RegArgs {
+    int64_t nt, n2, tiles_f, total;
+    const T *qp;            // [kQPF][nt*7]
+    const int32_t *tri;
+    const double *einfo;    // [nt][4]
+    double near_r;
+    int mode;               // 0 all regular, 1 far only, 2 near only
+    unsigned long long *near_count;
+    KernelConst K;
+    TS *Z[3];
+};
+
+template <typename T>
+__device__ inline vec3<T> qload(const T *qp, int64_t nq, int f, int64_t i) {
+    return {qp[(int64_t)f * nq + i], qp[(int64_t)(f + 1) * nq + i], qp[(int64_t)(f + 2) * nq + i]};
+}
+
+template <typename T, typename TS>
+__global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
+    __shared__ cx<T> s_kap[4][49 * 12];
+    __shared__ cx<T> s_T[4][7 * 6 * 12];
+    __shared__ T s_N[7][6];   // shape function j at rule point q
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int64_t tile = xcd_remap(blockIdx.x, a.total);
+    const int64_t e = tile / a.tiles_f;
+    const int64_t f = (tile % a.tiles_f) * 4 + w;
+    if (threadIdx.x < 7) {
+        double xi, eta, wq, N[6], d1[6], d2[6];
+        rule7(threadIdx.x, xi, eta, wq);
+        p2_shape(xi, eta, N, d1, d2);
+        for (int j = 0; j < 6; ++j) s_N[threadIdx.x][j] = (T)N[j];
+    }
+    // is (e, f) a regular pair handled by this launch?
+    bool active = f < a.nt;
+    if (active) {
+        const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) active = active && (te[i] != tf[j]);
+    }
+    if (active && a.mode != 0) {
+        const double *ce = a.einfo + 4 * e, *cf = a.einfo + 4 * f;
+        const double dx = ce[0] - cf[0], dy = ce[1] - cf[1], dz = ce[2] - cf[2];
+        const double gap = sqrt(dx * dx + dy * dy + dz * dz) - ce[3] - cf[3];
+        const bool near = gap < a.near_r;
+        active = (a.mode == 2) ? near : !near;
+        if (active && a.mode == 2 && lane == 0) atomicAdd(a.near_count, 1ull);
+    }
+    const int64_t nq = a.nt * kQP;
+    // phase A: one point pair per lane
+    if (active && lane < 49) {
+        const int p = lane / 7, q = lane % 7;
+        const int64_t ix = e * kQP + p, iy = f * kQP + q;
+        const vec3<T> x = qload(a.qp, nq, QX, ix), n = qload(a.qp, nq, QN, ix);
+        const vec3<T> ta[2] = {qload(a.qp, nq, QT1, ix), qload(a.qp, nq, QT2, ix)};
+        const vec3<T> sa[2] = {qload(a.qp, nq, QS1, ix), qload(a.qp, nq, QS2, ix)};
+        const vec3<T> y = qload(a.qp, nq, QX, iy);
+        const vec3<T> tb[2] = {qload(a.qp, nq, QT1, iy), qload(a.qp, nq, QT2, iy)};
+        const T ww = a.qp[(int64_t)QW * nq + ix] * a.qp[(int64_t)QW * nq + iy];
+        cx<T> k[12];
+        kappa12<T>(a.K, x, n, ta, sa, y, tb, ww, k);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) s_kap[w][lane * 12 + c] = k[c];
+    }
+    __syncthreads();
+    // phase B: contract the trial side, T[p][j][c] = sum_q kap[p][q][c] N_j(q)
+    if (active) {
+        for (int it = lane; it < 7 * 12; it += kWave) {
+            const int p = it / 12, c = it % 12;
+            cx<T> kv[7];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) kv[q] = s_kap[w][(p * 7 + q) * 12 + c];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                cx<T> acc = {0, 0};
+#pragma unroll
+                for (int q = 0; q < 7; ++q) acc = acc + s_N[q][j] * kv[q];
+                s_T[w][(p * 6 + j) * 12 + c] = acc;
+            }
+        }
+    }
+    __syncthreads();
+    // phase C: contract the test side and add to Z
+    if (active) {
+        const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
+        for (int it = lane; it < 6 * 12; it += kWave) {
+            const int j = it / 12, c = it % 12;
+            const int op = c / 4, al = (c / 2) % 2, be = c % 2;
+            cx<T> tv[7];
+#pragma unroll
+            for (int p = 0; p < 7; ++p) tv[p] = s_T[w][(p * 6 + j) * 12 + c];
+            const int64_t col = 2 * (int64_t)tf[j] + be;
+            TS *Z = a.Z[op];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                cx<T> acc = {0, 0};
+#pragma unroll
+                for (int p = 0; p < 7; ++p) acc = acc + s_N[p][i] * tv[p];
+                const int64_t row = 2 * (int64_t)te[i] + al;
+                TS *dst = Z + 2 * (row * a.n2 + col);
+                atomic_add(dst, acc.re);
+                atomic_add(dst + 1, acc.im);
+            }
+        }
+    }
+}
+
+// --------------------------------------------- Sauter-Schwab pairs ---
+// Maps of [0,1]^4 -> Th x Th, Th = {0 <= t <= s <= 1}; the common edge is
+// {t = 0} with the same s in both triangles, the common vertex is (0,0).
+// Returns the Jacobian of the region's map.
+__device__ inline double ss_region(int cls, int r, double u, double e1, double e2,
+                                   double e3, double &s1, double &t1, double &s2,
+                                   double &t2) {
+    const double u3 = u * u * u;
+    if (cls == 3) {
+        const double a = e1 * e2, b = a * e3;
+        switch (r) {
+        case 0: s1 = u; t1 = u * (1 - e1 + a); s2 = u * (1 - b); t2 = u * (1 - e1); break;
+        case 1: s1 = u * (1 - b); t1 = u * (1 - e1); s2 = u; t2 = u * (1 - e1 + a); break;
+        case 2: s1 = u; t1 = u * e1 * (1 - e2 + e2 * e3); s2 = u * (1 - a); t2 = u * e1 * (1 - e2); break;
+        case 3: s1 = u * (1 - a); t1 = u * e1 * (1 - e2); s2 = u; t2 = u * e1 * (1 - e2 + e2 * e3); break;
+        case 4: s1 = u * (1 - b); t1 = u * e1 * (1 - e2 * e3); s2 = u; t2 = u * e1 * (1 - e2); break;
+        default: s1 = u; t1 = u * e1 * (1 - e2); s2 = u * (1 - b); t2 = u * e1 * (1 - e2 * e3); break;
+        }
+        return u3 * e1 * e1 * e2;
+    }
+    if (cls == 2) {
+        const double a = e1 * e2, b = a * e3;
+        switch (r) {
+        case 0: s1 = u; t1 = u * e1 * e3; s2 = u * (1 - a); t2 = u * e1 * (1 - e2); return u3 * e1 * e1;
+        case 1: s1 = u; t1 = u * e1; s2 = u * (1 - b); t2 = u * a * (1 - e3); break;
+        case 2: s1 = u * (1 - a); t1 = u * e1 * (1 - e2); s2 = u; t2 = u * b; break;
+        case 3: s1 = u * (1 - b); t1 = u * a * (1 - e3); s2 = u; t2 = u * e1; break;
+        default: s1 = u * (1 - b); t1 = u * e1 * (1 - e2 * e3); s2 = u; t2 = u * a; break;
+        }
+        return u3 * e1 * e1 * e2;
+    }
+    if (r == 0) { s1 = u; t1 = u * e1; s2 = u * e2; t2 = u * e2 * e3; }
+    else        { s1 = u * e2; t1 = u * e2 * e3; s2 = u; t2 = u * e1; }
+    return u3 * e2;
+}
+
+// (s,t) of Th in the re-indexed triangle -> (xi, eta) of the stored one.
+// code holds the stored local vertex of re-indexed vertex k in bits 2k.
+__device__ inline void ss_local(int code, double s, double t, double &xi, double &eta) {
+    const double L[3] = {1.0 - s, s - t, t};
+    double l[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) l[(code >> (2 * k)) & 3] = L[k];
+    xi = l[1];
+    eta = l[2];
+}
+
+template <typename TS>
+struct SsqArgs {
+    int64_t n2, npairs;
+    const int32_t *pairs;   // e, f, class, perm codes
+    const int32_t *tri;
+    const double *xyz, *frames;
+    int order;
+    double glx[kMaxSSQ], glw[kMaxSSQ];   // Gauss-Legendre on [0,1]
+    KernelConst K;
+    TS *Z[3];
+};
+
+constexpr int kStreams = 5;   // consumer lanes per kernel component
+
+template <typename TS>
+__global__ __launch_bounds__(64) void k_ssq(SsqArgs<TS> a) {
+    __shared__ double s_pt[kWave][36];                 // w kappa (24), Nx, Ny
+    __shared__ double s_red[kStreams][36 * 12 * 2];
+    const int lane = threadIdx.x;
+    const int64_t pid = blockIdx.x;
+    const int32_t e = a.pairs[4 * pid], f = a.pairs[4 * pid + 1];
+    const int cls = a.pairs[4 * pid + 2], code = a.pairs[4 * pid + 3];
+    const int n = a.order, n4 = n * n * n * n;
+    const int nreg = cls == 3 ? 6 : (cls == 2 ? 5 : 2);
+    const int npts = nreg * n4;
+    const int c = lane % 12, stream = lane / 12;     // consumer role
+    const bool consumer = lane < 12 * kStreams;
+    double acc[36][2];
+#pragma unroll
+    for (int k = 0; k < 36; ++k) acc[k][0] = acc[k][1] = 0.0;
+    for (int base = 0; base < npts; base += kWave) {
+        const int idx = base + lane;
+        if (idx < npts) {
+            const int r = idx / n4;
+            int g = idx % n4;
+            const int i3 = g % n; g /= n;
+            const int i2 = g % n; g /= n;
+            const int i1 = g % n; g /= n;
+            const int i0 = g;
+            double s1, t1, s2, t2;
+            const double jac = ss_region(cls, r, a.glx[i0], a.glx[i1], a.glx[i2], a.glx[i3], s1, t1, s2, t2);
+            const double wg = jac * a.glw[i0] * a.glw[i1] * a.glw[i2] * a.glw[i3];
+            double xe, ye, xf, yf;
+            ss_local(code & 63, s1, t1, xe, ye);
+            ss_local(code >> 6, s2, t2, xf, yf);
+            P2Point X, Y;
+            p2_point(a.xyz, a.frames, a.tri + 6 * e, xe, ye, X);
+            p2_point(a.xyz, a.frames, a.tri + 6 * f, xf, yf, Y);
+            const dvec3 ta[2] = {X.t1, X.t2}, sa[2] = {X.s1, X.s2}, tb[2] = {Y.t1, Y.t2};
+            cx<double> k[12];
+            kappa12<double>(a.K, X.x, X.n, ta, sa, Y.x, tb, wg * X.J * Y.J, k);
+#pragma unroll
+            for (int q = 0; q < 12; ++q) { s_pt[lane][2 * q] = k[q].re; s_pt[lane][2 * q + 1] = k[q].im; }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) { s_pt[lane][24 + q] = X.N[q]; s_pt[lane][30 + q] = Y.N[q]; }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 36; ++q) s_pt[lane][q] = 0.0;
+        }
+        __syncthreads();
+        if (consumer) {
+            for (int r = stream; r < kWave; r += kStreams) {
+                const double kr = s_pt[r][2 * c], ki = s_pt[r][2 * c + 1];
+                double u[6][2];
+#pragma unroll
+                for (int j = 0; j < 6; ++j) { u[j][0] = s_pt[r][30 + j] * kr; u[j][1] = s_pt[r][30 + j] * ki; }
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    const double nx = s_pt[r][24 + i];
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) {
+                        acc[6 * i + j][0] += nx * u[j][0];
+                        acc[6 * i + j][1] += nx * u[j][1];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (consumer) {
+#pragma unroll
+        for (int k = 0; k < 36; ++k) {
+            s_red[stream][(k * 12 + c) * 2] = acc[k][0];
+            s_red[stream][(k * 12 + c) * 2 + 1] = acc[k][1];
+        }
+    }
+    __syncthreads();
+    const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
+    for (int it = lane; it < 36 * 12; it += kWave) {
+        double re = 0, im = 0;
+#pragma unroll
+        for (int s = 0; s < kStreams; ++s) { re += s_red[s][2 * it]; im += s_red[s][2 * it + 1]; }
+        const int k = it / 12, cc = it % 12;
+        const int i = k / 6, j = k % 6;
+        const int op = cc / 4, al = (cc / 2) % 2, be = cc % 2;
+        const int64_t row = 2 * (int64_t)te[i] + al, col = 2 * (int64_t)tf[j] + be;
+        TS *dst = a.Z[op] + 2 * (row * a.n2 + col);
+        atomic_add(dst, re);
+        atomic_add(dst + 1, im);
+    }
+}
+
+// ---------------------------------------------------------- mass ---
+// Element mass blocks int N_k N_l on the 7-point rule, added to the node
+// CSR values through the precomputed slot map.
+__global__ void k_mass(int64_t nt, const double *__restrict__ qp,
+                       const int32_t *__restrict__ slot, double *__restrict__ mval) {
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= nt * 36) return;
+    const int64_t e = id / 36;
+    const int k = (int)(id % 36) / 6, l = (int)(id % 6);
+    const int64_t nq = nt * kQP;
+    double s = 0.0;
+    for (int q = 0; q < kQP; ++q) {
+        double xi, eta, w, N[6], d1[6], d2[6];
+        rule7(q, xi, eta, w);
+        p2_shape(xi, eta, N, d1, d2);
+        s += qp[QW * nq + e * kQP + q] * N[k] * N[l];
+    }
+    unsafeAtomicAdd(mval + slot[id], s);
+}
+
+// ------------------------------------------------------------ host ---
+void derive_constants(const mbem_params *p, double2 *ka, double2 *ki, double2 *eps_i,
+                      double2 *mu_i) {
+    std::complex<double> er(p->eps_r_re, p->eps_r_im), mr(p->mu_r_re, p->mu_r_im);
+    std::complex<double> k = p->k0 * std::sqrt(er * mr);
+    if (k.imag() < 0) k = -k;
+    *ka = {p->k0, 0.0};
+    *ki = {k.real(), k.imag()};
+    *eps_i = {er.real(), er.imag()};
+    *mu_i = {mr.real(), mr.imag()};
+}
+
+static KernelConst make_kconst(const mbem_op *op) {
+    using C = std::complex<double>;
+    KernelConst K{};
+    const C ka(op->ka.x, op->ka.y), ki(op->ki.x, op->ki.y);
+    const C ea(1.0, 0.0), ei(op->eps_i.x, op->eps_i.y);
+    const C ma(1.0, 0.0), mi(op->mu_i.x, op->mu_i.y);
+    K.ka_re = ka.real(); K.ka_im = ka.imag(); K.ki_re = ki.real(); K.ki_im = ki.imag();
+    K.eps_a_re = 1.0; K.eps_a_im = 0.0; K.eps_i_re = ei.real(); K.eps_i_im = ei.imag();
+    K.mu_a_re = 1.0; K.mu_a_im = 0.0; K.mu_i_re = mi.real(); K.mu_i_im = mi.imag();
+    K.kmax = std::max(std::abs(ka), std::abs(ki));
+    C cna(1.0, 0.0), cni(1.0, 0.0);
+    const C I(0.0, 1.0);
+    for (int n = 0; n <= kSeriesTerms; ++n) {
+        if (n > 0) { cna *= I * ka / (double)n; cni *= I * ki / (double)n; }
+        const C d = cna - cni;
+        const C vD = ka * ka * cna - ki * ki * cni;
+        const C vF = (n >= 2) ? (double)((n - 1) * (n - 3)) * d : C(0.0);
+        const C vG = (n >= 2) ? -(double)(n - 1) * d : C(0.0);
+        const C vE = (double)(n - 1) * (ea * cna - ei * cni);
+        const C vM = (double)(n - 1) * (ma * cna - mi * cni);
+        K.cD[2 * n] = vD.real(); K.cD[2 * n + 1] = vD.imag();
+        K.cF[2 * n] = vF.real(); K.cF[2 * n + 1] = vF.imag();
+        K.cG[2 * n] = vG.real(); K.cG[2 * n + 1] = vG.imag();
+        K.cE[2 * n] = vE.real(); K.cE[2 * n + 1] = vE.imag();
+        K.cM[2 * n] = vM.real(); K.cM[2 * n + 1] = vM.imag();
+    }
+    return K;
+}
+
+template <typename T, typename TS>
+static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long *cnt,
+                          hipStream_t s) {
+    const mbem_mesh *m = op->mesh;
+    RegArgs<T, TS> a;
+    a.nt = m->nt;
+    a.n2 = op->n2;
+    a.tiles_f = (m->nt + 3) / 4;
+    a.total = m->nt * a.tiles_f;
+    a.qp = qp;
+    a.tri = m->d_tri;
+    a.einfo = m->d_elem;
+    a.mode = mode;
+    a.near_count = cnt;
+    a.K = make_kconst(op);
+    double dk2 = std::abs(std::complex<double>(op->ka.x, op->ka.y) * std::complex<double>(op->ka.x, op->ka.y) -
+                          std::complex<double>(op->ki.x, op->ki.y) * std::complex<double>(op->ki.x, op->ki.y));
+    a.near_r = op->p.near_radius > 0 ? op->p.near_radius : (dk2 > 0 ? 1.89 / std::sqrt(dk2) : 0.0);
+    for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)op->K[o];
+    if (a.total > 0x7fffffffLL) { set_error("too many element pairs for one launch"); return MBEM_EINVAL; }
+    hipLaunchKernelGGL((k_regular<T, TS>), dim3((unsigned)a.total), dim3(256), 0, s, a);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+template <typename TS>
+static int launch_ssq(mbem_op *op, hipStream_t s) {
+    const mbem_mesh *m = op->mesh;
+    SsqArgs<TS> a;
+    a.n2 = op->n2;
+    a.npairs = m->n_spairs;
+    a.pairs = m->d_spairs;
+    a.tri = m->d_tri;
+    a.xyz = m->d_xyz;
+    a.frames = m->d_frames;
+    a.order = op->p.ssq_order > 0 ? op->p.ssq_order : 4;
+    if (a.order > kMaxSSQ) { set_error("ssq_order above 8 is not supported"); return MBEM_EINVAL; }
+    double x[kMaxSSQ], w[kMaxSSQ];
+    gauss_legendre(a.order, x, w);
+    for (int i = 0; i < kMaxSSQ; ++i) {
+        a.glx[i] = i < a.order ? 0.5 * (1.0 + x[a.order - 1 - i]) : 0.0;
+        a.glw[i] = i < a.order ? 0.5 * w[a.order - 1 - i] : 0.0;
+    }
+    a.K = make_kconst(op);
+    for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)op->K[o];
+    if (a.npairs == 0) return MBEM_OK;
+    hipLaunchKernelGGL((k_ssq<TS>), dim3((unsigned)a.npairs), dim3(64), 0, s, a);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+int mass_run(mbem_op *op, hipStream_t s) {
+    const mbem_mesh *m = op->mesh;
+    MBEM_HIP(hipMemsetAsync(op->d_mval, 0, sizeof(double) * m->m_col.size(), s));
+    const int64_t n = m->nt * 36;
+    hipLaunchKernelGGL(k_mass, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       m->nt, m->d_qp, m->d_mslot, op->d_mval);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+// Events bracketing every launch of the fill; elapsed times are read after
+// the caller's synchronisation.
+struct PhaseEvents {
+    hipEvent_t ev[6] = {};
+    bool ok = true;
+    PhaseEvents() {
+        for (auto &e : ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+    }
+    ~PhaseEvents() {
+        for (auto &e : ev) if (e) (void)hipEventDestroy(e);
+    }
+    void mark(int i, hipStream_t s) { if (ok) (void)hipEventRecord(ev[i], s); }
+    double ms(int a, int b) {
+        float t = 0.f;
+        if (!ok || hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) return 0.0;
+        return t;
+    }
+};
+
+int fill_run(mbem_op *op, hipStream_t s) {
+    const mbem_mesh *m = op->mesh;
+    PhaseEvents pe;
+    const size_t esz = op->prec == MBEM_FP64 ? 16 : 8;
+    for (int o = 0; o < 3; ++o)
+        MBEM_HIP(hipMemsetAsync(op->K[o], 0, esz * op->n2 * op->n2, s));
+    pe.mark(0, s);
+    MBEM_TRY(geom_build(m, s));
+    pe.mark(1, s);
+    unsigned long long *cnt = nullptr;
+    if (op->prec == MBEM_FP64) {
+        MBEM_TRY((launch_regular<double, double>(op, 0, m->d_qp, nullptr, s)));
+        pe.mark(2, s);
+        pe.mark(3, s);
+        MBEM_TRY(launch_ssq<double>(op, s));
+    } else {
+        MBEM_HIP(hipMallocAsync((void **)&cnt, sizeof(unsigned long long), s));
+        MBEM_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
+        pe.mark(1, s);
+        MBEM_TRY((launch_regular<float, float>(op, 1, m->d_qp32, nullptr, s)));
+        pe.mark(2, s);
+        MBEM_TRY((launch_regular<double, float>(op, 2, m->d_qp, cnt, s)));
+        pe.mark(3, s);
+        MBEM_TRY(launch_ssq<float>(op, s));
+    }
+    pe.mark(4, s);
+    MBEM_TRY(mass_run(op, s));
+    pe.mark(5, s);
+    MBEM_HIP(hipStreamSynchronize(s));
+    if (cnt) {
+        unsigned long long h = 0;
+        MBEM_HIP(hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost));
+        MBEM_HIP(hipFree(cnt));
+        op->n_near = (int64_t)h;
+    }
+    op->t_phase[0] = pe.ms(0, 1);
+    op->t_phase[1] = pe.ms(1, 2);
+    op->t_phase[2] = pe.ms(2, 3);
+    op->t_phase[3] = pe.ms(3, 4);
+    op->t_phase[4] = pe.ms(4, 5);
+    return MBEM_OK;
+}
+
+}  // namespace mbem

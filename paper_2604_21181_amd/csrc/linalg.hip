@@ -1,0 +1,560 @@
+// Matrix-vector product with the stored Galerkin operator, export of Z, the
+// Morton block-Jacobi preconditioner (Sec. 5) and the vector kernels of
+// GMRES.
+//
+// Z is applied from its three distinct dense blocks and the sparse mass
+// matrix (eq. global_system):
+//   y_j  = (i/w) K1 x_j + K2^eps x_m + c_eps (M (x) I2) x_m
+//   y_m  = K2^mu x_j + c_mu (M (x) I2) x_j - (i/w) K1 x_m
+// so every dense entry is read once per product; K1 feeds two dot products.
+#include <type_traits>
+
+#include "mbem_internal.h"
+
+namespace mbem {
+
+constexpr int kW = 64;
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ inline double2 cadd(double2 a, double2 b) { return {a.x + b.x, a.y + b.y}; }
+__device__ inline double2 csub(double2 a, double2 b) { return {a.x - b.x, a.y - b.y}; }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = kW / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kW);
+    return v;
+}
+
+// ---------------------------------------------------------------- GEMV --
+// One wavefront per stored row; lanes stream the row with 16-byte loads.
+// The c64 variant loads two entries per lane per step and accumulates in
+// FP64.
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf4 __attribute__((ext_vector_type(4)));
+// streaming loads of the matrix: each entry is used exactly once per product
+__device__ inline double2 ntload(const double2 *p) {
+    const nd2 v = __builtin_nontemporal_load(reinterpret_cast<const nd2 *>(p));
+    return {v.x, v.y};
+}
+__device__ inline float4 ntload(const float4 *p) {
+    const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4 *>(p));
+    return {v.x, v.y, v.z, v.w};
+}
+
+template <int NV>
+__device__ inline void row_dots_c128(const double2 *__restrict__ row, int64_t n,
+                                     const double2 *const xs[NV], double2 out[NV]) {
+    const int lane = threadIdx.x % kW;
+    double re[NV], im[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) re[v] = im[v] = 0.0;
+    int64_t c = lane;
+    for (; c + 3 * kW < n; c += 4 * kW) {
+        double2 z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) z[u] = ntload(row + c + u * kW);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double2 x = xs[v][c + u * kW];
+                re[v] += z[u].x * x.x - z[u].y * x.y;
+                im[v] += z[u].x * x.y + z[u].y * x.x;
+            }
+    }
+    for (; c < n; c += kW) {
+        const double2 z = ntload(row + c);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double2 x = xs[v][c];
+            re[v] += z.x * x.x - z.y * x.y;
+            im[v] += z.x * x.y + z.y * x.x;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = {wave_sum(re[v]), wave_sum(im[v])};
+}
+
+template <int NV>
+__device__ inline void row_dots_c64(const float2 *__restrict__ row, int64_t n,
+                                    const double2 *const xs[NV], double2 out[NV]) {
+    const int lane = threadIdx.x % kW;
+    double re[NV], im[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) re[v] = im[v] = 0.0;
+    const float4 *r4 = reinterpret_cast<const float4 *>(row);
+    const int64_t n4 = n / 2;   // n is even (2 unknowns per node)
+    int64_t c = lane;
+    for (; c + kW < n4; c += 2 * kW) {
+        const float4 z0 = ntload(r4 + c);
+        const float4 z1 = ntload(r4 + c + kW);
+        const float4 zz[2] = {z0, z1};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t col = 2 * (c + u * kW);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double2 x0 = xs[v][col], x1 = xs[v][col + 1];
+                re[v] += (double)zz[u].x * x0.x - (double)zz[u].y * x0.y +
+                         (double)zz[u].z * x1.x - (double)zz[u].w * x1.y;
+                im[v] += (double)zz[u].x * x0.y + (double)zz[u].y * x0.x +
+                         (double)zz[u].z * x1.y + (double)zz[u].w * x1.x;
+            }
+        }
+    }
+    for (; c < n4; c += kW) {
+        const float4 z = ntload(r4 + c);
+        const int64_t col = 2 * c;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double2 x0 = xs[v][col], x1 = xs[v][col + 1];
+            re[v] += (double)z.x * x0.x - (double)z.y * x0.y + (double)z.z * x1.x - (double)z.w * x1.y;
+            im[v] += (double)z.x * x0.y + (double)z.y * x0.x + (double)z.z * x1.y + (double)z.w * x1.x;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = {wave_sum(re[v]), wave_sum(im[v])};
+}
+
+// t[0] = K1 x_j, t[1] = K1 x_m, t[2] = K2e x_m, t[3] = K2m x_j (each n2).
+template <typename TS>
+__global__ __launch_bounds__(256) void k_gemv3(int64_t n2, const TS *K1, const TS *K2e,
+                                               const TS *K2m, const double2 *xj,
+                                               const double2 *xm, double2 *t) {
+    const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kW;
+    if (wid >= 3 * n2) return;
+    const int blk = (int)(wid / n2);
+    const int64_t r = wid % n2;
+    const int lane = threadIdx.x % kW;
+    if (blk == 0) {
+        const double2 *xs[2] = {xj, xm};
+        double2 o[2];
+        if constexpr (std::is_same<TS, double2>::value) row_dots_c128<2>((const double2 *)K1 + r * n2, n2, xs, o);
+        else row_dots_c64<2>((const float2 *)K1 + r * n2, n2, xs, o);
+        if (lane == 0) { t[r] = o[0]; t[n2 + r] = o[1]; }
+    } else {
+        const TS *K = blk == 1 ? K2e : K2m;
+        const double2 *xs[1] = {blk == 1 ? xm : xj};
+        double2 o[1];
+        if constexpr (std::is_same<TS, double2>::value) row_dots_c128<1>((const double2 *)K + r * n2, n2, xs, o);
+        else row_dots_c64<1>((const float2 *)K + r * n2, n2, xs, o);
+        if (lane == 0) t[(1 + blk) * n2 + r] = o[0];
+    }
+}
+
+struct Coef { double2 iw, ce, cm; };
+
+__global__ void k_combine(int64_t n2, const double2 *__restrict__ t,
+                          const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
+                          const double *__restrict__ mval, const double2 *__restrict__ xj,
+                          const double2 *__restrict__ xm, Coef c, double2 *__restrict__ y) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n2) return;
+    const int64_t i = r / 2;
+    const int al = (int)(r % 2);
+    double2 Mj = {0, 0}, Mm = {0, 0};
+    for (int32_t s = mptr[i]; s < mptr[i + 1]; ++s) {
+        const int64_t col = 2 * (int64_t)mcol[s] + al;
+        const double v = mval[s];
+        Mj.x += v * xj[col].x; Mj.y += v * xj[col].y;
+        Mm.x += v * xm[col].x; Mm.y += v * xm[col].y;
+    }
+    y[r] = cadd(cadd(cmul(c.iw, t[r]), t[2 * n2 + r]), cmul(c.ce, Mm));
+    y[n2 + r] = csub(cadd(t[3 * n2 + r], cmul(c.cm, Mj)), cmul(c.iw, t[n2 + r]));
+}
+
+static Coef coef_of(const mbem_op *op) { return {op->iw, op->ce, op->cm}; }
+
+int matvec_run(const mbem_op *op, const double2 *x, double2 *y, double2 *tmp, hipStream_t s) {
+    const int64_t n2 = op->n2;
+    const int64_t waves = 3 * n2;
+    const unsigned blocks = (unsigned)((waves * kW + 255) / 256);
+    if (op->prec == MBEM_FP64)
+        hipLaunchKernelGGL((k_gemv3<double2>), dim3(blocks), dim3(256), 0, s, n2,
+                           (const double2 *)op->K[0], (const double2 *)op->K[1],
+                           (const double2 *)op->K[2], x, x + n2, tmp);
+    else
+        hipLaunchKernelGGL((k_gemv3<float2>), dim3(blocks), dim3(256), 0, s, n2,
+                           (const float2 *)op->K[0], (const float2 *)op->K[1],
+                           (const float2 *)op->K[2], x, x + n2, tmp);
+    MBEM_HIP(hipGetLastError());
+    const mbem_mesh *m = op->mesh;
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, n2, tmp,
+                       m->d_mptr, m->d_mcol, op->d_mval, x, x + n2, coef_of(op), y);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+// ------------------------------------------------------- entries of Z --
+template <typename TS>
+__device__ inline double2 kval(const void *K, int64_t idx) {
+    if constexpr (std::is_same<TS, double2>::value) return ((const double2 *)K)[idx];
+    else { const float2 v = ((const float2 *)K)[idx]; return {(double)v.x, (double)v.y}; }
+}
+
+__device__ inline double mass_entry(const int32_t *mptr, const int32_t *mcol, const double *mval,
+                                    int64_t i, int64_t j) {
+    for (int32_t s = mptr[i]; s < mptr[i + 1]; ++s)
+        if (mcol[s] == j) return mval[s];
+    return 0.0;
+}
+
+// Z[(ci n2 + r), (cc n2 + q)] for current indices ci, cc in {0, 1}
+template <typename TS>
+__device__ inline double2 z_entry(const void *const K[3], const int32_t *mptr,
+                                  const int32_t *mcol, const double *mval, Coef c,
+                                  int64_t n2, int ci, int64_t r, int cc, int64_t q) {
+    const int64_t idx = r * n2 + q;
+    double2 z;
+    if (ci == 0 && cc == 0) z = cmul(c.iw, kval<TS>(K[0], idx));
+    else if (ci == 1 && cc == 1) { const double2 k = cmul(c.iw, kval<TS>(K[0], idx)); z = {-k.x, -k.y}; }
+    else {
+        z = kval<TS>(K[ci == 0 ? 1 : 2], idx);
+        if ((r % 2) == (q % 2)) {
+            const double mv = mass_entry(mptr, mcol, mval, r / 2, q / 2);
+            const double2 cf = ci == 0 ? c.ce : c.cm;
+            z.x += cf.x * mv; z.y += cf.y * mv;
+        }
+    }
+    return z;
+}
+
+template <typename TS>
+__global__ void k_export_dense(int64_t n2, const void *K0, const void *K1, const void *K2,
+                               const int32_t *mptr, const int32_t *mcol, const double *mval,
+                               Coef c, double2 *Z) {
+    const int64_t N = 2 * n2;
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= N * N) return;
+    const int64_t R = id / N, C = id % N;
+    const void *K[3] = {K0, K1, K2};
+    Z[id] = z_entry<TS>(K, mptr, mcol, mval, c, n2, (int)(R / n2), R % n2, (int)(C / n2), C % n2);
+}
+
+int export_dense_run(const mbem_op *op, double2 *Z, hipStream_t s) {
+    const int64_t N = 2 * op->n2;
+    const mbem_mesh *m = op->mesh;
+    const unsigned blocks = (unsigned)((N * N + 255) / 256);
+    if (op->prec == MBEM_FP64)
+        hipLaunchKernelGGL((k_export_dense<double2>), dim3(blocks), dim3(256), 0, s, op->n2,
+                           op->K[0], op->K[1], op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), Z);
+    else
+        hipLaunchKernelGGL((k_export_dense<float2>), dim3(blocks), dim3(256), 0, s, op->n2,
+                           op->K[0], op->K[1], op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), Z);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+__global__ void k_c64_to_c128(int64_t n, const float2 *a, double2 *b) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = {(double)a[i].x, (double)a[i].y};
+}
+
+int export_blocks_run(const mbem_op *op, double2 *K1, double2 *K2e, double2 *K2m, hipStream_t s) {
+    double2 *dst[3] = {K1, K2e, K2m};
+    const int64_t n = op->n2 * op->n2;
+    for (int o = 0; o < 3; ++o) {
+        if (!dst[o]) continue;
+        if (op->prec == MBEM_FP64) {
+            MBEM_HIP(hipMemcpyAsync(dst[o], op->K[o], 16 * n, hipMemcpyDeviceToDevice, s));
+        } else {
+            hipLaunchKernelGGL(k_c64_to_c128, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                               (const float2 *)op->K[o], dst[o]);
+            MBEM_HIP(hipGetLastError());
+        }
+    }
+    return MBEM_OK;
+}
+
+// ------------------------------------------------- Morton block-Jacobi --
+// Block m covers indices I_m = [m B, m B + b) of each current (b = B except
+// possibly the last); A_m is the 2b x 2b restriction of Z to I_m in both
+// currents (eq. precond_block), stored with leading dimension 2B.
+template <typename TS>
+__global__ void k_mbj_gather(int64_t n2, int B, const void *K0, const void *K1, const void *K2,
+                             const int32_t *mptr, const int32_t *mcol, const double *mval,
+                             Coef c, double2 *A) {
+    const int m = blockIdx.y;
+    const int64_t b = min((int64_t)B, n2 - (int64_t)m * B);
+    const int64_t ld = 2 * B, n = 2 * b;
+    const void *K[3] = {K0, K1, K2};
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < n * n;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = id / n, q = id % n;
+        const int ci = r < b ? 0 : 1, cc = q < b ? 0 : 1;
+        const int64_t gr = (int64_t)m * B + (r % b), gq = (int64_t)m * B + (q % b);
+        A[(int64_t)m * ld * ld + r * ld + q] = z_entry<TS>(K, mptr, mcol, mval, c, n2, ci, gr, cc, gq);
+    }
+}
+
+// LU with partial pivoting (largest modulus), one workgroup per block.
+__global__ __launch_bounds__(1024) void k_mbj_lu(int64_t n2, int B, double2 *A, int32_t *piv,
+                                                 int32_t *info) {
+    __shared__ double s_v[1024];
+    __shared__ int s_i[1024];
+    const int m = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
+    const int b = (int)min((int64_t)B, n2 - (int64_t)m * B);
+    const int n = 2 * b, ld = 2 * B;
+    double2 *a = A + (int64_t)m * ld * ld;
+    int32_t *pv = piv + (int64_t)m * ld;
+    for (int k = 0; k < n; ++k) {
+        double best = -1.0;
+        int bi = k;
+        for (int i = k + tid; i < n; i += nth) {
+            const double2 v = a[(int64_t)i * ld + k];
+            const double mag = v.x * v.x + v.y * v.y;
+            if (mag > best) { best = mag; bi = i; }
+        }
+        s_v[tid] = best;
+        s_i[tid] = bi;
+        __syncthreads();
+        for (int off = nth / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                const double o = s_v[tid + off];
+                const int oi = s_i[tid + off];
+                if (o > s_v[tid] || (o == s_v[tid] && oi < s_i[tid])) { s_v[tid] = o; s_i[tid] = oi; }
+            }
+            __syncthreads();
+        }
+        const int p = s_i[0];
+        const bool zero = !(s_v[0] > 0.0);
+        __syncthreads();
+        if (tid == 0) { pv[k] = p; if (zero && *info == 0) *info = m + 1; }
+        if (zero) continue;
+        if (p != k)
+            for (int q = tid; q < n; q += nth) {
+                const double2 t = a[(int64_t)k * ld + q];
+                a[(int64_t)k * ld + q] = a[(int64_t)p * ld + q];
+                a[(int64_t)p * ld + q] = t;
+            }
+        __syncthreads();
+        const double2 d = a[(int64_t)k * ld + k];
+        const double dn = d.x * d.x + d.y * d.y;
+        const double2 inv = {d.x / dn, -d.y / dn};
+        for (int i = k + 1 + tid; i < n; i += nth) a[(int64_t)i * ld + k] = cmul(a[(int64_t)i * ld + k], inv);
+        __syncthreads();
+        const int rest = n - k - 1;
+        for (int64_t id = tid; id < (int64_t)rest * rest; id += nth) {
+            const int i = k + 1 + (int)(id / rest), q = k + 1 + (int)(id % rest);
+            const double2 l = a[(int64_t)i * ld + k], u = a[(int64_t)k * ld + q];
+            double2 &t = a[(int64_t)i * ld + q];
+            t = csub(t, cmul(l, u));
+        }
+        __syncthreads();
+    }
+}
+
+// Inverse from the factors: thread j solves L U x = P e_j for column j.
+__global__ __launch_bounds__(1024) void k_mbj_inverse(int64_t n2, int B, const double2 *A,
+                                                      const int32_t *piv, double2 *Minv) {
+    const int m = blockIdx.x, j = threadIdx.x;
+    const int b = (int)min((int64_t)B, n2 - (int64_t)m * B);
+    const int n = 2 * b, ld = 2 * B;
+    if (j >= n) return;
+    const double2 *a = A + (int64_t)m * ld * ld;
+    const int32_t *pv = piv + (int64_t)m * ld;
+    double2 *x = Minv + (int64_t)m * ld * ld;
+    for (int i = 0; i < n; ++i) x[(int64_t)i * ld + j] = {i == j ? 1.0 : 0.0, 0.0};
+    for (int k = 0; k < n; ++k) {
+        const int p = pv[k];
+        if (p != k) {
+            const double2 t = x[(int64_t)k * ld + j];
+            x[(int64_t)k * ld + j] = x[(int64_t)p * ld + j];
+            x[(int64_t)p * ld + j] = t;
+        }
+    }
+    for (int i = 1; i < n; ++i) {
+        double2 s = x[(int64_t)i * ld + j];
+        for (int k = 0; k < i; ++k) s = csub(s, cmul(a[(int64_t)i * ld + k], x[(int64_t)k * ld + j]));
+        x[(int64_t)i * ld + j] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double2 s = x[(int64_t)i * ld + j];
+        for (int k = i + 1; k < n; ++k) s = csub(s, cmul(a[(int64_t)i * ld + k], x[(int64_t)k * ld + j]));
+        const double2 d = a[(int64_t)i * ld + i];
+        const double dn = d.x * d.x + d.y * d.y;
+        x[(int64_t)i * ld + j] = cmul(s, double2{d.x / dn, -d.y / dn});
+    }
+}
+
+// z = blockdiag(A_m^-1) v; one wavefront per row of a block.
+__global__ __launch_bounds__(256) void k_mbj_apply(int64_t n2, int B, int nb, const double2 *Minv,
+                                                   const double2 *v, double2 *z) {
+    const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kW;
+    const int lane = threadIdx.x % kW;
+    const int64_t ld = 2 * B;
+    const int64_t m = wid / ld, r = wid % ld;
+    if (m >= nb) return;
+    const int64_t b = min((int64_t)B, n2 - m * B);
+    const int64_t n = 2 * b;
+    if (r >= n) return;
+    const double2 *row = Minv + m * ld * ld + r * ld;
+    double re = 0, im = 0;
+    for (int64_t q = lane; q < n; q += kW) {
+        const int64_t g = (q < b ? 0 : n2) + m * B + (q % b);
+        const double2 a = row[q], x = v[g];
+        re += a.x * x.x - a.y * x.y;
+        im += a.x * x.y + a.y * x.x;
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) z[(r < b ? 0 : n2) + m * B + (r % b)] = {re, im};
+}
+
+int mbj_setup_run(mbem_op *op, int B, hipStream_t s) {
+    if (op->d_minv) { MBEM_HIP(hipFree(op->d_minv)); op->d_minv = nullptr; }
+    if (op->d_lu) { MBEM_HIP(hipFree(op->d_lu)); op->d_lu = nullptr; }
+    op->B = 0; op->nb = 0;
+    if (B <= 0) return MBEM_OK;
+    if (B > 512) { set_error("preconditioner block above 512 is not supported"); return MBEM_EINVAL; }
+    const int64_t n2 = op->n2;
+    if (B > n2) B = (int)n2;
+    const int nb = (int)((n2 + B - 1) / B);
+    const int64_t ld = 2 * (int64_t)B;
+    const size_t bytes = sizeof(double2) * nb * ld * ld;
+    MBEM_HIP(hipMalloc((void **)&op->d_minv, bytes));
+    MBEM_HIP(hipMalloc((void **)&op->d_lu, bytes + sizeof(int32_t) * (nb * ld + 1)));
+    int32_t *piv = (int32_t *)((char *)op->d_lu + bytes);
+    int32_t *info = piv + nb * ld;
+    MBEM_HIP(hipMemsetAsync(info, 0, sizeof(int32_t), s));
+    const mbem_mesh *m = op->mesh;
+    dim3 g(64, nb);
+    if (op->prec == MBEM_FP64)
+        hipLaunchKernelGGL((k_mbj_gather<double2>), g, dim3(256), 0, s, n2, B, op->K[0], op->K[1],
+                           op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), op->d_lu);
+    else
+        hipLaunchKernelGGL((k_mbj_gather<float2>), g, dim3(256), 0, s, n2, B, op->K[0], op->K[1],
+                           op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), op->d_lu);
+    MBEM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_mbj_lu, dim3(nb), dim3(1024), 0, s, n2, B, op->d_lu, piv, info);
+    MBEM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_mbj_inverse, dim3(nb), dim3(1024), 0, s, n2, B, op->d_lu, piv, op->d_minv);
+    MBEM_HIP(hipGetLastError());
+    int32_t h = 0;
+    MBEM_HIP(hipMemcpyAsync(&h, info, sizeof(h), hipMemcpyDeviceToHost, s));
+    MBEM_HIP(hipStreamSynchronize(s));
+    MBEM_HIP(hipFree(op->d_lu));
+    op->d_lu = nullptr;
+    if (h) {
+        set_error("zero pivot in preconditioner block " + std::to_string(h - 1));
+        MBEM_HIP(hipFree(op->d_minv));
+        op->d_minv = nullptr;
+        return MBEM_ESINGULAR;
+    }
+    op->B = B;
+    op->nb = nb;
+    return MBEM_OK;
+}
+
+int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z, hipStream_t s) {
+    if (!op->d_minv) {
+        MBEM_HIP(hipMemcpyAsync(z, v, sizeof(double2) * 2 * op->n2, hipMemcpyDeviceToDevice, s));
+        return MBEM_OK;
+    }
+    const int64_t rows = (int64_t)op->nb * 2 * op->B;
+    hipLaunchKernelGGL(k_mbj_apply, dim3((unsigned)((rows * kW + 255) / 256)), dim3(256), 0, s,
+                       op->n2, op->B, op->nb, op->d_minv, v, z);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+// ---------------------------------------------------- GMRES vectors ---
+// out[j] = sum_n conj(V[j][n]) w[n], j = 0..k-1 (one workgroup per j)
+__global__ __launch_bounds__(256) void k_dots(const double2 *V, int64_t ldv, const double2 *w,
+                                              int64_t n, double2 *out) {
+    __shared__ double s_re[4], s_im[4];
+    const int j = blockIdx.x;
+    const double2 *v = V + (int64_t)j * ldv;
+    double re = 0, im = 0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double2 a = v[i], b = w[i];
+        re += a.x * b.x + a.y * b.y;
+        im += a.x * b.y - a.y * b.x;
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    const int wv = threadIdx.x / kW;
+    if (threadIdx.x % kW == 0) { s_re[wv] = re; s_im[wv] = im; }
+    __syncthreads();
+    if (threadIdx.x == 0) out[j] = {s_re[0] + s_re[1] + s_re[2] + s_re[3], s_im[0] + s_im[1] + s_im[2] + s_im[3]};
+}
+
+// w[n] -= sum_j V[j][n] h[j]
+__global__ void k_update(double2 *w, const double2 *V, int64_t ldv, int k, const double2 *h, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 s = w[i];
+    for (int j = 0; j < k; ++j) s = csub(s, cmul(V[(int64_t)j * ldv + i], h[j]));
+    w[i] = s;
+}
+
+// out[n] = sum_j V[j][n] y[j]
+__global__ void k_combine_basis(double2 *out, const double2 *V, int64_t ldv, int k, const double2 *y,
+                                int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 s = {0, 0};
+    for (int j = 0; j < k; ++j) s = cadd(s, cmul(V[(int64_t)j * ldv + i], y[j]));
+    out[i] = s;
+}
+
+__global__ __launch_bounds__(1024) void k_norm2(const double2 *v, int64_t n, double *out) {
+    __shared__ double s[16];
+    double a = 0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) a += v[i].x * v[i].x + v[i].y * v[i].y;
+    a = wave_sum(a);
+    if (threadIdx.x % kW == 0) s[threadIdx.x / kW] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int i = 0; i < (int)(blockDim.x / kW); ++i) t += s[i];
+        *out = sqrt(t);
+    }
+}
+
+__global__ void k_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = cmul(a, src[i]);
+}
+
+__global__ void k_axpy(double2 *y, const double2 *x, double2 a, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = cadd(y[i], cmul(a, x[i]));
+}
+
+static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+int vec_dots(const double2 *V, int64_t ldv, int k, const double2 *w, int64_t n, double2 *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_dots, dim3(k), dim3(256), 0, s, V, ldv, w, n, out);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+int vec_update(double2 *w, const double2 *V, int64_t ldv, int k, const double2 *h, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_update, dim3(nblk(n)), dim3(256), 0, s, w, V, ldv, k, h, n);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+int vec_combine(double2 *out, const double2 *V, int64_t ldv, int k, const double2 *y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_combine_basis, dim3(nblk(n)), dim3(256), 0, s, out, V, ldv, k, y, n);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+int vec_norm2(const double2 *v, int64_t n, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, s, v, n, out);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(nblk(n)), dim3(256), 0, s, dst, src, a, n);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+int vec_axpy(double2 *y, const double2 *x, double2 a, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, s, y, x, a, n);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+}  // namespace mbem

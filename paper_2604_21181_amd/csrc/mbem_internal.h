@@ -1,0 +1,160 @@
+// Internal declarations of the mbem library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mbem.h"
+
+namespace mbem {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const std::string &msg);
+
+#define MBEM_HIP(call)                                                       \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess) {                                              \
+            ::mbem::set_error(std::string(#call) + ": " +                    \
+                              hipGetErrorString(e_));                        \
+            return MBEM_EDEVICE;                                             \
+        }                                                                    \
+    } while (0)
+
+#define MBEM_TRY(call)                                                       \
+    do {                                                                     \
+        int s_ = (call);                                                     \
+        if (s_ != MBEM_OK) return s_;                                        \
+    } while (0)
+
+// ------------------------------------------------------------ constants --
+constexpr int kQP = 7;          // regular rule points per triangle
+constexpr int kQPF = 19;        // doubles per quadrature point in the table
+constexpr int kMaxSSQ = 8;      // largest Sauter-Schwab order supported
+// quadrature-point table fields (structure of arrays, each n_tris*7 long)
+enum QpField {
+    QX = 0, QW = 3, QN = 4, QT1 = 7, QT2 = 10, QS1 = 13, QS2 = 16
+};
+
+struct cplx {  // plain complex double for host-side bookkeeping
+    double re, im;
+};
+
+// ---------------------------------------------------------- handles --------
+}  // namespace mbem
+
+struct mbem_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+};
+
+struct mbem_mesh {
+    mbem_ctx *ctx = nullptr;
+    int64_t nn = 0, nt = 0;
+    std::vector<int64_t> node_order, tri_order;  // Morton position -> caller
+    std::vector<double> xyz;                     // Morton order [nn*3]
+    std::vector<int32_t> tri;                    // Morton numbering [nt*6]
+    double amax = 0.0;                           // max |x| over nodes
+    int64_t n_single[4] = {0, 0, 0, 0};          // ordered pairs per class
+    // device copies
+    double *d_xyz = nullptr;
+    int32_t *d_tri = nullptr;
+    int32_t *d_inc_ptr = nullptr;  // node -> (elem*8 + local) CSR
+    int32_t *d_inc = nullptr;
+    int32_t *d_spairs = nullptr;   // singular ordered pairs, int4 each
+    int64_t n_spairs = 0;
+    // geometry tables (rebuilt by every fill)
+    double *d_frames = nullptr;    // [nn][9]: n, t1, t2
+    double *d_qp = nullptr;        // [kQPF][nt*7]
+    float *d_qp32 = nullptr;       // [kQPF][nt*7]
+    double *d_elem = nullptr;      // [nt][4]: centroid, radius
+    // mass-matrix pattern (node CSR) and element -> CSR slot map
+    std::vector<int32_t> m_ptr, m_col;
+    int32_t *d_mptr = nullptr, *d_mcol = nullptr, *d_mslot = nullptr;
+};
+
+struct mbem_op {
+    mbem_ctx *ctx = nullptr;
+    const mbem_mesh *mesh = nullptr;
+    mbem_params p{};
+    int prec = MBEM_FP64;
+    int64_t n2 = 0;                 // 2 n_nodes: one current's length
+    double2 ka{}, ki{}, eps_i{}, mu_i{};
+    double2 iw{}, ce{}, cm{};       // i/omega, (eps_i+1)/2, (mu_i+1)/2
+    void *K[3] = {nullptr, nullptr, nullptr};  // c128 or c64 dense blocks
+    double *d_mval = nullptr;       // mass values on the node CSR pattern
+    int64_t n_near = 0;
+    double t_phase[5] = {0, 0, 0, 0, 0};  // geom, regular, near, ssq, mass (ms)
+    // Morton block-Jacobi
+    int32_t B = 0, nb = 0;
+    double2 *d_minv = nullptr;      // [nb][2B][2B] inverses
+    double2 *d_lu = nullptr;        // scratch of the factorisation
+    // solver workspace
+    double2 *d_work = nullptr;
+    size_t work_elems = 0;
+};
+
+namespace mbem {
+
+// host preprocessing (host_mesh.cpp)
+struct MeshTables {
+    std::vector<int32_t> inc_ptr, inc;      // node -> elem*8 + local
+    std::vector<int32_t> spairs;            // e, f, class, perm codes
+    int64_t n_single[4] = {0, 0, 0, 0};
+    std::vector<int32_t> m_ptr, m_col, m_slot;
+};
+int build_tables(const mbem_mesh *m, MeshTables &T);
+int build_mesh_host(const double *xyz, int64_t nn, const int64_t *tri6,
+                    int64_t nt, mbem_mesh *m);
+int morton_order_host(const double *xyz, int64_t nn, const int64_t *tri6,
+                      int64_t nt, std::vector<int64_t> &node_order,
+                      std::vector<int64_t> &tri_order);
+void gauss_legendre(int n, double *x, double *w);   // on [-1, 1]
+
+// geometry (geom.hip)
+int geom_build(const mbem_mesh *m, hipStream_t s);
+
+// fill (fill.hip)
+int fill_run(mbem_op *op, hipStream_t s);
+int mass_run(mbem_op *op, hipStream_t s);
+
+// linear algebra (linalg.hip)
+int matvec_run(const mbem_op *op, const double2 *x, double2 *y, double2 *tmp,
+               hipStream_t s);
+int export_dense_run(const mbem_op *op, double2 *Z, hipStream_t s);
+int export_blocks_run(const mbem_op *op, double2 *K1, double2 *K2e,
+                      double2 *K2m, hipStream_t s);
+int mbj_setup_run(mbem_op *op, int B, hipStream_t s);
+int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z,
+                  hipStream_t s);
+int vec_dots(const double2 *V, int64_t ldv, int k, const double2 *w,
+             int64_t n, double2 *out_dev, hipStream_t s);
+int vec_update(double2 *w, const double2 *V, int64_t ldv, int k,
+               const double2 *h_dev, int64_t n, hipStream_t s);
+int vec_norm2(const double2 *v, int64_t n, double *out_dev, hipStream_t s);
+int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n,
+                   hipStream_t s);
+int vec_axpy(double2 *y, const double2 *x, double2 a, int64_t n,
+             hipStream_t s);
+int vec_combine(double2 *out, const double2 *V, int64_t ldv, int k,
+                const double2 *y_dev, int64_t n, hipStream_t s);
+
+// post-processing (post.hip)
+int rhs_run(const mbem_mesh *m, const mbem_params *p, const double *khat,
+            const double2 *pol, int nrhs, double2 *b, hipStream_t s);
+int farfield_run(const mbem_mesh *m, const mbem_params *p, const double2 *x,
+                 int nrhs, const double *rhat, int64_t ndir, double2 *F,
+                 hipStream_t s);
+int absorbed_run(const mbem_mesh *m, const double2 *x, double *out_dev,
+                 hipStream_t s);
+int weighted_norm_run(int64_t ndir, const double2 *F, const double *w,
+                      double *out, hipStream_t s);
+
+// derived material constants
+void derive_constants(const mbem_params *p, double2 *ka, double2 *ki,
+                      double2 *eps_i, double2 *mu_i);
+
+}  // namespace mbem

@@ -1,0 +1,337 @@
+"""Thin Python binding of the mbem C ABI (include/mbem.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  torch provides device memory (tensor data pointers) and the
+stream.  Module-level functions carry the C names; ``Solver`` bundles the
+handles for convenience.  Importing this module without the built library
+raises immediately -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmbem.so")
+
+MBEM_OK, MBEM_EINVAL, MBEM_ENOMEM, MBEM_EDEVICE = 0, -1, -2, -3
+MBEM_ENOCONV, MBEM_ESINGULAR, MBEM_EMESH = -4, -5, -6
+MBEM_FP64, MBEM_MIXED = 0, 1
+
+EXPORTED = [
+    "mbem_ctx_create", "mbem_ctx_destroy", "mbem_mesh_create", "mbem_mesh_destroy",
+    "mbem_mesh_permutation", "mbem_mesh_info", "mbem_morton_order", "mbem_fill",
+    "mbem_op_destroy", "mbem_op_export_blocks", "mbem_op_export_dense", "mbem_matvec",
+    "mbem_precond_setup", "mbem_precond_apply", "mbem_rhs_planewave", "mbem_solve",
+    "mbem_farfield", "mbem_cross_sections", "mbem_last_error",
+]
+
+
+class MbemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mbem error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("k0", C.c_double), ("eps_r_re", C.c_double), ("eps_r_im", C.c_double),
+                ("mu_r_re", C.c_double), ("mu_r_im", C.c_double), ("ssq_order", C.c_int32),
+                ("precision", C.c_int32), ("near_radius", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("max_refine", C.c_int32),
+                ("inner_tol", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("outer_iters", C.c_int32), ("rel_resid", C.c_double),
+                ("t_fill_ms", C.c_double), ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
+                ("n_near_pairs", C.c_int64), ("t_geom_ms", C.c_double),
+                ("t_regular_ms", C.c_double), ("t_near_ms", C.c_double), ("t_ssq_ms", C.c_double),
+                ("t_mass_ms", C.c_double), ("t_matvec_ms", C.c_double), ("n_matvec", C.c_int32),
+                ("n_regular_pairs", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libmbem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2604_21181_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        P, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        PP = C.POINTER(C.c_void_p)
+        sig = {
+            "mbem_ctx_create": ([C.c_int, P, PP], C.c_int),
+            "mbem_ctx_destroy": ([P], None),
+            "mbem_mesh_create": ([P, P, i64, P, i64, PP], C.c_int),
+            "mbem_mesh_destroy": ([P], None),
+            "mbem_mesh_permutation": ([P, P, P], C.c_int),
+            "mbem_mesh_info": ([P, P], C.c_int),
+            "mbem_morton_order": ([P, i64, P, i64, P, P], C.c_int),
+            "mbem_fill": ([P, P, C.POINTER(Params), PP, C.POINTER(Stats)], C.c_int),
+            "mbem_op_destroy": ([P], None),
+            "mbem_op_export_blocks": ([P, P, P, P, P], C.c_int),
+            "mbem_op_export_dense": ([P, P, P], C.c_int),
+            "mbem_matvec": ([P, P, P, i32, P], C.c_int),
+            "mbem_precond_setup": ([P, P, i32, C.POINTER(Stats)], C.c_int),
+            "mbem_precond_apply": ([P, P, P, P], C.c_int),
+            "mbem_rhs_planewave": ([P, P, C.POINTER(Params), P, P, i32, P], C.c_int),
+            "mbem_solve": ([P, P, P, i32, C.POINTER(SolveOpts), P, C.POINTER(Stats)], C.c_int),
+            "mbem_farfield": ([P, P, C.POINTER(Params), P, i32, P, i64, P], C.c_int),
+            "mbem_cross_sections": ([P, P, C.POINTER(Params), P, P, P, i32, P], C.c_int),
+            "mbem_last_error": ([], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code, allow=()):
+    if code != MBEM_OK and code not in allow:
+        raise MbemError(code, lib().mbem_last_error().decode())
+    return code
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _t_ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------- C names --
+def mbem_ctx_create(device=0, stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device).cuda_stream
+    h = C.c_void_p()
+    _check(lib().mbem_ctx_create(device, C.c_void_p(stream), C.byref(h)))
+    return h
+
+
+def mbem_ctx_destroy(ctx):
+    lib().mbem_ctx_destroy(ctx)
+
+
+def mbem_mesh_create(ctx, xyz, tri6):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tri6 = np.ascontiguousarray(tri6, dtype=np.int64)
+    h = C.c_void_p()
+    _check(lib().mbem_mesh_create(ctx, _np_ptr(xyz), xyz.shape[0], _np_ptr(tri6), tri6.shape[0],
+                                  C.byref(h)))
+    return h
+
+
+def mbem_mesh_destroy(mesh):
+    lib().mbem_mesh_destroy(mesh)
+
+
+def mbem_mesh_info(mesh):
+    info = np.zeros(8, dtype=np.int64)
+    _check(lib().mbem_mesh_info(mesh, _np_ptr(info)))
+    return info
+
+
+def mbem_mesh_permutation(mesh):
+    n = mbem_mesh_info(mesh)
+    no = np.zeros(n[0], dtype=np.int64)
+    to = np.zeros(n[1], dtype=np.int64)
+    _check(lib().mbem_mesh_permutation(mesh, _np_ptr(no), _np_ptr(to)))
+    return no, to
+
+
+def mbem_morton_order(xyz, tri6):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tri6 = np.ascontiguousarray(tri6, dtype=np.int64)
+    no = np.zeros(xyz.shape[0], dtype=np.int64)
+    to = np.zeros(tri6.shape[0], dtype=np.int64)
+    _check(lib().mbem_morton_order(_np_ptr(xyz), xyz.shape[0], _np_ptr(tri6), tri6.shape[0],
+                                   _np_ptr(no), _np_ptr(to)))
+    return no, to
+
+
+def make_params(k0, eps_r, mu_r=1.0, precision=MBEM_FP64, ssq_order=4, near_radius=0.0):
+    e, m = complex(eps_r), complex(mu_r)
+    return Params(k0, e.real, e.imag, m.real, m.imag, ssq_order, precision, near_radius)
+
+
+def mbem_fill(ctx, mesh, params):
+    h = C.c_void_p()
+    st = Stats()
+    _check(lib().mbem_fill(ctx, mesh, C.byref(params), C.byref(h), C.byref(st)))
+    return h, st
+
+
+def mbem_op_destroy(op):
+    lib().mbem_op_destroy(op)
+
+
+def mbem_op_export_blocks(ctx, op, K1=None, K2e=None, K2m=None):
+    p = [_t_ptr(t) if t is not None else None for t in (K1, K2e, K2m)]
+    _check(lib().mbem_op_export_blocks(ctx, op, *p))
+
+
+def mbem_op_export_dense(ctx, op, Z):
+    _check(lib().mbem_op_export_dense(ctx, op, _t_ptr(Z)))
+
+
+def mbem_matvec(ctx, op, x, y, nrhs=1):
+    _check(lib().mbem_matvec(ctx, op, _t_ptr(x), nrhs, _t_ptr(y)))
+
+
+def mbem_precond_setup(ctx, op, block):
+    st = Stats()
+    _check(lib().mbem_precond_setup(ctx, op, block, C.byref(st)))
+    return st
+
+
+def mbem_precond_apply(ctx, op, v, z):
+    _check(lib().mbem_precond_apply(ctx, op, _t_ptr(v), _t_ptr(z)))
+
+
+def mbem_rhs_planewave(ctx, mesh, params, khat, pol, b):
+    khat = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+    pol = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.complex128)
+    _check(lib().mbem_rhs_planewave(ctx, mesh, C.byref(params), _np_ptr(khat), _np_ptr(pol),
+                                    khat.shape[0], _t_ptr(b)))
+
+
+def mbem_solve(ctx, op, b, x, nrhs, tol, maxit=500, max_refine=0, inner_tol=0.0):
+    o = SolveOpts(tol, maxit, max_refine, inner_tol)
+    st = Stats()
+    code = _check(lib().mbem_solve(ctx, op, _t_ptr(b), nrhs, C.byref(o), _t_ptr(x), C.byref(st)),
+                  allow=(MBEM_ENOCONV,))
+    return code, st
+
+
+def mbem_farfield(ctx, mesh, params, x, nrhs, rhat, F):
+    _check(lib().mbem_farfield(ctx, mesh, C.byref(params), _t_ptr(x), nrhs, _t_ptr(rhat),
+                               rhat.shape[0], _t_ptr(F)))
+
+
+def mbem_cross_sections(ctx, mesh, params, x, khat, pol, ntheta=0):
+    khat = np.ascontiguousarray(khat, dtype=np.float64)
+    pol = np.ascontiguousarray(pol, dtype=np.complex128)
+    out = np.zeros(3)
+    _check(lib().mbem_cross_sections(ctx, mesh, C.byref(params), _t_ptr(x), _np_ptr(khat),
+                                     _np_ptr(pol), ntheta, _np_ptr(out)))
+    return out
+
+
+# ------------------------------------------------------------- convenience --
+class Solver:
+    """Mesh + operator handles on one device; vectors are torch tensors in
+    Morton order (``to_morton`` / ``to_user`` map caller-ordered arrays)."""
+
+    def __init__(self, xyz, tri6, k0, eps_r, mu_r=1.0, precision=MBEM_FP64, ssq_order=4,
+                 device=0, near_radius=0.0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.ctx = mbem_ctx_create(device)
+        self.mesh = mbem_mesh_create(self.ctx, xyz, tri6)
+        info = mbem_mesh_info(self.mesh)
+        self.nn, self.nt, self.N = int(info[0]), int(info[1]), int(info[2])
+        self.n_singular = (int(info[3]), int(info[4]), int(info[5]))
+        self.node_order, self.tri_order = mbem_mesh_permutation(self.mesh)
+        self.params = make_params(k0, eps_r, mu_r, precision, ssq_order, near_radius)
+        self.op = None
+        self.fill_stats = None
+
+    # index map: x_morton = x_user[perm]
+    @property
+    def perm(self):
+        no = self.node_order
+        one = np.stack([2 * no, 2 * no + 1], 1).ravel()
+        return np.concatenate([one, 2 * self.nn + one])
+
+    def fill(self):
+        if self.op is not None:
+            mbem_op_destroy(self.op)
+        self.op, self.fill_stats = mbem_fill(self.ctx, self.mesh, self.params)
+        return self.fill_stats
+
+    def export_blocks(self):
+        t = self.torch
+        n2 = 2 * self.nn
+        K = [t.empty((n2, n2), dtype=t.complex128, device=self.device) for _ in range(3)]
+        mbem_op_export_blocks(self.ctx, self.op, *K)
+        t.cuda.synchronize()
+        return K
+
+    def export_dense(self):
+        t = self.torch
+        Z = t.empty((self.N, self.N), dtype=t.complex128, device=self.device)
+        mbem_op_export_dense(self.ctx, self.op, Z)
+        t.cuda.synchronize()
+        return Z
+
+    def matvec(self, x):
+        y = self.torch.empty_like(x)
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        mbem_matvec(self.ctx, self.op, x.contiguous(), y, nrhs)
+        return y
+
+    def precond_setup(self, block):
+        return mbem_precond_setup(self.ctx, self.op, block)
+
+    def precond_apply(self, v):
+        z = self.torch.empty_like(v)
+        mbem_precond_apply(self.ctx, self.op, v.contiguous(), z)
+        self.torch.cuda.synchronize()
+        return z
+
+    def rhs(self, khat, pol):
+        khat = np.atleast_2d(khat)
+        b = self.torch.empty((khat.shape[0], self.N), dtype=self.torch.complex128, device=self.device)
+        mbem_rhs_planewave(self.ctx, self.mesh, self.params, khat, pol, b)
+        return b
+
+    def solve(self, b, tol, maxit=500, max_refine=0, inner_tol=0.0):
+        b = b if b.dim() == 2 else b[None]
+        x = self.torch.empty_like(b)
+        code, st = mbem_solve(self.ctx, self.op, b.contiguous(), x, b.shape[0], tol, maxit,
+                              max_refine, inner_tol)
+        return x, st, code
+
+    def farfield(self, x, rhat):
+        t = self.torch
+        x = x if x.dim() == 2 else x[None]
+        r = t.as_tensor(np.ascontiguousarray(rhat, dtype=np.float64), device=self.device)
+        F = t.empty((x.shape[0], r.shape[0], 3), dtype=t.complex128, device=self.device)
+        mbem_farfield(self.ctx, self.mesh, self.params, x.contiguous(), x.shape[0], r, F)
+        return F
+
+    def cross_sections(self, x, khat, pol, ntheta=0):
+        return mbem_cross_sections(self.ctx, self.mesh, self.params, x.contiguous(), khat, pol, ntheta)
+
+    def close(self):
+        if self.op is not None:
+            mbem_op_destroy(self.op)
+            self.op = None
+        if self.mesh is not None:
+            mbem_mesh_destroy(self.mesh)
+            self.mesh = None
+        if self.ctx is not None:
+            mbem_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

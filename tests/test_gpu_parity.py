@@ -1,0 +1,179 @@
+"""GPU parity of the HIP path against the FP64 oracle (small meshes).
+
+Every comparison goes through the C ABI.  Tolerances:
+  FP64 path: 1e-12 of the block's largest entry (fill), 1e-10 (solution,
+             far field; the oracle solves by dense LU);
+  MIXED path: 2e-6 of the block's largest entry (complex64 storage and
+             FP32 far pairs: ~6e-8 rounding per stored entry plus FP32
+             kernel arithmetic), 1e-5 on far fields.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import core, galerkin, solver
+from workloads import icosphere_p2, uv_sphere_p2
+from workloads.configs import cut_plane_directions
+
+pytestmark = pytest.mark.gpu
+
+KH = np.array([0.0, 0.0, 1.0])
+POL = np.array([1.0, 0.0, 0.0], dtype=np.complex128)
+
+MESHES = {
+    # (mesh, k0, eps_r): the 80-triangle sphere of the small workload, and a
+    # latitude-longitude sphere whose 90 triangles leave a ragged trial tile
+    "sphere80": (lambda: icosphere_p2(80), 1.0, 4.0),
+    "uv90_lossy": (lambda: uv_sphere_p2(9, 6, (1.0, 1.0, 1.3)), 2.0, 3.0 + 0.5j),
+}
+
+
+def _mbem():
+    from paper_2604_21181_amd import mbem
+    return mbem
+
+
+@pytest.fixture(scope="module", params=list(MESHES))
+def case(request):
+    import torch
+    mesh, k0, eps = MESHES[request.param]
+    xyz, tri = mesh()
+    print(f"\n[case {request.param}: n_tris={tri.shape[0]} k0={k0} eps={eps}]", flush=True)
+    P = galerkin.Problem(xyz, tri, k0, eps)
+    K = core.fill(xyz, tri, P.phys)
+    M = galerkin.mass_matrix(P)
+    Z = galerkin.assemble(P, *K, M)
+    b = galerkin.planewave_rhs(P, KH[None], POL[None])[:, 0]
+    x = np.linalg.solve(Z, b)
+    S = _mbem().Solver(xyz, tri, k0, eps)
+    S.fill()
+    torch.cuda.synchronize()
+    yield dict(name=request.param, xyz=xyz, tri=tri, k0=k0, eps=eps, P=P, K=K, M=M, Z=Z, b=b,
+               x=x, S=S)
+    S.close()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def test_permutation_is_morton(case):
+    no, to = solver.morton_order(case["xyz"], case["tri"])
+    assert np.array_equal(case["S"].node_order, no)
+    assert np.array_equal(case["S"].tri_order, to)
+
+
+def test_singular_pair_counts(case):
+    tri = case["tri"]
+    cnt = {1: 0, 2: 0, 3: 0}
+    for e in range(tri.shape[0]):
+        s = set(tri[e, :3])
+        for f in range(tri.shape[0]):
+            c = len(s & set(tri[f, :3]))
+            if c:
+                cnt[c] += 1
+    assert case["S"].n_singular == (cnt[3], cnt[2], cnt[1])
+
+
+def test_fill_blocks_fp64(case):
+    S = case["S"]
+    p1 = S.perm[: 2 * S.nn]
+    Kg = [k.cpu().numpy() for k in S.export_blocks()]
+    for o in range(3):
+        Ko = case["K"][o][np.ix_(p1, p1)]
+        assert _rel(Kg[o], Ko) < 1e-12, (o, _rel(Kg[o], Ko))
+
+
+def test_export_dense_fp64(case):
+    S = case["S"]
+    p = S.perm
+    Zg = S.export_dense().cpu().numpy()
+    assert _rel(Zg, case["Z"][np.ix_(p, p)]) < 1e-12
+
+
+def test_matvec_fp64(case):
+    import torch
+    S = case["S"]
+    p = S.perm
+    rng = np.random.default_rng(11)
+    xs = rng.normal(size=(2, S.N)) + 1j * rng.normal(size=(2, S.N))
+    y = S.matvec(torch.as_tensor(xs, device=S.device)).cpu().numpy()
+    Zm = case["Z"][np.ix_(p, p)]
+    for r in range(2):
+        ref = Zm @ xs[r]
+        assert np.abs(y[r] - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_rhs(case):
+    S = case["S"]
+    b = S.rhs(KH[None], POL[None]).cpu().numpy()[0]
+    ref = case["b"][S.perm]
+    assert np.abs(b - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_precond_apply(case):
+    import torch
+    S = case["S"]
+    p = S.perm
+    Zm = case["Z"][np.ix_(p, p)]
+    for B in (50, 2 * S.nn):
+        S.precond_setup(B)
+        blocks = solver.mbj_matrices(Zm, B)
+        v = np.random.default_rng(3).normal(size=S.N) + 0j
+        z = S.precond_apply(torch.as_tensor(v, device=S.device)).cpu().numpy()
+        ref = solver.mbj_apply(blocks, v, B)
+        assert np.abs(z - ref).max() < 1e-10 * np.abs(ref).max(), B
+
+
+def test_solve_fp64_and_farfield(case):
+    import torch
+    S = case["S"]
+    S.precond_setup(100)
+    b = S.rhs(KH[None], POL[None])
+    x, st, code = S.solve(b, tol=1e-13, maxit=400)
+    assert code == 0 and st.rel_resid < 1e-12
+    xg = x.cpu().numpy()[0]
+    xo = case["x"][S.perm]
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-10
+    r = cut_plane_directions(360)
+    F = S.farfield(x, r).cpu().numpy()[0]
+    Fo = galerkin.far_field(case["P"], case["x"], r)
+    assert np.linalg.norm(F - Fo) / np.linalg.norm(Fo) < 1e-10
+    cs = S.cross_sections(x[0], KH, POL, ntheta=24)
+    co = galerkin.cross_sections(case["P"], case["x"], KH, POL, ntheta=24)
+    assert np.allclose(cs, co, rtol=1e-10, atol=1e-12 * abs(co[0]))
+
+
+def test_mixed_fill_and_solve(case):
+    mbem = _mbem()
+    S = mbem.Solver(case["xyz"], case["tri"], case["k0"], case["eps"], precision=mbem.MBEM_MIXED)
+    try:
+        st = S.fill()
+        p1 = S.perm[: 2 * S.nn]
+        Kg = [k.cpu().numpy() for k in S.export_blocks()]
+        for o in range(3):
+            assert _rel(Kg[o], case["K"][o][np.ix_(p1, p1)]) < 2e-6, o
+        S.precond_setup(100)
+        b = S.rhs(KH[None], POL[None])
+        x, sst, code = S.solve(b, tol=1e-12, maxit=300, inner_tol=1e-6)
+        assert code == 0
+        r = cut_plane_directions(360)
+        F = S.farfield(x, r).cpu().numpy()[0]
+        Fo = galerkin.far_field(case["P"], case["x"], r)
+        assert np.linalg.norm(F - Fo) / np.linalg.norm(Fo) < 1e-5
+    finally:
+        S.close()
+
+
+def test_invalid_mesh_is_rejected():
+    mbem = _mbem()
+    xyz, tri = icosphere_p2(80)
+    bad = tri.copy()
+    bad[0, [1, 2]] = bad[0, [2, 1]]            # flip one triangle
+    ctx = mbem.mbem_ctx_create(0)
+    try:
+        with pytest.raises(mbem.MbemError) as e:
+            mbem.mbem_mesh_create(ctx, xyz, bad)
+        assert e.value.code == mbem.MBEM_EMESH
+    finally:
+        mbem.mbem_ctx_destroy(ctx)

@@ -5,8 +5,8 @@ settings and seeded random vectors.  It holds none of the discretisation's
 arithmetic (no quadrature, no kernels, no frames), so the oracle and the HIP
 path can both consume it without sharing any computation.
 """
-from .meshes import icosphere_p2, mesh_counts
+from .meshes import icosphere_p2, mesh_counts, uv_sphere_p2
 from .configs import CONFIGS, get_config, planewaves, random_directions
 
-__all__ = ["icosphere_p2", "mesh_counts", "CONFIGS", "get_config",
+__all__ = ["icosphere_p2", "mesh_counts", "uv_sphere_p2", "CONFIGS", "get_config",
            "planewaves", "random_directions"]

@@ -99,3 +99,51 @@ def icosphere_p2(n_tris: int, axes=(1.0, 1.0, 1.0)):
     xyz = xyz * np.asarray(axes, dtype=np.float64)[None, :]
     assert xyz.shape[0] == mesh_counts(n_tris)[0]
     return np.ascontiguousarray(xyz), np.ascontiguousarray(tri6)
+
+
+def uv_sphere_p2(n_lon: int, n_lat: int, axes=(1.0, 1.0, 1.0)):
+    """Latitude-longitude triangulation of the unit sphere (two poles,
+    n_lat - 1 rings of n_lon vertices), P2 mid-edge nodes projected to the
+    sphere, oriented outward, then scaled by diag(axes).
+
+    n_tris = 2 n_lon (n_lat - 1); odd n_lon and even n_lat give a count
+    that is not a multiple of 4, and the poles have valence n_lon.
+    """
+    verts = [np.array([0.0, 0.0, 1.0])]
+    for k in range(1, n_lat):
+        th = math.pi * k / n_lat
+        for j in range(n_lon):
+            ph = 2 * math.pi * j / n_lon
+            verts.append(np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph),
+                                   math.cos(th)]))
+    verts.append(np.array([0.0, 0.0, -1.0]))
+    v = np.array(verts)
+    south = v.shape[0] - 1
+
+    def ring(k, j):
+        return 1 + (k - 1) * n_lon + (j % n_lon)
+
+    f = []
+    for j in range(n_lon):
+        f.append([0, ring(1, j), ring(1, j + 1)])
+        f.append([south, ring(n_lat - 1, j + 1), ring(n_lat - 1, j)])
+    for k in range(1, n_lat - 1):
+        for j in range(n_lon):
+            a, b = ring(k, j), ring(k, j + 1)
+            c, d = ring(k + 1, j), ring(k + 1, j + 1)
+            f += [[a, c, d], [a, d, b]]
+    f = _orient_outward(v, np.array(f, dtype=np.int64))
+    nv = v.shape[0]
+    edge_id, mids = {}, []
+    tri6 = np.zeros((f.shape[0], 6), dtype=np.int64)
+    for t, (a, b, c) in enumerate(f):
+        tri6[t, :3] = (a, b, c)
+        for k, (p, q) in enumerate(((a, b), (b, c), (c, a))):
+            key = (min(p, q), max(p, q))
+            if key not in edge_id:
+                m = v[p] + v[q]
+                mids.append(m / np.linalg.norm(m))
+                edge_id[key] = nv + len(mids) - 1
+            tri6[t, 3 + k] = edge_id[key]
+    xyz = np.concatenate([v, np.array(mids)], axis=0) * np.asarray(axes, dtype=np.float64)[None, :]
+    return np.ascontiguousarray(xyz), np.ascontiguousarray(tri6)
