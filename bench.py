@@ -1,0 +1,253 @@
+"""Benchmark of the nodal P2 Mueller hot path on one MI355X.
+
+Workload (default): the 1280-triangle unit sphere, k_a = 5, eps_r = 2.25,
+2562 nodes, N = 10248 complex unknowns, one x-polarised plane wave along
++z, 7-point regular rule, 4^4-point Sauter-Schwab rule, Morton block-Jacobi
+with B = 100, GMRES to 1e-8, far field at 360 angles of the xz plane.
+
+One step = the whole hot path, both precisions side by side:
+  FP64 : fill (geometry, all pair classes, mass) -> block-Jacobi setup ->
+         right-hand side -> GMRES -> far field
+  MIXED: the same with FP32 far pairs / complex64 storage and FP64
+         iterative refinement.
+Metric: Z-fill rate N^2 / t_fill (entries/s) of the mixed path when its far
+field is within 1e-6 of the FP64 path's, otherwise of the FP64 path; GMRES
+solve seconds of both are reported beside it.
+
+The roofline object describes the kernel with the largest device time per
+step, timed live with HIP events on the library's stream.  Its algorithmic
+work per launch is derived below; the CPU baseline is the FP64 oracle's
+dense fill on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU = 78.6      # TFLOP/s, MI355X vector FP64
+PEAK_FP32_VALU = 157.3     # TFLOP/s, MI355X vector FP32
+PEAK_HBM = 8000.0          # GB/s
+
+# Algorithmic flops of the regular-pair fill (FMA = 2 flops, every
+# transcendental call = 1).  Per point pair: distance and unit vector 13,
+# kernel differences 151 (two complex exponentials, f, g, phi for both
+# media, D0, df, dg and the two gradient scalars), twelve weighted kernel
+# values 155 -> 319.  Per element pair: trial-side contraction with the
+# shape functions 7*12*6*7 complex-by-real multiply-adds (4 flops) = 14112,
+# merge of a chunk's triangles by node 7*12*6 complex adds = 1008.  Per
+# trial chunk of 4 triangles with ns distinct nodes: test-side contraction
+# 6*12*ns*7 multiply-adds = 2016 ns.
+FLOP_POINT_PAIR = 319
+FLOP_PAIR_TRIAL = 14112 + 1008
+FLOP_CHUNK_TEST_PER_NODE = 2016
+CHUNK = 4
+# Sauter-Schwab: per point two P2 evaluations with frames (2 x 310), the
+# map and weights 20, kernel values 319, and the rank-one accumulation
+# into the 6 x 6 x 12 block 12 * (12 + 144) -> 2831.
+FLOP_SSQ_POINT = 2 * 310 + 20 + 319 + 12 * 156
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sphere1280")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--paths", default="fp64,mixed")
+    return ap.parse_args()
+
+
+def cpu_baseline(xyz, tri, cfg, N):
+    """FP64 oracle fill of the same mesh on the host cores."""
+    from oracle import core
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    phys = core.phys_vector(cfg["k0"], cfg["eps_r"], cfg["mu_r"])
+    core.lib()
+    t0 = time.perf_counter()
+    K = core.fill(xyz, tri, phys, nss=4, nthreads=threads)
+    dt = time.perf_counter() - t0
+    del K
+    return {"value": N * N / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
+            "sample": f"full FP64 dense fill (K1, K2eps, K2mu, all {tri.shape[0]}^2 element "
+                      f"pairs) of the same mesh, {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the method "
+              "is benchmarked on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2604_21181_amd import mbem
+    from workloads import get_config, icosphere_p2, planewaves
+    from workloads.configs import cut_plane_directions
+    from oracle import mie
+
+    cfg = get_config(args.workload)
+    xyz, tri = icosphere_p2(cfg["n_tris"], cfg["axes"])
+    khat, pol = planewaves(args.workload)
+    rdirs = cut_plane_directions(360)
+    paths = [p for p in args.paths.split(",") if p]
+    prec = {"fp64": mbem.MBEM_FP64, "mixed": mbem.MBEM_MIXED}
+    solvers = {p: mbem.Solver(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"], precision=prec[p])
+               for p in paths}
+    N = solvers[paths[0]].N
+    nt = tri.shape[0]
+
+    def step():
+        out = {}
+        for p in paths:
+            S = solvers[p]
+            fs = S.fill()
+            ps = S.precond_setup(cfg["mbj_block"])
+            b = S.rhs(khat, pol)
+            x, ss, code = S.solve(b, tol=cfg["tol"], maxit=600, inner_tol=1e-4)
+            F = S.farfield(x, rdirs)
+            out[p] = dict(fill=fs.as_dict(), setup_ms=ps.t_setup_ms, solve=ss.as_dict(), code=code,
+                          F=F, x=x)
+        return out
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    log(f"{args.workload}: {nt} triangles, N = {N}, paths {paths}")
+    for i in range(args.warmup):
+        step()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        recs.append(step())
+        log(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+
+    def mean(path, sect, key):
+        return float(np.mean([r[path][sect][key] for r in recs]))
+
+    res = {}
+    for p in paths:
+        res[p] = dict(
+            t_fill_ms=mean(p, "fill", "t_fill_ms"),
+            t_regular_ms=mean(p, "fill", "t_regular_ms"),
+            t_near_ms=mean(p, "fill", "t_near_ms"),
+            t_ssq_ms=mean(p, "fill", "t_ssq_ms"),
+            t_geom_ms=mean(p, "fill", "t_geom_ms"),
+            t_mass_ms=mean(p, "fill", "t_mass_ms"),
+            t_setup_ms=float(np.mean([r[p]["setup_ms"] for r in recs])),
+            t_solve_ms=mean(p, "solve", "t_solve_ms"),
+            t_matvec_ms=mean(p, "solve", "t_matvec_ms"),
+            n_matvec=int(recs[-1][p]["solve"]["n_matvec"]),
+            iters=int(recs[-1][p]["solve"]["iters"]),
+            outer=int(recs[-1][p]["solve"]["outer_iters"]),
+            rel_resid=float(recs[-1][p]["solve"]["rel_resid"]),
+            n_near=int(recs[-1][p]["fill"]["n_near_pairs"]),
+            n_regular=int(recs[-1][p]["fill"]["n_regular_pairs"]),
+        )
+        res[p]["fill_rate"] = N * N / (res[p]["t_fill_ms"] * 1e-3)
+
+    last = recs[-1]
+    ff = {p: last[p]["F"].cpu().numpy()[0] for p in paths}
+    info = {}
+    if "fp64" in paths and cfg["axes"] == (1.0, 1.0, 1.0):
+        Fm = mie.far_field(cfg["k0"], 1.0, cfg["eps_r"], rdirs)
+        info["farfield_err_fp64_vs_mie"] = float(np.linalg.norm(ff["fp64"] - Fm) / np.linalg.norm(Fm))
+    mixed_ok = False
+    if "fp64" in paths and "mixed" in paths:
+        e = float(np.linalg.norm(ff["mixed"] - ff["fp64"]) / np.linalg.norm(ff["fp64"]))
+        info["farfield_err_mixed_vs_fp64"] = e
+        mixed_ok = e <= 1e-6
+    head = "mixed" if (mixed_ok or paths == ["mixed"]) else paths[0]
+
+    # ---- roofline of the dominant kernel (largest device time per step)
+    cand = []
+    for p in paths:
+        r = res[p]
+        nm = r["n_matvec"]
+        cand.append((r["t_regular_ms"], "regular_pairs_" + p, p))
+        cand.append((r["t_ssq_ms"], "sauter_schwab_" + p, p))
+        if nm:
+            cand.append((r["t_matvec_ms"], "gemv_" + p, p))
+    cand.sort(reverse=True)
+    t_dom, kname, kp = cand[0]
+    r = res[kp]
+    n2 = N // 2
+    if kname.startswith("gemv"):
+        esz = 16 if kp == "fp64" else 8
+        traffic = 3 * n2 * n2 * esz + 2 * N * 16            # three blocks + x in, y out
+        per_launch_ms = r["t_matvec_ms"] / max(1, r["n_matvec"])
+        achieved = traffic / (per_launch_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM, "traffic": None, "kernel": "k_gemv3",
+                "algorithmic_bytes_per_launch": traffic, "launch_ms": per_launch_ms}
+    elif kname.startswith("regular"):
+        S = solvers[kp]
+        npairs = r["n_regular"]
+        rank = np.empty_like(S.node_order)
+        rank[S.node_order] = np.arange(S.nn)
+        tm = rank[tri[S.tri_order]]
+        ns = np.array([np.unique(tm[k:k + CHUNK]).size for k in range(0, nt, CHUNK)])
+        # every (test triangle, chunk) workgroup contracts ns test-side nodes
+        flops = (npairs * (49 * FLOP_POINT_PAIR + FLOP_PAIR_TRIAL)
+                 + nt * int(ns.sum()) * FLOP_CHUNK_TEST_PER_NODE)
+        achieved = flops / (r["t_regular_ms"] * 1e-3) / 1e12
+        peak = PEAK_FP64_VALU if kp == "fp64" else PEAK_FP32_VALU
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "kernel": "k_regular",
+                "algorithmic_flops_per_launch": flops, "launch_ms": r["t_regular_ms"]}
+    else:
+        S = solvers[kp]
+        ncoinc, nedge, nvert = S.n_singular
+        pts = (6 * ncoinc + 5 * nedge + 2 * nvert) * 256
+        flops = pts * FLOP_SSQ_POINT
+        achieved = flops / (r["t_ssq_ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_VALU, "traffic": None, "kernel": "k_ssq",
+                "algorithmic_flops_per_launch": flops, "launch_ms": r["t_ssq_ms"]}
+
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle fill")
+    cpu = None if args.no_cpu_baseline else cpu_baseline(xyz, tri, cfg, N)
+    line = {
+        "metric": "Z fill (entries/s) + GMRES solve s at 1e-6 far-field err; mixed vs FP64",
+        "value": res[head]["fill_rate"],
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64/f32+f64" if head == "mixed" else "c128/f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_tris": nt, "n_nodes": int(xyz.shape[0]),
+                   "unknowns": N, "k0": cfg["k0"], "eps_r": str(cfg["eps_r"]),
+                   "headline_path": head, "gmres_tol": cfg["tol"], "mbj_block": cfg["mbj_block"]},
+        "paths": {p: {k: v for k, v in res[p].items()} for p in paths},
+        "solve_s": {p: res[p]["t_solve_ms"] * 1e-3 for p in paths},
+        "accuracy": info,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    for S in solvers.values():
+        S.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -59,7 +59,8 @@ static int set_device(const mbem_ctx *ctx) {
 
 static void mesh_free_device(mbem_mesh *m) {
     void *ps[] = {m->d_xyz, m->d_tri, m->d_inc_ptr, m->d_inc, m->d_spairs, m->d_frames,
-                  m->d_qp, m->d_qp32, m->d_elem, m->d_mptr, m->d_mcol, m->d_mslot};
+                  m->d_qp, m->d_qp32, m->d_elem, m->d_mptr, m->d_mcol, m->d_mslot,
+                  m->d_chunks, m->d_tcol, m->d_ccol};
     for (void *p : ps) dfree(p);
 }
 
@@ -69,6 +70,7 @@ static void op_free_device(mbem_op *op) {
     dfree(op->d_minv);
     dfree(op->d_lu);
     dfree(op->d_work);
+    dfree(op->d_kconst);
 }
 
 // ---------------------------------------------------------------- GMRES --
@@ -88,9 +90,7 @@ struct Gmres {
     }
     int timed_matvec(const double2 *x, double2 *y) {
         (void)hipEventRecord(ev0, s);
-        MBEM_TRY(matvec_run(op, x, y, tmp, s));
-        (void)hipEventRecord(ev1, s);
-        return MBEM_OK;
+        return matvec_run(op, x, y, tmp, s, ev1);   // ev1 right after the GEMV
     }
     void collect() {   // after a synchronisation of the stream
         float t = 0.f;
@@ -254,11 +254,15 @@ int mbem_mesh_create(mbem_ctx *ctx, const double *xyz, int64_t n_nodes, const in
     for (int c = 0; c < 4; ++c) m->n_single[c] = T.n_single[c];
     m->m_ptr = T.m_ptr;
     m->m_col = T.m_col;
+    m->tcol_off = T.tcol_off;
+    m->ccol_off = T.ccol_off;
     const int64_t nq = m->nt * kQP;
     if ((st = upload(&m->d_xyz, m->xyz, s)) || (st = upload(&m->d_tri, m->tri, s)) ||
         (st = upload(&m->d_inc_ptr, T.inc_ptr, s)) || (st = upload(&m->d_inc, T.inc, s)) ||
         (st = upload(&m->d_spairs, T.spairs, s)) || (st = upload(&m->d_mptr, T.m_ptr, s)) ||
         (st = upload(&m->d_mcol, T.m_col, s)) || (st = upload(&m->d_mslot, T.m_slot, s)) ||
+        (st = upload(&m->d_chunks, T.chunks, s)) || (st = upload(&m->d_tcol, T.tcol_list, s)) ||
+        (st = upload(&m->d_ccol, T.ccol_list, s)) ||
         (st = dalloc(&m->d_frames, 9 * m->nn)) || (st = dalloc(&m->d_qp, kQPF * nq)) ||
         (st = dalloc(&m->d_qp32, kQPF * nq)) || (st = dalloc(&m->d_elem, 4 * m->nt)))
         return fail(st);

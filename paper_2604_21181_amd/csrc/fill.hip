@@ -11,6 +11,7 @@
 //  * MIXED precision: far regular pairs in FP32, near regular pairs and all
 //    singular pairs in FP64, everything accumulated into complex64 Z.
 #include <complex>
+#include <type_traits>
 
 #include "mbem_internal.h"
 #include "p2_device.h"
@@ -38,7 +39,7 @@ __device__ inline int64_t xcd_remap(int64_t bid, int64_t total) {
 //   kappa2_ab = G_chi [(t_a.t_b)(n.R) - (t_a.R)(n.t_b)],  R = (x - y)/|x - y|
 // output order c = 4 op + 2 a + b, op: K1, K2^eps, K2^mu.
 template <typename T>
-__device__ inline void kappa12(const KernelConst &K, vec3<T> x, vec3<T> n,
+__device__ __forceinline__ void kappa12(const KernelConst &K, vec3<T> x, vec3<T> n,
                                const vec3<T> ta[2], const vec3<T> sa[2],
                                vec3<T> y, const vec3<T> tb[2], T ww,
                                cx<T> out[12]) {
@@ -67,16 +68,32 @@ __device__ inline void kappa12(const KernelConst &K, vec3<T> x, vec3<T> n,
 }
 
 // ---------------------------------------------------- regular pairs ---
+// One workgroup per (test triangle e, trial chunk of kChunk Morton-
+// consecutive triangles); one launch per (test colour, chunk colour), so
+// that the workgroups of a launch write disjoint rows x columns of Z and
+// accumulate with plain read-modify-write (device-scope float atomics are
+// performed beyond the L2 on this multi-die part and are far slower).
+//  A: one point pair per lane (4 x 49 lanes): twelve weighted kernel values;
+//  B: trial-side contraction per triangle, Tf[fs][p][j][c] = sum_q kap N_j(q);
+//  B2: merge the chunk's triangles by node: Ts[p][slot][c] (a node shared by
+//      several trial triangles of the chunk is summed here, in LDS);
+//  C: test-side contraction, out[i][slot][c] = sum_p N_i(p) Ts[p][slot][c],
+//     added to Z once per (row, node) of the chunk; consecutive lanes walk
+//     along a row so that the accesses of a wavefront are contiguous.
 template <typename T, typename TS>
 struct RegArgs {
-    int64_t nt, n2, tiles_f, total;
+    int64_t nt, n2, n_te, n_ch, total;
+    const int32_t *te_list, *ch_list;   // this launch's colour classes
     const T *qp;            // [kQPF][nt*7]
+    const double *qp64;     // FP64 table (near pairs of the mixed path)
     const int32_t *tri;
+    const int32_t *chunks;  // kChunkRec ints per trial chunk
     const double *einfo;    // [nt][4]
     double near_r;
-    int mode;               // 0 all regular, 1 far only, 2 near only
+    int mode;               // 0: every regular pair in T; 1: pairs closer
+                            // than near_r in FP64, the others in T
     unsigned long long *near_count;
-    KernelConst K;
+    const KernelConst *K;   // device copy (uniform loads)
     TS *Z[3];
 };
 
@@ -85,91 +102,137 @@ __device__ inline vec3<T> qload(const T *qp, int64_t nq, int f, int64_t i) {
     return {qp[(int64_t)f * nq + i], qp[(int64_t)(f + 1) * nq + i], qp[(int64_t)(f + 2) * nq + i]};
 }
 
+constexpr int kPairLanes = 49 * kChunk;   // 196
+
 template <typename T, typename TS>
 __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
-    __shared__ cx<T> s_kap[4][49 * 12];
-    __shared__ cx<T> s_T[4][7 * 6 * 12];
-    __shared__ T s_N[7][6];   // shape function j at rule point q
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    // R1: point-pair kernel values, later the slot-merged trial contraction
+    __shared__ cx<T> s_r1[kPairLanes * 12];
+    __shared__ cx<T> s_tf[kChunk * 7 * 6 * 12];
+    __shared__ T s_N[7][6];
+    __shared__ int32_t s_rec[kChunkRec];
+    __shared__ int32_t s_te[6];
+    __shared__ int s_act[kChunk];      // 0 skip, 1 compute in T, 2 in FP64
+    const int tid = threadIdx.x;
     const int64_t tile = xcd_remap(blockIdx.x, a.total);
-    const int64_t e = tile / a.tiles_f;
-    const int64_t f = (tile % a.tiles_f) * 4 + w;
-    if (threadIdx.x < 7) {
+    const int64_t e = a.te_list[tile / a.n_ch];
+    const int64_t ch = a.ch_list[tile % a.n_ch];
+    if (tid < 7) {
         double xi, eta, wq, N[6], d1[6], d2[6];
-        rule7(threadIdx.x, xi, eta, wq);
+        rule7(tid, xi, eta, wq);
         p2_shape(xi, eta, N, d1, d2);
-        for (int j = 0; j < 6; ++j) s_N[threadIdx.x][j] = (T)N[j];
+        for (int j = 0; j < 6; ++j) s_N[tid][j] = (T)N[j];
     }
-    // is (e, f) a regular pair handled by this launch?
-    bool active = f < a.nt;
-    if (active) {
-        const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) active = active && (te[i] != tf[j]);
-    }
-    if (active && a.mode != 0) {
-        const double *ce = a.einfo + 4 * e, *cf = a.einfo + 4 * f;
-        const double dx = ce[0] - cf[0], dy = ce[1] - cf[1], dz = ce[2] - cf[2];
-        const double gap = sqrt(dx * dx + dy * dy + dz * dz) - ce[3] - cf[3];
-        const bool near = gap < a.near_r;
-        active = (a.mode == 2) ? near : !near;
-        if (active && a.mode == 2 && lane == 0) atomicAdd(a.near_count, 1ull);
-    }
-    const int64_t nq = a.nt * kQP;
-    // phase A: one point pair per lane
-    if (active && lane < 49) {
-        const int p = lane / 7, q = lane % 7;
-        const int64_t ix = e * kQP + p, iy = f * kQP + q;
-        const vec3<T> x = qload(a.qp, nq, QX, ix), n = qload(a.qp, nq, QN, ix);
-        const vec3<T> ta[2] = {qload(a.qp, nq, QT1, ix), qload(a.qp, nq, QT2, ix)};
-        const vec3<T> sa[2] = {qload(a.qp, nq, QS1, ix), qload(a.qp, nq, QS2, ix)};
-        const vec3<T> y = qload(a.qp, nq, QX, iy);
-        const vec3<T> tb[2] = {qload(a.qp, nq, QT1, iy), qload(a.qp, nq, QT2, iy)};
-        const T ww = a.qp[(int64_t)QW * nq + ix] * a.qp[(int64_t)QW * nq + iy];
-        cx<T> k[12];
-        kappa12<T>(a.K, x, n, ta, sa, y, tb, ww, k);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) s_kap[w][lane * 12 + c] = k[c];
+    for (int i = tid; i < kChunkRec; i += blockDim.x) s_rec[i] = a.chunks[ch * kChunkRec + i];
+    if (tid < 6) s_te[tid] = a.tri[6 * e + tid];
+    if (tid < kChunk) {
+        const int64_t f = ch * kChunk + tid;
+        bool act = f < a.nt;
+        if (act) {
+            const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) act = act && (te[i] != tf[j]);
+        }
+        int kind = act ? 1 : 0;
+        if (act && a.mode == 1) {
+            const double *ce = a.einfo + 4 * e, *cf = a.einfo + 4 * f;
+            const double dx = ce[0] - cf[0], dy = ce[1] - cf[1], dz = ce[2] - cf[2];
+            if (sqrt(dx * dx + dy * dy + dz * dz) - ce[3] - cf[3] < a.near_r) {
+                kind = 2;
+                atomicAdd(a.near_count, 1ull);
+            }
+        }
+        s_act[tid] = kind;
     }
     __syncthreads();
-    // phase B: contract the trial side, T[p][j][c] = sum_q kap[p][q][c] N_j(q)
-    if (active) {
-        for (int it = lane; it < 7 * 12; it += kWave) {
-            const int p = it / 12, c = it % 12;
-            cx<T> kv[7];
+    int any = 0;
 #pragma unroll
-            for (int q = 0; q < 7; ++q) kv[q] = s_kap[w][(p * 7 + q) * 12 + c];
+    for (int k = 0; k < kChunk; ++k) any |= s_act[k];
+    if (!any) return;                          // uniform over the workgroup
+    const int64_t nq = a.nt * kQP;
+    // A: kernel values
+    if (tid < kPairLanes) {
+        const int fs = tid / 49, r = tid % 49, p = r / 7, q = r % 7;
+        cx<T> k[12];
+        const int kind = s_act[fs];
+        const int64_t ix = e * kQP + p, iy = (ch * kChunk + fs) * kQP + q;
+        if (kind == 1) {
+            const vec3<T> x = qload(a.qp, nq, QX, ix), n = qload(a.qp, nq, QN, ix);
+            const vec3<T> ta[2] = {qload(a.qp, nq, QT1, ix), qload(a.qp, nq, QT2, ix)};
+            const vec3<T> sa[2] = {qload(a.qp, nq, QS1, ix), qload(a.qp, nq, QS2, ix)};
+            const vec3<T> y = qload(a.qp, nq, QX, iy);
+            const vec3<T> tb[2] = {qload(a.qp, nq, QT1, iy), qload(a.qp, nq, QT2, iy)};
+            const T ww = a.qp[(int64_t)QW * nq + ix] * a.qp[(int64_t)QW * nq + iy];
+            kappa12<T>(*a.K, x, n, ta, sa, y, tb, ww, k);
+        } else if (!std::is_same<T, double>::value && kind == 2) {
+            // near pair: FP64 kernel differences (cancellation), then rounded
+            const double *q64 = a.qp64;
+            const dvec3 x = qload(q64, nq, QX, ix), n = qload(q64, nq, QN, ix);
+            const dvec3 ta[2] = {qload(q64, nq, QT1, ix), qload(q64, nq, QT2, ix)};
+            const dvec3 sa[2] = {qload(q64, nq, QS1, ix), qload(q64, nq, QS2, ix)};
+            const dvec3 y = qload(q64, nq, QX, iy);
+            const dvec3 tb[2] = {qload(q64, nq, QT1, iy), qload(q64, nq, QT2, iy)};
+            const double ww = q64[(int64_t)QW * nq + ix] * q64[(int64_t)QW * nq + iy];
+            cx<double> kd[12];
+            kappa12<double>(*a.K, x, n, ta, sa, y, tb, ww, kd);
 #pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                cx<T> acc = {0, 0};
+            for (int c = 0; c < 12; ++c) k[c] = cx<T>{(T)kd[c].re, (T)kd[c].im};
+        } else {
 #pragma unroll
-                for (int q = 0; q < 7; ++q) acc = acc + s_N[q][j] * kv[q];
-                s_T[w][(p * 6 + j) * 12 + c] = acc;
-            }
+            for (int c = 0; c < 12; ++c) k[c] = cx<T>{0, 0};
+        }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) s_r1[tid * 12 + c] = k[c];
+    }
+    __syncthreads();
+    // B: trial side per triangle
+    for (int it = tid; it < kChunk * 7 * 12; it += blockDim.x) {
+        const int fs = it / 84, rem = it % 84, p = rem / 12, c = rem % 12;
+        cx<T> kv[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) kv[q] = s_r1[(fs * 49 + p * 7 + q) * 12 + c];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            cx<T> acc = {0, 0};
+#pragma unroll
+            for (int q = 0; q < 7; ++q) acc = acc + s_N[q][j] * kv[q];
+            s_tf[((fs * 7 + p) * 6 + j) * 12 + c] = acc;
         }
     }
     __syncthreads();
-    // phase C: contract the test side and add to Z
-    if (active) {
-        const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
-        for (int it = lane; it < 6 * 12; it += kWave) {
-            const int j = it / 12, c = it % 12;
-            const int op = c / 4, al = (c / 2) % 2, be = c % 2;
-            cx<T> tv[7];
+    // B2: merge by node slot into R1: Ts[p][slot][c]
+    const int ns = s_rec[0];
+    for (int it = tid; it < 7 * ns * 12; it += blockDim.x) {
+        const int p = it / (ns * 12), rem = it % (ns * 12), sl = rem / 12, c = rem % 12;
+        cx<T> acc = {0, 0};
+        for (int u = s_rec[25 + sl]; u < s_rec[26 + sl]; ++u) {
+            const int fs = s_rec[50 + u] >> 3, loc = s_rec[50 + u] & 7;
+            acc = acc + s_tf[((fs * 7 + p) * 6 + loc) * 12 + c];
+        }
+        s_r1[(p * 24 + sl) * 12 + c] = acc;
+    }
+    __syncthreads();
+    // C: test side, lanes along (slot, beta) of one (op, alpha) row group
+    const int rowlen = 2 * ns;
+    for (int it = tid; it < 6 * rowlen; it += blockDim.x) {
+        const int g = it / rowlen, rem = it % rowlen;       // g = 2 op + alpha
+        const int sl = rem / 2, be = rem % 2;
+        const int op = g / 2, al = g % 2;
+        const int c = 4 * op + 2 * al + be;
+        cx<T> tv[7];
 #pragma unroll
-            for (int p = 0; p < 7; ++p) tv[p] = s_T[w][(p * 6 + j) * 12 + c];
-            const int64_t col = 2 * (int64_t)tf[j] + be;
-            TS *Z = a.Z[op];
+        for (int p = 0; p < 7; ++p) tv[p] = s_r1[(p * 24 + sl) * 12 + c];
+        const int64_t col = 2 * (int64_t)s_rec[1 + sl] + be;
+        TS *Z = a.Z[op];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) {
-                cx<T> acc = {0, 0};
+        for (int i = 0; i < 6; ++i) {
+            cx<T> acc = {0, 0};
 #pragma unroll
-                for (int p = 0; p < 7; ++p) acc = acc + s_N[p][i] * tv[p];
-                const int64_t row = 2 * (int64_t)te[i] + al;
-                TS *dst = Z + 2 * (row * a.n2 + col);
-                atomic_add(dst, acc.re);
-                atomic_add(dst + 1, acc.im);
-            }
+            for (int p = 0; p < 7; ++p) acc = acc + s_N[p][i] * tv[p];
+            const int64_t row = 2 * (int64_t)s_te[i] + al;
+            TS *dst = Z + 2 * (row * a.n2 + col);
+            dst[0] += (TS)acc.re;      // race-free: see the colouring above
+            dst[1] += (TS)acc.im;
         }
     }
 }
@@ -229,7 +292,7 @@ struct SsqArgs {
     const double *xyz, *frames;
     int order;
     double glx[kMaxSSQ], glw[kMaxSSQ];   // Gauss-Legendre on [0,1]
-    KernelConst K;
+    const KernelConst *K;   // device copy (uniform loads)
     TS *Z[3];
 };
 
@@ -271,7 +334,7 @@ __global__ __launch_bounds__(64) void k_ssq(SsqArgs<TS> a) {
             p2_point(a.xyz, a.frames, a.tri + 6 * f, xf, yf, Y);
             const dvec3 ta[2] = {X.t1, X.t2}, sa[2] = {X.s1, X.s2}, tb[2] = {Y.t1, Y.t2};
             cx<double> k[12];
-            kappa12<double>(a.K, X.x, X.n, ta, sa, Y.x, tb, wg * X.J * Y.J, k);
+            kappa12<double>(*a.K, X.x, X.n, ta, sa, Y.x, tb, wg * X.J * Y.J, k);
 #pragma unroll
             for (int q = 0; q < 12; ++q) { s_pt[lane][2 * q] = k[q].re; s_pt[lane][2 * q + 1] = k[q].im; }
 #pragma unroll
@@ -391,21 +454,31 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
     RegArgs<T, TS> a;
     a.nt = m->nt;
     a.n2 = op->n2;
-    a.tiles_f = (m->nt + 3) / 4;
-    a.total = m->nt * a.tiles_f;
     a.qp = qp;
+    a.qp64 = m->d_qp;
     a.tri = m->d_tri;
+    a.chunks = m->d_chunks;
     a.einfo = m->d_elem;
     a.mode = mode;
     a.near_count = cnt;
-    a.K = make_kconst(op);
+    a.K = op->d_kconst;
     double dk2 = std::abs(std::complex<double>(op->ka.x, op->ka.y) * std::complex<double>(op->ka.x, op->ka.y) -
                           std::complex<double>(op->ki.x, op->ki.y) * std::complex<double>(op->ki.x, op->ki.y));
     a.near_r = op->p.near_radius > 0 ? op->p.near_radius : (dk2 > 0 ? 1.89 / std::sqrt(dk2) : 0.0);
     for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)op->K[o];
-    if (a.total > 0x7fffffffLL) { set_error("too many element pairs for one launch"); return MBEM_EINVAL; }
-    hipLaunchKernelGGL((k_regular<T, TS>), dim3((unsigned)a.total), dim3(256), 0, s, a);
-    MBEM_HIP(hipGetLastError());
+    const int ntc = (int)m->tcol_off.size() - 1, ncc = (int)m->ccol_off.size() - 1;
+    for (int tc = 0; tc < ntc; ++tc)
+        for (int cc = 0; cc < ncc; ++cc) {
+            a.te_list = m->d_tcol + m->tcol_off[tc];
+            a.n_te = m->tcol_off[tc + 1] - m->tcol_off[tc];
+            a.ch_list = m->d_ccol + m->ccol_off[cc];
+            a.n_ch = m->ccol_off[cc + 1] - m->ccol_off[cc];
+            a.total = a.n_te * a.n_ch;
+            if (a.total == 0) continue;
+            if (a.total > 0x7fffffffLL) { set_error("too many element pairs for one launch"); return MBEM_EINVAL; }
+            hipLaunchKernelGGL((k_regular<T, TS>), dim3((unsigned)a.total), dim3(256), 0, s, a);
+            MBEM_HIP(hipGetLastError());
+        }
     return MBEM_OK;
 }
 
@@ -427,7 +500,7 @@ static int launch_ssq(mbem_op *op, hipStream_t s) {
         a.glx[i] = i < a.order ? 0.5 * (1.0 + x[a.order - 1 - i]) : 0.0;
         a.glw[i] = i < a.order ? 0.5 * w[a.order - 1 - i] : 0.0;
     }
-    a.K = make_kconst(op);
+    a.K = op->d_kconst;
     for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)op->K[o];
     if (a.npairs == 0) return MBEM_OK;
     hipLaunchKernelGGL((k_ssq<TS>), dim3((unsigned)a.npairs), dim3(64), 0, s, a);
@@ -466,6 +539,12 @@ struct PhaseEvents {
 
 int fill_run(mbem_op *op, hipStream_t s) {
     const mbem_mesh *m = op->mesh;
+    if (!op->d_kconst) MBEM_HIP(hipMalloc((void **)&op->d_kconst, sizeof(KernelConst)));
+    {
+        const KernelConst K = make_kconst(op);
+        MBEM_HIP(hipMemcpyAsync(op->d_kconst, &K, sizeof(K), hipMemcpyHostToDevice, s));
+        MBEM_HIP(hipStreamSynchronize(s));   // K lives on this stack frame
+    }
     PhaseEvents pe;
     const size_t esz = op->prec == MBEM_FP64 ? 16 : 8;
     for (int o = 0; o < 3; ++o)
@@ -483,9 +562,8 @@ int fill_run(mbem_op *op, hipStream_t s) {
         MBEM_HIP(hipMallocAsync((void **)&cnt, sizeof(unsigned long long), s));
         MBEM_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
         pe.mark(1, s);
-        MBEM_TRY((launch_regular<float, float>(op, 1, m->d_qp32, nullptr, s)));
+        MBEM_TRY((launch_regular<float, float>(op, 1, m->d_qp32, cnt, s)));
         pe.mark(2, s);
-        MBEM_TRY((launch_regular<double, float>(op, 2, m->d_qp, cnt, s)));
         pe.mark(3, s);
         MBEM_TRY(launch_ssq<float>(op, s));
     }

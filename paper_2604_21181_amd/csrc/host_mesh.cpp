@@ -275,6 +275,69 @@ int build_tables(const mbem_mesh *m, MeshTables &T) {
                 auto b = T.m_col.begin() + T.m_ptr[i], en = T.m_col.begin() + T.m_ptr[i + 1];
                 T.m_slot[36 * t + 6 * k + l] = (int32_t)(std::lower_bound(b, en, j) - T.m_col.begin());
             }
+    // trial chunks: kChunk Morton-consecutive triangles, their distinct
+    // nodes ("slots", ascending) and, per slot, the (triangle, local node)
+    // pairs that touch it
+    const int64_t nch = (nt + kChunk - 1) / kChunk;
+    T.chunks.assign(nch * kChunkRec, 0);
+    for (int64_t k = 0; k < nch; ++k) {
+        int32_t *rec = T.chunks.data() + k * kChunkRec;
+        std::vector<std::pair<int32_t, int32_t>> uses;   // (node, fs*8 + loc)
+        for (int fs = 0; fs < kChunk; ++fs) {
+            const int64_t f = k * kChunk + fs;
+            if (f >= nt) break;
+            for (int l = 0; l < 6; ++l) uses.push_back({tri[6 * f + l], fs * 8 + l});
+        }
+        std::sort(uses.begin(), uses.end());
+        int ns = 0, ni = 0;
+        for (size_t u = 0; u < uses.size(); ++u) {
+            if (u == 0 || uses[u].first != uses[u - 1].first) {
+                rec[1 + ns] = uses[u].first;
+                rec[25 + ns] = ni;
+                ++ns;
+            }
+            rec[50 + ni] = uses[u].second;
+            ++ni;
+        }
+        rec[0] = ns;
+        rec[25 + ns] = ni;
+    }
+    // Greedy colouring (in Morton order) so that the regular-pair fill can
+    // add to Z with plain read-modify-write: inside one colour pair no two
+    // test triangles share a node (disjoint rows) and no two trial chunks
+    // share a node (disjoint columns).
+    auto colour = [&](int64_t nitems, auto nodes_of, std::vector<int32_t> &list,
+                      std::vector<int32_t> &off) {
+        std::vector<std::vector<int32_t>> users(nn);
+        std::vector<int32_t> col(nitems, -1);
+        int ncol = 0;
+        std::vector<int32_t> nodes;
+        for (int64_t it = 0; it < nitems; ++it) {
+            nodes.clear();
+            nodes_of(it, nodes);
+            std::vector<char> used(ncol + 1, 0);
+            for (int32_t v : nodes)
+                for (int32_t o : users[v]) used[col[o]] = 1;
+            int c = 0;
+            while (c < ncol && used[c]) ++c;
+            col[it] = c;
+            ncol = std::max(ncol, c + 1);
+            for (int32_t v : nodes) users[v].push_back((int32_t)it);
+        }
+        off.assign(ncol + 1, 0);
+        for (int64_t it = 0; it < nitems; ++it) off[col[it] + 1]++;
+        for (int c = 0; c < ncol; ++c) off[c + 1] += off[c];
+        list.assign(nitems, 0);
+        std::vector<int32_t> fill(off.begin(), off.end() - 1);
+        for (int64_t it = 0; it < nitems; ++it) list[fill[col[it]]++] = (int32_t)it;
+    };
+    colour(nt, [&](int64_t e, std::vector<int32_t> &out) {
+        for (int k = 0; k < 6; ++k) out.push_back(tri[6 * e + k]);
+    }, T.tcol_list, T.tcol_off);
+    colour(nch, [&](int64_t k, std::vector<int32_t> &out) {
+        const int32_t *rec = T.chunks.data() + k * kChunkRec;
+        for (int s2 = 0; s2 < rec[0]; ++s2) out.push_back(rec[1 + s2]);
+    }, T.ccol_list, T.ccol_off);
     return MBEM_OK;
 }
 

@@ -167,7 +167,8 @@ __global__ void k_combine(int64_t n2, const double2 *__restrict__ t,
 
 static Coef coef_of(const mbem_op *op) { return {op->iw, op->ce, op->cm}; }
 
-int matvec_run(const mbem_op *op, const double2 *x, double2 *y, double2 *tmp, hipStream_t s) {
+int matvec_run(const mbem_op *op, const double2 *x, double2 *y, double2 *tmp, hipStream_t s,
+               hipEvent_t after_gemv) {
     const int64_t n2 = op->n2;
     const int64_t waves = 3 * n2;
     const unsigned blocks = (unsigned)((waves * kW + 255) / 256);
@@ -180,6 +181,7 @@ int matvec_run(const mbem_op *op, const double2 *x, double2 *y, double2 *tmp, hi
                            (const float2 *)op->K[0], (const float2 *)op->K[1],
                            (const float2 *)op->K[2], x, x + n2, tmp);
     MBEM_HIP(hipGetLastError());
+    if (after_gemv) MBEM_HIP(hipEventRecord(after_gemv, s));
     const mbem_mesh *m = op->mesh;
     hipLaunchKernelGGL(k_combine, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, n2, tmp,
                        m->d_mptr, m->d_mcol, op->d_mval, x, x + n2, coef_of(op), y);

@@ -10,6 +10,7 @@
 #include "../../include/mbem.h"
 
 namespace mbem {
+struct KernelConst;
 
 // ---------------------------------------------------------------- errors --
 void set_error(const std::string &msg);
@@ -34,6 +35,10 @@ void set_error(const std::string &msg);
 constexpr int kQP = 7;          // regular rule points per triangle
 constexpr int kQPF = 19;        // doubles per quadrature point in the table
 constexpr int kMaxSSQ = 8;      // largest Sauter-Schwab order supported
+constexpr int kChunk = 4;       // trial triangles per regular-pair workgroup
+// per trial chunk: n_slots, slot nodes[24], incidence offsets[25],
+// incidences[24] (chunk-local triangle * 8 + local node)
+constexpr int kChunkRec = 1 + 24 + 25 + 24;
 // quadrature-point table fields (structure of arrays, each n_tris*7 long)
 enum QpField {
     QX = 0, QW = 3, QN = 4, QT1 = 7, QT2 = 10, QS1 = 13, QS2 = 16
@@ -74,6 +79,10 @@ struct mbem_mesh {
     // mass-matrix pattern (node CSR) and element -> CSR slot map
     std::vector<int32_t> m_ptr, m_col;
     int32_t *d_mptr = nullptr, *d_mcol = nullptr, *d_mslot = nullptr;
+    int32_t *d_chunks = nullptr;   // trial-chunk records, kChunkRec ints each
+    // colour classes of the race-free regular-pair fill
+    std::vector<int32_t> tcol_off, ccol_off;
+    int32_t *d_tcol = nullptr, *d_ccol = nullptr;
 };
 
 struct mbem_op {
@@ -88,6 +97,7 @@ struct mbem_op {
     double *d_mval = nullptr;       // mass values on the node CSR pattern
     int64_t n_near = 0;
     double t_phase[5] = {0, 0, 0, 0, 0};  // geom, regular, near, ssq, mass (ms)
+    mbem::KernelConst *d_kconst = nullptr;   // device copy of the kernel constants
     // Morton block-Jacobi
     int32_t B = 0, nb = 0;
     double2 *d_minv = nullptr;      // [nb][2B][2B] inverses
@@ -105,6 +115,10 @@ struct MeshTables {
     std::vector<int32_t> spairs;            // e, f, class, perm codes
     int64_t n_single[4] = {0, 0, 0, 0};
     std::vector<int32_t> m_ptr, m_col, m_slot;
+    std::vector<int32_t> chunks;            // kChunkRec ints per trial chunk
+    // colour classes: test triangles sharing no node, trial chunks sharing
+    // no node (offsets into the concatenated lists, one more than classes)
+    std::vector<int32_t> tcol_list, tcol_off, ccol_list, ccol_off;
 };
 int build_tables(const mbem_mesh *m, MeshTables &T);
 int build_mesh_host(const double *xyz, int64_t nn, const int64_t *tri6,
@@ -123,7 +137,7 @@ int mass_run(mbem_op *op, hipStream_t s);
 
 // linear algebra (linalg.hip)
 int matvec_run(const mbem_op *op, const double2 *x, double2 *y, double2 *tmp,
-               hipStream_t s);
+               hipStream_t s, hipEvent_t after_gemv = nullptr);
 int export_dense_run(const mbem_op *op, double2 *Z, hipStream_t s);
 int export_blocks_run(const mbem_op *op, double2 *K1, double2 *K2e,
                       double2 *K2m, hipStream_t s);

@@ -152,7 +152,7 @@ struct KScal {
 };
 
 template <typename T>
-__device__ inline cx<T> horner(const double *c, T R) {
+__device__ __forceinline__ cx<T> horner(const double *c, T R) {
     cx<T> s = {(T)c[2 * kSeriesTerms], (T)c[2 * kSeriesTerms + 1]};
 #pragma unroll
     for (int n = kSeriesTerms - 1; n >= 0; --n) s = cx<T>{s.re * R + (T)c[2 * n], s.im * R + (T)c[2 * n + 1]};
@@ -167,7 +167,7 @@ __device__ inline float exp_t(float x) { return expf(x); }
 // Scalar parts of D0 = k_a^2 phi_a - k_i^2 phi_i, H_diff = df RR^T - dg I
 // (eq. Hdiff_exact) and grad Phi_chi = G_chi Rhat at distance R.
 template <typename T>
-__device__ inline KScal<T> kernel_scalars(const KernelConst &K, T R) {
+__device__ __forceinline__ KScal<T> kernel_scalars(const KernelConst &K, T R) {
     const T inv4pi = (T)0.079577471545947667884;   // 1 / (4 pi)
     KScal<T> o;
     if ((T)K.kmax * R < (T)kSeriesRho) {
