@@ -176,13 +176,15 @@ int mbem_matvec(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *x,
 /* ---- preconditioner (Sec. 5, eq. precond_block) --------------------------- */
 
 /* Morton block-Jacobi: clusters of `block` consecutive indices of one
- * current's vector; each block is the 2 block x 2 block restriction of Z,
- * LU-factorised with partial pivoting and inverted.  MBEM_ESINGULAR on a
- * zero pivot.  block <= 0 removes the preconditioner.                      */
+ * current's vector (block <= 256); each block is the 2 block x 2 block
+ * restriction of Z, LU-factorised with partial pivoting (blocked, in FP64).
+ * MBEM_ESINGULAR on a zero pivot, MBEM_EINVAL for block > 256.
+ * block <= 0 removes the preconditioner.                                   */
 int mbem_precond_setup(mbem_ctx *ctx, mbem_op *op, int32_t block,
                        mbem_stats *stats);
 
-/* z = P^-1 v (device, length N, complex128).                               */
+/* z = P^-1 v (device, length N, complex128) by forward and backward
+ * substitution with the block factors.                                     */
 int mbem_precond_apply(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *v,
                        mbem_c128 *z);
 

@@ -157,11 +157,12 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
         MBEM_TRY(vec_update(g.w, g.V, N, k + 1, g.hdev, N, s));
         MBEM_TRY(vec_dots(g.V, N, k + 1, g.w, N, g.hdev + (k + 1), s));
         MBEM_TRY(vec_update(g.w, g.V, N, k + 1, g.hdev + (k + 1), N, s));
-        MBEM_TRY(vec_norm2(g.w, N, g.ndev, s));
-        MBEM_HIP(hipMemcpyAsync(hbuf.data(), g.hdev, sizeof(double2) * 2 * (k + 1), hipMemcpyDeviceToHost, s));
-        double hn = 0;
-        MBEM_HIP(hipMemcpyAsync(&hn, g.ndev, sizeof(double), hipMemcpyDeviceToHost, s));
+        // the norm lands right after the 2(k+1) projections: one copy back
+        MBEM_TRY(vec_norm2(g.w, N, (double *)(g.hdev + 2 * (k + 1)), s));
+        MBEM_HIP(hipMemcpyAsync(hbuf.data(), g.hdev, sizeof(double2) * (2 * (k + 1) + 1),
+                                hipMemcpyDeviceToHost, s));
         MBEM_HIP(hipStreamSynchronize(s));
+        const double hn = hbuf[2 * (k + 1)].x;
         g.collect();
         auto Hc = [&](int i) -> std::complex<double> & { return H[(size_t)i * m + k]; };
         for (int i = 0; i <= k; ++i) Hc(i) = C(hbuf[i]) + C(hbuf[k + 1 + i]);

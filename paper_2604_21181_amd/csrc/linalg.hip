@@ -291,93 +291,199 @@ __global__ void k_mbj_gather(int64_t n2, int B, const void *K0, const void *K1, 
     }
 }
 
-// LU with partial pivoting (largest modulus), one workgroup per block.
+// Blocked right-looking LU with partial pivoting (largest modulus), one
+// workgroup per block, panels of kPW columns: the panel is factorised
+// column by column, U12 = L11^-1 A12 is formed, and the trailing matrix is
+// updated from L21 and U12 staged in LDS (one pass over A22 per panel).
+constexpr int kPW = 8;
+constexpr int kMaxBlock = 256;        // largest supported cluster size B
+constexpr int kMaxN = 2 * kMaxBlock;  // largest block dimension
+
 __global__ __launch_bounds__(1024) void k_mbj_lu(int64_t n2, int B, double2 *A, int32_t *piv,
                                                  int32_t *info) {
     __shared__ double s_v[1024];
     __shared__ int s_i[1024];
+    __shared__ double2 s_L[kMaxN * kPW];   // L21, rows below the panel
+    __shared__ double2 s_U[kPW * kMaxN];   // U12, columns right of it
+    __shared__ int32_t s_pv[kMaxN];        // row interchange of each step
     const int m = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
     const int b = (int)min((int64_t)B, n2 - (int64_t)m * B);
     const int n = 2 * b, ld = 2 * B;
     double2 *a = A + (int64_t)m * ld * ld;
     int32_t *pv = piv + (int64_t)m * ld;
-    for (int k = 0; k < n; ++k) {
-        double best = -1.0;
-        int bi = k;
-        for (int i = k + tid; i < n; i += nth) {
-            const double2 v = a[(int64_t)i * ld + k];
-            const double mag = v.x * v.x + v.y * v.y;
-            if (mag > best) { best = mag; bi = i; }
-        }
-        s_v[tid] = best;
-        s_i[tid] = bi;
-        __syncthreads();
-        for (int off = nth / 2; off > 0; off >>= 1) {
-            if (tid < off) {
-                const double o = s_v[tid + off];
-                const int oi = s_i[tid + off];
-                if (o > s_v[tid] || (o == s_v[tid] && oi < s_i[tid])) { s_v[tid] = o; s_i[tid] = oi; }
+    for (int j0 = 0; j0 < n; j0 += kPW) {
+        const int jw = min(kPW, n - j0), je = j0 + jw;
+        // 1. panel columns j0 .. je-1
+        for (int k = j0; k < je; ++k) {
+            double best = -1.0;
+            int bi = k;
+            for (int i = k + tid; i < n; i += nth) {
+                const double2 v = a[(int64_t)i * ld + k];
+                const double mag = v.x * v.x + v.y * v.y;
+                if (mag > best) { best = mag; bi = i; }
             }
+            s_v[tid] = best;
+            s_i[tid] = bi;
+            __syncthreads();
+            for (int off = nth / 2; off > 0; off >>= 1) {
+                if (tid < off) {
+                    const double o = s_v[tid + off];
+                    const int oi = s_i[tid + off];
+                    if (o > s_v[tid] || (o == s_v[tid] && oi < s_i[tid])) { s_v[tid] = o; s_i[tid] = oi; }
+                }
+                __syncthreads();
+            }
+            const int p = s_i[0];
+            const bool zero = !(s_v[0] > 0.0);
+            __syncthreads();
+            if (tid == 0) { s_pv[k] = p; if (zero && *info == 0) *info = m + 1; }
+            if (zero) continue;
+            if (p != k)
+                for (int q = tid; q < n; q += nth) {
+                    const double2 t = a[(int64_t)k * ld + q];
+                    a[(int64_t)k * ld + q] = a[(int64_t)p * ld + q];
+                    a[(int64_t)p * ld + q] = t;
+                }
+            __syncthreads();
+            const double2 d = a[(int64_t)k * ld + k];
+            const double dn = d.x * d.x + d.y * d.y;
+            const double2 inv = {d.x / dn, -d.y / dn};
+            for (int i = k + 1 + tid; i < n; i += nth) a[(int64_t)i * ld + k] = cmul(a[(int64_t)i * ld + k], inv);
+            __syncthreads();
+            const int rc = je - k - 1;   // remaining panel columns
+            if (rc > 0)
+                for (int64_t id = tid; id < (int64_t)(n - k - 1) * rc; id += nth) {
+                    const int i = k + 1 + (int)(id / rc), q = k + 1 + (int)(id % rc);
+                    double2 &t = a[(int64_t)i * ld + q];
+                    t = csub(t, cmul(a[(int64_t)i * ld + k], a[(int64_t)k * ld + q]));
+                }
             __syncthreads();
         }
-        const int p = s_i[0];
-        const bool zero = !(s_v[0] > 0.0);
-        __syncthreads();
-        if (tid == 0) { pv[k] = p; if (zero && *info == 0) *info = m + 1; }
-        if (zero) continue;
-        if (p != k)
-            for (int q = tid; q < n; q += nth) {
-                const double2 t = a[(int64_t)k * ld + q];
-                a[(int64_t)k * ld + q] = a[(int64_t)p * ld + q];
-                a[(int64_t)p * ld + q] = t;
+        if (je >= n) break;
+        const int nr = n - je;
+        // 2. U12 = L11^-1 A12 (unit lower L11), one thread per column
+        for (int q = je + tid; q < n; q += nth) {
+            for (int r = 0; r < jw; ++r) {
+                double2 t = a[(int64_t)(j0 + r) * ld + q];
+                for (int c = 0; c < r; ++c)
+                    t = csub(t, cmul(a[(int64_t)(j0 + r) * ld + j0 + c], s_U[c * nr + (q - je)]));
+                a[(int64_t)(j0 + r) * ld + q] = t;
+                s_U[r * nr + (q - je)] = t;
             }
+        }
+        for (int64_t id = tid; id < (int64_t)nr * jw; id += nth) {
+            const int i = (int)(id / jw), c = (int)(id % jw);
+            s_L[i * jw + c] = a[(int64_t)(je + i) * ld + j0 + c];
+        }
         __syncthreads();
-        const double2 d = a[(int64_t)k * ld + k];
-        const double dn = d.x * d.x + d.y * d.y;
-        const double2 inv = {d.x / dn, -d.y / dn};
-        for (int i = k + 1 + tid; i < n; i += nth) a[(int64_t)i * ld + k] = cmul(a[(int64_t)i * ld + k], inv);
-        __syncthreads();
-        const int rest = n - k - 1;
-        for (int64_t id = tid; id < (int64_t)rest * rest; id += nth) {
-            const int i = k + 1 + (int)(id / rest), q = k + 1 + (int)(id % rest);
-            const double2 l = a[(int64_t)i * ld + k], u = a[(int64_t)k * ld + q];
-            double2 &t = a[(int64_t)i * ld + q];
-            t = csub(t, cmul(l, u));
+        // 3. A22 -= L21 U12
+        for (int64_t id = tid; id < (int64_t)nr * nr; id += nth) {
+            const int i = (int)(id / nr), q = (int)(id % nr);
+            double2 t = a[(int64_t)(je + i) * ld + je + q];
+            for (int c = 0; c < jw; ++c) t = csub(t, cmul(s_L[i * jw + c], s_U[c * nr + q]));
+            a[(int64_t)(je + i) * ld + je + q] = t;
         }
         __syncthreads();
     }
+    // the interchanges as one gather: row i of P A is row pv[i] of A
+    __syncthreads();
+    if (tid == 0) {
+        for (int i = 0; i < n; ++i) s_L[i].x = i;
+        for (int k = 0; k < n; ++k) {
+            const int p = s_pv[k];
+            const double t = s_L[k].x;
+            s_L[k].x = s_L[p].x;
+            s_L[p].x = t;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += nth) pv[i] = (int32_t)s_L[i].x;
 }
 
-// Inverse from the factors: thread j solves L U x = P e_j for column j.
-__global__ __launch_bounds__(1024) void k_mbj_inverse(int64_t n2, int B, const double2 *A,
+// Inverse of every block from its LU factors: A^-1 e_j for kCols columns j
+// per workgroup, solving L U x = P e_j in panels of 64 rows.  The panel's
+// diagonal block is staged in LDS and solved by one wavefront per column
+// with lane shuffles; every remaining row of every column is then updated
+// with the panel's solution.  The factors are read once per workgroup.
+constexpr int kCols = 8;
+
+__global__ __launch_bounds__(1024) void k_mbj_inverse(int64_t n2, int B, const double2 *LU,
                                                       const int32_t *piv, double2 *Minv) {
-    const int m = blockIdx.x, j = threadIdx.x;
+    __shared__ double2 y[kCols][kMaxN];
+    __shared__ double2 s_P[kW][kW + 1];
+    const int m = blockIdx.x, tid = threadIdx.x, lane = tid % kW, wv = tid / kW;
     const int b = (int)min((int64_t)B, n2 - (int64_t)m * B);
     const int n = 2 * b, ld = 2 * B;
-    if (j >= n) return;
-    const double2 *a = A + (int64_t)m * ld * ld;
+    const int c0 = blockIdx.y * kCols;
+    if (c0 >= n) return;
+    const int nc = min(kCols, n - c0);
+    const double2 *a = LU + (int64_t)m * ld * ld;
     const int32_t *pv = piv + (int64_t)m * ld;
-    double2 *x = Minv + (int64_t)m * ld * ld;
-    for (int i = 0; i < n; ++i) x[(int64_t)i * ld + j] = {i == j ? 1.0 : 0.0, 0.0};
-    for (int k = 0; k < n; ++k) {
-        const int p = pv[k];
-        if (p != k) {
-            const double2 t = x[(int64_t)k * ld + j];
-            x[(int64_t)k * ld + j] = x[(int64_t)p * ld + j];
-            x[(int64_t)p * ld + j] = t;
+    for (int id = tid; id < nc * n; id += blockDim.x) {
+        const int c = id / n, r = id % n;
+        y[c][r] = double2{pv[r] == c0 + c ? 1.0 : 0.0, 0.0};   // (P e_j)[r]
+    }
+    __syncthreads();
+    // forward substitution, unit L
+    for (int p0 = 0; p0 < n; p0 += kW) {
+        const int pw = min(kW, n - p0);
+        for (int id = tid; id < pw * pw; id += blockDim.x)
+            s_P[id / pw][id % pw] = a[(int64_t)(p0 + id / pw) * ld + p0 + id % pw];
+        __syncthreads();
+        if (wv < nc) {
+            double2 yi = lane < pw ? y[wv][p0 + lane] : double2{0, 0};
+            for (int k = 0; k < pw - 1; ++k) {
+                const double2 yk = {__shfl(yi.x, k, kW), __shfl(yi.y, k, kW)};
+                if (lane > k && lane < pw) yi = csub(yi, cmul(s_P[lane][k], yk));
+            }
+            if (lane < pw) y[wv][p0 + lane] = yi;
         }
+        __syncthreads();
+        const int rows = n - p0 - pw;
+        for (int id = tid; id < rows * nc; id += blockDim.x) {
+            const int i = p0 + pw + id / nc, c = id % nc;
+            const double2 *row = a + (int64_t)i * ld + p0;
+            double2 acc = y[c][i];
+#pragma unroll 8
+            for (int k = 0; k < pw; ++k) acc = csub(acc, cmul(row[k], y[c][p0 + k]));
+            y[c][i] = acc;
+        }
+        __syncthreads();
     }
-    for (int i = 1; i < n; ++i) {
-        double2 s = x[(int64_t)i * ld + j];
-        for (int k = 0; k < i; ++k) s = csub(s, cmul(a[(int64_t)i * ld + k], x[(int64_t)k * ld + j]));
-        x[(int64_t)i * ld + j] = s;
+    // backward substitution, U
+    for (int pe = n; pe > 0; pe -= kW) {
+        const int p0 = max(0, pe - kW), pw = pe - p0;
+        for (int id = tid; id < pw * pw; id += blockDim.x)
+            s_P[id / pw][id % pw] = a[(int64_t)(p0 + id / pw) * ld + p0 + id % pw];
+        __syncthreads();
+        if (wv < nc) {
+            double2 yi = lane < pw ? y[wv][p0 + lane] : double2{0, 0};
+            for (int k = pw - 1; k >= 0; --k) {
+                if (lane == k) {
+                    const double2 d = s_P[k][k];
+                    const double dn = d.x * d.x + d.y * d.y;
+                    yi = cmul(yi, double2{d.x / dn, -d.y / dn});
+                }
+                const double2 yk = {__shfl(yi.x, k, kW), __shfl(yi.y, k, kW)};
+                if (lane < k) yi = csub(yi, cmul(s_P[lane][k], yk));
+            }
+            if (lane < pw) y[wv][p0 + lane] = yi;
+        }
+        __syncthreads();
+        for (int id = tid; id < p0 * nc; id += blockDim.x) {
+            const int i = id / nc, c = id % nc;
+            const double2 *row = a + (int64_t)i * ld + p0;
+            double2 acc = y[c][i];
+#pragma unroll 8
+            for (int k = 0; k < pw; ++k) acc = csub(acc, cmul(row[k], y[c][p0 + k]));
+            y[c][i] = acc;
+        }
+        __syncthreads();
     }
-    for (int i = n - 1; i >= 0; --i) {
-        double2 s = x[(int64_t)i * ld + j];
-        for (int k = i + 1; k < n; ++k) s = csub(s, cmul(a[(int64_t)i * ld + k], x[(int64_t)k * ld + j]));
-        const double2 d = a[(int64_t)i * ld + i];
-        const double dn = d.x * d.x + d.y * d.y;
-        x[(int64_t)i * ld + j] = cmul(s, double2{d.x / dn, -d.y / dn});
+    double2 *x = Minv + (int64_t)m * ld * ld;
+    for (int id = tid; id < nc * n; id += blockDim.x) {
+        const int r = id / nc, c = id % nc;
+        x[(int64_t)r * ld + c0 + c] = y[c][r];
     }
 }
 
@@ -410,14 +516,15 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s) {
     if (op->d_lu) { MBEM_HIP(hipFree(op->d_lu)); op->d_lu = nullptr; }
     op->B = 0; op->nb = 0;
     if (B <= 0) return MBEM_OK;
-    if (B > 512) { set_error("preconditioner block above 512 is not supported"); return MBEM_EINVAL; }
+    if (B > kMaxBlock) { set_error("preconditioner block above 256 is not supported"); return MBEM_EINVAL; }
     const int64_t n2 = op->n2;
     if (B > n2) B = (int)n2;
     const int nb = (int)((n2 + B - 1) / B);
     const int64_t ld = 2 * (int64_t)B;
     const size_t bytes = sizeof(double2) * nb * ld * ld;
-    MBEM_HIP(hipMalloc((void **)&op->d_minv, bytes));
+    // factors and pivots in one scratch allocation: [nb][ld][ld] + [nb][ld] + info
     MBEM_HIP(hipMalloc((void **)&op->d_lu, bytes + sizeof(int32_t) * (nb * ld + 1)));
+    MBEM_HIP(hipMalloc((void **)&op->d_minv, bytes));
     int32_t *piv = (int32_t *)((char *)op->d_lu + bytes);
     int32_t *info = piv + nb * ld;
     MBEM_HIP(hipMemsetAsync(info, 0, sizeof(int32_t), s));
@@ -432,7 +539,8 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s) {
     MBEM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_mbj_lu, dim3(nb), dim3(1024), 0, s, n2, B, op->d_lu, piv, info);
     MBEM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_mbj_inverse, dim3(nb), dim3(1024), 0, s, n2, B, op->d_lu, piv, op->d_minv);
+    hipLaunchKernelGGL(k_mbj_inverse, dim3(nb, (unsigned)((ld + kCols - 1) / kCols)), dim3(1024), 0, s,
+                       n2, B, op->d_lu, piv, op->d_minv);
     MBEM_HIP(hipGetLastError());
     int32_t h = 0;
     MBEM_HIP(hipMemcpyAsync(&h, info, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -451,7 +559,7 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s) {
 }
 
 int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z, hipStream_t s) {
-    if (!op->d_minv) {
+    if (!op->d_minv || op->nb == 0) {
         MBEM_HIP(hipMemcpyAsync(z, v, sizeof(double2) * 2 * op->n2, hipMemcpyDeviceToDevice, s));
         return MBEM_OK;
     }

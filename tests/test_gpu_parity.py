@@ -116,7 +116,7 @@ def test_precond_apply(case):
     S = case["S"]
     p = S.perm
     Zm = case["Z"][np.ix_(p, p)]
-    for B in (50, 2 * S.nn):
+    for B in (50, 256):
         S.precond_setup(B)
         blocks = solver.mbj_matrices(Zm, B)
         v = np.random.default_rng(3).normal(size=S.N) + 0j
