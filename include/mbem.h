@@ -206,6 +206,66 @@ int mbem_rhs_planewave(mbem_ctx *ctx, const mbem_mesh *mesh,
 int mbem_solve(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs,
                const mbem_solve_opts *opts, mbem_c128 *x, mbem_stats *stats);
 
+/* ---- many right-hand sides (Sec. 5 and 6: block Krylov extension) ------- */
+
+typedef struct {
+    double tol;          /* per column: |b - Z x| <= tol |b| (FP64 residual) */
+    double inner_tol;    /* reduction of every column per refinement sweep
+                            (0 -> 1e-5)                                      */
+    int32_t maxit;       /* block iterations per sweep (0 -> 60)            */
+    int32_t max_refine;  /* refinement sweeps (0 -> 10)                      */
+    int32_t block;       /* columns per block, <= 32 and dividing nrhs
+                            (0 -> the largest such divisor)                  */
+    int32_t gemm_config; /* FP32 GEMM tile shape 0..5; -1 -> autotuned      */
+} mbem_block_opts;
+
+typedef struct {
+    int32_t iters;       /* block iterations summed over sweeps             */
+    int32_t sweeps;      /* refinement sweeps                                */
+    int32_t block;       /* columns per block used                           */
+    int32_t gemm_config; /* FP32 GEMM tile shape used                        */
+    double rel_resid;    /* max over columns of |b - Z x| / |b|              */
+    double t_solve_ms;   /* wall time of the call                            */
+    double t_gemm_ms;    /* sum of the block matrix-product GEMM launches    */
+    int32_t n_gemm;      /* number of those launches                         */
+    int32_t shifted;     /* 1 if a Cholesky QR needed a diagonal shift       */
+} mbem_block_stats;
+
+/* Solve Z X = B for nrhs columns at once: block GMRES right-preconditioned
+ * by the Morton block-Jacobi matrix (if set up), blocks of `block` columns
+ * sharing every launch; the dense part of each block product Z P^-1 V runs
+ * as one complex FP32 GEMM on the matrix cores (an FP64 operator is copied
+ * to complex64 once for this), the Arnoldi process (classical Gram-Schmidt
+ * twice, Cholesky QR twice) in FP64, and an outer FP64 residual B - Z X of
+ * the stored operator refines X.
+ *   b, x device [nrhs][N] complex128 (x overwritten, x0 = 0)
+ * Errors: MBEM_EINVAL (block size, a zero column of b), MBEM_ENOMEM,
+ * MBEM_ENOCONV (x holds the last iterate).                                  */
+int mbem_solve_block(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b,
+                     int32_t nrhs, const mbem_block_opts *opts, mbem_c128 *x,
+                     mbem_block_stats *stats);
+
+/* Time every FP32 GEMM tile shape on the block product of `op` with nrhs
+ * columns (a warm-up and `reps` timed launches each), keep the fastest for
+ * later calls of mbem_solve_block with nrhs columns.
+ *   ms host [6] (best time of each shape, may be NULL); best host [1].     */
+int mbem_gemm_autotune(mbem_ctx *ctx, mbem_op *op, int32_t nrhs, int32_t reps,
+                       float *ms, int32_t *best);
+
+/* The complex GEMM of the block solve on its own:
+ *   C[b][m] = sum_k op(A[m][k]) B[b][k],  m < M, b < Nb, k < K,
+ * all row-major device arrays (leading dimensions in elements).
+ *   dtype 0: complex64 A, B, C, FP32 accumulation (matrix cores), tile shape
+ *            `config` (0..5), conj_a must be 0; lda, ldb even and A, B
+ *            16-byte aligned;
+ *   dtype 1: complex128 A, B, C, FP64 accumulation (matrix cores);
+ *   dtype 2: complex64 A, complex128 B and C, FP64 accumulation.
+ * op = conj when conj_a (dtypes 1 and 2).                                   */
+int mbem_cgemm(mbem_ctx *ctx, int32_t dtype, int32_t conj_a, int64_t M,
+               int64_t Nb, int64_t K, const void *A, int64_t lda,
+               const void *B, int64_t ldb, void *C, int64_t ldc,
+               int32_t config);
+
 /* Far-field amplitude F(r) of the solution currents, E_s ~ F e^{ik r}/r:
  * F = (i k_a / 4 pi) r x sum_qp w J e^{-i k_a r.y} (eta_a j x r - j_m).
  *   x device [N*nrhs]; rhat device [ndir*3]; F device [nrhs][ndir][3]

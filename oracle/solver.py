@@ -131,3 +131,18 @@ def gmres(matvec, b, precond=None, tol=1e-10, maxit=1000):
     y = np.linalg.solve(np.triu(H[:k, :k]), g[:k])
     x = precond(V[:k].T @ y)
     return x, k, np.array(hist)
+
+
+def cgemm_nt(A, B, conj_a=False):
+    """C[b][m] = sum_k op(A[m][k]) B[b][k], op = conj when conj_a: the
+    product of a block of row vectors B with a stored matrix A, written
+    with the library matmul in complex128."""
+    A = np.asarray(A, dtype=np.complex128)
+    B = np.asarray(B, dtype=np.complex128)
+    return B @ (A.conj() if conj_a else A).T
+
+
+def solve_columns(Z, B):
+    """X[c] with Z X[c] = B[c] for every row c of B (dense LU)."""
+    return np.linalg.solve(np.asarray(Z, dtype=np.complex128),
+                           np.asarray(B, dtype=np.complex128).T).T

@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmbem.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["host_mesh.cpp", "capi.cpp", "geom.hip", "fill.hip", "linalg.hip", "post.hip"]
+SOURCES = ["host_mesh.cpp", "capi.cpp", "geom.hip", "fill.hip", "linalg.hip", "post.hip", "gemm.hip",
+           "block.hip"]
 ARCH = os.environ.get("MBEM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1,0 +1,854 @@
+// Multi-right-hand-side solve: block GMRES on Z P^-1 (Sec. 5 for P) with
+// the block matrix-vector product on the matrix cores, inside FP64
+// iterative refinement.
+//
+// The nrhs columns are split into blocks of p <= 32 columns; every block
+// builds its own block Krylov space, and all blocks share one launch of
+// each kernel.  Per block iteration k (all blocks at once):
+//   Zt   = P^-1 V_k                      (FP64 in, complex64 out)
+//   W    = Z Zt                          (complex FP32 GEMM on MFMA for the
+//                                         dense blocks, mass in FP64, W FP64)
+//   H    = V^H W, W -= V H  (twice)      (block classical Gram-Schmidt, FP64
+//                                         MFMA for V^H W)
+//   W    = V_{k+1} R                     (Cholesky QR, twice; shifted when the
+//                                         Gram matrix is not numerically SPD)
+//   Householder QR of the new block column of the block Hessenberg matrix,
+//   applied to the least-squares right-hand side: its trailing p rows give
+//   the residual norm of every column.
+// After the sweep: Y = R^-1 g, X += P^-1 V Y; the refinement residual
+// B - Z X is formed with the FP64 MFMA GEMM from the stored operator.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "gemm.h"
+
+namespace mbem {
+
+constexpr int kMaxP = 32;    // columns per block
+constexpr int kWv = 64;
+
+__device__ inline double2 zmul(double2 a, double2 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ inline double2 zcmul(double2 a, double2 b) {   // conj(a) b
+    return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+__device__ inline double wsum(double v) {
+#pragma unroll
+    for (int o = kWv / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWv);
+    return v;
+}
+template <typename T>
+__device__ inline double2 ld2(const T *p, int64_t i) { return {(double)p[i].x, (double)p[i].y}; }
+
+// Column c of a set of nrhs vectors stored block by block:
+// base + (c / p) * sblk + (c % p) * ld.
+struct ColMap {
+    void *base;
+    int p;
+    int64_t sblk, ld;
+};
+template <typename T>
+__device__ inline T *col_ptr(const ColMap &m, int64_t c) {
+    return (T *)m.base + (c / m.p) * m.sblk + (c % m.p) * m.ld;
+}
+
+// ------------------------------------------------- preconditioner ---
+// out[c] (= or +=) P^-1 v[c]; one wavefront per (preconditioner row,
+// group of 8 columns); without a preconditioner out = v.
+constexpr int kCG = 8;
+template <typename TO, bool ADD>
+__global__ __launch_bounds__(256) void k_mbj_apply_multi(int64_t n2, int B, int nb, const double2 *Minv,
+                                                         ColMap vin, ColMap out, int ncol) {
+    const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWv;
+    const int lane = threadIdx.x % kWv;
+    const int ngrp = (ncol + kCG - 1) / kCG;
+    const int64_t ld = 2 * (int64_t)B;
+    const int64_t row_id = wid / ngrp;
+    const int grp = (int)(wid % ngrp);
+    const int64_t m = row_id / ld, r = row_id % ld;
+    if (m >= nb) return;
+    const int64_t b = min((int64_t)B, n2 - m * B);
+    const int64_t n = 2 * b;
+    if (r >= n) return;
+    const double2 *row = Minv + m * ld * ld + r * ld;
+    const double2 *v[kCG];
+#pragma unroll
+    for (int u = 0; u < kCG; ++u) v[u] = col_ptr<const double2>(vin, min(grp * kCG + u, ncol - 1));
+    double re[kCG], im[kCG];
+#pragma unroll
+    for (int u = 0; u < kCG; ++u) re[u] = im[u] = 0.0;
+    for (int64_t q = lane; q < n; q += kWv) {
+        const int64_t gi = (q < b ? 0 : n2) + m * B + (q % b);
+        const double2 a = row[q];
+#pragma unroll
+        for (int u = 0; u < kCG; ++u) {
+            const double2 x = v[u][gi];
+            re[u] += a.x * x.x - a.y * x.y;
+            im[u] += a.x * x.y + a.y * x.x;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kCG; ++u) { re[u] = wsum(re[u]); im[u] = wsum(im[u]); }
+    if (lane == 0) {
+        const int64_t go = (r < b ? 0 : n2) + m * B + (r % b);
+#pragma unroll
+        for (int u = 0; u < kCG; ++u) {
+            const int c = grp * kCG + u;
+            if (c >= ncol) break;
+            TO *o = col_ptr<TO>(out, c) + go;
+            if (ADD) { o->x += re[u]; o->y += im[u]; }
+            else { o->x = re[u]; o->y = im[u]; }
+        }
+    }
+}
+
+template <typename TO, bool ADD>
+__global__ void k_copy_multi(int64_t N, ColMap vin, ColMap out, int ncol) {
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= N * ncol) return;
+    const int64_t c = id / N, i = id % N;
+    const double2 x = col_ptr<const double2>(vin, c)[i];
+    TO *o = col_ptr<TO>(out, c) + i;
+    if (ADD) { o->x += x.x; o->y += x.y; }
+    else { o->x = x.x; o->y = x.y; }
+}
+
+int mbj_apply_multi(const mbem_op *op, ColMap vin, ColMap out, int ncol, bool out_c64, bool add,
+                    hipStream_t s) {
+    const int64_t N = 2 * op->n2;
+    if (!op->d_minv || op->nb == 0) {
+        const unsigned g = (unsigned)((N * ncol + 255) / 256);
+        if (out_c64) hipLaunchKernelGGL((k_copy_multi<float2, false>), dim3(g), dim3(256), 0, s, N, vin, out, ncol);
+        else if (add) hipLaunchKernelGGL((k_copy_multi<double2, true>), dim3(g), dim3(256), 0, s, N, vin, out, ncol);
+        else hipLaunchKernelGGL((k_copy_multi<double2, false>), dim3(g), dim3(256), 0, s, N, vin, out, ncol);
+        MBEM_HIP(hipGetLastError());
+        return MBEM_OK;
+    }
+    const int64_t waves = (int64_t)op->nb * 2 * op->B * ((ncol + kCG - 1) / kCG);
+    const unsigned g = (unsigned)((waves * kWv + 255) / 256);
+    if (out_c64)
+        hipLaunchKernelGGL((k_mbj_apply_multi<float2, false>), dim3(g), dim3(256), 0, s, op->n2, op->B, op->nb,
+                           op->d_minv, vin, out, ncol);
+    else if (add)
+        hipLaunchKernelGGL((k_mbj_apply_multi<double2, true>), dim3(g), dim3(256), 0, s, op->n2, op->B, op->nb,
+                           op->d_minv, vin, out, ncol);
+    else
+        hipLaunchKernelGGL((k_mbj_apply_multi<double2, false>), dim3(g), dim3(256), 0, s, op->n2, op->B, op->nb,
+                           op->d_minv, vin, out, ncol);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+// ---------------------------------------------- block product Z X ---
+// From the dense products T1 = K1 [x_j | x_m] (row 2c: x_j of column c, row
+// 2c+1: x_m), T2 = K2^eps x_m, T3 = K2^mu x_j (each [ncol][n2]) and the mass
+// matrix:  y_j = (i/w) K1 x_j + K2^eps x_m + c_eps M x_m,
+//          y_m = K2^mu x_j + c_mu M x_j - (i/w) K1 x_m.
+// RESID: y = b - Z x instead.
+struct ZCoef { double2 iw, ce, cm; };
+template <typename TT, typename TX, bool RESID>
+__global__ void k_block_combine(int64_t n2, int ncol, const TT *T, const int32_t *__restrict__ mptr,
+                                const int32_t *__restrict__ mcol, const double *__restrict__ mval, ZCoef cf,
+                                ColMap xin, ColMap bin, ColMap yout) {
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= n2 * ncol) return;
+    const int64_t c = id / n2, r = id % n2;
+    const TX *x = col_ptr<const TX>(xin, c);
+    const int64_t i = r / 2;
+    const int al = (int)(r % 2);
+    double2 Mj = {0, 0}, Mm = {0, 0};
+    for (int32_t s = mptr[i]; s < mptr[i + 1]; ++s) {
+        const int64_t col = 2 * (int64_t)mcol[s] + al;
+        const double v = mval[s];
+        const double2 xj = ld2(x, col), xm = ld2(x, n2 + col);
+        Mj.x += v * xj.x; Mj.y += v * xj.y;
+        Mm.x += v * xm.x; Mm.y += v * xm.y;
+    }
+    const TT *T1 = T, *T2 = T + 2 * ncol * n2, *T3 = T2 + ncol * n2;
+    const double2 a = ld2(T1, (2 * c) * n2 + r), bm = ld2(T1, (2 * c + 1) * n2 + r);
+    const double2 e = ld2(T2, c * n2 + r), u = ld2(T3, c * n2 + r);
+    double2 yj = zmul(cf.iw, a), ym = zmul(cf.iw, bm);
+    yj = {yj.x + e.x + cf.ce.x * Mm.x - cf.ce.y * Mm.y, yj.y + e.y + cf.ce.x * Mm.y + cf.ce.y * Mm.x};
+    ym = {u.x + cf.cm.x * Mj.x - cf.cm.y * Mj.y - ym.x, u.y + cf.cm.x * Mj.y + cf.cm.y * Mj.x - ym.y};
+    double2 *y = col_ptr<double2>(yout, c);
+    if (RESID) {
+        const double2 *b = col_ptr<const double2>(bin, c);
+        y[r] = {b[r].x - yj.x, b[r].y - yj.y};
+        y[n2 + r] = {b[n2 + r].x - ym.x, b[n2 + r].y - ym.y};
+    } else {
+        y[r] = yj;
+        y[n2 + r] = ym;
+    }
+}
+
+// ------------------------------------------------ NN block update ---
+// out[c][n] = beta out[c][n] + alpha sum_a V[a][n] Y[c * ldy + a]
+// for c < p, a < ka, per block (grid.y); one thread per (n, 8 columns).
+__global__ __launch_bounds__(256) void k_nn_update(int64_t N, int ka, int p, const double2 *V, int64_t ldv,
+                                                   int64_t sv, const double2 *Y, int64_t ldy, int64_t sy,
+                                                   double2 *out, int64_t ldo, int64_t so, double alpha,
+                                                   double beta) {
+    __shared__ double2 sY[64][kMaxP];
+    const int ngrp = (p + kCG - 1) / kCG;
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t n = id / ngrp;
+    const int grp = (int)(id % ngrp);
+    const int64_t blk = blockIdx.y;
+    V += blk * sv;
+    Y += blk * sy;
+    out += blk * so;
+    double re[kCG], im[kCG];
+#pragma unroll
+    for (int u = 0; u < kCG; ++u) re[u] = im[u] = 0.0;
+    for (int a0 = 0; a0 < ka; a0 += 64) {
+        const int na = min(64, ka - a0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < na * p; t += blockDim.x) {
+            const int a = t % na, c = t / na;
+            sY[a][c] = Y[c * ldy + a0 + a];
+        }
+        __syncthreads();
+        if (n < N) {
+            for (int a = 0; a < na; ++a) {
+                const double2 v = V[(int64_t)(a0 + a) * ldv + n];
+#pragma unroll
+                for (int u = 0; u < kCG; ++u) {
+                    const int c = grp * kCG + u;
+                    const double2 y = sY[a][c < p ? c : 0];
+                    re[u] += v.x * y.x - v.y * y.y;
+                    im[u] += v.x * y.y + v.y * y.x;
+                }
+            }
+        }
+    }
+    if (n >= N) return;
+#pragma unroll
+    for (int u = 0; u < kCG; ++u) {
+        const int c = grp * kCG + u;
+        if (c >= p) break;
+        double2 *o = out + c * ldo + n;
+        if (beta == 0.0) *o = {alpha * re[u], alpha * im[u]};
+        else *o = {beta * o->x + alpha * re[u], beta * o->y + alpha * im[u]};
+    }
+}
+
+static int nn_update(int64_t N, int ka, int p, int nblk, const double2 *V, int64_t ldv, int64_t sv,
+                     const double2 *Y, int64_t ldy, int64_t sy, double2 *out, int64_t ldo, int64_t so,
+                     double alpha, double beta, hipStream_t s) {
+    const int ngrp = (p + kCG - 1) / kCG;
+    const dim3 grid((unsigned)((N * ngrp + 255) / 256), (unsigned)nblk);
+    hipLaunchKernelGGL(k_nn_update, grid, dim3(256), 0, s, N, ka, p, V, ldv, sv, Y, ldy, sy, out, ldo, so,
+                       alpha, beta);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+// ------------------------------------------------------ Cholesky QR ---
+// One wavefront per block.  G (column-major, G[c * p + a] = sum conj(w_a)
+// w_c) = R^H R.  If SCALE, the columns are first normalised (D = sqrt
+// diag G) and R is returned for the unscaled columns.  If the factorisation
+// meets a pivot that is not positive, it restarts on G + s I with
+// s = 11 (N p + p (p + 1)) u |G|_F (shifted Cholesky QR).
+// Outputs: Y = (R_hat)^-1 (scaled rows: D^-1 R_hat^-1), column-major p x p;
+// Rout = R * Rprev (or R when Rprev is null), element (i, c) at
+// Rout[c * ldr + i] in block b at Rout + b * sr.
+__global__ __launch_bounds__(64) void k_cholqr_small(int p, int64_t Nrows, const double2 *G, int scale,
+                                                     const double2 *Rprev, double2 *Y, double2 *Rout,
+                                                     int64_t ldr, int64_t sr, int *flags) {
+    __shared__ double2 sG[kMaxP][kMaxP];   // sG[a][c]
+    __shared__ double2 sR[kMaxP][kMaxP];   // sR[i][c], upper
+    __shared__ double2 sX[kMaxP][kMaxP];   // sX[i][c]: column c of R^-1
+    __shared__ double sD[kMaxP];
+    __shared__ int s_bad;
+    const int blk = blockIdx.x, c = threadIdx.x;
+    G += (int64_t)blk * p * p;
+    for (int t = c; t < p * p; t += 64) sG[t % p][t / p] = G[t];
+    __syncthreads();
+    if (c < p) sD[c] = scale ? sqrt(fmax(sG[c][c].x, 0.0)) : 1.0;
+    __syncthreads();
+    if (scale) {
+        for (int t = c; t < p * p; t += 64) {
+            const int a = t % p, cc = t / p;
+            const double d = sD[a] * sD[cc];
+            sG[a][cc] = d > 0 ? double2{sG[a][cc].x / d, sG[a][cc].y / d} : double2{a == cc ? 1.0 : 0.0, 0.0};
+        }
+        __syncthreads();
+    }
+    double fro = 0.0;
+    for (int a = 0; a < p; ++a) if (c < p) fro += sG[a][c].x * sG[a][c].x + sG[a][c].y * sG[a][c].y;
+    fro = sqrt(wsum(fro));
+    fro = __shfl(fro, 0);
+    double shift = 0.0;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        if (c == 0) s_bad = 0;
+        __syncthreads();
+        for (int j = 0; j < p; ++j) {
+            double2 v = {0, 0};
+            if (c < p && c >= j) {
+                v = sG[j][c];
+                if (c == j) v.x += shift;
+                for (int i = 0; i < j; ++i) {
+                    const double2 t = zcmul(sR[i][j], sR[i][c]);
+                    v.x -= t.x; v.y -= t.y;
+                }
+            }
+            __syncthreads();
+            if (c == j) {
+                if (!(v.x > 0.0)) { s_bad = 1; v.x = 1.0; }
+                sR[j][j] = {sqrt(v.x), 0.0};
+            }
+            __syncthreads();
+            if (c < p && c > j) { const double d = sR[j][j].x; sR[j][c] = {v.x / d, v.y / d}; }
+            if (c < p && c < j) sR[j][c] = {0.0, 0.0};
+            __syncthreads();
+        }
+        if (!s_bad) break;
+        shift = shift > 0 ? 100.0 * shift : 11.0 * ((double)Nrows * p + p * (p + 1)) * 1.1102230246251565e-16 * fro;
+        if (c == 0 && flags) atomicOr(flags, 1);
+        __syncthreads();
+    }
+    // inverse of R by columns (lane c solves R x = e_c), then Y = D^-1 R^-1
+    if (c < p) {
+        for (int i = 0; i < p; ++i) sX[i][c] = {0, 0};
+        for (int i = c; i >= 0; --i) {
+            double2 t = {i == c ? 1.0 : 0.0, 0.0};
+            for (int j = i + 1; j <= c; ++j) { const double2 u = zmul(sR[i][j], sX[j][c]); t.x -= u.x; t.y -= u.y; }
+            sX[i][c] = {t.x / sR[i][i].x, t.y / sR[i][i].x};
+        }
+        double2 *y = Y + (int64_t)blk * p * p + (int64_t)c * p;
+        for (int i = 0; i < p; ++i) {
+            const double d = sD[i] > 0 ? sD[i] : 1.0;
+            y[i] = i <= c ? double2{sX[i][c].x / d, sX[i][c].y / d} : double2{0, 0};
+        }
+        // Rout[:, c] = R (Rprev[:, c]) or R[:, c] D_c
+        double2 *ro = Rout + (int64_t)blk * sr + (int64_t)c * ldr;
+        if (Rprev) {
+            const double2 *rp = Rprev + (int64_t)blk * p * p + (int64_t)c * p;
+            for (int i = 0; i < p; ++i) {
+                double2 t = {0, 0};
+                for (int j = i; j <= c; ++j) { const double2 u = zmul(sR[i][j], rp[j]); t.x += u.x; t.y += u.y; }
+                ro[i] = t;
+            }
+        } else {
+            for (int i = 0; i < p; ++i) ro[i] = {sR[i][c].x * sD[c], sR[i][c].y * sD[c]};
+        }
+    }
+}
+
+// --------------------------------------------- block Hessenberg QR ---
+// One workgroup per block.  Hcol: the new block column (column-major,
+// leading dimension ldh, rows 0 .. (k+2)p); refl: Householder vectors
+// [m][p][p+1] and tau [m][p]; g: least-squares right-hand side (column-
+// major, ldg).  Applies the reflectors of block columns 0..k-1, factors
+// rows kp .. (k+2)p, applies the new reflectors to g and writes the norm
+// of rows (k+1)p .. (k+2)p of g for every column.
+// Reflector (v, tau) acts as y <- y - conj(tau) v (v^H y), v[0] = 1.
+// Windows are 2p x p, element (r, c) at [r * kMaxP + c].
+__device__ __forceinline__ void bqr_reflect(int p, int i, double2 *win, double2 *gw, const double2 *v,
+                                            double2 tau, int c0, double2 *sred) {
+    // columns c0..p-1 of win and, when gw is given, 0..p-1 of gw; rows i..i+p
+    const int tid = threadIdx.x;
+    const int col = tid % (2 * kMaxP), part = tid / (2 * kMaxP);   // 4 parts
+    const bool in_g = col >= kMaxP;
+    const int cc = in_g ? col - kMaxP : col;
+    const bool active = cc < p && (in_g ? gw != nullptr : cc >= c0);
+    double2 *w = in_g ? gw : win;
+    double2 sacc = {0, 0};
+    if (active) {
+        for (int r = part; r <= p; r += 4) {
+            const double2 t = zcmul(v[r], w[(i + r) * kMaxP + cc]);
+            sacc.x += t.x; sacc.y += t.y;
+        }
+    }
+    sred[part * 2 * kMaxP + col] = sacc;
+    __syncthreads();
+    if (active) {
+        double2 tot = {0, 0};
+        for (int q = 0; q < 4; ++q) { tot.x += sred[q * 2 * kMaxP + col].x; tot.y += sred[q * 2 * kMaxP + col].y; }
+        const double2 f = zmul(double2{tau.x, -tau.y}, tot);
+        for (int r = part; r <= p; r += 4) {
+            const double2 d = zmul(v[r], f);
+            double2 *e = &w[(i + r) * kMaxP + cc];
+            e->x -= d.x;
+            e->y -= d.y;
+        }
+    }
+    __syncthreads();
+}
+
+// rows [row0, row0 + p) of a column-major matrix <-> window rows [lrow0, lrow0 + p)
+__device__ __forceinline__ void win_load(int p, double2 *dst, const double2 *src, int64_t ld, int64_t row0,
+                                         int lrow0) {
+    for (int t = threadIdx.x; t < p * p; t += blockDim.x) {
+        const int r = t % p, c = t / p;
+        dst[(lrow0 + r) * kMaxP + c] = src[c * ld + row0 + r];
+    }
+}
+__device__ __forceinline__ void win_store(int p, const double2 *srcw, double2 *dst, int64_t ld, int64_t row0,
+                                          int lrow0) {
+    for (int t = threadIdx.x; t < p * p; t += blockDim.x) {
+        const int r = t % p, c = t / p;
+        dst[c * ld + row0 + r] = srcw[(lrow0 + r) * kMaxP + c];
+    }
+}
+__device__ __forceinline__ void win_shift(int p, double2 *w) {
+    for (int t = threadIdx.x; t < p * p; t += blockDim.x) {
+        const int r = t % p, c = t / p;
+        w[r * kMaxP + c] = w[(p + r) * kMaxP + c];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bqr_update(int p, int k, double2 *Hcol, int64_t ldh, int64_t sh,
+                                                    double2 *refl, double2 *taus, int64_t srefl, int64_t staus,
+                                                    double2 *g, int64_t ldg, int64_t sg, double *res) {
+    __shared__ double2 win[2 * kMaxP * kMaxP];
+    __shared__ double2 gw[2 * kMaxP * kMaxP];
+    __shared__ double2 sv[kMaxP + 1];
+    __shared__ double2 s_tau[1];
+    __shared__ double2 sred[4 * 2 * kMaxP];
+    const int blk = blockIdx.x, tid = threadIdx.x;
+    Hcol += blk * sh;
+    refl += blk * srefl;
+    taus += blk * staus;
+    g += blk * sg;
+    win_load(p, win, Hcol, ldh, 0, 0);
+    win_load(p, win, Hcol, ldh, p, p);
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        if (j > 0) {
+            win_shift(p, win);
+            __syncthreads();
+            win_load(p, win, Hcol, ldh, (int64_t)(j + 1) * p, p);
+            __syncthreads();
+        }
+        for (int i = 0; i < p; ++i) {
+            if (tid <= p) sv[tid] = refl[((int64_t)j * p + i) * (p + 1) + tid];
+            if (tid == 0) s_tau[0] = taus[(int64_t)j * p + i];
+            __syncthreads();
+            bqr_reflect(p, i, win, nullptr, sv, s_tau[0], 0, sred);
+        }
+        win_store(p, win, Hcol, ldh, (int64_t)j * p, 0);
+        __syncthreads();
+    }
+    if (k > 0) {
+        win_shift(p, win);
+        __syncthreads();
+        win_load(p, win, Hcol, ldh, (int64_t)(k + 1) * p, p);
+    }
+    win_load(p, gw, g, ldg, (int64_t)k * p, 0);
+    win_load(p, gw, g, ldg, (int64_t)(k + 1) * p, p);
+    __syncthreads();
+    // factor the 2p x p window; column i has nonzeros in rows 0 .. p + i
+    for (int i = 0; i < p; ++i) {
+        if (tid < kWv) {
+            const double2 x = tid <= p ? win[(i + tid) * kMaxP + i] : double2{0, 0};
+            const double sq = (tid >= 1 && tid <= p) ? x.x * x.x + x.y * x.y : 0.0;
+            const double xn2 = __shfl(wsum(sq), 0);
+            const double2 al = {__shfl(x.x, 0), __shfl(x.y, 0)};
+            double2 tau = {0, 0}, scale = {0, 0};
+            if (!(xn2 == 0.0 && al.y == 0.0)) {
+                const double nb = sqrt(al.x * al.x + al.y * al.y + xn2);
+                const double bt = al.x >= 0 ? -nb : nb;
+                tau = {(bt - al.x) / bt, -al.y / bt};
+                const double2 d = {al.x - bt, al.y};   // scale = 1 / (alpha - beta)
+                const double dd = d.x * d.x + d.y * d.y;
+                scale = {d.x / dd, -d.y / dd};
+            }
+            if (tid <= p) {
+                const double2 vr = tid == 0 ? double2{1.0, 0.0} : zmul(x, scale);
+                sv[tid] = vr;
+                refl[((int64_t)k * p + i) * (p + 1) + tid] = vr;
+            }
+            if (tid == 0) { s_tau[0] = tau; taus[(int64_t)k * p + i] = tau; }
+        }
+        __syncthreads();
+        bqr_reflect(p, i, win, gw, sv, s_tau[0], i, sred);
+    }
+    win_store(p, win, Hcol, ldh, (int64_t)k * p, 0);
+    win_store(p, win, Hcol, ldh, (int64_t)(k + 1) * p, p);
+    win_store(p, gw, g, ldg, (int64_t)k * p, 0);
+    win_store(p, gw, g, ldg, (int64_t)(k + 1) * p, p);
+    if (tid < p) {
+        double sacc = 0.0;
+        for (int r = 0; r < p; ++r) {
+            const double2 e = gw[(p + r) * kMaxP + tid];
+            sacc += e.x * e.x + e.y * e.y;
+        }
+        res[blk * p + tid] = sqrt(sacc);
+    }
+}
+
+// Back substitution R Y = g (n x n upper triangular, column-major ldh; g
+// column-major ldg), Y overwrites g.  One workgroup per block.
+__global__ __launch_bounds__(256) void k_bqr_solve(int p, int n, const double2 *H, int64_t ldh, int64_t sh,
+                                                   double2 *g, int64_t ldg, int64_t sg) {
+    __shared__ double2 sy[kMaxP];
+    const int blk = blockIdx.x, tid = threadIdx.x;
+    H += blk * sh;
+    g += blk * sg;
+    for (int i = n - 1; i >= 0; --i) {
+        if (tid < p) {
+            const double2 d = H[(int64_t)i * ldh + i], v = g[(int64_t)tid * ldg + i];
+            const double dd = d.x * d.x + d.y * d.y;
+            const double2 y = {(v.x * d.x + v.y * d.y) / dd, (v.y * d.x - v.x * d.y) / dd};
+            sy[tid] = y;
+            g[(int64_t)tid * ldg + i] = y;
+        }
+        __syncthreads();
+        const double2 *hc = H + (int64_t)i * ldh;
+        for (int t = tid; t < i * p; t += blockDim.x) {
+            const int r = t % i, c = t / i;
+            const double2 u = zmul(hc[r], sy[c]);
+            double2 *gp = g + (int64_t)c * ldg + r;
+            gp->x -= u.x;
+            gp->y -= u.y;
+        }
+        __syncthreads();
+    }
+}
+
+// Norm of every column (one workgroup per column).
+__global__ __launch_bounds__(256) void k_colnorm(int64_t N, ColMap vin, double *out) {
+    __shared__ double sp[4];
+    const double2 *v = col_ptr<const double2>(vin, blockIdx.x);
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) s += v[i].x * v[i].x + v[i].y * v[i].y;
+    s = wsum(s);
+    if (threadIdx.x % kWv == 0) sp[threadIdx.x / kWv] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(sp[0] + sp[1] + sp[2] + sp[3]);
+}
+
+__global__ void k_zero(double2 *p, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = {0.0, 0.0};
+}
+__global__ void k_add_blocks(double2 *dst, int64_t ldd, int64_t sd, const double2 *src, int64_t lds,
+                             int64_t ss, int rows, int cols, int nblk) {
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= (int64_t)rows * cols * nblk) return;
+    const int64_t b = id / ((int64_t)rows * cols), t = id % ((int64_t)rows * cols);
+    const int64_t r = t % rows, c = t / rows;
+    double2 *d = dst + b * sd + c * ldd + r;
+    const double2 v = src[b * ss + c * lds + r];
+    d->x += v.x;
+    d->y += v.y;
+}
+__global__ void k_c128_to_c64(const double2 *a, float2 *b, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = {(float)a[i].x, (float)a[i].y};
+}
+
+// ------------------------------------------------------------ driver ---
+namespace {
+struct BlockWork {
+    int64_t N = 0, n2 = 0;
+    int ncol = 0, p = 0, nblk = 0, m = 0;
+    double2 *V = nullptr;      // [nblk][m+1][p][N]
+    float2 *Zt = nullptr;      // [ncol][N]
+    float2 *T32 = nullptr;     // [4 ncol][n2]
+    double2 *T64 = nullptr;    // [4 ncol][n2]
+    double2 *Q = nullptr;      // [ncol][N]
+    double2 *R = nullptr;      // [ncol][N] refinement residual
+    double2 *Hs = nullptr;     // [nblk][m p][(m+1) p] column-major
+    double2 *Ht = nullptr;     // [nblk][p][(m+1) p]
+    double2 *G = nullptr, *Yi = nullptr, *Rt = nullptr;   // [nblk][p][p]
+    double2 *refl = nullptr, *tau = nullptr;
+    double2 *g = nullptr;      // [nblk][p][(m+1) p]
+    double2 *split = nullptr;
+    int64_t split_elems = 0;
+    double *res = nullptr;     // [ncol]
+    int *flags = nullptr;
+    std::vector<void *> owned;
+    ~BlockWork() { for (void *q : owned) (void)hipFree(q); }
+    template <typename T>
+    int get(T **p, size_t n) {
+        hipError_t e = hipMalloc((void **)p, sizeof(T) * std::max<size_t>(n, 1));
+        if (e != hipSuccess) { set_error(std::string("block solve workspace: ") + hipGetErrorString(e)); return MBEM_ENOMEM; }
+        owned.push_back(*p);
+        return MBEM_OK;
+    }
+    int64_t ldh() const { return (int64_t)(m + 1) * p; }
+    int64_t sV() const { return (int64_t)(m + 1) * p * N; }
+    ColMap vcol(int k) const { return ColMap{V + (int64_t)k * p * N, p, sV(), N}; }
+};
+
+ColMap flat(void *base, int64_t ld) { return ColMap{base, 1 << 30, 0, ld}; }
+}  // namespace
+
+static int zero(double2 *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return MBEM_OK;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+// k-splits of a projection with ka basis rows: enough workgroups to cover
+// the chip, each split at least 256 long.
+static int proj_splits(int64_t ka, int p, int nblk, int64_t N) {
+    const int64_t tiles = ((ka + 63) / 64) * ((2 * p + 63) / 64) * nblk;
+    int64_t sp = 1024 / std::max<int64_t>(tiles, 1);
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, N / 256));
+    return (int)std::max<int64_t>(2, std::min<int64_t>(sp, 64));
+}
+
+// H-type product out = op(V)^H W for all blocks: A rows = ka basis vectors
+// of one block, B rows = p columns of W; output column-major ld ldo.
+static int block_project(BlockWork &w, const double2 *Vb, int64_t sVb, int ka, ColMap W, double2 *out,
+                         int64_t ldo, int64_t so, hipStream_t s) {
+    CgemmList L;
+    L.np = 1;
+    CgemmProb &P = L.p[0];
+    P.A = Vb; P.lda = w.N; P.sa = sVb;
+    P.B = W.base; P.ldb = W.ld; P.sb = W.sblk;
+    P.C = out; P.ldc = ldo; P.sc = so;
+    P.M = ka; P.Nb = w.p; P.K = w.N; P.batch = w.nblk;
+    const int splits = proj_splits(ka, w.p, w.nblk, w.N);
+    if (cgemm_f64_work(L, splits) > w.split_elems) { set_error("split workspace too small"); return MBEM_EINVAL; }
+    return cgemm_f64_run(L, false, true, splits, w.split, s);
+}
+
+// Cholesky QR (twice) of the p columns of every block in `W` into `out`;
+// the triangular factor R (R W-hat = W) goes to Rdst (column-major ldr).
+static int block_cholqr2(BlockWork &w, ColMap W, ColMap out, bool scale, double2 *Rdst, int64_t ldr,
+                         int64_t sr, hipStream_t s) {
+    const int64_t pp = (int64_t)w.p * w.p;
+    // pass 1: W -> Q
+    MBEM_TRY(block_project(w, (const double2 *)W.base, W.sblk, w.p, W, w.G, w.p, pp, s));
+    hipLaunchKernelGGL(k_cholqr_small, dim3(w.nblk), dim3(64), 0, s, w.p, w.N, w.G, scale ? 1 : 0,
+                       (const double2 *)nullptr, w.Yi, w.Rt, (int64_t)w.p, pp, w.flags);
+    MBEM_HIP(hipGetLastError());
+    MBEM_TRY(nn_update(w.N, w.p, w.p, w.nblk, (const double2 *)W.base, w.N, W.sblk, w.Yi, w.p, pp, w.Q, w.N,
+                       (int64_t)w.p * w.N, 1.0, 0.0, s));
+    // pass 2: Q -> out, R = R2 R1
+    const ColMap Qm{w.Q, w.p, (int64_t)w.p * w.N, w.N};
+    MBEM_TRY(block_project(w, w.Q, Qm.sblk, w.p, Qm, w.G, w.p, pp, s));
+    hipLaunchKernelGGL(k_cholqr_small, dim3(w.nblk), dim3(64), 0, s, w.p, w.N, w.G, 0, (const double2 *)w.Rt,
+                       w.Yi, Rdst, ldr, sr, w.flags);
+    MBEM_HIP(hipGetLastError());
+    return nn_update(w.N, w.p, w.p, w.nblk, w.Q, w.N, Qm.sblk, w.Yi, w.p, pp, (double2 *)out.base, w.N, out.sblk,
+                     1.0, 0.0, s);
+}
+
+// Dense part of Z X for ncol columns, X in FP32 (Zt) through the MFMA GEMM
+static CgemmList matvec_list32(const mbem_op *op, const void *const K32[3], const float2 *X, int ncol,
+                               float2 *T) {
+    const int64_t n2 = op->n2, N = 2 * n2;
+    CgemmList L;
+    L.np = 3;
+    for (int q = 0; q < 3; ++q) {
+        CgemmProb &P = L.p[q];
+        P.A = K32[q]; P.lda = n2; P.M = n2; P.K = n2; P.ldc = n2; P.batch = 1;
+    }
+    L.p[0].B = X; L.p[0].ldb = n2; L.p[0].Nb = 2 * ncol; L.p[0].C = T;
+    L.p[1].B = X + n2; L.p[1].ldb = N; L.p[1].Nb = ncol; L.p[1].C = T + 2 * ncol * n2;
+    L.p[2].B = X; L.p[2].ldb = N; L.p[2].Nb = ncol; L.p[2].C = T + 3 * ncol * n2;
+    return L;
+}
+
+static ZCoef zcoef(const mbem_op *op) { return {op->iw, op->ce, op->cm}; }
+
+int block_matvec32_list(const mbem_op *op, const float2 *X, int ncol, float2 *T, CgemmList *out) {
+    const void *K32[3];
+    for (int q = 0; q < 3; ++q) K32[q] = op->prec == MBEM_MIXED ? op->K[q] : op->K32[q];
+    if (!K32[0]) { set_error("complex64 operator copy missing"); return MBEM_EINVAL; }
+    *out = matvec_list32(op, K32, X, ncol, T);
+    return MBEM_OK;
+}
+
+int ensure_c64_copy(mbem_op *op, hipStream_t s) {
+    if (op->prec == MBEM_MIXED || op->K32[0]) return MBEM_OK;
+    const int64_t n = op->n2 * op->n2;
+    for (int q = 0; q < 3; ++q) {
+        hipError_t e = hipMalloc(&op->K32[q], sizeof(float2) * n);
+        if (e != hipSuccess) { set_error("complex64 operator copy: out of memory"); return MBEM_ENOMEM; }
+        hipLaunchKernelGGL(k_c128_to_c64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           (const double2 *)op->K[q], (float2 *)op->K32[q], n);
+        MBEM_HIP(hipGetLastError());
+    }
+    return MBEM_OK;
+}
+
+// R = B - Z X with FP64 accumulation of the stored operator
+static int block_residual(const mbem_op *op, BlockWork &w, const double2 *X, const double2 *B, double2 *R,
+                          hipStream_t s) {
+    const int64_t n2 = w.n2, N = w.N;
+    CgemmList L;
+    L.np = 3;
+    for (int q = 0; q < 3; ++q) {
+        CgemmProb &P = L.p[q];
+        P.A = op->K[q]; P.lda = n2; P.M = n2; P.K = n2; P.ldc = n2; P.batch = 1;
+    }
+    L.p[0].B = X; L.p[0].ldb = n2; L.p[0].Nb = 2 * w.ncol; L.p[0].C = w.T64;
+    L.p[1].B = X + n2; L.p[1].ldb = N; L.p[1].Nb = w.ncol; L.p[1].C = w.T64 + 2 * w.ncol * n2;
+    L.p[2].B = X; L.p[2].ldb = N; L.p[2].Nb = w.ncol; L.p[2].C = w.T64 + 3 * w.ncol * n2;
+    MBEM_TRY(cgemm_f64_run(L, op->prec == MBEM_MIXED, false, 1, nullptr, s));
+    const mbem_mesh *m = op->mesh;
+    const int64_t tot = n2 * w.ncol;
+    hipLaunchKernelGGL((k_block_combine<double2, double2, true>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       s, n2, w.ncol, (const double2 *)w.T64, m->d_mptr, m->d_mcol, op->d_mval, zcoef(op),
+                       flat((void *)X, N), flat((void *)B, N), flat(R, N));
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_opts *o, double2 *X,
+                    mbem_block_stats *st, hipStream_t s) {
+    BlockWork w;
+    w.n2 = op->n2;
+    w.N = 2 * op->n2;
+    w.ncol = ncol;
+    int p = o->block > 0 ? o->block : 0;
+    if (p == 0) {
+        for (int d = std::min(ncol, kMaxP); d >= 1; --d)
+            if (ncol % d == 0) { p = d; break; }
+    }
+    if (p < 1 || p > kMaxP || ncol % p != 0) { set_error("block size must divide nrhs and be at most 32"); return MBEM_EINVAL; }
+    w.p = p;
+    w.nblk = ncol / p;
+    w.m = o->maxit > 0 ? o->maxit : 60;
+    const int maxref = o->max_refine > 0 ? o->max_refine : 10;
+    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-5;
+    const int64_t N = w.N, n2 = w.n2, ldh = w.ldh();
+    MBEM_TRY(ensure_c64_copy(op, s));
+    MBEM_TRY(w.get(&w.V, (size_t)w.nblk * w.sV()));
+    MBEM_TRY(w.get(&w.Zt, (size_t)ncol * N));
+    MBEM_TRY(w.get(&w.T32, (size_t)4 * ncol * n2));
+    MBEM_TRY(w.get(&w.T64, (size_t)4 * ncol * n2));
+    MBEM_TRY(w.get(&w.Q, (size_t)ncol * N));
+    MBEM_TRY(w.get(&w.R, (size_t)ncol * N));
+    MBEM_TRY(w.get(&w.Hs, (size_t)w.nblk * ldh * w.m * p));
+    MBEM_TRY(w.get(&w.Ht, (size_t)w.nblk * ldh * p));
+    MBEM_TRY(w.get(&w.G, (size_t)w.nblk * p * p));
+    MBEM_TRY(w.get(&w.Yi, (size_t)w.nblk * p * p));
+    MBEM_TRY(w.get(&w.Rt, (size_t)w.nblk * p * p));
+    MBEM_TRY(w.get(&w.refl, (size_t)w.nblk * w.m * p * (p + 1)));
+    MBEM_TRY(w.get(&w.tau, (size_t)w.nblk * w.m * p));
+    MBEM_TRY(w.get(&w.g, (size_t)w.nblk * ldh * p));
+    w.split_elems = 0;
+    for (int ka = p; ka <= w.m * p; ka += p)
+        w.split_elems = std::max<int64_t>(w.split_elems, (int64_t)proj_splits(ka, p, w.nblk, N) * ka * p * w.nblk);
+    MBEM_TRY(w.get(&w.split, (size_t)w.split_elems));
+    MBEM_TRY(w.get(&w.res, (size_t)2 * ncol));
+    MBEM_TRY(w.get(&w.flags, 1));
+    MBEM_HIP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
+
+    // FP32 GEMM tile shape: caller's choice, the tuned one, or tune now
+    int cfg = o->gemm_config;
+    CgemmList L32;
+    MBEM_TRY(block_matvec32_list(op, w.Zt, ncol, w.T32, &L32));
+    if (cfg < 0 || cfg >= kGemmConfigs) {
+        if (op->tuned_ncol == ncol) cfg = op->tuned_cfg;
+        else {
+            MBEM_TRY(cgemm_f32_autotune(L32, s, 2, nullptr, &cfg));
+            op->tuned_ncol = ncol;
+            op->tuned_cfg = cfg;
+        }
+    }
+    hipEvent_t ea, eb;
+    MBEM_HIP(hipEventCreate(&ea));
+    MBEM_HIP(hipEventCreate(&eb));
+    double t_gemm = 0.0;
+    int n_gemm = 0;
+
+    std::vector<double> bn(ncol), rn(ncol), resh(ncol);
+    MBEM_TRY(zero(X, (int64_t)ncol * N, s));
+    hipLaunchKernelGGL(k_colnorm, dim3(ncol), dim3(256), 0, s, N, flat((void *)B, N), w.res);
+    MBEM_HIP(hipGetLastError());
+    MBEM_HIP(hipMemcpyAsync(bn.data(), w.res, sizeof(double) * ncol, hipMemcpyDeviceToHost, s));
+    MBEM_HIP(hipMemcpyAsync(w.R, B, sizeof(double2) * ncol * N, hipMemcpyDeviceToDevice, s));
+    MBEM_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < ncol; ++c)
+        if (!(bn[c] > 0)) { set_error("right-hand side column with zero norm"); return MBEM_EINVAL; }
+    const mbem_mesh *mesh = op->mesh;
+    const int64_t tot = n2 * ncol;
+    const ColMap Zcols{w.Zt, 1 << 30, 0, N};
+    int total_it = 0, sweeps = 0;
+    double worst = 0.0;
+    bool done = false;
+    for (int sw = 0; sw < maxref && !done; ++sw) {
+        ++sweeps;
+        // V_0 R_0 = residual (columns normalised first), g = [R_0; 0]
+        MBEM_TRY(zero(w.g, (int64_t)w.nblk * ldh * p, s));
+        const ColMap Rm{w.R, p, (int64_t)p * N, N};
+        MBEM_TRY(block_cholqr2(w, Rm, w.vcol(0), true, w.g, ldh, ldh * p, s));
+        int k = 0;
+        for (k = 0; k < w.m; ++k) {
+            // W = Z P^-1 V_k  into the slot of V_{k+1}
+            MBEM_TRY(mbj_apply_multi(op, w.vcol(k), Zcols, ncol, true, false, s));
+            MBEM_HIP(hipEventRecord(ea, s));
+            MBEM_TRY(cgemm_f32_run(L32, cfg, s));
+            MBEM_HIP(hipEventRecord(eb, s));
+            const ColMap Wk = w.vcol(k + 1);
+            hipLaunchKernelGGL((k_block_combine<float2, float2, false>), dim3((unsigned)((tot + 255) / 256)),
+                               dim3(256), 0, s, n2, ncol, (const float2 *)w.T32, mesh->d_mptr, mesh->d_mcol,
+                               op->d_mval, zcoef(op), Zcols, Zcols, Wk);
+            MBEM_HIP(hipGetLastError());
+            // two passes of block classical Gram-Schmidt against V_0..V_k
+            const int ka = (k + 1) * p;
+            double2 *hk = w.Hs + (int64_t)k * p * ldh;
+            MBEM_TRY(block_project(w, w.V, w.sV(), ka, Wk, hk, ldh, ldh * w.m * p, s));
+            MBEM_TRY(nn_update(N, ka, p, w.nblk, w.V, N, w.sV(), hk, ldh, ldh * w.m * p, (double2 *)Wk.base, N,
+                               w.sV(), -1.0, 1.0, s));
+            MBEM_TRY(block_project(w, w.V, w.sV(), ka, Wk, w.Ht, ldh, ldh * p, s));
+            MBEM_TRY(nn_update(N, ka, p, w.nblk, w.V, N, w.sV(), w.Ht, ldh, ldh * p, (double2 *)Wk.base, N,
+                               w.sV(), -1.0, 1.0, s));
+            hipLaunchKernelGGL(k_add_blocks, dim3((unsigned)(((int64_t)ka * p * w.nblk + 255) / 256)), dim3(256),
+                               0, s, hk, ldh, ldh * w.m * p, (const double2 *)w.Ht, ldh, ldh * p, ka, p, w.nblk);
+            MBEM_HIP(hipGetLastError());
+            // W = V_{k+1} R  (R into rows (k+1)p .. (k+2)p of the block column)
+            MBEM_TRY(block_cholqr2(w, Wk, Wk, false, hk + (int64_t)(k + 1) * p, ldh, ldh * w.m * p, s));
+            hipLaunchKernelGGL(k_bqr_update, dim3(w.nblk), dim3(256), 0, s, p, k, hk, ldh, ldh * w.m * p, w.refl,
+                               w.tau, (int64_t)w.m * p * (p + 1), (int64_t)w.m * p, w.g, ldh, ldh * p, w.res);
+            MBEM_HIP(hipGetLastError());
+            MBEM_HIP(hipMemcpyAsync(resh.data(), w.res, sizeof(double) * ncol, hipMemcpyDeviceToHost, s));
+            MBEM_HIP(hipStreamSynchronize(s));
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ea, eb) == hipSuccess) { t_gemm += ms; ++n_gemm; }
+            // every column reduced by inner_tol from this sweep's start, or
+            // already well below the overall tolerance
+            bool ok = true;
+            for (int c = 0; c < ncol; ++c) {
+                const double r0 = sw == 0 ? bn[c] : rn[c];
+                if (!(resh[c] <= std::max(itol * r0, 0.3 * o->tol * bn[c]))) { ok = false; break; }
+            }
+            if (ok) { ++k; break; }
+        }
+        total_it += k;
+        // X += P^-1 V Y,  Y = R^-1 g
+        const int n = k * p;
+        hipLaunchKernelGGL(k_bqr_solve, dim3(w.nblk), dim3(256), 0, s, p, n, (const double2 *)w.Hs, ldh,
+                           ldh * w.m * p, w.g, ldh, ldh * p);
+        MBEM_HIP(hipGetLastError());
+        MBEM_TRY(nn_update(N, n, p, w.nblk, w.V, N, w.sV(), w.g, ldh, ldh * p, w.Q, N, (int64_t)p * N, 1.0, 0.0,
+                           s));
+        MBEM_TRY(mbj_apply_multi(op, flat(w.Q, N), flat(X, N), ncol, false, true, s));
+        // refinement residual in FP64
+        MBEM_TRY(block_residual(op, w, X, B, w.R, s));
+        hipLaunchKernelGGL(k_colnorm, dim3(ncol), dim3(256), 0, s, N, flat(w.R, N), w.res);
+        MBEM_HIP(hipGetLastError());
+        MBEM_HIP(hipMemcpyAsync(rn.data(), w.res, sizeof(double) * ncol, hipMemcpyDeviceToHost, s));
+        MBEM_HIP(hipStreamSynchronize(s));
+        worst = 0.0;
+        for (int c = 0; c < ncol; ++c) worst = std::max(worst, bn[c] > 0 ? rn[c] / bn[c] : 0.0);
+        done = worst <= o->tol;
+    }
+    int flags = 0;
+    MBEM_HIP(hipMemcpy(&flags, w.flags, sizeof(int), hipMemcpyDeviceToHost));
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    if (st) {
+        st->iters = total_it;
+        st->sweeps = sweeps;
+        st->block = p;
+        st->gemm_config = cfg;
+        st->rel_resid = worst;
+        st->t_gemm_ms = t_gemm;
+        st->n_gemm = n_gemm;
+        st->shifted = flags;
+    }
+    if (!done) { set_error("block GMRES did not reach the tolerance"); return MBEM_ENOCONV; }
+    return MBEM_OK;
+}
+
+}  // namespace mbem

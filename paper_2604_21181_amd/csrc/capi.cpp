@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 
+#include "gemm.h"
 #include "mbem_internal.h"
 
 namespace mbem {
@@ -66,6 +67,7 @@ static void mesh_free_device(mbem_mesh *m) {
 
 static void op_free_device(mbem_op *op) {
     for (int o = 0; o < 3; ++o) dfree(op->K[o]);
+    for (int o = 0; o < 3; ++o) dfree(op->K32[o]);
     dfree(op->d_mval);
     dfree(op->d_minv);
     dfree(op->d_lu);
@@ -487,6 +489,80 @@ int mbem_solve(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs, con
     }
     if (status == MBEM_ENOCONV) set_error("GMRES did not reach the tolerance");
     return status;
+}
+
+int mbem_solve_block(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs, const mbem_block_opts *o,
+                     mbem_c128 *x, mbem_block_stats *stats) {
+    if (!op || !b || !x || !o || nrhs < 1 || o->maxit < 0 || o->max_refine < 0 || !(o->tol > 0)) {
+        set_error("bad argument");
+        return MBEM_EINVAL;
+    }
+    MBEM_TRY(set_device(ctx));
+    Timer t;
+    t.start(ctx->stream);
+    const int st = block_solve_run(op, (const double2 *)b, nrhs, o, (double2 *)x, stats, ctx->stream);
+    const double ms = t.stop(ctx->stream);
+    if (stats) stats->t_solve_ms = ms;
+    return st;
+}
+
+int mbem_gemm_autotune(mbem_ctx *ctx, mbem_op *op, int32_t nrhs, int32_t reps, float *ms, int32_t *best) {
+    if (!op || nrhs < 1 || !best) { set_error("bad argument"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    const hipStream_t s = ctx->stream;
+    MBEM_TRY(ensure_c64_copy(op, s));
+    const int64_t n2 = op->n2, N = 2 * n2;
+    float2 *X = nullptr, *T = nullptr;
+    MBEM_TRY(dalloc(&X, (size_t)nrhs * N));
+    int st = dalloc(&T, (size_t)4 * nrhs * n2);
+    if (st == MBEM_OK) {
+        MBEM_HIP(hipMemsetAsync(X, 0, sizeof(float2) * nrhs * N, s));
+        CgemmList L;
+        L.np = 3;
+        for (int q = 0; q < 3; ++q) {
+            CgemmProb &P = L.p[q];
+            P.A = op->prec == MBEM_MIXED ? op->K[q] : op->K32[q];
+            P.lda = n2; P.M = n2; P.K = n2; P.ldc = n2; P.batch = 1;
+        }
+        L.p[0].B = X; L.p[0].ldb = n2; L.p[0].Nb = 2 * nrhs; L.p[0].C = T;
+        L.p[1].B = X + n2; L.p[1].ldb = N; L.p[1].Nb = nrhs; L.p[1].C = T + 2 * nrhs * n2;
+        L.p[2].B = X; L.p[2].ldb = N; L.p[2].Nb = nrhs; L.p[2].C = T + 3 * nrhs * n2;
+        int b = 0;
+        st = cgemm_f32_autotune(L, s, std::max(1, (int)reps), ms, &b);
+        if (st == MBEM_OK) { op->tuned_ncol = nrhs; op->tuned_cfg = b; *best = b; }
+    }
+    (void)hipStreamSynchronize(s);
+    dfree(X);
+    dfree(T);
+    return st;
+}
+
+int mbem_cgemm(mbem_ctx *ctx, int32_t dtype, int32_t conj_a, int64_t M, int64_t Nb, int64_t K, const void *A,
+               int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc, int32_t config) {
+    if (dtype < 0 || dtype > 2 || M < 0 || Nb < 0 || K < 0 || (dtype == 0 && conj_a)) {
+        set_error("bad argument");
+        return MBEM_EINVAL;
+    }
+    MBEM_TRY(set_device(ctx));
+    CgemmList L;
+    L.np = 1;
+    CgemmProb &P = L.p[0];
+    P.A = A; P.B = B; P.C = C; P.lda = lda; P.ldb = ldb; P.ldc = ldc; P.M = M; P.Nb = Nb; P.K = K;
+    P.batch = 1;
+    if (!cgemm_list_valid(L, dtype == 1 ? 16 : 8, dtype == 0 ? 8 : 16)) {
+        set_error("GEMM operands: null pointer, leading dimension or alignment");
+        return MBEM_EINVAL;
+    }
+    if (M == 0 || Nb == 0) return MBEM_OK;
+    int st;
+    if (dtype == 0) {
+        if (config < 0 || config >= kGemmConfigs) { set_error("unknown GEMM configuration"); return MBEM_EINVAL; }
+        st = cgemm_f32_run(L, config, ctx->stream);
+    } else {
+        st = cgemm_f64_run(L, dtype == 2, conj_a != 0, 1, nullptr, ctx->stream);
+    }
+    if (st == MBEM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) { set_error("GEMM failed"); st = MBEM_EDEVICE; }
+    return st;
 }
 
 int mbem_farfield(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const mbem_c128 *x,

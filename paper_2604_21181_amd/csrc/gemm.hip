@@ -1,0 +1,480 @@
+// Complex GEMMs on the matrix cores for the multi-right-hand-side solve.
+//
+// Every product here has the shape
+//     C[b][m] = sum_k op(A[m][k]) * B[b][k]        (complex, op = id or conj)
+// with both operands contiguous along k: A is a stored operator block
+// (row-major) or a Krylov basis block, B holds one vector per row (the
+// right-hand sides of a block).  The complex product is carried out as a
+// real GEMM of twice the size in k and in the output columns:
+//     A_r = [a_re a_im a_re a_im ...]  (the complex row read as floats)
+//     B'  row 2b   = [ b_re  -b_im ...]   -> Re C      (conj: [b_re  b_im])
+//     B'  row 2b+1 = [ b_im   b_re ...]   -> Im C      (conj: [b_im -b_re])
+// B' is formed while staging B through LDS; A is used as stored.
+//
+// FP32 (complex64 operator, FP32 accumulation): v_mfma_f32_32x32x2f32, one
+// template per tile shape; the shape is chosen at run time by measuring
+// every candidate on the problem at hand (autotune below).
+// FP64 (basis projections, Gram matrices, refinement residuals):
+// v_mfma_f64_16x16x4f64 on 64 x 64 tiles with an optional split of k.
+#include <algorithm>
+#include <cstdio>
+#include <type_traits>
+
+#include "gemm.h"
+
+namespace mbem {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Each of the 8 XCDs receives workgroups round-robin; give each one a
+// contiguous range of tiles so that tiles sharing rows of A meet in one L2.
+__device__ inline int64_t xcd_tile(int64_t bid, int64_t total) {
+    const int64_t q = total / 8, r = total % 8;
+    const int64_t xcd = bid % 8, local = bid / 8;
+    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+struct TileRef {
+    int q;            // problem
+    int64_t bidx;     // batch entry
+    int64_t tm, tn;   // tile coordinates
+};
+
+__device__ inline TileRef locate(const CgemmList &L, int64_t tile) {
+    TileRef t;
+    t.q = 0;
+    if (L.np > 1 && tile >= L.p[1].tile0) t.q = 1;
+    if (L.np > 2 && tile >= L.p[2].tile0) t.q = 2;
+    return t;
+}
+
+// Uniform selection of one of the (at most three) problems without
+// dynamic indexing of the kernel argument.
+#define MBEM_PICK(L, q, field) ((q) == 0 ? (L).p[0].field : (q) == 1 ? (L).p[1].field : (L).p[2].field)
+
+// ------------------------------------------------------------- FP32 ----
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_cgemm_f32(CgemmList L) {
+    constexpr int NWN = BN / WN;
+    constexpr int NT = 64 * (BM / WM) * NWN;
+    constexpr int TM = WM / 32, TN = WN / 32;
+    constexpr int LD = 20;                        // 16 real k + pad, in floats
+    constexpr int NA = (BM * 4 + NT - 1) / NT;    // float4 loads of A per stage
+    constexpr int NB = (BN * 2 + NT - 1) / NT;    // float4 loads of B per stage
+    __shared__ __align__(16) float sA[2][BM * LD];
+    __shared__ __align__(16) float sB[2][BN * LD];
+
+    const int64_t tile = xcd_tile(blockIdx.x, L.total);
+    const int q = locate(L, tile).q;
+    const int64_t t = tile - MBEM_PICK(L, q, tile0);
+    const int64_t per = MBEM_PICK(L, q, tiles);
+    const int64_t tn_count = MBEM_PICK(L, q, tn);
+    const int64_t bidx = t / per, r = t % per;
+    const int64_t m0 = (r / tn_count) * BM, n0 = (r % tn_count) * BN;
+    const int64_t M = MBEM_PICK(L, q, M), Nb = MBEM_PICK(L, q, Nb), K = MBEM_PICK(L, q, K);
+    const int64_t lda = MBEM_PICK(L, q, lda), ldb = MBEM_PICK(L, q, ldb), ldc = MBEM_PICK(L, q, ldc);
+    const float2 *A = (const float2 *)MBEM_PICK(L, q, A) + bidx * MBEM_PICK(L, q, sa);
+    const float2 *B = (const float2 *)MBEM_PICK(L, q, B) + bidx * MBEM_PICK(L, q, sb);
+    float2 *C = (float2 *)MBEM_PICK(L, q, C) + bidx * MBEM_PICK(L, q, sc);
+    const int64_t b0 = n0 / 2;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / NWN, wn = wave % NWN;
+    const int h = lane >> 5, l32 = lane & 31;
+
+    f32x4 ra[NA], rb[NB];
+    auto gload = [&](int64_t kc0) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int idx = tid + i * NT;
+            f32x4 v = {0.f, 0.f, 0.f, 0.f};
+            const int64_t m = m0 + (idx >> 2), kc = kc0 + 2 * (idx & 3);
+            if (idx < BM * 4 && m < M) {
+                const float2 *src = A + m * lda + kc;
+                if (kc + 1 < K) v = *(const f32x4 *)src;
+                else if (kc < K) { const float2 w = src[0]; v = {w.x, w.y, 0.f, 0.f}; }
+            }
+            ra[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int idx = tid + i * NT;
+            f32x4 v = {0.f, 0.f, 0.f, 0.f};
+            const int64_t b = b0 + (idx >> 2), kc = kc0 + 2 * (idx & 3);
+            if (idx < BN * 2 && b < Nb) {
+                const float2 *src = B + b * ldb + kc;
+                if (kc + 1 < K) v = *(const f32x4 *)src;
+                else if (kc < K) { const float2 w = src[0]; v = {w.x, w.y, 0.f, 0.f}; }
+            }
+            rb[i] = v;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < BM * 4) *(f32x4 *)&sA[buf][(idx >> 2) * LD + 4 * (idx & 3)] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < BN * 2) {
+                const f32x4 v = rb[i];
+                const int row = idx >> 2, k4 = 4 * (idx & 3);
+                *(f32x4 *)&sB[buf][(2 * row) * LD + k4] = f32x4{v.x, -v.y, v.z, -v.w};
+                *(f32x4 *)&sB[buf][(2 * row + 1) * LD + k4] = f32x4{v.y, v.x, v.w, v.z};
+            }
+        }
+    };
+
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+    const int64_t nst = (K + 7) / 8;   // stages of 8 complex k
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int64_t st = 0; st < nst; ++st) {
+        const int cur = (int)(st & 1);
+        if (st + 1 < nst) gload((st + 1) * 8);
+        // lane (l32, h) feeds MFMA step s with real k = 8 h + s of the stage
+        f32x4 a[TM][2], b[TN][2];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const float *src = &sA[cur][(wm * WM + i * 32 + l32) * LD + 8 * h];
+            a[i][0] = *(const f32x4 *)src;
+            a[i][1] = *(const f32x4 *)(src + 4);
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const float *src = &sB[cur][(wn * WN + j * 32 + l32) * LD + 8 * h];
+            b[j][0] = *(const f32x4 *)src;
+            b[j][1] = *(const f32x4 *)(src + 4);
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][s >> 2][s & 3], b[j][s >> 2][s & 3],
+                                                                     acc[i][j], 0, 0, 0);
+        if (st + 1 < nst) sstore(cur ^ 1);
+        __syncthreads();
+    }
+    // accumulator (lane, e): column l32, row 8 (e / 4) + 4 h + e % 4; even
+    // real columns are real parts, the odd neighbour holds the imaginary part
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const float v = acc[i][j][e];
+                const float w = __shfl_xor(v, 1);
+                const int64_t m = m0 + wm * WM + i * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                const int64_t n = n0 + wn * WN + j * 32 + l32;
+                if ((l32 & 1) == 0 && m < M && (n >> 1) < Nb) C[(n >> 1) * ldc + m] = float2{v, w};
+            }
+}
+
+// ------------------------------------------------------------- FP64 ----
+// 64 x 64 real tile, 4 waves of 32 x 32, k split over gridDim.y: split y
+// covers complex k in [y kchunk, (y + 1) kchunk) and writes its partial
+// product at C + y * split_stride.
+template <typename TA, typename TB, bool CONJ>
+__global__ __launch_bounds__(256) void k_cgemm_f64(CgemmList L, int64_t kchunk, int64_t split_stride) {
+    constexpr int BM = 64, BN = 64, WM = 32, WN = 32, NT = 256;
+    constexpr int LD = 18;   // 16 real k + pad, in doubles
+    __shared__ __align__(16) double sA[2][BM * LD];
+    __shared__ __align__(16) double sB[2][BN * LD];
+
+    const int64_t tile = xcd_tile(blockIdx.x, L.total);
+    const int q = locate(L, tile).q;
+    const int64_t t = tile - MBEM_PICK(L, q, tile0);
+    const int64_t per = MBEM_PICK(L, q, tiles);
+    const int64_t tn_count = MBEM_PICK(L, q, tn);
+    const int64_t bidx = t / per, r = t % per;
+    const int64_t m0 = (r / tn_count) * BM, n0 = (r % tn_count) * BN;
+    const int64_t M = MBEM_PICK(L, q, M), Nb = MBEM_PICK(L, q, Nb), Kall = MBEM_PICK(L, q, K);
+    const int64_t lda = MBEM_PICK(L, q, lda), ldb = MBEM_PICK(L, q, ldb), ldc = MBEM_PICK(L, q, ldc);
+    const TA *A = (const TA *)MBEM_PICK(L, q, A) + bidx * MBEM_PICK(L, q, sa);
+    const TB *B = (const TB *)MBEM_PICK(L, q, B) + bidx * MBEM_PICK(L, q, sb);
+    double2 *C = (double2 *)MBEM_PICK(L, q, C) + bidx * MBEM_PICK(L, q, sc) + blockIdx.y * split_stride;
+    const int64_t kbeg = blockIdx.y * kchunk;
+    const int64_t K = std::min(Kall, kbeg + kchunk);
+    const int64_t b0 = n0 / 2;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int g = lane >> 4, l16 = lane & 15;
+
+    // per stage: A 64 rows x 8 complex, B 32 rows x 8 complex; a thread
+    // loads two complex numbers of A (one row, adjacent k) and one of B
+    double ra[4], rb[2];
+    auto ld1 = [](const auto *p, int64_t kc, int64_t Kend, double *o) {
+        if (kc < Kend) { o[0] = (double)p[kc].x; o[1] = (double)p[kc].y; }
+        else { o[0] = 0.0; o[1] = 0.0; }
+    };
+    auto gload = [&](int64_t kc0) {
+        {
+            const int row = tid >> 2, kq = 2 * (tid & 3);
+            const int64_t m = m0 + row;
+            if (m < M) {
+                const TA *p = A + m * lda;
+                ld1(p, kc0 + kq, K, ra);
+                ld1(p, kc0 + kq + 1, K, ra + 2);
+            } else { ra[0] = ra[1] = ra[2] = ra[3] = 0.0; }
+        }
+        {
+            const int row = tid >> 3, kq = tid & 7;
+            const int64_t b = b0 + row;
+            if (b < Nb) ld1(B + b * ldb, kc0 + kq, K, rb);
+            else { rb[0] = rb[1] = 0.0; }
+        }
+    };
+    auto sstore = [&](int buf) {
+        {
+            const int row = tid >> 2, k4 = 4 * (tid & 3);
+            double *d = &sA[buf][row * LD + k4];
+            *(f64x2 *)d = f64x2{ra[0], ra[1]};
+            *(f64x2 *)(d + 2) = f64x2{ra[2], ra[3]};
+        }
+        {
+            const int row = tid >> 3, k2 = 2 * (tid & 7);
+            const double br = rb[0], bi = rb[1];
+            if (CONJ) {
+                *(f64x2 *)&sB[buf][(2 * row) * LD + k2] = f64x2{br, bi};
+                *(f64x2 *)&sB[buf][(2 * row + 1) * LD + k2] = f64x2{bi, -br};
+            } else {
+                *(f64x2 *)&sB[buf][(2 * row) * LD + k2] = f64x2{br, -bi};
+                *(f64x2 *)&sB[buf][(2 * row + 1) * LD + k2] = f64x2{bi, br};
+            }
+        }
+    };
+
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    const int64_t nst = K > kbeg ? (K - kbeg + 7) / 8 : 0;
+    if (nst > 0) {
+        gload(kbeg);
+        sstore(0);
+    }
+    __syncthreads();
+    for (int64_t st = 0; st < nst; ++st) {
+        const int cur = (int)(st & 1);
+        if (st + 1 < nst) gload(kbeg + (st + 1) * 8);
+        // lane (l16, g) feeds MFMA step s with real k = 4 g + s of the stage
+        f64x4 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const double *src = &sA[cur][(wm * WM + i * 16 + l16) * LD + 4 * g];
+            const f64x2 x0 = *(const f64x2 *)src, x1 = *(const f64x2 *)(src + 2);
+            a[i] = f64x4{x0.x, x0.y, x1.x, x1.y};
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const double *src = &sB[cur][(wn * WN + j * 16 + l16) * LD + 4 * g];
+            const f64x2 x0 = *(const f64x2 *)src, x1 = *(const f64x2 *)(src + 2);
+            b[j] = f64x4{x0.x, x0.y, x1.x, x1.y};
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+        if (st + 1 < nst) sstore(cur ^ 1);
+        __syncthreads();
+    }
+    // accumulator (lane, e): column l16, row g + 4 e
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double v = acc[i][j][e];
+                const double w = __shfl_xor(v, 1);
+                const int64_t m = m0 + wm * WM + i * 16 + g + 4 * e;
+                const int64_t n = n0 + wn * WN + j * 16 + l16;
+                if ((l16 & 1) == 0 && m < M && (n >> 1) < Nb) C[(n >> 1) * ldc + m] = double2{v, w};
+            }
+}
+
+// Sum of the k-split partial products (compact [split][batch][Nb][M]) into
+// the output layout; ACC adds to what the output holds.
+template <bool ACC>
+__global__ void k_split_reduce(const double2 *part, int splits, int64_t M, int64_t Nb, int64_t batch,
+                               double2 *out, int64_t ldc, int64_t sc) {
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t per = M * Nb, stride = per * batch;
+    if (id >= stride) return;
+    const int64_t bi = id / per, r = id % per, b = r / M, m = r % M;
+    double2 s = {0.0, 0.0};
+    for (int y = 0; y < splits; ++y) { const double2 v = part[y * stride + id]; s.x += v.x; s.y += v.y; }
+    double2 *o = out + bi * sc + b * ldc + m;
+    if (ACC) { o->x += s.x; o->y += s.y; }
+    else *o = s;
+}
+
+// ------------------------------------------------------------- host ----
+namespace {
+struct F32Cfg { int BM, BN, WM, WN; };
+constexpr F32Cfg kF32Cfg[kGemmConfigs] = {
+    {128, 128, 64, 64}, {128, 64, 64, 32}, {64, 128, 32, 64}, {64, 64, 32, 32},
+    {256, 128, 64, 64}, {128, 256, 64, 64},
+};
+
+int64_t plan(CgemmList &L, int BM, int BN) {
+    int64_t tile0 = 0;
+    for (int q = 0; q < L.np; ++q) {
+        CgemmProb &P = L.p[q];
+        const int64_t tm = (P.M + BM - 1) / BM, tn = (2 * P.Nb + BN - 1) / BN;
+        P.tn = tn;
+        P.tiles = tm * tn;
+        P.tile0 = tile0;
+        tile0 += P.tiles * P.batch;
+    }
+    L.total = tile0;
+    return tile0;
+}
+
+template <int BM, int BN, int WM, int WN>
+int launch_f32(CgemmList L, hipStream_t s) {
+    const int64_t total = plan(L, BM, BN);
+    if (total == 0) return MBEM_OK;
+    constexpr int NT = 64 * (BM / WM) * (BN / WN);
+    hipLaunchKernelGGL((k_cgemm_f32<BM, BN, WM, WN>), dim3((unsigned)total), dim3(NT), 0, s, L);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+}  // namespace
+
+bool cgemm_list_valid(const CgemmList &L, size_t esz_a, size_t esz_b) {
+    if (L.np < 1 || L.np > 3) return false;
+    for (int q = 0; q < L.np; ++q) {
+        const CgemmProb &P = L.p[q];
+        if (P.M < 0 || P.Nb < 0 || P.K < 0 || P.batch < 1) return false;
+        if (P.lda < P.K || P.ldb < P.K || P.ldc < P.M) return false;
+        // 16-byte vector loads of two complex64 need even strides and offsets
+        if (esz_a == 8 && ((P.lda | P.sa) & 1 || ((uintptr_t)P.A & 15))) return false;
+        if (esz_b == 8 && ((P.ldb | P.sb) & 1 || ((uintptr_t)P.B & 15))) return false;
+        if (!P.A || !P.B || !P.C) return false;
+    }
+    return true;
+}
+
+int cgemm_f32_run(CgemmList L, int cfg, hipStream_t s) {
+    switch (cfg) {
+        case 0: return launch_f32<128, 128, 64, 64>(L, s);
+        case 1: return launch_f32<128, 64, 64, 32>(L, s);
+        case 2: return launch_f32<64, 128, 32, 64>(L, s);
+        case 3: return launch_f32<64, 64, 32, 32>(L, s);
+        case 4: return launch_f32<256, 128, 64, 64>(L, s);
+        case 5: return launch_f32<128, 256, 64, 64>(L, s);
+        default: set_error("unknown GEMM configuration"); return MBEM_EINVAL;
+    }
+}
+
+void cgemm_f32_config(int cfg, int *bm, int *bn, int *wm, int *wn) {
+    const F32Cfg c = kF32Cfg[std::clamp(cfg, 0, kGemmConfigs - 1)];
+    *bm = c.BM; *bn = c.BN; *wm = c.WM; *wn = c.WN;
+}
+
+int cgemm_f64_run(CgemmList L, bool a_c64, bool conj_a, int splits, double2 *work, hipStream_t s,
+                  bool accumulate) {
+    const int64_t total = plan(L, 64, 64);
+    if (total == 0) return MBEM_OK;
+    if (splits < 1) splits = 1;
+    int64_t kmax = 0;
+    for (int q = 0; q < L.np; ++q) kmax = std::max(kmax, L.p[q].K);
+    const int64_t kchunk = std::max<int64_t>(8, ((kmax + splits - 1) / splits + 7) / 8 * 8);
+    splits = (int)std::max<int64_t>(1, (kmax + kchunk - 1) / kchunk);
+    const bool staged = splits > 1 || accumulate;
+    if (staged && (L.np != 1 || !work)) { set_error("split GEMM needs one problem and a workspace"); return MBEM_EINVAL; }
+    CgemmList Lw = L;
+    int64_t stride = 0;
+    if (staged) {
+        // partial products in a compact [split][batch][Nb][M] layout
+        CgemmProb &P = Lw.p[0];
+        P.C = work;
+        P.ldc = P.M;
+        P.sc = P.M * P.Nb;
+        stride = P.sc * P.batch;
+    }
+    const dim3 grid((unsigned)total, (unsigned)splits);
+    if (a_c64 && conj_a)
+        hipLaunchKernelGGL((k_cgemm_f64<float2, double2, true>), grid, dim3(256), 0, s, Lw, kchunk, stride);
+    else if (a_c64)
+        hipLaunchKernelGGL((k_cgemm_f64<float2, double2, false>), grid, dim3(256), 0, s, Lw, kchunk, stride);
+    else if (conj_a)
+        hipLaunchKernelGGL((k_cgemm_f64<double2, double2, true>), grid, dim3(256), 0, s, Lw, kchunk, stride);
+    else
+        hipLaunchKernelGGL((k_cgemm_f64<double2, double2, false>), grid, dim3(256), 0, s, Lw, kchunk, stride);
+    MBEM_HIP(hipGetLastError());
+    if (staged) {
+        const CgemmProb &P = L.p[0];
+        const int64_t n = P.M * P.Nb * P.batch;
+        const unsigned g = (unsigned)((n + 255) / 256);
+        if (accumulate)
+            hipLaunchKernelGGL(k_split_reduce<true>, dim3(g), dim3(256), 0, s, work, splits, P.M, P.Nb,
+                               (int64_t)P.batch, (double2 *)P.C, P.ldc, P.sc);
+        else
+            hipLaunchKernelGGL(k_split_reduce<false>, dim3(g), dim3(256), 0, s, work, splits, P.M, P.Nb,
+                               (int64_t)P.batch, (double2 *)P.C, P.ldc, P.sc);
+        MBEM_HIP(hipGetLastError());
+    }
+    return MBEM_OK;
+}
+
+int64_t cgemm_f64_work(const CgemmList &L, int splits) {
+    if (L.np != 1) return 0;
+    const CgemmProb &P = L.p[0];
+    return (int64_t)std::max(splits, 1) * P.M * P.Nb * P.batch;
+}
+
+// Measure every FP32 tile shape on this exact problem list (one warm-up,
+// then the best of `reps` timed launches) and return the fastest.
+int cgemm_f32_autotune(const CgemmList &L, hipStream_t s, int reps, float *ms_out, int *best) {
+    hipEvent_t e0, e1;
+    MBEM_HIP(hipEventCreate(&e0));
+    MBEM_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int arg = 0;
+    int st = MBEM_OK;
+    for (int c = 0; c < kGemmConfigs && st == MBEM_OK; ++c) {
+        st = cgemm_f32_run(L, c, s);
+        float tmin = 1e30f;
+        for (int r = 0; r < reps && st == MBEM_OK; ++r) {
+            (void)hipEventRecord(e0, s);
+            st = cgemm_f32_run(L, c, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tmin = std::min(tmin, ms);
+        }
+        if (ms_out) ms_out[c] = tmin;
+        if (tmin < best_ms) { best_ms = tmin; arg = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best) *best = arg;
+    return st;
+}
+
+}  // namespace mbem

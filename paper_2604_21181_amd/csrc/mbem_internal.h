@@ -105,6 +105,10 @@ struct mbem_op {
     // solver workspace
     double2 *d_work = nullptr;
     size_t work_elems = 0;
+    // multi-right-hand-side solve: complex64 copy of an FP64 operator's
+    // blocks for the FP32 GEMM, and the tile shape tuned for ncol columns
+    void *K32[3] = {nullptr, nullptr, nullptr};
+    int tuned_ncol = 0, tuned_cfg = 0;
 };
 
 namespace mbem {
@@ -155,6 +159,11 @@ int vec_axpy(double2 *y, const double2 *x, double2 a, int64_t n,
              hipStream_t s);
 int vec_combine(double2 *out, const double2 *V, int64_t ldv, int k,
                 const double2 *y_dev, int64_t n, hipStream_t s);
+
+// multi-right-hand-side solve (block.hip)
+int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_opts *o, double2 *X,
+                    mbem_block_stats *st, hipStream_t s);
+int ensure_c64_copy(mbem_op *op, hipStream_t s);
 
 // post-processing (post.hip)
 int rhs_run(const mbem_mesh *m, const mbem_params *p, const double *khat,

@@ -25,8 +25,10 @@ EXPORTED = [
     "mbem_mesh_permutation", "mbem_mesh_info", "mbem_morton_order", "mbem_fill",
     "mbem_op_destroy", "mbem_op_export_blocks", "mbem_op_export_dense", "mbem_matvec",
     "mbem_precond_setup", "mbem_precond_apply", "mbem_rhs_planewave", "mbem_solve",
-    "mbem_farfield", "mbem_cross_sections", "mbem_last_error",
+    "mbem_farfield", "mbem_cross_sections", "mbem_last_error", "mbem_solve_block",
+    "mbem_gemm_autotune", "mbem_cgemm",
 ]
+GEMM_CONFIGS = 6   # FP32 GEMM tile shapes known to the autotuner
 
 
 class MbemError(RuntimeError):
@@ -53,6 +55,20 @@ class Stats(C.Structure):
                 ("t_regular_ms", C.c_double), ("t_near_ms", C.c_double), ("t_ssq_ms", C.c_double),
                 ("t_mass_ms", C.c_double), ("t_matvec_ms", C.c_double), ("n_matvec", C.c_int32),
                 ("n_regular_pairs", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BlockOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("maxit", C.c_int32),
+                ("max_refine", C.c_int32), ("block", C.c_int32), ("gemm_config", C.c_int32)]
+
+
+class BlockStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("sweeps", C.c_int32), ("block", C.c_int32),
+                ("gemm_config", C.c_int32), ("rel_resid", C.c_double), ("t_solve_ms", C.c_double),
+                ("t_gemm_ms", C.c_double), ("n_gemm", C.c_int32), ("shifted", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -90,6 +106,10 @@ def lib():
             "mbem_farfield": ([P, P, C.POINTER(Params), P, i32, P, i64, P], C.c_int),
             "mbem_cross_sections": ([P, P, C.POINTER(Params), P, P, P, i32, P], C.c_int),
             "mbem_last_error": ([], C.c_char_p),
+            "mbem_solve_block": ([P, P, P, i32, C.POINTER(BlockOpts), P, C.POINTER(BlockStats)],
+                                 C.c_int),
+            "mbem_gemm_autotune": ([P, P, i32, i32, P, P], C.c_int),
+            "mbem_cgemm": ([P, i32, i32, i64, i64, i64, P, i64, P, i64, P, i64, i32], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -218,6 +238,30 @@ def mbem_solve(ctx, op, b, x, nrhs, tol, maxit=500, max_refine=0, inner_tol=0.0)
     return code, st
 
 
+def mbem_solve_block(ctx, op, b, x, nrhs, tol, inner_tol=0.0, maxit=0, max_refine=0, block=0,
+                     gemm_config=-1):
+    o = BlockOpts(tol, inner_tol, maxit, max_refine, block, gemm_config)
+    st = BlockStats()
+    code = _check(lib().mbem_solve_block(ctx, op, _t_ptr(b), nrhs, C.byref(o), _t_ptr(x),
+                                         C.byref(st)), allow=(MBEM_ENOCONV,))
+    return code, st
+
+
+def mbem_gemm_autotune(ctx, op, nrhs, reps=3):
+    ms = np.zeros(GEMM_CONFIGS, dtype=np.float32)
+    best = np.zeros(1, dtype=np.int32)
+    _check(lib().mbem_gemm_autotune(ctx, op, nrhs, reps, _np_ptr(ms), _np_ptr(best)))
+    return int(best[0]), ms
+
+
+def mbem_cgemm(ctx, dtype, conj_a, A, B, C_out, config=0):
+    """C_out[b][m] = sum_k op(A[m][k]) B[b][k] for row-major device tensors."""
+    M, K = A.shape
+    Nb = B.shape[0]
+    _check(lib().mbem_cgemm(ctx, dtype, int(conj_a), M, Nb, K, _t_ptr(A), A.stride(0), _t_ptr(B),
+                            B.stride(0), _t_ptr(C_out), C_out.stride(0), config))
+
+
 def mbem_farfield(ctx, mesh, params, x, nrhs, rhat, F):
     _check(lib().mbem_farfield(ctx, mesh, C.byref(params), _t_ptr(x), nrhs, _t_ptr(rhat),
                                rhat.shape[0], _t_ptr(F)))
@@ -307,6 +351,15 @@ class Solver:
         code, st = mbem_solve(self.ctx, self.op, b.contiguous(), x, b.shape[0], tol, maxit,
                               max_refine, inner_tol)
         return x, st, code
+
+    def solve_block(self, b, tol, **kw):
+        """b [nrhs, N] complex128 device tensor -> (x, BlockStats, code)."""
+        x = self.torch.empty_like(b)
+        code, st = mbem_solve_block(self.ctx, self.op, b.contiguous(), x, b.shape[0], tol, **kw)
+        return x, st, code
+
+    def gemm_autotune(self, nrhs, reps=3):
+        return mbem_gemm_autotune(self.ctx, self.op, nrhs, reps)
 
     def farfield(self, x, rhat):
         t = self.torch

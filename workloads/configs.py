@@ -57,11 +57,16 @@ def planewaves(name: str):
     if nrhs == 1:
         return (np.array([[0.0, 0.0, 1.0]]),
                 np.array([[1.0 + 0j, 0.0, 0.0]], dtype=np.complex128))
-    ndir = nrhs // 2
-    g = np.random.default_rng(0).normal(size=(ndir, 3))
+    return planewave_set(nrhs // 2, seed=0)
+
+
+def planewave_set(ndir: int, seed: int = 0):
+    """2 ndir plane waves: ndir directions normalize(g), g ~ N(0, I3) from
+    default_rng(seed), each with the two polarisations described above."""
+    g = np.random.default_rng(seed).normal(size=(ndir, 3))
     kh = g / np.linalg.norm(g, axis=1, keepdims=True)
-    khat = np.zeros((nrhs, 3))
-    pol = np.zeros((nrhs, 3), dtype=np.complex128)
+    khat = np.zeros((2 * ndir, 3))
+    pol = np.zeros((2 * ndir, 3), dtype=np.complex128)
     for d in range(ndir):
         k = kh[d]
         vref = np.array([1.0, 0, 0]) if abs(k[2]) > 0.9 else np.array([0, 0, 1.0])
