@@ -139,6 +139,73 @@ int mbj_apply_multi(const mbem_op *op, ColMap vin, ColMap out, int ncol, bool ou
     return MBEM_OK;
 }
 
+// The same product as a batched GEMM on the matrix cores: the columns are
+// gathered per preconditioner block (Vg[m][c][q], q over the 2B indices
+// of block m), multiplied by the stored inverses (FP64 MFMA) and
+// scattered back.
+__global__ void k_mbj_gather_cols(int64_t n2, int B, int nb, ColMap vin, int ncol, double2 *Vg) {
+    const int64_t ld = 2 * (int64_t)B;
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= (int64_t)nb * ncol * ld) return;
+    const int64_t m = id / (ncol * ld), t = id % (ncol * ld), c = t / ld, q = t % ld;
+    const int64_t b = min((int64_t)B, n2 - m * B);
+    double2 v = {0.0, 0.0};
+    if (q < 2 * b) v = col_ptr<const double2>(vin, c)[(q < b ? 0 : n2) + m * B + (q % b)];
+    Vg[id] = v;
+}
+
+template <typename TO, bool ADD>
+__global__ void k_mbj_scatter_cols(int64_t n2, int B, int nb, const double2 *Og, ColMap out, int ncol) {
+    const int64_t ld = 2 * (int64_t)B;
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= (int64_t)nb * ncol * ld) return;
+    const int64_t m = id / (ncol * ld), t = id % (ncol * ld), c = t / ld, r = t % ld;
+    const int64_t b = min((int64_t)B, n2 - m * B);
+    if (r >= 2 * b) return;
+    const double2 v = Og[id];
+    TO *o = col_ptr<TO>(out, c) + (r < b ? 0 : n2) + m * B + (r % b);
+    if (ADD) { o->x += v.x; o->y += v.y; }
+    else { o->x = v.x; o->y = v.y; }
+}
+
+int mbj_apply_multi_mfma(const mbem_op *op, ColMap vin, ColMap out, int ncol, bool out_c64, bool add,
+                         double2 *Vg, double2 *Og, hipStream_t s) {
+    if (!op->d_minv || op->nb == 0) return mbj_apply_multi(op, vin, out, ncol, out_c64, add, s);
+    const int64_t n2 = op->n2, ld = 2 * (int64_t)op->B, nb = op->nb;
+    const int64_t tot = nb * ncol * ld;
+    const unsigned g = (unsigned)((tot + 255) / 256);
+    hipLaunchKernelGGL(k_mbj_gather_cols, dim3(g), dim3(256), 0, s, n2, op->B, op->nb, vin, ncol, Vg);
+    MBEM_HIP(hipGetLastError());
+    // full blocks as one batch, the last (possibly shorter) block on its own
+    const int64_t blast = n2 - (nb - 1) * op->B;
+    CgemmList L;
+    L.np = 0;
+    auto add_prob = [&](int64_t m0, int64_t count, int64_t size) {
+        CgemmProb &P = L.p[L.np++];
+        P.A = op->d_minv + m0 * ld * ld; P.lda = ld; P.sa = ld * ld;
+        P.B = Vg + m0 * ncol * ld; P.ldb = ld; P.sb = ncol * ld;
+        P.C = Og + m0 * ncol * ld; P.ldc = ld; P.sc = ncol * ld;
+        P.M = size; P.K = size; P.Nb = ncol; P.batch = (int32_t)count;
+    };
+    if (blast == op->B) add_prob(0, nb, ld);
+    else {
+        if (nb > 1) add_prob(0, nb - 1, ld);
+        add_prob(nb - 1, 1, 2 * blast);
+    }
+    MBEM_TRY(cgemm_f64_run(L, false, false, 1, nullptr, s));
+    if (out_c64)
+        hipLaunchKernelGGL((k_mbj_scatter_cols<float2, false>), dim3(g), dim3(256), 0, s, n2, op->B, op->nb,
+                           (const double2 *)Og, out, ncol);
+    else if (add)
+        hipLaunchKernelGGL((k_mbj_scatter_cols<double2, true>), dim3(g), dim3(256), 0, s, n2, op->B, op->nb,
+                           (const double2 *)Og, out, ncol);
+    else
+        hipLaunchKernelGGL((k_mbj_scatter_cols<double2, false>), dim3(g), dim3(256), 0, s, n2, op->B, op->nb,
+                           (const double2 *)Og, out, ncol);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
 // ---------------------------------------------- block product Z X ---
 // From the dense products T1 = K1 [x_j | x_m] (row 2c: x_j of column c, row
 // 2c+1: x_m), T2 = K2^eps x_m, T3 = K2^mu x_j (each [ncol][n2]) and the mass
@@ -244,45 +311,52 @@ static int nn_update(int64_t N, int ka, int p, int nblk, const double2 *V, int64
 }
 
 // ------------------------------------------------------ Cholesky QR ---
-// One wavefront per block.  G (column-major, G[c * p + a] = sum conj(w_a)
+// One workgroup per block.  G (column-major, G[c * p + a] = sum conj(w_a)
 // w_c) = R^H R.  If SCALE, the columns are first normalised (D = sqrt
 // diag G) and R is returned for the unscaled columns.  If the factorisation
 // meets a pivot that is not positive, it restarts on G + s I with
 // s = 11 (N p + p (p + 1)) u |G|_F (shifted Cholesky QR).
 // Outputs: Y = (R_hat)^-1 (scaled rows: D^-1 R_hat^-1), column-major p x p;
-// Rout = R * Rprev (or R when Rprev is null), element (i, c) at
+// Rout = R * Rprev (or R D when Rprev is null), element (i, c) at
 // Rout[c * ldr + i] in block b at Rout + b * sr.
-__global__ __launch_bounds__(64) void k_cholqr_small(int p, int64_t Nrows, const double2 *G, int scale,
-                                                     const double2 *Rprev, double2 *Y, double2 *Rout,
-                                                     int64_t ldr, int64_t sr, int *flags) {
-    __shared__ double2 sG[kMaxP][kMaxP];   // sG[a][c]
-    __shared__ double2 sR[kMaxP][kMaxP];   // sR[i][c], upper
-    __shared__ double2 sX[kMaxP][kMaxP];   // sX[i][c]: column c of R^-1
+__global__ __launch_bounds__(256) void k_cholqr_small(int p, int64_t Nrows, const double2 *G, int scale,
+                                                      const double2 *Rprev, double2 *Y, double2 *Rout,
+                                                      int64_t ldr, int64_t sr, int *flags) {
+    __shared__ double2 sG[kMaxP][kMaxP + 1];   // sG[a][c]
+    __shared__ double2 sR[kMaxP][kMaxP + 1];   // sR[i][c], upper
+    __shared__ double2 sX[kMaxP][kMaxP + 1];   // R^-1, or Rprev
+    __shared__ double2 sV[kMaxP];
     __shared__ double sD[kMaxP];
+    __shared__ double s_fro;
     __shared__ int s_bad;
-    const int blk = blockIdx.x, c = threadIdx.x;
+    const int blk = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     G += (int64_t)blk * p * p;
-    for (int t = c; t < p * p; t += 64) sG[t % p][t / p] = G[t];
+    for (int t = tid; t < p * p; t += nt) sG[t % p][t / p] = G[t];
     __syncthreads();
-    if (c < p) sD[c] = scale ? sqrt(fmax(sG[c][c].x, 0.0)) : 1.0;
+    if (tid < p) sD[tid] = scale ? sqrt(fmax(sG[tid][tid].x, 0.0)) : 1.0;
     __syncthreads();
-    if (scale) {
-        for (int t = c; t < p * p; t += 64) {
+    if (scale)
+        for (int t = tid; t < p * p; t += nt) {
             const int a = t % p, cc = t / p;
             const double d = sD[a] * sD[cc];
             sG[a][cc] = d > 0 ? double2{sG[a][cc].x / d, sG[a][cc].y / d} : double2{a == cc ? 1.0 : 0.0, 0.0};
         }
-        __syncthreads();
+    __syncthreads();
+    if (tid < kWv) {
+        double f = 0.0;
+        for (int t = tid; t < p * p; t += kWv) { const double2 g = sG[t % p][t / p]; f += g.x * g.x + g.y * g.y; }
+        f = wsum(f);
+        if (tid == 0) s_fro = sqrt(f);
     }
-    double fro = 0.0;
-    for (int a = 0; a < p; ++a) if (c < p) fro += sG[a][c].x * sG[a][c].x + sG[a][c].y * sG[a][c].y;
-    fro = sqrt(wsum(fro));
-    fro = __shfl(fro, 0);
+    __syncthreads();
     double shift = 0.0;
     for (int attempt = 0; attempt < 3; ++attempt) {
-        if (c == 0) s_bad = 0;
+        if (tid == 0) s_bad = 0;
+        for (int t = tid; t < p * p; t += nt) sR[t % p][t / p] = {0.0, 0.0};
         __syncthreads();
         for (int j = 0; j < p; ++j) {
+            // row j of R: v_c = G[j][c] - sum_{i<j} conj(R[i][j]) R[i][c], c >= j
+            const int c = tid;
             double2 v = {0, 0};
             if (c < p && c >= j) {
                 v = sG[j][c];
@@ -291,46 +365,55 @@ __global__ __launch_bounds__(64) void k_cholqr_small(int p, int64_t Nrows, const
                     const double2 t = zcmul(sR[i][j], sR[i][c]);
                     v.x -= t.x; v.y -= t.y;
                 }
+                sV[c] = v;
             }
             __syncthreads();
-            if (c == j) {
-                if (!(v.x > 0.0)) { s_bad = 1; v.x = 1.0; }
-                sR[j][j] = {sqrt(v.x), 0.0};
+            if (c < p && c >= j) {
+                double d = sV[j].x;
+                if (!(d > 0.0)) { d = 1.0; if (c == j) s_bad = 1; }
+                d = sqrt(d);
+                sR[j][c] = c == j ? double2{d, 0.0} : double2{v.x / d, v.y / d};
             }
-            __syncthreads();
-            if (c < p && c > j) { const double d = sR[j][j].x; sR[j][c] = {v.x / d, v.y / d}; }
-            if (c < p && c < j) sR[j][c] = {0.0, 0.0};
             __syncthreads();
         }
         if (!s_bad) break;
-        shift = shift > 0 ? 100.0 * shift : 11.0 * ((double)Nrows * p + p * (p + 1)) * 1.1102230246251565e-16 * fro;
-        if (c == 0 && flags) atomicOr(flags, 1);
+        shift = shift > 0 ? 100.0 * shift : 11.0 * ((double)Nrows * p + p * (p + 1)) * 1.1102230246251565e-16 * s_fro;
+        if (tid == 0 && flags) atomicOr(flags, 1);
         __syncthreads();
     }
-    // inverse of R by columns (lane c solves R x = e_c), then Y = D^-1 R^-1
-    if (c < p) {
-        for (int i = 0; i < p; ++i) sX[i][c] = {0, 0};
-        for (int i = c; i >= 0; --i) {
+    // R^-1 by columns (thread c solves R x = e_c), then Y = D^-1 R^-1
+    if (tid < p) {
+        const int c = tid;
+        for (int i = p - 1; i >= 0; --i) {
             double2 t = {i == c ? 1.0 : 0.0, 0.0};
-            for (int j = i + 1; j <= c; ++j) { const double2 u = zmul(sR[i][j], sX[j][c]); t.x -= u.x; t.y -= u.y; }
-            sX[i][c] = {t.x / sR[i][i].x, t.y / sR[i][i].x};
+            if (i <= c)
+                for (int j = i + 1; j <= c; ++j) { const double2 u = zmul(sR[i][j], sX[j][c]); t.x -= u.x; t.y -= u.y; }
+            sX[i][c] = i <= c ? double2{t.x / sR[i][i].x, t.y / sR[i][i].x} : double2{0.0, 0.0};
         }
-        double2 *y = Y + (int64_t)blk * p * p + (int64_t)c * p;
-        for (int i = 0; i < p; ++i) {
-            const double d = sD[i] > 0 ? sD[i] : 1.0;
-            y[i] = i <= c ? double2{sX[i][c].x / d, sX[i][c].y / d} : double2{0, 0};
+    }
+    __syncthreads();
+    double2 *y = Y + (int64_t)blk * p * p;
+    for (int t = tid; t < p * p; t += nt) {
+        const int i = t % p, c = t / p;
+        const double d = sD[i] > 0 ? sD[i] : 1.0;
+        y[t] = {sX[i][c].x / d, sX[i][c].y / d};
+    }
+    __syncthreads();
+    double2 *ro = Rout + (int64_t)blk * sr;
+    if (Rprev) {
+        const double2 *rp = Rprev + (int64_t)blk * p * p;
+        for (int t = tid; t < p * p; t += nt) sX[t % p][t / p] = rp[t];
+        __syncthreads();
+        for (int t = tid; t < p * p; t += nt) {
+            const int i = t % p, c = t / p;
+            double2 acc = {0, 0};
+            for (int j = i; j <= c; ++j) { const double2 u = zmul(sR[i][j], sX[j][c]); acc.x += u.x; acc.y += u.y; }
+            ro[(int64_t)c * ldr + i] = acc;
         }
-        // Rout[:, c] = R (Rprev[:, c]) or R[:, c] D_c
-        double2 *ro = Rout + (int64_t)blk * sr + (int64_t)c * ldr;
-        if (Rprev) {
-            const double2 *rp = Rprev + (int64_t)blk * p * p + (int64_t)c * p;
-            for (int i = 0; i < p; ++i) {
-                double2 t = {0, 0};
-                for (int j = i; j <= c; ++j) { const double2 u = zmul(sR[i][j], rp[j]); t.x += u.x; t.y += u.y; }
-                ro[i] = t;
-            }
-        } else {
-            for (int i = 0; i < p; ++i) ro[i] = {sR[i][c].x * sD[c], sR[i][c].y * sD[c]};
+    } else {
+        for (int t = tid; t < p * p; t += nt) {
+            const int i = t % p, c = t / p;
+            ro[(int64_t)c * ldr + i] = {sR[i][c].x * sD[c], sR[i][c].y * sD[c]};
         }
     }
 }
@@ -398,7 +481,59 @@ __device__ __forceinline__ void win_shift(int p, double2 *w) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_bqr_update(int p, int k, double2 *Hcol, int64_t ldh, int64_t sh,
+// Reflectors of block columns 0..k-1 applied to the new block column:
+// every column independently (one wavefront each, 8 per workgroup sharing
+// the reflectors of one block column through LDS).  Lane L holds row
+// j p + L of the sliding 2p-row window.
+__device__ __forceinline__ double wsum_all(double v) {
+#pragma unroll
+    for (int o = 1; o < kWv; o <<= 1) v += __shfl_xor(v, o, kWv);
+    return v;
+}
+
+__global__ __launch_bounds__(512) void k_bqr_prev(int p, int k, double2 *Hcol, int64_t ldh, int64_t sh,
+                                                  const double2 *refl, const double2 *taus, int64_t srefl,
+                                                  int64_t staus) {
+    __shared__ double2 sref[kMaxP][kMaxP + 1];
+    __shared__ double2 stau[kMaxP];
+    const int blk = blockIdx.x, lane = threadIdx.x % kWv, wave = threadIdx.x / kWv;
+    const int c = blockIdx.y * 8 + wave;
+    const bool col_ok = c < p;
+    double2 *h = Hcol + blk * sh + (int64_t)(col_ok ? c : 0) * ldh;
+    refl += blk * srefl;
+    taus += blk * staus;
+    double2 w = (col_ok && lane < 2 * p) ? h[lane] : double2{0, 0};
+    for (int j = 0; j < k; ++j) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < p * (p + 1); t += blockDim.x)
+            sref[t / (p + 1)][t % (p + 1)] = refl[(int64_t)j * p * (p + 1) + t];
+        if (threadIdx.x < p) stau[threadIdx.x] = taus[(int64_t)j * p + threadIdx.x];
+        __syncthreads();
+        for (int i = 0; i < p; ++i) {
+            const int r = lane - i;
+            const double2 v = (r >= 0 && r <= p) ? sref[i][r] : double2{0, 0};
+            const double2 t = zcmul(v, w);
+            const double2 sm = {wsum_all(t.x), wsum_all(t.y)};
+            const double2 f = zmul(double2{stau[i].x, -stau[i].y}, sm);
+            const double2 d = zmul(v, f);
+            w.x -= d.x;
+            w.y -= d.y;
+        }
+        // rows j p .. (j+1) p are final; slide the window down by p rows
+        if (col_ok && lane < p) h[(int64_t)j * p + lane] = w;
+        const double2 up = {__shfl(w.x, (lane + p) % kWv), __shfl(w.y, (lane + p) % kWv)};
+        if (j + 1 < k) {
+            if (lane < p) w = up;
+            else if (lane < 2 * p) w = col_ok ? h[(int64_t)(j + 2) * p + (lane - p)] : double2{0, 0};
+        } else if (col_ok && lane >= p && lane < 2 * p) {
+            h[(int64_t)(j + 1) * p + (lane - p)] = w;
+        }
+    }
+}
+
+// Householder QR of rows kp .. (k+2)p of the new block column (after
+// k_bqr_prev), applied to g; residual norms of every column.
+__global__ __launch_bounds__(256) void k_bqr_factor(int p, int k, double2 *Hcol, int64_t ldh, int64_t sh,
                                                     double2 *refl, double2 *taus, int64_t srefl, int64_t staus,
                                                     double2 *g, int64_t ldg, int64_t sg, double *res) {
     __shared__ double2 win[2 * kMaxP * kMaxP];
@@ -411,34 +546,12 @@ __global__ __launch_bounds__(256) void k_bqr_update(int p, int k, double2 *Hcol,
     refl += blk * srefl;
     taus += blk * staus;
     g += blk * sg;
-    win_load(p, win, Hcol, ldh, 0, 0);
-    win_load(p, win, Hcol, ldh, p, p);
-    __syncthreads();
-    for (int j = 0; j < k; ++j) {
-        if (j > 0) {
-            win_shift(p, win);
-            __syncthreads();
-            win_load(p, win, Hcol, ldh, (int64_t)(j + 1) * p, p);
-            __syncthreads();
-        }
-        for (int i = 0; i < p; ++i) {
-            if (tid <= p) sv[tid] = refl[((int64_t)j * p + i) * (p + 1) + tid];
-            if (tid == 0) s_tau[0] = taus[(int64_t)j * p + i];
-            __syncthreads();
-            bqr_reflect(p, i, win, nullptr, sv, s_tau[0], 0, sred);
-        }
-        win_store(p, win, Hcol, ldh, (int64_t)j * p, 0);
-        __syncthreads();
-    }
-    if (k > 0) {
-        win_shift(p, win);
-        __syncthreads();
-        win_load(p, win, Hcol, ldh, (int64_t)(k + 1) * p, p);
-    }
+    win_load(p, win, Hcol, ldh, (int64_t)k * p, 0);
+    win_load(p, win, Hcol, ldh, (int64_t)(k + 1) * p, p);
     win_load(p, gw, g, ldg, (int64_t)k * p, 0);
     win_load(p, gw, g, ldg, (int64_t)(k + 1) * p, p);
     __syncthreads();
-    // factor the 2p x p window; column i has nonzeros in rows 0 .. p + i
+    // column i has nonzeros in window rows 0 .. p + i
     for (int i = 0; i < p; ++i) {
         if (tid < kWv) {
             const double2 x = tid <= p ? win[(i + tid) * kMaxP + i] : double2{0, 0};
@@ -550,6 +663,7 @@ struct BlockWork {
     double2 *T64 = nullptr;    // [4 ncol][n2]
     double2 *Q = nullptr;      // [ncol][N]
     double2 *R = nullptr;      // [ncol][N] refinement residual
+    double2 *Vg = nullptr, *Og = nullptr;   // [nb][ncol][2B] preconditioner staging
     double2 *Hs = nullptr;     // [nblk][m p][(m+1) p] column-major
     double2 *Ht = nullptr;     // [nblk][p][(m+1) p]
     double2 *G = nullptr, *Yi = nullptr, *Rt = nullptr;   // [nblk][p][p]
@@ -615,7 +729,7 @@ static int block_cholqr2(BlockWork &w, ColMap W, ColMap out, bool scale, double2
     const int64_t pp = (int64_t)w.p * w.p;
     // pass 1: W -> Q
     MBEM_TRY(block_project(w, (const double2 *)W.base, W.sblk, w.p, W, w.G, w.p, pp, s));
-    hipLaunchKernelGGL(k_cholqr_small, dim3(w.nblk), dim3(64), 0, s, w.p, w.N, w.G, scale ? 1 : 0,
+    hipLaunchKernelGGL(k_cholqr_small, dim3(w.nblk), dim3(256), 0, s, w.p, w.N, w.G, scale ? 1 : 0,
                        (const double2 *)nullptr, w.Yi, w.Rt, (int64_t)w.p, pp, w.flags);
     MBEM_HIP(hipGetLastError());
     MBEM_TRY(nn_update(w.N, w.p, w.p, w.nblk, (const double2 *)W.base, w.N, W.sblk, w.Yi, w.p, pp, w.Q, w.N,
@@ -623,7 +737,7 @@ static int block_cholqr2(BlockWork &w, ColMap W, ColMap out, bool scale, double2
     // pass 2: Q -> out, R = R2 R1
     const ColMap Qm{w.Q, w.p, (int64_t)w.p * w.N, w.N};
     MBEM_TRY(block_project(w, w.Q, Qm.sblk, w.p, Qm, w.G, w.p, pp, s));
-    hipLaunchKernelGGL(k_cholqr_small, dim3(w.nblk), dim3(64), 0, s, w.p, w.N, w.G, 0, (const double2 *)w.Rt,
+    hipLaunchKernelGGL(k_cholqr_small, dim3(w.nblk), dim3(256), 0, s, w.p, w.N, w.G, 0, (const double2 *)w.Rt,
                        w.Yi, Rdst, ldr, sr, w.flags);
     MBEM_HIP(hipGetLastError());
     return nn_update(w.N, w.p, w.p, w.nblk, w.Q, w.N, Qm.sblk, w.Yi, w.p, pp, (double2 *)out.base, w.N, out.sblk,
@@ -717,6 +831,10 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
     MBEM_TRY(w.get(&w.T64, (size_t)4 * ncol * n2));
     MBEM_TRY(w.get(&w.Q, (size_t)ncol * N));
     MBEM_TRY(w.get(&w.R, (size_t)ncol * N));
+    if (op->d_minv && op->nb > 0) {
+        MBEM_TRY(w.get(&w.Vg, (size_t)op->nb * ncol * 2 * op->B));
+        MBEM_TRY(w.get(&w.Og, (size_t)op->nb * ncol * 2 * op->B));
+    }
     MBEM_TRY(w.get(&w.Hs, (size_t)w.nblk * ldh * w.m * p));
     MBEM_TRY(w.get(&w.Ht, (size_t)w.nblk * ldh * p));
     MBEM_TRY(w.get(&w.G, (size_t)w.nblk * p * p));
@@ -775,7 +893,7 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
         int k = 0;
         for (k = 0; k < w.m; ++k) {
             // W = Z P^-1 V_k  into the slot of V_{k+1}
-            MBEM_TRY(mbj_apply_multi(op, w.vcol(k), Zcols, ncol, true, false, s));
+            MBEM_TRY(mbj_apply_multi_mfma(op, w.vcol(k), Zcols, ncol, true, false, w.Vg, w.Og, s));
             MBEM_HIP(hipEventRecord(ea, s));
             MBEM_TRY(cgemm_f32_run(L32, cfg, s));
             MBEM_HIP(hipEventRecord(eb, s));
@@ -798,7 +916,13 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
             MBEM_HIP(hipGetLastError());
             // W = V_{k+1} R  (R into rows (k+1)p .. (k+2)p of the block column)
             MBEM_TRY(block_cholqr2(w, Wk, Wk, false, hk + (int64_t)(k + 1) * p, ldh, ldh * w.m * p, s));
-            hipLaunchKernelGGL(k_bqr_update, dim3(w.nblk), dim3(256), 0, s, p, k, hk, ldh, ldh * w.m * p, w.refl,
+            if (k > 0) {
+                hipLaunchKernelGGL(k_bqr_prev, dim3(w.nblk, (p + 7) / 8), dim3(512), 0, s, p, k, hk, ldh,
+                                   ldh * w.m * p, (const double2 *)w.refl, (const double2 *)w.tau,
+                                   (int64_t)w.m * p * (p + 1), (int64_t)w.m * p);
+                MBEM_HIP(hipGetLastError());
+            }
+            hipLaunchKernelGGL(k_bqr_factor, dim3(w.nblk), dim3(256), 0, s, p, k, hk, ldh, ldh * w.m * p, w.refl,
                                w.tau, (int64_t)w.m * p * (p + 1), (int64_t)w.m * p, w.g, ldh, ldh * p, w.res);
             MBEM_HIP(hipGetLastError());
             MBEM_HIP(hipMemcpyAsync(resh.data(), w.res, sizeof(double) * ncol, hipMemcpyDeviceToHost, s));
@@ -822,7 +946,7 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
         MBEM_HIP(hipGetLastError());
         MBEM_TRY(nn_update(N, n, p, w.nblk, w.V, N, w.sV(), w.g, ldh, ldh * p, w.Q, N, (int64_t)p * N, 1.0, 0.0,
                            s));
-        MBEM_TRY(mbj_apply_multi(op, flat(w.Q, N), flat(X, N), ncol, false, true, s));
+        MBEM_TRY(mbj_apply_multi_mfma(op, flat(w.Q, N), flat(X, N), ncol, false, true, w.Vg, w.Og, s));
         // refinement residual in FP64
         MBEM_TRY(block_residual(op, w, X, B, w.R, s));
         hipLaunchKernelGGL(k_colnorm, dim3(ncol), dim3(256), 0, s, N, flat(w.R, N), w.res);
