@@ -10,9 +10,16 @@ One step = the whole hot path, both precisions side by side:
          right-hand side -> GMRES -> far field
   MIXED: the same with FP32 far pairs / complex64 storage and FP64
          iterative refinement.
+  MULTI-RHS: the same sphere at k_a = 3, eps_r = 6 with 128 plane waves
+         (64 seeded directions x 2 polarisations): mixed fill ->
+         block-Jacobi setup -> 128 right-hand sides -> block GMRES (complex
+         FP32 GEMM on the matrix cores, FP64 refinement) to 1e-8 -> far
+         fields in the 64 incidence directions.
 Metric: Z-fill rate N^2 / t_fill (entries/s) of the mixed path when its far
 field is within 1e-6 of the FP64 path's, otherwise of the FP64 path; GMRES
-solve seconds of both are reported beside it.
+solve seconds of both are reported beside it.  The multi-RHS pass reports
+its per-RHS solve time against 128 sequential single-RHS solves of the same
+operator (timed once, after the timed steps).
 
 The roofline object describes the kernel with the largest device time per
 step, timed live with HIP events on the library's stream.  Its algorithmic
@@ -36,6 +43,7 @@ if ROOT not in sys.path:
 PEAK_FP64_VALU = 78.6      # TFLOP/s, MI355X vector FP64
 PEAK_FP32_VALU = 157.3     # TFLOP/s, MI355X vector FP32
 PEAK_HBM = 8000.0          # GB/s
+PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix cores
 
 # Algorithmic flops of the regular-pair fill (FMA = 2 flops, every
 # transcendental call = 1).  Per point pair: distance and unit vector 13,
@@ -64,6 +72,7 @@ def parse():
     ap.add_argument("--workload", default="sphere1280")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="fp64,mixed")
+    ap.add_argument("--no-mrhs", action="store_true", help="skip the 128-RHS block solve pass")
     return ap.parse_args()
 
 
@@ -93,7 +102,6 @@ def main():
     from paper_2604_21181_amd import mbem
     from workloads import get_config, icosphere_p2, planewaves
     from workloads.configs import cut_plane_directions
-    from oracle import mie
 
     cfg = get_config(args.workload)
     xyz, tri = icosphere_p2(cfg["n_tris"], cfg["axes"])
@@ -105,6 +113,13 @@ def main():
                for p in paths}
     N = solvers[paths[0]].N
     nt = tri.shape[0]
+    Smr = None
+    if not args.no_mrhs:
+        mcfg = get_config("sphere1280_mrhs")
+        mxyz, mtri = icosphere_p2(mcfg["n_tris"], mcfg["axes"])
+        mkh, mpol = planewaves("sphere1280_mrhs")
+        Smr = mbem.Solver(mxyz, mtri, mcfg["k0"], mcfg["eps_r"], mcfg["mu_r"],
+                          precision=mbem.MBEM_MIXED)
 
     def step():
         out = {}
@@ -117,6 +132,14 @@ def main():
             F = S.farfield(x, rdirs)
             out[p] = dict(fill=fs.as_dict(), setup_ms=ps.t_setup_ms, solve=ss.as_dict(), code=code,
                           F=F, x=x)
+        if Smr is not None:
+            fs = Smr.fill()
+            ps = Smr.precond_setup(mcfg["mbj_block"])
+            b = Smr.rhs(mkh, mpol)
+            x, bs, code = Smr.solve_block(b, mcfg["tol"])
+            F = Smr.farfield(x, mkh)              # every solution in every incidence direction
+            out["mrhs"] = dict(fill=fs.as_dict(), setup_ms=ps.t_setup_ms, solve=bs.as_dict(),
+                               code=code, F=F, b=b)
         return out
 
     def log(msg):
@@ -163,9 +186,6 @@ def main():
     last = recs[-1]
     ff = {p: last[p]["F"].cpu().numpy()[0] for p in paths}
     info = {}
-    if "fp64" in paths and cfg["axes"] == (1.0, 1.0, 1.0):
-        Fm = mie.far_field(cfg["k0"], 1.0, cfg["eps_r"], rdirs)
-        info["farfield_err_fp64_vs_mie"] = float(np.linalg.norm(ff["fp64"] - Fm) / np.linalg.norm(Fm))
     mixed_ok = False
     if "fp64" in paths and "mixed" in paths:
         e = float(np.linalg.norm(ff["mixed"] - ff["fp64"]) / np.linalg.norm(ff["fp64"]))
@@ -219,6 +239,48 @@ def main():
                 "frac": achieved / PEAK_FP64_VALU, "traffic": None, "kernel": "k_ssq",
                 "algorithmic_flops_per_launch": flops, "launch_ms": r["t_ssq_ms"]}
 
+    mrhs = None
+    if Smr is not None:
+        mr = recs[-1]["mrhs"]
+        bsd = [r["mrhs"]["solve"] for r in recs]
+        t_block = float(np.mean([d["t_solve_ms"] for d in bsd]))
+        n_gemm = sum(d["n_gemm"] for d in bsd)
+        t_gemm = sum(d["t_gemm_ms"] for d in bsd) / max(1, n_gemm)
+        nr = mkh.shape[0]
+        mn2 = Smr.N // 2
+        gflop = 32.0 * nr * mn2 * mn2                     # K1 on 2 nr, K2 on nr + nr columns
+        # C_ext of every right-hand side by the optical theorem: a sphere's
+        # is the same for every incidence, up to the mesh's anisotropy
+        F = mr["F"].cpu().numpy()
+        cext = np.array([4 * np.pi / mcfg["k0"] * np.imag(np.vdot(mpol[r], F[r, r])) for r in range(nr)])
+        log("timing 128 sequential single-RHS solves of the same operator")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = 0
+        for c in range(nr):
+            xs, ss, code = Smr.solve(mr["b"][c], tol=mcfg["tol"], maxit=600, inner_tol=1e-4)
+            its += ss.iters
+        torch.cuda.synchronize()
+        t_seq = 1e3 * (time.perf_counter() - t0)
+        mrhs = {
+            "workload": "sphere1280_mrhs", "nrhs": nr, "unknowns": Smr.N, "k0": mcfg["k0"],
+            "eps_r": str(mcfg["eps_r"]), "gmres_tol": mcfg["tol"],
+            "t_fill_ms": float(np.mean([r["mrhs"]["fill"]["t_fill_ms"] for r in recs])),
+            "t_setup_ms": float(np.mean([r["mrhs"]["setup_ms"] for r in recs])),
+            "t_block_solve_ms": t_block, "block_iters": int(bsd[-1]["iters"]),
+            "sweeps": int(bsd[-1]["sweeps"]), "block": int(bsd[-1]["block"]),
+            "gemm_config": int(bsd[-1]["gemm_config"]), "rel_resid": float(bsd[-1]["rel_resid"]),
+            "ms_per_rhs_block": t_block / nr, "ms_per_rhs_sequential": t_seq / nr,
+            "sequential_iters": its, "speedup_vs_sequential": t_seq / t_block,
+            "cext_mean": float(cext.mean()),
+            "cext_rel_spread": float((cext.max() - cext.min()) / cext.mean()),
+            "gemm": {"bound": "mfma", "achieved": gflop / (t_gemm * 1e-3) / 1e12,
+                     "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
+                     "frac": gflop / (t_gemm * 1e-3) / 1e12 / PEAK_FP32_MFMA,
+                     "kernel": "k_cgemm_f32", "algorithmic_flops_per_launch": gflop,
+                     "launch_ms": t_gemm},
+        }
+
     if not args.no_cpu_baseline:
         log("timing the CPU oracle fill")
     cpu = None if args.no_cpu_baseline else cpu_baseline(xyz, tri, cfg, N)
@@ -242,11 +304,14 @@ def main():
         "solve_s": {p: res[p]["t_solve_ms"] * 1e-3 for p in paths},
         "accuracy": info,
         "roofline": roof,
+        "multi_rhs": mrhs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     for S in solvers.values():
         S.close()
+    if Smr is not None:
+        Smr.close()
 
 
 if __name__ == "__main__":

@@ -246,8 +246,10 @@ int mbem_solve_block(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b,
                      mbem_block_stats *stats);
 
 /* Time every FP32 GEMM tile shape on the block product of `op` with nrhs
- * columns (a warm-up and `reps` timed launches each), keep the fastest for
- * later calls of mbem_solve_block with nrhs columns.
+ * columns (a warm-up and `reps` timed launches each) and keep the fastest in
+ * the context for later calls of mbem_solve_block with nrhs columns on
+ * operators of the same size (mbem_solve_block tunes by itself when the
+ * context holds no choice for its size).
  *   ms host [6] (best time of each shape, may be NULL); best host [1].     */
 int mbem_gemm_autotune(mbem_ctx *ctx, mbem_op *op, int32_t nrhs, int32_t reps,
                        float *ms, int32_t *best);

@@ -856,11 +856,13 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
     CgemmList L32;
     MBEM_TRY(block_matvec32_list(op, w.Zt, ncol, w.T32, &L32));
     if (cfg < 0 || cfg >= kGemmConfigs) {
-        if (op->tuned_ncol == ncol) cfg = op->tuned_cfg;
+        mbem_ctx *ctx = op->ctx;
+        if (ctx->tuned_n2 == n2 && ctx->tuned_ncol == ncol) cfg = ctx->tuned_cfg;
         else {
             MBEM_TRY(cgemm_f32_autotune(L32, s, 2, nullptr, &cfg));
-            op->tuned_ncol = ncol;
-            op->tuned_cfg = cfg;
+            ctx->tuned_n2 = n2;
+            ctx->tuned_ncol = ncol;
+            ctx->tuned_cfg = cfg;
         }
     }
     hipEvent_t ea, eb;

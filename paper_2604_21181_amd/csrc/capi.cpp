@@ -529,7 +529,7 @@ int mbem_gemm_autotune(mbem_ctx *ctx, mbem_op *op, int32_t nrhs, int32_t reps, f
         L.p[2].B = X; L.p[2].ldb = N; L.p[2].Nb = nrhs; L.p[2].C = T + 3 * nrhs * n2;
         int b = 0;
         st = cgemm_f32_autotune(L, s, std::max(1, (int)reps), ms, &b);
-        if (st == MBEM_OK) { op->tuned_ncol = nrhs; op->tuned_cfg = b; *best = b; }
+        if (st == MBEM_OK) { ctx->tuned_n2 = n2; ctx->tuned_ncol = nrhs; ctx->tuned_cfg = b; *best = b; }
     }
     (void)hipStreamSynchronize(s);
     dfree(X);

@@ -54,6 +54,10 @@ struct cplx {  // plain complex double for host-side bookkeeping
 struct mbem_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // FP32 GEMM tile shape measured fastest for the block product of an
+    // operator with n2 rows per block and ncol right-hand sides
+    int64_t tuned_n2 = 0;
+    int tuned_ncol = 0, tuned_cfg = 0;
 };
 
 struct mbem_mesh {
@@ -106,9 +110,8 @@ struct mbem_op {
     double2 *d_work = nullptr;
     size_t work_elems = 0;
     // multi-right-hand-side solve: complex64 copy of an FP64 operator's
-    // blocks for the FP32 GEMM, and the tile shape tuned for ncol columns
+    // blocks for the FP32 GEMM
     void *K32[3] = {nullptr, nullptr, nullptr};
-    int tuned_ncol = 0, tuned_cfg = 0;
 };
 
 namespace mbem {
