@@ -206,6 +206,43 @@ int mbem_rhs_planewave(mbem_ctx *ctx, const mbem_mesh *mesh,
 int mbem_solve(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs,
                const mbem_solve_opts *opts, mbem_c128 *x, mbem_stats *stats);
 
+/* ---- adjoint and gradients of sigma_ext (extension of Sec. 6) ------------- */
+
+/* Solve Z^T lambda = g (transpose, no conjugation) by the same GMRES
+ * (right-preconditioned by the transposed block-Jacobi matrix; MIXED
+ * operators refine in FP64 as mbem_solve).  g, lambda device [N*nrhs].      */
+int mbem_solve_adjoint(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *g,
+                       int32_t nrhs, const mbem_solve_opts *opts,
+                       mbem_c128 *lambda, mbem_stats *stats);
+
+/* Fill dZ/d eps_r at fixed k_0, mu_r (FP64): the same Galerkin quadrature
+ * as mbem_fill applied to the derivatives of the kernel differences with
+ * respect to eps_i through k_i = k_0 sqrt(eps_r mu_r) and the eps_i factor
+ * of G_eps (Sec. 2.3 and 4), plus the derivative (1/2) M of the mass term.
+ * The returned operator works with mbem_matvec and the export calls.       */
+int mbem_fill_deps(mbem_ctx *ctx, const mbem_mesh *mesh,
+                   const mbem_params *params, mbem_op **out,
+                   mbem_stats *stats);
+
+/* g (device [N] complex128) with g^T x = e . F(rhat) for every solution x,
+ * F the far-field amplitude of mbem_farfield.  rhat, e host [3].          */
+int mbem_farfield_functional(mbem_ctx *ctx, const mbem_mesh *mesh,
+                             const mbem_params *params, const double *rhat,
+                             const mbem_c128 *e, mbem_c128 *g);
+
+/* sigma_ext = (4 pi / k_a) Im(conj(pol) . F(khat)) of the solution x of
+ * Z x = b(khat, pol) and its derivatives by the adjoint method:
+ *   lambda: Z^T lambda = g (g from mbem_farfield_functional, e = conj pol),
+ *   d sigma / d eps_r = (4 pi / k_a) (-lambda^T (dZ/deps_r) x)  (holomorphic:
+ *   d/dRe eps_r = Im, d/dIm eps_r = Re of the bracket times 4 pi / k_a).
+ *   out host [3]: sigma_ext, d/dRe eps_r, d/dIm eps_r;
+ *   lambda_out device [N] or NULL; stats: the adjoint solve.               */
+int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh,
+                        const mbem_params *params, const mbem_c128 *x,
+                        const double *khat, const mbem_c128 *pol,
+                        const mbem_solve_opts *opts, double *out,
+                        mbem_c128 *lambda_out, mbem_stats *stats);
+
 /* ---- many right-hand sides (Sec. 5 and 6: block Krylov extension) ------- */
 
 typedef struct {

@@ -70,18 +70,22 @@ static void op_free_device(mbem_op *op) {
     for (int o = 0; o < 3; ++o) dfree(op->K32[o]);
     dfree(op->d_mval);
     dfree(op->d_minv);
+    dfree(op->d_minv_t);
     dfree(op->d_lu);
     dfree(op->d_work);
     dfree(op->d_kconst);
 }
 
 // ---------------------------------------------------------------- GMRES --
+// trans: the same iteration on Z^T with P^-T (adjoint systems).
 struct Gmres {
     const mbem_op *op;
     hipStream_t s;
     int64_t N;
     int m;              // Krylov dimension limit
+    bool trans = false;
     double2 *V, *w, *z, *tmp, *hdev;
+    double2 *tpart = nullptr;   // partial sums of the transposed product
     double *ndev;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // bracket every matvec launch
     double t_matvec = 0.0;
@@ -89,9 +93,18 @@ struct Gmres {
     ~Gmres() {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        if (tpart) (void)hipFree(tpart);
+    }
+    int apply(const double2 *x, double2 *y) {   // y = Z x or Z^T x
+        return trans ? matvec_t_run(op, x, y, tpart, s) : matvec_run(op, x, y, tmp, s);
     }
     int timed_matvec(const double2 *x, double2 *y) {
         (void)hipEventRecord(ev0, s);
+        if (trans) {
+            MBEM_TRY(matvec_t_run(op, x, y, tpart, s));
+            MBEM_HIP(hipEventRecord(ev1, s));
+            return MBEM_OK;
+        }
         return matvec_run(op, x, y, tmp, s, ev1);   // ev1 right after the GEMV
     }
     void collect() {   // after a synchronisation of the stream
@@ -122,6 +135,7 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
     g.ndev = (double *)(g.hdev + 2 * (maxit + 2));
     if (!g.ev0) MBEM_HIP(hipEventCreate(&g.ev0));
     if (!g.ev1) MBEM_HIP(hipEventCreate(&g.ev1));
+    if (g.trans && !g.tpart) MBEM_TRY(dalloc(&g.tpart, (size_t)matvec_t_work(op)));
     return MBEM_OK;
 }
 
@@ -153,7 +167,7 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
     bool conv = false;
     for (k = 0; k < m; ++k) {
         double2 *vk = g.V + (size_t)k * N;
-        MBEM_TRY(mbj_apply_run(g.op, vk, g.z, s));
+        MBEM_TRY(mbj_apply_run(g.op, vk, g.z, s, g.trans));
         MBEM_TRY(g.timed_matvec(g.z, g.w));
         MBEM_TRY(vec_dots(g.V, N, k + 1, g.w, N, g.hdev, s));
         MBEM_TRY(vec_update(g.w, g.V, N, k + 1, g.hdev, N, s));
@@ -198,7 +212,7 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
     for (int i = 0; i < k; ++i) yd[i] = {y[i].real(), y[i].imag()};
     MBEM_HIP(hipMemcpyAsync(g.hdev, yd.data(), sizeof(double2) * k, hipMemcpyHostToDevice, s));
     MBEM_TRY(vec_combine(g.w, g.V, N, k, g.hdev, N, s));
-    MBEM_TRY(mbj_apply_run(g.op, g.w, x, s));
+    MBEM_TRY(mbj_apply_run(g.op, g.w, x, s, g.trans));
     MBEM_HIP(hipStreamSynchronize(s));
     *iters = k;
     *est = res;
@@ -298,8 +312,8 @@ int mbem_mesh_info(const mbem_mesh *m, int64_t *info) {
     return MBEM_OK;
 }
 
-int mbem_fill(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_op **out,
-              mbem_stats *stats) {
+// Operator handle with its dense blocks and mass values allocated.
+static int op_create(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_op **out) {
     if (!mesh || !p || !out) { set_error("null argument"); return MBEM_EINVAL; }
     if (p->precision != MBEM_FP64 && p->precision != MBEM_MIXED) { set_error("bad precision"); return MBEM_EINVAL; }
     if (!(p->k0 > 0)) { set_error("k0 must be positive"); return MBEM_EINVAL; }
@@ -324,13 +338,18 @@ int mbem_fill(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_o
     }
     if (st == MBEM_OK) st = dalloc(&op->d_mval, mesh->m_col.size());
     if (st != MBEM_OK) { op_free_device(op); delete op; return st; }
+    *out = op;
+    return MBEM_OK;
+}
+
+static int op_fill(mbem_ctx *ctx, mbem_op *op, bool deriv, mbem_stats *stats) {
     Timer t;
     t.start(ctx->stream);
-    st = fill_run(op, ctx->stream);
+    int st = fill_run(op, ctx->stream, deriv);
     const double ms = t.stop(ctx->stream);
     if (st == MBEM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) { set_error("fill failed"); st = MBEM_EDEVICE; }
-    if (st != MBEM_OK) { op_free_device(op); delete op; return st; }
-    if (stats) {
+    if (st == MBEM_OK && stats) {
+        const mbem_mesh *mesh = op->mesh;
         stats->t_fill_ms = ms;
         stats->n_near_pairs = op->n_near;
         stats->t_geom_ms = op->t_phase[0];
@@ -340,6 +359,15 @@ int mbem_fill(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_o
         stats->t_mass_ms = op->t_phase[4];
         stats->n_regular_pairs = mesh->nt * mesh->nt - mesh->n_spairs;
     }
+    return st;
+}
+
+int mbem_fill(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_op **out,
+              mbem_stats *stats) {
+    mbem_op *op = nullptr;
+    MBEM_TRY(op_create(ctx, mesh, p, &op));
+    const int st = op_fill(ctx, op, false, stats);
+    if (st != MBEM_OK) { op_free_device(op); delete op; return st; }
     *out = op;
     return MBEM_OK;
 }
@@ -412,15 +440,17 @@ int mbem_rhs_planewave(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *
     return st;
 }
 
-int mbem_solve(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs, const mbem_solve_opts *o,
-               mbem_c128 *x, mbem_stats *stats) {
+static int solve_impl(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs, const mbem_solve_opts *o,
+                      mbem_c128 *x, mbem_stats *stats, bool trans) {
     if (!op || !b || !x || !o || nrhs < 1 || o->maxit < 1 || !(o->tol > 0)) {
         set_error("bad argument");
         return MBEM_EINVAL;
     }
     MBEM_TRY(set_device(ctx));
     const hipStream_t s = ctx->stream;
+    if (trans) MBEM_TRY(mbj_transpose_run(op, s));
     Gmres g;
+    g.trans = trans;
     MBEM_TRY(gmres_alloc(g, op, o->maxit, s));
     const int64_t N = g.N;
     double2 *r = nullptr, *d = nullptr;
@@ -456,7 +486,7 @@ int mbem_solve(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs, con
                 total_it += it;
                 sweeps += 1;
                 MBEM_TRY(vec_axpy(xc, d, double2{1.0, 0.0}, N, s));
-                MBEM_TRY(matvec_run(op, xc, r, g.tmp, s));
+                MBEM_TRY(g.apply(xc, r));
                 MBEM_TRY(vec_scale_copy(r, r, double2{-1.0, 0.0}, N, s));
                 MBEM_TRY(vec_axpy(r, bc, double2{1.0, 0.0}, N, s));
                 MBEM_TRY(vec_norm2(r, N, g.ndev, s));
@@ -466,7 +496,7 @@ int mbem_solve(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs, con
             }
         }
         // explicit residual of the final iterate
-        MBEM_TRY(matvec_run(op, xc, r, g.tmp, s));
+        MBEM_TRY(g.apply(xc, r));
         MBEM_TRY(vec_scale_copy(r, r, double2{-1.0, 0.0}, N, s));
         MBEM_TRY(vec_axpy(r, bc, double2{1.0, 0.0}, N, s));
         MBEM_TRY(vec_norm2(r, N, g.ndev, s));
@@ -489,6 +519,85 @@ int mbem_solve(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs, con
     }
     if (status == MBEM_ENOCONV) set_error("GMRES did not reach the tolerance");
     return status;
+}
+
+int mbem_solve(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs, const mbem_solve_opts *o,
+               mbem_c128 *x, mbem_stats *stats) {
+    return solve_impl(ctx, op, b, nrhs, o, x, stats, false);
+}
+
+int mbem_solve_adjoint(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *g, int32_t nrhs, const mbem_solve_opts *o,
+                       mbem_c128 *lambda, mbem_stats *stats) {
+    return solve_impl(ctx, op, g, nrhs, o, lambda, stats, true);
+}
+
+int mbem_fill_deps(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_op **out, mbem_stats *stats) {
+    if (!p) { set_error("null argument"); return MBEM_EINVAL; }
+    mbem_params q = *p;
+    q.precision = MBEM_FP64;
+    mbem_op *op = nullptr;
+    MBEM_TRY(op_create(ctx, mesh, &q, &op));
+    const int st = op_fill(ctx, op, true, stats);
+    if (st != MBEM_OK) { op_free_device(op); delete op; return st; }
+    op->ce = {0.5, 0.0};   // d((eps_i + 1) / 2) / deps_i; the mass matrix itself is fixed
+    op->cm = {0.0, 0.0};
+    *out = op;
+    return MBEM_OK;
+}
+
+int mbem_farfield_functional(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const double *rhat,
+                             const mbem_c128 *e, mbem_c128 *g) {
+    if (!mesh || !p || !rhat || !e || !g) { set_error("null argument"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    int st = ff_functional_run(mesh, p, rhat, (const double2 *)e, (double2 *)g, ctx->stream);
+    (void)hipStreamSynchronize(ctx->stream);
+    return st;
+}
+
+int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh, const mbem_params *p,
+                        const mbem_c128 *x, const double *khat, const mbem_c128 *pol, const mbem_solve_opts *o,
+                        double *out, mbem_c128 *lambda_out, mbem_stats *stats) {
+    if (!op || !mesh || !p || !x || !khat || !pol || !o || !out) { set_error("null argument"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    const hipStream_t s = ctx->stream;
+    const int64_t N = 2 * op->n2;
+    double2 *g = nullptr, *lam = nullptr, *y = nullptr, *dots = nullptr;
+    MBEM_TRY(dalloc(&g, N));
+    int st = dalloc(&lam, N);
+    if (st == MBEM_OK) st = dalloc(&y, N);
+    if (st == MBEM_OK) st = dalloc(&dots, 2);
+    mbem_op *dop = nullptr;
+    mbem_stats sst{};
+    double2 hd[2] = {{0, 0}, {0, 0}};
+    if (st == MBEM_OK) {
+        const mbem_c128 ec[3] = {{pol[0].re, -pol[0].im}, {pol[1].re, -pol[1].im}, {pol[2].re, -pol[2].im}};
+        st = ff_functional_run(mesh, p, khat, (const double2 *)ec, g, s);
+    }
+    if (st == MBEM_OK) st = solve_impl(ctx, op, (const mbem_c128 *)g, 1, o, (mbem_c128 *)lam, &sst, true);
+    if (st == MBEM_OK) st = mbem_fill_deps(ctx, mesh, p, &dop, nullptr);
+    if (st == MBEM_OK) {
+        double2 *tmp = nullptr;
+        st = dalloc(&tmp, 4 * op->n2);
+        if (st == MBEM_OK) st = matvec_run(dop, (const double2 *)x, y, tmp, s);
+        if (st == MBEM_OK) st = dotu_run(g, (const double2 *)x, N, dots, s);
+        if (st == MBEM_OK) st = dotu_run(lam, y, N, dots + 1, s);
+        if (st == MBEM_OK && hipMemcpyAsync(hd, dots, sizeof(hd), hipMemcpyDeviceToHost, s) != hipSuccess) st = MBEM_EDEVICE;
+        (void)hipStreamSynchronize(s);
+        dfree(tmp);
+    }
+    if (st == MBEM_OK && lambda_out)
+        if (hipMemcpy(lambda_out, lam, sizeof(double2) * N, hipMemcpyDeviceToDevice) != hipSuccess) st = MBEM_EDEVICE;
+    if (dop) mbem_op_destroy(dop);
+    dfree(g); dfree(lam); dfree(y); dfree(dots);
+    if (st != MBEM_OK) return st;
+    // C = (4 pi / k) Im(g^T x);  dC/deps = (4 pi / k) Im(s'), s' = -lambda^T (dZ/deps) x,
+    // holomorphic in eps: d/dRe = Im(s'), d/dIm = Im(i s') = Re(s')
+    const double c = 4.0 * 3.14159265358979323846 / p->k0;
+    out[0] = c * hd[0].y;
+    out[1] = c * (-hd[1].y);
+    out[2] = c * (-hd[1].x);
+    if (stats) *stats = sst;
+    return MBEM_OK;
 }
 
 int mbem_solve_block(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs, const mbem_block_opts *o,

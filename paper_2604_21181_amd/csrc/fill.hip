@@ -38,7 +38,7 @@ __device__ inline int64_t xcd_remap(int64_t bid, int64_t total) {
 //   kappa1_ab = (D0 - dg)(s_a.t_b) + df (s_a.R)(R.t_b)
 //   kappa2_ab = G_chi [(t_a.t_b)(n.R) - (t_a.R)(n.t_b)],  R = (x - y)/|x - y|
 // output order c = 4 op + 2 a + b, op: K1, K2^eps, K2^mu.
-template <typename T>
+template <typename T, bool DK = false>
 __device__ __forceinline__ void kappa12(const KernelConst &K, vec3<T> x, vec3<T> n,
                                const vec3<T> ta[2], const vec3<T> sa[2],
                                vec3<T> y, const vec3<T> tb[2], T ww,
@@ -46,7 +46,9 @@ __device__ __forceinline__ void kappa12(const KernelConst &K, vec3<T> x, vec3<T>
     vec3<T> Rv = x - y;
     const T R = sqrt(dot(Rv, Rv));
     const vec3<T> Rh = ((T)1 / R) * Rv;
-    const KScal<T> s = kernel_scalars<T>(K, R);
+    KScal<T> s;
+    if constexpr (DK) s = kernel_scalars_deps(K, R);
+    else s = kernel_scalars<T>(K, R);
     const cx<T> A = s.D0 - s.dg;
     const T nR = dot(n, Rh);
     T tRy[2], ntb[2];
@@ -104,7 +106,7 @@ __device__ inline vec3<T> qload(const T *qp, int64_t nq, int f, int64_t i) {
 
 constexpr int kPairLanes = 49 * kChunk;   // 196
 
-template <typename T, typename TS>
+template <typename T, typename TS, bool DK = false>
 __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     // R1: point-pair kernel values, later the slot-merged trial contraction
     __shared__ cx<T> s_r1[kPairLanes * 12];
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
             const vec3<T> y = qload(a.qp, nq, QX, iy);
             const vec3<T> tb[2] = {qload(a.qp, nq, QT1, iy), qload(a.qp, nq, QT2, iy)};
             const T ww = a.qp[(int64_t)QW * nq + ix] * a.qp[(int64_t)QW * nq + iy];
-            kappa12<T>(*a.K, x, n, ta, sa, y, tb, ww, k);
+            kappa12<T, DK>(*a.K, x, n, ta, sa, y, tb, ww, k);
         } else if (!std::is_same<T, double>::value && kind == 2) {
             // near pair: FP64 kernel differences (cancellation), then rounded
             const double *q64 = a.qp64;
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
             const dvec3 tb[2] = {qload(q64, nq, QT1, iy), qload(q64, nq, QT2, iy)};
             const double ww = q64[(int64_t)QW * nq + ix] * q64[(int64_t)QW * nq + iy];
             cx<double> kd[12];
-            kappa12<double>(*a.K, x, n, ta, sa, y, tb, ww, kd);
+            kappa12<double, DK>(*a.K, x, n, ta, sa, y, tb, ww, kd);
 #pragma unroll
             for (int c = 0; c < 12; ++c) k[c] = cx<T>{(T)kd[c].re, (T)kd[c].im};
         } else {
@@ -298,7 +300,7 @@ struct SsqArgs {
 
 constexpr int kStreams = 5;   // consumer lanes per kernel component
 
-template <typename TS>
+template <typename TS, bool DK = false>
 __global__ __launch_bounds__(64) void k_ssq(SsqArgs<TS> a) {
     __shared__ double s_pt[kWave][36];                 // w kappa (24), Nx, Ny
     __shared__ double s_red[kStreams][36 * 12 * 2];
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(64) void k_ssq(SsqArgs<TS> a) {
             p2_point(a.xyz, a.frames, a.tri + 6 * f, xf, yf, Y);
             const dvec3 ta[2] = {X.t1, X.t2}, sa[2] = {X.s1, X.s2}, tb[2] = {Y.t1, Y.t2};
             cx<double> k[12];
-            kappa12<double>(*a.K, X.x, X.n, ta, sa, Y.x, tb, wg * X.J * Y.J, k);
+            kappa12<double, DK>(*a.K, X.x, X.n, ta, sa, Y.x, tb, wg * X.J * Y.J, k);
 #pragma unroll
             for (int q = 0; q < 12; ++q) { s_pt[lane][2 * q] = k[q].re; s_pt[lane][2 * q + 1] = k[q].im; }
 #pragma unroll
@@ -418,7 +420,7 @@ void derive_constants(const mbem_params *p, double2 *ka, double2 *ki, double2 *e
     *mu_i = {mr.real(), mr.imag()};
 }
 
-static KernelConst make_kconst(const mbem_op *op) {
+static KernelConst make_kconst(const mbem_op *op, bool deriv) {
     using C = std::complex<double>;
     KernelConst K{};
     const C ka(op->ka.x, op->ka.y), ki(op->ki.x, op->ki.y);
@@ -428,16 +430,29 @@ static KernelConst make_kconst(const mbem_op *op) {
     K.eps_a_re = 1.0; K.eps_a_im = 0.0; K.eps_i_re = ei.real(); K.eps_i_im = ei.imag();
     K.mu_a_re = 1.0; K.mu_a_im = 0.0; K.mu_i_re = mi.real(); K.mu_i_im = mi.imag();
     K.kmax = std::max(std::abs(ka), std::abs(ki));
-    C cna(1.0, 0.0), cni(1.0, 0.0);
     const C I(0.0, 1.0);
+    // c_n(k) = (i k)^n / n!, and d c_n / dk = i c_{n-1}(k)
+    C cna(1.0, 0.0), cni(1.0, 0.0), cni_prev(0.0, 0.0);
+    const C dk = ki / (2.0 * ei);          // dk_i / deps_i
+    if (deriv) { K.ka_re = dk.real(); K.ka_im = dk.imag(); }
     for (int n = 0; n <= kSeriesTerms; ++n) {
-        if (n > 0) { cna *= I * ka / (double)n; cni *= I * ki / (double)n; }
-        const C d = cna - cni;
-        const C vD = ka * ka * cna - ki * ki * cni;
-        const C vF = (n >= 2) ? (double)((n - 1) * (n - 3)) * d : C(0.0);
-        const C vG = (n >= 2) ? -(double)(n - 1) * d : C(0.0);
-        const C vE = (double)(n - 1) * (ea * cna - ei * cni);
-        const C vM = (double)(n - 1) * (ma * cna - mi * cni);
+        if (n > 0) { cni_prev = cni; cna *= I * ka / (double)n; cni *= I * ki / (double)n; }
+        C vD, vF, vG, vE, vM;
+        if (!deriv) {
+            const C d = cna - cni;
+            vD = ka * ka * cna - ki * ki * cni;
+            vF = (n >= 2) ? (double)((n - 1) * (n - 3)) * d : C(0.0);
+            vG = (n >= 2) ? -(double)(n - 1) * d : C(0.0);
+            vE = (double)(n - 1) * (ea * cna - ei * cni);
+            vM = (double)(n - 1) * (ma * cna - mi * cni);
+        } else {
+            const C dci = n > 0 ? I * cni_prev : C(0.0);   // d c_n(k_i) / dk_i
+            vD = -(2.0 * ki * cni + ki * ki * dci) * dk;
+            vF = (n >= 2) ? -(double)((n - 1) * (n - 3)) * dci * dk : C(0.0);
+            vG = (n >= 2) ? (double)(n - 1) * dci * dk : C(0.0);
+            vE = (double)(n - 1) * (-cni - ei * dci * dk);
+            vM = (double)(n - 1) * (-mi * dci * dk);
+        }
         K.cD[2 * n] = vD.real(); K.cD[2 * n + 1] = vD.imag();
         K.cF[2 * n] = vF.real(); K.cF[2 * n + 1] = vF.imag();
         K.cG[2 * n] = vG.real(); K.cG[2 * n + 1] = vG.imag();
@@ -447,7 +462,7 @@ static KernelConst make_kconst(const mbem_op *op) {
     return K;
 }
 
-template <typename T, typename TS>
+template <typename T, typename TS, bool DK = false>
 static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long *cnt,
                           hipStream_t s) {
     const mbem_mesh *m = op->mesh;
@@ -476,13 +491,13 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
             a.total = a.n_te * a.n_ch;
             if (a.total == 0) continue;
             if (a.total > 0x7fffffffLL) { set_error("too many element pairs for one launch"); return MBEM_EINVAL; }
-            hipLaunchKernelGGL((k_regular<T, TS>), dim3((unsigned)a.total), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_regular<T, TS, DK>), dim3((unsigned)a.total), dim3(256), 0, s, a);
             MBEM_HIP(hipGetLastError());
         }
     return MBEM_OK;
 }
 
-template <typename TS>
+template <typename TS, bool DK = false>
 static int launch_ssq(mbem_op *op, hipStream_t s) {
     const mbem_mesh *m = op->mesh;
     SsqArgs<TS> a;
@@ -503,7 +518,7 @@ static int launch_ssq(mbem_op *op, hipStream_t s) {
     a.K = op->d_kconst;
     for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)op->K[o];
     if (a.npairs == 0) return MBEM_OK;
-    hipLaunchKernelGGL((k_ssq<TS>), dim3((unsigned)a.npairs), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_ssq<TS, DK>), dim3((unsigned)a.npairs), dim3(64), 0, s, a);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
@@ -537,11 +552,11 @@ struct PhaseEvents {
     }
 };
 
-int fill_run(mbem_op *op, hipStream_t s) {
+int fill_run(mbem_op *op, hipStream_t s, bool deriv) {
     const mbem_mesh *m = op->mesh;
     if (!op->d_kconst) MBEM_HIP(hipMalloc((void **)&op->d_kconst, sizeof(KernelConst)));
     {
-        const KernelConst K = make_kconst(op);
+        const KernelConst K = make_kconst(op, deriv);
         MBEM_HIP(hipMemcpyAsync(op->d_kconst, &K, sizeof(K), hipMemcpyHostToDevice, s));
         MBEM_HIP(hipStreamSynchronize(s));   // K lives on this stack frame
     }
@@ -553,7 +568,13 @@ int fill_run(mbem_op *op, hipStream_t s) {
     MBEM_TRY(geom_build(m, s));
     pe.mark(1, s);
     unsigned long long *cnt = nullptr;
-    if (op->prec == MBEM_FP64) {
+    if (deriv) {
+        if (op->prec != MBEM_FP64) { set_error("derivative operators are filled in FP64"); return MBEM_EINVAL; }
+        MBEM_TRY((launch_regular<double, double, true>(op, 0, m->d_qp, nullptr, s)));
+        pe.mark(2, s);
+        pe.mark(3, s);
+        MBEM_TRY((launch_ssq<double, true>(op, s)));
+    } else if (op->prec == MBEM_FP64) {
         MBEM_TRY((launch_regular<double, double>(op, 0, m->d_qp, nullptr, s)));
         pe.mark(2, s);
         pe.mark(3, s);

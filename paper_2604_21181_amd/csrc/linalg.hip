@@ -514,6 +514,7 @@ __global__ __launch_bounds__(256) void k_mbj_apply(int64_t n2, int B, int nb, co
 int mbj_setup_run(mbem_op *op, int B, hipStream_t s) {
     if (op->d_minv) { MBEM_HIP(hipFree(op->d_minv)); op->d_minv = nullptr; }
     if (op->d_lu) { MBEM_HIP(hipFree(op->d_lu)); op->d_lu = nullptr; }
+    if (op->d_minv_t) { MBEM_HIP(hipFree(op->d_minv_t)); op->d_minv_t = nullptr; }
     op->B = 0; op->nb = 0;
     if (B <= 0) return MBEM_OK;
     if (B > kMaxBlock) { set_error("preconditioner block above 256 is not supported"); return MBEM_EINVAL; }
@@ -558,14 +559,14 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s) {
     return MBEM_OK;
 }
 
-int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z, hipStream_t s) {
+int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z, hipStream_t s, bool trans) {
     if (!op->d_minv || op->nb == 0) {
         MBEM_HIP(hipMemcpyAsync(z, v, sizeof(double2) * 2 * op->n2, hipMemcpyDeviceToDevice, s));
         return MBEM_OK;
     }
     const int64_t rows = (int64_t)op->nb * 2 * op->B;
     hipLaunchKernelGGL(k_mbj_apply, dim3((unsigned)((rows * kW + 255) / 256)), dim3(256), 0, s,
-                       op->n2, op->B, op->nb, op->d_minv, v, z);
+                       op->n2, op->B, op->nb, trans ? op->d_minv_t : op->d_minv, v, z);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }

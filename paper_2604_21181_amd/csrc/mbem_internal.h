@@ -105,6 +105,7 @@ struct mbem_op {
     // Morton block-Jacobi
     int32_t B = 0, nb = 0;
     double2 *d_minv = nullptr;      // [nb][2B][2B] inverses
+    double2 *d_minv_t = nullptr;    // their transposes (adjoint solves)
     double2 *d_lu = nullptr;        // scratch of the factorisation
     // solver workspace
     double2 *d_work = nullptr;
@@ -139,7 +140,8 @@ void gauss_legendre(int n, double *x, double *w);   // on [-1, 1]
 int geom_build(const mbem_mesh *m, hipStream_t s);
 
 // fill (fill.hip)
-int fill_run(mbem_op *op, hipStream_t s);
+// deriv: fill dK/deps_i instead of K (FP64 operators only)
+int fill_run(mbem_op *op, hipStream_t s, bool deriv = false);
 int mass_run(mbem_op *op, hipStream_t s);
 
 // linear algebra (linalg.hip)
@@ -149,8 +151,9 @@ int export_dense_run(const mbem_op *op, double2 *Z, hipStream_t s);
 int export_blocks_run(const mbem_op *op, double2 *K1, double2 *K2e,
                       double2 *K2m, hipStream_t s);
 int mbj_setup_run(mbem_op *op, int B, hipStream_t s);
+// trans: apply P^-T (mbj_transpose_run must have run)
 int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z,
-                  hipStream_t s);
+                  hipStream_t s, bool trans = false);
 int vec_dots(const double2 *V, int64_t ldv, int k, const double2 *w,
              int64_t n, double2 *out_dev, hipStream_t s);
 int vec_update(double2 *w, const double2 *V, int64_t ldv, int k,
@@ -162,6 +165,14 @@ int vec_axpy(double2 *y, const double2 *x, double2 a, int64_t n,
              hipStream_t s);
 int vec_combine(double2 *out, const double2 *V, int64_t ldv, int k,
                 const double2 *y_dev, int64_t n, hipStream_t s);
+
+// adjoint (adjoint.hip)
+int ff_functional_run(const mbem_mesh *m, const mbem_params *p, const double *rhat, const double2 *e,
+                      double2 *g, hipStream_t s);
+int matvec_t_run(const mbem_op *op, const double2 *x, double2 *y, double2 *part, hipStream_t s);
+int64_t matvec_t_work(const mbem_op *op);
+int mbj_transpose_run(mbem_op *op, hipStream_t s);
+int dotu_run(const double2 *a, const double2 *b, int64_t n, double2 *out, hipStream_t s);
 
 // multi-right-hand-side solve (block.hip)
 int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_opts *o, double2 *X,

@@ -205,4 +205,46 @@ __device__ __forceinline__ KScal<T> kernel_scalars(const KernelConst &K, T R) {
     return o;
 }
 
+// Derivatives of the same scalars with respect to the interior permittivity
+// eps_i at fixed k_0 and mu_i (k_i = k_0 sqrt(eps_i mu_i), dk_i/deps_i =
+// k_i / (2 eps_i)), for the adjoint gradient.  With e = e^{i k_i R}:
+//   d phi_i/dk = i R phi_i,  d f_i/dk = e k (1 - i k R) / (4 pi R),
+//   d g_i/dk = e k / (4 pi R);
+//   dD0 = -k phi_i (2 + i k R) dk,  ddf = -d f_i/dk dk,  ddg = -d g_i/dk dk,
+//   dG_eps = R (g_i + eps_i d g_i/dk dk),  dG_mu = R mu_i d g_i/dk dk.
+// Below max|k| R = 1/2 the host supplies the term-by-term derivative of the
+// Taylor coefficients instead (same Horner evaluation as kernel_scalars).
+// KernelConst.ka_re/ka_im hold dk_i/deps_i in this mode.
+__device__ __forceinline__ KScal<double> kernel_scalars_deps(const KernelConst &K, double R) {
+    const double inv4pi = 0.079577471545947667884;
+    KScal<double> o;
+    if (K.kmax * R < kSeriesRho) {
+        const double r1 = inv4pi / R, r2 = r1 / R, r3 = r2 / R;
+        o.D0 = r1 * horner<double>(K.cD, R);
+        o.df = r3 * horner<double>(K.cF, R);
+        o.dg = r3 * horner<double>(K.cG, R);
+        o.Ge = r2 * horner<double>(K.cE, R);
+        o.Gm = r2 * horner<double>(K.cM, R);
+        return o;
+    }
+    const double r1 = inv4pi / R;
+    const cx<double> k = {K.ki_re, K.ki_im}, dk = {K.ka_re, K.ka_im};
+    double sn, cs;
+    sincos(k.re * R, &sn, &cs);
+    const double am = exp(-k.im * R);
+    const cx<double> e = {am * cs, am * sn};
+    const cx<double> phi = r1 * e;
+    const cx<double> ikR = {-k.im * R, k.re * R};
+    const cx<double> ek = r1 * (e * k);                       // e k / (4 pi R)
+    const cx<double> dfk = ek * cx<double>{1.0 - ikR.re, -ikR.im};
+    const cx<double> g = (r1 / (R * R)) * (e * cx<double>{1.0 - ikR.re, -ikR.im});
+    o.D0 = ((-1.0) * (k * phi) * cx<double>{2.0 + ikR.re, ikR.im}) * dk;
+    o.df = (-1.0) * (dfk * dk);
+    o.dg = (-1.0) * (ek * dk);
+    const cx<double> ei = {K.eps_i_re, K.eps_i_im}, mi = {K.mu_i_re, K.mu_i_im};
+    o.Ge = R * (g + ei * (ek * dk));
+    o.Gm = R * (mi * (ek * dk));
+    return o;
+}
+
 }  // namespace mbem

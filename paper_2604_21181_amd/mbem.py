@@ -26,7 +26,8 @@ EXPORTED = [
     "mbem_op_destroy", "mbem_op_export_blocks", "mbem_op_export_dense", "mbem_matvec",
     "mbem_precond_setup", "mbem_precond_apply", "mbem_rhs_planewave", "mbem_solve",
     "mbem_farfield", "mbem_cross_sections", "mbem_last_error", "mbem_solve_block",
-    "mbem_gemm_autotune", "mbem_cgemm",
+    "mbem_gemm_autotune", "mbem_cgemm", "mbem_solve_adjoint", "mbem_fill_deps",
+    "mbem_farfield_functional", "mbem_grad_sigma_ext",
 ]
 GEMM_CONFIGS = 6   # FP32 GEMM tile shapes known to the autotuner
 
@@ -110,6 +111,11 @@ def lib():
                                  C.c_int),
             "mbem_gemm_autotune": ([P, P, i32, i32, P, P], C.c_int),
             "mbem_cgemm": ([P, i32, i32, i64, i64, i64, P, i64, P, i64, P, i64, i32], C.c_int),
+            "mbem_solve_adjoint": ([P, P, P, i32, C.POINTER(SolveOpts), P, C.POINTER(Stats)], C.c_int),
+            "mbem_fill_deps": ([P, P, C.POINTER(Params), PP, C.POINTER(Stats)], C.c_int),
+            "mbem_farfield_functional": ([P, P, C.POINTER(Params), P, P, P], C.c_int),
+            "mbem_grad_sigma_ext": ([P, P, P, C.POINTER(Params), P, P, P, C.POINTER(SolveOpts), P, P,
+                                     C.POINTER(Stats)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -262,6 +268,41 @@ def mbem_cgemm(ctx, dtype, conj_a, A, B, C_out, config=0):
                             B.stride(0), _t_ptr(C_out), C_out.stride(0), config))
 
 
+def mbem_solve_adjoint(ctx, op, g, lam, nrhs, tol, maxit=500, max_refine=0, inner_tol=0.0):
+    o = SolveOpts(tol, maxit, max_refine, inner_tol)
+    st = Stats()
+    code = _check(lib().mbem_solve_adjoint(ctx, op, _t_ptr(g), nrhs, C.byref(o), _t_ptr(lam),
+                                           C.byref(st)), allow=(MBEM_ENOCONV,))
+    return code, st
+
+
+def mbem_fill_deps(ctx, mesh, params):
+    op = C.c_void_p()
+    st = Stats()
+    _check(lib().mbem_fill_deps(ctx, mesh, C.byref(params), C.byref(op), C.byref(st)))
+    return op, st
+
+
+def mbem_farfield_functional(ctx, mesh, params, rhat, e, g):
+    rhat = np.ascontiguousarray(rhat, dtype=np.float64).ravel()
+    e = np.ascontiguousarray(e, dtype=np.complex128).ravel()
+    _check(lib().mbem_farfield_functional(ctx, mesh, C.byref(params), _np_ptr(rhat), _np_ptr(e),
+                                          _t_ptr(g)))
+
+
+def mbem_grad_sigma_ext(ctx, op, mesh, params, x, khat, pol, tol=1e-12, maxit=500, inner_tol=0.0,
+                        lam=None):
+    khat = np.ascontiguousarray(khat, dtype=np.float64).ravel()
+    pol = np.ascontiguousarray(pol, dtype=np.complex128).ravel()
+    o = SolveOpts(tol, maxit, 0, inner_tol)
+    out = np.zeros(3)
+    st = Stats()
+    _check(lib().mbem_grad_sigma_ext(ctx, op, mesh, C.byref(params), _t_ptr(x), _np_ptr(khat),
+                                     _np_ptr(pol), C.byref(o), _np_ptr(out),
+                                     _t_ptr(lam) if lam is not None else None, C.byref(st)))
+    return out, st
+
+
 def mbem_farfield(ctx, mesh, params, x, nrhs, rhat, F):
     _check(lib().mbem_farfield(ctx, mesh, C.byref(params), _t_ptr(x), nrhs, _t_ptr(rhat),
                                rhat.shape[0], _t_ptr(F)))
@@ -357,6 +398,39 @@ class Solver:
         x = self.torch.empty_like(b)
         code, st = mbem_solve_block(self.ctx, self.op, b.contiguous(), x, b.shape[0], tol, **kw)
         return x, st, code
+
+    def solve_adjoint(self, g, tol, maxit=500, max_refine=0, inner_tol=0.0):
+        g = g if g.dim() == 2 else g[None]
+        lam = self.torch.empty_like(g)
+        code, st = mbem_solve_adjoint(self.ctx, self.op, g.contiguous(), lam, g.shape[0], tol, maxit,
+                                      max_refine, inner_tol)
+        return lam, st, code
+
+    def deps_blocks(self):
+        """dK1, dK2eps, dK2mu / d eps_r (complex128 device tensors)."""
+        t = self.torch
+        dop, _ = mbem_fill_deps(self.ctx, self.mesh, self.params)
+        try:
+            n2 = 2 * self.nn
+            K = [t.empty((n2, n2), dtype=t.complex128, device=self.device) for _ in range(3)]
+            mbem_op_export_blocks(self.ctx, dop, *K)
+            t.cuda.synchronize()
+        finally:
+            mbem_op_destroy(dop)
+        return K
+
+    def farfield_functional(self, rhat, e):
+        g = self.torch.empty(self.N, dtype=self.torch.complex128, device=self.device)
+        mbem_farfield_functional(self.ctx, self.mesh, self.params, rhat, e, g)
+        return g
+
+    def grad_sigma_ext(self, x, khat, pol, tol=1e-12, maxit=500, inner_tol=0.0):
+        """(sigma_ext, d/dRe eps_r, d/dIm eps_r), adjoint-solve stats, lambda."""
+        lam = self.torch.empty(self.N, dtype=self.torch.complex128, device=self.device)
+        x = x.reshape(-1)[: self.N].contiguous()
+        out, st = mbem_grad_sigma_ext(self.ctx, self.op, self.mesh, self.params, x, khat, pol, tol,
+                                      maxit, inner_tol, lam)
+        return out, st, lam
 
     def gemm_autotune(self, nrhs, reps=3):
         return mbem_gemm_autotune(self.ctx, self.op, nrhs, reps)
