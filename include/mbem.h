@@ -234,14 +234,26 @@ int mbem_farfield_functional(mbem_ctx *ctx, const mbem_mesh *mesh,
  * Z x = b(khat, pol) and its derivatives by the adjoint method:
  *   lambda: Z^T lambda = g (g from mbem_farfield_functional, e = conj pol),
  *   d sigma / d eps_r = (4 pi / k_a) (-lambda^T (dZ/deps_r) x)  (holomorphic:
- *   d/dRe eps_r = Im, d/dIm eps_r = Re of the bracket times 4 pi / k_a).
+ *   d/dRe eps_r = Im, d/dIm eps_r = Re of the bracket times 4 pi / k_a),
+ *   d sigma / d theta = (4 pi / k_a) d/dtheta Im(g^T x + lambda^T b
+ *   - lambda^T Z x) with x, lambda frozen for the node positions theta: a
+ *   reverse pass over every quadrature point and point pair of the fill
+ *   (regular and Sauter-Schwab), the P2 map, the continuous frame and the
+ *   nodal triads and normals (Sec. 3), with the singular-pair classes and
+ *   the reference-vector choice of every node held fixed.
  *   out host [3]: sigma_ext, d/dRe eps_r, d/dIm eps_r;
- *   lambda_out device [N] or NULL; stats: the adjoint solve.               */
+ *   lambda_out device [N] or NULL;
+ *   dsig_dnode device [n_nodes] float64 or NULL: derivative for a
+ *     displacement of node v along its nodal normal n_v (Morton order);
+ *   dsig_dx device [n_nodes*3] float64 or NULL: derivative for every
+ *     coordinate of every node (Morton order);
+ *   stats: the adjoint solve.                                              */
 int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh,
                         const mbem_params *params, const mbem_c128 *x,
                         const double *khat, const mbem_c128 *pol,
                         const mbem_solve_opts *opts, double *out,
-                        mbem_c128 *lambda_out, mbem_stats *stats);
+                        mbem_c128 *lambda_out, double *dsig_dnode,
+                        double *dsig_dx, mbem_stats *stats);
 
 /* ---- many right-hand sides (Sec. 5 and 6: block Krylov extension) ------- */
 

@@ -48,3 +48,13 @@ def dK_deps(xyz, tri, k0, eps_r, h=1e-3, mu_r=1.0):
     def K(e):
         return np.stack(core.fill(xyz, tri, core.phys_vector(k0, e, mu_r)))
     return richardson(K, complex(eps_r), h)
+
+
+def dsigma_dnormal(xyz, tri, k0, eps_r, khat, pol, weights, h=1e-4):
+    """d sigma / dt for the displacement x_v -> x_v + t weights_v n_v of
+    every node, n_v the nodal normals of the unperturbed mesh (held fixed),
+    by differences of the whole discrete map.  One node: a unit weight."""
+    n0, _, _ = core.nodal_frames(xyz, tri)
+    dirs = np.asarray(weights, dtype=np.float64)[:, None] * n0
+    f = lambda t: solve_sigma_ext(xyz + t * dirs, tri, k0, eps_r, khat, pol)[0]
+    return richardson(f, 0.0, h)

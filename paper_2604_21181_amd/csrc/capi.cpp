@@ -556,7 +556,8 @@ int mbem_farfield_functional(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_pa
 
 int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh, const mbem_params *p,
                         const mbem_c128 *x, const double *khat, const mbem_c128 *pol, const mbem_solve_opts *o,
-                        double *out, mbem_c128 *lambda_out, mbem_stats *stats) {
+                        double *out, mbem_c128 *lambda_out, double *dsig_dnode, double *dsig_dx,
+                        mbem_stats *stats) {
     if (!op || !mesh || !p || !x || !khat || !pol || !o || !out) { set_error("null argument"); return MBEM_EINVAL; }
     MBEM_TRY(set_device(ctx));
     const hipStream_t s = ctx->stream;
@@ -587,6 +588,8 @@ int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh, const
     }
     if (st == MBEM_OK && lambda_out)
         if (hipMemcpy(lambda_out, lam, sizeof(double2) * N, hipMemcpyDeviceToDevice) != hipSuccess) st = MBEM_EDEVICE;
+    if (st == MBEM_OK && (dsig_dnode || dsig_dx))
+        st = shape_grad_run(op, p, (const double2 *)x, lam, khat, (const double2 *)pol, dsig_dnode, dsig_dx, s);
     if (dop) mbem_op_destroy(dop);
     dfree(g); dfree(lam); dfree(y); dfree(dots);
     if (st != MBEM_OK) return st;

@@ -115,7 +115,7 @@ def lib():
             "mbem_fill_deps": ([P, P, C.POINTER(Params), PP, C.POINTER(Stats)], C.c_int),
             "mbem_farfield_functional": ([P, P, C.POINTER(Params), P, P, P], C.c_int),
             "mbem_grad_sigma_ext": ([P, P, P, C.POINTER(Params), P, P, P, C.POINTER(SolveOpts), P, P,
-                                     C.POINTER(Stats)], C.c_int),
+                                     P, P, C.POINTER(Stats)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -291,15 +291,16 @@ def mbem_farfield_functional(ctx, mesh, params, rhat, e, g):
 
 
 def mbem_grad_sigma_ext(ctx, op, mesh, params, x, khat, pol, tol=1e-12, maxit=500, inner_tol=0.0,
-                        lam=None):
+                        lam=None, dnode=None, dx=None):
     khat = np.ascontiguousarray(khat, dtype=np.float64).ravel()
     pol = np.ascontiguousarray(pol, dtype=np.complex128).ravel()
     o = SolveOpts(tol, maxit, 0, inner_tol)
     out = np.zeros(3)
     st = Stats()
+    opt = lambda t: _t_ptr(t) if t is not None else None
     _check(lib().mbem_grad_sigma_ext(ctx, op, mesh, C.byref(params), _t_ptr(x), _np_ptr(khat),
-                                     _np_ptr(pol), C.byref(o), _np_ptr(out),
-                                     _t_ptr(lam) if lam is not None else None, C.byref(st)))
+                                     _np_ptr(pol), C.byref(o), _np_ptr(out), opt(lam), opt(dnode),
+                                     opt(dx), C.byref(st)))
     return out, st
 
 
@@ -424,13 +425,21 @@ class Solver:
         mbem_farfield_functional(self.ctx, self.mesh, self.params, rhat, e, g)
         return g
 
-    def grad_sigma_ext(self, x, khat, pol, tol=1e-12, maxit=500, inner_tol=0.0):
-        """(sigma_ext, d/dRe eps_r, d/dIm eps_r), adjoint-solve stats, lambda."""
-        lam = self.torch.empty(self.N, dtype=self.torch.complex128, device=self.device)
+    def grad_sigma_ext(self, x, khat, pol, tol=1e-12, maxit=500, inner_tol=0.0, shape=False):
+        """(sigma_ext, d/dRe eps_r, d/dIm eps_r), adjoint-solve stats, lambda and,
+        with shape=True, d sigma/d(normal displacement) [n_nodes] and
+        d sigma/d(node coordinates) [n_nodes, 3], both in the caller's node order."""
+        t = self.torch
+        lam = t.empty(self.N, dtype=t.complex128, device=self.device)
+        dnode = t.empty(self.nn, dtype=t.float64, device=self.device) if shape else None
+        dx = t.empty((self.nn, 3), dtype=t.float64, device=self.device) if shape else None
         x = x.reshape(-1)[: self.N].contiguous()
         out, st = mbem_grad_sigma_ext(self.ctx, self.op, self.mesh, self.params, x, khat, pol, tol,
-                                      maxit, inner_tol, lam)
-        return out, st, lam
+                                      maxit, inner_tol, lam, dnode, dx)
+        if not shape:
+            return out, st, lam
+        inv = t.as_tensor(np.argsort(self.node_order), device=self.device)
+        return out, st, lam, dnode[inv], dx[inv]
 
     def gemm_autotune(self, nrhs, reps=3):
         return mbem_gemm_autotune(self.ctx, self.op, nrhs, reps)

@@ -8,7 +8,11 @@
                    oracle's Z^T;
   sigma_ext and d sigma/d eps_r (adjoint) vs the oracle's sigma_ext and its
                    central differences: 1e-10 and 1e-7 (FP64 operator),
-                   1e-5 (MIXED operator, whose Z differs by ~1e-7).
+                   1e-5 (MIXED operator, whose Z differs by ~1e-7);
+  d sigma / d(normal displacement of node v) vs central differences of the
+                   oracle (unperturbed nodal normals as directions): 1e-6
+                   (FP64) and 1e-4 (MIXED) of the largest nodal derivative,
+                   for single nodes and a seeded combination of all nodes.
 """
 import numpy as np
 import pytest
@@ -114,5 +118,42 @@ def test_grad_sigma_ext_eps(case, prec):
         scale = max(abs(d_re), abs(d_im))
         assert abs(out[1] - d_re) < tol_d * scale, (out[1], d_re)
         assert abs(out[2] - d_im) < tol_d * scale, (out[2], d_im)
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_grad_sigma_ext_shape(case, prec):
+    """Per-node normal-displacement derivatives (adjoint) against central
+    differences of the oracle, for single nodes (vertex and mid-edge) and a
+    seeded random combination of all nodes."""
+    import torch
+    mbem = _mbem()
+    S = _solver(case, mbem.MBEM_FP64 if prec == "fp64" else mbem.MBEM_MIXED)
+    try:
+        S.fill()
+        S.precond_setup(100)
+        b = S.rhs(KH[None], POL[None])
+        x, st, code = S.solve(b, tol=1e-13, maxit=400, inner_tol=1e-6)
+        assert code == 0
+        out, ast, lam, dnode, dx = S.grad_sigma_ext(x[0], KH, POL, tol=1e-13, inner_tol=1e-6, shape=True)
+        dnode = dnode.cpu().numpy()
+        nn = dnode.shape[0]
+        scale = np.abs(dnode).max()
+        tol = 1e-6 if prec == "fp64" else 1e-4
+        xyz, tri = case["xyz"], case["tri"]
+        for v in (int(tri[0, 0]), int(tri[0, 3]), int(tri[-1, 4]), nn // 2):
+            w = np.zeros(nn)
+            w[v] = 1.0
+            ref = adjoint.dsigma_dnormal(xyz, tri, case["k0"], case["eps"], KH, POL, w)
+            assert abs(dnode[v] - ref) < tol * scale, (v, dnode[v], ref)
+        d = np.random.default_rng(1).normal(size=nn)
+        ref = adjoint.dsigma_dnormal(xyz, tri, case["k0"], case["eps"], KH, POL, d)
+        got = float(np.dot(dnode, d))
+        assert abs(got - ref) < tol * np.abs(dnode).sum() * 0.1, (got, ref)
+        # the normal component of the full coordinate gradient
+        n0, _, _ = core.nodal_frames(xyz, tri)
+        dxn = np.einsum("ij,ij->i", dx.cpu().numpy(), n0)
+        assert np.abs(dxn - dnode).max() < 1e-12 * scale
     finally:
         S.close()
