@@ -133,6 +133,11 @@ int mbem_mesh_create(mbem_ctx *ctx, const double *xyz, int64_t n_nodes,
                      const int64_t *tri6, int64_t n_tris, mbem_mesh **out);
 void mbem_mesh_destroy(mbem_mesh *mesh);
 
+/* Nodal frames (Sec. 3.1-3.2): metric-weighted normal n, t1 = normalize(
+ * v_ref x n) with v_ref = x if |n.z| > 0.9 else z, t2 = n x t1.
+ *   frames host [n_nodes*9] float64 (n, t1, t2 per node, caller's order).  */
+int mbem_mesh_frames(mbem_ctx *ctx, const mbem_mesh *mesh, double *frames);
+
 /* host outputs: node_order[m] = caller's node at Morton position m,
  * tri_order[t] = caller's triangle at Morton position t (either may be
  * NULL).                                                                    */

@@ -50,6 +50,12 @@ def dK_deps(xyz, tri, k0, eps_r, h=1e-3, mu_r=1.0):
     return richardson(K, complex(eps_r), h)
 
 
+def dsigma_ddirs(xyz, tri, k0, eps_r, khat, pol, dirs, h=1e-4):
+    """d sigma / dt for the node displacement x -> x + t dirs ([n_nodes, 3])."""
+    f = lambda t: solve_sigma_ext(xyz + t * dirs, tri, k0, eps_r, khat, pol)[0]
+    return richardson(f, 0.0, h)
+
+
 def dsigma_dnormal(xyz, tri, k0, eps_r, khat, pol, weights, h=1e-4):
     """d sigma / dt for the displacement x_v -> x_v + t weights_v n_v of
     every node, n_v the nodal normals of the unperturbed mesh (held fixed),

@@ -304,6 +304,17 @@ int mbem_mesh_permutation(const mbem_mesh *m, int64_t *node_order, int64_t *tri_
     return MBEM_OK;
 }
 
+int mbem_mesh_frames(mbem_ctx *ctx, const mbem_mesh *m, double *frames) {
+    if (!m || !frames) { set_error("null argument"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    std::vector<double> f(9 * m->nn);
+    MBEM_HIP(hipMemcpyAsync(f.data(), m->d_frames, sizeof(double) * f.size(), hipMemcpyDeviceToHost, ctx->stream));
+    MBEM_HIP(hipStreamSynchronize(ctx->stream));
+    for (int64_t k = 0; k < m->nn; ++k)
+        std::copy(f.begin() + 9 * k, f.begin() + 9 * k + 9, frames + 9 * m->node_order[k]);
+    return MBEM_OK;
+}
+
 int mbem_mesh_info(const mbem_mesh *m, int64_t *info) {
     if (!m || !info) { set_error("null argument"); return MBEM_EINVAL; }
     info[0] = m->nn; info[1] = m->nt; info[2] = 4 * m->nn;

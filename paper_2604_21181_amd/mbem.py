@@ -27,7 +27,7 @@ EXPORTED = [
     "mbem_precond_setup", "mbem_precond_apply", "mbem_rhs_planewave", "mbem_solve",
     "mbem_farfield", "mbem_cross_sections", "mbem_last_error", "mbem_solve_block",
     "mbem_gemm_autotune", "mbem_cgemm", "mbem_solve_adjoint", "mbem_fill_deps",
-    "mbem_farfield_functional", "mbem_grad_sigma_ext",
+    "mbem_farfield_functional", "mbem_grad_sigma_ext", "mbem_mesh_frames",
 ]
 GEMM_CONFIGS = 6   # FP32 GEMM tile shapes known to the autotuner
 
@@ -94,6 +94,7 @@ def lib():
             "mbem_mesh_destroy": ([P], None),
             "mbem_mesh_permutation": ([P, P, P], C.c_int),
             "mbem_mesh_info": ([P, P], C.c_int),
+            "mbem_mesh_frames": ([P, P, P], C.c_int),
             "mbem_morton_order": ([P, i64, P, i64, P, P], C.c_int),
             "mbem_fill": ([P, P, C.POINTER(Params), PP, C.POINTER(Stats)], C.c_int),
             "mbem_op_destroy": ([P], None),
@@ -419,6 +420,12 @@ class Solver:
         finally:
             mbem_op_destroy(dop)
         return K
+
+    def nodal_frames(self):
+        """[n_nodes, 9]: nodal normal, t1, t2 in the caller's node order."""
+        out = np.zeros((self.nn, 9))
+        _check(lib().mbem_mesh_frames(self.ctx, self.mesh, _np_ptr(out)))
+        return out
 
     def farfield_functional(self, rhat, e):
         g = self.torch.empty(self.N, dtype=self.torch.complex128, device=self.device)

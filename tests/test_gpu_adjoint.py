@@ -157,3 +157,33 @@ def test_grad_sigma_ext_shape(case, prec):
         assert np.abs(dxn - dnode).max() < 1e-12 * scale
     finally:
         S.close()
+
+
+def test_sigma_ext_autograd_function(case):
+    """SigmaExt: forward value and torch gradients (eps_r and per-node normal
+    displacements, at a displaced configuration) against the oracle."""
+    import torch
+    from paper_2604_21181_amd.autograd import SigmaExt, SigmaExtProblem
+    xyz, tri = case["xyz"], case["tri"]
+    prob = SigmaExtProblem(xyz, tri, case["k0"], KH, POL, tol=1e-13)
+    n0 = prob.nodal_normals()
+    on, _, _ = core.nodal_frames(xyz, tri)
+    assert np.abs(n0 - on).max() < 1e-13            # the library's normals are the oracle's
+    nn = xyz.shape[0]
+    rng = np.random.default_rng(5)
+    disp0 = 0.01 * rng.normal(size=nn)
+    eps = torch.tensor([case["eps"].real, case["eps"].imag], dtype=torch.float64, requires_grad=True)
+    disp = torch.tensor(disp0, dtype=torch.float64, requires_grad=True)
+    sig = SigmaExt.apply(eps, disp, prob)
+    sig.backward()
+    xyz1 = xyz + disp0[:, None] * n0
+    ref_sig = adjoint.solve_sigma_ext(xyz1, tri, case["k0"], case["eps"], KH, POL)[0]
+    assert abs(float(sig) - ref_sig) < 1e-10 * abs(ref_sig)
+    d_re, d_im = adjoint.dsigma_deps(xyz1, tri, case["k0"], case["eps"], KH, POL)
+    g = eps.grad.numpy()
+    assert abs(g[0] - d_re) < 1e-7 * max(abs(d_re), abs(d_im))
+    assert abs(g[1] - d_im) < 1e-7 * max(abs(d_re), abs(d_im))
+    d = rng.normal(size=nn)
+    ref = adjoint.dsigma_ddirs(xyz1, tri, case["k0"], case["eps"], KH, POL, d[:, None] * n0)
+    got = float(np.dot(disp.grad.numpy(), d))
+    assert abs(got - ref) < 1e-6 * np.abs(disp.grad.numpy()).sum(), (got, ref)
