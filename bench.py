@@ -10,6 +10,11 @@ One step = the whole hot path, both precisions side by side:
          right-hand side -> GMRES -> far field
   MIXED: the same with FP32 far pairs / complex64 storage and FP64
          iterative refinement.
+  GRADIENT: 1280-triangle ellipsoid (1, 0.8, 0.6), k_a = 3, eps_r = 3 + 0.1i:
+         FP64 fill -> block-Jacobi setup -> GMRES to 1e-12 -> adjoint
+         (Z^T solve, dZ/deps_r fill, reverse pass over every point pair and
+         the geometry) -> sigma_ext, d sigma/d eps_r, d sigma/d(normal
+         displacement) of every node.
   MULTI-RHS: the same sphere at k_a = 3, eps_r = 6 with 128 plane waves
          (64 seeded directions x 2 polarisations): mixed fill ->
          block-Jacobi setup -> 128 right-hand sides -> block GMRES (complex
@@ -73,6 +78,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="fp64,mixed")
     ap.add_argument("--no-mrhs", action="store_true", help="skip the 128-RHS block solve pass")
+    ap.add_argument("--no-grad", action="store_true", help="skip the adjoint gradient pass")
     return ap.parse_args()
 
 
@@ -120,6 +126,12 @@ def main():
         mkh, mpol = planewaves("sphere1280_mrhs")
         Smr = mbem.Solver(mxyz, mtri, mcfg["k0"], mcfg["eps_r"], mcfg["mu_r"],
                           precision=mbem.MBEM_MIXED)
+    Sg = None
+    if not args.no_grad:
+        gcfg = get_config("ellipsoid1280")
+        gxyz, gtri = icosphere_p2(gcfg["n_tris"], gcfg["axes"])
+        gkh, gpol = planewaves("ellipsoid1280")
+        Sg = mbem.Solver(gxyz, gtri, gcfg["k0"], gcfg["eps_r"], gcfg["mu_r"], precision=mbem.MBEM_FP64)
 
     def step():
         out = {}
@@ -140,6 +152,17 @@ def main():
             F = Smr.farfield(x, mkh)              # every solution in every incidence direction
             out["mrhs"] = dict(fill=fs.as_dict(), setup_ms=ps.t_setup_ms, solve=bs.as_dict(),
                                code=code, F=F, b=b)
+        if Sg is not None:
+            t0 = time.perf_counter()
+            fs = Sg.fill()
+            ps = Sg.precond_setup(gcfg["mbj_block"])
+            b = Sg.rhs(gkh, gpol)
+            x, ss, code = Sg.solve(b, tol=gcfg["tol"], maxit=600)
+            g, ags, lam, dnode, dx = Sg.grad_sigma_ext(x[0], gkh[0], gpol[0], tol=gcfg["tol"], shape=True)
+            torch.cuda.synchronize()
+            out["grad"] = dict(fill=fs.as_dict(), setup_ms=ps.t_setup_ms, solve=ss.as_dict(), code=code,
+                               adj=ags.as_dict(), out=g, dnode_norm=float(torch.linalg.norm(dnode)),
+                               wall_ms=1e3 * (time.perf_counter() - t0))
         return out
 
     def log(msg):
@@ -281,6 +304,26 @@ def main():
                      "launch_ms": t_gemm},
         }
 
+    grad = None
+    if Sg is not None:
+        gr = [r["grad"] for r in recs]
+        gm = lambda f: float(np.mean([f(r) for r in gr]))
+        grad = {
+            "workload": "ellipsoid1280", "unknowns": Sg.N, "n_nodes": Sg.nn, "k0": gcfg["k0"],
+            "eps_r": str(gcfg["eps_r"]), "gmres_tol": gcfg["tol"],
+            "sigma_ext": float(gr[-1]["out"][0]),
+            "dsigma_deps_re": float(gr[-1]["out"][1]), "dsigma_deps_im": float(gr[-1]["out"][2]),
+            "dsigma_dnode_norm": gr[-1]["dnode_norm"],
+            "t_fill_ms": gm(lambda r: r["fill"]["t_fill_ms"]),
+            "t_setup_ms": gm(lambda r: r["setup_ms"]),
+            "t_solve_ms": gm(lambda r: r["solve"]["t_solve_ms"]),
+            "t_adjoint_solve_ms": gm(lambda r: r["adj"]["t_adjoint_ms"]),
+            "t_deps_ms": gm(lambda r: r["adj"]["t_deps_ms"]),
+            "t_shape_ms": gm(lambda r: r["adj"]["t_shape_ms"]),
+            "t_pass_ms": gm(lambda r: r["wall_ms"]),
+            "adjoint_iters": int(gr[-1]["adj"]["iters"]),
+        }
+
     if not args.no_cpu_baseline:
         log("timing the CPU oracle fill")
     cpu = None if args.no_cpu_baseline else cpu_baseline(xyz, tri, cfg, N)
@@ -305,6 +348,7 @@ def main():
         "accuracy": info,
         "roofline": roof,
         "multi_rhs": mrhs,
+        "gradient": grad,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -312,6 +356,8 @@ def main():
         S.close()
     if Smr is not None:
         Smr.close()
+    if Sg is not None:
+        Sg.close()
 
 
 if __name__ == "__main__":

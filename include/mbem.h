@@ -108,6 +108,10 @@ typedef struct {
     double t_matvec_ms;   /* solve: sum of dense GEMV kernel times            */
     int32_t n_matvec;     /* solve: number of GEMV launches                   */
     int64_t n_regular_pairs; /* regular element pairs (all launches)          */
+    /* mbem_grad_sigma_ext: wall times of its phases                          */
+    double t_adjoint_ms;  /* Z^T lambda = g                                   */
+    double t_deps_ms;     /* dZ/deps_r fill and lambda^T dZ x                 */
+    double t_shape_ms;    /* reverse pass over the geometry                   */
 } mbem_stats;
 
 /* ---- context ---------------------------------------------------------- */

@@ -585,7 +585,12 @@ int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh, const
         const mbem_c128 ec[3] = {{pol[0].re, -pol[0].im}, {pol[1].re, -pol[1].im}, {pol[2].re, -pol[2].im}};
         st = ff_functional_run(mesh, p, khat, (const double2 *)ec, g, s);
     }
+    Timer tm;
+    double t_adj = 0, t_deps = 0, t_shape = 0;
+    tm.start(s);
     if (st == MBEM_OK) st = solve_impl(ctx, op, (const mbem_c128 *)g, 1, o, (mbem_c128 *)lam, &sst, true);
+    t_adj = tm.stop(s);
+    tm.start(s);
     if (st == MBEM_OK) st = mbem_fill_deps(ctx, mesh, p, &dop, nullptr);
     if (st == MBEM_OK) {
         double2 *tmp = nullptr;
@@ -597,10 +602,16 @@ int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh, const
         (void)hipStreamSynchronize(s);
         dfree(tmp);
     }
+    t_deps = tm.stop(s);
     if (st == MBEM_OK && lambda_out)
         if (hipMemcpy(lambda_out, lam, sizeof(double2) * N, hipMemcpyDeviceToDevice) != hipSuccess) st = MBEM_EDEVICE;
+    tm.start(s);
     if (st == MBEM_OK && (dsig_dnode || dsig_dx))
         st = shape_grad_run(op, p, (const double2 *)x, lam, khat, (const double2 *)pol, dsig_dnode, dsig_dx, s);
+    t_shape = tm.stop(s);
+    sst.t_adjoint_ms = t_adj;
+    sst.t_deps_ms = t_deps;
+    sst.t_shape_ms = t_shape;
     if (dop) mbem_op_destroy(dop);
     dfree(g); dfree(lam); dfree(y); dfree(dots);
     if (st != MBEM_OK) return st;

@@ -55,7 +55,8 @@ class Stats(C.Structure):
                 ("n_near_pairs", C.c_int64), ("t_geom_ms", C.c_double),
                 ("t_regular_ms", C.c_double), ("t_near_ms", C.c_double), ("t_ssq_ms", C.c_double),
                 ("t_mass_ms", C.c_double), ("t_matvec_ms", C.c_double), ("n_matvec", C.c_int32),
-                ("n_regular_pairs", C.c_int64)]
+                ("n_regular_pairs", C.c_int64), ("t_adjoint_ms", C.c_double),
+                ("t_deps_ms", C.c_double), ("t_shape_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
