@@ -50,6 +50,17 @@ PEAK_FP32_VALU = 157.3     # TFLOP/s, MI355X vector FP32
 PEAK_HBM = 8000.0          # GB/s
 PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix cores
 
+# HBM bytes moved per launch (per fill for the regular-pair kernel: all its
+# colour-class launches), from rocprofv3 FETCH_SIZE and WRITE_SIZE counters
+# scaled by a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  A
+# kernel changed after its counters were taken gets None here.
+MEASURED_TRAFFIC = {
+    ("k_regular", "fp64"): 15.156e9 + 7.892e9,
+    ("k_regular", "mixed"): 9.776e9 + 5.584e9,
+    ("k_gemv3", "fp64"): 1.283e9,
+    ("k_gemv3", "mixed"): 0.652e9,
+}
+
 # Algorithmic flops of the regular-pair fill (FMA = 2 flops, every
 # transcendental call = 1).  Per point pair: distance and unit vector 13,
 # kernel differences 151 (two complex exponentials, f, g, phi for both
@@ -79,6 +90,12 @@ def parse():
     ap.add_argument("--paths", default="fp64,mixed")
     ap.add_argument("--no-mrhs", action="store_true", help="skip the 128-RHS block solve pass")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint gradient pass")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 1 GiB device to device once (scales the FETCH_SIZE / WRITE_SIZE "
+                         "counters) and exit")
+    ap.add_argument("--only", choices=["all", "main", "mrhs", "grad"], default="all",
+                    help="run one pass of the step only (for profiling); the JSON line is "
+                         "printed for 'all' and 'main'")
     return ap.parse_args()
 
 
@@ -105,10 +122,27 @@ def main():
               "is benchmarked on a single MI355X", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        a = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30}), flush=True)
+        return
     from paper_2604_21181_amd import mbem
     from workloads import get_config, icosphere_p2, planewaves
     from workloads.configs import cut_plane_directions
 
+    if args.only in ("mrhs", "grad"):
+        args.paths = ""
+        args.no_cpu_baseline = True
+    if args.only == "main":
+        args.no_mrhs = args.no_grad = True
+    if args.only == "mrhs":
+        args.no_grad = True
+    if args.only == "grad":
+        args.no_mrhs = True
     cfg = get_config(args.workload)
     xyz, tri = icosphere_p2(cfg["n_tris"], cfg["axes"])
     khat, pol = planewaves(args.workload)
@@ -117,7 +151,7 @@ def main():
     prec = {"fp64": mbem.MBEM_FP64, "mixed": mbem.MBEM_MIXED}
     solvers = {p: mbem.Solver(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"], precision=prec[p])
                for p in paths}
-    N = solvers[paths[0]].N
+    N = solvers[paths[0]].N if paths else 0
     nt = tri.shape[0]
     Smr = None
     if not args.no_mrhs:
@@ -185,82 +219,83 @@ def main():
     def mean(path, sect, key):
         return float(np.mean([r[path][sect][key] for r in recs]))
 
-    res = {}
-    for p in paths:
-        res[p] = dict(
-            t_fill_ms=mean(p, "fill", "t_fill_ms"),
-            t_regular_ms=mean(p, "fill", "t_regular_ms"),
-            t_near_ms=mean(p, "fill", "t_near_ms"),
-            t_ssq_ms=mean(p, "fill", "t_ssq_ms"),
-            t_geom_ms=mean(p, "fill", "t_geom_ms"),
-            t_mass_ms=mean(p, "fill", "t_mass_ms"),
-            t_setup_ms=float(np.mean([r[p]["setup_ms"] for r in recs])),
-            t_solve_ms=mean(p, "solve", "t_solve_ms"),
-            t_matvec_ms=mean(p, "solve", "t_matvec_ms"),
-            n_matvec=int(recs[-1][p]["solve"]["n_matvec"]),
-            iters=int(recs[-1][p]["solve"]["iters"]),
-            outer=int(recs[-1][p]["solve"]["outer_iters"]),
-            rel_resid=float(recs[-1][p]["solve"]["rel_resid"]),
-            n_near=int(recs[-1][p]["fill"]["n_near_pairs"]),
-            n_regular=int(recs[-1][p]["fill"]["n_regular_pairs"]),
-        )
-        res[p]["fill_rate"] = N * N / (res[p]["t_fill_ms"] * 1e-3)
+    if paths:
+        res = {}
+        for p in paths:
+            res[p] = dict(
+                t_fill_ms=mean(p, "fill", "t_fill_ms"),
+                t_regular_ms=mean(p, "fill", "t_regular_ms"),
+                t_near_ms=mean(p, "fill", "t_near_ms"),
+                t_ssq_ms=mean(p, "fill", "t_ssq_ms"),
+                t_geom_ms=mean(p, "fill", "t_geom_ms"),
+                t_mass_ms=mean(p, "fill", "t_mass_ms"),
+                t_setup_ms=float(np.mean([r[p]["setup_ms"] for r in recs])),
+                t_solve_ms=mean(p, "solve", "t_solve_ms"),
+                t_matvec_ms=mean(p, "solve", "t_matvec_ms"),
+                n_matvec=int(recs[-1][p]["solve"]["n_matvec"]),
+                iters=int(recs[-1][p]["solve"]["iters"]),
+                outer=int(recs[-1][p]["solve"]["outer_iters"]),
+                rel_resid=float(recs[-1][p]["solve"]["rel_resid"]),
+                n_near=int(recs[-1][p]["fill"]["n_near_pairs"]),
+                n_regular=int(recs[-1][p]["fill"]["n_regular_pairs"]),
+            )
+            res[p]["fill_rate"] = N * N / (res[p]["t_fill_ms"] * 1e-3)
 
-    last = recs[-1]
-    ff = {p: last[p]["F"].cpu().numpy()[0] for p in paths}
-    info = {}
-    mixed_ok = False
-    if "fp64" in paths and "mixed" in paths:
-        e = float(np.linalg.norm(ff["mixed"] - ff["fp64"]) / np.linalg.norm(ff["fp64"]))
-        info["farfield_err_mixed_vs_fp64"] = e
-        mixed_ok = e <= 1e-6
-    head = "mixed" if (mixed_ok or paths == ["mixed"]) else paths[0]
+        last = recs[-1]
+        ff = {p: last[p]["F"].cpu().numpy()[0] for p in paths}
+        info = {}
+        mixed_ok = False
+        if "fp64" in paths and "mixed" in paths:
+            e = float(np.linalg.norm(ff["mixed"] - ff["fp64"]) / np.linalg.norm(ff["fp64"]))
+            info["farfield_err_mixed_vs_fp64"] = e
+            mixed_ok = e <= 1e-6
+        head = "mixed" if (mixed_ok or paths == ["mixed"]) else paths[0]
 
-    # ---- roofline of the dominant kernel (largest device time per step)
-    cand = []
-    for p in paths:
-        r = res[p]
-        nm = r["n_matvec"]
-        cand.append((r["t_regular_ms"], "regular_pairs_" + p, p))
-        cand.append((r["t_ssq_ms"], "sauter_schwab_" + p, p))
-        if nm:
-            cand.append((r["t_matvec_ms"], "gemv_" + p, p))
-    cand.sort(reverse=True)
-    t_dom, kname, kp = cand[0]
-    r = res[kp]
-    n2 = N // 2
-    if kname.startswith("gemv"):
-        esz = 16 if kp == "fp64" else 8
-        traffic = 3 * n2 * n2 * esz + 2 * N * 16            # three blocks + x in, y out
-        per_launch_ms = r["t_matvec_ms"] / max(1, r["n_matvec"])
-        achieved = traffic / (per_launch_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM, "traffic": None, "kernel": "k_gemv3",
-                "algorithmic_bytes_per_launch": traffic, "launch_ms": per_launch_ms}
-    elif kname.startswith("regular"):
-        S = solvers[kp]
-        npairs = r["n_regular"]
-        rank = np.empty_like(S.node_order)
-        rank[S.node_order] = np.arange(S.nn)
-        tm = rank[tri[S.tri_order]]
-        ns = np.array([np.unique(tm[k:k + CHUNK]).size for k in range(0, nt, CHUNK)])
-        # every (test triangle, chunk) workgroup contracts ns test-side nodes
-        flops = (npairs * (49 * FLOP_POINT_PAIR + FLOP_PAIR_TRIAL)
-                 + nt * int(ns.sum()) * FLOP_CHUNK_TEST_PER_NODE)
-        achieved = flops / (r["t_regular_ms"] * 1e-3) / 1e12
-        peak = PEAK_FP64_VALU if kp == "fp64" else PEAK_FP32_VALU
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "kernel": "k_regular",
-                "algorithmic_flops_per_launch": flops, "launch_ms": r["t_regular_ms"]}
-    else:
-        S = solvers[kp]
-        ncoinc, nedge, nvert = S.n_singular
-        pts = (6 * ncoinc + 5 * nedge + 2 * nvert) * 256
-        flops = pts * FLOP_SSQ_POINT
-        achieved = flops / (r["t_ssq_ms"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_VALU, "traffic": None, "kernel": "k_ssq",
-                "algorithmic_flops_per_launch": flops, "launch_ms": r["t_ssq_ms"]}
+        # ---- roofline of the dominant kernel (largest device time per step)
+        cand = []
+        for p in paths:
+            r = res[p]
+            nm = r["n_matvec"]
+            cand.append((r["t_regular_ms"], "regular_pairs_" + p, p))
+            cand.append((r["t_ssq_ms"], "sauter_schwab_" + p, p))
+            if nm:
+                cand.append((r["t_matvec_ms"], "gemv_" + p, p))
+        cand.sort(reverse=True)
+        t_dom, kname, kp = cand[0]
+        r = res[kp]
+        n2 = N // 2
+        if kname.startswith("gemv"):
+            esz = 16 if kp == "fp64" else 8
+            traffic = 3 * n2 * n2 * esz + 2 * N * 16            # three blocks + x in, y out
+            per_launch_ms = r["t_matvec_ms"] / max(1, r["n_matvec"])
+            achieved = traffic / (per_launch_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
+                    "frac": achieved / PEAK_HBM, "traffic": MEASURED_TRAFFIC.get(("k_gemv3", kp)), "kernel": "k_gemv3",
+                    "algorithmic_bytes_per_launch": traffic, "launch_ms": per_launch_ms}
+        elif kname.startswith("regular"):
+            S = solvers[kp]
+            npairs = r["n_regular"]
+            rank = np.empty_like(S.node_order)
+            rank[S.node_order] = np.arange(S.nn)
+            tm = rank[tri[S.tri_order]]
+            ns = np.array([np.unique(tm[k:k + CHUNK]).size for k in range(0, nt, CHUNK)])
+            # every (test triangle, chunk) workgroup contracts ns test-side nodes
+            flops = (npairs * (49 * FLOP_POINT_PAIR + FLOP_PAIR_TRIAL)
+                     + nt * int(ns.sum()) * FLOP_CHUNK_TEST_PER_NODE)
+            achieved = flops / (r["t_regular_ms"] * 1e-3) / 1e12
+            peak = PEAK_FP64_VALU if kp == "fp64" else PEAK_FP32_VALU
+            roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                    "frac": achieved / peak, "traffic": MEASURED_TRAFFIC.get(("k_regular", kp)), "kernel": "k_regular",
+                    "algorithmic_flops_per_launch": flops, "launch_ms": r["t_regular_ms"]}
+        else:
+            S = solvers[kp]
+            ncoinc, nedge, nvert = S.n_singular
+            pts = (6 * ncoinc + 5 * nedge + 2 * nvert) * 256
+            flops = pts * FLOP_SSQ_POINT
+            achieved = flops / (r["t_ssq_ms"] * 1e-3) / 1e12
+            roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_FP64_VALU, "traffic": None, "kernel": "k_ssq",
+                    "algorithmic_flops_per_launch": flops, "launch_ms": r["t_ssq_ms"]}
 
     mrhs = None
     if Smr is not None:
@@ -323,6 +358,15 @@ def main():
             "t_pass_ms": gm(lambda r: r["wall_ms"]),
             "adjoint_iters": int(gr[-1]["adj"]["iters"]),
         }
+
+    if not paths:
+        # profiling run of one pass: its own section only
+        print(json.dumps({"pass": args.only, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": ms_per_step, "multi_rhs": mrhs, "gradient": grad}), flush=True)
+        for S in (Smr, Sg):
+            if S is not None:
+                S.close()
+        return
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle fill")
