@@ -186,14 +186,15 @@ int mbem_matvec(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *x,
 
 /* Morton block-Jacobi: clusters of `block` consecutive indices of one
  * current's vector (block <= 256); each block is the 2 block x 2 block
- * restriction of Z, LU-factorised with partial pivoting (blocked, in FP64).
+ * restriction of Z, LU-factorised with partial pivoting (blocked, in FP64)
+ * and inverted explicitly (the apply is then one matrix-vector product).
  * MBEM_ESINGULAR on a zero pivot, MBEM_EINVAL for block > 256.
  * block <= 0 removes the preconditioner.                                   */
 int mbem_precond_setup(mbem_ctx *ctx, mbem_op *op, int32_t block,
                        mbem_stats *stats);
 
-/* z = P^-1 v (device, length N, complex128) by forward and backward
- * substitution with the block factors.                                     */
+/* z = P^-1 v (device, length N, complex128): one product of every block's
+ * explicit inverse with its 2 block entries of v.                          */
 int mbem_precond_apply(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *v,
                        mbem_c128 *z);
 
