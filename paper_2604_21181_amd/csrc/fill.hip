@@ -107,11 +107,22 @@ __device__ inline vec3<T> qload(const T *qp, int64_t nq, int f, int64_t i) {
 
 constexpr int kPairLanes = 49 * kChunk;   // 196
 
+// Phase-C destinations of one workgroup: 6 row groups (op, alpha) x 2 ns
+// columns (slot, beta) items, each touching the 6 rows of the test
+// triangle's nodes; at most 6 x 2 x 24 items.  Their current values are
+// prefetched into LDS by direct global-to-LDS loads as soon as the
+// workgroup knows its tile, so the read of the read-modify-write overlaps
+// the kernel evaluations.
+constexpr int kItemsMax = 6 * 2 * 24;
+
 template <typename T, typename TS, bool DK = false>
 __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
-    // R1: point-pair kernel values, later the slot-merged trial contraction
+    // point-pair kernel values; the trial-side contraction and the merge by
+    // node are later written over them in place
     __shared__ cx<T> s_r1[kPairLanes * 12];
-    __shared__ cx<T> s_tf[kChunk * 7 * 6 * 12];
+    // prefetched destination values: plane i (row of the test triangle),
+    // item it; FP64 as complex pairs, FP32 as separate real / imaginary planes
+    __shared__ __align__(16) TS s_dst[2 * 6 * kItemsMax];
     __shared__ T s_N[7][6];
     __shared__ int32_t s_rec[kChunkRec];
     __shared__ int32_t s_te[6];
@@ -152,6 +163,45 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) any |= s_act[k];
     if (!any) return;                          // uniform over the workgroup
+    const int ns = s_rec[0];
+    const int rowlen = 2 * ns;
+    const int nitems = 6 * rowlen;
+    // item it: row group g = 2 op + alpha, slot sl, beta; destination of
+    // row i of the test triangle: Z[op][2 te_i + alpha][2 node(sl) + beta].
+    // No other workgroup of this launch touches these entries (colour
+    // classes), and earlier launches completed in stream order.
+    {
+        const int wave = tid / 64;
+        for (int base = 0; base < nitems; base += 256) {
+            const int it = base + tid;
+            const bool on = it < nitems;
+            const int itc = on ? it : 0;
+            const int g = itc / rowlen, rem = itc % rowlen;
+            const int sl = rem / 2, be = rem % 2, op = g / 2, al = g % 2;
+            const int64_t col = 2 * (int64_t)s_rec[1 + sl] + be;
+            const TS *Z = a.Z[op];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                const int64_t row = 2 * (int64_t)s_te[i] + al;
+                const TS *src = Z + 2 * (row * a.n2 + col);
+                const int first = base + wave * 64;        // wave-uniform item of lane 0
+                if constexpr (std::is_same<TS, double>::value) {
+                    TS *dst = s_dst + 2 * (i * kItemsMax + first);
+                    if (on)
+                        __builtin_amdgcn_global_load_lds((const void *)src,
+                                                         (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+                } else {
+                    TS *dre = s_dst + (2 * i) * kItemsMax + first, *dim = s_dst + (2 * i + 1) * kItemsMax + first;
+                    if (on) {
+                        __builtin_amdgcn_global_load_lds((const void *)src,
+                                                         (__attribute__((address_space(3))) void *)dre, 4, 0, 0);
+                        __builtin_amdgcn_global_load_lds((const void *)(src + 1),
+                                                         (__attribute__((address_space(3))) void *)dim, 4, 0, 0);
+                    }
+                }
+            }
+        }
+    }
     const int64_t nq = a.nt * kQP;
     // A: kernel values
     if (tid < kPairLanes) {
@@ -188,7 +238,8 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
         for (int c = 0; c < 12; ++c) s_r1[tid * 12 + c] = k[c];
     }
     __syncthreads();
-    // B: trial side per triangle
+    // B: trial side per triangle, in place: Tf[fs][p][j][c] = sum_q N_j(q) k
+    // over the 7 entries (fs, p, q = 0..6, c) it replaces (j = 0..5)
     for (int it = tid; it < kChunk * 7 * 12; it += blockDim.x) {
         const int fs = it / 84, rem = it % 84, p = rem / 12, c = rem % 12;
         cx<T> kv[7];
@@ -199,32 +250,36 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
             cx<T> acc = {0, 0};
 #pragma unroll
             for (int q = 0; q < 7; ++q) acc = acc + s_N[q][j] * kv[q];
-            s_tf[((fs * 7 + p) * 6 + j) * 12 + c] = acc;
+            s_r1[(fs * 49 + p * 7 + j) * 12 + c] = acc;
         }
     }
     __syncthreads();
-    // B2: merge by node slot into R1: Ts[p][slot][c]
-    const int ns = s_rec[0];
+    // B2: merge by node slot, in place at the slot's first incidence:
+    // Ts[p][slot][c] = sum over the (triangle, local node) incidences
     for (int it = tid; it < 7 * ns * 12; it += blockDim.x) {
         const int p = it / (ns * 12), rem = it % (ns * 12), sl = rem / 12, c = rem % 12;
         cx<T> acc = {0, 0};
-        for (int u = s_rec[25 + sl]; u < s_rec[26 + sl]; ++u) {
+        const int u0 = s_rec[25 + sl];
+        for (int u = u0; u < s_rec[26 + sl]; ++u) {
             const int fs = s_rec[50 + u] >> 3, loc = s_rec[50 + u] & 7;
-            acc = acc + s_tf[((fs * 7 + p) * 6 + loc) * 12 + c];
+            acc = acc + s_r1[(fs * 49 + p * 7 + loc) * 12 + c];
         }
-        s_r1[(p * 24 + sl) * 12 + c] = acc;
+        const int fs0 = s_rec[50 + u0] >> 3, loc0 = s_rec[50 + u0] & 7;
+        s_r1[(fs0 * 49 + p * 7 + loc0) * 12 + c] = acc;
     }
+    __builtin_amdgcn_s_waitcnt(0);             // prefetched destinations have landed
     __syncthreads();
     // C: test side, lanes along (slot, beta) of one (op, alpha) row group
-    const int rowlen = 2 * ns;
-    for (int it = tid; it < 6 * rowlen; it += blockDim.x) {
+    for (int it = tid; it < nitems; it += blockDim.x) {
         const int g = it / rowlen, rem = it % rowlen;       // g = 2 op + alpha
         const int sl = rem / 2, be = rem % 2;
         const int op = g / 2, al = g % 2;
         const int c = 4 * op + 2 * al + be;
+        const int u0 = s_rec[25 + sl];
+        const int fs0 = s_rec[50 + u0] >> 3, loc0 = s_rec[50 + u0] & 7;
         cx<T> tv[7];
 #pragma unroll
-        for (int p = 0; p < 7; ++p) tv[p] = s_r1[(p * 24 + sl) * 12 + c];
+        for (int p = 0; p < 7; ++p) tv[p] = s_r1[(fs0 * 49 + p * 7 + loc0) * 12 + c];
         const int64_t col = 2 * (int64_t)s_rec[1 + sl] + be;
         TS *Z = a.Z[op];
 #pragma unroll
@@ -234,8 +289,16 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
             for (int p = 0; p < 7; ++p) acc = acc + s_N[p][i] * tv[p];
             const int64_t row = 2 * (int64_t)s_te[i] + al;
             TS *dst = Z + 2 * (row * a.n2 + col);
-            dst[0] += (TS)acc.re;      // race-free: see the colouring above
-            dst[1] += (TS)acc.im;
+            TS ore, oim;
+            if constexpr (std::is_same<TS, double>::value) {
+                ore = s_dst[2 * (i * kItemsMax + it)];
+                oim = s_dst[2 * (i * kItemsMax + it) + 1];
+            } else {
+                ore = s_dst[(2 * i) * kItemsMax + it];
+                oim = s_dst[(2 * i + 1) * kItemsMax + it];
+            }
+            dst[0] = ore + (TS)acc.re;         // race-free: see the colouring above
+            dst[1] = oim + (TS)acc.im;
         }
     }
 }

@@ -159,8 +159,62 @@ __device__ __forceinline__ cx<T> horner(const double *c, T R) {
     return s;
 }
 
-__device__ inline void sincos_t(double x, double *s, double *c) { sincos(x, s, c); }
-__device__ inline void sincos_t(float x, float *s, float *c) { sincosf(x, s, c); }
+// sin and cos of the phases k R of the kernels (|x| far below 2^20).
+// Cody and Waite's reduction x = n pi/2 + r, |r| <= pi/4, with pi/2 split
+// into three floating-point parts (each product n P_i is exact inside the
+// fused multiply-add), then the Taylor series of sin r and cos r, truncated
+// where the next term is below the unit roundoff on |r| <= pi/4 (FP64:
+// r^15 and r^16; FP32: r^9 and r^10), and the quadrant n mod 4.
+template <typename T>
+__device__ __forceinline__ void quadrant(int q, T sr, T cr, T *s, T *c) {
+    const T ss = (q & 1) ? cr : sr, cc = (q & 1) ? sr : cr;
+    *s = (q & 2) ? -ss : ss;
+    *c = ((q + 1) & 2) ? -cc : cc;
+}
+__device__ __forceinline__ void sincos_t(double x, double *s, double *c) {
+    const double n = rint(x * 0.63661977236758134308);
+    double r = fma(-n, 0x1.921fb54442d18p+0, x);
+    r = fma(-n, 0x1.1a62633145c07p-54, r);
+    r = fma(-n, -0x1.f1976b7ed8fbcp-110, r);
+    const double u = r * r;
+    double ps = -1.0 / 1307674368000.0;                 // -1/15!
+    ps = fma(ps, u, 1.0 / 6227020800.0);                // 1/13!
+    ps = fma(ps, u, -1.0 / 39916800.0);                 // -1/11!
+    ps = fma(ps, u, 1.0 / 362880.0);
+    ps = fma(ps, u, -1.0 / 5040.0);
+    ps = fma(ps, u, 1.0 / 120.0);
+    ps = fma(ps, u, -1.0 / 6.0);
+    const double sr = fma(r * u, ps, r);
+    double pc = 1.0 / 20922789888000.0;                 // 1/16!
+    pc = fma(pc, u, -1.0 / 87178291200.0);              // -1/14!
+    pc = fma(pc, u, 1.0 / 479001600.0);                 // 1/12!
+    pc = fma(pc, u, -1.0 / 3628800.0);
+    pc = fma(pc, u, 1.0 / 40320.0);
+    pc = fma(pc, u, -1.0 / 720.0);
+    pc = fma(pc, u, 1.0 / 24.0);
+    pc = fma(pc, u, -0.5);
+    const double cr = fma(u, pc, 1.0);
+    quadrant((int)n, sr, cr, s, c);
+}
+__device__ __forceinline__ void sincos_t(float x, float *s, float *c) {
+    const float n = rintf(x * 0.636619772f);
+    float r = fmaf(-n, 0x1.921fb6p+0f, x);
+    r = fmaf(-n, -0x1.777a5cp-25f, r);
+    r = fmaf(-n, -0x1.ee59dap-50f, r);
+    const float u = r * r;
+    float ps = 1.0f / 362880.0f;
+    ps = fmaf(ps, u, -1.0f / 5040.0f);
+    ps = fmaf(ps, u, 1.0f / 120.0f);
+    ps = fmaf(ps, u, -1.0f / 6.0f);
+    const float sr = fmaf(r * u, ps, r);
+    float pc = -1.0f / 3628800.0f;
+    pc = fmaf(pc, u, 1.0f / 40320.0f);
+    pc = fmaf(pc, u, -1.0f / 720.0f);
+    pc = fmaf(pc, u, 1.0f / 24.0f);
+    pc = fmaf(pc, u, -0.5f);
+    const float cr = fmaf(u, pc, 1.0f);
+    quadrant((int)n, sr, cr, s, c);
+}
 __device__ inline double exp_t(double x) { return exp(x); }
 __device__ inline float exp_t(float x) { return expf(x); }
 
@@ -187,7 +241,7 @@ __device__ __forceinline__ KScal<T> kernel_scalars(const KernelConst &K, T R) {
         const cx<T> ikR = {-k[s].im * R, k[s].re * R};
         T sn, cs;
         sincos_t(k[s].re * R, &sn, &cs);
-        const T am = exp_t(-k[s].im * R);
+        const T am = k[s].im == (T)0 ? (T)1 : exp_t(-k[s].im * R);
         const cx<T> e = {am * cs, am * sn};
         const cx<T> k2R2 = (R * R) * (k[s] * k[s]);
         phi[s] = r1 * e;
@@ -230,7 +284,7 @@ __device__ __forceinline__ KScal<double> kernel_scalars_deps(const KernelConst &
     const double r1 = inv4pi / R;
     const cx<double> k = {K.ki_re, K.ki_im}, dk = {K.ka_re, K.ka_im};
     double sn, cs;
-    sincos(k.re * R, &sn, &cs);
+    sincos_t(k.re * R, &sn, &cs);
     const double am = exp(-k.im * R);
     const cx<double> e = {am * cs, am * sn};
     const cx<double> phi = r1 * e;

@@ -104,7 +104,7 @@ __device__ KScalD kernel_scalars_dr(const KernelConst &K, double R) {
     for (int s = 0; s < 2; ++s) {
         const double sg = s == 0 ? 1.0 : -1.0;
         double sn, cs;
-        sincos(k[s].re * R, &sn, &cs);
+        sincos_t(k[s].re * R, &sn, &cs);
         const double am = exp(-k[s].im * R);
         const cxd e = {am * cs, am * sn};
         const cxd ikR = {-k[s].im * R, k[s].re * R};
