@@ -6,7 +6,7 @@
 //    pair go to LDS and are contracted with the shape-function table in two
 //    steps (trial side, then test side) before being added to Z;
 //  * singular pairs (coincident, common edge, common vertex): Sauter-Schwab
-//    quadrature, 6 / 5 / 2 regions x n^4 Gauss points, one wavefront per
+//    quadrature, 6 / 5 / 2 regions x n^4 Gauss points, two wavefronts per
 //    pair, FP64;
 //  * MIXED precision: far regular pairs in FP32, near regular pairs and all
 //    singular pairs in FP64, everything accumulated into complex64 Z.
@@ -318,26 +318,35 @@ struct SsqArgs {
     TS *Z[3];
 };
 
-constexpr int kStreams = 5;   // consumer lanes per kernel component
+// Two wavefronts per pair.  Every lane evaluates one quadrature point per
+// batch (kernel values and the six test / trial shape functions) into LDS;
+// then 120 consumer lanes, one real component (2 c + re/im) of the twelve
+// kernel values each, split the batch's points into kStreams interleaved
+// streams and accumulate the 6 x 6 outer products N_i(x) N_j(y) kappa in
+// registers.  The streams are summed through the same LDS buffer at the end.
+constexpr int kSsqThreads = 128;
+constexpr int kStreams = 5;
+constexpr int kPtStride = 37;   // 24 kernel reals, N_i(x), N_j(y); padded
 
 template <typename TS, bool DK = false>
-__global__ __launch_bounds__(64) void k_ssq(SsqArgs<TS> a) {
-    __shared__ double s_pt[kWave][36];                 // w kappa (24), Nx, Ny
-    __shared__ double s_red[kStreams][36 * 12 * 2];
-    const int lane = threadIdx.x;
+__global__ __launch_bounds__(kSsqThreads) void k_ssq(SsqArgs<TS> a) {
+    __shared__ double s_pt[kSsqThreads * kPtStride];
+    static_assert(kStreams * 36 * 24 <= kSsqThreads * kPtStride, "reduction buffer");
+    const int tid = threadIdx.x;
     const int64_t pid = blockIdx.x;
     const int32_t e = a.pairs[4 * pid], f = a.pairs[4 * pid + 1];
     const int cls = a.pairs[4 * pid + 2], code = a.pairs[4 * pid + 3];
     const int n = a.order, n4 = n * n * n * n;
     const int nreg = cls == 3 ? 6 : (cls == 2 ? 5 : 2);
     const int npts = nreg * n4;
-    const int c = lane % 12, stream = lane / 12;     // consumer role
-    const bool consumer = lane < 12 * kStreams;
-    double acc[36][2];
+    const int comp = tid % 24, stream = tid / 24;    // consumer role
+    const bool consumer = tid < 24 * kStreams;
+    double acc[36];
 #pragma unroll
-    for (int k = 0; k < 36; ++k) acc[k][0] = acc[k][1] = 0.0;
-    for (int base = 0; base < npts; base += kWave) {
-        const int idx = base + lane;
+    for (int k = 0; k < 36; ++k) acc[k] = 0.0;
+    for (int base = 0; base < npts; base += kSsqThreads) {
+        const int idx = base + tid;
+        double *pt = s_pt + tid * kPtStride;
         if (idx < npts) {
             const int r = idx / n4;
             int g = idx % n4;
@@ -358,47 +367,46 @@ __global__ __launch_bounds__(64) void k_ssq(SsqArgs<TS> a) {
             cx<double> k[12];
             kappa12<double, DK>(*a.K, X.x, X.n, ta, sa, Y.x, tb, wg * X.J * Y.J, k);
 #pragma unroll
-            for (int q = 0; q < 12; ++q) { s_pt[lane][2 * q] = k[q].re; s_pt[lane][2 * q + 1] = k[q].im; }
+            for (int q = 0; q < 12; ++q) { pt[2 * q] = k[q].re; pt[2 * q + 1] = k[q].im; }
 #pragma unroll
-            for (int q = 0; q < 6; ++q) { s_pt[lane][24 + q] = X.N[q]; s_pt[lane][30 + q] = Y.N[q]; }
+            for (int q = 0; q < 6; ++q) { pt[24 + q] = X.N[q]; pt[30 + q] = Y.N[q]; }
         } else {
 #pragma unroll
-            for (int q = 0; q < 36; ++q) s_pt[lane][q] = 0.0;
+            for (int q = 0; q < 36; ++q) pt[q] = 0.0;
         }
         __syncthreads();
         if (consumer) {
-            for (int r = stream; r < kWave; r += kStreams) {
-                const double kr = s_pt[r][2 * c], ki = s_pt[r][2 * c + 1];
-                double u[6][2];
+            for (int r = stream; r < kSsqThreads; r += kStreams) {
+                const double *row = s_pt + r * kPtStride;
+                const double kv = row[comp];
+                double u[6];
 #pragma unroll
-                for (int j = 0; j < 6; ++j) { u[j][0] = s_pt[r][30 + j] * kr; u[j][1] = s_pt[r][30 + j] * ki; }
+                for (int j = 0; j < 6; ++j) u[j] = row[30 + j] * kv;
 #pragma unroll
                 for (int i = 0; i < 6; ++i) {
-                    const double nx = s_pt[r][24 + i];
+                    const double nx = row[24 + i];
 #pragma unroll
-                    for (int j = 0; j < 6; ++j) {
-                        acc[6 * i + j][0] += nx * u[j][0];
-                        acc[6 * i + j][1] += nx * u[j][1];
-                    }
+                    for (int j = 0; j < 6; ++j) acc[6 * i + j] += nx * u[j];
                 }
             }
         }
         __syncthreads();
     }
+    // stream partial sums: s_pt[(stream * 36 + k) * 24 + comp]
     if (consumer) {
 #pragma unroll
-        for (int k = 0; k < 36; ++k) {
-            s_red[stream][(k * 12 + c) * 2] = acc[k][0];
-            s_red[stream][(k * 12 + c) * 2 + 1] = acc[k][1];
-        }
+        for (int k = 0; k < 36; ++k) s_pt[(stream * 36 + k) * 24 + comp] = acc[k];
     }
     __syncthreads();
     const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
-    for (int it = lane; it < 36 * 12; it += kWave) {
+    for (int it = tid; it < 36 * 12; it += kSsqThreads) {
+        const int k = it / 12, cc = it % 12;
         double re = 0, im = 0;
 #pragma unroll
-        for (int s = 0; s < kStreams; ++s) { re += s_red[s][2 * it]; im += s_red[s][2 * it + 1]; }
-        const int k = it / 12, cc = it % 12;
+        for (int s = 0; s < kStreams; ++s) {
+            re += s_pt[(s * 36 + k) * 24 + 2 * cc];
+            im += s_pt[(s * 36 + k) * 24 + 2 * cc + 1];
+        }
         const int i = k / 6, j = k % 6;
         const int op = cc / 4, al = (cc / 2) % 2, be = cc % 2;
         const int64_t row = 2 * (int64_t)te[i] + al, col = 2 * (int64_t)tf[j] + be;
@@ -538,7 +546,7 @@ static int launch_ssq(mbem_op *op, hipStream_t s) {
     a.K = op->d_kconst;
     for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)op->K[o];
     if (a.npairs == 0) return MBEM_OK;
-    hipLaunchKernelGGL((k_ssq<TS, DK>), dim3((unsigned)a.npairs), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_ssq<TS, DK>), dim3((unsigned)a.npairs), dim3(kSsqThreads), 0, s, a);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
