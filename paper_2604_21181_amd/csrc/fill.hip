@@ -78,11 +78,11 @@ __device__ __forceinline__ void kappa12(const KernelConst &K, vec3<T> x, vec3<T>
 // performed beyond the L2 on this multi-die part and are far slower).
 //  A: one point pair per lane (4 x 49 lanes): twelve weighted kernel values;
 //  B: trial-side contraction per triangle, Tf[fs][p][j][c] = sum_q kap N_j(q);
-//  B2: merge the chunk's triangles by node: Ts[p][slot][c] (a node shared by
-//      several trial triangles of the chunk is summed here, in LDS);
-//  C: test-side contraction, out[i][slot][c] = sum_p N_i(p) Ts[p][slot][c],
-//     added to Z once per (row, node) of the chunk; consecutive lanes walk
-//     along a row so that the accesses of a wavefront are contiguous.
+//  C: per (row group, chunk node, beta): Ts[p] = the sum of Tf over the
+//     chunk's triangles that contain the node (node merge), then the
+//     test-side contraction out[i] = sum_p N_i(p) Ts[p], added to Z once per
+//     (row, node) of the chunk; consecutive lanes walk along a row so that
+//     the accesses of a wavefront are contiguous.
 template <typename T, typename TS>
 struct RegArgs {
     int64_t nt, n2, n_te, n_ch, total;
@@ -115,30 +115,42 @@ constexpr int kPairLanes = 49 * kChunk;   // 196
 // the kernel evaluations.
 constexpr int kItemsMax = 6 * 2 * 24;
 
+// P2 shape functions at the points of the 7-point rule (rule7: centroid,
+// then the two three-point orbits with (6 -+ sqrt 15)/21), evaluated at
+// compile time: n7(q, j) = N_j(xi_q, eta_q).  The literal is sqrt(15)
+// rounded to double, so the values equal those of rule7 + p2_shape.
+__host__ __device__ constexpr double n7(int q, int j) {
+    const double r15 = 3.8729833462074168851792653997824;
+    const double s = q == 0 ? 1.0 / 3.0 : (q <= 3 ? (6.0 - r15) / 21.0 : (6.0 + r15) / 21.0);
+    const int r = q == 0 ? 0 : (q - 1) % 3;
+    const double xi = q == 0 ? s : (r == 1 ? 1.0 - 2.0 * s : s);
+    const double eta = q == 0 ? s : (r == 2 ? 1.0 - 2.0 * s : s);
+    const double L0 = 1.0 - xi - eta, L1 = xi, L2 = eta;
+    return j == 0 ? L0 * (2.0 * L0 - 1.0) : j == 1 ? L1 * (2.0 * L1 - 1.0)
+         : j == 2 ? L2 * (2.0 * L2 - 1.0) : j == 3 ? 4.0 * L0 * L1
+         : j == 4 ? 4.0 * L1 * L2 : 4.0 * L2 * L0;
+}
+
 template <typename T, typename TS, bool DK = false>
 __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
-    // point-pair kernel values; the trial-side contraction and the merge by
-    // node are later written over them in place
+    // point-pair kernel values; the trial-side contraction is later written
+    // over them in place
     __shared__ cx<T> s_r1[kPairLanes * 12];
     // prefetched destination values: plane i (row of the test triangle),
     // item it; FP64 as complex pairs, FP32 as separate real / imaginary planes
     __shared__ __align__(16) TS s_dst[2 * 6 * kItemsMax];
-    __shared__ T s_N[7][6];
+    __shared__ int64_t s_row[6][6];    // [2 op + alpha][i]: offset of row 2 te_i + alpha
     __shared__ int32_t s_rec[kChunkRec];
-    __shared__ int32_t s_te[6];
     __shared__ int s_act[kChunk];      // 0 skip, 1 compute in T, 2 in FP64
     const int tid = threadIdx.x;
     const int64_t tile = xcd_remap(blockIdx.x, a.total);
     const int64_t e = a.te_list[tile / a.n_ch];
     const int64_t ch = a.ch_list[tile % a.n_ch];
-    if (tid < 7) {
-        double xi, eta, wq, N[6], d1[6], d2[6];
-        rule7(tid, xi, eta, wq);
-        p2_shape(xi, eta, N, d1, d2);
-        for (int j = 0; j < 6; ++j) s_N[tid][j] = (T)N[j];
-    }
     for (int i = tid; i < kChunkRec; i += blockDim.x) s_rec[i] = a.chunks[ch * kChunkRec + i];
-    if (tid < 6) s_te[tid] = a.tri[6 * e + tid];
+    if (tid < 36) {
+        const int g = tid / 6, i = tid % 6;
+        s_row[g][i] = 2 * (2 * (int64_t)a.tri[6 * e + i] + (g & 1)) * a.n2;
+    }
     if (tid < kChunk) {
         const int64_t f = ch * kChunk + tid;
         bool act = f < a.nt;
@@ -166,6 +178,10 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     const int ns = s_rec[0];
     const int rowlen = 2 * ns;
     const int nitems = 6 * rowlen;
+    // item it -> row group g = it / rowlen through a float reciprocal: the
+    // exact quotient (it + 1/2) / rowlen is at least 1/(2 rowlen) > 0.01 away
+    // from an integer for it < 6 rowlen <= 288, far beyond float rounding
+    const float inv_rowlen = 1.0f / (float)rowlen;
     // item it: row group g = 2 op + alpha, slot sl, beta; destination of
     // row i of the test triangle: Z[op][2 te_i + alpha][2 node(sl) + beta].
     // No other workgroup of this launch touches these entries (colour
@@ -176,15 +192,15 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
             const int it = base + tid;
             const bool on = it < nitems;
             const int itc = on ? it : 0;
-            const int g = itc / rowlen, rem = itc % rowlen;
-            const int sl = rem / 2, be = rem % 2, op = g / 2, al = g % 2;
-            const int64_t col = 2 * (int64_t)s_rec[1 + sl] + be;
-            const TS *Z = a.Z[op];
+            const int g = (int)(((float)itc + 0.5f) * inv_rowlen);
+            const int rem = itc - g * rowlen;
+            const int sl = rem >> 1, be = rem & 1, op = g >> 1;
+            const int64_t col = 2 * (2 * (int64_t)s_rec[1 + sl] + be);
+            const TS *Z = a.Z[op] + col;
+            const int first = base + wave * 64;        // wave-uniform item of lane 0
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
-                const int64_t row = 2 * (int64_t)s_te[i] + al;
-                const TS *src = Z + 2 * (row * a.n2 + col);
-                const int first = base + wave * 64;        // wave-uniform item of lane 0
+                const TS *src = Z + s_row[g][i];
                 if constexpr (std::is_same<TS, double>::value) {
                     TS *dst = s_dst + 2 * (i * kItemsMax + first);
                     if (on)
@@ -249,46 +265,37 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
         for (int j = 0; j < 6; ++j) {
             cx<T> acc = {0, 0};
 #pragma unroll
-            for (int q = 0; q < 7; ++q) acc = acc + s_N[q][j] * kv[q];
+            for (int q = 0; q < 7; ++q) acc = acc + (T)n7(q, j) * kv[q];
             s_r1[(fs * 49 + p * 7 + j) * 12 + c] = acc;
         }
     }
-    __syncthreads();
-    // B2: merge by node slot, in place at the slot's first incidence:
-    // Ts[p][slot][c] = sum over the (triangle, local node) incidences
-    for (int it = tid; it < 7 * ns * 12; it += blockDim.x) {
-        const int p = it / (ns * 12), rem = it % (ns * 12), sl = rem / 12, c = rem % 12;
-        cx<T> acc = {0, 0};
-        const int u0 = s_rec[25 + sl];
-        for (int u = u0; u < s_rec[26 + sl]; ++u) {
-            const int fs = s_rec[50 + u] >> 3, loc = s_rec[50 + u] & 7;
-            acc = acc + s_r1[(fs * 49 + p * 7 + loc) * 12 + c];
-        }
-        const int fs0 = s_rec[50 + u0] >> 3, loc0 = s_rec[50 + u0] & 7;
-        s_r1[(fs0 * 49 + p * 7 + loc0) * 12 + c] = acc;
-    }
     __builtin_amdgcn_s_waitcnt(0);             // prefetched destinations have landed
     __syncthreads();
-    // C: test side, lanes along (slot, beta) of one (op, alpha) row group
+    // C: test side, lanes along (slot, beta) of one (op, alpha) row group;
+    // the chunk's triangles that share the slot's node are summed here
+    // (node merge): Ts[p] = sum over incidences (fs, loc) of Tf[fs][p][loc]
     for (int it = tid; it < nitems; it += blockDim.x) {
-        const int g = it / rowlen, rem = it % rowlen;       // g = 2 op + alpha
-        const int sl = rem / 2, be = rem % 2;
-        const int op = g / 2, al = g % 2;
-        const int c = 4 * op + 2 * al + be;
-        const int u0 = s_rec[25 + sl];
-        const int fs0 = s_rec[50 + u0] >> 3, loc0 = s_rec[50 + u0] & 7;
+        const int g = (int)(((float)it + 0.5f) * inv_rowlen);    // g = 2 op + alpha
+        const int rem = it - g * rowlen;
+        const int sl = rem >> 1, be = rem & 1, op = g >> 1;
+        const int c = 2 * g + be;                                // 4 op + 2 alpha + beta
         cx<T> tv[7];
 #pragma unroll
-        for (int p = 0; p < 7; ++p) tv[p] = s_r1[(fs0 * 49 + p * 7 + loc0) * 12 + c];
-        const int64_t col = 2 * (int64_t)s_rec[1 + sl] + be;
-        TS *Z = a.Z[op];
+        for (int p = 0; p < 7; ++p) tv[p] = cx<T>{0, 0};
+        const int u1 = s_rec[26 + sl];
+        for (int u = s_rec[25 + sl]; u < u1; ++u) {
+            const int fl = s_rec[50 + u];
+            const cx<T> *src = s_r1 + ((fl >> 3) * 49 + (fl & 7)) * 12 + c;
+#pragma unroll
+            for (int p = 0; p < 7; ++p) tv[p] = tv[p] + src[p * 84];
+        }
+        TS *Z = a.Z[op] + 2 * (2 * (int64_t)s_rec[1 + sl] + be);
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
             cx<T> acc = {0, 0};
 #pragma unroll
-            for (int p = 0; p < 7; ++p) acc = acc + s_N[p][i] * tv[p];
-            const int64_t row = 2 * (int64_t)s_te[i] + al;
-            TS *dst = Z + 2 * (row * a.n2 + col);
+            for (int p = 0; p < 7; ++p) acc = acc + (T)n7(p, i) * tv[p];
+            TS *dst = Z + s_row[g][i];
             TS ore, oim;
             if constexpr (std::is_same<TS, double>::value) {
                 ore = s_dst[2 * (i * kItemsMax + it)];
