@@ -131,11 +131,39 @@ __host__ __device__ constexpr double n7(int q, int j) {
          : j == 4 ? 4.0 * L1 * L2 : 4.0 * L2 * L0;
 }
 
+// out[j] = sum_q n7(q, j) v[q] through the symmetry of the rule: the three
+// points of an orbit carry the same weight pattern, so with the orbit sums
+// S_a = v1 + v2 + v3, S_b = v4 + v5 + v6 every vertex function is
+// N(centroid) v0 + B_a S_a + B_b S_b plus (A - B) times the value at the
+// orbit point nearest that vertex, and every mid-edge function
+// N(centroid) v0 + E_a S_a + E_b S_b plus (F - E) times the value at the
+// orbit point nearest the opposite vertex (A, B, E, F: the shape-function
+// values at the orbit points).  44 real operations instead of 84.
+template <typename T>
+__host__ __device__ inline void contract7(const cx<T> v[7], cx<T> out[6]) {
+    constexpr double c0v = n7(0, 0), c0e = n7(0, 3);
+    constexpr double Ba = n7(2, 0), Bb = n7(5, 0), Da = n7(1, 0) - Ba, Db = n7(4, 0) - Bb;
+    constexpr double Ea = n7(1, 3), Eb = n7(4, 3), Ga = n7(3, 3) - Ea, Gb = n7(6, 3) - Eb;
+    const cx<T> Sa = v[1] + v[2] + v[3], Sb = v[4] + v[5] + v[6];
+    const cx<T> V = (T)c0v * v[0] + (T)Ba * Sa + (T)Bb * Sb;
+    const cx<T> E = (T)c0e * v[0] + (T)Ea * Sa + (T)Eb * Sb;
+    out[0] = V + (T)Da * v[1] + (T)Db * v[4];
+    out[1] = V + (T)Da * v[2] + (T)Db * v[5];
+    out[2] = V + (T)Da * v[3] + (T)Db * v[6];
+    out[3] = E + (T)Ga * v[3] + (T)Gb * v[6];    // edge 0-1, opposite vertex 2
+    out[4] = E + (T)Ga * v[1] + (T)Gb * v[4];    // edge 1-2, opposite vertex 0
+    out[5] = E + (T)Ga * v[2] + (T)Gb * v[5];    // edge 2-0, opposite vertex 1
+}
+
+// component-major kernel-value buffer: entry (c, lane) at c * kR1Stride + lane;
+// the stride (= 1 mod 16) spreads consecutive components over the banks
+constexpr int kR1Stride = 209;
+
 template <typename T, typename TS, bool DK = false>
 __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     // point-pair kernel values; the trial-side contraction is later written
     // over them in place
-    __shared__ cx<T> s_r1[kPairLanes * 12];
+    __shared__ cx<T> s_r1[12 * kR1Stride];
     // prefetched destination values: plane i (row of the test triangle),
     // item it; FP64 as complex pairs, FP32 as separate real / imaginary planes
     __shared__ __align__(16) TS s_dst[2 * 6 * kItemsMax];
@@ -251,23 +279,20 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
             for (int c = 0; c < 12; ++c) k[c] = cx<T>{0, 0};
         }
 #pragma unroll
-        for (int c = 0; c < 12; ++c) s_r1[tid * 12 + c] = k[c];
+        for (int c = 0; c < 12; ++c) s_r1[c * kR1Stride + tid] = k[c];
     }
     __syncthreads();
-    // B: trial side per triangle, in place: Tf[fs][p][j][c] = sum_q N_j(q) k
-    // over the 7 entries (fs, p, q = 0..6, c) it replaces (j = 0..5)
-    for (int it = tid; it < kChunk * 7 * 12; it += blockDim.x) {
-        const int fs = it / 84, rem = it % 84, p = rem / 12, c = rem % 12;
-        cx<T> kv[7];
+    // B: trial side per triangle, in place: Tf[c][fs][p][j] = sum_q N_j(q) k
+    // over the 7 entries (c, fs, p, q = 0..6) it replaces (j = 0..5)
+    for (int it = tid; it < 12 * kChunk * 7; it += blockDim.x) {
+        const int c = it / (kChunk * 7), fp = it % (kChunk * 7);   // fp = 7 fs + p
+        cx<T> *row = s_r1 + c * kR1Stride + 7 * fp;
+        cx<T> kv[7], tf[6];
 #pragma unroll
-        for (int q = 0; q < 7; ++q) kv[q] = s_r1[(fs * 49 + p * 7 + q) * 12 + c];
+        for (int q = 0; q < 7; ++q) kv[q] = row[q];
+        contract7(kv, tf);
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            cx<T> acc = {0, 0};
-#pragma unroll
-            for (int q = 0; q < 7; ++q) acc = acc + (T)n7(q, j) * kv[q];
-            s_r1[(fs * 49 + p * 7 + j) * 12 + c] = acc;
-        }
+        for (int j = 0; j < 6; ++j) row[j] = tf[j];
     }
     __builtin_amdgcn_s_waitcnt(0);             // prefetched destinations have landed
     __syncthreads();
@@ -285,16 +310,16 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
         const int u1 = s_rec[26 + sl];
         for (int u = s_rec[25 + sl]; u < u1; ++u) {
             const int fl = s_rec[50 + u];
-            const cx<T> *src = s_r1 + ((fl >> 3) * 49 + (fl & 7)) * 12 + c;
+            const cx<T> *src = s_r1 + c * kR1Stride + (fl >> 3) * 49 + (fl & 7);
 #pragma unroll
-            for (int p = 0; p < 7; ++p) tv[p] = tv[p] + src[p * 84];
+            for (int p = 0; p < 7; ++p) tv[p] = tv[p] + src[7 * p];
         }
         TS *Z = a.Z[op] + 2 * (2 * (int64_t)s_rec[1 + sl] + be);
+        cx<T> out[6];
+        contract7(tv, out);
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            cx<T> acc = {0, 0};
-#pragma unroll
-            for (int p = 0; p < 7; ++p) acc = acc + (T)n7(p, i) * tv[p];
+            const cx<T> acc = out[i];
             TS *dst = Z + s_row[g][i];
             TS ore, oim;
             if constexpr (std::is_same<TS, double>::value) {
