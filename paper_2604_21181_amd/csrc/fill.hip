@@ -96,9 +96,26 @@ struct RegArgs {
     int mode;               // 0: every regular pair in T; 1: pairs closer
                             // than near_r in FP64, the others in T
     unsigned long long *near_count;
-    const KernelConst *K;   // device copy (uniform loads)
+    const KernelConst *K;   // device copy, staged in LDS by every workgroup
     TS *Z[3];
 };
+
+// Copy the kernel constants (a few hundred doubles) into LDS; every use
+// after the next barrier is a uniform LDS read issued where it is needed.
+__device__ __forceinline__ void stage_kconst(const KernelConst *src, KernelConst *dst, int tid, int nthr) {
+    constexpr int nw = (int)(sizeof(KernelConst) / sizeof(double));
+    static_assert(sizeof(KernelConst) % sizeof(double) == 0, "KernelConst is a block of doubles");
+    const double *s = (const double *)src;
+    double *d = (double *)dst;
+    for (int i = tid; i < nw; i += nthr) d[i] = s[i];
+}
+
+// operator block op of the argument block, selected without a runtime index
+// into the argument struct (which would force a private copy of it)
+template <typename TS>
+__device__ __forceinline__ TS *zblock(TS *const (&Z)[3], int op) {
+    return op == 0 ? Z[0] : (op == 1 ? Z[1] : Z[2]);
+}
 
 template <typename T>
 __device__ inline vec3<T> qload(const T *qp, int64_t nq, int f, int64_t i) {
@@ -164,13 +181,20 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     // point-pair kernel values; the trial-side contraction is later written
     // over them in place
     __shared__ cx<T> s_r1[12 * kR1Stride];
-    // prefetched destination values: plane i (row of the test triangle),
-    // item it; FP64 as complex pairs, FP32 as separate real / imaginary planes
-    __shared__ __align__(16) TS s_dst[2 * 6 * kItemsMax];
+    // prefetched destination values.  FP32: in LDS by direct global-to-LDS
+    // loads, plane (i, re / im) (i: row of the test triangle), item it.
+    // FP64: in registers (pre), which keeps the LDS of a workgroup low enough
+    // for three workgroups per compute unit.
+    constexpr bool kF64 = std::is_same<TS, double>::value;
+    __shared__ __align__(16) TS s_dst[kF64 ? 1 : 2 * 6 * kItemsMax];
+    constexpr int kRounds = (kItemsMax + 255) / 256;
+    double2 pre[kF64 ? kRounds : 1][6];
     __shared__ int64_t s_row[6][6];    // [2 op + alpha][i]: offset of row 2 te_i + alpha
     __shared__ int32_t s_rec[kChunkRec];
     __shared__ int s_act[kChunk];      // 0 skip, 1 compute in T, 2 in FP64
+    __shared__ KernelConst s_K;
     const int tid = threadIdx.x;
+    stage_kconst(a.K, &s_K, tid, blockDim.x);
     const int64_t tile = xcd_remap(blockIdx.x, a.total);
     const int64_t e = a.te_list[tile / a.n_ch];
     const int64_t ch = a.ch_list[tile % a.n_ch];
@@ -198,6 +222,26 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
         }
         s_act[tid] = kind;
     }
+    // point data of this lane's pair, loaded before the barrier so that the
+    // loads overlap those of the chunk record
+    const int64_t nq = a.nt * kQP;
+    const int fsl = tid / 49, pl = (tid % 49) / 7, ql = tid % 7;
+    const int64_t ix = e * kQP + pl, iy = (ch * kChunk + fsl) * kQP + ql;
+    vec3<T> x = {0, 0, 0}, n = {0, 0, 0}, y = {0, 0, 0};
+    vec3<T> ta[2] = {x, x}, sa[2] = {x, x}, tb[2] = {x, x};
+    T ww = 0;
+    if (tid < kPairLanes && ch * kChunk + fsl < a.nt) {
+        x = qload(a.qp, nq, QX, ix);
+        n = qload(a.qp, nq, QN, ix);
+        ta[0] = qload(a.qp, nq, QT1, ix);
+        ta[1] = qload(a.qp, nq, QT2, ix);
+        sa[0] = qload(a.qp, nq, QS1, ix);
+        sa[1] = qload(a.qp, nq, QS2, ix);
+        y = qload(a.qp, nq, QX, iy);
+        tb[0] = qload(a.qp, nq, QT1, iy);
+        tb[1] = qload(a.qp, nq, QT2, iy);
+        ww = a.qp[(int64_t)QW * nq + ix] * a.qp[(int64_t)QW * nq + iy];
+    }
     __syncthreads();
     int any = 0;
 #pragma unroll
@@ -216,24 +260,22 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     // classes), and earlier launches completed in stream order.
     {
         const int wave = tid / 64;
-        for (int base = 0; base < nitems; base += 256) {
-            const int it = base + tid;
+#pragma unroll
+        for (int k = 0; k < kRounds; ++k) {
+            const int base = 256 * k, it = base + tid;
             const bool on = it < nitems;
             const int itc = on ? it : 0;
             const int g = (int)(((float)itc + 0.5f) * inv_rowlen);
             const int rem = itc - g * rowlen;
             const int sl = rem >> 1, be = rem & 1, op = g >> 1;
             const int64_t col = 2 * (2 * (int64_t)s_rec[1 + sl] + be);
-            const TS *Z = a.Z[op] + col;
+            const TS *Z = zblock(a.Z, op) + col;
             const int first = base + wave * 64;        // wave-uniform item of lane 0
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
                 const TS *src = Z + s_row[g][i];
-                if constexpr (std::is_same<TS, double>::value) {
-                    TS *dst = s_dst + 2 * (i * kItemsMax + first);
-                    if (on)
-                        __builtin_amdgcn_global_load_lds((const void *)src,
-                                                         (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+                if constexpr (kF64) {
+                    if (on) pre[k][i] = *(const double2 *)src;
                 } else {
                     TS *dre = s_dst + (2 * i) * kItemsMax + first, *dim = s_dst + (2 * i + 1) * kItemsMax + first;
                     if (on) {
@@ -246,21 +288,12 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
             }
         }
     }
-    const int64_t nq = a.nt * kQP;
     // A: kernel values
     if (tid < kPairLanes) {
-        const int fs = tid / 49, r = tid % 49, p = r / 7, q = r % 7;
         cx<T> k[12];
-        const int kind = s_act[fs];
-        const int64_t ix = e * kQP + p, iy = (ch * kChunk + fs) * kQP + q;
+        const int kind = s_act[fsl];
         if (kind == 1) {
-            const vec3<T> x = qload(a.qp, nq, QX, ix), n = qload(a.qp, nq, QN, ix);
-            const vec3<T> ta[2] = {qload(a.qp, nq, QT1, ix), qload(a.qp, nq, QT2, ix)};
-            const vec3<T> sa[2] = {qload(a.qp, nq, QS1, ix), qload(a.qp, nq, QS2, ix)};
-            const vec3<T> y = qload(a.qp, nq, QX, iy);
-            const vec3<T> tb[2] = {qload(a.qp, nq, QT1, iy), qload(a.qp, nq, QT2, iy)};
-            const T ww = a.qp[(int64_t)QW * nq + ix] * a.qp[(int64_t)QW * nq + iy];
-            kappa12<T, DK>(*a.K, x, n, ta, sa, y, tb, ww, k);
+            kappa12<T, DK>(s_K, x, n, ta, sa, y, tb, ww, k);
         } else if (!std::is_same<T, double>::value && kind == 2) {
             // near pair: FP64 kernel differences (cancellation), then rounded
             const double *q64 = a.qp64;
@@ -271,7 +304,7 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
             const dvec3 tb[2] = {qload(q64, nq, QT1, iy), qload(q64, nq, QT2, iy)};
             const double ww = q64[(int64_t)QW * nq + ix] * q64[(int64_t)QW * nq + iy];
             cx<double> kd[12];
-            kappa12<double, DK>(*a.K, x, n, ta, sa, y, tb, ww, kd);
+            kappa12<double, DK>(s_K, x, n, ta, sa, y, tb, ww, kd);
 #pragma unroll
             for (int c = 0; c < 12; ++c) k[c] = cx<T>{(T)kd[c].re, (T)kd[c].im};
         } else {
@@ -294,12 +327,15 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
 #pragma unroll
         for (int j = 0; j < 6; ++j) row[j] = tf[j];
     }
-    __builtin_amdgcn_s_waitcnt(0);             // prefetched destinations have landed
+    __builtin_amdgcn_s_waitcnt(0);             // prefetched destinations have landed (FP32)
     __syncthreads();
     // C: test side, lanes along (slot, beta) of one (op, alpha) row group;
     // the chunk's triangles that share the slot's node are summed here
     // (node merge): Ts[p] = sum over incidences (fs, loc) of Tf[fs][p][loc]
-    for (int it = tid; it < nitems; it += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k) {
+        const int it = 256 * k + tid;
+        if (it >= nitems) break;
         const int g = (int)(((float)it + 0.5f) * inv_rowlen);    // g = 2 op + alpha
         const int rem = it - g * rowlen;
         const int sl = rem >> 1, be = rem & 1, op = g >> 1;
@@ -314,7 +350,7 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
 #pragma unroll
             for (int p = 0; p < 7; ++p) tv[p] = tv[p] + src[7 * p];
         }
-        TS *Z = a.Z[op] + 2 * (2 * (int64_t)s_rec[1 + sl] + be);
+        TS *Z = zblock(a.Z, op) + 2 * (2 * (int64_t)s_rec[1 + sl] + be);
         cx<T> out[6];
         contract7(tv, out);
 #pragma unroll
@@ -322,9 +358,9 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
             const cx<T> acc = out[i];
             TS *dst = Z + s_row[g][i];
             TS ore, oim;
-            if constexpr (std::is_same<TS, double>::value) {
-                ore = s_dst[2 * (i * kItemsMax + it)];
-                oim = s_dst[2 * (i * kItemsMax + it) + 1];
+            if constexpr (kF64) {
+                ore = pre[k][i].x;
+                oim = pre[k][i].y;
             } else {
                 ore = s_dst[(2 * i) * kItemsMax + it];
                 oim = s_dst[(2 * i + 1) * kItemsMax + it];
@@ -346,7 +382,7 @@ struct SsqArgs {
     const double *xyz, *frames;
     int order;
     double glx[kMaxSSQ], glw[kMaxSSQ];   // Gauss-Legendre on [0,1]
-    const KernelConst *K;   // device copy (uniform loads)
+    const KernelConst *K;   // device copy
     TS *Z[3];
 };
 
@@ -361,7 +397,7 @@ constexpr int kStreams = 5;
 constexpr int kPtStride = 37;   // 24 kernel reals, N_i(x), N_j(y); padded
 
 template <typename TS, bool DK = false>
-__global__ __launch_bounds__(kSsqThreads) void k_ssq(SsqArgs<TS> a) {
+__global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_ssq(SsqArgs<TS> a) {
     __shared__ double s_pt[kSsqThreads * kPtStride];
     static_assert(kStreams * 36 * 24 <= kSsqThreads * kPtStride, "reduction buffer");
     const int tid = threadIdx.x;
@@ -442,7 +478,7 @@ __global__ __launch_bounds__(kSsqThreads) void k_ssq(SsqArgs<TS> a) {
         const int i = k / 6, j = k % 6;
         const int op = cc / 4, al = (cc / 2) % 2, be = cc % 2;
         const int64_t row = 2 * (int64_t)te[i] + al, col = 2 * (int64_t)tf[j] + be;
-        TS *dst = a.Z[op] + 2 * (row * a.n2 + col);
+        TS *dst = zblock(a.Z, op) + 2 * (row * a.n2 + col);
         atomic_add(dst, re);
         atomic_add(dst + 1, im);
     }
