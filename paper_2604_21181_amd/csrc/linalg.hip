@@ -28,9 +28,16 @@ __device__ inline double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------- GEMV --
-// One wavefront per stored row; lanes stream the row with 16-byte loads.
-// The c64 variant loads two entries per lane per step and accumulates in
-// FP64.
+// One wavefront per R consecutive stored rows of one block; lanes stream
+// the rows with 16-byte loads, and every load of the right-hand vector(s)
+// (FP64, from L2) serves all R rows.  The c64 variant loads two entries per
+// lane and row per step and accumulates in FP64; with eight rows per
+// wavefront its vector loads no longer outweigh the matrix stream (measured
+// per product on the 1280-triangle sphere: 158 us at one row, 118 us at
+// eight, 440 us at sixteen; c128: 221 us at one row, slower at two).
+template <typename TS> constexpr int gemv_rows_per_wave();
+template <> constexpr int gemv_rows_per_wave<double2>() { return 1; }
+template <> constexpr int gemv_rows_per_wave<float2>() { return 8; }
 typedef double nd2 __attribute__((ext_vector_type(2)));
 typedef float nf4 __attribute__((ext_vector_type(4)));
 // streaming loads of the matrix: each entry is used exactly once per product
@@ -43,104 +50,101 @@ __device__ inline float4 ntload(const float4 *p) {
     return {v.x, v.y, v.z, v.w};
 }
 
-template <int NV>
-__device__ inline void row_dots_c128(const double2 *__restrict__ row, int64_t n,
-                                     const double2 *const xs[NV], double2 out[NV]) {
+// re/im[k][v] += row r0 + k of K (row length n) . xs[v], for k < nr
+// (nr is uniform over the wavefront)
+template <int NV, int R>
+__device__ inline void rows_dots(const double2 *__restrict__ K, int64_t n, int64_t r0, int nr,
+                                 const double2 *const xs[NV], double re[R][NV], double im[R][NV]) {
     const int lane = threadIdx.x % kW;
-    double re[NV], im[NV];
+    const double2 *row[R];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) re[v] = im[v] = 0.0;
-    int64_t c = lane;
-    for (; c + 3 * kW < n; c += 4 * kW) {
-        double2 z[4];
+    for (int k = 0; k < R; ++k) row[k] = K + (r0 + (k < nr ? k : 0)) * n;
+#pragma unroll 4
+    for (int64_t c = lane; c < n; c += kW) {
+        double2 x[NV];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) z[u] = ntload(row + c + u * kW);
+        for (int v = 0; v < NV; ++v) x[v] = xs[v][c];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int k = 0; k < R; ++k) {
+            if (k >= nr) break;
+            const double2 z = ntload(row[k] + c);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double2 x = xs[v][c + u * kW];
-                re[v] += z[u].x * x.x - z[u].y * x.y;
-                im[v] += z[u].x * x.y + z[u].y * x.x;
+                re[k][v] += z.x * x[v].x - z.y * x[v].y;
+                im[k][v] += z.x * x[v].y + z.y * x[v].x;
             }
-    }
-    for (; c < n; c += kW) {
-        const double2 z = ntload(row + c);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double2 x = xs[v][c];
-            re[v] += z.x * x.x - z.y * x.y;
-            im[v] += z.x * x.y + z.y * x.x;
         }
     }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = {wave_sum(re[v]), wave_sum(im[v])};
 }
 
-template <int NV>
-__device__ inline void row_dots_c64(const float2 *__restrict__ row, int64_t n,
-                                    const double2 *const xs[NV], double2 out[NV]) {
+template <int NV, int R>
+__device__ inline void rows_dots(const float2 *__restrict__ K, int64_t n, int64_t r0, int nr,
+                                 const double2 *const xs[NV], double re[R][NV], double im[R][NV]) {
     const int lane = threadIdx.x % kW;
-    double re[NV], im[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) re[v] = im[v] = 0.0;
-    const float4 *r4 = reinterpret_cast<const float4 *>(row);
     const int64_t n4 = n / 2;   // n is even (2 unknowns per node)
-    int64_t c = lane;
-    for (; c + kW < n4; c += 2 * kW) {
-        const float4 z0 = ntload(r4 + c);
-        const float4 z1 = ntload(r4 + c + kW);
-        const float4 zz[2] = {z0, z1};
+    const float4 *row[R];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int64_t col = 2 * (c + u * kW);
+    for (int k = 0; k < R; ++k)
+        row[k] = reinterpret_cast<const float4 *>(K + (r0 + (k < nr ? k : 0)) * n);
+#pragma unroll 2
+    for (int64_t c = lane; c < n4; c += kW) {
+        double2 x0[NV], x1[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { x0[v] = xs[v][2 * c]; x1[v] = xs[v][2 * c + 1]; }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (k >= nr) break;
+            const float4 z = ntload(row[k] + c);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double2 x0 = xs[v][col], x1 = xs[v][col + 1];
-                re[v] += (double)zz[u].x * x0.x - (double)zz[u].y * x0.y +
-                         (double)zz[u].z * x1.x - (double)zz[u].w * x1.y;
-                im[v] += (double)zz[u].x * x0.y + (double)zz[u].y * x0.x +
-                         (double)zz[u].z * x1.y + (double)zz[u].w * x1.x;
+                re[k][v] += (double)z.x * x0[v].x - (double)z.y * x0[v].y +
+                            (double)z.z * x1[v].x - (double)z.w * x1[v].y;
+                im[k][v] += (double)z.x * x0[v].y + (double)z.y * x0[v].x +
+                            (double)z.z * x1[v].y + (double)z.w * x1[v].x;
             }
         }
     }
-    for (; c < n4; c += kW) {
-        const float4 z = ntload(r4 + c);
-        const int64_t col = 2 * c;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double2 x0 = xs[v][col], x1 = xs[v][col + 1];
-            re[v] += (double)z.x * x0.x - (double)z.y * x0.y + (double)z.z * x1.x - (double)z.w * x1.y;
-            im[v] += (double)z.x * x0.y + (double)z.y * x0.x + (double)z.z * x1.y + (double)z.w * x1.x;
-        }
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = {wave_sum(re[v]), wave_sum(im[v])};
 }
 
 // t[0] = K1 x_j, t[1] = K1 x_m, t[2] = K2e x_m, t[3] = K2m x_j (each n2).
+template <typename TS, int NV, int R>
+__device__ inline void gemv_rows(const TS *K, int64_t n2, int64_t r0, int nr,
+                                 const double2 *const xs[NV], double2 *const ts[NV]) {
+    double re[R][NV], im[R][NV];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) re[k][v] = im[k][v] = 0.0;
+    rows_dots<NV, R>(K, n2, r0, nr, xs, re, im);
+    const int lane = threadIdx.x % kW;
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double2 o = {wave_sum(re[k][v]), wave_sum(im[k][v])};
+            if (lane == 0 && k < nr) ts[v][r0 + k] = o;
+        }
+}
+
 template <typename TS>
 __global__ __launch_bounds__(256) void k_gemv3(int64_t n2, const TS *K1, const TS *K2e,
                                                const TS *K2m, const double2 *xj,
                                                const double2 *xm, double2 *t) {
+    constexpr int R = gemv_rows_per_wave<TS>();
+    const int64_t nwr = (n2 + R - 1) / R;                    // wavefronts per block
     const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kW;
-    if (wid >= 3 * n2) return;
-    const int blk = (int)(wid / n2);
-    const int64_t r = wid % n2;
-    const int lane = threadIdx.x % kW;
+    if (wid >= 3 * nwr) return;
+    const int blk = (int)(wid / nwr);
+    const int64_t r0 = (wid % nwr) * R;
+    const int nr = (int)(n2 - r0 < R ? n2 - r0 : R);
     if (blk == 0) {
         const double2 *xs[2] = {xj, xm};
-        double2 o[2];
-        if constexpr (std::is_same<TS, double2>::value) row_dots_c128<2>((const double2 *)K1 + r * n2, n2, xs, o);
-        else row_dots_c64<2>((const float2 *)K1 + r * n2, n2, xs, o);
-        if (lane == 0) { t[r] = o[0]; t[n2 + r] = o[1]; }
+        double2 *ts[2] = {t, t + n2};
+        gemv_rows<TS, 2, R>(K1, n2, r0, nr, xs, ts);
     } else {
-        const TS *K = blk == 1 ? K2e : K2m;
         const double2 *xs[1] = {blk == 1 ? xm : xj};
-        double2 o[1];
-        if constexpr (std::is_same<TS, double2>::value) row_dots_c128<1>((const double2 *)K + r * n2, n2, xs, o);
-        else row_dots_c64<1>((const float2 *)K + r * n2, n2, xs, o);
-        if (lane == 0) t[(1 + blk) * n2 + r] = o[0];
+        double2 *ts[1] = {t + (1 + blk) * n2};
+        gemv_rows<TS, 1, R>(blk == 1 ? K2e : K2m, n2, r0, nr, xs, ts);
     }
 }
 
@@ -170,15 +174,14 @@ static Coef coef_of(const mbem_op *op) { return {op->iw, op->ce, op->cm}; }
 int matvec_run(const mbem_op *op, const double2 *x, double2 *y, double2 *tmp, hipStream_t s,
                hipEvent_t after_gemv) {
     const int64_t n2 = op->n2;
-    const int64_t waves = 3 * n2;
-    const unsigned blocks = (unsigned)((waves * kW + 255) / 256);
+    auto blocks = [n2](int R) { return (unsigned)((3 * ((n2 + R - 1) / R) * kW + 255) / 256); };
     if (op->prec == MBEM_FP64)
-        hipLaunchKernelGGL((k_gemv3<double2>), dim3(blocks), dim3(256), 0, s, n2,
-                           (const double2 *)op->K[0], (const double2 *)op->K[1],
+        hipLaunchKernelGGL((k_gemv3<double2>), dim3(blocks(gemv_rows_per_wave<double2>())), dim3(256), 0, s,
+                           n2, (const double2 *)op->K[0], (const double2 *)op->K[1],
                            (const double2 *)op->K[2], x, x + n2, tmp);
     else
-        hipLaunchKernelGGL((k_gemv3<float2>), dim3(blocks), dim3(256), 0, s, n2,
-                           (const float2 *)op->K[0], (const float2 *)op->K[1],
+        hipLaunchKernelGGL((k_gemv3<float2>), dim3(blocks(gemv_rows_per_wave<float2>())), dim3(256), 0, s,
+                           n2, (const float2 *)op->K[0], (const float2 *)op->K[1],
                            (const float2 *)op->K[2], x, x + n2, tmp);
     MBEM_HIP(hipGetLastError());
     if (after_gemv) MBEM_HIP(hipEventRecord(after_gemv, s));
