@@ -74,6 +74,8 @@ static void op_free_device(mbem_op *op) {
     dfree(op->d_lu);
     dfree(op->d_work);
     dfree(op->d_kconst);
+    if (op->h_pin) (void)hipHostFree(op->h_pin);
+    op->h_pin = nullptr;
 }
 
 // ---------------------------------------------------------------- GMRES --
@@ -87,29 +89,34 @@ struct Gmres {
     double2 *V, *w, *z, *tmp, *hdev;
     double2 *tpart = nullptr;   // partial sums of the transposed product
     double *ndev;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // bracket every matvec launch
+    double2 *hpin[2] = {nullptr, nullptr};     // pinned copies of Hessenberg columns
+    // per column slot (two in flight): bracket the matvec, mark the column copy
+    hipEvent_t ev0[2] = {nullptr, nullptr}, ev1[2] = {nullptr, nullptr}, evh[2] = {nullptr, nullptr};
     double t_matvec = 0.0;
     int n_matvec = 0;
     ~Gmres() {
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
+        for (int i = 0; i < 2; ++i) {
+            if (ev0[i]) (void)hipEventDestroy(ev0[i]);
+            if (ev1[i]) (void)hipEventDestroy(ev1[i]);
+            if (evh[i]) (void)hipEventDestroy(evh[i]);
+        }
         if (tpart) (void)hipFree(tpart);
     }
     int apply(const double2 *x, double2 *y) {   // y = Z x or Z^T x
         return trans ? matvec_t_run(op, x, y, tpart, s) : matvec_run(op, x, y, tmp, s);
     }
-    int timed_matvec(const double2 *x, double2 *y) {
-        (void)hipEventRecord(ev0, s);
+    int timed_matvec(const double2 *x, double2 *y, int slot) {
+        (void)hipEventRecord(ev0[slot], s);
         if (trans) {
             MBEM_TRY(matvec_t_run(op, x, y, tpart, s));
-            MBEM_HIP(hipEventRecord(ev1, s));
+            MBEM_HIP(hipEventRecord(ev1[slot], s));
             return MBEM_OK;
         }
-        return matvec_run(op, x, y, tmp, s, ev1);   // ev1 right after the GEMV
+        return matvec_run(op, x, y, tmp, s, ev1[slot]);   // ev1 right after the GEMV
     }
-    void collect() {   // after a synchronisation of the stream
+    void collect(int slot) {   // after the slot's column copy has completed
         float t = 0.f;
-        if (hipEventElapsedTime(&t, ev0, ev1) == hipSuccess) { t_matvec += t; ++n_matvec; }
+        if (hipEventElapsedTime(&t, ev0[slot], ev1[slot]) == hipSuccess) { t_matvec += t; ++n_matvec; }
     }
 };
 
@@ -118,23 +125,38 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
     g.s = s;
     g.N = 2 * op->n2;
     g.m = maxit;
-    const size_t need = (size_t)(maxit + 1) * g.N + 2 * g.N + 2 * op->n2 + 4 * op->n2 + 2 * (maxit + 2) + 1;
+    // V, w, z, matvec partials (4 n2), two Hessenberg column slots, a norm
+    const size_t hslots = 2 * (size_t)(2 * (maxit + 1) + 1);
+    const size_t need = (size_t)(maxit + 1) * g.N + 2 * g.N + 4 * op->n2 + hslots + 1;
+    mbem_op *mop = const_cast<mbem_op *>(op);
     if (op->work_elems < need) {
-        mbem_op *mop = const_cast<mbem_op *>(op);
         dfree(mop->d_work);
         mop->d_work = nullptr;
         mop->work_elems = 0;
         MBEM_TRY(dalloc(&mop->d_work, need));
         mop->work_elems = need;
     }
+    const size_t pin = 2 * (size_t)(2 * (maxit + 1) + 1);
+    if (op->pin_elems < pin) {
+        if (mop->h_pin) (void)hipHostFree(mop->h_pin);
+        mop->h_pin = nullptr;
+        mop->pin_elems = 0;
+        MBEM_HIP(hipHostMalloc((void **)&mop->h_pin, sizeof(double2) * pin, hipHostMallocDefault));
+        mop->pin_elems = pin;
+    }
+    g.hpin[0] = op->h_pin;
+    g.hpin[1] = op->h_pin + pin / 2;
     g.V = op->d_work;
     g.w = g.V + (size_t)(maxit + 1) * g.N;
     g.z = g.w + g.N;
     g.tmp = g.z + g.N;                 // 4 n2 for the matvec partials
-    g.hdev = g.tmp + 4 * op->n2;       // 2 (maxit + 2)
-    g.ndev = (double *)(g.hdev + 2 * (maxit + 2));
-    if (!g.ev0) MBEM_HIP(hipEventCreate(&g.ev0));
-    if (!g.ev1) MBEM_HIP(hipEventCreate(&g.ev1));
+    g.hdev = g.tmp + 4 * op->n2;       // two column slots of 2 (maxit + 1) + 1
+    g.ndev = (double *)(g.hdev + hslots);
+    for (int i = 0; i < 2; ++i) {
+        if (!g.ev0[i]) MBEM_HIP(hipEventCreate(&g.ev0[i]));
+        if (!g.ev1[i]) MBEM_HIP(hipEventCreate(&g.ev1[i]));
+        if (!g.evh[i]) MBEM_HIP(hipEventCreateWithFlags(&g.evh[i], hipEventDisableTiming));
+    }
     if (g.trans && !g.tpart) MBEM_TRY(dalloc(&g.tpart, (size_t)matvec_t_work(op)));
     return MBEM_OK;
 }
@@ -143,6 +165,11 @@ static inline std::complex<double> C(double2 v) { return {v.x, v.y}; }
 
 // Right-preconditioned GMRES on Z P^-1, x0 = 0, CGS2 Arnoldi in FP64.
 // Solves Z x = b to |r_k| <= tol |b| (Arnoldi estimate).  x, b device.
+// The host lags the device by one column: Arnoldi step k (preconditioner,
+// matvec, two projection passes, norm, and V_{k+1} = w / h_{k+1,k} with the
+// norm read on the device) is queued before the host waits for column k-1
+// and applies its Givens rotation, so the stream never drains between
+// steps.  When column k-1 meets the tolerance the queued step k is unused.
 static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *iters,
                        double *est) {
     const hipStream_t s = g.s;
@@ -160,30 +187,38 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
     MBEM_TRY(vec_scale_copy(g.V, b, double2{1.0 / beta, 0.0}, N, s));
     const int m = g.m;
     std::vector<std::complex<double>> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1);
-    std::vector<double2> hbuf(2 * (m + 1) + 1);
     gv[0] = beta;
-    int k = 0;
-    double res = 1.0;
-    bool conv = false;
-    for (k = 0; k < m; ++k) {
+    // queue Arnoldi step k; its column lands in hpin[k % 2]
+    auto enqueue = [&](int k) -> int {
+        const int slot = k & 1;
         double2 *vk = g.V + (size_t)k * N;
+        double2 *hk = g.hdev + (size_t)slot * (2 * (m + 1) + 1);
         MBEM_TRY(mbj_apply_run(g.op, vk, g.z, s, g.trans));
-        MBEM_TRY(g.timed_matvec(g.z, g.w));
-        MBEM_TRY(vec_dots(g.V, N, k + 1, g.w, N, g.hdev, s));
-        MBEM_TRY(vec_update(g.w, g.V, N, k + 1, g.hdev, N, s));
-        MBEM_TRY(vec_dots(g.V, N, k + 1, g.w, N, g.hdev + (k + 1), s));
-        MBEM_TRY(vec_update(g.w, g.V, N, k + 1, g.hdev + (k + 1), N, s));
-        // the norm lands right after the 2(k+1) projections: one copy back
-        MBEM_TRY(vec_norm2(g.w, N, (double *)(g.hdev + 2 * (k + 1)), s));
-        MBEM_HIP(hipMemcpyAsync(hbuf.data(), g.hdev, sizeof(double2) * (2 * (k + 1) + 1),
+        MBEM_TRY(g.timed_matvec(g.z, g.w, slot));
+        MBEM_TRY(vec_dots(g.V, N, k + 1, g.w, N, hk, s));
+        MBEM_TRY(vec_update(g.w, g.V, N, k + 1, hk, N, s));
+        MBEM_TRY(vec_dots(g.V, N, k + 1, g.w, N, hk + (k + 1), s));
+        MBEM_TRY(vec_update(g.w, g.V, N, k + 1, hk + (k + 1), N, s));
+        double *hn = (double *)(hk + 2 * (k + 1));
+        MBEM_TRY(vec_norm2(g.w, N, hn, s));
+        MBEM_HIP(hipMemcpyAsync(g.hpin[slot], hk, sizeof(double2) * (2 * (k + 1) + 1),
                                 hipMemcpyDeviceToHost, s));
-        MBEM_HIP(hipStreamSynchronize(s));
-        const double hn = hbuf[2 * (k + 1)].x;
-        g.collect();
+        MBEM_HIP(hipEventRecord(g.evh[slot], s));
+        if (k + 1 <= m) MBEM_TRY(vec_scale_inv_norm(g.V + (size_t)(k + 1) * N, g.w, hn, N, s));
+        return MBEM_OK;
+    };
+    double res = 1.0;
+    bool conv = false, breakdown = false;
+    // wait for column k and fold it into the QR factorisation of H
+    auto process = [&](int k) -> int {
+        const int slot = k & 1;
+        MBEM_HIP(hipEventSynchronize(g.evh[slot]));
+        g.collect(slot);
+        const double2 *hb = g.hpin[slot];
+        const double hn = hb[2 * (k + 1)].x;
         auto Hc = [&](int i) -> std::complex<double> & { return H[(size_t)i * m + k]; };
-        for (int i = 0; i <= k; ++i) Hc(i) = C(hbuf[i]) + C(hbuf[k + 1 + i]);
+        for (int i = 0; i <= k; ++i) Hc(i) = C(hb[i]) + C(hb[k + 1 + i]);
         Hc(k + 1) = hn;
-        if (hn > 0) MBEM_TRY(vec_scale_copy(g.V + (size_t)(k + 1) * N, g.w, double2{1.0 / hn, 0.0}, N, s));
         for (int i = 0; i < k; ++i) {
             const std::complex<double> t = cs[i] * Hc(i) + sn[i] * Hc(i + 1);
             Hc(i + 1) = -std::conj(sn[i]) * Hc(i) + cs[i] * Hc(i + 1);
@@ -199,8 +234,24 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
         gv[k + 1] = -std::conj(sn[k]) * gv[k];
         gv[k] = cs[k] * gv[k];
         res = std::abs(gv[k + 1]) / beta;
-        if (res <= tol || hn == 0) { ++k; conv = true; break; }
+        breakdown = hn == 0;
+        conv = res <= tol || breakdown;
+        return MBEM_OK;
+    };
+    int k = 0;       // columns folded into H
+    for (int q = 0; q < m; ++q) {
+        MBEM_TRY(enqueue(q));
+        if (q >= 1) {
+            MBEM_TRY(process(q - 1));
+            k = q;
+            if (conv) break;
+        }
     }
+    if (!conv) {
+        MBEM_TRY(process(m - 1));
+        k = m;
+    }
+    conv = res <= tol || breakdown;
     // back substitution H y = g
     std::vector<std::complex<double>> y(k);
     for (int i = k - 1; i >= 0; --i) {

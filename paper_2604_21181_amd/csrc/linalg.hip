@@ -633,6 +633,13 @@ __global__ void k_scale_copy(double2 *dst, const double2 *src, double2 a, int64_
     if (i < n) dst[i] = cmul(a, src[i]);
 }
 
+__global__ void k_scale_inv_norm(double2 *dst, const double2 *src, const double *nrm, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double h = *nrm, a = h > 0 ? 1.0 / h : 0.0;
+    dst[i] = {a * src[i].x, a * src[i].y};
+}
+
 __global__ void k_axpy(double2 *y, const double2 *x, double2 a, int64_t n) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) y[i] = cadd(y[i], cmul(a, x[i]));
@@ -662,6 +669,12 @@ int vec_norm2(const double2 *v, int64_t n, double *out, hipStream_t s) {
 }
 int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_scale_copy, dim3(nblk(n)), dim3(256), 0, s, dst, src, a, n);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+int vec_scale_inv_norm(double2 *dst, const double2 *src, const double *nrm_dev, int64_t n,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_inv_norm, dim3(nblk(n)), dim3(256), 0, s, dst, src, nrm_dev, n);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }

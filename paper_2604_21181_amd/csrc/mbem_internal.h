@@ -110,6 +110,8 @@ struct mbem_op {
     // solver workspace
     double2 *d_work = nullptr;
     size_t work_elems = 0;
+    double2 *h_pin = nullptr;       // pinned host copies of Hessenberg columns
+    size_t pin_elems = 0;
     // multi-right-hand-side solve: complex64 copy of an FP64 operator's
     // blocks for the FP32 GEMM
     void *K32[3] = {nullptr, nullptr, nullptr};
@@ -159,6 +161,9 @@ int vec_dots(const double2 *V, int64_t ldv, int k, const double2 *w,
 int vec_update(double2 *w, const double2 *V, int64_t ldv, int k,
                const double2 *h_dev, int64_t n, hipStream_t s);
 int vec_norm2(const double2 *v, int64_t n, double *out_dev, hipStream_t s);
+// dst = src / *nrm_dev (0 where the norm is 0), the norm read on the device
+int vec_scale_inv_norm(double2 *dst, const double2 *src, const double *nrm_dev, int64_t n,
+                       hipStream_t s);
 int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n,
                    hipStream_t s);
 int vec_axpy(double2 *y, const double2 *x, double2 a, int64_t n,
