@@ -89,6 +89,8 @@ struct Gmres {
     double2 *V, *w, *z, *tmp, *hdev;
     double2 *tpart = nullptr;   // partial sums of the transposed product
     double *ndev;
+    double2 *ppart;             // per-chunk projection partials, (m + 1) x chunks
+    double *npart;              // per-chunk parts of |w|^2
     double2 *hpin[2] = {nullptr, nullptr};     // pinned copies of Hessenberg columns
     // per column slot (two in flight): bracket the matvec, mark the column copy
     hipEvent_t ev0[2] = {nullptr, nullptr}, ev1[2] = {nullptr, nullptr}, evh[2] = {nullptr, nullptr};
@@ -125,9 +127,12 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
     g.s = s;
     g.N = 2 * op->n2;
     g.m = maxit;
-    // V, w, z, matvec partials (4 n2), two Hessenberg column slots, a norm
+    // V, w, z, matvec partials (4 n2), two Hessenberg column slots, a norm,
+    // projection partials, norm partials
     const size_t hslots = 2 * (size_t)(2 * (maxit + 1) + 1);
-    const size_t need = (size_t)(maxit + 1) * g.N + 2 * g.N + 4 * op->n2 + hslots + 1;
+    const size_t nch = (size_t)arnoldi_chunks(g.N);
+    const size_t need = (size_t)(maxit + 1) * g.N + 2 * g.N + 4 * op->n2 + hslots + 1 +
+                        (size_t)(maxit + 1) * nch + nch;
     mbem_op *mop = const_cast<mbem_op *>(op);
     if (op->work_elems < need) {
         dfree(mop->d_work);
@@ -152,6 +157,8 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
     g.tmp = g.z + g.N;                 // 4 n2 for the matvec partials
     g.hdev = g.tmp + 4 * op->n2;       // two column slots of 2 (maxit + 1) + 1
     g.ndev = (double *)(g.hdev + hslots);
+    g.ppart = g.hdev + hslots + 1;
+    g.npart = (double *)(g.ppart + (size_t)(maxit + 1) * nch);
     for (int i = 0; i < 2; ++i) {
         if (!g.ev0[i]) MBEM_HIP(hipEventCreate(&g.ev0[i]));
         if (!g.ev1[i]) MBEM_HIP(hipEventCreate(&g.ev1[i]));
@@ -195,16 +202,14 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
         double2 *hk = g.hdev + (size_t)slot * (2 * (m + 1) + 1);
         MBEM_TRY(mbj_apply_run(g.op, vk, g.z, s, g.trans));
         MBEM_TRY(g.timed_matvec(g.z, g.w, slot));
-        MBEM_TRY(vec_dots(g.V, N, k + 1, g.w, N, hk, s));
-        MBEM_TRY(vec_update(g.w, g.V, N, k + 1, hk, N, s));
-        MBEM_TRY(vec_dots(g.V, N, k + 1, g.w, N, hk + (k + 1), s));
-        MBEM_TRY(vec_update(g.w, g.V, N, k + 1, hk + (k + 1), N, s));
+        // CGS2: two projection passes, the second also yields |w|^2 by chunk
+        MBEM_TRY(arnoldi_pass(g.w, g.V, N, k + 1, N, g.ppart, hk, nullptr, s));
+        MBEM_TRY(arnoldi_pass(g.w, g.V, N, k + 1, N, g.ppart, hk + (k + 1), g.npart, s));
         double *hn = (double *)(hk + 2 * (k + 1));
-        MBEM_TRY(vec_norm2(g.w, N, hn, s));
+        MBEM_TRY(scale_by_norm_parts(g.V + (size_t)(k + 1) * N, g.w, g.npart, hn, N, s));
         MBEM_HIP(hipMemcpyAsync(g.hpin[slot], hk, sizeof(double2) * (2 * (k + 1) + 1),
                                 hipMemcpyDeviceToHost, s));
         MBEM_HIP(hipEventRecord(g.evh[slot], s));
-        if (k + 1 <= m) MBEM_TRY(vec_scale_inv_norm(g.V + (size_t)(k + 1) * N, g.w, hn, N, s));
         return MBEM_OK;
     };
     double res = 1.0;

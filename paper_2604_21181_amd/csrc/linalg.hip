@@ -595,6 +595,90 @@ __global__ __launch_bounds__(256) void k_dots(const double2 *V, int64_t ldv, con
     if (threadIdx.x == 0) out[j] = {s_re[0] + s_re[1] + s_re[2] + s_re[3], s_im[0] + s_im[1] + s_im[2] + s_im[3]};
 }
 
+// ----------------------------------------------- Arnoldi projections --
+// One Gram-Schmidt pass over k basis vectors in two launches, both with one
+// 256-element chunk of the vectors per workgroup:
+//   k_dots_part:  part[j][c] = sum over chunk c of conj(V_j) w   (j < k)
+//   k_update_red: h_j = sum_c part[j][c] (fixed order), w -= sum_j V_j h_j,
+//                 h written by workgroup 0, and optionally the chunk's part
+//                 of |w|^2 for the normalisation that follows.
+constexpr int kChunkN = 256;
+constexpr int kBatch = 64;      // basis vectors per LDS round
+
+__global__ __launch_bounds__(kChunkN) void k_dots_part(const double2 *V, int64_t ldv, int k,
+                                                      const double2 *w, int64_t n, double2 *part,
+                                                      int64_t nch) {
+    __shared__ double s_re[4][kBatch], s_im[4][kBatch];
+    const int64_t c = blockIdx.x, i = c * kChunkN + threadIdx.x;
+    const int wv = threadIdx.x / kW, lane = threadIdx.x % kW;
+    const double2 b = i < n ? w[i] : double2{0, 0};
+    for (int j0 = 0; j0 < k; j0 += kBatch) {
+        const int nb = k - j0 < kBatch ? k - j0 : kBatch;
+        for (int jj = 0; jj < nb; ++jj) {
+            const double2 a = i < n ? V[(int64_t)(j0 + jj) * ldv + i] : double2{0, 0};
+            const double re = wave_sum(a.x * b.x + a.y * b.y), im = wave_sum(a.x * b.y - a.y * b.x);
+            if (lane == 0) { s_re[wv][jj] = re; s_im[wv][jj] = im; }
+        }
+        __syncthreads();
+        if (threadIdx.x < nb) {
+            const int jj = threadIdx.x;
+            part[(int64_t)(j0 + jj) * nch + c] = {s_re[0][jj] + s_re[1][jj] + s_re[2][jj] + s_re[3][jj],
+                                                  s_im[0][jj] + s_im[1][jj] + s_im[2][jj] + s_im[3][jj]};
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kChunkN) void k_update_red(double2 *w, const double2 *V, int64_t ldv, int k,
+                                                       const double2 *part, int64_t nch, double2 *hout,
+                                                       int64_t n, double *npart) {
+    __shared__ double2 s_h[kBatch];
+    __shared__ double s_n[4];
+    const int wv = threadIdx.x / kW, lane = threadIdx.x % kW;
+    const int64_t i = blockIdx.x * (int64_t)kChunkN + threadIdx.x;
+    double2 t = i < n ? w[i] : double2{0, 0};
+    for (int j0 = 0; j0 < k; j0 += kBatch) {
+        const int nb = k - j0 < kBatch ? k - j0 : kBatch;
+        for (int jj = wv; jj < nb; jj += 4) {    // wavefront wv reduces h_j over the chunks
+            const int64_t j = j0 + jj;
+            double re = 0, im = 0;
+            for (int64_t cc = lane; cc < nch; cc += kW) { re += part[j * nch + cc].x; im += part[j * nch + cc].y; }
+            re = wave_sum(re);
+            im = wave_sum(im);
+            if (lane == 0) s_h[jj] = {re, im};
+        }
+        __syncthreads();
+        if (blockIdx.x == 0 && threadIdx.x < nb) hout[j0 + threadIdx.x] = s_h[threadIdx.x];
+        if (i < n)
+            for (int jj = 0; jj < nb; ++jj) t = csub(t, cmul(V[(int64_t)(j0 + jj) * ldv + i], s_h[jj]));
+        __syncthreads();
+    }
+    if (i < n) w[i] = t;
+    if (npart) {
+        const double nn = wave_sum(i < n ? t.x * t.x + t.y * t.y : 0.0);
+        if (lane == 0) s_n[wv] = nn;
+        __syncthreads();
+        if (threadIdx.x == 0) npart[blockIdx.x] = s_n[0] + s_n[1] + s_n[2] + s_n[3];
+    }
+}
+
+// dst = src / h with h = sqrt(sum_c npart[c]); workgroup 0 stores h
+__global__ __launch_bounds__(kChunkN) void k_scale_norm_part(double2 *dst, const double2 *src,
+                                                            const double *npart, int64_t nch,
+                                                            double *hout, int64_t n) {
+    __shared__ double s_h;
+    if (threadIdx.x < kW) {
+        double a = 0;
+        for (int64_t c = threadIdx.x; c < nch; c += kW) a += npart[c];
+        a = wave_sum(a);
+        if (threadIdx.x == 0) { s_h = sqrt(a); if (blockIdx.x == 0) *hout = s_h; }
+    }
+    __syncthreads();
+    const double h = s_h, inv = h > 0 ? 1.0 / h : 0.0;
+    const int64_t i = blockIdx.x * (int64_t)kChunkN + threadIdx.x;
+    if (i < n) dst[i] = {inv * src[i].x, inv * src[i].y};
+}
+
 // w[n] -= sum_j V[j][n] h[j]
 __global__ void k_update(double2 *w, const double2 *V, int64_t ldv, int k, const double2 *h, int64_t n) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -675,6 +759,25 @@ int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n, hipSt
 int vec_scale_inv_norm(double2 *dst, const double2 *src, const double *nrm_dev, int64_t n,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_scale_inv_norm, dim3(nblk(n)), dim3(256), 0, s, dst, src, nrm_dev, n);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+int64_t arnoldi_chunks(int64_t n) { return (n + kChunkN - 1) / kChunkN; }
+int arnoldi_pass(double2 *w, const double2 *V, int64_t ldv, int k, int64_t n, double2 *part,
+                 double2 *hout, double *npart, hipStream_t s) {
+    const int64_t nch = arnoldi_chunks(n);
+    hipLaunchKernelGGL(k_dots_part, dim3((unsigned)nch), dim3(kChunkN), 0, s, V, ldv, k, w, n, part, nch);
+    MBEM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_update_red, dim3((unsigned)nch), dim3(kChunkN), 0, s, w, V, ldv, k, part, nch,
+                       hout, n, npart);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+int scale_by_norm_parts(double2 *dst, const double2 *src, const double *npart, double *hout, int64_t n,
+                        hipStream_t s) {
+    const int64_t nch = arnoldi_chunks(n);
+    hipLaunchKernelGGL(k_scale_norm_part, dim3((unsigned)nch), dim3(kChunkN), 0, s, dst, src, npart, nch,
+                       hout, n);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
