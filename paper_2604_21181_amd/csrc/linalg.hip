@@ -575,27 +575,6 @@ int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z, hipStream_t s
 }
 
 // ---------------------------------------------------- GMRES vectors ---
-// out[j] = sum_n conj(V[j][n]) w[n], j = 0..k-1 (one workgroup per j)
-__global__ __launch_bounds__(256) void k_dots(const double2 *V, int64_t ldv, const double2 *w,
-                                              int64_t n, double2 *out) {
-    __shared__ double s_re[4], s_im[4];
-    const int j = blockIdx.x;
-    const double2 *v = V + (int64_t)j * ldv;
-    double re = 0, im = 0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const double2 a = v[i], b = w[i];
-        re += a.x * b.x + a.y * b.y;
-        im += a.x * b.y - a.y * b.x;
-    }
-    re = wave_sum(re);
-    im = wave_sum(im);
-    const int wv = threadIdx.x / kW;
-    if (threadIdx.x % kW == 0) { s_re[wv] = re; s_im[wv] = im; }
-    __syncthreads();
-    if (threadIdx.x == 0) out[j] = {s_re[0] + s_re[1] + s_re[2] + s_re[3], s_im[0] + s_im[1] + s_im[2] + s_im[3]};
-}
-
-// ----------------------------------------------- Arnoldi projections --
 // One Gram-Schmidt pass over k basis vectors in two launches, both with one
 // 256-element chunk of the vectors per workgroup:
 //   k_dots_part:  part[j][c] = sum over chunk c of conj(V_j) w   (j < k)
@@ -679,15 +658,6 @@ __global__ __launch_bounds__(kChunkN) void k_scale_norm_part(double2 *dst, const
     if (i < n) dst[i] = {inv * src[i].x, inv * src[i].y};
 }
 
-// w[n] -= sum_j V[j][n] h[j]
-__global__ void k_update(double2 *w, const double2 *V, int64_t ldv, int k, const double2 *h, int64_t n) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double2 s = w[i];
-    for (int j = 0; j < k; ++j) s = csub(s, cmul(V[(int64_t)j * ldv + i], h[j]));
-    w[i] = s;
-}
-
 // out[n] = sum_j V[j][n] y[j]
 __global__ void k_combine_basis(double2 *out, const double2 *V, int64_t ldv, int k, const double2 *y,
                                 int64_t n) {
@@ -717,13 +687,6 @@ __global__ void k_scale_copy(double2 *dst, const double2 *src, double2 a, int64_
     if (i < n) dst[i] = cmul(a, src[i]);
 }
 
-__global__ void k_scale_inv_norm(double2 *dst, const double2 *src, const double *nrm, int64_t n) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double h = *nrm, a = h > 0 ? 1.0 / h : 0.0;
-    dst[i] = {a * src[i].x, a * src[i].y};
-}
-
 __global__ void k_axpy(double2 *y, const double2 *x, double2 a, int64_t n) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) y[i] = cadd(y[i], cmul(a, x[i]));
@@ -731,16 +694,6 @@ __global__ void k_axpy(double2 *y, const double2 *x, double2 a, int64_t n) {
 
 static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-int vec_dots(const double2 *V, int64_t ldv, int k, const double2 *w, int64_t n, double2 *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_dots, dim3(k), dim3(256), 0, s, V, ldv, w, n, out);
-    MBEM_HIP(hipGetLastError());
-    return MBEM_OK;
-}
-int vec_update(double2 *w, const double2 *V, int64_t ldv, int k, const double2 *h, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_update, dim3(nblk(n)), dim3(256), 0, s, w, V, ldv, k, h, n);
-    MBEM_HIP(hipGetLastError());
-    return MBEM_OK;
-}
 int vec_combine(double2 *out, const double2 *V, int64_t ldv, int k, const double2 *y, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_combine_basis, dim3(nblk(n)), dim3(256), 0, s, out, V, ldv, k, y, n);
     MBEM_HIP(hipGetLastError());
@@ -753,12 +706,6 @@ int vec_norm2(const double2 *v, int64_t n, double *out, hipStream_t s) {
 }
 int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_scale_copy, dim3(nblk(n)), dim3(256), 0, s, dst, src, a, n);
-    MBEM_HIP(hipGetLastError());
-    return MBEM_OK;
-}
-int vec_scale_inv_norm(double2 *dst, const double2 *src, const double *nrm_dev, int64_t n,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_inv_norm, dim3(nblk(n)), dim3(256), 0, s, dst, src, nrm_dev, n);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }

@@ -156,10 +156,6 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s);
 // trans: apply P^-T (mbj_transpose_run must have run)
 int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z,
                   hipStream_t s, bool trans = false);
-int vec_dots(const double2 *V, int64_t ldv, int k, const double2 *w,
-             int64_t n, double2 *out_dev, hipStream_t s);
-int vec_update(double2 *w, const double2 *V, int64_t ldv, int k,
-               const double2 *h_dev, int64_t n, hipStream_t s);
 int vec_norm2(const double2 *v, int64_t n, double *out_dev, hipStream_t s);
 // One classical Gram-Schmidt pass w -= V h, h = V^H w over k basis vectors
 // (h stored to hout); with npart, the per-chunk parts of |w|^2 after the
@@ -171,9 +167,6 @@ int arnoldi_pass(double2 *w, const double2 *V, int64_t ldv, int k, int64_t n, do
 // dst = src / h, h = sqrt(sum of npart) stored to *hout (0 -> dst = 0)
 int scale_by_norm_parts(double2 *dst, const double2 *src, const double *npart, double *hout, int64_t n,
                         hipStream_t s);
-// dst = src / *nrm_dev (0 where the norm is 0), the norm read on the device
-int vec_scale_inv_norm(double2 *dst, const double2 *src, const double *nrm_dev, int64_t n,
-                       hipStream_t s);
 int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n,
                    hipStream_t s);
 int vec_axpy(double2 *y, const double2 *x, double2 a, int64_t n,
