@@ -55,10 +55,10 @@ PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix cores
 # scaled by a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  A
 # kernel changed after its counters were taken gets None here.
 MEASURED_TRAFFIC = {
-    ("k_regular", "fp64"): None,
-    ("k_regular", "mixed"): None,
-    ("k_gemv3", "fp64"): 1.283e9,
-    ("k_gemv3", "mixed"): 0.652e9,
+    ("k_regular", "fp64"): 23.33e9,     # 15.39 GB read + 7.94 GB written per fill
+    ("k_regular", "mixed"): 15.43e9,    # 9.78 GB read + 5.65 GB written per fill
+    ("k_gemv3", "fp64"): 1.291e9,
+    ("k_gemv3", "mixed"): 0.683e9,
 }
 
 # Algorithmic flops of the regular-pair fill (FMA = 2 flops, every
@@ -251,51 +251,56 @@ def main():
             mixed_ok = e <= 1e-6
         head = "mixed" if (mixed_ok or paths == ["mixed"]) else paths[0]
 
-        # ---- roofline of the dominant kernel (largest device time per step)
-        cand = []
-        for p in paths:
-            r = res[p]
-            nm = r["n_matvec"]
-            cand.append((r["t_regular_ms"], "regular_pairs_" + p, p))
-            cand.append((r["t_ssq_ms"], "sauter_schwab_" + p, p))
-            if nm:
-                cand.append((r["t_matvec_ms"], "gemv_" + p, p))
-        cand.sort(reverse=True)
-        t_dom, kname, kp = cand[0]
-        r = res[kp]
-        n2 = N // 2
-        if kname.startswith("gemv"):
-            esz = 16 if kp == "fp64" else 8
-            traffic = 3 * n2 * n2 * esz + 2 * N * 16            # three blocks + x in, y out
-            per_launch_ms = r["t_matvec_ms"] / max(1, r["n_matvec"])
-            achieved = traffic / (per_launch_ms * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
-                    "frac": achieved / PEAK_HBM, "traffic": MEASURED_TRAFFIC.get(("k_gemv3", kp)), "kernel": "k_gemv3",
-                    "algorithmic_bytes_per_launch": traffic, "launch_ms": per_launch_ms}
-        elif kname.startswith("regular"):
-            S = solvers[kp]
-            npairs = r["n_regular"]
-            rank = np.empty_like(S.node_order)
-            rank[S.node_order] = np.arange(S.nn)
-            tm = rank[tri[S.tri_order]]
-            ns = np.array([np.unique(tm[k:k + CHUNK]).size for k in range(0, nt, CHUNK)])
-            # every (test triangle, chunk) workgroup contracts ns test-side nodes
-            flops = (npairs * (49 * FLOP_POINT_PAIR + FLOP_PAIR_TRIAL)
-                     + nt * int(ns.sum()) * FLOP_CHUNK_TEST_PER_NODE)
-            achieved = flops / (r["t_regular_ms"] * 1e-3) / 1e12
-            peak = PEAK_FP64_VALU if kp == "fp64" else PEAK_FP32_VALU
-            roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                    "frac": achieved / peak, "traffic": MEASURED_TRAFFIC.get(("k_regular", kp)), "kernel": "k_regular",
-                    "algorithmic_flops_per_launch": flops, "launch_ms": r["t_regular_ms"]}
-        else:
+        # ---- rooflines of the candidate kernels; `roofline` is the one with
+        # the largest device time per step
+        def roofline_of(kname, kp):
+            r = res[kp]
+            n2 = N // 2
+            if kname == "gemv":
+                esz = 16 if kp == "fp64" else 8
+                traffic = 3 * n2 * n2 * esz + 2 * N * 16            # three blocks + x in, y out
+                per_launch_ms = r["t_matvec_ms"] / max(1, r["n_matvec"])
+                achieved = traffic / (per_launch_ms * 1e-3) / 1e9
+                return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
+                        "frac": achieved / PEAK_HBM, "traffic": MEASURED_TRAFFIC.get(("k_gemv3", kp)),
+                        "kernel": "k_gemv3", "path": kp,
+                        "algorithmic_bytes_per_launch": traffic, "launch_ms": per_launch_ms}
+            if kname == "regular":
+                S = solvers[kp]
+                npairs = r["n_regular"]
+                rank = np.empty_like(S.node_order)
+                rank[S.node_order] = np.arange(S.nn)
+                tm = rank[tri[S.tri_order]]
+                ns = np.array([np.unique(tm[k:k + CHUNK]).size for k in range(0, nt, CHUNK)])
+                # every (test triangle, chunk) workgroup contracts ns test-side nodes
+                flops = (npairs * (49 * FLOP_POINT_PAIR + FLOP_PAIR_TRIAL)
+                         + nt * int(ns.sum()) * FLOP_CHUNK_TEST_PER_NODE)
+                achieved = flops / (r["t_regular_ms"] * 1e-3) / 1e12
+                peak = PEAK_FP64_VALU if kp == "fp64" else PEAK_FP32_VALU
+                return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                        "frac": achieved / peak, "traffic": MEASURED_TRAFFIC.get(("k_regular", kp)),
+                        "kernel": "k_regular", "path": kp,
+                        "algorithmic_flops_per_launch": flops, "launch_ms": r["t_regular_ms"]}
             S = solvers[kp]
             ncoinc, nedge, nvert = S.n_singular
             pts = (6 * ncoinc + 5 * nedge + 2 * nvert) * 256
             flops = pts * FLOP_SSQ_POINT
             achieved = flops / (r["t_ssq_ms"] * 1e-3) / 1e12
-            roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
-                    "frac": achieved / PEAK_FP64_VALU, "traffic": None, "kernel": "k_ssq",
+            return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_FP64_VALU, "traffic": None, "kernel": "k_ssq", "path": kp,
                     "algorithmic_flops_per_launch": flops, "launch_ms": r["t_ssq_ms"]}
+
+        cand = []
+        for p in paths:
+            r = res[p]
+            cand.append((r["t_regular_ms"], "regular", p))
+            cand.append((r["t_ssq_ms"], "ssq", p))
+            if r["n_matvec"]:
+                cand.append((r["t_matvec_ms"], "gemv", p))
+        cand.sort(reverse=True)
+        rooflines = [roofline_of(kname, kp) for _, kname, kp in cand]
+        roof = dict(rooflines[0])
+        roof.pop("path", None)
 
     mrhs = None
     if Smr is not None:
@@ -391,6 +396,7 @@ def main():
         "solve_s": {p: res[p]["t_solve_ms"] * 1e-3 for p in paths},
         "accuracy": info,
         "roofline": roof,
+        "rooflines": rooflines,
         "multi_rhs": mrhs,
         "gradient": grad,
         "cpu_baseline": cpu,
