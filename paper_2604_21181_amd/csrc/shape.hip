@@ -486,8 +486,10 @@ __global__ void k_qp_backprop(int64_t nt, const double *__restrict__ xyz, const 
 
 // ------------------------------------------------- singular pairs ---
 // One wavefront per coincident / common-edge / common-vertex pair, the
-// Sauter-Schwab points of the fill; each lane keeps the 12 x 9 node
-// adjoints of its points in its own slice of LDS.
+// Sauter-Schwab points of the fill, one point per lane and batch.  After
+// each batch the 6 x 9 test-node adjoints of every lane go through LDS and
+// lane c < 54 adds column c over the 64 points (then the same for the trial
+// nodes), so each lane keeps two running sums and the workgroup 28 KB of LDS.
 struct ShapeSsqArgs {
     int64_t n2, npairs;
     const int32_t *pairs, *tri;
@@ -501,7 +503,8 @@ struct ShapeSsqArgs {
 };
 
 __global__ __launch_bounds__(64) void k_shape_ssq(ShapeSsqArgs a) {
-    __shared__ double s_acc[64][12 * 9];
+    constexpr int kCols = 54, kStride = 55;
+    __shared__ double s_buf[64 * kStride];
     const int lane = threadIdx.x;
     const int64_t pid = blockIdx.x;
     const int32_t e = a.pairs[4 * pid], f = a.pairs[4 * pid + 1];
@@ -509,67 +512,92 @@ __global__ __launch_bounds__(64) void k_shape_ssq(ShapeSsqArgs a) {
     const int n = a.order, n4 = n * n * n * n;
     const int nreg = cls == 3 ? 6 : (cls == 2 ? 5 : 2);
     const int npts = nreg * n4;
-    for (int c = 0; c < 12 * 9; ++c) s_acc[lane][c] = 0.0;
     const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
     const KernelConst &K = *a.K;
-    for (int idx = lane; idx < npts; idx += 64) {
-        const int r = idx / n4;
-        int g = idx % n4;
-        const int i3 = g % n; g /= n;
-        const int i2 = g % n; g /= n;
-        const int i1 = g % n; g /= n;
-        const int i0 = g;
-        double s1, t1, s2, t2;
-        const double jac = ss_region(cls, r, a.glx[i0], a.glx[i1], a.glx[i2], a.glx[i3], s1, t1, s2, t2);
-        const double wg = jac * a.glw[i0] * a.glw[i1] * a.glw[i2] * a.glw[i3];
-        double xe, ye, xf, yf;
-        ss_local(code & 63, s1, t1, xe, ye);
-        ss_local(code >> 6, s2, t2, xf, yf);
+    double accT = 0.0, accS = 0.0;       // column `lane` of the test / trial adjoints
+    double *row = s_buf + lane * kStride;
+    for (int base = 0; base < npts; base += 64) {
+        const int idx = base + lane;
+        const bool on = idx < npts;
         P2Fwd X, Y;
-        p2_forward(a.xyz, a.frames, te, xe, ye, X);
-        p2_forward(a.xyz, a.frames, tf, xf, yf, Y);
-        TPt P;
-        SPt Q;
-        P.x = X.x; P.n = X.n; P.t1 = X.t1; P.t2 = X.t2; P.W = X.J;
-        Q.y = Y.x; Q.t1 = Y.t1; Q.t2 = Y.t2; Q.W = Y.J;
-        for (int c = 0; c < 4; ++c) { P.L[c] = {0, 0}; Q.X[c] = {0, 0}; }
-        for (int k = 0; k < 6; ++k) {
-            const int64_t ne = te[k], nf = tf[k];
-            const double2 l[4] = {a.lam[2 * ne], a.lam[2 * ne + 1], a.lam[a.n2 + 2 * ne], a.lam[a.n2 + 2 * ne + 1]};
-            const double2 u[4] = {a.x[2 * nf], a.x[2 * nf + 1], a.x[a.n2 + 2 * nf], a.x[a.n2 + 2 * nf + 1]};
-            for (int c = 0; c < 4; ++c) {
-                P.L[c] = P.L[c] + cxd{X.N[k] * l[c].x, X.N[k] * l[c].y};
-                Q.X[c] = Q.X[c] + cxd{Y.N[k] * u[c].x, Y.N[k] * u[c].y};
-            }
-        }
         TGrad gt;
         SGrad gs;
         zero(gt);
         zero(gs);
-        pair_adjoint<true, true>(K, a.iw, P, Q, wg, gt, gs);
-        dvec3 gX[6], gT1[6], gT2[6];
-        p2_reverse(X, gt.x, gt.W, gt.n, gt.t1, gt.t2, gX, gT1, gT2);
-        for (int k = 0; k < 6; ++k) {
-            double *o = &s_acc[lane][9 * k];
-            o[0] += gX[k].x; o[1] += gX[k].y; o[2] += gX[k].z;
-            o[3] += gT1[k].x; o[4] += gT1[k].y; o[5] += gT1[k].z;
-            o[6] += gT2[k].x; o[7] += gT2[k].y; o[8] += gT2[k].z;
+        if (on) {
+            const int r = idx / n4;
+            int g = idx % n4;
+            const int i3 = g % n; g /= n;
+            const int i2 = g % n; g /= n;
+            const int i1 = g % n; g /= n;
+            const int i0 = g;
+            double s1, t1, s2, t2;
+            const double jac = ss_region(cls, r, a.glx[i0], a.glx[i1], a.glx[i2], a.glx[i3], s1, t1, s2, t2);
+            const double wg = jac * a.glw[i0] * a.glw[i1] * a.glw[i2] * a.glw[i3];
+            double xe, ye, xf, yf;
+            ss_local(code & 63, s1, t1, xe, ye);
+            ss_local(code >> 6, s2, t2, xf, yf);
+            p2_forward(a.xyz, a.frames, te, xe, ye, X);
+            p2_forward(a.xyz, a.frames, tf, xf, yf, Y);
+            TPt P;
+            SPt Q;
+            P.x = X.x; P.n = X.n; P.t1 = X.t1; P.t2 = X.t2; P.W = X.J;
+            Q.y = Y.x; Q.t1 = Y.t1; Q.t2 = Y.t2; Q.W = Y.J;
+            for (int c = 0; c < 4; ++c) { P.L[c] = {0, 0}; Q.X[c] = {0, 0}; }
+            for (int k = 0; k < 6; ++k) {
+                const int64_t ne = te[k], nf = tf[k];
+                const double2 l[4] = {a.lam[2 * ne], a.lam[2 * ne + 1], a.lam[a.n2 + 2 * ne], a.lam[a.n2 + 2 * ne + 1]};
+                const double2 u[4] = {a.x[2 * nf], a.x[2 * nf + 1], a.x[a.n2 + 2 * nf], a.x[a.n2 + 2 * nf + 1]};
+                for (int c = 0; c < 4; ++c) {
+                    P.L[c] = P.L[c] + cxd{X.N[k] * l[c].x, X.N[k] * l[c].y};
+                    Q.X[c] = Q.X[c] + cxd{Y.N[k] * u[c].x, Y.N[k] * u[c].y};
+                }
+            }
+            pair_adjoint<true, true>(K, a.iw, P, Q, wg, gt, gs);
         }
-        p2_reverse(Y, gs.y, gs.W, {0, 0, 0}, gs.t1, gs.t2, gX, gT1, gT2);
-        for (int k = 0; k < 6; ++k) {
-            double *o = &s_acc[lane][54 + 9 * k];
-            o[0] += gX[k].x; o[1] += gX[k].y; o[2] += gX[k].z;
-            o[3] += gT1[k].x; o[4] += gT1[k].y; o[5] += gT1[k].z;
-            o[6] += gT2[k].x; o[7] += gT2[k].y; o[8] += gT2[k].z;
+        // test side
+        {
+            dvec3 gX[6], gT1[6], gT2[6];
+            if (on) p2_reverse(X, gt.x, gt.W, gt.n, gt.t1, gt.t2, gX, gT1, gT2);
+            for (int k = 0; k < 6; ++k) {
+                double *o = row + 9 * k;
+                if (on) {
+                    o[0] = gX[k].x; o[1] = gX[k].y; o[2] = gX[k].z;
+                    o[3] = gT1[k].x; o[4] = gT1[k].y; o[5] = gT1[k].z;
+                    o[6] = gT2[k].x; o[7] = gT2[k].y; o[8] = gT2[k].z;
+                } else {
+                    for (int c = 0; c < 9; ++c) o[c] = 0.0;
+                }
+            }
         }
+        __syncthreads();
+        if (lane < kCols)
+            for (int l = 0; l < 64; ++l) accT += s_buf[l * kStride + lane];
+        __syncthreads();
+        // trial side
+        {
+            dvec3 gX[6], gT1[6], gT2[6];
+            if (on) p2_reverse(Y, gs.y, gs.W, {0, 0, 0}, gs.t1, gs.t2, gX, gT1, gT2);
+            for (int k = 0; k < 6; ++k) {
+                double *o = row + 9 * k;
+                if (on) {
+                    o[0] = gX[k].x; o[1] = gX[k].y; o[2] = gX[k].z;
+                    o[3] = gT1[k].x; o[4] = gT1[k].y; o[5] = gT1[k].z;
+                    o[6] = gT2[k].x; o[7] = gT2[k].y; o[8] = gT2[k].z;
+                } else {
+                    for (int c = 0; c < 9; ++c) o[c] = 0.0;
+                }
+            }
+        }
+        __syncthreads();
+        if (lane < kCols)
+            for (int l = 0; l < 64; ++l) accS += s_buf[l * kStride + lane];
+        __syncthreads();
     }
-    __syncthreads();
-    for (int c = lane; c < 12 * 9; c += 64) {
-        double sum = 0.0;
-        for (int l = 0; l < 64; ++l) sum += s_acc[l][c];
-        const int k = c / 9, comp = c % 9;
-        const int64_t node = k < 6 ? te[k] : tf[k - 6];
-        unsafeAtomicAdd(&a.nodeb[9 * node + comp], sum);
+    if (lane < kCols) {
+        const int k = lane / 9, comp = lane % 9;
+        unsafeAtomicAdd(&a.nodeb[9 * (int64_t)te[k] + comp], accT);
+        unsafeAtomicAdd(&a.nodeb[9 * (int64_t)tf[k] + comp], accS);
     }
 }
 
