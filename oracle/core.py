@@ -40,6 +40,7 @@ def lib():
         P = C.c_void_p
         i64 = C.c_int64
         L.or_rule7.argtypes = [P, P, P]
+        L.or_rule12.argtypes = [P, P, P]
         L.or_gauss_legendre01.argtypes = [C.c_int, P, P]
         L.or_nodal_frames.argtypes = [P, i64, P, i64, P]
         L.or_point_data.argtypes = [P, i64, P, i64, i64, P, P, P, P]
@@ -63,14 +64,25 @@ def _mesh(xyz, tri6):
     return xyz, tri6
 
 
-def phys_vector(k0, eps_r, mu_r=1.0):
+def phys_vector(k0, eps_r, mu_r=1.0, variant=0):
+    """variant 0: 7-point regular rule, Sauter-Schwab on the full kernels,
+    16-term series; 1: the paper's own scheme (12-point rule, Sauter-Schwab
+    on the singular parts, the remainder by the 12-point rule, series
+    truncated after n = 6)."""
     eps_r, mu_r = complex(eps_r), complex(mu_r)
-    return np.array([k0, eps_r.real, eps_r.imag, mu_r.real, mu_r.imag])
+    return np.array([k0, eps_r.real, eps_r.imag, mu_r.real, mu_r.imag, float(variant)])
 
 
 def rule7():
     xi, eta, w = (np.zeros(7) for _ in range(3))
     lib().or_rule7(_p(xi), _p(eta), _p(w))
+    return xi, eta, w
+
+
+def rule12():
+    """(xi, eta, w) of the 12-point degree-6 rule on the reference triangle."""
+    xi, eta, w = np.zeros(12), np.zeros(12), np.zeros(12)
+    lib().or_rule12(_p(xi), _p(eta), _p(w))
     return xi, eta, w
 
 
@@ -102,7 +114,8 @@ def point_data(xyz, tri6, elem, xi, eta):
 
 
 def kernel_scalars(phys, R, mode=0):
-    """D0, df, dg, G_eps, G_mu at distances R (mode 0 hybrid, 1 closed, 2 series)."""
+    """D0, df, dg, G_eps, G_mu at distances R (mode 0 hybrid, 1 closed, 2 series,
+    3 singular parts, 4 remainders = kernel - singular part)."""
     R = np.ascontiguousarray(R, dtype=np.float64)
     out = np.zeros((R.shape[0], 10))
     lib().or_kernel_scalars(_p(np.asarray(phys, dtype=np.float64)), mode,

@@ -17,7 +17,7 @@ from . import core
 class Problem:
     """A mesh plus material: everything the oracle's formulas need."""
 
-    def __init__(self, xyz, tri6, k0, eps_r, mu_r=1.0, nss=4):
+    def __init__(self, xyz, tri6, k0, eps_r, mu_r=1.0, nss=4, variant=0):
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self.tri6 = np.ascontiguousarray(tri6, dtype=np.int64)
         self.nn = self.xyz.shape[0]
@@ -26,7 +26,10 @@ class Problem:
         self.eps_r = complex(eps_r)
         self.mu_r = complex(mu_r)
         self.nss = nss
-        self.phys = core.phys_vector(k0, eps_r, mu_r)
+        # variant selects the quadrature of the operator blocks (core.phys_vector);
+        # mass matrix, right-hand side and far field keep the 7-point rule
+        self.variant = variant
+        self.phys = core.phys_vector(k0, eps_r, mu_r, variant)
         self.ka = self.k0
         ki = self.k0 * np.sqrt(self.eps_r * self.mu_r)
         self.ki = -ki if ki.imag < 0 else ki

@@ -63,6 +63,35 @@ void or_rule7(double xi[7], double eta[7], double w[7]) {
     for (int q = 0; q < 7; ++q) { xi[q] = X[q]; eta[q] = Y[q]; w[q] = W[q]; }
 }
 
+/* The 12-point degree-6 symmetric rule on the reference triangle (area
+ * 1/2): two three-point orbits (a, a, 1 - 2a) and one six-point orbit
+ * (b, c, 1 - b - c).  Its seven parameters solve the seven moment
+ * equations of the S3-invariant polynomials e2^i e3^j, 2i + 3j <= 6
+ * (Witherden and Vincent's 12-point rule for degree 6, whose points
+ * Dunavant also lists); the values were refined by Newton's method on those
+ * equations to double precision.  Order: orbit a1, orbit a2, then the six
+ * permutations of (b, c, 1 - b - c).                                       */
+void or_rule12(double xi[12], double eta[12], double w[12]) {
+    const double a[2] = {0.06308901449150309, 0.24928674517091215};
+    const double wa[2] = {0.05084490637020728, 0.11678627572637695};
+    const double b = 0.053145049844817806, c = 0.3103524510337839;
+    const double wb = 0.08285107561837454;
+    int q = 0;
+    for (int o = 0; o < 2; ++o)
+        for (int k = 0; k < 3; ++k) {
+            double l[3] = {a[o], a[o], a[o]};
+            l[k] = 1.0 - 2.0 * a[o];
+            xi[q] = l[1]; eta[q] = l[2]; w[q] = 0.5 * wa[o]; ++q;
+        }
+    const double v[3] = {b, c, 1.0 - b - c};
+    const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (int k = 0; k < 6; ++k) {
+        double l[3];
+        for (int d = 0; d < 3; ++d) l[perm[k][d]] = v[d];
+        xi[q] = l[1]; eta[q] = l[2]; w[q] = 0.5 * wb; ++q;
+    }
+}
+
 /* n-point Gauss-Legendre rule on [0,1], by Newton iteration on P_n.     */
 int or_gauss_legendre01(int n, double *x, double *w) {
     if (n < 1 || n > 64) return -1;
@@ -237,6 +266,13 @@ typedef struct {
     double omega;
     int nss;               /* Gauss points per SSQ dimension       */
     int mode;              /* 0 hybrid, 1 closed form, 2 series    */
+    int variant;           /* 0: 7-point regular rule, Sauter-Schwab on the
+                              full kernels, 16-term series;
+                              1: the paper's variant: 12-point rule, Sauter-
+                              Schwab on the singular parts only, the
+                              remainder by the 12-point rule, series
+                              truncated after n = 6                    */
+    int nterms;            /* highest Taylor term n of the series  */
 } or_phys;
 
 #define OR_SERIES_RHO 0.5
@@ -277,7 +313,7 @@ static void kernel_scalars(const or_phys *ph, double R, cplx *D0, cplx *df,
     cplx ca = 1.0, ci = 1.0;
     cplx sD = 0, sf = 0, sg = 0, se = 0, sm = 0;
     double Rp = 1.0 / R;            /* R^(n-1) at n = 0 */
-    for (int n = 0; n <= OR_SERIES_TERMS; ++n) {
+    for (int n = 0; n <= ph->nterms; ++n) {
         if (n > 0) { ca *= I * ph->ka / n; ci *= I * ph->ki / n; }
         double Rn1 = Rp;            /* R^(n-1) */
         double Rn2 = Rp / R;        /* R^(n-2) */
@@ -297,20 +333,70 @@ static void kernel_scalars(const or_phys *ph, double R, cplx *D0, cplx *df,
 }
 
 /*
- * The twelve scalar kernels at a test point X and a trial point Y:
+ * Singular parts of the scalars (the paper's kappa^s, eqs. kappa_S and the
+ * singular part of grad Phi_chi): the terms of negative order in R of the
+ * expansions, D0: n = 0, df and dg: n = 2, G_chi: n = 0.
+ *   D0^s = (k_a^2 - k_i^2) / (4 pi R),  df^s = dg^s = (k_a^2 - k_i^2) / (8 pi R),
+ *   G_chi^s = -(chi_a - chi_i) / (4 pi R^2)
+ */
+static void kernel_scalars_sing(const or_phys *ph, double R, cplx *D0, cplx *df,
+                                cplx *dg, cplx *Ge, cplx *Gm) {
+    cplx dk2 = ph->ka * ph->ka - ph->ki * ph->ki;
+    *D0 = dk2 / (4 * OR_PI * R);
+    *df = dk2 / (8 * OR_PI * R);
+    *dg = *df;
+    *Ge = -(ph->eps_a - ph->eps_i) / (4 * OR_PI * R * R);
+    *Gm = -(ph->mu_a - ph->mu_i) / (4 * OR_PI * R * R);
+}
+
+/*
+ * Regular remainders kernel - kernel^s.  For max|k| R < 1/2 (and at R = 0)
+ * the expansions without their singular terms, truncated after n = nterms;
+ * only non-negative powers of R remain, so R = 0 is an ordinary point.
+ * Otherwise the closed forms minus the singular parts.
+ */
+static void kernel_scalars_rem(const or_phys *ph, double R, cplx *D0, cplx *df,
+                               cplx *dg, cplx *Ge, cplx *Gm) {
+    double rho = fmax(cabs(ph->ka), cabs(ph->ki)) * R;
+    if (R > 0 && rho >= OR_SERIES_RHO) {
+        or_phys q = *ph;
+        q.mode = 1;
+        cplx s[5];
+        kernel_scalars(&q, R, D0, df, dg, Ge, Gm);
+        kernel_scalars_sing(ph, R, &s[0], &s[1], &s[2], &s[3], &s[4]);
+        *D0 -= s[0]; *df -= s[1]; *dg -= s[2]; *Ge -= s[3]; *Gm -= s[4];
+        return;
+    }
+    cplx ca = 1.0, ci = 1.0;
+    cplx sD = 0, sf = 0, sg = 0, se = 0, sm = 0;
+    for (int n = 0; n <= ph->nterms; ++n) {
+        if (n > 0) { ca *= I * ph->ka / n; ci *= I * ph->ki / n; }
+        if (n >= 1) sD += (ph->ka * ph->ka * ca - ph->ki * ph->ki * ci) * pow(R, n - 1);
+        if (n >= 3) {
+            cplx d = ca - ci;
+            if (n >= 4) sf += d * (double)((n - 1) * (n - 3)) * pow(R, n - 3);
+            sg -= d * (double)(n - 1) * pow(R, n - 3);
+        }
+        if (n >= 2) {
+            se += (ph->eps_a * ca - ph->eps_i * ci) * (double)(n - 1) * pow(R, n - 2);
+            sm += (ph->mu_a * ca - ph->mu_i * ci) * (double)(n - 1) * pow(R, n - 2);
+        }
+    }
+    *D0 = sD / (4 * OR_PI); *df = sf / (4 * OR_PI); *dg = sg / (4 * OR_PI);
+    *Ge = se / (4 * OR_PI); *Gm = sm / (4 * OR_PI);
+}
+
+/*
+ * The twelve scalar kernels at a test point X and a trial point Y from the
+ * scalars and the unit vector Rh = (x - y)/|x - y|:
  *  kappa1_ab = D0 (s_a . t_b) + s_a . H_diff . t_b          (eq. kappa1_alphabeta)
  *  kappa2_ab = (t_a . t_b)(n . grad Phi) - (t_a . grad Phi)(n . t_b)
  *                                                          (eq. kappa2_alpha_beta)
- * with H_diff built as a full 3x3 matrix and grad Phi as a vector.
+ * with H_diff = df Rh Rh^T - dg I built as a full 3x3 matrix and grad Phi
+ * = G Rh as a vector.
  */
-static void kappa12(const or_phys *ph, const or_point *X, const or_point *Y,
-                    cplx out[12]) {
-    double Rv[3], R, Rh[3];
-    for (int d = 0; d < 3; ++d) Rv[d] = X->x[d] - Y->x[d];
-    R = norm3(Rv);
-    for (int d = 0; d < 3; ++d) Rh[d] = Rv[d] / R;
-    cplx D0, df, dg, Ge, Gm;
-    kernel_scalars(ph, R, &D0, &df, &dg, &Ge, &Gm);
+static void kappa_combine(const or_point *X, const or_point *Y, const double Rh[3],
+                          cplx D0, cplx df, cplx dg, cplx Ge, cplx Gm, cplx out[12]) {
     cplx H[3][3], gE[3], gM[3];
     for (int a = 0; a < 3; ++a) {
         for (int b = 0; b < 3; ++b) H[a][b] = df * Rh[a] * Rh[b] - (a == b ? dg : 0.0);
@@ -335,6 +421,24 @@ static void kappa12(const or_phys *ph, const or_point *X, const or_point *Y,
         }
 }
 
+/* which = 0: the full kernels; 1: their singular parts; 2: the remainders.
+ * At coincident points (R = 0, only the remainders can be asked for there)
+ * the direction Rh is undefined; it multiplies df, which vanishes, and
+ * G_chi, whose contribution is taken as its average over directions, 0.   */
+static void kappa_eval(const or_phys *ph, const or_point *X, const or_point *Y,
+                       int which, cplx out[12]) {
+    double Rv[3], R, Rh[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) Rv[d] = X->x[d] - Y->x[d];
+    R = norm3(Rv);
+    if (R > 0)
+        for (int d = 0; d < 3; ++d) Rh[d] = Rv[d] / R;
+    cplx D0, df, dg, Ge, Gm;
+    if (which == 0) kernel_scalars(ph, R, &D0, &df, &dg, &Ge, &Gm);
+    else if (which == 1) kernel_scalars_sing(ph, R, &D0, &df, &dg, &Ge, &Gm);
+    else kernel_scalars_rem(ph, R, &D0, &df, &dg, &Ge, &Gm);
+    kappa_combine(X, Y, Rh, D0, df, dg, Ge, Gm, out);
+}
+
 /* ------------------------------------------------------------------ */
 /* element-pair integration                                             */
 /* ------------------------------------------------------------------ */
@@ -352,17 +456,23 @@ static int pair_class(const or_mesh *m, int64_t e, int64_t f, int sh_e[3],
     return n;
 }
 
-/* Accumulate w * N_i(x) N_j(y) kappa_c(x,y) into blk[i][j][c].          */
-static void accumulate(const or_phys *ph, const or_point *X, const or_point *Y,
-                       double w, cplx blk[6][6][12]) {
+/* Accumulate w * N_i(x) N_j(y) kappa_c(x,y) into blk[i][j][c]; `which`
+ * selects the full kernels, their singular parts or the remainders.      */
+static void accumulate_k(const or_phys *ph, const or_point *X, const or_point *Y,
+                         double w, int which, cplx blk[6][6][12]) {
     cplx k[12];
-    kappa12(ph, X, Y, k);
+    kappa_eval(ph, X, Y, which, k);
     double ww = w * X->J * Y->J;
     for (int i = 0; i < 6; ++i)
         for (int j = 0; j < 6; ++j) {
             double s = ww * X->N[i] * Y->N[j];
             for (int c = 0; c < 12; ++c) blk[i][j][c] += s * k[c];
         }
+}
+
+static void accumulate(const or_phys *ph, const or_point *X, const or_point *Y,
+                       double w, cplx blk[6][6][12]) {
+    accumulate_k(ph, X, Y, w, 0, blk);
 }
 
 /*
@@ -451,7 +561,24 @@ static void pair_block(const or_mesh *m, const or_phys *ph, int64_t e,
     memset(blk, 0, sizeof(cplx) * 6 * 6 * 12);
     int sh_e[3], sh_f[3];
     int cls = pair_class(m, e, f, sh_e, sh_f);
-    if (cls == 0) {
+    if (ph->variant == 1) {
+        /* 12-point rule: every regular pair with the closed-form kernels
+         * (the truncated series is for singular pairs only), every singular
+         * pair for the remainder kernel - kernel^s                          */
+        double xi[12], eta[12], w[12];
+        or_rule12(xi, eta, w);
+        or_point X[12], Y[12];
+        for (int q = 0; q < 12; ++q) {
+            point_data(m, e, xi[q], eta[q], &X[q]);
+            point_data(m, f, xi[q], eta[q], &Y[q]);
+        }
+        or_phys q = *ph;
+        if (q.mode == 0) q.mode = 1;
+        for (int p = 0; p < 12; ++p)
+            for (int r = 0; r < 12; ++r)
+                accumulate_k(&q, &X[p], &Y[r], w[p] * w[r], cls == 0 ? 0 : 2, blk);
+        if (cls == 0) return;
+    } else if (cls == 0) {
         double xi[7], eta[7], w[7];
         or_rule7(xi, eta, w);
         or_point X[7], Y[7];
@@ -480,7 +607,8 @@ static void pair_block(const or_mesh *m, const or_phys *ph, int64_t e,
                         or_point X, Y;
                         point_data(m, e, x1, y1, &X);
                         point_data(m, f, x2, y2, &Y);
-                        accumulate(ph, &X, &Y, jac * gw[a] * gw[b] * gw[c] * gw[d], blk);
+                        accumulate_k(ph, &X, &Y, jac * gw[a] * gw[b] * gw[c] * gw[d],
+                                     ph->variant == 1 ? 1 : 0, blk);
                     }
 }
 
@@ -488,7 +616,7 @@ static void pair_block(const or_mesh *m, const or_phys *ph, int64_t e,
 /* exported entry points (ctypes)                                       */
 /* ------------------------------------------------------------------ */
 
-/* phys[] = {k0, Re eps_r, Im eps_r, Re mu_r, Im mu_r}                    */
+/* phys[] = {k0, Re eps_r, Im eps_r, Re mu_r, Im mu_r, variant}           */
 static or_phys make_phys(const double *phys, int nss, int mode) {
     or_phys ph;
     cplx er = phys[1] + I * phys[2], mr = phys[3] + I * phys[4];
@@ -498,6 +626,8 @@ static or_phys make_phys(const double *phys, int nss, int mode) {
     ph.ki = phys[0] * csqrt(er * mr);
     if (cimag(ph.ki) < 0) ph.ki = -ph.ki;
     ph.nss = nss; ph.mode = mode;
+    ph.variant = (int)phys[5];
+    ph.nterms = ph.variant == 1 ? 6 : OR_SERIES_TERMS;
     return ph;
 }
 
@@ -552,13 +682,16 @@ int or_point_data(const double *xyz, int64_t nn, const int64_t *tri, int64_t nt,
     return 0;
 }
 
-/* kernel scalars at distances R[n]; out[n*10] = D0, df, dg, Ge, Gm (re,im) */
+/* kernel scalars at distances R[n]; out[n*10] = D0, df, dg, Ge, Gm (re,im);
+ * mode 0 hybrid, 1 closed form, 2 series, 3 singular parts, 4 remainders */
 int or_kernel_scalars(const double *phys, int mode, int64_t n, const double *R,
                       double *out) {
     or_phys ph = make_phys(phys, 4, mode);
     for (int64_t i = 0; i < n; ++i) {
         cplx v[5];
-        kernel_scalars(&ph, R[i], &v[0], &v[1], &v[2], &v[3], &v[4]);
+        if (mode == 3) kernel_scalars_sing(&ph, R[i], &v[0], &v[1], &v[2], &v[3], &v[4]);
+        else if (mode == 4) kernel_scalars_rem(&ph, R[i], &v[0], &v[1], &v[2], &v[3], &v[4]);
+        else kernel_scalars(&ph, R[i], &v[0], &v[1], &v[2], &v[3], &v[4]);
         for (int k = 0; k < 5; ++k) { out[10 * i + 2 * k] = creal(v[k]); out[10 * i + 2 * k + 1] = cimag(v[k]); }
     }
     return 0;
