@@ -20,6 +20,15 @@ One step = the whole hot path, both precisions side by side:
          block-Jacobi setup -> 128 right-hand sides -> block GMRES (complex
          FP32 GEMM on the matrix cores, FP64 refinement) to 1e-8 -> far
          fields in the 64 incidence directions.
+  PRECONDITIONER STUDY (once, after the timed steps): FP64 operators of the
+         1280-triangle sphere and the 5120-triangle spheroid (1, 1, 2),
+         k_a = 4, eps_r = -10 + 1i; GMRES to 1e-5 without a preconditioner
+         and with Morton block-Jacobi for clusters of 50, 100, 256 and 512:
+         iterations, setup and solve times.
+  QUADRATURE STUDY (once): the paper's own scheme (12-point rule, Sauter-
+         Schwab on the singular kernels only, 12-point remainder) against the
+         default on the same sphere, FP64 and mixed: fill times and far-field
+         differences.
 Metric: Z-fill rate N^2 / t_fill (entries/s) of the mixed path when its far
 field is within 1e-6 of the FP64 path's, otherwise of the FP64 path; GMRES
 solve seconds of both are reported beside it.  The multi-RHS pass reports
@@ -90,10 +99,14 @@ def parse():
     ap.add_argument("--paths", default="fp64,mixed")
     ap.add_argument("--no-mrhs", action="store_true", help="skip the 128-RHS block solve pass")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint gradient pass")
+    ap.add_argument("--no-precond-study", action="store_true",
+                    help="skip the preconditioner study (GMRES without vs with block-Jacobi)")
+    ap.add_argument("--no-quad-study", action="store_true",
+                    help="skip the comparison of the default quadrature with the paper's scheme")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device to device once (scales the FETCH_SIZE / WRITE_SIZE "
                          "counters) and exit")
-    ap.add_argument("--only", choices=["all", "main", "mrhs", "grad"], default="all",
+    ap.add_argument("--only", choices=["all", "main", "mrhs", "grad", "precond", "quad"], default="all",
                     help="run one pass of the step only (for profiling); the JSON line is "
                          "printed for 'all' and 'main'")
     return ap.parse_args()
@@ -115,6 +128,85 @@ def cpu_baseline(xyz, tri, cfg, N):
                       f"pairs) of the same mesh, {dt:.2f} s"}
 
 
+PRECOND_STUDY = (("sphere1280", (50, 100, 256, 512), 1500),
+                 ("spheroid5120", (50, 100, 256, 512), 2000))
+PRECOND_TOL = 1e-5        # the tolerance of the paper's preconditioner comparisons
+
+
+def precond_study(mbem, get_config, icosphere_p2, planewaves, log):
+    """GMRES iterations and times without a preconditioner and with Morton
+    block-Jacobi over a sweep of the cluster size, FP64 operator, one plane
+    wave, tolerance 1e-5; run once after the timed steps."""
+    out = {}
+    for wl, blocks, maxit in PRECOND_STUDY:
+        c = get_config(wl)
+        xyz, tri = icosphere_p2(c["n_tris"], c["axes"])
+        kh, po = planewaves(wl)
+        S = mbem.Solver(xyz, tri, c["k0"], c["eps_r"], c["mu_r"], precision=mbem.MBEM_FP64)
+        try:
+            fs = S.fill()
+            b = S.rhs(kh, po)
+            n2 = S.N // 2
+            res = {"unknowns": S.N, "k0": c["k0"], "eps_r": str(c["eps_r"]), "tol": PRECOND_TOL,
+                   "precision": "fp64", "t_fill_ms": fs.t_fill_ms}
+            S.precond_setup(0)
+            x, st, code = S.solve(b, tol=PRECOND_TOL, maxit=maxit)
+            base = {"iters": st.iters, "t_solve_ms": st.t_solve_ms, "converged": code == 0,
+                    "rel_resid": st.rel_resid}
+            res["none"] = base
+            log(f"precond study {wl}: no preconditioner {st.iters} iterations")
+            for B in blocks:
+                ps = S.precond_setup(B)
+                x, st, code = S.solve(b, tol=PRECOND_TOL, maxit=maxit)
+                nb = (n2 + B - 1) // B
+                res[f"B{B}"] = {"blocks": nb, "mbytes": nb * (2 * B) ** 2 * 16 / 1e6,
+                                "t_setup_ms": ps.t_setup_ms, "iters": st.iters,
+                                "t_solve_ms": st.t_solve_ms, "converged": code == 0,
+                                "rel_resid": st.rel_resid,
+                                "iter_reduction": base["iters"] / max(1, st.iters),
+                                "solve_speedup": base["t_solve_ms"] / max(1e-9, st.t_solve_ms)}
+                log(f"precond study {wl}: B = {B}, {st.iters} iterations")
+            out[wl] = res
+        finally:
+            S.close()
+    return out
+
+
+def quad_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3):
+    """The paper's own quadrature (12-point rule, Sauter-Schwab on the
+    singular kernels, 12-point remainder) against the default on the
+    1280-triangle sphere: fill times and the far-field difference of the two
+    (FP64 and mixed), GMRES to 1e-8."""
+    c = get_config("sphere1280")
+    xyz, tri = icosphere_p2(c["n_tris"], c["axes"])
+    kh, po = planewaves("sphere1280")
+    out = {"workload": "sphere1280", "unknowns": None}
+    F = {}
+    for name, prec, quad in (("default_fp64", mbem.MBEM_FP64, mbem.MBEM_QUAD_DEFAULT),
+                             ("paper_fp64", mbem.MBEM_FP64, mbem.MBEM_QUAD_PAPER),
+                             ("default_mixed", mbem.MBEM_MIXED, mbem.MBEM_QUAD_DEFAULT),
+                             ("paper_mixed", mbem.MBEM_MIXED, mbem.MBEM_QUAD_PAPER)):
+        S = mbem.Solver(xyz, tri, c["k0"], c["eps_r"], c["mu_r"], precision=prec, quadrature=quad)
+        try:
+            fs = [S.fill() for _ in range(reps + 1)][1:]
+            S.precond_setup(c["mbj_block"])
+            x, st, code = S.solve(S.rhs(kh, po), tol=c["tol"], maxit=600, inner_tol=1e-4)
+            F[name] = S.farfield(x, rdirs).cpu().numpy()[0]
+            out["unknowns"] = S.N
+            out[name] = {"t_fill_ms": float(np.mean([f.t_fill_ms for f in fs])),
+                         "t_regular_ms": float(np.mean([f.t_regular_ms for f in fs])),
+                         "t_singular_ms": float(np.mean([f.t_ssq_ms for f in fs])),
+                         "fill_rate": S.N ** 2 / (1e-3 * float(np.mean([f.t_fill_ms for f in fs]))),
+                         "iters": st.iters, "converged": code == 0}
+            log(f"quadrature study: {name} fill {out[name]['t_fill_ms']:.2f} ms")
+        finally:
+            S.close()
+    rel = lambda a, b: float(np.linalg.norm(F[a] - F[b]) / np.linalg.norm(F[b]))
+    out["farfield_paper_vs_default_fp64"] = rel("paper_fp64", "default_fp64")
+    out["farfield_paper_mixed_vs_paper_fp64"] = rel("paper_mixed", "paper_fp64")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -134,15 +226,21 @@ def main():
     from workloads import get_config, icosphere_p2, planewaves
     from workloads.configs import cut_plane_directions
 
-    if args.only in ("mrhs", "grad"):
+    if args.only in ("mrhs", "grad", "precond", "quad"):
         args.paths = ""
         args.no_cpu_baseline = True
     if args.only == "main":
-        args.no_mrhs = args.no_grad = True
+        args.no_mrhs = args.no_grad = args.no_precond_study = args.no_quad_study = True
     if args.only == "mrhs":
-        args.no_grad = True
+        args.no_grad = args.no_precond_study = args.no_quad_study = True
     if args.only == "grad":
-        args.no_mrhs = True
+        args.no_mrhs = args.no_precond_study = args.no_quad_study = True
+    if args.only == "precond":
+        args.no_mrhs = args.no_grad = args.no_quad_study = True
+        args.steps, args.warmup = 0, 0
+    if args.only == "quad":
+        args.no_mrhs = args.no_grad = args.no_precond_study = True
+        args.steps, args.warmup = 0, 0
     cfg = get_config(args.workload)
     xyz, tri = icosphere_p2(cfg["n_tris"], cfg["axes"])
     khat, pol = planewaves(args.workload)
@@ -214,7 +312,7 @@ def main():
         log(f"step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_per_step = 1e3 * wall / args.steps
+    ms_per_step = 1e3 * wall / max(1, args.steps)
 
     def mean(path, sect, key):
         return float(np.mean([r[path][sect][key] for r in recs]))
@@ -364,10 +462,18 @@ def main():
             "adjoint_iters": int(gr[-1]["adj"]["iters"]),
         }
 
+    pstudy = None
+    if not args.no_precond_study:
+        pstudy = precond_study(mbem, get_config, icosphere_p2, planewaves, log)
+    qstudy = None
+    if not args.no_quad_study:
+        qstudy = quad_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log)
+
     if not paths:
         # profiling run of one pass: its own section only
         print(json.dumps({"pass": args.only, "steps": args.steps, "warmup": args.warmup,
-                          "ms_per_step": ms_per_step, "multi_rhs": mrhs, "gradient": grad}), flush=True)
+                          "ms_per_step": ms_per_step, "multi_rhs": mrhs, "gradient": grad,
+                          "precond_study": pstudy, "quadrature_study": qstudy}), flush=True)
         for S in (Smr, Sg):
             if S is not None:
                 S.close()
@@ -399,6 +505,8 @@ def main():
         "rooflines": rooflines,
         "multi_rhs": mrhs,
         "gradient": grad,
+        "precond_study": pstudy,
+        "quadrature_study": qstudy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -81,7 +81,20 @@ typedef struct {
     double near_radius;         /* MIXED: element pairs whose gap is below
                                    this are computed in FP64; <= 0 selects
                                    1.89 / sqrt|k_a^2 - k_i^2|                */
+    int32_t quadrature;         /* MBEM_QUAD_DEFAULT or MBEM_QUAD_PAPER      */
 } mbem_params;
+
+/* Quadrature of the operator blocks.
+ * MBEM_QUAD_DEFAULT: the 7-point rule on every regular element pair (closed
+ *   forms, or the Taylor series to n = 16 below max|k| R = 1/2), Sauter-
+ *   Schwab on the full kernels of every singular pair.
+ * MBEM_QUAD_PAPER: the paper's own scheme (Sec. 4.1-4.2, 6.1): the 12-point
+ *   degree-6 rule on every regular pair with the closed-form kernels;
+ *   Sauter-Schwab on the singular kernels kappa^s only (their terms of
+ *   negative order in R), the remainder kappa - kappa^s by the 12-point rule
+ *   on the same pair with the Taylor series truncated after n = 6.  Fill and
+ *   solve only: mbem_fill_deps and mbem_grad_sigma_ext reject it.          */
+enum { MBEM_QUAD_DEFAULT = 0, MBEM_QUAD_PAPER = 1 };
 
 typedef struct {
     double tol;          /* relative residual target |b - Z x| / |b|        */
@@ -185,10 +198,10 @@ int mbem_matvec(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *x,
 /* ---- preconditioner (Sec. 5, eq. precond_block) --------------------------- */
 
 /* Morton block-Jacobi: clusters of `block` consecutive indices of one
- * current's vector (block <= 256); each block is the 2 block x 2 block
+ * current's vector (block <= 512); each block is the 2 block x 2 block
  * restriction of Z, LU-factorised with partial pivoting (blocked, in FP64)
  * and inverted explicitly (the apply is then one matrix-vector product).
- * MBEM_ESINGULAR on a zero pivot, MBEM_EINVAL for block > 256.
+ * MBEM_ESINGULAR on a zero pivot, MBEM_EINVAL for block > 512.
  * block <= 0 removes the preconditioner.                                   */
 int mbem_precond_setup(mbem_ctx *ctx, mbem_op *op, int32_t block,
                        mbem_stats *stats);

@@ -61,7 +61,7 @@ static int set_device(const mbem_ctx *ctx) {
 static void mesh_free_device(mbem_mesh *m) {
     void *ps[] = {m->d_xyz, m->d_tri, m->d_inc_ptr, m->d_inc, m->d_spairs, m->d_frames,
                   m->d_qp, m->d_qp32, m->d_elem, m->d_mptr, m->d_mcol, m->d_mslot,
-                  m->d_chunks, m->d_tcol, m->d_ccol};
+                  m->d_chunks, m->d_tcol, m->d_ccol, m->d_qp12, m->d_qp12_32};
     for (void *p : ps) dfree(p);
 }
 
@@ -337,7 +337,8 @@ int mbem_mesh_create(mbem_ctx *ctx, const double *xyz, int64_t n_nodes, const in
         (st = upload(&m->d_chunks, T.chunks, s)) || (st = upload(&m->d_tcol, T.tcol_list, s)) ||
         (st = upload(&m->d_ccol, T.ccol_list, s)) ||
         (st = dalloc(&m->d_frames, 9 * m->nn)) || (st = dalloc(&m->d_qp, kQPF * nq)) ||
-        (st = dalloc(&m->d_qp32, kQPF * nq)) || (st = dalloc(&m->d_elem, 4 * m->nt)))
+        (st = dalloc(&m->d_qp32, kQPF * nq)) || (st = dalloc(&m->d_elem, 4 * m->nt)) ||
+        (st = dalloc(&m->d_qp12, kQPF * m->nt * kQP12)) || (st = dalloc(&m->d_qp12_32, kQPF * m->nt * kQP12)))
         return fail(st);
     if ((st = geom_build(m, s))) return fail(st);
     if (hipStreamSynchronize(s) != hipSuccess) { set_error("mesh upload failed"); return fail(MBEM_EDEVICE); }
@@ -385,6 +386,10 @@ static int op_create(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p,
     if (p->precision != MBEM_FP64 && p->precision != MBEM_MIXED) { set_error("bad precision"); return MBEM_EINVAL; }
     if (!(p->k0 > 0)) { set_error("k0 must be positive"); return MBEM_EINVAL; }
     if (p->ssq_order < 0 || p->ssq_order > kMaxSSQ) { set_error("ssq_order out of range"); return MBEM_EINVAL; }
+    if (p->quadrature != MBEM_QUAD_DEFAULT && p->quadrature != MBEM_QUAD_PAPER) {
+        set_error("unknown quadrature scheme");
+        return MBEM_EINVAL;
+    }
     MBEM_TRY(set_device(ctx));
     mbem_op *op = new (std::nothrow) mbem_op;
     if (!op) { set_error("host allocation"); return MBEM_ENOMEM; }
@@ -600,6 +605,10 @@ int mbem_solve_adjoint(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *g, int32_t n
 
 int mbem_fill_deps(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_op **out, mbem_stats *stats) {
     if (!p) { set_error("null argument"); return MBEM_EINVAL; }
+    if (p->quadrature != MBEM_QUAD_DEFAULT) {
+        set_error("the eps derivative is built for the default quadrature only");
+        return MBEM_EINVAL;
+    }
     mbem_params q = *p;
     q.precision = MBEM_FP64;
     mbem_op *op = nullptr;
@@ -626,6 +635,10 @@ int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh, const
                         double *out, mbem_c128 *lambda_out, double *dsig_dnode, double *dsig_dx,
                         mbem_stats *stats) {
     if (!op || !mesh || !p || !x || !khat || !pol || !o || !out) { set_error("null argument"); return MBEM_EINVAL; }
+    if (p->quadrature != MBEM_QUAD_DEFAULT || op->p.quadrature != MBEM_QUAD_DEFAULT) {
+        set_error("the gradient is built for the default quadrature only");
+        return MBEM_EINVAL;
+    }
     MBEM_TRY(set_device(ctx));
     const hipStream_t s = ctx->stream;
     const int64_t N = 2 * op->n2;

@@ -14,6 +14,7 @@
 #include <type_traits>
 
 #include "mbem_internal.h"
+#include "kappa.h"
 #include "p2_device.h"
 #include "ssq_map.h"
 
@@ -32,42 +33,6 @@ __device__ inline int64_t xcd_remap(int64_t bid, int64_t total) {
     const int64_t q = total / 8, r = total % 8;
     const int64_t xcd = bid % 8, local = bid / 8;
     return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
-}
-
-// Twelve weighted kernel values (eqs. kappa1_alphabeta, kappa2_alpha_beta)
-// at a test point (x, n, t_a, s_a) and a trial point (y, t_b):
-//   kappa1_ab = (D0 - dg)(s_a.t_b) + df (s_a.R)(R.t_b)
-//   kappa2_ab = G_chi [(t_a.t_b)(n.R) - (t_a.R)(n.t_b)],  R = (x - y)/|x - y|
-// output order c = 4 op + 2 a + b, op: K1, K2^eps, K2^mu.
-template <typename T, bool DK = false>
-__device__ __forceinline__ void kappa12(const KernelConst &K, vec3<T> x, vec3<T> n,
-                               const vec3<T> ta[2], const vec3<T> sa[2],
-                               vec3<T> y, const vec3<T> tb[2], T ww,
-                               cx<T> out[12]) {
-    vec3<T> Rv = x - y;
-    const T R = sqrt(dot(Rv, Rv));
-    const vec3<T> Rh = ((T)1 / R) * Rv;
-    KScal<T> s;
-    if constexpr (DK) s = kernel_scalars_deps(K, R);
-    else s = kernel_scalars<T>(K, R);
-    const cx<T> A = s.D0 - s.dg;
-    const T nR = dot(n, Rh);
-    T tRy[2], ntb[2];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) { tRy[b] = dot(tb[b], Rh); ntb[b] = dot(n, tb[b]); }
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const T sR = dot(sa[a], Rh), tR = dot(ta[a], Rh);
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const T st = dot(sa[a], tb[b]);
-            const T g2 = dot(ta[a], tb[b]) * nR - tR * ntb[b];
-            const cx<T> k1 = st * A + (sR * tRy[b]) * s.df;
-            out[0 + 2 * a + b] = ww * k1;
-            out[4 + 2 * a + b] = (ww * g2) * s.Ge;
-            out[8 + 2 * a + b] = (ww * g2) * s.Gm;
-        }
-    }
 }
 
 // ---------------------------------------------------- regular pairs ---
@@ -484,6 +449,305 @@ __global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 
     }
 }
 
+// ------------------------------------- the paper's own scheme ---
+// Regular pairs on the 12-point rule (144 point pairs per element pair) and
+// singular pairs as Sauter-Schwab on kappa^s plus the 12-point rule on the
+// remainder kappa - kappa^s.  Same tiles, colour classes and chunk records
+// as k_regular; the chunk's four trial triangles are taken one at a time:
+//  A: 144 lanes, one point pair each: kernel values into s_k[c][pair];
+//  B: 144 lanes (c, p): the trial-side contraction of the 12 values of
+//     (c, p) into s_tf[c][fs][p][j];
+//  C: as in k_regular, with the test-side contraction over 12 points.
+constexpr int kPP12 = kQP12 * kQP12;
+constexpr int kK12Stride = 145;     // = 1 mod 16: consecutive components spread over the banks
+
+__host__ __device__ constexpr double n12(int q, int j) {
+    const double L0 = r12_bary(q, 0), L1 = r12_bary(q, 1), L2 = r12_bary(q, 2);
+    return j == 0 ? L0 * (2.0 * L0 - 1.0) : j == 1 ? L1 * (2.0 * L1 - 1.0)
+         : j == 2 ? L2 * (2.0 * L2 - 1.0) : j == 3 ? 4.0 * L0 * L1
+         : j == 4 ? 4.0 * L1 * L2 : 4.0 * L2 * L0;
+}
+
+template <typename T>
+__device__ __forceinline__ void contract12(const cx<T> v[kQP12], cx<T> out[6]) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        cx<T> acc = {0, 0};
+#pragma unroll
+        for (int q = 0; q < kQP12; ++q) acc = acc + (T)n12(q, j) * v[q];
+        out[j] = acc;
+    }
+}
+
+template <typename T, typename TS>
+__global__ __launch_bounds__(256) void k_regular12(RegArgs<T, TS> a) {
+    __shared__ cx<T> s_k[12 * kK12Stride];
+    __shared__ cx<T> s_tf[12 * kChunk * kQP12 * 6];   // [c][fs][p][j]
+    constexpr bool kF64 = std::is_same<TS, double>::value;
+    __shared__ __align__(16) TS s_dst[kF64 ? 1 : 2 * 6 * kItemsMax];
+    constexpr int kRounds = (kItemsMax + 255) / 256;
+    double2 pre[kF64 ? kRounds : 1][6];
+    __shared__ int64_t s_row[6][6];
+    __shared__ int32_t s_rec[kChunkRec];
+    __shared__ int s_act[kChunk];
+    __shared__ KernelConst s_K;
+    const int tid = threadIdx.x;
+    stage_kconst(a.K, &s_K, tid, blockDim.x);
+    const int64_t tile = xcd_remap(blockIdx.x, a.total);
+    const int64_t e = a.te_list[tile / a.n_ch];
+    const int64_t ch = a.ch_list[tile % a.n_ch];
+    for (int i = tid; i < kChunkRec; i += blockDim.x) s_rec[i] = a.chunks[ch * kChunkRec + i];
+    if (tid < 36) {
+        const int g = tid / 6, i = tid % 6;
+        s_row[g][i] = 2 * (2 * (int64_t)a.tri[6 * e + i] + (g & 1)) * a.n2;
+    }
+    if (tid < kChunk) {
+        const int64_t f = ch * kChunk + tid;
+        bool act = f < a.nt;
+        if (act) {
+            const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) act = act && (te[i] != tf[j]);
+        }
+        int kind = act ? 1 : 0;
+        if (act && a.mode == 1) {
+            const double *ce = a.einfo + 4 * e, *cf = a.einfo + 4 * f;
+            const double dx = ce[0] - cf[0], dy = ce[1] - cf[1], dz = ce[2] - cf[2];
+            if (sqrt(dx * dx + dy * dy + dz * dz) - ce[3] - cf[3] < a.near_r) {
+                kind = 2;
+                atomicAdd(a.near_count, 1ull);
+            }
+        }
+        s_act[tid] = kind;
+    }
+    __syncthreads();
+    int any = 0;
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) any |= s_act[k];
+    if (!any) return;
+    const int ns = s_rec[0];
+    const int rowlen = 2 * ns;
+    const int nitems = 6 * rowlen;
+    const float inv_rowlen = 1.0f / (float)rowlen;
+    {
+        const int wave = tid / 64;
+#pragma unroll
+        for (int k = 0; k < kRounds; ++k) {
+            const int base = 256 * k, it = base + tid;
+            const bool on = it < nitems;
+            const int itc = on ? it : 0;
+            const int g = (int)(((float)itc + 0.5f) * inv_rowlen);
+            const int rem = itc - g * rowlen;
+            const int sl = rem >> 1, be = rem & 1, op = g >> 1;
+            const int64_t col = 2 * (2 * (int64_t)s_rec[1 + sl] + be);
+            const TS *Z = zblock(a.Z, op) + col;
+            const int first = base + wave * 64;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                const TS *src = Z + s_row[g][i];
+                if constexpr (kF64) {
+                    if (on) pre[k][i] = *(const double2 *)src;
+                } else {
+                    TS *dre = s_dst + (2 * i) * kItemsMax + first, *dim = s_dst + (2 * i + 1) * kItemsMax + first;
+                    if (on) {
+                        __builtin_amdgcn_global_load_lds((const void *)src,
+                                                         (__attribute__((address_space(3))) void *)dre, 4, 0, 0);
+                        __builtin_amdgcn_global_load_lds((const void *)(src + 1),
+                                                         (__attribute__((address_space(3))) void *)dim, 4, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    const int64_t nq = a.nt * kQP12;
+    const int pl = tid / kQP12, ql = tid % kQP12;      // point pair of lane tid < 144
+    for (int fs = 0; fs < kChunk; ++fs) {
+        const int kind = s_act[fs];                     // uniform
+        if (tid < kPP12) {
+            cx<T> k[12];
+            const int64_t ix = e * kQP12 + pl, iy = (ch * kChunk + fs) * kQP12 + ql;
+            if (kind == 1) {
+                const vec3<T> x = qload(a.qp, nq, QX, ix), n = qload(a.qp, nq, QN, ix);
+                const vec3<T> ta[2] = {qload(a.qp, nq, QT1, ix), qload(a.qp, nq, QT2, ix)};
+                const vec3<T> sa[2] = {qload(a.qp, nq, QS1, ix), qload(a.qp, nq, QS2, ix)};
+                const vec3<T> y = qload(a.qp, nq, QX, iy);
+                const vec3<T> tb[2] = {qload(a.qp, nq, QT1, iy), qload(a.qp, nq, QT2, iy)};
+                const T ww = a.qp[(int64_t)QW * nq + ix] * a.qp[(int64_t)QW * nq + iy];
+                kappa12<T>(s_K, x, n, ta, sa, y, tb, ww, k);
+            } else if (!std::is_same<T, double>::value && kind == 2) {
+                const double *q64 = a.qp64;
+                const dvec3 x = qload(q64, nq, QX, ix), n = qload(q64, nq, QN, ix);
+                const dvec3 ta[2] = {qload(q64, nq, QT1, ix), qload(q64, nq, QT2, ix)};
+                const dvec3 sa[2] = {qload(q64, nq, QS1, ix), qload(q64, nq, QS2, ix)};
+                const dvec3 y = qload(q64, nq, QX, iy);
+                const dvec3 tb[2] = {qload(q64, nq, QT1, iy), qload(q64, nq, QT2, iy)};
+                const double ww = q64[(int64_t)QW * nq + ix] * q64[(int64_t)QW * nq + iy];
+                cx<double> kd[12];
+                kappa12<double>(s_K, x, n, ta, sa, y, tb, ww, kd);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) k[c] = cx<T>{(T)kd[c].re, (T)kd[c].im};
+            } else {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) k[c] = cx<T>{0, 0};
+            }
+#pragma unroll
+            for (int c = 0; c < 12; ++c) s_k[c * kK12Stride + tid] = k[c];
+        }
+        __syncthreads();
+        if (tid < kPP12) {
+            const int c = tid / kQP12, p = tid % kQP12;
+            cx<T> kv[kQP12], tf[6];
+#pragma unroll
+            for (int q = 0; q < kQP12; ++q) kv[q] = s_k[c * kK12Stride + p * kQP12 + q];
+            contract12(kv, tf);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) s_tf[((c * kChunk + fs) * kQP12 + p) * 6 + j] = tf[j];
+        }
+        __syncthreads();
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k) {
+        const int it = 256 * k + tid;
+        if (it >= nitems) break;
+        const int g = (int)(((float)it + 0.5f) * inv_rowlen);
+        const int rem = it - g * rowlen;
+        const int sl = rem >> 1, be = rem & 1, op = g >> 1;
+        const int c = 2 * g + be;
+        cx<T> tv[kQP12];
+#pragma unroll
+        for (int p = 0; p < kQP12; ++p) tv[p] = cx<T>{0, 0};
+        const int u1 = s_rec[26 + sl];
+        for (int u = s_rec[25 + sl]; u < u1; ++u) {
+            const int fl = s_rec[50 + u];
+            const cx<T> *src = s_tf + ((c * kChunk + (fl >> 3)) * kQP12) * 6 + (fl & 7);
+#pragma unroll
+            for (int p = 0; p < kQP12; ++p) tv[p] = tv[p] + src[6 * p];
+        }
+        TS *Z = zblock(a.Z, op) + 2 * (2 * (int64_t)s_rec[1 + sl] + be);
+        cx<T> out[6];
+        contract12(tv, out);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            TS *dst = Z + s_row[g][i];
+            TS ore, oim;
+            if constexpr (kF64) {
+                ore = pre[k][i].x;
+                oim = pre[k][i].y;
+            } else {
+                ore = s_dst[(2 * i) * kItemsMax + it];
+                oim = s_dst[(2 * i + 1) * kItemsMax + it];
+            }
+            dst[0] = ore + (TS)out[i].re;
+            dst[1] = oim + (TS)out[i].im;
+        }
+    }
+}
+
+// Singular pairs of the paper's scheme, one launch: per pair the Sauter-
+// Schwab points with the singular kernels kappa^s, then the 144 point pairs
+// of the 12-point rule with the remainders (constants a.K[0] = the kernels,
+// a.K[1] = the shifted truncated series of the remainders); the
+// accumulation into the pair's 6 x 6 x 12 block is that of k_ssq.
+template <typename TS>
+__global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
+void k_ssq_paper(SsqArgs<TS> a) {
+    __shared__ double s_pt[kSsqThreads * kPtStride];
+    const int tid = threadIdx.x;
+    const int64_t pid = blockIdx.x;
+    const int32_t e = a.pairs[4 * pid], f = a.pairs[4 * pid + 1];
+    const int cls = a.pairs[4 * pid + 2], code = a.pairs[4 * pid + 3];
+    const int n = a.order, n4 = n * n * n * n;
+    const int nreg = cls == 3 ? 6 : (cls == 2 ? 5 : 2);
+    const int nssq = nreg * n4, npts = nssq + kPP12;
+    const int comp = tid % 24, stream = tid / 24;
+    const bool consumer = tid < 24 * kStreams;
+    double acc[36];
+#pragma unroll
+    for (int k = 0; k < 36; ++k) acc[k] = 0.0;
+    for (int base = 0; base < npts; base += kSsqThreads) {
+        const int idx = base + tid;
+        double *pt = s_pt + tid * kPtStride;
+        if (idx < npts) {
+            P2Point X, Y;
+            cx<double> k[12];
+            if (idx < nssq) {
+                const int r = idx / n4;
+                int g = idx % n4;
+                const int i3 = g % n; g /= n;
+                const int i2 = g % n; g /= n;
+                const int i1 = g % n; g /= n;
+                const int i0 = g;
+                double s1, t1, s2, t2;
+                const double jac = ss_region(cls, r, a.glx[i0], a.glx[i1], a.glx[i2], a.glx[i3], s1, t1, s2, t2);
+                const double wg = jac * a.glw[i0] * a.glw[i1] * a.glw[i2] * a.glw[i3];
+                double xe, ye, xf, yf;
+                ss_local(code & 63, s1, t1, xe, ye);
+                ss_local(code >> 6, s2, t2, xf, yf);
+                p2_point(a.xyz, a.frames, a.tri + 6 * e, xe, ye, X);
+                p2_point(a.xyz, a.frames, a.tri + 6 * f, xf, yf, Y);
+                const dvec3 ta[2] = {X.t1, X.t2}, sa[2] = {X.s1, X.s2}, tb[2] = {Y.t1, Y.t2};
+                kappa12_sing(a.K[0], X.x, X.n, ta, sa, Y.x, tb, wg * X.J * Y.J, k);
+            } else {
+                const int rr = idx - nssq, p = rr / kQP12, q = rr % kQP12;
+                double xe, ye, we, xf, yf, wf;
+                rule12(p, xe, ye, we);
+                rule12(q, xf, yf, wf);
+                p2_point(a.xyz, a.frames, a.tri + 6 * e, xe, ye, X);
+                p2_point(a.xyz, a.frames, a.tri + 6 * f, xf, yf, Y);
+                const dvec3 ta[2] = {X.t1, X.t2}, sa[2] = {X.s1, X.s2}, tb[2] = {Y.t1, Y.t2};
+                kappa12_rem(a.K[0], a.K[1], X.x, X.n, ta, sa, Y.x, tb, we * wf * X.J * Y.J, k);
+            }
+#pragma unroll
+            for (int q = 0; q < 12; ++q) { pt[2 * q] = k[q].re; pt[2 * q + 1] = k[q].im; }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) { pt[24 + q] = X.N[q]; pt[30 + q] = Y.N[q]; }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 36; ++q) pt[q] = 0.0;
+        }
+        __syncthreads();
+        if (consumer) {
+            for (int r = stream; r < kSsqThreads; r += kStreams) {
+                const double *row = s_pt + r * kPtStride;
+                const double kv = row[comp];
+                double u[6];
+#pragma unroll
+                for (int j = 0; j < 6; ++j) u[j] = row[30 + j] * kv;
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    const double nx = row[24 + i];
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) acc[6 * i + j] += nx * u[j];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (consumer) {
+#pragma unroll
+        for (int k = 0; k < 36; ++k) s_pt[(stream * 36 + k) * 24 + comp] = acc[k];
+    }
+    __syncthreads();
+    const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
+    for (int it = tid; it < 36 * 12; it += kSsqThreads) {
+        const int k = it / 12, cc = it % 12;
+        double re = 0, im = 0;
+#pragma unroll
+        for (int s = 0; s < kStreams; ++s) {
+            re += s_pt[(s * 36 + k) * 24 + 2 * cc];
+            im += s_pt[(s * 36 + k) * 24 + 2 * cc + 1];
+        }
+        const int i = k / 6, j = k % 6;
+        const int op = cc / 4, al = (cc / 2) % 2, be = cc % 2;
+        const int64_t row = 2 * (int64_t)te[i] + al, col = 2 * (int64_t)tf[j] + be;
+        TS *dst = zblock(a.Z, op) + 2 * (row * a.n2 + col);
+        atomic_add(dst, re);
+        atomic_add(dst + 1, im);
+    }
+}
+
 // ---------------------------------------------------------- mass ---
 // Element mass blocks int N_k N_l on the 7-point rule, added to the node
 // CSR values through the precomputed slot map.
@@ -558,7 +822,39 @@ static KernelConst make_kconst(const mbem_op *op, bool deriv) {
     return K;
 }
 
-template <typename T, typename TS, bool DK = false>
+// Constants of the remainders kappa - kappa^s of the paper's scheme: the
+// Taylor series without their singular terms, truncated after n = 6, with
+// the coefficients shifted to non-negative powers of R (D0: c_{m+1}, df and
+// dg: c_{m+3}, G: c_{m+2} multiply R^m).
+static KernelConst make_rem_kconst(const mbem_op *op) {
+    using C = std::complex<double>;
+    constexpr int kPaperTerms = 6;
+    KernelConst K = make_kconst(op, false);
+    KernelConst R = K;
+    for (int i = 0; i < 2 * (kSeriesTerms + 1); ++i) R.cD[i] = R.cF[i] = R.cG[i] = R.cE[i] = R.cM[i] = 0.0;
+    const C ka(op->ka.x, op->ka.y), ki(op->ki.x, op->ki.y);
+    const C ea(1.0, 0.0), ei(op->eps_i.x, op->eps_i.y);
+    const C ma(1.0, 0.0), mi(op->mu_i.x, op->mu_i.y);
+    const C I(0.0, 1.0);
+    C cna(1.0, 0.0), cni(1.0, 0.0);
+    auto put = [](double *c, int m, C v) { c[2 * m] = v.real(); c[2 * m + 1] = v.imag(); };
+    for (int n = 0; n <= kPaperTerms; ++n) {
+        if (n > 0) { cna *= I * ka / (double)n; cni *= I * ki / (double)n; }
+        const C d = cna - cni;
+        if (n >= 1) put(R.cD, n - 1, ka * ka * cna - ki * ki * cni);
+        if (n >= 3) {
+            put(R.cF, n - 3, (double)((n - 1) * (n - 3)) * d);
+            put(R.cG, n - 3, -(double)(n - 1) * d);
+        }
+        if (n >= 2) {
+            put(R.cE, n - 2, (double)(n - 1) * (ea * cna - ei * cni));
+            put(R.cM, n - 2, (double)(n - 1) * (ma * cna - mi * cni));
+        }
+    }
+    return R;
+}
+
+template <typename T, typename TS, bool DK = false, bool P12 = false>
 static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long *cnt,
                           hipStream_t s) {
     const mbem_mesh *m = op->mesh;
@@ -566,7 +862,7 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
     a.nt = m->nt;
     a.n2 = op->n2;
     a.qp = qp;
-    a.qp64 = m->d_qp;
+    a.qp64 = P12 ? m->d_qp12 : m->d_qp;
     a.tri = m->d_tri;
     a.chunks = m->d_chunks;
     a.einfo = m->d_elem;
@@ -587,13 +883,16 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
             a.total = a.n_te * a.n_ch;
             if (a.total == 0) continue;
             if (a.total > 0x7fffffffLL) { set_error("too many element pairs for one launch"); return MBEM_EINVAL; }
-            hipLaunchKernelGGL((k_regular<T, TS, DK>), dim3((unsigned)a.total), dim3(256), 0, s, a);
+            if constexpr (P12)
+                hipLaunchKernelGGL((k_regular12<T, TS>), dim3((unsigned)a.total), dim3(256), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_regular<T, TS, DK>), dim3((unsigned)a.total), dim3(256), 0, s, a);
             MBEM_HIP(hipGetLastError());
         }
     return MBEM_OK;
 }
 
-template <typename TS, bool DK = false>
+template <typename TS, bool DK = false, bool PAPER = false>
 static int launch_ssq(mbem_op *op, hipStream_t s) {
     const mbem_mesh *m = op->mesh;
     SsqArgs<TS> a;
@@ -611,10 +910,13 @@ static int launch_ssq(mbem_op *op, hipStream_t s) {
         a.glx[i] = i < a.order ? 0.5 * (1.0 + x[a.order - 1 - i]) : 0.0;
         a.glw[i] = i < a.order ? 0.5 * w[a.order - 1 - i] : 0.0;
     }
-    a.K = op->d_kconst;
+    a.K = PAPER ? op->d_kconst + 1 : op->d_kconst;   // paper: the kernels, then the remainders
     for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)op->K[o];
     if (a.npairs == 0) return MBEM_OK;
-    hipLaunchKernelGGL((k_ssq<TS, DK>), dim3((unsigned)a.npairs), dim3(kSsqThreads), 0, s, a);
+    if constexpr (PAPER)
+        hipLaunchKernelGGL((k_ssq_paper<TS>), dim3((unsigned)a.npairs), dim3(kSsqThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_ssq<TS, DK>), dim3((unsigned)a.npairs), dim3(kSsqThreads), 0, s, a);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
@@ -650,10 +952,18 @@ struct PhaseEvents {
 
 int fill_run(mbem_op *op, hipStream_t s, bool deriv) {
     const mbem_mesh *m = op->mesh;
-    if (!op->d_kconst) MBEM_HIP(hipMalloc((void **)&op->d_kconst, sizeof(KernelConst)));
+    const bool paper = op->p.quadrature == MBEM_QUAD_PAPER;
+    if (paper && deriv) { set_error("the eps derivative is built for the default quadrature only"); return MBEM_EINVAL; }
+    // [0]: the kernels of the regular pairs, [1]: the kernels of the singular
+    // pairs, [2]: the remainders (paper's scheme)
+    if (!op->d_kconst) MBEM_HIP(hipMalloc((void **)&op->d_kconst, 3 * sizeof(KernelConst)));
     {
-        const KernelConst K = make_kconst(op, deriv);
-        MBEM_HIP(hipMemcpyAsync(op->d_kconst, &K, sizeof(K), hipMemcpyHostToDevice, s));
+        KernelConst K[3] = {make_kconst(op, deriv), make_kconst(op, deriv), KernelConst{}};
+        if (paper) {
+            K[0].kmax = 1e300;           // regular pairs: the closed forms at every distance
+            K[2] = make_rem_kconst(op);
+        }
+        MBEM_HIP(hipMemcpyAsync(op->d_kconst, K, sizeof(K), hipMemcpyHostToDevice, s));
         MBEM_HIP(hipStreamSynchronize(s));   // K lives on this stack frame
     }
     PhaseEvents pe;
@@ -661,10 +971,23 @@ int fill_run(mbem_op *op, hipStream_t s, bool deriv) {
     for (int o = 0; o < 3; ++o)
         MBEM_HIP(hipMemsetAsync(op->K[o], 0, esz * op->n2 * op->n2, s));
     pe.mark(0, s);
-    MBEM_TRY(geom_build(m, s));
+    MBEM_TRY(geom_build(m, s, paper));
     pe.mark(1, s);
     unsigned long long *cnt = nullptr;
-    if (deriv) {
+    if (paper && op->prec == MBEM_FP64) {
+        MBEM_TRY((launch_regular<double, double, false, true>(op, 0, m->d_qp12, nullptr, s)));
+        pe.mark(2, s);
+        pe.mark(3, s);
+        MBEM_TRY((launch_ssq<double, false, true>(op, s)));
+    } else if (paper) {
+        MBEM_HIP(hipMallocAsync((void **)&cnt, sizeof(unsigned long long), s));
+        MBEM_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
+        pe.mark(1, s);
+        MBEM_TRY((launch_regular<float, float, false, true>(op, 1, m->d_qp12_32, cnt, s)));
+        pe.mark(2, s);
+        pe.mark(3, s);
+        MBEM_TRY((launch_ssq<float, false, true>(op, s)));
+    } else if (deriv) {
         if (op->prec != MBEM_FP64) { set_error("derivative operators are filled in FP64"); return MBEM_EINVAL; }
         MBEM_TRY((launch_regular<double, double, true>(op, 0, m->d_qp, nullptr, s)));
         pe.mark(2, s);

@@ -56,17 +56,19 @@ __global__ void k_nodal_frames(int64_t nn, const double *__restrict__ xyz,
 // Gram-Schmidt frame t1, t2 (Sec. 3.3) and the rotated test vectors
 // s_alpha = t_alpha x n (Sec. 4.1), at the 7 regular points of every
 // triangle; written in FP64 and FP32 (structure of arrays).
+template <int NQ>
 __global__ void k_qp_table(int64_t nt, const double *__restrict__ xyz,
                            const int32_t *__restrict__ tri,
                            const double *__restrict__ frames,
                            double *__restrict__ qp, float *__restrict__ qp32) {
     int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int64_t nq = nt * kQP;
+    int64_t nq = nt * NQ;
     if (id >= nq) return;
-    int64_t e = id / kQP;
-    int q = (int)(id % kQP);
+    int64_t e = id / NQ;
+    int q = (int)(id % NQ);
     double xi, eta, w;
-    rule7(q, xi, eta, w);
+    if constexpr (NQ == 12) rule12(q, xi, eta, w);
+    else rule7(q, xi, eta, w);
     P2Point P;
     p2_point(xyz, frames, tri + 6 * e, xi, eta, P);
     double vals[kQPF] = {P.x.x, P.x.y, P.x.z, w * P.J,
@@ -100,15 +102,21 @@ __global__ void k_elem_info(int64_t nt, const double *__restrict__ xyz,
     info[4 * e + 3] = 1.25 * r;
 }
 
-int geom_build(const mbem_mesh *m, hipStream_t s) {
+int geom_build(const mbem_mesh *m, hipStream_t s, bool with12) {
     const int bs = 256;
     hipLaunchKernelGGL(k_nodal_frames, dim3((unsigned)((m->nn + bs - 1) / bs)), dim3(bs), 0, s,
                        m->nn, m->d_xyz, m->d_tri, m->d_inc_ptr, m->d_inc, m->d_frames);
     MBEM_HIP(hipGetLastError());
     int64_t nq = m->nt * kQP;
-    hipLaunchKernelGGL(k_qp_table, dim3((unsigned)((nq + bs - 1) / bs)), dim3(bs), 0, s,
+    hipLaunchKernelGGL(k_qp_table<kQP>, dim3((unsigned)((nq + bs - 1) / bs)), dim3(bs), 0, s,
                        m->nt, m->d_xyz, m->d_tri, m->d_frames, m->d_qp, m->d_qp32);
     MBEM_HIP(hipGetLastError());
+    if (with12) {
+        nq = m->nt * kQP12;
+        hipLaunchKernelGGL(k_qp_table<kQP12>, dim3((unsigned)((nq + bs - 1) / bs)), dim3(bs), 0, s,
+                           m->nt, m->d_xyz, m->d_tri, m->d_frames, m->d_qp12, m->d_qp12_32);
+        MBEM_HIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_elem_info, dim3((unsigned)((m->nt + bs - 1) / bs)), dim3(bs), 0, s,
                        m->nt, m->d_xyz, m->d_tri, m->d_elem);
     MBEM_HIP(hipGetLastError());

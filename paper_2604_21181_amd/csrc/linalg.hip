@@ -298,17 +298,18 @@ __global__ void k_mbj_gather(int64_t n2, int B, const void *K0, const void *K1, 
 // workgroup per block, panels of kPW columns: the panel is factorised
 // column by column, U12 = L11^-1 A12 is formed, and the trailing matrix is
 // updated from L21 and U12 staged in LDS (one pass over A22 per panel).
-constexpr int kPW = 8;
-constexpr int kMaxBlock = 256;        // largest supported cluster size B
-constexpr int kMaxN = 2 * kMaxBlock;  // largest block dimension
+// Instantiated for blocks up to 512 (B <= 256, panels of 8) and up to 1024
+// (B <= 512, panels of 4, so that L21 and U12 still fit in LDS).
+constexpr int kMaxBlock = 512;        // largest supported cluster size B
 
+template <int MAXN, int kPW>
 __global__ __launch_bounds__(1024) void k_mbj_lu(int64_t n2, int B, double2 *A, int32_t *piv,
                                                  int32_t *info) {
     __shared__ double s_v[1024];
     __shared__ int s_i[1024];
-    __shared__ double2 s_L[kMaxN * kPW];   // L21, rows below the panel
-    __shared__ double2 s_U[kPW * kMaxN];   // U12, columns right of it
-    __shared__ int32_t s_pv[kMaxN];        // row interchange of each step
+    __shared__ double2 s_L[MAXN * kPW];    // L21, rows below the panel
+    __shared__ double2 s_U[kPW * MAXN];    // U12, columns right of it
+    __shared__ int32_t s_pv[MAXN];         // row interchange of each step
     const int m = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
     const int b = (int)min((int64_t)B, n2 - (int64_t)m * B);
     const int n = 2 * b, ld = 2 * B;
@@ -408,11 +409,11 @@ __global__ __launch_bounds__(1024) void k_mbj_lu(int64_t n2, int B, double2 *A, 
 // diagonal block is staged in LDS and solved by one wavefront per column
 // with lane shuffles; every remaining row of every column is then updated
 // with the panel's solution.  The factors are read once per workgroup.
-constexpr int kCols = 8;
-
+// Instantiated as (512, 8) and (1024, 4) like the factorisation.
+template <int MAXN, int kCols>
 __global__ __launch_bounds__(1024) void k_mbj_inverse(int64_t n2, int B, const double2 *LU,
                                                       const int32_t *piv, double2 *Minv) {
-    __shared__ double2 y[kCols][kMaxN];
+    __shared__ double2 y[kCols][MAXN];
     __shared__ double2 s_P[kW][kW + 1];
     const int m = blockIdx.x, tid = threadIdx.x, lane = tid % kW, wv = tid / kW;
     const int b = (int)min((int64_t)B, n2 - (int64_t)m * B);
@@ -520,7 +521,7 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s) {
     if (op->d_minv_t) { MBEM_HIP(hipFree(op->d_minv_t)); op->d_minv_t = nullptr; }
     op->B = 0; op->nb = 0;
     if (B <= 0) return MBEM_OK;
-    if (B > kMaxBlock) { set_error("preconditioner block above 256 is not supported"); return MBEM_EINVAL; }
+    if (B > kMaxBlock) { set_error("preconditioner block above 512 is not supported"); return MBEM_EINVAL; }
     const int64_t n2 = op->n2;
     if (B > n2) B = (int)n2;
     const int nb = (int)((n2 + B - 1) / B);
@@ -541,10 +542,17 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s) {
         hipLaunchKernelGGL((k_mbj_gather<float2>), g, dim3(256), 0, s, n2, B, op->K[0], op->K[1],
                            op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), op->d_lu);
     MBEM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_mbj_lu, dim3(nb), dim3(1024), 0, s, n2, B, op->d_lu, piv, info);
-    MBEM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_mbj_inverse, dim3(nb, (unsigned)((ld + kCols - 1) / kCols)), dim3(1024), 0, s,
-                       n2, B, op->d_lu, piv, op->d_minv);
+    if (ld <= 512) {
+        hipLaunchKernelGGL((k_mbj_lu<512, 8>), dim3(nb), dim3(1024), 0, s, n2, B, op->d_lu, piv, info);
+        MBEM_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_mbj_inverse<512, 8>), dim3(nb, (unsigned)((ld + 7) / 8)), dim3(1024), 0, s,
+                           n2, B, op->d_lu, piv, op->d_minv);
+    } else {
+        hipLaunchKernelGGL((k_mbj_lu<1024, 4>), dim3(nb), dim3(1024), 0, s, n2, B, op->d_lu, piv, info);
+        MBEM_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_mbj_inverse<1024, 4>), dim3(nb, (unsigned)((ld + 3) / 4)), dim3(1024), 0, s,
+                           n2, B, op->d_lu, piv, op->d_minv);
+    }
     MBEM_HIP(hipGetLastError());
     int32_t h = 0;
     MBEM_HIP(hipMemcpyAsync(&h, info, sizeof(h), hipMemcpyDeviceToHost, s));

@@ -33,6 +33,7 @@ void set_error(const std::string &msg);
 
 // ------------------------------------------------------------ constants --
 constexpr int kQP = 7;          // regular rule points per triangle
+constexpr int kQP12 = 12;       // points of the 12-point rule (paper's scheme)
 constexpr int kQPF = 19;        // doubles per quadrature point in the table
 constexpr int kMaxSSQ = 8;      // largest Sauter-Schwab order supported
 constexpr int kChunk = 4;       // trial triangles per regular-pair workgroup
@@ -79,6 +80,8 @@ struct mbem_mesh {
     double *d_frames = nullptr;    // [nn][9]: n, t1, t2
     double *d_qp = nullptr;        // [kQPF][nt*7]
     float *d_qp32 = nullptr;       // [kQPF][nt*7]
+    double *d_qp12 = nullptr;      // [kQPF][nt*12], the 12-point rule (paper's scheme)
+    float *d_qp12_32 = nullptr;    // [kQPF][nt*12]
     double *d_elem = nullptr;      // [nt][4]: centroid, radius
     // mass-matrix pattern (node CSR) and element -> CSR slot map
     std::vector<int32_t> m_ptr, m_col;
@@ -139,7 +142,8 @@ int morton_order_host(const double *xyz, int64_t nn, const int64_t *tri6,
 void gauss_legendre(int n, double *x, double *w);   // on [-1, 1]
 
 // geometry (geom.hip)
-int geom_build(const mbem_mesh *m, hipStream_t s);
+// with12: also the 12-point quadrature tables (the paper's scheme)
+int geom_build(const mbem_mesh *m, hipStream_t s, bool with12 = false);
 
 // fill (fill.hip)
 // deriv: fill dK/deps_i instead of K (FP64 operators only)

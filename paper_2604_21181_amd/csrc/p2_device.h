@@ -62,6 +62,34 @@ __device__ inline void rule7(int q, double &xi, double &eta, double &w) {
     eta = (r == 2) ? 1.0 - 2.0 * s : s;
 }
 
+// The 12-point degree-6 symmetric rule (the regular rule of the paper's own
+// scheme): two three-point orbits (a, a, 1 - 2a) and one six-point orbit
+// (b, c, 1 - b - c) in barycentric coordinates (L0, L1, L2) = (1 - xi - eta,
+// xi, eta); its seven parameters solve the moment equations of the
+// S3-invariant polynomials of degree <= 6.  Weights sum to 1/2.
+__host__ __device__ constexpr double r12_bary(int q, int k) {
+    if (q < 6) {
+        const double a = q < 3 ? 0.06308901449150309 : 0.24928674517091215;
+        return k == q % 3 ? 1.0 - 2.0 * a : a;
+    }
+    const double v[3] = {0.053145049844817806, 0.3103524510337839,
+                         1.0 - 0.053145049844817806 - 0.3103524510337839};
+    // orbit point m: L[perm(m)[d]] = v[d] for the six permutations
+    const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    const int m = q - 6;
+    for (int d = 0; d < 3; ++d)
+        if (perm[m][d] == k) return v[d];
+    return 0.0;
+}
+__host__ __device__ constexpr double r12_weight(int q) {
+    return 0.5 * (q < 3 ? 0.05084490637020728 : (q < 6 ? 0.11678627572637695 : 0.08285107561837454));
+}
+__device__ inline void rule12(int q, double &xi, double &eta, double &w) {
+    xi = r12_bary(q, 1);
+    eta = r12_bary(q, 2);
+    w = r12_weight(q);
+}
+
 // ------------------------------------------------------- P2 element ---
 // Shape functions in barycentric form: vertex l(2l-1), mid-edge 4 l l'.
 __device__ inline void p2_shape(double xi, double eta, double N[6], double Nxi[6],
@@ -221,6 +249,9 @@ __device__ inline float exp_t(float x) { return expf(x); }
 // Scalar parts of D0 = k_a^2 phi_a - k_i^2 phi_i, H_diff = df RR^T - dg I
 // (eq. Hdiff_exact) and grad Phi_chi = G_chi Rhat at distance R.
 template <typename T>
+__device__ __forceinline__ KScal<T> kernel_scalars_closed(const KernelConst &K, T R);
+
+template <typename T>
 __device__ __forceinline__ KScal<T> kernel_scalars(const KernelConst &K, T R) {
     const T inv4pi = (T)0.079577471545947667884;   // 1 / (4 pi)
     KScal<T> o;
@@ -233,6 +264,14 @@ __device__ __forceinline__ KScal<T> kernel_scalars(const KernelConst &K, T R) {
         o.Gm = r2 * horner<T>(K.cM, R);
         return o;
     }
+    return kernel_scalars_closed<T>(K, R);
+}
+
+// The closed forms alone (every R > 0).
+template <typename T>
+__device__ __forceinline__ KScal<T> kernel_scalars_closed(const KernelConst &K, T R) {
+    const T inv4pi = (T)0.079577471545947667884;
+    KScal<T> o;
     const T r1 = inv4pi / R, r3 = r1 / (R * R);
     cx<T> k[2] = {{(T)K.ka_re, (T)K.ka_im}, {(T)K.ki_re, (T)K.ki_im}};
     cx<T> phi[2], f[2], g[2];
@@ -256,6 +295,50 @@ __device__ __forceinline__ KScal<T> kernel_scalars(const KernelConst &K, T R) {
     const cx<T> ma = {(T)K.mu_a_re, (T)K.mu_a_im}, mi = {(T)K.mu_i_re, (T)K.mu_i_im};
     o.Ge = (-R) * (ea * g[0] - ei * g[1]);
     o.Gm = (-R) * (ma * g[0] - mi * g[1]);
+    return o;
+}
+
+// Singular parts of the scalars (kappa^s of the paper's scheme, Sec. 4.1
+// and 4.2): the terms of negative order in R of the expansions,
+//   D0^s = (k_a^2 - k_i^2)/(4 pi R), df^s = dg^s = (k_a^2 - k_i^2)/(8 pi R),
+//   G_chi^s = -(chi_a - chi_i)/(4 pi R^2).
+__device__ __forceinline__ KScal<double> kernel_scalars_sing(const KernelConst &K, double R) {
+    const double inv4pi = 0.079577471545947667884;
+    const cx<double> ka = {K.ka_re, K.ka_im}, ki = {K.ki_re, K.ki_im};
+    const cx<double> dk2 = ka * ka - ki * ki;
+    const double r1 = inv4pi / R, r2 = r1 / R;
+    KScal<double> o;
+    o.D0 = r1 * dk2;
+    o.df = (0.5 * r1) * dk2;
+    o.dg = o.df;
+    o.Ge = (-r2) * cx<double>{K.eps_a_re - K.eps_i_re, K.eps_a_im - K.eps_i_im};
+    o.Gm = (-r2) * cx<double>{K.mu_a_re - K.mu_i_re, K.mu_a_im - K.mu_i_im};
+    return o;
+}
+
+// Remainders kernel - kernel^s.  Below max|k| R = 1/2 (and at R = 0): the
+// expansions without their singular terms, whose coefficients the host
+// shifts into Kr so that only non-negative powers of R remain (D0 by one
+// power, df and dg by three, G by two; truncated after n = 6); otherwise the
+// closed forms minus the singular parts.
+__device__ __forceinline__ KScal<double> kernel_scalars_rem(const KernelConst &K, const KernelConst &Kr,
+                                                           double R) {
+    const double inv4pi = 0.079577471545947667884;
+    KScal<double> o;
+    if (R > 0.0 && K.kmax * R >= kSeriesRho) {
+        const KScal<double> c = kernel_scalars_closed<double>(K, R), s = kernel_scalars_sing(K, R);
+        o.D0 = c.D0 - s.D0;
+        o.df = c.df - s.df;
+        o.dg = c.dg - s.dg;
+        o.Ge = c.Ge - s.Ge;
+        o.Gm = c.Gm - s.Gm;
+        return o;
+    }
+    o.D0 = inv4pi * horner<double>(Kr.cD, R);
+    o.df = inv4pi * horner<double>(Kr.cF, R);
+    o.dg = inv4pi * horner<double>(Kr.cG, R);
+    o.Ge = inv4pi * horner<double>(Kr.cE, R);
+    o.Gm = inv4pi * horner<double>(Kr.cM, R);
     return o;
 }
 

@@ -110,6 +110,93 @@ def test_sphere1280_sampled_entries_and_solve(sphere1280, prec):
         S.close()
 
 
+def test_sphere1280_precond_512_blocks(sphere1280):
+    """Block-Jacobi with the largest cluster (B = 512: ten 1024 x 1024 blocks
+    and a partial one) in the bench configuration: every block of
+    z = P^-1 v solves A_m z_m = v_m with A_m gathered from the exported Z."""
+    import torch
+    from paper_2604_21181_amd import mbem
+    cfg, xyz, tri = sphere1280
+    print("\n[sphere1280 B=512]", flush=True)
+    S = mbem.Solver(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"], precision=mbem.MBEM_FP64)
+    try:
+        S.fill()
+        B, n2 = 512, S.N // 2
+        S.precond_setup(B)
+        rng = np.random.default_rng(11)
+        v = torch.as_tensor(rng.normal(size=S.N) + 1j * rng.normal(size=S.N), device=S.device)
+        z = S.precond_apply(v)
+        Z = S.export_dense()
+        worst = 0.0
+        for m in range((n2 + B - 1) // B):
+            I = torch.arange(m * B, min((m + 1) * B, n2), device=S.device)
+            idx = torch.cat([I, n2 + I])
+            A = Z.index_select(0, idx).index_select(1, idx)
+            r = A @ z[idx] - v[idx]
+            worst = max(worst, float(r.abs().max() / v[idx].abs().max()))
+        assert worst < 1e-10, worst
+        del Z
+        torch.cuda.empty_cache()
+    finally:
+        S.close()
+
+
+def test_sphere1280_paper_scheme_sampled_entries(sphere1280):
+    """The paper's quadrature at full size: sampled node-pair entries (the
+    oracle evaluates each from every element pair touching the two nodes
+    with its variant 1) and a solve at the bench tolerance."""
+    from paper_2604_21181_amd import mbem
+    cfg, xyz, tri = sphere1280
+    print("\n[sphere1280 paper scheme]", flush=True)
+    S = mbem.Solver(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"], precision=mbem.MBEM_FP64,
+                    quadrature=mbem.MBEM_QUAD_PAPER)
+    try:
+        S.fill()
+        K = S.export_blocks()
+        I, J = _samples(xyz, tri, 32, seed=9)
+        ph = core.phys_vector(cfg["k0"], cfg["eps_r"], cfg["mu_r"], variant=1)
+        ref = core.entries(xyz, tri, ph, I, J)
+        got = _gpu_entries(S, K, I, J)
+        scale = np.abs(ref).reshape(len(I), -1).max(axis=1)
+        err = np.abs(got - ref).reshape(len(I), -1).max(axis=1)
+        assert np.all(err <= 1e-11 * scale + 1e-14 * scale.max()), (err / scale).max()
+        del K
+        S.precond_setup(cfg["mbj_block"])
+        kh, pol = planewaves("sphere1280")
+        b = S.rhs(kh, pol)
+        xs, st, code = S.solve(b, tol=cfg["tol"], maxit=600)
+        assert code == 0 and st.rel_resid <= 2 * cfg["tol"]
+    finally:
+        S.close()
+
+
+def test_sphere1280_paper_scheme_vs_default_and_mie(sphere1280):
+    """Far fields of the paper's scheme and of the default (FP64, GMRES to
+    1e-10) at 360 angles: both within the discretisation error of Mie, and
+    within the schemes' quadrature difference of each other."""
+    from paper_2604_21181_amd import mbem
+    cfg, xyz, tri = sphere1280
+    r = cut_plane_directions(360)
+    Fm = mie.far_field(cfg["k0"], 1.0, cfg["eps_r"], r)
+    kh, pol = planewaves("sphere1280")
+    F = {}
+    for q in (mbem.MBEM_QUAD_DEFAULT, mbem.MBEM_QUAD_PAPER):
+        S = mbem.Solver(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"], precision=mbem.MBEM_FP64, quadrature=q)
+        try:
+            S.fill()
+            S.precond_setup(cfg["mbj_block"])
+            x, st, code = S.solve(S.rhs(kh, pol), tol=1e-10, maxit=600)
+            assert code == 0
+            F[q] = S.farfield(x, r).cpu().numpy()[0]
+        finally:
+            S.close()
+    e_def = np.linalg.norm(F[0] - Fm) / np.linalg.norm(Fm)
+    e_pap = np.linalg.norm(F[1] - Fm) / np.linalg.norm(Fm)
+    d = np.linalg.norm(F[1] - F[0]) / np.linalg.norm(F[0])
+    print(f"\n[far field vs Mie: default {e_def:.3e}, paper scheme {e_pap:.3e}; between {d:.3e}]", flush=True)
+    assert e_def < 2e-2 and e_pap < 2e-2 and d < 5e-3
+
+
 def test_sphere1280_mixed_farfield_matches_fp64_and_mie(sphere1280):
     from paper_2604_21181_amd import mbem
     cfg, xyz, tri = sphere1280

@@ -116,7 +116,9 @@ def test_precond_apply(case):
     S = case["S"]
     p = S.perm
     Zm = case["Z"][np.ix_(p, p)]
-    for B in (50, 256):
+    # 512 exceeds this mesh's unknowns per current: one block wider than 512,
+    # the factorisation's second instantiation (panels of 4)
+    for B in (50, 256, 512):
         S.precond_setup(B)
         blocks = solver.mbj_matrices(Zm, B)
         v = np.random.default_rng(3).normal(size=S.N) + 0j
@@ -144,6 +146,36 @@ def test_solve_fp64_and_farfield(case):
     assert np.allclose(cs, co, rtol=1e-10, atol=1e-12 * abs(co[0]))
 
 
+def test_solve_unpreconditioned_and_whole_block(case):
+    """GMRES without the preconditioner reaches the oracle's LU solution; a
+    single block covering the whole system makes P = Z, so GMRES converges
+    in one iteration."""
+    S = case["S"]
+    b = S.rhs(KH[None], POL[None])
+    xo = case["x"][S.perm]
+    S.precond_setup(0)
+    x, st, code = S.solve(b, tol=1e-12, maxit=S.N)
+    assert code == 0 and st.rel_resid < 1e-11
+    assert np.linalg.norm(x.cpu().numpy()[0] - xo) / np.linalg.norm(xo) < 1e-9
+    n_plain = st.iters
+    S.precond_setup(S.N // 2)
+    x, st, code = S.solve(b, tol=1e-12, maxit=50)
+    assert code == 0 and st.iters == 1, st.iters
+    assert np.linalg.norm(x.cpu().numpy()[0] - xo) / np.linalg.norm(xo) < 1e-10
+    S.precond_setup(100)
+    x, st, code = S.solve(b, tol=1e-12, maxit=400)
+    assert code == 0 and st.iters < n_plain, (st.iters, n_plain)
+
+
+def test_precond_block_limit(case):
+    mbem = _mbem()
+    S = case["S"]
+    with pytest.raises(mbem.MbemError) as ei:
+        S.precond_setup(513)
+    assert ei.value.code == mbem.MBEM_EINVAL
+    S.precond_setup(100)
+
+
 def test_mixed_fill_and_solve(case):
     mbem = _mbem()
     S = mbem.Solver(case["xyz"], case["tri"], case["k0"], case["eps"], precision=mbem.MBEM_MIXED)
@@ -161,6 +193,54 @@ def test_mixed_fill_and_solve(case):
         F = S.farfield(x, r).cpu().numpy()[0]
         Fo = galerkin.far_field(case["P"], case["x"], r)
         assert np.linalg.norm(F - Fo) / np.linalg.norm(Fo) < 1e-5
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_paper_scheme_fill_and_solve(case, prec):
+    """The paper's own quadrature (12-point rule, Sauter-Schwab on kappa^s,
+    12-point remainder, series to n = 6) against the oracle's variant 1."""
+    mbem = _mbem()
+    xyz, tri = case["xyz"], case["tri"]
+    P = galerkin.Problem(xyz, tri, case["k0"], case["eps"], variant=1)
+    K = core.fill(xyz, tri, P.phys)
+    S = mbem.Solver(xyz, tri, case["k0"], case["eps"], quadrature=mbem.MBEM_QUAD_PAPER,
+                    precision=mbem.MBEM_FP64 if prec == "fp64" else mbem.MBEM_MIXED)
+    try:
+        S.fill()
+        p1 = S.perm[: 2 * S.nn]
+        Kg = [k.cpu().numpy() for k in S.export_blocks()]
+        tol = 1e-12 if prec == "fp64" else 2e-6
+        for o in range(3):
+            assert _rel(Kg[o], K[o][np.ix_(p1, p1)]) < tol, o
+        M = galerkin.mass_matrix(P)
+        Z = galerkin.assemble(P, *K, M)
+        x_or = np.linalg.solve(Z, galerkin.planewave_rhs(P, KH[None], POL[None])[:, 0])
+        S.precond_setup(100)
+        b = S.rhs(KH[None], POL[None])
+        x, st, code = S.solve(b, tol=1e-12, maxit=400, inner_tol=1e-6)
+        assert code == 0
+        r = cut_plane_directions(72)
+        F = S.farfield(x, r).cpu().numpy()[0]
+        Fo = galerkin.far_field(P, x_or, r)
+        assert np.linalg.norm(F - Fo) / np.linalg.norm(Fo) < (1e-10 if prec == "fp64" else 1e-5)
+    finally:
+        S.close()
+
+
+def test_paper_scheme_rejected_by_the_gradient(case):
+    import torch
+    mbem = _mbem()
+    S = mbem.Solver(case["xyz"], case["tri"], case["k0"], case["eps"], quadrature=mbem.MBEM_QUAD_PAPER)
+    try:
+        S.fill()
+        x = torch.zeros(S.N, dtype=torch.complex128, device=S.device)
+        with pytest.raises(mbem.MbemError) as ei:
+            S.grad_sigma_ext(x, KH, POL)
+        assert ei.value.code == mbem.MBEM_EINVAL
+        with pytest.raises(mbem.MbemError):
+            S.deps_blocks()
     finally:
         S.close()
 
