@@ -13,6 +13,7 @@ direct form, from the paper (arXiv 2604.21181):
                far field and cross sections
   solver.py    Morton order, Morton block-Jacobi, GMRES
   mie.py       Mie series (spheres)
+  spectrum.py  sweeps over wavenumber and material on one mesh
 
 Parity status of every function is listed in the design notes; everything
 here is pinned by the CPU test-suite (quadrature exactness, closed forms,
@@ -22,10 +23,10 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import core, galerkin, mie, solver
+from . import core, galerkin, mie, solver, spectrum
 from .galerkin import Problem
 
-__all__ = ["core", "galerkin", "mie", "solver", "Problem", "solve_dense"]
+__all__ = ["core", "galerkin", "mie", "solver", "spectrum", "Problem", "solve_dense"]
 
 
 def solve_dense(P: Problem, khat, pol, K=None):

@@ -1,0 +1,116 @@
+"""Pins of the spectrum sweep and its inputs (CPU).
+
+* The permittivity interpolation reproduces the table rows and the value the
+  paper quotes at the resonance peak (Sec. 7, Benchmark II).
+* The cubed-sphere mesh has the paper's element, node and unknown counts.
+* The Mie series for a plasmonic sphere tends to the quasi-static dipole.
+* The oracle's sweep on silver spheres matches Mie at every wavelength,
+  including the dipole resonance, with energy balance.
+* On the silver spheroid the sweep puts the extinction peak where the paper
+  does, at the paper's magnitude.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mie, spectrum
+from workloads.materials import JC_SILVER, lspr_wavelengths, silver_eps
+from workloads.meshes import cubesphere_p2, icosphere_p2
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "lspr_silver_spheroid.txt")
+
+
+def _golden():
+    out = {}
+    for line in open(GOLD):
+        line = line.split("#")[0].split()
+        if len(line) == 2:
+            out[line[0]] = float(line[1])
+    return out
+
+
+def test_permittivity_table_and_peak_value():
+    g = _golden()
+    eps_rows = silver_eps(JC_SILVER[:, 0])
+    assert np.allclose(eps_rows, (JC_SILVER[:, 1] + 1j * JC_SILVER[:, 2]) ** 2, rtol=0, atol=1e-14)
+    e = complex(silver_eps(g["lambda_peak_nm"])[0])
+    # the paper prints two decimals
+    assert abs(e.real - g["eps_re_peak"]) <= 0.005
+    assert abs(e.imag - g["eps_im_peak"]) <= 0.005
+    with pytest.raises(ValueError):
+        silver_eps(250.0)
+
+
+def test_wavelength_grid():
+    lam = lspr_wavelengths()
+    assert lam[0] == 350.0 and lam[-1] == 800.0 and lam.shape[0] == 131
+    d = np.diff(lam)
+    near = (lam[:-1] >= 475) & (lam[1:] <= 525)
+    assert np.all(d[near] == 1.0) and np.all(d[~near] == 5.0)
+
+
+def test_cubed_sphere_counts_match_the_papers_mesh():
+    g = _golden()
+    xyz, tri = cubesphere_p2(16, (15.0, 15.0, 45.0))
+    assert tri.shape[0] == g["n_elements"] and xyz.shape[0] == g["n_nodes"]
+    assert 4 * xyz.shape[0] == g["n_dofs"]
+    # block-Jacobi clusters of 100 entries of one current's 2 n_nodes vector
+    assert int(np.ceil(2 * xyz.shape[0] / g["mbj_cluster"])) == g["mbj_blocks"]
+    # every node on the spheroid, every edge shared by exactly two triangles
+    r = np.linalg.norm(xyz / np.array([15.0, 15.0, 45.0]), axis=1)
+    assert np.abs(r - 1).max() < 1e-14
+    edges = np.sort(np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]]), axis=1)
+    _, cnt = np.unique(edges, axis=0, return_counts=True)
+    assert np.all(cnt == 2)
+    # outward orientation: the signed volume is the spheroid's
+    v = xyz[tri[:, :3]]
+    vol = np.einsum("ij,ij->i", v[:, 0], np.cross(v[:, 1], v[:, 2])).sum() / 6
+    assert 0.97 < vol / (4 / 3 * np.pi * 15 * 15 * 45) < 1.0
+
+
+def test_mie_plasmonic_sphere_tends_to_the_quasistatic_dipole():
+    """x = k a << 1: C_abs -> k Im(alpha), C_sca -> k^4 |alpha|^2 / (6 pi),
+    alpha = 4 pi a^3 (eps - 1) / (eps + 2), for silver near its dipole
+    resonance (eps ~ -2)."""
+    a = 0.5
+    for lam in (356.0, 400.0):
+        k = 2 * np.pi / lam
+        eps = complex(silver_eps(lam)[0])
+        alpha = 4 * np.pi * a ** 3 * (eps - 1) / (eps + 2)
+        ext, sca, ab = mie.cross_sections(k, a, eps)
+        assert abs(ab / (k * alpha.imag) - 1) < 1e-3
+        assert abs(sca / (k ** 4 * abs(alpha) ** 2 / (6 * np.pi)) - 1) < 1e-3
+
+
+@pytest.mark.parametrize("n_tris,lams,tol", [
+    (80, (350.0, 400.0, 500.0, 700.0), 2.5e-2),
+    (320, (356.0,), 1e-2),
+])
+def test_silver_sphere_sweep_matches_mie(n_tris, lams, tol):
+    a = 20.0
+    xyz, tri = icosphere_p2(n_tris, (a, a, a))
+    lam = np.array(lams)
+    k0 = 2 * np.pi / lam
+    eps = silver_eps(lam)
+    cs = spectrum.spectrum(xyz, tri, k0, eps, [1.0, 0, 0], [0, 0, 1.0])
+    for i in range(lam.shape[0]):
+        ref = np.array(mie.cross_sections(k0[i], a, complex(eps[i])))
+        assert np.all(np.abs(cs[i] / ref - 1) < tol), (lam[i], cs[i], ref)
+        # energy balance: extinction = scattering + absorption
+        assert abs((cs[i, 1] + cs[i, 2]) / cs[i, 0] - 1) < 2e-3
+
+
+def test_spheroid_extinction_peak_where_the_paper_puts_it():
+    """Coarse cubed sphere (192 triangles; the peak moves by < 0.1 % from
+    192 to 768 triangles): the 1 nm samples around 506 nm peak within 1 nm
+    of it, at the paper's magnitude (given to one significant figure)."""
+    g = _golden()
+    xyz, tri = cubesphere_p2(4, (15.0, 15.0, 45.0))
+    lam = np.arange(503.0, 511.0)
+    cs = spectrum.spectrum(xyz, tri, 2 * np.pi / lam, silver_eps(lam), [1.0, 0, 0], [0, 0, 1.0])
+    i = int(np.argmax(cs[:, 0]))
+    assert 0 < i < lam.shape[0] - 1          # an interior maximum
+    assert abs(lam[i] - g["lambda_peak_nm"]) <= 1.0
+    assert 75000.0 <= cs[i, 0] <= 85000.0
+    assert np.all(np.abs((cs[:, 1] + cs[:, 2]) / cs[:, 0] - 1) < 1e-3)

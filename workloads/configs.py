@@ -101,3 +101,32 @@ def gradient_setup(n_nodes: int):
     d = np.random.default_rng(1).normal(size=n_nodes)
     nodes = np.random.default_rng(2).choice(n_nodes, 16, replace=False)
     return d, np.sort(nodes).astype(np.int64)
+
+
+# ---------------------------------------------------------------- spectra --
+# Sweeps over the vacuum wavelength on one mesh (lengths in nm, free space,
+# silver from workloads.materials).
+#   spheroid_lspr  silver prolate spheroid, semi-axes 15, 15, 45 nm, cubed
+#                  sphere n = 16 (3072 triangles, 6146 nodes, 24584
+#                  unknowns); wave along +x, field along the major axis +z;
+#                  the 131-wavelength grid of lspr_wavelengths(); block-Jacobi
+#                  clusters of 100, GMRES to 1e-5.
+#   sphere_lspr    silver sphere of radius 20 nm on the same cubed-sphere
+#                  mesh and grid, the case with a closed form (Mie).
+SPECTRA = {
+    "spheroid_lspr": dict(cube_n=16, axes=(15.0, 15.0, 45.0), mbj_block=100, tol=1e-5),
+    "sphere_lspr": dict(cube_n=16, axes=(20.0, 20.0, 20.0), mbj_block=100, tol=1e-5),
+}
+
+
+def spectrum_workload(name: str, lambdas=None):
+    """(xyz, tri6, lam[npts] nm, k0[npts] 1/nm, eps_r[npts], khat[3], pol[3],
+    settings) of a spectrum workload; lambdas overrides the grid."""
+    from .materials import lspr_wavelengths, silver_eps
+    from .meshes import cubesphere_p2
+    c = dict(SPECTRA[name])
+    xyz, tri = cubesphere_p2(c["cube_n"], c["axes"])
+    lam = lspr_wavelengths() if lambdas is None else np.atleast_1d(np.asarray(lambdas, dtype=np.float64))
+    khat = np.array([1.0, 0.0, 0.0])
+    pol = np.array([0.0, 0.0, 1.0], dtype=np.complex128)
+    return xyz, tri, lam, 2 * np.pi / lam, silver_eps(lam), khat, pol, c

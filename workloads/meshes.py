@@ -9,6 +9,13 @@ Recipe (used for every workload):
   4. every triangle oriented counter-clockwise seen from outside;
   5. all nodes scaled by diag(a, b, c) for spheroids and ellipsoids.
 
+The cubed-sphere meshes (``cubesphere_p2``) replace steps 1-2 by: the
+surface lattice points (i, j, k) in {0..n}^3 of a cube (some coordinate 0 or
+n), mapped coordinate-wise by t -> tan(pi/4 (2t/n - 1)) (the equiangular
+gnomonic map; the face coordinate becomes +-1) and projected to the unit
+sphere; each of the 6 n^2 lattice squares split along its (i, j) -> (i+1,
+j+1) diagonal (F = 12 n^2 triangles).  Steps 3-5 are the same.
+
 Node order is the generation order (vertices first, then edge nodes); it is
 deliberately *not* spatially sorted, so that the library's own reordering is
 exercised.  Local node order of a triangle is (v0, v1, v2, m01, m12, m20).
@@ -101,6 +108,62 @@ def icosphere_p2(n_tris: int, axes=(1.0, 1.0, 1.0)):
     return np.ascontiguousarray(xyz), np.ascontiguousarray(tri6)
 
 
+def _p2_nodes(v, f, axes):
+    """Mid-edge nodes (step 3), tri6 connectivity and the scaling of step 5."""
+    nv = v.shape[0]
+    edge_id, mids = {}, []
+    tri6 = np.zeros((f.shape[0], 6), dtype=np.int64)
+    for t, (a, b, c) in enumerate(f):
+        tri6[t, :3] = (a, b, c)
+        for k, (p, q) in enumerate(((a, b), (b, c), (c, a))):
+            key = (min(p, q), max(p, q))
+            if key not in edge_id:
+                m = v[p] + v[q]
+                mids.append(m / np.linalg.norm(m))
+                edge_id[key] = nv + len(mids) - 1
+            tri6[t, 3 + k] = edge_id[key]
+    xyz = np.concatenate([v, np.array(mids)], axis=0) * np.asarray(axes, dtype=np.float64)[None, :]
+    return np.ascontiguousarray(xyz), np.ascontiguousarray(tri6)
+
+
+def cubesphere_p2(n: int, axes=(1.0, 1.0, 1.0)):
+    """Equiangular cubed sphere with n x n squares per cube face, each split
+    into two triangles: 12 n^2 P2 triangles on 6 n^2 + 2 vertices, 24 n^2 + 2
+    nodes in all.  n = 16 gives 3072 triangles and 6146 nodes.
+    Returns (xyz[n_nodes,3] float64, tri6[n_tris,6] int64)."""
+    if n < 1:
+        raise ValueError("n must be positive")
+    index = {}
+    verts = []
+
+    def vid(i, j, k):
+        key = (i, j, k)
+        if key not in index:
+            q = np.tan(0.25 * math.pi * (2.0 * np.array(key, dtype=np.float64) / n - 1.0))
+            verts.append(q / np.linalg.norm(q))
+            index[key] = len(verts) - 1
+        return index[key]
+
+    f = []
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        for side in (0, n):
+            for i in range(n):
+                for j in range(n):
+                    corners = []
+                    for di, dj in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                        p = [0, 0, 0]
+                        p[a], p[b], p[c] = side, i + di, j + dj
+                        corners.append(vid(*p))
+                    p00, p10, p11, p01 = corners
+                    f += [[p00, p10, p11], [p00, p11, p01]]
+    v = np.array(verts)
+    f = _orient_outward(v, np.array(f, dtype=np.int64))
+    xyz, tri6 = _p2_nodes(v, f, axes)
+    assert xyz.shape[0] == mesh_counts(tri6.shape[0])[0]
+    return xyz, tri6
+
+
 def uv_sphere_p2(n_lon: int, n_lat: int, axes=(1.0, 1.0, 1.0)):
     """Latitude-longitude triangulation of the unit sphere (two poles,
     n_lat - 1 rings of n_lon vertices), P2 mid-edge nodes projected to the
@@ -133,17 +196,4 @@ def uv_sphere_p2(n_lon: int, n_lat: int, axes=(1.0, 1.0, 1.0)):
             c, d = ring(k + 1, j), ring(k + 1, j + 1)
             f += [[a, c, d], [a, d, b]]
     f = _orient_outward(v, np.array(f, dtype=np.int64))
-    nv = v.shape[0]
-    edge_id, mids = {}, []
-    tri6 = np.zeros((f.shape[0], 6), dtype=np.int64)
-    for t, (a, b, c) in enumerate(f):
-        tri6[t, :3] = (a, b, c)
-        for k, (p, q) in enumerate(((a, b), (b, c), (c, a))):
-            key = (min(p, q), max(p, q))
-            if key not in edge_id:
-                m = v[p] + v[q]
-                mids.append(m / np.linalg.norm(m))
-                edge_id[key] = nv + len(mids) - 1
-            tri6[t, 3 + k] = edge_id[key]
-    xyz = np.concatenate([v, np.array(mids)], axis=0) * np.asarray(axes, dtype=np.float64)[None, :]
-    return np.ascontiguousarray(xyz), np.ascontiguousarray(tri6)
+    return _p2_nodes(v, f, axes)
