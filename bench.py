@@ -25,6 +25,14 @@ One step = the whole hot path, both precisions side by side:
          k_a = 4, eps_r = -10 + 1i; GMRES to 1e-5 without a preconditioner
          and with Morton block-Jacobi for clusters of 50, 100, 256 and 512:
          iterations, setup and solve times.
+  SPECTRUM STUDY (once): the silver-spheroid LSPR spectrum (15 x 15 x 45 nm,
+         3072-triangle cubed sphere, 24584 unknowns, permittivity from the
+         printed Johnson-Christy table) over the 131-wavelength grid in one
+         call of the sweep entry point, FP64 and mixed: per-point refill,
+         block-Jacobi (clusters of 100), GMRES to 1e-5 and cross sections;
+         points per second, phase times, the extinction peak and the energy
+         balance.  The preconditioner study also runs this spheroid at its
+         506 nm resonance (the paper's comparison of 822 vs 18 iterations).
   QUADRATURE STUDY (once): the paper's own scheme (12-point rule, Sauter-
          Schwab on the singular kernels only, 12-point remainder) against the
          default on the same sphere, FP64 and mixed: fill times and far-field
@@ -89,6 +97,20 @@ CHUNK = 4
 FLOP_SSQ_POINT = 2 * 310 + 20 + 319 + 12 * 156
 
 
+def regular_fill_flops(S, tri, npairs):
+    """Algorithmic flops of one regular-pair fill (all colour-class launches)
+    of the solver's mesh: per element pair the point-pair work and the
+    trial-side contraction, per (test triangle, trial chunk) workgroup the
+    test-side contraction of its ns distinct chunk nodes."""
+    nt = tri.shape[0]
+    rank = np.empty_like(S.node_order)
+    rank[S.node_order] = np.arange(S.nn)
+    tm = rank[tri[S.tri_order]]
+    ns = np.array([np.unique(tm[k:k + CHUNK]).size for k in range(0, nt, CHUNK)])
+    return (npairs * (49 * FLOP_POINT_PAIR + FLOP_PAIR_TRIAL)
+            + nt * int(ns.sum()) * FLOP_CHUNK_TEST_PER_NODE)
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,10 +125,13 @@ def parse():
                     help="skip the preconditioner study (GMRES without vs with block-Jacobi)")
     ap.add_argument("--no-quad-study", action="store_true",
                     help="skip the comparison of the default quadrature with the paper's scheme")
+    ap.add_argument("--no-spectrum-study", action="store_true",
+                    help="skip the LSPR spectrum sweep of the silver spheroid")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device to device once (scales the FETCH_SIZE / WRITE_SIZE "
                          "counters) and exit")
-    ap.add_argument("--only", choices=["all", "main", "mrhs", "grad", "precond", "quad"], default="all",
+    ap.add_argument("--only", choices=["all", "main", "mrhs", "grad", "precond", "quad", "spectrum"],
+                    default="all",
                     help="run one pass of the step only (for profiling); the JSON line is "
                          "printed for 'all' and 'main'")
     return ap.parse_args()
@@ -129,8 +154,21 @@ def cpu_baseline(xyz, tri, cfg, N):
 
 
 PRECOND_STUDY = (("sphere1280", (50, 100, 256, 512), 1500),
-                 ("spheroid5120", (50, 100, 256, 512), 2000))
+                 ("spheroid5120", (50, 100, 256, 512), 2000),
+                 ("spheroid_lspr@506nm", (50, 100, 256, 512), 2000))
 PRECOND_TOL = 1e-5        # the tolerance of the paper's preconditioner comparisons
+
+
+def _precond_case(name, get_config, icosphere_p2, planewaves):
+    """(xyz, tri, k0, eps_r, mu_r, khat, pol) of a preconditioner-study case."""
+    if name == "spheroid_lspr@506nm":
+        from workloads import spectrum_workload
+        xyz, tri, _, k0, eps, kh, po, _ = spectrum_workload("spheroid_lspr", [506.0])
+        return xyz, tri, float(k0[0]), complex(eps[0]), 1.0, kh[None], po[None]
+    c = get_config(name)
+    xyz, tri = icosphere_p2(c["n_tris"], c["axes"])
+    kh, po = planewaves(name)
+    return xyz, tri, c["k0"], c["eps_r"], c["mu_r"], kh, po
 
 
 def precond_study(mbem, get_config, icosphere_p2, planewaves, log):
@@ -139,15 +177,13 @@ def precond_study(mbem, get_config, icosphere_p2, planewaves, log):
     wave, tolerance 1e-5; run once after the timed steps."""
     out = {}
     for wl, blocks, maxit in PRECOND_STUDY:
-        c = get_config(wl)
-        xyz, tri = icosphere_p2(c["n_tris"], c["axes"])
-        kh, po = planewaves(wl)
-        S = mbem.Solver(xyz, tri, c["k0"], c["eps_r"], c["mu_r"], precision=mbem.MBEM_FP64)
+        xyz, tri, k0, eps, mu, kh, po = _precond_case(wl, get_config, icosphere_p2, planewaves)
+        S = mbem.Solver(xyz, tri, k0, eps, mu, precision=mbem.MBEM_FP64)
         try:
             fs = S.fill()
             b = S.rhs(kh, po)
             n2 = S.N // 2
-            res = {"unknowns": S.N, "k0": c["k0"], "eps_r": str(c["eps_r"]), "tol": PRECOND_TOL,
+            res = {"unknowns": S.N, "k0": k0, "eps_r": str(eps), "tol": PRECOND_TOL,
                    "precision": "fp64", "t_fill_ms": fs.t_fill_ms}
             S.precond_setup(0)
             x, st, code = S.solve(b, tol=PRECOND_TOL, maxit=maxit)
@@ -169,6 +205,60 @@ def precond_study(mbem, get_config, icosphere_p2, planewaves, log):
             out[wl] = res
         finally:
             S.close()
+    return out
+
+
+def spectrum_study(mbem, log):
+    """The LSPR spectrum of the silver spheroid in one sweep call per
+    precision (the first point includes the one geometry build)."""
+    from workloads import spectrum_workload
+    xyz, tri, lam, k0, eps, kh, po, c = spectrum_workload("spheroid_lspr")
+    out = {"workload": "spheroid_lspr", "n_tris": int(tri.shape[0]), "n_nodes": int(xyz.shape[0]),
+           "unknowns": 4 * int(xyz.shape[0]), "points": int(lam.shape[0]),
+           "lambda_nm": [float(lam[0]), float(lam[-1])], "mbj_block": c["mbj_block"],
+           "tol": c["tol"]}
+    sig = {}
+    npts = lam.shape[0]
+    for name, prec in (("fp64", mbem.MBEM_FP64), ("mixed", mbem.MBEM_MIXED)):
+        S = mbem.Solver(xyz, tri, 1.0, 1.0, precision=prec)
+        try:
+            t0 = time.perf_counter()
+            # mixed: one inner GMRES to the sweep's tolerance, then the FP64
+            # residual check
+            sg, it, st = S.spectrum(k0, eps, kh, po, block=c["mbj_block"], tol=c["tol"],
+                                    maxit=800, inner_tol=c["tol"])
+            wall = time.perf_counter() - t0
+            flops = regular_fill_flops(S, tri, st.n_regular_pairs)
+        finally:
+            S.close()
+        sig[name] = sg
+        i = int(np.argmax(sg[:, 0]))
+        t_reg = st.t_regular_ms / npts
+        gemv_ms = st.t_matvec_ms / max(1, st.n_matvec)
+        n2 = 2 * xyz.shape[0]
+        gemv_bytes = 3 * n2 * n2 * (16 if name == "fp64" else 8) + 4 * n2 * 16
+        peak = PEAK_FP64_VALU
+        out[name] = {"wall_s": wall, "points_per_s": npts / wall,
+                     # FP64: every regular pair in one kernel; mixed: the FP32 far-pair
+                     # launch only (its near pairs run in FP64 beside it)
+                     "k_regular": ({"ms_per_point": t_reg, "tflops": flops / (t_reg * 1e-3) / 1e12,
+                                    "peak": peak, "frac": flops / (t_reg * 1e-3) / 1e12 / peak}
+                                   if name == "fp64" else
+                                   {"far_ms_per_point": t_reg, "near_ms_per_point": st.t_near_ms / npts,
+                                    "near_pairs_per_point": st.n_near_pairs / npts,
+                                    "regular_pairs": int(st.n_regular_pairs)}),
+                     "k_gemv3": {"ms_per_launch": gemv_ms,
+                                 "gbps": gemv_bytes / (gemv_ms * 1e-3) / 1e9,
+                                 "frac": gemv_bytes / (gemv_ms * 1e-3) / 1e9 / PEAK_HBM},
+                     "t_fill_ms": st.t_fill_ms, "t_setup_ms": st.t_setup_ms,
+                     "t_solve_ms": st.t_solve_ms, "t_matvec_ms": st.t_matvec_ms,
+                     "iters_total": int(st.iters), "iters_max": int(it.max()),
+                     "worst_rel_resid": st.rel_resid,
+                     "peak_lambda_nm": float(lam[i]), "peak_c_ext_nm2": float(sg[i, 0]),
+                     "energy_balance_max": float(np.abs((sg[:, 1] + sg[:, 2]) / sg[:, 0] - 1).max())}
+        log(f"spectrum study {name}: {lam.shape[0]} points in {wall:.2f} s, peak "
+            f"{sg[i, 0]:.0f} nm^2 at {lam[i]:.0f} nm")
+    out["mixed_vs_fp64_max_rel"] = float(np.abs(sig["mixed"] / sig["fp64"] - 1).max())
     return out
 
 
@@ -226,21 +316,18 @@ def main():
     from workloads import get_config, icosphere_p2, planewaves
     from workloads.configs import cut_plane_directions
 
-    if args.only in ("mrhs", "grad", "precond", "quad"):
-        args.paths = ""
-        args.no_cpu_baseline = True
-    if args.only == "main":
-        args.no_mrhs = args.no_grad = args.no_precond_study = args.no_quad_study = True
-    if args.only == "mrhs":
-        args.no_grad = args.no_precond_study = args.no_quad_study = True
-    if args.only == "grad":
-        args.no_mrhs = args.no_precond_study = args.no_quad_study = True
-    if args.only == "precond":
-        args.no_mrhs = args.no_grad = args.no_quad_study = True
-        args.steps, args.warmup = 0, 0
-    if args.only == "quad":
-        args.no_mrhs = args.no_grad = args.no_precond_study = True
-        args.steps, args.warmup = 0, 0
+    if args.only != "all":
+        # one pass of the step, or one study
+        keep = {"mrhs": "no_mrhs", "grad": "no_grad", "precond": "no_precond_study",
+                "quad": "no_quad_study", "spectrum": "no_spectrum_study"}
+        for name, flag in keep.items():
+            if name != args.only:
+                setattr(args, flag, True)
+        if args.only != "main":
+            args.paths = ""
+            args.no_cpu_baseline = True
+        if args.only in ("precond", "quad", "spectrum"):
+            args.steps, args.warmup = 0, 0
     cfg = get_config(args.workload)
     xyz, tri = icosphere_p2(cfg["n_tris"], cfg["axes"])
     khat, pol = planewaves(args.workload)
@@ -364,15 +451,7 @@ def main():
                         "kernel": "k_gemv3", "path": kp,
                         "algorithmic_bytes_per_launch": traffic, "launch_ms": per_launch_ms}
             if kname == "regular":
-                S = solvers[kp]
-                npairs = r["n_regular"]
-                rank = np.empty_like(S.node_order)
-                rank[S.node_order] = np.arange(S.nn)
-                tm = rank[tri[S.tri_order]]
-                ns = np.array([np.unique(tm[k:k + CHUNK]).size for k in range(0, nt, CHUNK)])
-                # every (test triangle, chunk) workgroup contracts ns test-side nodes
-                flops = (npairs * (49 * FLOP_POINT_PAIR + FLOP_PAIR_TRIAL)
-                         + nt * int(ns.sum()) * FLOP_CHUNK_TEST_PER_NODE)
+                flops = regular_fill_flops(solvers[kp], tri, r["n_regular"])
                 achieved = flops / (r["t_regular_ms"] * 1e-3) / 1e12
                 peak = PEAK_FP64_VALU if kp == "fp64" else PEAK_FP32_VALU
                 return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -468,12 +547,16 @@ def main():
     qstudy = None
     if not args.no_quad_study:
         qstudy = quad_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log)
+    sstudy = None
+    if not args.no_spectrum_study:
+        sstudy = spectrum_study(mbem, log)
 
     if not paths:
         # profiling run of one pass: its own section only
         print(json.dumps({"pass": args.only, "steps": args.steps, "warmup": args.warmup,
                           "ms_per_step": ms_per_step, "multi_rhs": mrhs, "gradient": grad,
-                          "precond_study": pstudy, "quadrature_study": qstudy}), flush=True)
+                          "precond_study": pstudy, "quadrature_study": qstudy,
+                          "spectrum_study": sstudy}), flush=True)
         for S in (Smr, Sg):
             if S is not None:
                 S.close()
@@ -507,6 +590,7 @@ def main():
         "gradient": grad,
         "precond_study": pstudy,
         "quadrature_study": qstudy,
+        "spectrum_study": sstudy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

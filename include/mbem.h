@@ -357,6 +357,36 @@ int mbem_cross_sections(mbem_ctx *ctx, const mbem_mesh *mesh,
                         const double *khat, const mbem_c128 *pol,
                         int32_t ntheta, double *out);
 
+/* ---- spectrum sweep (Sec. 7, Benchmark II: the LSPR spectrum) ------------- */
+
+/* The single-frequency path repeated over npts (k0, eps_r, mu_r) points on
+ * one mesh for one plane wave: at each point the operator is refilled in
+ * place (the geometry tables are built once for the sweep), the block-
+ * Jacobi preconditioner set up again (block > 0; block <= 0 solves without
+ * it), the right-hand side formed (mbem_rhs_planewave), the system solved
+ * (mbem_solve with opts) and the cross sections evaluated
+ * (mbem_cross_sections with ntheta; ntheta <= 0 picks 2 k0 a_max + 20 per
+ * point).  One operator, one preconditioner and one Krylov workspace serve
+ * the whole sweep; all are released before the call returns.
+ *   params  precision, quadrature, ssq_order and near_radius of every
+ *           point; its k0 and materials are ignored
+ *   k0      host [npts], each > 0;  eps_r host [npts];  mu_r host [npts]
+ *           or NULL (non-magnetic, mu_r = 1)
+ *   khat    host [3] unit direction;  pol host [3] polarisation
+ *   sigma   host [npts*3]: C_ext, C_sca, C_abs of point i at 3i..3i+2
+ *   iters   host [npts] GMRES iterations per point, or NULL
+ *   stats   NULL, or times and iteration counts summed over the points
+ *           (t_geom_ms: the one geometry build; rel_resid: the worst)
+ * MBEM_EINVAL for a bad argument (nothing is run), MBEM_ENOCONV when some
+ * point missed the tolerance (every point is still solved and written),
+ * MBEM_ESINGULAR on a singular preconditioner block (sigma holds the points
+ * before it).                                                              */
+int mbem_spectrum(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *params,
+                  int32_t npts, const double *k0, const mbem_c128 *eps_r,
+                  const mbem_c128 *mu_r, const double *khat, const mbem_c128 *pol,
+                  int32_t block, const mbem_solve_opts *opts, int32_t ntheta,
+                  double *sigma, int32_t *iters, mbem_stats *stats);
+
 const char *mbem_last_error(void);
 
 #ifdef __cplusplus

@@ -37,6 +37,15 @@ static void dfree(void *p) {
     if (p) (void)hipFree(p);
 }
 
+// Frees a device allocation when the scope ends (error returns included).
+struct Owned {
+    void *p = nullptr;
+    Owned() = default;
+    Owned(const Owned &) = delete;
+    Owned &operator=(const Owned &) = delete;
+    ~Owned() { dfree(p); }
+};
+
 // Elapsed milliseconds between two events recorded on the stream.
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
@@ -275,6 +284,74 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
     return conv ? MBEM_OK : MBEM_ENOCONV;
 }
 
+// Device buffers of the cross-section evaluation, grown on demand and kept
+// across the points of a sweep.
+struct CsWork {
+    int64_t cap = 0;
+    double *dirs = nullptr, *w = nullptr, *acc = nullptr;
+    double2 *F = nullptr;
+    CsWork() = default;
+    CsWork(const CsWork &) = delete;
+    CsWork &operator=(const CsWork &) = delete;
+    ~CsWork() { release(); }
+    void release() {
+        dfree(dirs); dfree(w); dfree(acc); dfree(F);
+        dirs = w = acc = nullptr; F = nullptr; cap = 0;
+    }
+    int reserve(int64_t ndir) {
+        if (ndir <= cap) return MBEM_OK;
+        release();
+        MBEM_TRY(dalloc(&dirs, 3 * ndir));
+        MBEM_TRY(dalloc(&w, ndir));
+        MBEM_TRY(dalloc(&acc, 2));
+        MBEM_TRY(dalloc(&F, 3 * ndir));
+        cap = ndir;
+        return MBEM_OK;
+    }
+};
+
+// C_ext by the optical theorem, C_sca by the product rule on the unit sphere
+// (Gauss-Legendre in cos theta x trapezoid in phi), C_abs by the surface
+// integral of the currents; ntheta <= 0 picks 2 k0 a_max + 20.
+static int cross_sections_impl(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const double2 *x,
+                               const double *khat, const mbem_c128 *pol, int32_t ntheta, double *out,
+                               CsWork &cw) {
+    const hipStream_t s = ctx->stream;
+    if (ntheta <= 0) ntheta = (int32_t)std::ceil(2.0 * p->k0 * mesh->amax) + 20;
+    const int nphi = 2 * ntheta;
+    const int64_t ndir = (int64_t)ntheta * nphi + 1;   // last one: khat
+    std::vector<double> dirs(3 * ndir), w(ndir, 0.0), u(ntheta), wu(ntheta);
+    gauss_legendre(ntheta, u.data(), wu.data());
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < ntheta; ++i)
+        for (int j = 0; j < nphi; ++j) {
+            const double ph = 2.0 * pi * j / nphi, st = std::sqrt(std::max(0.0, 1.0 - u[i] * u[i]));
+            const int64_t d = (int64_t)i * nphi + j;
+            dirs[3 * d] = st * std::cos(ph);
+            dirs[3 * d + 1] = st * std::sin(ph);
+            dirs[3 * d + 2] = u[i];
+            w[d] = wu[i] * 2.0 * pi / nphi;
+        }
+    for (int k = 0; k < 3; ++k) dirs[3 * (ndir - 1) + k] = khat[k];
+    MBEM_TRY(cw.reserve(ndir));
+    MBEM_HIP(hipMemcpyAsync(cw.dirs, dirs.data(), sizeof(double) * 3 * ndir, hipMemcpyHostToDevice, s));
+    MBEM_HIP(hipMemcpyAsync(cw.w, w.data(), sizeof(double) * ndir, hipMemcpyHostToDevice, s));
+    MBEM_TRY(farfield_run(mesh, p, x, 1, cw.dirs, ndir, cw.F, s));
+    MBEM_TRY(weighted_norm_run(ndir, cw.F, cw.w, cw.acc, s));
+    MBEM_TRY(absorbed_run(mesh, x, cw.acc + 1, s));
+    double acc[2];
+    double2 Ff[3];
+    MBEM_HIP(hipMemcpyAsync(acc, cw.acc, sizeof(acc), hipMemcpyDeviceToHost, s));
+    MBEM_HIP(hipMemcpyAsync(Ff, cw.F + 3 * (ndir - 1), sizeof(Ff), hipMemcpyDeviceToHost, s));
+    MBEM_HIP(hipStreamSynchronize(s));   // dirs and w are host vectors of this frame
+    std::complex<double> pe(0.0, 0.0);
+    for (int k = 0; k < 3; ++k) pe += std::conj(std::complex<double>(pol[k].re, pol[k].im)) * C(Ff[k]);
+    out[0] = 4.0 * pi / p->k0 * pe.imag();
+    out[1] = acc[0];
+    out[2] = acc[1];
+    return MBEM_OK;
+}
+
 }  // namespace mbem
 
 using namespace mbem;
@@ -381,6 +458,16 @@ int mbem_mesh_info(const mbem_mesh *m, int64_t *info) {
 }
 
 // Operator handle with its dense blocks and mass values allocated.
+// Wavenumbers, interior material and the coefficients of the combined
+// blocks (i/omega, (eps_i + 1)/2, (mu_i + 1)/2) of one frequency point.
+static void op_set_material(mbem_op *op, const mbem_params *p) {
+    op->p = *p;
+    derive_constants(p, &op->ka, &op->ki, &op->eps_i, &op->mu_i);
+    op->iw = {0.0, 1.0 / p->k0};
+    op->ce = {(op->eps_i.x + 1.0) / 2.0, op->eps_i.y / 2.0};
+    op->cm = {(op->mu_i.x + 1.0) / 2.0, op->mu_i.y / 2.0};
+}
+
 static int op_create(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_op **out) {
     if (!mesh || !p || !out) { set_error("null argument"); return MBEM_EINVAL; }
     if (p->precision != MBEM_FP64 && p->precision != MBEM_MIXED) { set_error("bad precision"); return MBEM_EINVAL; }
@@ -395,13 +482,9 @@ static int op_create(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p,
     if (!op) { set_error("host allocation"); return MBEM_ENOMEM; }
     op->ctx = ctx;
     op->mesh = mesh;
-    op->p = *p;
     op->prec = p->precision;
     op->n2 = 2 * mesh->nn;
-    derive_constants(p, &op->ka, &op->ki, &op->eps_i, &op->mu_i);
-    op->iw = {0.0, 1.0 / p->k0};
-    op->ce = {(op->eps_i.x + 1.0) / 2.0, op->eps_i.y / 2.0};
-    op->cm = {(op->mu_i.x + 1.0) / 2.0, op->mu_i.y / 2.0};
+    op_set_material(op, p);
     const size_t esz = op->prec == MBEM_FP64 ? 16 : 8;
     int st = MBEM_OK;
     for (int o = 0; o < 3 && st == MBEM_OK; ++o) {
@@ -512,8 +595,11 @@ int mbem_rhs_planewave(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *
     return st;
 }
 
+// r_ws, d_ws: optional device vectors of N elements (residual and
+// correction); allocated here when null.
 static int solve_impl(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs, const mbem_solve_opts *o,
-                      mbem_c128 *x, mbem_stats *stats, bool trans) {
+                      mbem_c128 *x, mbem_stats *stats, bool trans, double2 *r_ws = nullptr,
+                      double2 *d_ws = nullptr) {
     if (!op || !b || !x || !o || nrhs < 1 || o->maxit < 1 || !(o->tol > 0)) {
         set_error("bad argument");
         return MBEM_EINVAL;
@@ -525,9 +611,10 @@ static int solve_impl(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nr
     g.trans = trans;
     MBEM_TRY(gmres_alloc(g, op, o->maxit, s));
     const int64_t N = g.N;
-    double2 *r = nullptr, *d = nullptr;
-    MBEM_TRY(dalloc(&r, N));
-    MBEM_TRY(dalloc(&d, N));
+    double2 *r = r_ws, *d = d_ws;
+    Owned own_r, own_d;
+    if (!r_ws) { MBEM_TRY(dalloc(&r, N)); own_r.p = r; }
+    if (!d_ws) { MBEM_TRY(dalloc(&d, N)); own_d.p = d; }
     Timer t;
     t.start(s);
     int total_it = 0, sweeps = 0, status = MBEM_OK;
@@ -579,8 +666,6 @@ static int solve_impl(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nr
         if (!(rel <= 10 * o->tol)) status = MBEM_ENOCONV;
     }
     const double ms = t.stop(s);
-    dfree(r);
-    dfree(d);
     if (stats) {
         stats->iters = total_it;
         stats->outer_iters = sweeps;
@@ -777,50 +862,94 @@ int mbem_farfield(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, co
     return st;
 }
 
+int mbem_spectrum(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, int32_t npts, const double *k0,
+                  const mbem_c128 *eps_r, const mbem_c128 *mu_r, const double *khat, const mbem_c128 *pol,
+                  int32_t block, const mbem_solve_opts *o, int32_t ntheta, double *sigma, int32_t *iters,
+                  mbem_stats *stats) {
+    if (!mesh || !p || !k0 || !eps_r || !khat || !pol || !o || !sigma || npts < 1) {
+        set_error("bad argument");
+        return MBEM_EINVAL;
+    }
+    if (o->maxit < 1 || !(o->tol > 0)) { set_error("bad solve options"); return MBEM_EINVAL; }
+    if (block > kMaxBlock) { set_error("preconditioner block above 512 is not supported"); return MBEM_EINVAL; }
+    for (int32_t i = 0; i < npts; ++i)
+        if (!(k0[i] > 0)) { set_error("k0 must be positive at every point"); return MBEM_EINVAL; }
+    MBEM_TRY(set_device(ctx));
+    const hipStream_t s = ctx->stream;
+    auto point = [&](int32_t i) {
+        mbem_params q = *p;
+        q.k0 = k0[i];
+        q.eps_r_re = eps_r[i].re;
+        q.eps_r_im = eps_r[i].im;
+        q.mu_r_re = mu_r ? mu_r[i].re : 1.0;
+        q.mu_r_im = mu_r ? mu_r[i].im : 0.0;
+        return q;
+    };
+    mbem_params q = point(0);
+    mbem_op *op = nullptr;
+    MBEM_TRY(op_create(ctx, mesh, &q, &op));
+    struct OpRelease {
+        mbem_op *op;
+        ~OpRelease() { mbem_op_destroy(op); }
+    } release{op};
+    // one allocation for b, x, the residual and the correction
+    const int64_t N = 2 * op->n2;
+    double2 *vec = nullptr;
+    MBEM_TRY(dalloc(&vec, 4 * N + 3));
+    Owned own_vec;
+    own_vec.p = vec;
+    double2 *b = vec, *x = vec + N, *r = vec + 2 * N, *d = vec + 3 * N, *dpol = vec + 4 * N;
+    double *dk = nullptr;
+    MBEM_TRY(dalloc(&dk, 3));
+    Owned own_dk;
+    own_dk.p = dk;
+    MBEM_HIP(hipMemcpyAsync(dk, khat, sizeof(double) * 3, hipMemcpyHostToDevice, s));
+    MBEM_HIP(hipMemcpyAsync(dpol, pol, sizeof(double2) * 3, hipMemcpyHostToDevice, s));
+    CsWork cw;
+    mbem_stats tot{};
+    int status = MBEM_OK;
+    for (int32_t i = 0; i < npts; ++i) {
+        q = point(i);
+        op_set_material(op, &q);
+        Timer t;
+        t.start(s);
+        MBEM_TRY(fill_run(op, s, false, i == 0));   // the geometry tables once
+        tot.t_fill_ms += t.stop(s);
+        if (i == 0) tot.t_geom_ms = op->t_phase[0];
+        tot.t_regular_ms += op->t_phase[1];
+        tot.t_near_ms += op->t_phase[2];
+        tot.t_ssq_ms += op->t_phase[3];
+        tot.t_mass_ms += op->t_phase[4];
+        tot.n_near_pairs += op->n_near;
+        t.start(s);
+        MBEM_TRY(mbj_setup_run(op, block, s, true));
+        tot.t_setup_ms += t.stop(s);
+        MBEM_TRY(rhs_run(mesh, &q, dk, dpol, 1, b, s));
+        mbem_stats ss{};
+        const int st = solve_impl(ctx, op, (const mbem_c128 *)b, 1, o, (mbem_c128 *)x, &ss, false, r, d);
+        if (st != MBEM_OK && st != MBEM_ENOCONV) return st;
+        if (st == MBEM_ENOCONV) status = MBEM_ENOCONV;
+        tot.iters += ss.iters;
+        tot.outer_iters += ss.outer_iters;
+        tot.rel_resid = std::max(tot.rel_resid, ss.rel_resid);
+        tot.t_solve_ms += ss.t_solve_ms;
+        tot.t_matvec_ms += ss.t_matvec_ms;
+        tot.n_matvec += ss.n_matvec;
+        if (iters) iters[i] = ss.iters;
+        MBEM_TRY(cross_sections_impl(ctx, mesh, &q, x, khat, pol, ntheta, sigma + 3 * (int64_t)i, cw));
+    }
+    tot.n_regular_pairs = mesh->nt * mesh->nt - mesh->n_spairs;
+    if (stats) *stats = tot;
+    if (status == MBEM_ENOCONV) set_error("GMRES did not reach the tolerance at some point of the sweep");
+    return status;
+}
+
 int mbem_cross_sections(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const mbem_c128 *x,
                         const double *khat, const mbem_c128 *pol, int32_t ntheta, double *out) {
     if (!mesh || !p || !x || !khat || !pol || !out) { set_error("null argument"); return MBEM_EINVAL; }
     MBEM_TRY(set_device(ctx));
-    const hipStream_t s = ctx->stream;
-    if (ntheta <= 0) ntheta = (int32_t)std::ceil(2.0 * p->k0 * mesh->amax) + 20;
-    const int nphi = 2 * ntheta;
-    const int64_t ndir = (int64_t)ntheta * nphi + 1;   // last one: khat
-    std::vector<double> dirs(3 * ndir), w(ndir, 0.0), u(ntheta), wu(ntheta);
-    gauss_legendre(ntheta, u.data(), wu.data());
-    const double pi = 3.14159265358979323846;
-    for (int i = 0; i < ntheta; ++i)
-        for (int j = 0; j < nphi; ++j) {
-            const double ph = 2.0 * pi * j / nphi, st = std::sqrt(std::max(0.0, 1.0 - u[i] * u[i]));
-            const int64_t d = (int64_t)i * nphi + j;
-            dirs[3 * d] = st * std::cos(ph);
-            dirs[3 * d + 1] = st * std::sin(ph);
-            dirs[3 * d + 2] = u[i];
-            w[d] = wu[i] * 2.0 * pi / nphi;
-        }
-    for (int k = 0; k < 3; ++k) dirs[3 * (ndir - 1) + k] = khat[k];
-    double *dd = nullptr, *dw = nullptr, *dacc = nullptr;
-    double2 *dF = nullptr;
-    MBEM_TRY(dalloc(&dd, 3 * ndir));
-    MBEM_TRY(dalloc(&dw, ndir));
-    MBEM_TRY(dalloc(&dacc, 2));
-    MBEM_TRY(dalloc(&dF, 3 * ndir));
-    MBEM_HIP(hipMemcpyAsync(dd, dirs.data(), sizeof(double) * 3 * ndir, hipMemcpyHostToDevice, s));
-    MBEM_HIP(hipMemcpyAsync(dw, w.data(), sizeof(double) * ndir, hipMemcpyHostToDevice, s));
-    MBEM_TRY(farfield_run(mesh, p, (const double2 *)x, 1, dd, ndir, dF, s));
-    MBEM_TRY(weighted_norm_run(ndir, dF, dw, dacc, s));
-    MBEM_TRY(absorbed_run(mesh, (const double2 *)x, dacc + 1, s));
-    double acc[2];
-    double2 Ff[3];
-    MBEM_HIP(hipMemcpyAsync(acc, dacc, sizeof(acc), hipMemcpyDeviceToHost, s));
-    MBEM_HIP(hipMemcpyAsync(Ff, dF + 3 * (ndir - 1), sizeof(Ff), hipMemcpyDeviceToHost, s));
-    MBEM_HIP(hipStreamSynchronize(s));
-    std::complex<double> pe(0.0, 0.0);
-    for (int k = 0; k < 3; ++k) pe += std::conj(std::complex<double>(pol[k].re, pol[k].im)) * C(Ff[k]);
-    out[0] = 4.0 * pi / p->k0 * pe.imag();
-    out[1] = acc[0];
-    out[2] = acc[1];
-    dfree(dd); dfree(dw); dfree(dacc); dfree(dF);
-    return MBEM_OK;
+    CsWork w;
+    return cross_sections_impl(ctx, mesh, p, (const double2 *)x, khat, pol, ntheta, out, w);
 }
 
 }  // extern "C"

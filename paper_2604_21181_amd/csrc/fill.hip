@@ -950,7 +950,7 @@ struct PhaseEvents {
     }
 };
 
-int fill_run(mbem_op *op, hipStream_t s, bool deriv) {
+int fill_run(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     const mbem_mesh *m = op->mesh;
     const bool paper = op->p.quadrature == MBEM_QUAD_PAPER;
     if (paper && deriv) { set_error("the eps derivative is built for the default quadrature only"); return MBEM_EINVAL; }
@@ -971,7 +971,7 @@ int fill_run(mbem_op *op, hipStream_t s, bool deriv) {
     for (int o = 0; o < 3; ++o)
         MBEM_HIP(hipMemsetAsync(op->K[o], 0, esz * op->n2 * op->n2, s));
     pe.mark(0, s);
-    MBEM_TRY(geom_build(m, s, paper));
+    if (geom) MBEM_TRY(geom_build(m, s, paper));
     pe.mark(1, s);
     unsigned long long *cnt = nullptr;
     if (paper && op->prec == MBEM_FP64) {

@@ -300,7 +300,6 @@ __global__ void k_mbj_gather(int64_t n2, int B, const void *K0, const void *K1, 
 // updated from L21 and U12 staged in LDS (one pass over A22 per panel).
 // Instantiated for blocks up to 512 (B <= 256, panels of 8) and up to 1024
 // (B <= 512, panels of 4, so that L21 and U12 still fit in LDS).
-constexpr int kMaxBlock = 512;        // largest supported cluster size B
 
 template <int MAXN, int kPW>
 __global__ __launch_bounds__(1024) void k_mbj_lu(int64_t n2, int B, double2 *A, int32_t *piv,
@@ -515,21 +514,27 @@ __global__ __launch_bounds__(256) void k_mbj_apply(int64_t n2, int B, int nb, co
     if (lane == 0) z[(r < b ? 0 : n2) + m * B + (r % b)] = {re, im};
 }
 
-int mbj_setup_run(mbem_op *op, int B, hipStream_t s) {
-    if (op->d_minv) { MBEM_HIP(hipFree(op->d_minv)); op->d_minv = nullptr; }
-    if (op->d_lu) { MBEM_HIP(hipFree(op->d_lu)); op->d_lu = nullptr; }
+int mbj_setup_run(mbem_op *op, int B, hipStream_t s, bool keep) {
+    // the transposed inverses belong to the previous blocks
     if (op->d_minv_t) { MBEM_HIP(hipFree(op->d_minv_t)); op->d_minv_t = nullptr; }
     op->B = 0; op->nb = 0;
-    if (B <= 0) return MBEM_OK;
     if (B > kMaxBlock) { set_error("preconditioner block above 512 is not supported"); return MBEM_EINVAL; }
     const int64_t n2 = op->n2;
     if (B > n2) B = (int)n2;
-    const int nb = (int)((n2 + B - 1) / B);
+    const int nb = B > 0 ? (int)((n2 + B - 1) / B) : 0;
     const int64_t ld = 2 * (int64_t)B;
-    const size_t bytes = sizeof(double2) * nb * ld * ld;
+    const size_t bytes = B > 0 ? sizeof(double2) * nb * ld * ld : 0;
     // factors and pivots in one scratch allocation: [nb][ld][ld] + [nb][ld] + info
-    MBEM_HIP(hipMalloc((void **)&op->d_lu, bytes + sizeof(int32_t) * (nb * ld + 1)));
-    MBEM_HIP(hipMalloc((void **)&op->d_minv, bytes));
+    const size_t lu_bytes = B > 0 ? bytes + sizeof(int32_t) * (nb * ld + 1) : 0;
+    if (op->d_minv && op->minv_bytes != bytes) {
+        MBEM_HIP(hipFree(op->d_minv)); op->d_minv = nullptr; op->minv_bytes = 0;
+    }
+    if (op->d_lu && op->lu_bytes != lu_bytes) {
+        MBEM_HIP(hipFree(op->d_lu)); op->d_lu = nullptr; op->lu_bytes = 0;
+    }
+    if (B <= 0) return MBEM_OK;
+    if (!op->d_lu) { MBEM_HIP(hipMalloc((void **)&op->d_lu, lu_bytes)); op->lu_bytes = lu_bytes; }
+    if (!op->d_minv) { MBEM_HIP(hipMalloc((void **)&op->d_minv, bytes)); op->minv_bytes = bytes; }
     int32_t *piv = (int32_t *)((char *)op->d_lu + bytes);
     int32_t *info = piv + nb * ld;
     MBEM_HIP(hipMemsetAsync(info, 0, sizeof(int32_t), s));
@@ -557,12 +562,12 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s) {
     int32_t h = 0;
     MBEM_HIP(hipMemcpyAsync(&h, info, sizeof(h), hipMemcpyDeviceToHost, s));
     MBEM_HIP(hipStreamSynchronize(s));
-    MBEM_HIP(hipFree(op->d_lu));
-    op->d_lu = nullptr;
+    if (!keep) { MBEM_HIP(hipFree(op->d_lu)); op->d_lu = nullptr; op->lu_bytes = 0; }
     if (h) {
         set_error("zero pivot in preconditioner block " + std::to_string(h - 1));
         MBEM_HIP(hipFree(op->d_minv));
         op->d_minv = nullptr;
+        op->minv_bytes = 0;
         return MBEM_ESINGULAR;
     }
     op->B = B;

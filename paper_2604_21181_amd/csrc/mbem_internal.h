@@ -34,6 +34,7 @@ void set_error(const std::string &msg);
 // ------------------------------------------------------------ constants --
 constexpr int kQP = 7;          // regular rule points per triangle
 constexpr int kQP12 = 12;       // points of the 12-point rule (paper's scheme)
+constexpr int kMaxBlock = 512;  // largest supported block-Jacobi cluster size B
 constexpr int kQPF = 19;        // doubles per quadrature point in the table
 constexpr int kMaxSSQ = 8;      // largest Sauter-Schwab order supported
 constexpr int kChunk = 4;       // trial triangles per regular-pair workgroup
@@ -110,6 +111,7 @@ struct mbem_op {
     double2 *d_minv = nullptr;      // [nb][2B][2B] inverses
     double2 *d_minv_t = nullptr;    // their transposes (adjoint solves)
     double2 *d_lu = nullptr;        // scratch of the factorisation
+    size_t minv_bytes = 0, lu_bytes = 0;   // sizes of d_minv and d_lu
     // solver workspace
     double2 *d_work = nullptr;
     size_t work_elems = 0;
@@ -147,7 +149,9 @@ int geom_build(const mbem_mesh *m, hipStream_t s, bool with12 = false);
 
 // fill (fill.hip)
 // deriv: fill dK/deps_i instead of K (FP64 operators only)
-int fill_run(mbem_op *op, hipStream_t s, bool deriv = false);
+// geom = false: the mesh's geometry tables are already built (a sweep that
+// refills the same mesh)
+int fill_run(mbem_op *op, hipStream_t s, bool deriv = false, bool geom = true);
 int mass_run(mbem_op *op, hipStream_t s);
 
 // linear algebra (linalg.hip)
@@ -156,7 +160,10 @@ int matvec_run(const mbem_op *op, const double2 *x, double2 *y, double2 *tmp,
 int export_dense_run(const mbem_op *op, double2 *Z, hipStream_t s);
 int export_blocks_run(const mbem_op *op, double2 *K1, double2 *K2e,
                       double2 *K2m, hipStream_t s);
-int mbj_setup_run(mbem_op *op, int B, hipStream_t s);
+// keep = true: the factorisation scratch stays allocated for the next setup
+// of the same block size (sweeps); the inverses are reused whenever the size
+// matches
+int mbj_setup_run(mbem_op *op, int B, hipStream_t s, bool keep = false);
 // trans: apply P^-T (mbj_transpose_run must have run)
 int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z,
                   hipStream_t s, bool trans = false);

@@ -28,7 +28,7 @@ EXPORTED = [
     "mbem_precond_setup", "mbem_precond_apply", "mbem_rhs_planewave", "mbem_solve",
     "mbem_farfield", "mbem_cross_sections", "mbem_last_error", "mbem_solve_block",
     "mbem_gemm_autotune", "mbem_cgemm", "mbem_solve_adjoint", "mbem_fill_deps",
-    "mbem_farfield_functional", "mbem_grad_sigma_ext", "mbem_mesh_frames",
+    "mbem_farfield_functional", "mbem_grad_sigma_ext", "mbem_mesh_frames", "mbem_spectrum",
 ]
 GEMM_CONFIGS = 6   # FP32 GEMM tile shapes known to the autotuner
 
@@ -119,6 +119,8 @@ def lib():
             "mbem_farfield_functional": ([P, P, C.POINTER(Params), P, P, P], C.c_int),
             "mbem_grad_sigma_ext": ([P, P, P, C.POINTER(Params), P, P, P, C.POINTER(SolveOpts), P, P,
                                      P, P, C.POINTER(Stats)], C.c_int),
+            "mbem_spectrum": ([P, P, C.POINTER(Params), i32, P, P, P, P, P, i32,
+                               C.POINTER(SolveOpts), i32, P, P, C.POINTER(Stats)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -322,6 +324,32 @@ def mbem_cross_sections(ctx, mesh, params, x, khat, pol, ntheta=0):
     return out
 
 
+def mbem_spectrum(ctx, mesh, params, k0, eps_r, khat, pol, mu_r=None, block=100, tol=1e-5,
+                  maxit=500, max_refine=0, inner_tol=0.0, ntheta=0):
+    """Cross sections over (k0, eps_r[, mu_r]) points.  Returns
+    (sigma[npts, 3] = C_ext, C_sca, C_abs; iters[npts]; Stats, summed).
+    A point that missed the tolerance does not raise: its iteration count
+    and stats.rel_resid show it."""
+    k0 = np.ascontiguousarray(np.atleast_1d(k0), dtype=np.float64)
+    eps = np.ascontiguousarray(np.atleast_1d(eps_r), dtype=np.complex128)
+    mu = None if mu_r is None else np.ascontiguousarray(np.atleast_1d(mu_r), dtype=np.complex128)
+    if eps.shape != k0.shape or (mu is not None and mu.shape != k0.shape):
+        raise ValueError("k0, eps_r and mu_r need one entry per point")
+    khat = np.ascontiguousarray(khat, dtype=np.float64).ravel()
+    pol = np.ascontiguousarray(pol, dtype=np.complex128).ravel()
+    if khat.shape != (3,) or pol.shape != (3,):
+        raise ValueError("khat and pol are 3-vectors")
+    sigma = np.zeros((k0.shape[0], 3))
+    iters = np.zeros(k0.shape[0], dtype=np.int32)
+    o = SolveOpts(tol, maxit, max_refine, inner_tol)
+    st = Stats()
+    _check(lib().mbem_spectrum(ctx, mesh, C.byref(params), k0.shape[0], _np_ptr(k0), _np_ptr(eps),
+                               _np_ptr(mu) if mu is not None else None, _np_ptr(khat), _np_ptr(pol),
+                               block, C.byref(o), ntheta, _np_ptr(sigma), _np_ptr(iters),
+                               C.byref(st)), allow=(MBEM_ENOCONV,))
+    return sigma, iters, st
+
+
 # ------------------------------------------------------------- convenience --
 class Solver:
     """Mesh + operator handles on one device; vectors are torch tensors in
@@ -464,6 +492,12 @@ class Solver:
 
     def cross_sections(self, x, khat, pol, ntheta=0):
         return mbem_cross_sections(self.ctx, self.mesh, self.params, x.contiguous(), khat, pol, ntheta)
+
+    def spectrum(self, k0, eps_r, khat, pol, mu_r=None, block=100, tol=1e-5, **kw):
+        """Sweep on this solver's mesh with its precision and quadrature (its
+        own k0 and materials are not used); see mbem_spectrum."""
+        return mbem_spectrum(self.ctx, self.mesh, self.params, k0, eps_r, khat, pol, mu_r, block,
+                             tol, **kw)
 
     def close(self):
         if self.op is not None:
