@@ -14,6 +14,7 @@ direct form, from the paper (arXiv 2604.21181):
   solver.py    Morton order, Morton block-Jacobi, GMRES
   mie.py       Mie series (spheres)
   spectrum.py  sweeps over wavenumber and material on one mesh
+  blr.py       block low-rank compression of the operator blocks (ACA)
 
 Parity status of every function is listed in the design notes; everything
 here is pinned by the CPU test-suite (quadrature exactness, closed forms,
@@ -23,10 +24,10 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import core, galerkin, mie, solver, spectrum
+from . import blr, core, galerkin, mie, solver, spectrum
 from .galerkin import Problem
 
-__all__ = ["core", "galerkin", "mie", "solver", "spectrum", "Problem", "solve_dense"]
+__all__ = ["blr", "core", "galerkin", "mie", "solver", "spectrum", "Problem", "solve_dense"]
 
 
 def solve_dense(P: Problem, khat, pol, K=None):
