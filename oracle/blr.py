@@ -6,9 +6,12 @@ The paper leaves compressed far-field interactions to future work (Sec. 8,
 FMM for problems beyond dense memory).  The compressed operator checked
 here is defined as follows, on the Morton-ordered nodes of Sec. 5:
 
-  * clusters: consecutive runs of L Morton-ordered nodes (the last one
-    shorter); cluster c owns rows / columns 2 i + alpha of every operator
-    block for its nodes i;
+  * clusters: the leaves of the octree of the nodes' Morton keys (63 bits,
+    Sec. 5): the nodes sharing the top 3 l key bits form a cell of level l,
+    a contiguous run of the Morton order; a cell with more than L nodes is
+    split into its children (the runs sharing 3 (l + 1) bits), down to level
+    21, where a run still longer than L is cut into pieces of L.  Cluster c
+    owns rows / columns 2 i + alpha of every operator block for its nodes i;
   * support box of a cluster: the axis-aligned bounding box of the six nodes
     of every element that has a node in the cluster (it holds the support of
     every basis function of the cluster);
@@ -26,9 +29,32 @@ from __future__ import annotations
 import numpy as np
 
 
-def clusters(nn, L):
-    """[(first, last + 1)] node ranges of the Morton-ordered nodes."""
-    return [(s, min(s + L, nn)) for s in range(0, nn, L)]
+def node_keys(xyz_m):
+    """Morton keys of the Morton-ordered nodes (non-decreasing)."""
+    from . import solver
+    lo = xyz_m.min(axis=0)
+    ext = float((xyz_m.max(axis=0) - lo).max())
+    return solver.morton_keys(xyz_m, lo, ext)
+
+
+def clusters(keys, L):
+    """[(first, last + 1)] node ranges of the octree leaves (see above)."""
+    out = []
+
+    def split(a, b, lev):
+        if b - a <= L:
+            out.append((a, b))
+            return
+        if lev == 21:
+            out.extend((s, min(s + L, b)) for s in range(a, b, L))
+            return
+        pre = keys[a:b] >> np.uint64(3 * (20 - lev))
+        cuts = [a] + (np.nonzero(pre[1:] != pre[:-1])[0] + 1 + a).tolist() + [b]
+        for u, v in zip(cuts[:-1], cuts[1:]):
+            split(u, v, lev + 1)
+
+    split(0, keys.shape[0], 0)
+    return out
 
 
 def support_boxes(xyz_m, tri_m, cl):
@@ -113,8 +139,7 @@ def compress(Ks, xyz_m, tri_m, L, eta, eps, rmax, keep_all=False):
     Returns dict(cl, adm, tiles) with tiles[(o, t, s)] = ("dense", A) or
     ("lowrank", U, V).  keep_all keeps every converged approximation low-rank
     even when it stores more than the dense tile (exercises small meshes)."""
-    nn = xyz_m.shape[0]
-    cl = clusters(nn, L)
+    cl = clusters(node_keys(xyz_m), L)
     lo, hi = support_boxes(xyz_m, tri_m, cl)
     adm = admissibility(lo, hi, eta)
     tiles = {}

@@ -64,13 +64,27 @@ def _morton(xyz, tri):
     return no, xyz[no], rank[tri]
 
 
-@pytest.mark.parametrize("L,eta", [(8, 3.0), (16, 2.0), (5, 1.5)])
+@pytest.mark.parametrize("L,eta", [(16, 3.0), (12, 2.0), (24, 1.5)])
 def test_partition_and_admissibility(L, eta):
     xyz, tri = icosphere_p2(320)
     no, xyz_m, tri_m = _morton(xyz, tri)
-    cl = blr.clusters(xyz.shape[0], L)
+    keys = blr.node_keys(xyz_m)
+    cl = blr.clusters(keys, L)
     assert cl[0][0] == 0 and cl[-1][1] == xyz.shape[0]
     assert all(a[1] == b[0] for a, b in zip(cl[:-1], cl[1:]))
+    assert all(0 < b - a <= L for a, b in cl)
+    # each cluster is an octree cell (or a piece of a finest cell): its keys
+    # share a prefix that no neighbouring cluster's keys extend
+    for a, b in cl:
+        common = 0
+        for lev in range(22):
+            sh = np.uint64(3 * (21 - lev))
+            if np.all((keys[a:b] >> sh) == (keys[a] >> sh)):
+                common = lev
+        sh = np.uint64(3 * (21 - common))
+        inside = (keys >> sh) == (keys[a] >> sh)
+        # the cell of that prefix holds more than L nodes unless it is the cluster
+        assert inside.sum() == b - a or inside.sum() > L
     lo, hi = blr.support_boxes(xyz_m, tri_m, cl)
     adm = blr.admissibility(lo, hi, eta)
     assert not np.any(np.diag(adm)) and adm.sum() > 0
@@ -103,9 +117,9 @@ def sphere320():
 def test_compressed_operator_error(sphere320):
     P, K, Km, no, xyz_m, tri_m = sphere320
     eps = 1e-6
-    C = blr.compress(Km, xyz_m, tri_m, 8, 3.0, eps, 64, keep_all=True)
+    C = blr.compress(Km, xyz_m, tri_m, 16, 3.0, eps, 64, keep_all=True)
     n_lr = sum(1 for v in C["tiles"].values() if v[0] == "lowrank")
-    assert n_lr > 1000
+    assert n_lr > 3000
     for o in range(3):
         E = blr.expand(C, o, Km[o].shape[0])
         assert np.linalg.norm(E - Km[o]) <= 10 * eps * np.linalg.norm(Km[o])
@@ -124,7 +138,7 @@ def test_compressed_solve_far_field(sphere320):
     rdir = np.array([[np.sin(t), 0, np.cos(t)] for t in np.linspace(0, np.pi, 19)])
     F = galerkin.far_field(P, x, rdir)
     for eps, tol in ((1e-4, 2e-3), (1e-6, 2e-5)):
-        C = blr.compress(Km, xyz_m, tri_m, 8, 3.0, eps, 64, keep_all=True)
+        C = blr.compress(Km, xyz_m, tri_m, 16, 3.0, eps, 64, keep_all=True)
         xc = np.linalg.solve(blr.assemble(P, C, no), b)
         Fc = galerkin.far_field(P, xc, rdir)
         assert np.linalg.norm(Fc - F) / np.linalg.norm(F) <= tol, eps
