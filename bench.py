@@ -33,6 +33,13 @@ One step = the whole hot path, both precisions side by side:
          points per second, phase times, the extinction peak and the energy
          balance.  The preconditioner study also runs this spheroid at its
          506 nm resonance (the paper's comparison of 822 vs 18 iterations).
+  COMPRESSED OPERATOR STUDY (once): the block low-rank operator (octree
+         clusters of at most 512 nodes, eta = 2, cross approximation to 1e-6)
+         on a 20480-triangle sphere, k_a = 5, eps_r = 2.25: 163848 unknowns,
+         whose dense FP64 blocks (322 GB) exceed the device; fill and
+         compression time, stored bytes, the compressed product's time and
+         bandwidth, GMRES (block-Jacobi, 100) to 1e-8, cross sections and
+         their energy balance.
   QUADRATURE STUDY (once): the paper's own scheme (12-point rule, Sauter-
          Schwab on the singular kernels only, 12-point remainder) against the
          default on the same sphere, FP64 and mixed: fill times and far-field
@@ -127,10 +134,12 @@ def parse():
                     help="skip the comparison of the default quadrature with the paper's scheme")
     ap.add_argument("--no-spectrum-study", action="store_true",
                     help="skip the LSPR spectrum sweep of the silver spheroid")
+    ap.add_argument("--no-blr-study", action="store_true",
+                    help="skip the block low-rank operator beyond dense memory")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device to device once (scales the FETCH_SIZE / WRITE_SIZE "
                          "counters) and exit")
-    ap.add_argument("--only", choices=["all", "main", "mrhs", "grad", "precond", "quad", "spectrum"],
+    ap.add_argument("--only", choices=["all", "main", "mrhs", "grad", "precond", "quad", "spectrum", "blr"],
                     default="all",
                     help="run one pass of the step only (for profiling); the JSON line is "
                          "printed for 'all' and 'main'")
@@ -262,6 +271,45 @@ def spectrum_study(mbem, log):
     return out
 
 
+BLR_STUDY = dict(n_tris=20480, k0=5.0, eps_r=2.25,
+                 opts=dict(cluster=512, eta=2.0, eps=1e-6, rmax=128), block=100, tol=1e-8)
+
+
+def blr_study(mbem, icosphere_p2, log):
+    """Block low-rank operator beyond dense memory (see the module docstring);
+    its accuracy against the Mie series is checked by the GPU tests, here the
+    energy balance C_ext = C_sca + C_abs (a lossless sphere) is reported."""
+    c = BLR_STUDY
+    xyz, tri = icosphere_p2(c["n_tris"])
+    S = mbem.Solver(xyz, tri, c["k0"], c["eps_r"])
+    try:
+        bs = S.fill_compressed(**c["opts"])
+        ps = S.precond_setup(c["block"])
+        kh, po = np.array([0, 0, 1.0]), np.array([1.0, 0, 0], dtype=np.complex128)
+        x, st, code = S.solve(S.rhs(kh, po), c["tol"], maxit=800)
+        cs = S.cross_sections(x[0], kh, po)
+        mv = st.t_matvec_ms / max(1, st.n_matvec)
+        # bytes of one product: every stored tile once, x twice per block, t out
+        mv_bytes = bs.stored_bytes + 4 * S.N * 16
+        out = {"workload": f"sphere{c['n_tris']}", "unknowns": S.N, "k0": c["k0"], "eps_r": c["eps_r"],
+               "options": c["opts"], "t_fill_ms": bs.t_total_ms, "t_band_fill_ms": bs.t_fill_ms,
+               "t_aca_ms": bs.t_aca_ms, "stored_gb": bs.stored_bytes / 1e9,
+               "dense_gb": bs.dense_bytes / 1e9, "stored_fraction": bs.stored_bytes / bs.dense_bytes,
+               "clusters": bs.n_clusters, "lowrank_tiles": bs.n_lowrank, "tiles": bs.n_tiles,
+               "mean_rank": bs.mean_rank, "max_rank": bs.max_rank,
+               "matvec_ms": mv, "matvec_gbps": mv_bytes / (mv * 1e-3) / 1e9,
+               "matvec_hbm_frac": mv_bytes / (mv * 1e-3) / 1e9 / PEAK_HBM,
+               "t_setup_ms": ps.t_setup_ms if ps is not None else None,
+               "gmres_iters": st.iters, "t_solve_ms": st.t_solve_ms, "converged": code == 0,
+               "c_ext": cs[0], "c_sca": cs[1], "c_abs": cs[2]}
+        out["energy_balance"] = (cs[1] + cs[2]) / cs[0] - 1
+        log(f"compressed study: {S.N} unknowns, {bs.stored_bytes / 1e9:.1f} of {bs.dense_bytes / 1e9:.1f} GB, "
+            f"fill {bs.t_total_ms:.0f} ms, product {mv:.2f} ms, {st.iters} iterations")
+        return out
+    finally:
+        S.close()
+
+
 def quad_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3):
     """The paper's own quadrature (12-point rule, Sauter-Schwab on the
     singular kernels, 12-point remainder) against the default on the
@@ -319,14 +367,14 @@ def main():
     if args.only != "all":
         # one pass of the step, or one study
         keep = {"mrhs": "no_mrhs", "grad": "no_grad", "precond": "no_precond_study",
-                "quad": "no_quad_study", "spectrum": "no_spectrum_study"}
+                "quad": "no_quad_study", "spectrum": "no_spectrum_study", "blr": "no_blr_study"}
         for name, flag in keep.items():
             if name != args.only:
                 setattr(args, flag, True)
         if args.only != "main":
             args.paths = ""
             args.no_cpu_baseline = True
-        if args.only in ("precond", "quad", "spectrum"):
+        if args.only in ("precond", "quad", "spectrum", "blr"):
             args.steps, args.warmup = 0, 0
     cfg = get_config(args.workload)
     xyz, tri = icosphere_p2(cfg["n_tris"], cfg["axes"])
@@ -550,13 +598,16 @@ def main():
     sstudy = None
     if not args.no_spectrum_study:
         sstudy = spectrum_study(mbem, log)
+    bstudy = None
+    if not args.no_blr_study:
+        bstudy = blr_study(mbem, icosphere_p2, log)
 
     if not paths:
         # profiling run of one pass: its own section only
         print(json.dumps({"pass": args.only, "steps": args.steps, "warmup": args.warmup,
                           "ms_per_step": ms_per_step, "multi_rhs": mrhs, "gradient": grad,
                           "precond_study": pstudy, "quadrature_study": qstudy,
-                          "spectrum_study": sstudy}), flush=True)
+                          "spectrum_study": sstudy, "blr_study": bstudy}), flush=True)
         for S in (Smr, Sg):
             if S is not None:
                 S.close()
@@ -591,6 +642,7 @@ def main():
         "precond_study": pstudy,
         "quadrature_study": qstudy,
         "spectrum_study": sstudy,
+        "blr_study": bstudy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -357,6 +357,57 @@ int mbem_cross_sections(mbem_ctx *ctx, const mbem_mesh *mesh,
                         const double *khat, const mbem_c128 *pol,
                         int32_t ntheta, double *out);
 
+/* ---- block low-rank operator (compressed far interactions) ---------------- */
+
+/* The paper leaves compressed far-field interactions to future work (Sec. 8);
+ * this operator stores far tiles of K1, K2^eps, K2^mu in low-rank form.
+ * Clusters: the leaves of the octree of the nodes' Morton keys (Sec. 5),
+ * cells of more than `cluster` nodes split into their eight children, each
+ * leaf a run of the Morton order; a cluster's support box bounds the nodes
+ * of every element touching it; a cluster pair
+ * is admissible when its boxes are apart and max(diam) <= eta * dist.  Every
+ * admissible tile is approximated by adaptive cross approximation with
+ * partial pivoting to relative Frobenius accuracy eps (at most rmax terms);
+ * it is kept low-rank when that converged and stores less than the dense
+ * tile (or always, keep_lowrank = 1), else dense.  Other tiles are dense.
+ * The dense operator is never formed: rows are filled one cluster band at a
+ * time into a scratch of 3 x 2(cluster + halo) x 2 n_nodes entries.        */
+typedef struct {
+    int32_t cluster;       /* largest nodes per cluster, 1..2048            */
+    double eta;            /* admissibility parameter, > 0                  */
+    double eps;            /* cross-approximation tolerance, (0, 1)         */
+    int32_t rmax;          /* largest rank, 1..128                          */
+    int32_t keep_lowrank;  /* 1: keep every converged approximation low-rank */
+} mbem_blr_opts;
+
+typedef struct {
+    int64_t stored_bytes;  /* dense and low-rank tiles                      */
+    int64_t dense_bytes;   /* the three dense blocks it stands for          */
+    int32_t n_clusters;
+    int32_t n_tiles;       /* 3 n_clusters^2                                */
+    int32_t n_admissible;  /* admissible tiles (all three blocks)           */
+    int32_t n_lowrank;     /* tiles stored low-rank                         */
+    int32_t max_rank;
+    double mean_rank;      /* over the low-rank tiles                       */
+    double t_fill_ms;      /* band fills (regular and singular pairs)       */
+    double t_aca_ms;       /* cross approximation                           */
+    double t_total_ms;     /* the whole call                                */
+} mbem_blr_stats;
+
+/* Fill a block low-rank operator (FP64, default quadrature only).  The
+ * returned operator works with mbem_matvec, mbem_precond_setup/apply,
+ * mbem_solve and mbem_op_export_blocks (which expands it; small meshes);
+ * mbem_op_export_dense, mbem_solve_adjoint, mbem_solve_block,
+ * mbem_gemm_autotune and mbem_grad_sigma_ext reject it (MBEM_EINVAL).  The
+ * far field and cross sections take the solution only.  MBEM_EINVAL for
+ * options out of range, MBEM_ENOMEM when the band scratch or the tiles do
+ * not fit.  stats may be NULL (t_fill_ms: the whole call); bstats may be
+ * NULL.                                                                     */
+int mbem_fill_compressed(mbem_ctx *ctx, const mbem_mesh *mesh,
+                         const mbem_params *params, const mbem_blr_opts *opts,
+                         mbem_op **out, mbem_stats *stats,
+                         mbem_blr_stats *bstats);
+
 /* ---- spectrum sweep (Sec. 7, Benchmark II: the LSPR spectrum) ------------- */
 
 /* The single-frequency path repeated over npts (k0, eps_r, mu_r) points on

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmbem.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["host_mesh.cpp", "capi.cpp", "geom.hip", "fill.hip", "linalg.hip", "post.hip", "gemm.hip",
-           "block.hip", "adjoint.hip", "shape.hip"]
+           "block.hip", "adjoint.hip", "shape.hip", "blr.hip"]
 ARCH = os.environ.get("MBEM_OFFLOAD_ARCH", "gfx950")
 
 

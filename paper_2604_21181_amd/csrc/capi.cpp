@@ -85,6 +85,8 @@ static void op_free_device(mbem_op *op) {
     dfree(op->d_kconst);
     if (op->h_pin) (void)hipHostFree(op->h_pin);
     op->h_pin = nullptr;
+    blr_free(op->blr);
+    op->blr = nullptr;
 }
 
 // ---------------------------------------------------------------- GMRES --
@@ -406,6 +408,8 @@ int mbem_mesh_create(mbem_ctx *ctx, const double *xyz, int64_t n_nodes, const in
     m->m_col = T.m_col;
     m->tcol_off = T.tcol_off;
     m->ccol_off = T.ccol_off;
+    m->tcol_list = T.tcol_list;
+    m->spairs = T.spairs;
     const int64_t nq = m->nt * kQP;
     if ((st = upload(&m->d_xyz, m->xyz, s)) || (st = upload(&m->d_tri, m->tri, s)) ||
         (st = upload(&m->d_inc_ptr, T.inc_ptr, s)) || (st = upload(&m->d_inc, T.inc, s)) ||
@@ -468,7 +472,8 @@ static void op_set_material(mbem_op *op, const mbem_params *p) {
     op->cm = {(op->mu_i.x + 1.0) / 2.0, op->mu_i.y / 2.0};
 }
 
-static int op_create(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_op **out) {
+static int op_create(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_op **out,
+                     bool dense = true) {
     if (!mesh || !p || !out) { set_error("null argument"); return MBEM_EINVAL; }
     if (p->precision != MBEM_FP64 && p->precision != MBEM_MIXED) { set_error("bad precision"); return MBEM_EINVAL; }
     if (!(p->k0 > 0)) { set_error("k0 must be positive"); return MBEM_EINVAL; }
@@ -487,7 +492,7 @@ static int op_create(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p,
     op_set_material(op, p);
     const size_t esz = op->prec == MBEM_FP64 ? 16 : 8;
     int st = MBEM_OK;
-    for (int o = 0; o < 3 && st == MBEM_OK; ++o) {
+    for (int o = 0; o < 3 && st == MBEM_OK && dense; ++o) {
         hipError_t e = hipMalloc(&op->K[o], esz * op->n2 * op->n2);
         if (e != hipSuccess) { set_error(std::string("operator allocation: ") + hipGetErrorString(e)); st = MBEM_ENOMEM; }
     }
@@ -523,6 +528,39 @@ int mbem_fill(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_o
     MBEM_TRY(op_create(ctx, mesh, p, &op));
     const int st = op_fill(ctx, op, false, stats);
     if (st != MBEM_OK) { op_free_device(op); delete op; return st; }
+    *out = op;
+    return MBEM_OK;
+}
+
+int mbem_fill_compressed(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const mbem_blr_opts *o,
+                         mbem_op **out, mbem_stats *stats, mbem_blr_stats *bstats) {
+    if (!mesh || !p || !o || !out) { set_error("null argument"); return MBEM_EINVAL; }
+    if (p->precision != MBEM_FP64 || p->quadrature != MBEM_QUAD_DEFAULT) {
+        set_error("the block low-rank operator is built for FP64 and the default quadrature");
+        return MBEM_EINVAL;
+    }
+    if (o->cluster < 1 || o->cluster > 2048 || !(o->eta > 0) || !(o->eps > 0 && o->eps < 1) || o->rmax < 1 ||
+        o->rmax > 128) {
+        set_error("block low-rank options out of range (cluster 1..2048, eta > 0, 0 < eps < 1, rmax 1..128)");
+        return MBEM_EINVAL;
+    }
+    mbem_op *op = nullptr;
+    MBEM_TRY(op_create(ctx, mesh, p, &op, false));
+    Timer t;
+    t.start(ctx->stream);
+    mbem_blr_stats bs{};
+    int st = blr_fill_run(op, o, &bs, ctx->stream);
+    const double ms = t.stop(ctx->stream);
+    if (st == MBEM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) { set_error("fill failed"); st = MBEM_EDEVICE; }
+    if (st != MBEM_OK) { mbem_op_destroy(op); return st; }
+    bs.t_total_ms = ms;
+    if (bstats) *bstats = bs;
+    if (stats) {
+        *stats = mbem_stats{};
+        stats->t_fill_ms = ms;
+        stats->t_regular_ms = bs.t_fill_ms;
+        stats->n_regular_pairs = mesh->nt * mesh->nt - mesh->n_spairs;
+    }
     *out = op;
     return MBEM_OK;
 }
@@ -685,6 +723,7 @@ int mbem_solve(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs, con
 
 int mbem_solve_adjoint(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *g, int32_t nrhs, const mbem_solve_opts *o,
                        mbem_c128 *lambda, mbem_stats *stats) {
+    if (op && op->blr) { set_error("the transposed solve needs a dense operator"); return MBEM_EINVAL; }
     return solve_impl(ctx, op, g, nrhs, o, lambda, stats, true);
 }
 
@@ -720,6 +759,7 @@ int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh, const
                         double *out, mbem_c128 *lambda_out, double *dsig_dnode, double *dsig_dx,
                         mbem_stats *stats) {
     if (!op || !mesh || !p || !x || !khat || !pol || !o || !out) { set_error("null argument"); return MBEM_EINVAL; }
+    if (op->blr) { set_error("the gradient needs a dense operator"); return MBEM_EINVAL; }
     if (p->quadrature != MBEM_QUAD_DEFAULT || op->p.quadrature != MBEM_QUAD_DEFAULT) {
         set_error("the gradient is built for the default quadrature only");
         return MBEM_EINVAL;
@@ -785,6 +825,7 @@ int mbem_solve_block(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrh
         set_error("bad argument");
         return MBEM_EINVAL;
     }
+    if (op->blr) { set_error("the block solve needs a dense operator"); return MBEM_EINVAL; }
     MBEM_TRY(set_device(ctx));
     Timer t;
     t.start(ctx->stream);
@@ -796,6 +837,7 @@ int mbem_solve_block(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrh
 
 int mbem_gemm_autotune(mbem_ctx *ctx, mbem_op *op, int32_t nrhs, int32_t reps, float *ms, int32_t *best) {
     if (!op || nrhs < 1 || !best) { set_error("bad argument"); return MBEM_EINVAL; }
+    if (op->blr) { set_error("the block product needs a dense operator"); return MBEM_EINVAL; }
     MBEM_TRY(set_device(ctx));
     const hipStream_t s = ctx->stream;
     MBEM_TRY(ensure_c64_copy(op, s));

@@ -62,6 +62,7 @@ struct RegArgs {
                             // than near_r in FP64, the others in T
     unsigned long long *near_count;
     const KernelConst *K;   // device copy, staged in LDS by every workgroup
+    const int32_t *row_map; // null, or node -> row node of a band buffer
     TS *Z[3];
 };
 
@@ -166,7 +167,9 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     for (int i = tid; i < kChunkRec; i += blockDim.x) s_rec[i] = a.chunks[ch * kChunkRec + i];
     if (tid < 36) {
         const int g = tid / 6, i = tid % 6;
-        s_row[g][i] = 2 * (2 * (int64_t)a.tri[6 * e + i] + (g & 1)) * a.n2;
+        int64_t node = a.tri[6 * e + i];
+        if (a.row_map) node = a.row_map[node];
+        s_row[g][i] = 2 * (2 * node + (g & 1)) * a.n2;
     }
     if (tid < kChunk) {
         const int64_t f = ch * kChunk + tid;
@@ -348,6 +351,7 @@ struct SsqArgs {
     int order;
     double glx[kMaxSSQ], glw[kMaxSSQ];   // Gauss-Legendre on [0,1]
     const KernelConst *K;   // device copy
+    const int32_t *row_map; // null, or node -> row node of a band buffer
     TS *Z[3];
 };
 
@@ -442,7 +446,8 @@ __global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 
         }
         const int i = k / 6, j = k % 6;
         const int op = cc / 4, al = (cc / 2) % 2, be = cc % 2;
-        const int64_t row = 2 * (int64_t)te[i] + al, col = 2 * (int64_t)tf[j] + be;
+        const int64_t tn = a.row_map ? a.row_map[te[i]] : te[i];
+        const int64_t row = 2 * tn + al, col = 2 * (int64_t)tf[j] + be;
         TS *dst = zblock(a.Z, op) + 2 * (row * a.n2 + col);
         atomic_add(dst, re);
         atomic_add(dst + 1, im);
@@ -499,7 +504,9 @@ __global__ __launch_bounds__(256) void k_regular12(RegArgs<T, TS> a) {
     for (int i = tid; i < kChunkRec; i += blockDim.x) s_rec[i] = a.chunks[ch * kChunkRec + i];
     if (tid < 36) {
         const int g = tid / 6, i = tid % 6;
-        s_row[g][i] = 2 * (2 * (int64_t)a.tri[6 * e + i] + (g & 1)) * a.n2;
+        int64_t node = a.tri[6 * e + i];
+        if (a.row_map) node = a.row_map[node];
+        s_row[g][i] = 2 * (2 * node + (g & 1)) * a.n2;
     }
     if (tid < kChunk) {
         const int64_t f = ch * kChunk + tid;
@@ -741,7 +748,8 @@ void k_ssq_paper(SsqArgs<TS> a) {
         }
         const int i = k / 6, j = k % 6;
         const int op = cc / 4, al = (cc / 2) % 2, be = cc % 2;
-        const int64_t row = 2 * (int64_t)te[i] + al, col = 2 * (int64_t)tf[j] + be;
+        const int64_t tn = a.row_map ? a.row_map[te[i]] : te[i];
+        const int64_t row = 2 * tn + al, col = 2 * (int64_t)tf[j] + be;
         TS *dst = zblock(a.Z, op) + 2 * (row * a.n2 + col);
         atomic_add(dst, re);
         atomic_add(dst + 1, im);
@@ -856,7 +864,7 @@ static KernelConst make_rem_kconst(const mbem_op *op) {
 
 template <typename T, typename TS, bool DK = false, bool P12 = false>
 static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long *cnt,
-                          hipStream_t s) {
+                          hipStream_t s, const FillBand *band = nullptr) {
     const mbem_mesh *m = op->mesh;
     RegArgs<T, TS> a;
     a.nt = m->nt;
@@ -872,12 +880,15 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
     double dk2 = std::abs(std::complex<double>(op->ka.x, op->ka.y) * std::complex<double>(op->ka.x, op->ka.y) -
                           std::complex<double>(op->ki.x, op->ki.y) * std::complex<double>(op->ki.x, op->ki.y));
     a.near_r = op->p.near_radius > 0 ? op->p.near_radius : (dk2 > 0 ? 1.89 / std::sqrt(dk2) : 0.0);
-    for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)op->K[o];
-    const int ntc = (int)m->tcol_off.size() - 1, ncc = (int)m->ccol_off.size() - 1;
+    a.row_map = band ? band->row_map : nullptr;
+    for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)(band ? band->Z[o] : op->K[o]);
+    const std::vector<int32_t> &toff = band ? band->tcol_off : m->tcol_off;
+    const int32_t *tlist = band ? band->tcol : m->d_tcol;
+    const int ntc = (int)toff.size() - 1, ncc = (int)m->ccol_off.size() - 1;
     for (int tc = 0; tc < ntc; ++tc)
         for (int cc = 0; cc < ncc; ++cc) {
-            a.te_list = m->d_tcol + m->tcol_off[tc];
-            a.n_te = m->tcol_off[tc + 1] - m->tcol_off[tc];
+            a.te_list = tlist + toff[tc];
+            a.n_te = toff[tc + 1] - toff[tc];
             a.ch_list = m->d_ccol + m->ccol_off[cc];
             a.n_ch = m->ccol_off[cc + 1] - m->ccol_off[cc];
             a.total = a.n_te * a.n_ch;
@@ -893,12 +904,13 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
 }
 
 template <typename TS, bool DK = false, bool PAPER = false>
-static int launch_ssq(mbem_op *op, hipStream_t s) {
+static int launch_ssq(mbem_op *op, hipStream_t s, const FillBand *band = nullptr) {
     const mbem_mesh *m = op->mesh;
     SsqArgs<TS> a;
     a.n2 = op->n2;
-    a.npairs = m->n_spairs;
-    a.pairs = m->d_spairs;
+    a.npairs = band ? band->n_spairs : m->n_spairs;
+    a.pairs = band ? band->spairs : m->d_spairs;
+    a.row_map = band ? band->row_map : nullptr;
     a.tri = m->d_tri;
     a.xyz = m->d_xyz;
     a.frames = m->d_frames;
@@ -911,7 +923,7 @@ static int launch_ssq(mbem_op *op, hipStream_t s) {
         a.glw[i] = i < a.order ? 0.5 * w[a.order - 1 - i] : 0.0;
     }
     a.K = PAPER ? op->d_kconst + 1 : op->d_kconst;   // paper: the kernels, then the remainders
-    for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)op->K[o];
+    for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)(band ? band->Z[o] : op->K[o]);
     if (a.npairs == 0) return MBEM_OK;
     if constexpr (PAPER)
         hipLaunchKernelGGL((k_ssq_paper<TS>), dim3((unsigned)a.npairs), dim3(kSsqThreads), 0, s, a);
@@ -950,22 +962,36 @@ struct PhaseEvents {
     }
 };
 
+int fill_prepare(mbem_op *op, hipStream_t s, bool deriv) {
+    const bool paper = op->p.quadrature == MBEM_QUAD_PAPER;
+    // [0]: the kernels of the regular pairs, [1]: the kernels of the singular
+    // pairs, [2]: the remainders (paper's scheme)
+    if (!op->d_kconst) MBEM_HIP(hipMalloc((void **)&op->d_kconst, 3 * sizeof(KernelConst)));
+    KernelConst K[3] = {make_kconst(op, deriv), make_kconst(op, deriv), KernelConst{}};
+    if (paper) {
+        K[0].kmax = 1e300;           // regular pairs: the closed forms at every distance
+        K[2] = make_rem_kconst(op);
+    }
+    MBEM_HIP(hipMemcpyAsync(op->d_kconst, K, sizeof(K), hipMemcpyHostToDevice, s));
+    MBEM_HIP(hipStreamSynchronize(s));   // K lives on this stack frame
+    return MBEM_OK;
+}
+
+int fill_band_run(mbem_op *op, const FillBand &band, hipStream_t s) {
+    if (op->prec != MBEM_FP64 || op->p.quadrature != MBEM_QUAD_DEFAULT) {
+        set_error("band fills are built for the FP64 default scheme only");
+        return MBEM_EINVAL;
+    }
+    MBEM_TRY((launch_regular<double, double>(op, 0, op->mesh->d_qp, nullptr, s, &band)));
+    MBEM_TRY(launch_ssq<double>(op, s, &band));
+    return MBEM_OK;
+}
+
 int fill_run(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     const mbem_mesh *m = op->mesh;
     const bool paper = op->p.quadrature == MBEM_QUAD_PAPER;
     if (paper && deriv) { set_error("the eps derivative is built for the default quadrature only"); return MBEM_EINVAL; }
-    // [0]: the kernels of the regular pairs, [1]: the kernels of the singular
-    // pairs, [2]: the remainders (paper's scheme)
-    if (!op->d_kconst) MBEM_HIP(hipMalloc((void **)&op->d_kconst, 3 * sizeof(KernelConst)));
-    {
-        KernelConst K[3] = {make_kconst(op, deriv), make_kconst(op, deriv), KernelConst{}};
-        if (paper) {
-            K[0].kmax = 1e300;           // regular pairs: the closed forms at every distance
-            K[2] = make_rem_kconst(op);
-        }
-        MBEM_HIP(hipMemcpyAsync(op->d_kconst, K, sizeof(K), hipMemcpyHostToDevice, s));
-        MBEM_HIP(hipStreamSynchronize(s));   // K lives on this stack frame
-    }
+    MBEM_TRY(fill_prepare(op, s, deriv));
     PhaseEvents pe;
     const size_t esz = op->prec == MBEM_FP64 ? 16 : 8;
     for (int o = 0; o < 3; ++o)

@@ -49,7 +49,7 @@ std::vector<int64_t> stable_order(const std::vector<uint64_t> &key) {
 
 int morton_order_host(const double *xyz, int64_t nn, const int64_t *tri6,
                       int64_t nt, std::vector<int64_t> &node_order,
-                      std::vector<int64_t> &tri_order) {
+                      std::vector<int64_t> &tri_order, std::vector<uint64_t> *node_keys) {
     double lo[3], hi[3];
     for (int d = 0; d < 3; ++d) lo[d] = hi[d] = xyz[d];
     for (int64_t v = 0; v < nn; ++v)
@@ -65,6 +65,10 @@ int morton_order_host(const double *xyz, int64_t nn, const int64_t *tri6,
     std::vector<uint64_t> key(nn);
     for (int64_t v = 0; v < nn; ++v) key[v] = zorder(xyz + 3 * v, lo, ext);
     node_order = stable_order(key);
+    if (node_keys) {
+        node_keys->resize(nn);
+        for (int64_t k = 0; k < nn; ++k) (*node_keys)[k] = key[node_order[k]];
+    }
     key.assign(nt, 0);
     for (int64_t t = 0; t < nt; ++t) {
         double c[3];
@@ -166,7 +170,7 @@ int build_mesh_host(const double *xyz_in, int64_t nn, const int64_t *tri_in,
     }
     // ---- Morton permutation and renumbering
     std::vector<int64_t> no, to;
-    MBEM_TRY(morton_order_host(xyz_in, nn, tri_in, nt, no, to));
+    MBEM_TRY(morton_order_host(xyz_in, nn, tri_in, nt, no, to, &m->node_key));
     std::vector<int64_t> rank(nn);
     for (int64_t k = 0; k < nn; ++k) rank[no[k]] = k;
     m->nn = nn;

@@ -175,7 +175,9 @@ int matvec_run(const mbem_op *op, const double2 *x, double2 *y, double2 *tmp, hi
                hipEvent_t after_gemv) {
     const int64_t n2 = op->n2;
     auto blocks = [n2](int R) { return (unsigned)((3 * ((n2 + R - 1) / R) * kW + 255) / 256); };
-    if (op->prec == MBEM_FP64)
+    if (op->blr)
+        MBEM_TRY(blr_gemv_run(op, x, x + n2, tmp, s));
+    else if (op->prec == MBEM_FP64)
         hipLaunchKernelGGL((k_gemv3<double2>), dim3(blocks(gemv_rows_per_wave<double2>())), dim3(256), 0, s,
                            n2, (const double2 *)op->K[0], (const double2 *)op->K[1],
                            (const double2 *)op->K[2], x, x + n2, tmp);
@@ -239,6 +241,7 @@ __global__ void k_export_dense(int64_t n2, const void *K0, const void *K1, const
 }
 
 int export_dense_run(const mbem_op *op, double2 *Z, hipStream_t s) {
+    if (op->blr) { set_error("a block low-rank operator exports its blocks only"); return MBEM_EINVAL; }
     const int64_t N = 2 * op->n2;
     const mbem_mesh *m = op->mesh;
     const unsigned blocks = (unsigned)((N * N + 255) / 256);
@@ -258,6 +261,7 @@ __global__ void k_c64_to_c128(int64_t n, const float2 *a, double2 *b) {
 }
 
 int export_blocks_run(const mbem_op *op, double2 *K1, double2 *K2e, double2 *K2m, hipStream_t s) {
+    if (op->blr) return blr_expand_run(op, K1, K2e, K2m, s);
     double2 *dst[3] = {K1, K2e, K2m};
     const int64_t n = op->n2 * op->n2;
     for (int o = 0; o < 3; ++o) {
@@ -291,6 +295,34 @@ __global__ void k_mbj_gather(int64_t n2, int B, const void *K0, const void *K1, 
         const int ci = r < b ? 0 : 1, cc = q < b ? 0 : 1;
         const int64_t gr = (int64_t)m * B + (r % b), gq = (int64_t)m * B + (q % b);
         A[(int64_t)m * ld * ld + r * ld + q] = z_entry<TS>(K, mptr, mcol, mval, c, n2, ci, gr, cc, gq);
+    }
+}
+
+// The same restrictions read from a block low-rank operator.
+__global__ void k_mbj_gather_blr(int64_t n2, int B, BlrView v, const int32_t *mptr, const int32_t *mcol,
+                                 const double *mval, Coef c, double2 *A) {
+    const int m = blockIdx.y;
+    const int64_t b = min((int64_t)B, n2 - (int64_t)m * B);
+    const int64_t ld = 2 * B, n = 2 * b;
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < n * n;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = id / n, q = id % n;
+        const int ci = r < b ? 0 : 1, cc = q < b ? 0 : 1;
+        const int64_t gr = (int64_t)m * B + (r % b), gq = (int64_t)m * B + (q % b);
+        double2 z;
+        if (ci == cc) {
+            const double2 k = cmul(c.iw, blr_entry(v, 0, gr, gq));
+            z = ci == 0 ? k : double2{-k.x, -k.y};
+        } else {
+            z = blr_entry(v, ci == 0 ? 1 : 2, gr, gq);
+            if ((gr % 2) == (gq % 2)) {
+                const double mv = mass_entry(mptr, mcol, mval, gr / 2, gq / 2);
+                const double2 cf = ci == 0 ? c.ce : c.cm;
+                z.x += cf.x * mv;
+                z.y += cf.y * mv;
+            }
+        }
+        A[(int64_t)m * ld * ld + r * ld + q] = z;
     }
 }
 
@@ -540,7 +572,10 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s, bool keep) {
     MBEM_HIP(hipMemsetAsync(info, 0, sizeof(int32_t), s));
     const mbem_mesh *m = op->mesh;
     dim3 g(64, nb);
-    if (op->prec == MBEM_FP64)
+    if (op->blr)
+        hipLaunchKernelGGL(k_mbj_gather_blr, g, dim3(256), 0, s, n2, B, blr_view(op), m->d_mptr, m->d_mcol,
+                           op->d_mval, coef_of(op), op->d_lu);
+    else if (op->prec == MBEM_FP64)
         hipLaunchKernelGGL((k_mbj_gather<double2>), g, dim3(256), 0, s, n2, B, op->K[0], op->K[1],
                            op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), op->d_lu);
     else

@@ -11,6 +11,7 @@
 
 namespace mbem {
 struct KernelConst;
+struct BlrOp;
 
 // ---------------------------------------------------------------- errors --
 void set_error(const std::string &msg);
@@ -67,6 +68,7 @@ struct mbem_mesh {
     int64_t nn = 0, nt = 0;
     std::vector<int64_t> node_order, tri_order;  // Morton position -> caller
     std::vector<double> xyz;                     // Morton order [nn*3]
+    std::vector<uint64_t> node_key;              // Morton keys, Morton order
     std::vector<int32_t> tri;                    // Morton numbering [nt*6]
     double amax = 0.0;                           // max |x| over nodes
     int64_t n_single[4] = {0, 0, 0, 0};          // ordered pairs per class
@@ -91,6 +93,8 @@ struct mbem_mesh {
     // colour classes of the race-free regular-pair fill
     std::vector<int32_t> tcol_off, ccol_off;
     int32_t *d_tcol = nullptr, *d_ccol = nullptr;
+    // host copies for band fills: the test colour lists and singular pairs
+    std::vector<int32_t> tcol_list, spairs;
 };
 
 struct mbem_op {
@@ -120,6 +124,8 @@ struct mbem_op {
     // multi-right-hand-side solve: complex64 copy of an FP64 operator's
     // blocks for the FP32 GEMM
     void *K32[3] = {nullptr, nullptr, nullptr};
+    // block low-rank operator: set instead of K
+    mbem::BlrOp *blr = nullptr;
 };
 
 namespace mbem {
@@ -138,9 +144,10 @@ struct MeshTables {
 int build_tables(const mbem_mesh *m, MeshTables &T);
 int build_mesh_host(const double *xyz, int64_t nn, const int64_t *tri6,
                     int64_t nt, mbem_mesh *m);
+// node_keys (optional): the nodes' Morton keys in Morton order
 int morton_order_host(const double *xyz, int64_t nn, const int64_t *tri6,
                       int64_t nt, std::vector<int64_t> &node_order,
-                      std::vector<int64_t> &tri_order);
+                      std::vector<int64_t> &tri_order, std::vector<uint64_t> *node_keys = nullptr);
 void gauss_legendre(int n, double *x, double *w);   // on [-1, 1]
 
 // geometry (geom.hip)
@@ -152,6 +159,58 @@ int geom_build(const mbem_mesh *m, hipStream_t s, bool with12 = false);
 // geom = false: the mesh's geometry tables are already built (a sweep that
 // refills the same mesh)
 int fill_run(mbem_op *op, hipStream_t s, bool deriv = false, bool geom = true);
+// The kernel constants of the op's wavenumbers on the device (first step of
+// every fill).
+int fill_prepare(mbem_op *op, hipStream_t s, bool deriv);
+// A band of test rows (compressed fill): every regular and singular pair
+// whose test triangle is listed, added into band buffers whose rows are
+// numbered by row_map.
+struct FillBand {
+    const int32_t *tcol = nullptr;        // device: the band's test triangles by colour class
+    std::vector<int32_t> tcol_off;        // host offsets, one more than the classes
+    const int32_t *spairs = nullptr;      // device: the band's singular pairs (4 ints each)
+    int64_t n_spairs = 0;
+    const int32_t *row_map = nullptr;     // device [nn]: node -> band row node
+    void *Z[3] = {nullptr, nullptr, nullptr};   // band buffers, leading dimension 2 nn
+};
+// FP64, default scheme; the geometry tables and kernel constants are current.
+int fill_band_run(mbem_op *op, const FillBand &band, hipStream_t s);
+
+// block low-rank operator (blr.hip)
+struct BlrTile {
+    int32_t op, t, s, rank;   // block, row / column cluster; rank < 0: dense
+    int32_t m, n;             // rows, columns (twice the cluster sizes)
+    int64_t r0, c0;           // first row / column in the block
+    double2 *a;               // dense m x n, or U (m x rank), row-major
+    double2 *vt;              // V^T (rank x n, row-major); null when dense
+    int64_t w;                // offset of this tile's V^T x in the product workspace
+};
+struct BlrView {              // what device code needs to read entries
+    int32_t nc;
+    const int32_t *cl_of;     // node -> cluster
+    const BlrTile *tiles;     // tile (op, t, s) at (op nc + t) nc + s
+};
+// One entry of block op, row r, column q.
+__device__ inline double2 blr_entry(const BlrView &v, int op, int64_t r, int64_t q) {
+    const int64_t t = v.cl_of[r >> 1], sc = v.cl_of[q >> 1];
+    const BlrTile &T = v.tiles[((int64_t)op * v.nc + t) * v.nc + sc];
+    const int64_t lr = r - T.r0, lc = q - T.c0;
+    if (T.rank < 0) return T.a[lr * T.n + lc];
+    double2 z = {0.0, 0.0};
+    for (int k = 0; k < T.rank; ++k) {
+        const double2 u = T.a[lr * T.rank + k], w = T.vt[(int64_t)k * T.n + lc];
+        z.x += u.x * w.x - u.y * w.y;
+        z.y += u.x * w.y + u.y * w.x;
+    }
+    return z;
+}
+int blr_fill_run(mbem_op *op, const mbem_blr_opts *o, mbem_blr_stats *bs, hipStream_t s);
+// t = [K1 xj, K1 xm, K2e xm, K2m xj] (4 n2), as the dense product
+int blr_gemv_run(const mbem_op *op, const double2 *xj, const double2 *xm, double2 *t, hipStream_t s);
+// the three blocks expanded into dense n2 x n2 buffers (any may be null)
+int blr_expand_run(const mbem_op *op, double2 *K0, double2 *K1, double2 *K2, hipStream_t s);
+BlrView blr_view(const mbem_op *op);
+void blr_free(BlrOp *b);
 int mass_run(mbem_op *op, hipStream_t s);
 
 // linear algebra (linalg.hip)

@@ -29,6 +29,7 @@ EXPORTED = [
     "mbem_farfield", "mbem_cross_sections", "mbem_last_error", "mbem_solve_block",
     "mbem_gemm_autotune", "mbem_cgemm", "mbem_solve_adjoint", "mbem_fill_deps",
     "mbem_farfield_functional", "mbem_grad_sigma_ext", "mbem_mesh_frames", "mbem_spectrum",
+    "mbem_fill_compressed",
 ]
 GEMM_CONFIGS = 6   # FP32 GEMM tile shapes known to the autotuner
 
@@ -58,6 +59,21 @@ class Stats(C.Structure):
                 ("t_mass_ms", C.c_double), ("t_matvec_ms", C.c_double), ("n_matvec", C.c_int32),
                 ("n_regular_pairs", C.c_int64), ("t_adjoint_ms", C.c_double),
                 ("t_deps_ms", C.c_double), ("t_shape_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BlrOpts(C.Structure):
+    _fields_ = [("cluster", C.c_int32), ("eta", C.c_double), ("eps", C.c_double), ("rmax", C.c_int32),
+                ("keep_lowrank", C.c_int32)]
+
+
+class BlrStats(C.Structure):
+    _fields_ = [("stored_bytes", C.c_int64), ("dense_bytes", C.c_int64), ("n_clusters", C.c_int32),
+                ("n_tiles", C.c_int32), ("n_admissible", C.c_int32), ("n_lowrank", C.c_int32),
+                ("max_rank", C.c_int32), ("mean_rank", C.c_double), ("t_fill_ms", C.c_double),
+                ("t_aca_ms", C.c_double), ("t_total_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -121,6 +137,8 @@ def lib():
                                      P, P, C.POINTER(Stats)], C.c_int),
             "mbem_spectrum": ([P, P, C.POINTER(Params), i32, P, P, P, P, P, i32,
                                C.POINTER(SolveOpts), i32, P, P, C.POINTER(Stats)], C.c_int),
+            "mbem_fill_compressed": ([P, P, C.POINTER(Params), C.POINTER(BlrOpts), PP, C.POINTER(Stats),
+                                      C.POINTER(BlrStats)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -206,6 +224,16 @@ def mbem_fill(ctx, mesh, params):
     st = Stats()
     _check(lib().mbem_fill(ctx, mesh, C.byref(params), C.byref(h), C.byref(st)))
     return h, st
+
+
+def mbem_fill_compressed(ctx, mesh, params, cluster=256, eta=2.0, eps=1e-6, rmax=128, keep_lowrank=False):
+    """Block low-rank operator; returns (op, Stats, BlrStats)."""
+    op = C.c_void_p()
+    st, bs = Stats(), BlrStats()
+    o = BlrOpts(cluster, eta, eps, rmax, 1 if keep_lowrank else 0)
+    _check(lib().mbem_fill_compressed(ctx, mesh, C.byref(params), C.byref(o), C.byref(op), C.byref(st),
+                                      C.byref(bs)))
+    return op, st, bs
 
 
 def mbem_op_destroy(op):
@@ -382,6 +410,15 @@ class Solver:
             mbem_op_destroy(self.op)
         self.op, self.fill_stats = mbem_fill(self.ctx, self.mesh, self.params)
         return self.fill_stats
+
+    def fill_compressed(self, **kw):
+        """Replace the operator by a block low-rank one (see
+        mbem_fill_compressed); returns its BlrStats."""
+        if self.op is not None:
+            mbem_op_destroy(self.op)
+            self.op = None
+        self.op, self.fill_stats, bs = mbem_fill_compressed(self.ctx, self.mesh, self.params, **kw)
+        return bs
 
     def export_blocks(self):
         t = self.torch
