@@ -79,8 +79,8 @@ PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix cores
 # scaled by a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  A
 # kernel changed after its counters were taken gets None here.
 MEASURED_TRAFFIC = {
-    ("k_regular", "fp64"): 23.33e9,     # 15.39 GB read + 7.94 GB written per fill
-    ("k_regular", "mixed"): 15.43e9,    # 9.78 GB read + 5.65 GB written per fill
+    ("k_regular", "fp64"): 23.31e9,     # 15.37 GB read + 7.94 GB written per fill
+    ("k_regular", "mixed"): 15.40e9,    # 9.76 GB read + 5.64 GB written per fill
     ("k_gemv3", "fp64"): 1.291e9,
     ("k_gemv3", "mixed"): 0.683e9,
 }
@@ -248,14 +248,14 @@ def spectrum_study(mbem, log):
         gemv_bytes = 3 * n2 * n2 * (16 if name == "fp64" else 8) + 4 * n2 * 16
         peak = PEAK_FP64_VALU
         out[name] = {"wall_s": wall, "points_per_s": npts / wall,
-                     # FP64: every regular pair in one kernel; mixed: the FP32 far-pair
-                     # launch only (its near pairs run in FP64 beside it)
+                     # FP64: every regular pair in FP64; mixed: the FP32 kernel, which
+                     # evaluates its near pairs in FP64 (on this electrically small,
+                     # high-contrast body most pairs are near)
                      "k_regular": ({"ms_per_point": t_reg, "tflops": flops / (t_reg * 1e-3) / 1e12,
                                     "peak": peak, "frac": flops / (t_reg * 1e-3) / 1e12 / peak}
                                    if name == "fp64" else
-                                   {"far_ms_per_point": t_reg, "near_ms_per_point": st.t_near_ms / npts,
-                                    "near_pairs_per_point": st.n_near_pairs / npts,
-                                    "regular_pairs": int(st.n_regular_pairs)}),
+                                   {"ms_per_point": t_reg,
+                                    "near_pair_fraction": st.n_near_pairs / npts / max(1, st.n_regular_pairs)}),
                      "k_gemv3": {"ms_per_launch": gemv_ms,
                                  "gbps": gemv_bytes / (gemv_ms * 1e-3) / 1e9,
                                  "frac": gemv_bytes / (gemv_ms * 1e-3) / 1e9 / PEAK_HBM},

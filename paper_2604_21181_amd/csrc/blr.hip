@@ -33,6 +33,9 @@ struct BlrOp {
     int32_t *d_lr = nullptr;                   // tiles with rank > 0
     int32_t n_lr = 0;
     double2 *d_w = nullptr;                    // V^T x of every low-rank tile
+    double2 *d_z = nullptr;                    // row products of every tile
+    int32_t *d_dense = nullptr;                // dense tiles
+    int32_t n_dense = 0;
     std::vector<void *> store;                 // tile storage, one allocation per band
 };
 
@@ -40,7 +43,7 @@ void blr_free(BlrOp *b) {
     if (!b) return;
     for (void *p : b->store)
         if (p) (void)hipFree(p);
-    void *ps[] = {b->d_tiles, b->d_lr, b->d_w, b->d_cl_of};
+    void *ps[] = {b->d_tiles, b->d_lr, b->d_w, b->d_cl_of, b->d_z, b->d_dense};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete b;
@@ -271,10 +274,7 @@ __global__ __launch_bounds__(256) void k_blr_pack(const PackTask *tasks, const d
         return;
     }
     const int64_t cu = (int64_t)T.m * T.rank, cv = (int64_t)T.rank * T.n;
-    for (int64_t e = first; e < cu; e += step) {   // U: scratch [k][m] -> [m][rank]
-        const int64_t i = e / T.rank, kk = e % T.rank;
-        T.a[e] = scr[T.u + kk * T.m + i];
-    }
+    for (int64_t e = first; e < cu; e += step) T.a[e] = scr[T.u + e];    // U^T = scratch [k][m]
     for (int64_t e = first; e < cv; e += step) T.vt[e] = scr[T.v + e];   // V^T = scratch [k][n]
 }
 
@@ -311,60 +311,91 @@ __global__ __launch_bounds__(256) void k_blr_vt(const BlrTile *tiles, const int3
     }
 }
 
-// One wavefront per (block, row): the row of every tile of its band, dense
-// rows against x, low-rank rows of U against the tile's V^T x.
-__global__ __launch_bounds__(256) void k_blr_rows(int64_t n2, const int32_t *cl_of, int32_t nc,
-                                                  const BlrTile *tiles, const double2 *xj, const double2 *xm,
-                                                  const double2 *w, double2 *t) {
-    const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 64;
-    const int lane = threadIdx.x & 63;
-    if (wid >= 3 * n2) return;
-    const int op = (int)(wid / n2);
-    const int64_t r = wid % n2;
-    const int64_t tc = cl_of[r >> 1];
-    const bool two = op == 0;
-    const double2 *x0 = op == 1 ? xm : xj;
-    double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
-    const BlrTile *row = tiles + ((int64_t)op * nc + tc) * nc;
-    for (int sc = 0; sc < nc; ++sc) {
-        const BlrTile &T = row[sc];
-        const int64_t lr = r - T.r0;
-        if (T.rank < 0) {
-            const double2 *a = T.a + lr * T.n, *y0 = x0 + T.c0, *y1 = xm + T.c0;
-            for (int j = lane; j < T.n; j += 64) {
-                const double2 v = a[j];
-                const double2 p = cmul2(v, y0[j]);
-                a0r += p.x;
-                a0i += p.y;
-                if (two) {
-                    const double2 q = cmul2(v, y1[j]);
-                    a1r += q.x;
-                    a1i += q.y;
-                }
-            }
-        } else if (T.rank > 0) {
-            const double2 *u = T.a + lr * T.rank;
-            for (int kk = lane; kk < T.rank; kk += 64) {
-                const double2 v = u[kk];
-                const double2 p = cmul2(v, w[T.w + kk]);
-                a0r += p.x;
-                a0i += p.y;
-                if (two) {
-                    const double2 q = cmul2(v, w[T.w + T.rank + kk]);
-                    a1r += q.x;
-                    a1i += q.y;
-                }
+// Row products of every tile into its own slice of z (K1: x_j then x_m):
+//   dense tiles: one wavefront per row, lanes along the columns;
+//   low-rank tiles: U (m x rank) against the tile's V^T x, one lane per row;
+// then one lane per (block, row) sums the slices of its band in column order
+// (a fixed order: the product is reproducible).
+__global__ __launch_bounds__(256) void k_blr_dense(const BlrTile *tiles, const int32_t *dense,
+                                                   const double2 *xj, const double2 *xm, double2 *z) {
+    const BlrTile T = tiles[dense[blockIdx.x]];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool two = T.op == 0;
+    const double2 *y0 = (T.op == 1 ? xm : xj) + T.c0, *y1 = xm + T.c0;
+    for (int i = wv; i < T.m; i += 4) {
+        const double2 *a = T.a + (int64_t)i * T.n;
+        double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
+        for (int j = lane; j < T.n; j += 64) {
+            const double2 v = a[j];
+            const double2 p = cmul2(v, y0[j]);
+            a0r += p.x;
+            a0i += p.y;
+            if (two) {
+                const double2 q = cmul2(v, y1[j]);
+                a1r += q.x;
+                a1i += q.y;
             }
         }
+        a0r = wave_sum(a0r);
+        a0i = wave_sum(a0i);
+        if (two) { a1r = wave_sum(a1r); a1i = wave_sum(a1i); }
+        if (lane == 0) {
+            z[T.z + i] = {a0r, a0i};
+            if (two) z[T.z + T.m + i] = {a1r, a1i};
+        }
     }
-    a0r = wave_sum(a0r);
-    a0i = wave_sum(a0i);
-    if (two) { a1r = wave_sum(a1r); a1i = wave_sum(a1i); }
-    if (lane == 0) {
-        if (op == 0) { t[r] = {a0r, a0i}; t[n2 + r] = {a1r, a1i}; }
-        else if (op == 1) t[2 * n2 + r] = {a0r, a0i};
-        else t[3 * n2 + r] = {a0r, a0i};
+}
+
+__global__ __launch_bounds__(256) void k_blr_u(const BlrTile *tiles, const int32_t *lr, const double2 *w,
+                                               double2 *z) {
+    __shared__ double2 s_w[2 * kMaxRank];
+    const BlrTile T = tiles[lr[blockIdx.x]];
+    const bool two = T.op == 0;
+    const int nw = (two ? 2 : 1) * T.rank;
+    for (int q = threadIdx.x; q < nw; q += blockDim.x) s_w[q] = w[T.w + q];
+    __syncthreads();
+    for (int i = threadIdx.x; i < T.m; i += blockDim.x) {
+        double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
+        for (int k = 0; k < T.rank; ++k) {
+            const double2 v = T.a[(int64_t)k * T.m + i];
+            const double2 p = cmul2(v, s_w[k]);
+            a0r += p.x;
+            a0i += p.y;
+            if (two) {
+                const double2 q = cmul2(v, s_w[T.rank + k]);
+                a1r += q.x;
+                a1i += q.y;
+            }
+        }
+        z[T.z + i] = {a0r, a0i};
+        if (two) z[T.z + T.m + i] = {a1r, a1i};
     }
+}
+
+__global__ __launch_bounds__(256) void k_blr_sum(int64_t n2, const int32_t *cl_of, int32_t nc,
+                                                 const BlrTile *tiles, const double2 *z, double2 *t) {
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= 3 * n2) return;
+    const int op = (int)(id / n2);
+    const int64_t r = id % n2;
+    const BlrTile *row = tiles + ((int64_t)op * nc + cl_of[r >> 1]) * nc;
+    const int64_t lr = r - row[0].r0;
+    double2 a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+    for (int sc = 0; sc < nc; ++sc) {
+        const BlrTile &T = row[sc];
+        if (T.rank == 0) continue;
+        const double2 v = z[T.z + lr];
+        a0.x += v.x;
+        a0.y += v.y;
+        if (op == 0) {
+            const double2 u = z[T.z + T.m + lr];
+            a1.x += u.x;
+            a1.y += u.y;
+        }
+    }
+    if (op == 0) { t[r] = a0; t[n2 + r] = a1; }
+    else if (op == 1) t[2 * n2 + r] = a0;
+    else t[3 * n2 + r] = a0;
 }
 
 // one workgroup per tile
@@ -381,7 +412,7 @@ __global__ __launch_bounds__(256) void k_blr_expand(const BlrTile *tiles, int64_
         else {
             z = {0.0, 0.0};
             for (int kk = 0; kk < T.rank; ++kk) {
-                const double2 p = cmul2(T.a[i * T.rank + kk], T.vt[(int64_t)kk * T.n + j]);
+                const double2 p = cmul2(T.a[(int64_t)kk * T.m + i], T.vt[(int64_t)kk * T.n + j]);
                 z.x += p.x;
                 z.y += p.y;
             }
@@ -396,9 +427,18 @@ int blr_gemv_run(const mbem_op *op, const double2 *xj, const double2 *xm, double
         hipLaunchKernelGGL(k_blr_vt, dim3((unsigned)b->n_lr), dim3(256), 0, s, b->d_tiles, b->d_lr, xj, xm, b->d_w);
         MBEM_HIP(hipGetLastError());
     }
-    const int64_t waves = 3 * op->n2;
-    hipLaunchKernelGGL(k_blr_rows, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, s, op->n2,
-                       b->d_cl_of, b->nc, b->d_tiles, xj, xm, b->d_w, t);
+    if (b->n_lr > 0) {
+        hipLaunchKernelGGL(k_blr_u, dim3((unsigned)b->n_lr), dim3(256), 0, s, b->d_tiles, b->d_lr, b->d_w, b->d_z);
+        MBEM_HIP(hipGetLastError());
+    }
+    if (b->n_dense > 0) {
+        hipLaunchKernelGGL(k_blr_dense, dim3((unsigned)b->n_dense), dim3(256), 0, s, b->d_tiles, b->d_dense, xj, xm,
+                           b->d_z);
+        MBEM_HIP(hipGetLastError());
+    }
+    const int64_t rows = 3 * op->n2;
+    hipLaunchKernelGGL(k_blr_sum, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, op->n2, b->d_cl_of, b->nc,
+                       b->d_tiles, b->d_z, t);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
@@ -658,7 +698,7 @@ int blr_fill_run(mbem_op *op, const mbem_blr_opts *o, mbem_blr_stats *bs, hipStr
             for (int q = 0; q < 3; ++q) {
                 const int32_t r = keep_rank[(size_t)q * nc + sc];
                 BlrTile &T = b->tiles[((size_t)q * nc + c) * nc + sc];
-                T = BlrTile{q, c, sc, r, mt, ns, 2 * n0, 2 * (int64_t)start[sc], store + pos, nullptr, 0};
+                T = BlrTile{q, c, sc, r, mt, ns, 2 * n0, 2 * (int64_t)start[sc], store + pos, nullptr, 0, 0};
                 PackTask P{q, r, mt, ns, 2 * (int64_t)start[sc], 0, 0, store + pos, nullptr};
                 if (a) {
                     P.u = tasks[ti].u;
@@ -689,26 +729,35 @@ int blr_fill_run(mbem_op *op, const mbem_blr_opts *o, mbem_blr_stats *bs, hipStr
         for (int32_t v : halo[c]) rmap[v] = 0;
     }
     // product workspace and device tables
-    std::vector<int32_t> lr;
-    int64_t w = 0;
+    std::vector<int32_t> lr, dn;
+    int64_t w = 0, zz = 0;
     for (size_t q = 0; q < b->tiles.size(); ++q) {
         BlrTile &T = b->tiles[q];
+        const int nv = T.op == 0 ? 2 : 1;
+        T.z = zz;
+        if (T.rank != 0) zz += nv * (int64_t)T.m;
         if (T.rank > 0) {
             T.w = w;
-            w += (T.op == 0 ? 2 : 1) * (int64_t)T.rank;
+            w += nv * (int64_t)T.rank;
             lr.push_back((int32_t)q);
+        } else if (T.rank < 0) {
+            dn.push_back((int32_t)q);
         }
     }
     b->n_lr = (int32_t)lr.size();
+    b->n_dense = (int32_t)dn.size();
     hipError_t e1 = hipMalloc((void **)&b->d_tiles, sizeof(BlrTile) * b->tiles.size());
     hipError_t e2 = hipMalloc((void **)&b->d_lr, sizeof(int32_t) * std::max<size_t>(1, lr.size()));
     hipError_t e3 = hipMalloc((void **)&b->d_w, sizeof(double2) * std::max<int64_t>(1, w));
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    hipError_t e4 = hipMalloc((void **)&b->d_z, sizeof(double2) * std::max<int64_t>(1, zz));
+    hipError_t e5 = hipMalloc((void **)&b->d_dense, sizeof(int32_t) * std::max<size_t>(1, dn.size()));
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess) {
         set_error("block low-rank tables: device allocation");
         return MBEM_ENOMEM;
     }
     MBEM_HIP(hipMemcpyAsync(b->d_tiles, b->tiles.data(), sizeof(BlrTile) * b->tiles.size(), hipMemcpyHostToDevice, s));
     if (!lr.empty()) MBEM_HIP(hipMemcpyAsync(b->d_lr, lr.data(), sizeof(int32_t) * lr.size(), hipMemcpyHostToDevice, s));
+    if (!dn.empty()) MBEM_HIP(hipMemcpyAsync(b->d_dense, dn.data(), sizeof(int32_t) * dn.size(), hipMemcpyHostToDevice, s));
     MBEM_HIP(hipStreamSynchronize(s));
     if (bs) {
         bs->stored_bytes = stored;

@@ -181,9 +181,10 @@ struct BlrTile {
     int32_t op, t, s, rank;   // block, row / column cluster; rank < 0: dense
     int32_t m, n;             // rows, columns (twice the cluster sizes)
     int64_t r0, c0;           // first row / column in the block
-    double2 *a;               // dense m x n, or U (m x rank), row-major
+    double2 *a;               // dense m x n row-major, or U^T (rank x m, row-major)
     double2 *vt;              // V^T (rank x n, row-major); null when dense
     int64_t w;                // offset of this tile's V^T x in the product workspace
+    int64_t z;                // offset of this tile's row products (m per vector)
 };
 struct BlrView {              // what device code needs to read entries
     int32_t nc;
@@ -198,7 +199,7 @@ __device__ inline double2 blr_entry(const BlrView &v, int op, int64_t r, int64_t
     if (T.rank < 0) return T.a[lr * T.n + lc];
     double2 z = {0.0, 0.0};
     for (int k = 0; k < T.rank; ++k) {
-        const double2 u = T.a[lr * T.rank + k], w = T.vt[(int64_t)k * T.n + lc];
+        const double2 u = T.a[(int64_t)k * T.m + lr], w = T.vt[(int64_t)k * T.n + lc];
         z.x += u.x * w.x - u.y * w.y;
         z.y += u.x * w.y + u.y * w.x;
     }
