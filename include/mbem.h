@@ -427,7 +427,8 @@ int mbem_fill_compressed(mbem_ctx *ctx, const mbem_mesh *mesh,
  *   sigma   host [npts*3]: C_ext, C_sca, C_abs of point i at 3i..3i+2
  *   iters   host [npts] GMRES iterations per point, or NULL
  *   stats   NULL, or times and iteration counts summed over the points
- *           (t_geom_ms: the one geometry build; rel_resid: the worst)
+ *           (t_geom_ms: the one geometry build; t_fill_ms: device time of
+ *           the fills; rel_resid: the worst)
  * MBEM_EINVAL for a bad argument (nothing is run), MBEM_ENOCONV when some
  * point missed the tolerance (every point is still solved and written),
  * MBEM_ESINGULAR on a singular preconditioner block (sigma holds the points

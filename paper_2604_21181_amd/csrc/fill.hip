@@ -13,6 +13,8 @@
 #include <complex>
 #include <type_traits>
 
+#include <new>
+
 #include "mbem_internal.h"
 #include "kappa.h"
 #include "p2_device.h"
@@ -943,37 +945,58 @@ int mass_run(mbem_op *op, hipStream_t s) {
     return MBEM_OK;
 }
 
-// Events bracketing every launch of the fill; elapsed times are read after
-// the caller's synchronisation.
-struct PhaseEvents {
-    hipEvent_t ev[6] = {};
-    bool ok = true;
-    PhaseEvents() {
-        for (auto &e : ev) ok = ok && hipEventCreate(&e) == hipSuccess;
-    }
-    ~PhaseEvents() {
-        for (auto &e : ev) if (e) (void)hipEventDestroy(e);
-    }
-    void mark(int i, hipStream_t s) { if (ok) (void)hipEventRecord(ev[i], s); }
-    double ms(int a, int b) {
-        float t = 0.f;
-        if (!ok || hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) return 0.0;
-        return t;
-    }
+// What a fill leaves on the op between its enqueueing and its collection:
+// events at its phase boundaries, the pinned staging of the kernel constants
+// and of the near-pair count, and the device counter.
+struct FillState {
+    hipEvent_t ev[7] = {};               // 0..5 phase marks, 6 start
+    KernelConst *h_k = nullptr;          // pinned, three
+    unsigned long long *h_cnt = nullptr; // pinned
+    unsigned long long *d_cnt = nullptr;
+    bool pending = false, counted = false;
 };
+
+void fill_state_free(FillState *f) {
+    if (!f) return;
+    for (auto &e : f->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (f->h_k) (void)hipHostFree(f->h_k);
+    if (f->h_cnt) (void)hipHostFree(f->h_cnt);
+    if (f->d_cnt) (void)hipFree(f->d_cnt);
+    delete f;
+}
+
+static int fill_state(mbem_op *op, FillState **out) {
+    if (!op->fs) {
+        FillState *f = new (std::nothrow) FillState;
+        if (!f) { set_error("host allocation"); return MBEM_ENOMEM; }
+        op->fs = f;
+        for (auto &e : f->ev) MBEM_HIP(hipEventCreate(&e));
+        MBEM_HIP(hipHostMalloc((void **)&f->h_k, 3 * sizeof(KernelConst), hipHostMallocDefault));
+        MBEM_HIP(hipHostMalloc((void **)&f->h_cnt, sizeof(unsigned long long), hipHostMallocDefault));
+        MBEM_HIP(hipMalloc((void **)&f->d_cnt, sizeof(unsigned long long)));
+    }
+    *out = op->fs;
+    return MBEM_OK;
+}
 
 int fill_prepare(mbem_op *op, hipStream_t s, bool deriv) {
     const bool paper = op->p.quadrature == MBEM_QUAD_PAPER;
+    FillState *f = nullptr;
+    MBEM_TRY(fill_state(op, &f));
+    // the staging buffer may still feed the previous fill's copy
+    if (f->pending) MBEM_HIP(hipEventSynchronize(f->ev[5]));
     // [0]: the kernels of the regular pairs, [1]: the kernels of the singular
     // pairs, [2]: the remainders (paper's scheme)
     if (!op->d_kconst) MBEM_HIP(hipMalloc((void **)&op->d_kconst, 3 * sizeof(KernelConst)));
-    KernelConst K[3] = {make_kconst(op, deriv), make_kconst(op, deriv), KernelConst{}};
+    f->h_k[0] = make_kconst(op, deriv);
+    f->h_k[1] = f->h_k[0];
+    f->h_k[2] = KernelConst{};
     if (paper) {
-        K[0].kmax = 1e300;           // regular pairs: the closed forms at every distance
-        K[2] = make_rem_kconst(op);
+        f->h_k[0].kmax = 1e300;           // regular pairs: the closed forms at every distance
+        f->h_k[2] = make_rem_kconst(op);
     }
-    MBEM_HIP(hipMemcpyAsync(op->d_kconst, K, sizeof(K), hipMemcpyHostToDevice, s));
-    MBEM_HIP(hipStreamSynchronize(s));   // K lives on this stack frame
+    MBEM_HIP(hipMemcpyAsync(op->d_kconst, f->h_k, 3 * sizeof(KernelConst), hipMemcpyHostToDevice, s));
     return MBEM_OK;
 }
 
@@ -987,68 +1010,73 @@ int fill_band_run(mbem_op *op, const FillBand &band, hipStream_t s) {
     return MBEM_OK;
 }
 
-int fill_run(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
+int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     const mbem_mesh *m = op->mesh;
     const bool paper = op->p.quadrature == MBEM_QUAD_PAPER;
     if (paper && deriv) { set_error("the eps derivative is built for the default quadrature only"); return MBEM_EINVAL; }
+    if (deriv && op->prec != MBEM_FP64) { set_error("derivative operators are filled in FP64"); return MBEM_EINVAL; }
     MBEM_TRY(fill_prepare(op, s, deriv));
-    PhaseEvents pe;
+    FillState *f = op->fs;
+    hipEvent_t *ev = f->ev;
+    MBEM_HIP(hipEventRecord(ev[6], s));
     const size_t esz = op->prec == MBEM_FP64 ? 16 : 8;
     for (int o = 0; o < 3; ++o)
         MBEM_HIP(hipMemsetAsync(op->K[o], 0, esz * op->n2 * op->n2, s));
-    pe.mark(0, s);
+    f->counted = op->prec != MBEM_FP64 && !deriv;
+    if (f->counted) MBEM_HIP(hipMemsetAsync(f->d_cnt, 0, sizeof(unsigned long long), s));
+    MBEM_HIP(hipEventRecord(ev[0], s));
     if (geom) MBEM_TRY(geom_build(m, s, paper));
-    pe.mark(1, s);
-    unsigned long long *cnt = nullptr;
+    MBEM_HIP(hipEventRecord(ev[1], s));
+    unsigned long long *cnt = f->counted ? f->d_cnt : nullptr;
     if (paper && op->prec == MBEM_FP64) {
         MBEM_TRY((launch_regular<double, double, false, true>(op, 0, m->d_qp12, nullptr, s)));
-        pe.mark(2, s);
-        pe.mark(3, s);
-        MBEM_TRY((launch_ssq<double, false, true>(op, s)));
     } else if (paper) {
-        MBEM_HIP(hipMallocAsync((void **)&cnt, sizeof(unsigned long long), s));
-        MBEM_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
-        pe.mark(1, s);
         MBEM_TRY((launch_regular<float, float, false, true>(op, 1, m->d_qp12_32, cnt, s)));
-        pe.mark(2, s);
-        pe.mark(3, s);
-        MBEM_TRY((launch_ssq<float, false, true>(op, s)));
     } else if (deriv) {
-        if (op->prec != MBEM_FP64) { set_error("derivative operators are filled in FP64"); return MBEM_EINVAL; }
         MBEM_TRY((launch_regular<double, double, true>(op, 0, m->d_qp, nullptr, s)));
-        pe.mark(2, s);
-        pe.mark(3, s);
-        MBEM_TRY((launch_ssq<double, true>(op, s)));
     } else if (op->prec == MBEM_FP64) {
         MBEM_TRY((launch_regular<double, double>(op, 0, m->d_qp, nullptr, s)));
-        pe.mark(2, s);
-        pe.mark(3, s);
-        MBEM_TRY(launch_ssq<double>(op, s));
     } else {
-        MBEM_HIP(hipMallocAsync((void **)&cnt, sizeof(unsigned long long), s));
-        MBEM_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
-        pe.mark(1, s);
         MBEM_TRY((launch_regular<float, float>(op, 1, m->d_qp32, cnt, s)));
-        pe.mark(2, s);
-        pe.mark(3, s);
-        MBEM_TRY(launch_ssq<float>(op, s));
     }
-    pe.mark(4, s);
+    MBEM_HIP(hipEventRecord(ev[2], s));
+    MBEM_HIP(hipEventRecord(ev[3], s));   // near pairs run inside the regular launches
+    if (paper && op->prec == MBEM_FP64) MBEM_TRY((launch_ssq<double, false, true>(op, s)));
+    else if (paper) MBEM_TRY((launch_ssq<float, false, true>(op, s)));
+    else if (deriv) MBEM_TRY((launch_ssq<double, true>(op, s)));
+    else if (op->prec == MBEM_FP64) MBEM_TRY(launch_ssq<double>(op, s));
+    else MBEM_TRY(launch_ssq<float>(op, s));
+    MBEM_HIP(hipEventRecord(ev[4], s));
     MBEM_TRY(mass_run(op, s));
-    pe.mark(5, s);
-    MBEM_HIP(hipStreamSynchronize(s));
-    if (cnt) {
-        unsigned long long h = 0;
-        MBEM_HIP(hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost));
-        MBEM_HIP(hipFree(cnt));
-        op->n_near = (int64_t)h;
-    }
-    op->t_phase[0] = pe.ms(0, 1);
-    op->t_phase[1] = pe.ms(1, 2);
-    op->t_phase[2] = pe.ms(2, 3);
-    op->t_phase[3] = pe.ms(3, 4);
-    op->t_phase[4] = pe.ms(4, 5);
+    if (f->counted)
+        MBEM_HIP(hipMemcpyAsync(f->h_cnt, f->d_cnt, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    MBEM_HIP(hipEventRecord(ev[5], s));
+    f->pending = true;
     return MBEM_OK;
+}
+
+int fill_collect(mbem_op *op, double *t_total_ms) {
+    FillState *f = op->fs;
+    if (!f || !f->pending) { set_error("no fill to collect"); return MBEM_EINVAL; }
+    MBEM_HIP(hipEventSynchronize(f->ev[5]));
+    f->pending = false;
+    auto ms = [&](int a, int b) {
+        float t = 0.f;
+        return hipEventElapsedTime(&t, f->ev[a], f->ev[b]) == hipSuccess ? (double)t : 0.0;
+    };
+    op->n_near = f->counted ? (int64_t)*f->h_cnt : 0;
+    op->t_phase[0] = ms(0, 1);
+    op->t_phase[1] = ms(1, 2);
+    op->t_phase[2] = ms(2, 3);
+    op->t_phase[3] = ms(3, 4);
+    op->t_phase[4] = ms(4, 5);
+    if (t_total_ms) *t_total_ms = ms(6, 5);
+    return MBEM_OK;
+}
+
+int fill_run(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
+    MBEM_TRY(fill_enqueue(op, s, deriv, geom));
+    return fill_collect(op, nullptr);
 }
 
 }  // namespace mbem

@@ -12,6 +12,7 @@
 namespace mbem {
 struct KernelConst;
 struct BlrOp;
+struct FillState;
 
 // ---------------------------------------------------------------- errors --
 void set_error(const std::string &msg);
@@ -126,6 +127,8 @@ struct mbem_op {
     void *K32[3] = {nullptr, nullptr, nullptr};
     // block low-rank operator: set instead of K
     mbem::BlrOp *blr = nullptr;
+    // events and staging of the last enqueued fill
+    mbem::FillState *fs = nullptr;
 };
 
 namespace mbem {
@@ -160,8 +163,15 @@ int geom_build(const mbem_mesh *m, hipStream_t s, bool with12 = false);
 // refills the same mesh)
 int fill_run(mbem_op *op, hipStream_t s, bool deriv = false, bool geom = true);
 // The kernel constants of the op's wavenumbers on the device (first step of
-// every fill).
+// every fill), through the op's pinned staging buffer.
 int fill_prepare(mbem_op *op, hipStream_t s, bool deriv);
+// fill_run in two halves: enqueue every launch of the fill on s without
+// waiting (fill_run = fill_enqueue + fill_collect); fill_collect waits for
+// the fill's last event and reads its phase times, the near-pair count and,
+// if asked, the device time from its first launch to its last.
+int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom);
+int fill_collect(mbem_op *op, double *t_total_ms);
+void fill_state_free(FillState *f);
 // A band of test rows (compressed fill): every regular and singular pair
 // whose test triangle is listed, added into band buffers whose rows are
 // numbered by row_map.
