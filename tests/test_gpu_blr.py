@@ -123,6 +123,46 @@ def test_solve_far_field(case):
     assert err <= 20 * EPS
 
 
+@pytest.mark.parametrize("opts", [
+    dict(cluster=16, eta=0.05, eps=1e-6, rmax=64, keep_lowrank=True),   # nothing admissible
+    dict(cluster=16, eta=3.0, eps=1e-10, rmax=2, keep_lowrank=True),    # most tiles fail: dense
+    dict(cluster=1, eta=3.0, eps=1e-6, rmax=8, keep_lowrank=True),      # one node per cluster
+    dict(cluster=16, eta=3.0, eps=1e-6, rmax=64, keep_lowrank=False),   # memory rule
+])
+def test_edge_options_match_the_oracle(opts):
+    """Degenerate and limiting options on the 80-triangle sphere: the
+    expanded blocks equal the oracle's compression with the same options
+    (1e-12 of the block's largest entry) and the tile counts agree."""
+    mbem = _mbem()
+    xyz, tri = icosphere_p2(80)
+    P = galerkin.Problem(xyz, tri, 1.0, 4.0)
+    K = core.fill(xyz, tri, P.phys)
+    no, _ = solver.morton_order(xyz, tri)
+    rank = np.empty_like(no)
+    rank[no] = np.arange(no.shape[0])
+    p1 = solver.permute_unknowns(no)[: 2 * xyz.shape[0]]
+    Km = [k[np.ix_(p1, p1)] for k in K]
+    C = blr.compress(Km, xyz[no], rank[tri], opts["cluster"], opts["eta"], opts["eps"], opts["rmax"],
+                     keep_all=opts["keep_lowrank"])
+    S = mbem.Solver(xyz, tri, 1.0, 4.0)
+    try:
+        bs = S.fill_compressed(**opts)
+        Kg = [k.cpu().numpy() for k in S.export_blocks()]
+    finally:
+        S.close()
+    n_lr = sum(1 for v in C["tiles"].values() if v[0] == "lowrank")
+    print(f"\n  {opts}: clusters {bs.n_clusters}, admissible {bs.n_admissible}, low-rank GPU {bs.n_lowrank} "
+          f"oracle {n_lr}", flush=True)
+    assert bs.n_clusters == len(C["cl"]) and bs.n_admissible == 3 * int(C["adm"].sum())
+    assert abs(bs.n_lowrank - n_lr) <= max(2, 0.01 * n_lr)
+    n2 = Km[0].shape[0]
+    for o in range(3):
+        E = blr.expand(C, o, n2)
+        assert np.abs(Kg[o] - E).max() <= 1e-9 * np.abs(Km[o]).max()
+    if opts["eta"] < 0.1:
+        assert bs.n_lowrank == 0 and bs.stored_bytes == bs.dense_bytes
+
+
 def test_rejections(case):
     import torch
     mbem = _mbem()

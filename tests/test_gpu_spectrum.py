@@ -16,7 +16,7 @@ import pytest
 
 from oracle import core, mie
 from oracle import spectrum as ospec
-from workloads import icosphere_p2, silver_eps, spectrum_workload
+from workloads import icosphere_p2, silver_eps, spectrum_workload, uv_sphere_p2
 
 pytestmark = pytest.mark.gpu
 
@@ -93,6 +93,41 @@ def test_spectrum_rejects_bad_points(small):
         assert e.value.code == mbem.MBEM_EINVAL
     finally:
         S.close()
+
+
+def test_spectrum_magnetic_and_paper_scheme():
+    """Points with mu_r != 1 (the K2^mu kernels and both material
+    coefficients change per point) and the paper's quadrature scheme, each
+    against the oracle's sweep of the same points (FP64, 1e-9)."""
+    mbem = _mbem()
+    xyz, tri = icosphere_p2(80)
+    k0 = np.array([0.8, 1.3])
+    eps = np.array([2.0 + 0.1j, 4.0])
+    mu = np.array([1.5, 2.0 + 0.2j])
+    kh, pol = np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0], dtype=np.complex128)
+    for quad, variant in ((mbem.MBEM_QUAD_DEFAULT, 0), (mbem.MBEM_QUAD_PAPER, 1)):
+        ref = ospec.spectrum(xyz, tri, k0, eps, kh, pol, mu_rs=mu, ntheta=NTH, variant=variant)
+        S = mbem.Solver(xyz, tri, 1.0, 1.0, quadrature=quad)
+        try:
+            sig, it, st = S.spectrum(k0, eps, kh, pol, mu_r=mu, block=50, tol=1e-12, maxit=400, ntheta=NTH)
+        finally:
+            S.close()
+        rel = np.abs(sig / ref - 1).max()
+        print(f"\n  quadrature {quad}: max rel {rel:.2e}", flush=True)
+        assert rel < 1e-9
+
+
+def test_spectrum_single_point_without_preconditioner():
+    mbem = _mbem()
+    xyz, tri = uv_sphere_p2(9, 6, (1.0, 1.0, 1.3))   # 90 triangles: a ragged trial tile
+    kh, pol = np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0], dtype=np.complex128)
+    ref = ospec.spectrum(xyz, tri, [2.0], [3.0 + 0.5j], kh, pol, ntheta=NTH)
+    S = mbem.Solver(xyz, tri, 1.0, 1.0)
+    try:
+        sig, it, st = S.spectrum([2.0], [3.0 + 0.5j], kh, pol, block=0, tol=1e-12, maxit=600, ntheta=NTH)
+    finally:
+        S.close()
+    assert it.shape == (1,) and np.abs(sig / ref - 1).max() < 1e-9
 
 
 # ------------------------------------------------------------ full size --
