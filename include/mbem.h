@@ -370,14 +370,17 @@ int mbem_cross_sections(mbem_ctx *ctx, const mbem_mesh *mesh,
  * partial pivoting to relative Frobenius accuracy eps (at most rmax terms);
  * it is kept low-rank when that converged and stores less than the dense
  * tile (or always, keep_lowrank = 1), else dense.  Other tiles are dense.
- * The dense operator is never formed: rows are filled one cluster band at a
- * time into a scratch of 3 x 2(cluster + halo) x 2 n_nodes entries.        */
+ * The dense operator is never formed: rows are filled one band of whole
+ * clusters at a time into a scratch of 3 x 2(band + halo) x 2 n_nodes
+ * entries, and every cluster's tiles are approximated from them.            */
 typedef struct {
     int32_t cluster;       /* largest nodes per cluster, 1..2048            */
     double eta;            /* admissibility parameter, > 0                  */
     double eps;            /* cross-approximation tolerance, (0, 1)         */
     int32_t rmax;          /* largest rank, 1..128                          */
     int32_t keep_lowrank;  /* 1: keep every converged approximation low-rank */
+    int32_t band;          /* nodes per row band of the assembly (whole
+                              clusters); 0: about 16 GB of band buffers      */
 } mbem_blr_opts;
 
 typedef struct {

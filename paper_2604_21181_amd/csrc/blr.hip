@@ -125,7 +125,7 @@ __device__ inline double2 cdotc(double2 a, double2 b) { return {a.x * b.x + a.y 
 // ------------------------------------------------------------ ACA ---
 struct AcaTask {
     int32_t op, m, n, pad;
-    int64_t c0;          // first column of the tile in the block
+    int64_t org;         // offset of the tile's first entry in the band buffer
     int64_t u, v;        // scratch offsets of U [rmax][m] and V [rmax][n]
 };
 
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const AcaTask *tasks, const
     __shared__ double s_bv[kAcaWaves];
     __shared__ int s_bi[kAcaWaves];
     const AcaTask T = tasks[blockIdx.x];
-    const double2 *A = (T.op == 0 ? Z0 : (T.op == 1 ? Z1 : Z2)) + T.c0;
+    const double2 *A = (T.op == 0 ? Z0 : (T.op == 1 ? Z1 : Z2)) + T.org;
     double2 *U = scr + T.u, *V = scr + T.v;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = T.m, n = T.n;
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kAcaThreads) void k_aca(const AcaTask *tasks, const
 // ------------------------------------------------------------ packing ---
 struct PackTask {
     int32_t op, rank, m, n;  // rank < 0: dense copy of the band's tile
-    int64_t c0;              // first column of the tile
+    int64_t org;             // offset of the tile's first entry in the band buffer
     int64_t u, v;            // scratch offsets (low-rank)
     double2 *a, *vt;         // destinations
 };
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void k_blr_pack(const PackTask *tasks, const d
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
     const int64_t first = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (T.rank < 0) {
-        const double2 *A = (T.op == 0 ? Z0 : (T.op == 1 ? Z1 : Z2)) + T.c0;
+        const double2 *A = (T.op == 0 ? Z0 : (T.op == 1 ? Z1 : Z2)) + T.org;
         const int64_t cnt = (int64_t)T.m * T.n;
         for (int64_t e = first; e < cnt; e += step) T.a[e] = A[(e / T.n) * ld + e % T.n];
         return;
@@ -537,25 +537,46 @@ int blr_fill_run(mbem_op *op, const mbem_blr_opts *o, mbem_blr_stats *bs, hipStr
             const double dist = std::sqrt(g2), diam = std::sqrt(std::max(dt, ds));
             if (dist > 0 && diam <= o->eta * dist) { adm[(size_t)t * nc + sc] = 1; ++n_adm; }
         }
-    // band lists: test triangles by colour class, singular pairs, row maps
+    // Row bands: runs of whole clusters of up to `band` nodes (automatic:
+    // three band buffers of about 16 GB), filled together so that the halo
+    // and the number of launches shrink; every cluster's tiles are then
+    // approximated from the band's rows.
+    int64_t band_nodes = o->band > 0 ? o->band : (int64_t)(16e9 / (3.0 * 2.5 * 16.0 * (double)n2));
+    band_nodes = std::max<int64_t>(band_nodes, L);
+    if (o->band <= 0) band_nodes = std::min<int64_t>(band_nodes, 8192);
+    std::vector<int32_t> bstart(1, 0);   // first cluster of each band, then nc
+    for (int c = 0; c < nc; ++c)
+        if (c > bstart.back() && (int64_t)start[c + 1] - start[bstart.back()] > band_nodes) bstart.push_back(c);
+    bstart.push_back(nc);
+    const int nb = (int)bstart.size() - 1;
+    std::vector<int32_t> band_of(nc);
+    for (int bb = 0; bb < nb; ++bb)
+        for (int c = bstart[bb]; c < bstart[bb + 1]; ++c) band_of[c] = bb;
+    // band lists: test triangles by colour class, singular pairs, halo nodes
     const int ntc = (int)m->tcol_off.size() - 1;
-    std::vector<std::vector<int32_t>> btri(nc), boff(nc, std::vector<int32_t>(1, 0)), bsp(nc);
+    std::vector<std::vector<int32_t>> tri_b(nt);   // bands with a node of the triangle
+    for (int64_t e = 0; e < nt; ++e)
+        for (int32_t c : tri_bands[e]) {
+            const int32_t bb = band_of[c];
+            if (std::find(tri_b[e].begin(), tri_b[e].end(), bb) == tri_b[e].end()) tri_b[e].push_back(bb);
+        }
+    std::vector<std::vector<int32_t>> btri(nb), boff(nb, std::vector<int32_t>(1, 0)), bsp(nb);
     for (int tc = 0; tc < ntc; ++tc) {
         for (int32_t q = m->tcol_off[tc]; q < m->tcol_off[tc + 1]; ++q) {
             const int32_t e = m->tcol_list[q];
-            for (int32_t c : tri_bands[e]) btri[c].push_back(e);
+            for (int32_t bb : tri_b[e]) btri[bb].push_back(e);
         }
-        for (int c = 0; c < nc; ++c) boff[c].push_back((int32_t)btri[c].size());
+        for (int bb = 0; bb < nb; ++bb) boff[bb].push_back((int32_t)btri[bb].size());
     }
     for (size_t q = 0; q + 3 < m->spairs.size(); q += 4)
-        for (int32_t c : tri_bands[m->spairs[q]])
-            for (int k = 0; k < 4; ++k) bsp[c].push_back(m->spairs[q + k]);
-    std::vector<std::vector<int32_t>> halo(nc);
-    size_t rows_max = 0, tri_max = 0, sp_max = 0, scr_max = 0, task_max = 0;
-    for (int c = 0; c < nc; ++c) {
-        const int64_t n0 = start[c], n1 = start[c + 1];
-        std::vector<int32_t> &h = halo[c];
-        for (int32_t e : btri[c])
+        for (int32_t bb : tri_b[m->spairs[q]])
+            for (int k = 0; k < 4; ++k) bsp[bb].push_back(m->spairs[q + k]);
+    std::vector<std::vector<int32_t>> halo(nb);
+    size_t rows_max = 0, tri_max = 0, sp_max = 0, scr_max = 0, task_max = 0, pack_max = 0;
+    for (int bb = 0; bb < nb; ++bb) {
+        const int64_t n0 = start[bstart[bb]], n1 = start[bstart[bb + 1]];
+        std::vector<int32_t> &h = halo[bb];
+        for (int32_t e : btri[bb])
             for (int i = 0; i < 6; ++i) {
                 const int32_t v = m->tri[6 * (size_t)e + i];
                 if (v < n0 || v >= n1) h.push_back(v);
@@ -563,17 +584,18 @@ int blr_fill_run(mbem_op *op, const mbem_blr_opts *o, mbem_blr_stats *bs, hipStr
         std::sort(h.begin(), h.end());
         h.erase(std::unique(h.begin(), h.end()), h.end());
         rows_max = std::max(rows_max, (size_t)(2 * (n1 - n0) + 2 * h.size()));
-        tri_max = std::max(tri_max, btri[c].size());
-        sp_max = std::max(sp_max, bsp[c].size());
+        tri_max = std::max(tri_max, btri[bb].size());
+        sp_max = std::max(sp_max, bsp[bb].size());
         size_t scr = 0, ntask = 0;
-        for (int sc = 0; sc < nc; ++sc)
-            if (adm[(size_t)c * nc + sc]) {
-                const int64_t ns = size_of(sc);
-                scr += 3 * (size_t)o->rmax * (size_t)(2 * (n1 - n0) + 2 * ns);
-                ntask += 3;
-            }
+        for (int c = bstart[bb]; c < bstart[bb + 1]; ++c)
+            for (int sc = 0; sc < nc; ++sc)
+                if (adm[(size_t)c * nc + sc]) {
+                    scr += 3 * (size_t)o->rmax * (size_t)(2 * size_of(c) + 2 * size_of(sc));
+                    ntask += 3;
+                }
         scr_max = std::max(scr_max, scr);
         task_max = std::max(task_max, ntask);
+        pack_max = std::max(pack_max, 3 * (size_t)nc * (size_t)(bstart[bb + 1] - bstart[bb]));
     }
     // device buffers of the assembly
     Scratch S;
@@ -589,7 +611,7 @@ int blr_fill_run(mbem_op *op, const mbem_blr_opts *o, mbem_blr_stats *bs, hipStr
     MBEM_TRY(S.alloc(&d_sp, sp_max));
     MBEM_TRY(S.alloc(&d_rank, task_max));
     MBEM_TRY(S.alloc(&d_tasks, task_max));
-    MBEM_TRY(S.alloc(&d_pack, 3 * (size_t)nc));
+    MBEM_TRY(S.alloc(&d_pack, pack_max));
     BlrOp *b = new (std::nothrow) BlrOp;
     if (!b) { set_error("host allocation"); return MBEM_ENOMEM; }
     op->blr = b;
@@ -615,38 +637,42 @@ int blr_fill_run(mbem_op *op, const mbem_blr_opts *o, mbem_blr_stats *bs, hipStr
     std::vector<AcaTask> tasks;
     std::vector<int32_t> ranks;
     std::vector<PackTask> packs;
-    for (int c = 0; c < nc; ++c) {
-        const int64_t n0 = start[c], n1 = start[c + 1];
-        const int32_t mt = (int32_t)(2 * (n1 - n0));
+    for (int bb = 0; bb < nb; ++bb) {
+        const int cb = bstart[bb], ce = bstart[bb + 1];
+        const int64_t n0 = start[cb], n1 = start[ce];
         // rows: the band's nodes first (node - n0), then its halo
         for (int64_t v = n0; v < n1; ++v) rmap[v] = (int32_t)(v - n0);
-        for (size_t q = 0; q < halo[c].size(); ++q) rmap[halo[c][q]] = (int32_t)(n1 - n0 + q);
-        const size_t rows = (size_t)mt + 2 * halo[c].size();
+        for (size_t q = 0; q < halo[bb].size(); ++q) rmap[halo[bb][q]] = (int32_t)(n1 - n0 + q);
+        const size_t rows = (size_t)(2 * (n1 - n0)) + 2 * halo[bb].size();
         MBEM_HIP(hipMemcpyAsync(d_map, rmap.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, s));
-        MBEM_HIP(hipMemcpyAsync(d_tri, btri[c].data(), sizeof(int32_t) * btri[c].size(), hipMemcpyHostToDevice, s));
-        MBEM_HIP(hipMemcpyAsync(d_sp, bsp[c].data(), sizeof(int32_t) * bsp[c].size(), hipMemcpyHostToDevice, s));
+        MBEM_HIP(hipMemcpyAsync(d_tri, btri[bb].data(), sizeof(int32_t) * btri[bb].size(), hipMemcpyHostToDevice, s));
+        MBEM_HIP(hipMemcpyAsync(d_sp, bsp[bb].data(), sizeof(int32_t) * bsp[bb].size(), hipMemcpyHostToDevice, s));
         for (int q = 0; q < 3; ++q)
             MBEM_HIP(hipMemsetAsync(zb + q * band_elems, 0, sizeof(double2) * rows * n2, s));
         FillBand fb;
         fb.tcol = d_tri;
-        fb.tcol_off = boff[c];
+        fb.tcol_off = boff[bb];
         fb.spairs = d_sp;
-        fb.n_spairs = (int64_t)bsp[c].size() / 4;
+        fb.n_spairs = (int64_t)bsp[bb].size() / 4;
         fb.row_map = d_map;
         for (int q = 0; q < 3; ++q) fb.Z[q] = zb + q * band_elems;
         MBEM_HIP(hipEventRecord(ev.a, s));
         MBEM_TRY(fill_band_run(op, fb, s));
         MBEM_HIP(hipEventRecord(ev.b, s));
-        // cross approximation of the band's admissible tiles
+        // cross approximation of the admissible tiles of the band's clusters
         tasks.clear();
         int64_t off = 0;
-        for (int sc = 0; sc < nc; ++sc) {
-            if (!adm[(size_t)c * nc + sc]) continue;
-            const int32_t ns = (int32_t)(2 * size_of(sc));
-            for (int q = 0; q < 3; ++q) {
-                AcaTask a{q, mt, ns, 0, 2 * (int64_t)start[sc], off, off + (int64_t)o->rmax * mt};
-                off += (int64_t)o->rmax * (mt + ns);
-                tasks.push_back(a);
+        for (int c = cb; c < ce; ++c) {
+            const int32_t mt = (int32_t)(2 * size_of(c));
+            const int64_t rorg = 2 * (int64_t)(start[c] - n0) * n2;   // first row of c in the band
+            for (int sc = 0; sc < nc; ++sc) {
+                if (!adm[(size_t)c * nc + sc]) continue;
+                const int32_t ns = (int32_t)(2 * size_of(sc));
+                for (int q = 0; q < 3; ++q) {
+                    AcaTask a{q, mt, ns, 0, rorg + 2 * (int64_t)start[sc], off, off + (int64_t)o->rmax * mt};
+                    off += (int64_t)o->rmax * (mt + ns);
+                    tasks.push_back(a);
+                }
             }
         }
         if (!tasks.empty()) {
@@ -662,21 +688,25 @@ int blr_fill_run(mbem_op *op, const mbem_blr_opts *o, mbem_blr_stats *bs, hipStr
         MBEM_HIP(hipStreamSynchronize(s));
         t_fill += Events::ms(ev.a, ev.b);
         t_aca += Events::ms(ev.b, ev.c);
-        // storage of the band's tiles
-        std::vector<int32_t> keep_rank(3 * (size_t)nc, -1);
+        // storage of the band's tiles: what each one keeps
+        const size_t ncb = (size_t)(ce - cb);
+        std::vector<int32_t> keep_rank(3 * ncb * nc, -1);   // [c - cb][q][sc]
         size_t ti = 0;
         int64_t elems = 0;
-        for (int sc = 0; sc < nc; ++sc) {
-            const int64_t ns = 2 * size_of(sc);
-            const bool a = adm[(size_t)c * nc + sc];
-            for (int q = 0; q < 3; ++q) {
-                int32_t r = -1;
-                if (a) {
-                    const int32_t got = ranks[ti++];
-                    if (got >= 0 && (o->keep_lowrank || (int64_t)got * (mt + ns) < (int64_t)mt * ns)) r = got;
+        for (int c = cb; c < ce; ++c) {
+            const int64_t mt = 2 * size_of(c);
+            for (int sc = 0; sc < nc; ++sc) {
+                const int64_t ns = 2 * size_of(sc);
+                const bool a = adm[(size_t)c * nc + sc];
+                for (int q = 0; q < 3; ++q) {
+                    int32_t r = -1;
+                    if (a) {
+                        const int32_t got = ranks[ti++];
+                        if (got >= 0 && (o->keep_lowrank || (int64_t)got * (mt + ns) < mt * ns)) r = got;
+                    }
+                    keep_rank[((size_t)(c - cb) * 3 + q) * nc + sc] = r;
+                    elems += r < 0 ? mt * ns : (int64_t)r * (mt + ns);
                 }
-                keep_rank[(size_t)q * nc + sc] = r;
-                elems += r < 0 ? (int64_t)mt * ns : (int64_t)r * (mt + ns);
             }
         }
         double2 *store = nullptr;
@@ -692,41 +722,51 @@ int blr_fill_run(mbem_op *op, const mbem_blr_opts *o, mbem_blr_stats *bs, hipStr
         packs.clear();
         int64_t pos = 0;
         ti = 0;
-        for (int sc = 0; sc < nc; ++sc) {
-            const int32_t ns = (int32_t)(2 * size_of(sc));
-            const bool a = adm[(size_t)c * nc + sc];
-            for (int q = 0; q < 3; ++q) {
-                const int32_t r = keep_rank[(size_t)q * nc + sc];
-                BlrTile &T = b->tiles[((size_t)q * nc + c) * nc + sc];
-                T = BlrTile{q, c, sc, r, mt, ns, 2 * n0, 2 * (int64_t)start[sc], store + pos, nullptr, 0, 0};
-                PackTask P{q, r, mt, ns, 2 * (int64_t)start[sc], 0, 0, store + pos, nullptr};
-                if (a) {
-                    P.u = tasks[ti].u;
-                    P.v = tasks[ti].v;
-                    ++ti;
+        for (int c = cb; c < ce; ++c) {
+            const int32_t mt = (int32_t)(2 * size_of(c));
+            const int64_t rorg = 2 * (int64_t)(start[c] - n0) * n2;
+            for (int sc = 0; sc < nc; ++sc) {
+                const int32_t ns = (int32_t)(2 * size_of(sc));
+                const bool a = adm[(size_t)c * nc + sc];
+                for (int q = 0; q < 3; ++q) {
+                    const int32_t r = keep_rank[((size_t)(c - cb) * 3 + q) * nc + sc];
+                    BlrTile &T = b->tiles[((size_t)q * nc + c) * nc + sc];
+                    T = BlrTile{q, c, sc, r, mt, ns, 2 * (int64_t)start[c], 2 * (int64_t)start[sc], store + pos,
+                                nullptr, 0, 0};
+                    PackTask P{q, r, mt, ns, rorg + 2 * (int64_t)start[sc], 0, 0, store + pos, nullptr};
+                    if (a) {
+                        P.u = tasks[ti].u;
+                        P.v = tasks[ti].v;
+                        ++ti;
+                    }
+                    if (r < 0) pos += (int64_t)mt * ns;
+                    else {
+                        T.vt = store + pos + (int64_t)mt * r;
+                        P.vt = T.vt;
+                        pos += (int64_t)r * (mt + ns);
+                        ++n_lowrank;
+                        max_rank = std::max(max_rank, (int)r);
+                        sum_rank += r;
+                    }
+                    if (r != 0) packs.push_back(P);
                 }
-                if (r < 0) pos += (int64_t)mt * ns;
-                else {
-                    T.vt = store + pos + (int64_t)mt * r;
-                    P.vt = T.vt;
-                    pos += (int64_t)r * (mt + ns);
-                    ++n_lowrank;
-                    max_rank = std::max(max_rank, (int)r);
-                    sum_rank += r;
-                }
-                if (r != 0) packs.push_back(P);
             }
         }
         if (!packs.empty()) {
             MBEM_HIP(hipMemcpyAsync(d_pack, packs.data(), sizeof(PackTask) * packs.size(), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_blr_pack, dim3(64, (unsigned)packs.size()), dim3(256), 0, s, d_pack, zb,
-                               zb + band_elems, zb + 2 * band_elems, (int64_t)n2, scr);
+            // tasks along y, at most 65535 per launch
+            for (size_t p0 = 0; p0 < packs.size(); p0 += 65535) {
+                const size_t ny = std::min<size_t>(65535, packs.size() - p0);
+                hipLaunchKernelGGL(k_blr_pack, dim3(64, (unsigned)ny), dim3(256), 0, s, d_pack + p0, zb,
+                                   zb + band_elems, zb + 2 * band_elems, (int64_t)n2, scr);
+                MBEM_HIP(hipGetLastError());
+            }
             MBEM_HIP(hipGetLastError());
         }
         // the host lists of the next band overwrite what these copies read
         MBEM_HIP(hipStreamSynchronize(s));
         for (int64_t v = n0; v < n1; ++v) rmap[v] = 0;
-        for (int32_t v : halo[c]) rmap[v] = 0;
+        for (int32_t v : halo[bb]) rmap[v] = 0;
     }
     // product workspace and device tables
     std::vector<int32_t> lr, dn;

@@ -542,8 +542,9 @@ int mbem_fill_compressed(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params
         return MBEM_EINVAL;
     }
     if (o->cluster < 1 || o->cluster > 2048 || !(o->eta > 0) || !(o->eps > 0 && o->eps < 1) || o->rmax < 1 ||
-        o->rmax > 128) {
-        set_error("block low-rank options out of range (cluster 1..2048, eta > 0, 0 < eps < 1, rmax 1..128)");
+        o->rmax > 128 || o->band < 0) {
+        set_error("block low-rank options out of range (cluster 1..2048, eta > 0, 0 < eps < 1, rmax 1..128, "
+                  "band >= 0)");
         return MBEM_EINVAL;
     }
     mbem_op *op = nullptr;

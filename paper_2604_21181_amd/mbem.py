@@ -66,7 +66,7 @@ class Stats(C.Structure):
 
 class BlrOpts(C.Structure):
     _fields_ = [("cluster", C.c_int32), ("eta", C.c_double), ("eps", C.c_double), ("rmax", C.c_int32),
-                ("keep_lowrank", C.c_int32)]
+                ("keep_lowrank", C.c_int32), ("band", C.c_int32)]
 
 
 class BlrStats(C.Structure):
@@ -226,11 +226,12 @@ def mbem_fill(ctx, mesh, params):
     return h, st
 
 
-def mbem_fill_compressed(ctx, mesh, params, cluster=256, eta=2.0, eps=1e-6, rmax=128, keep_lowrank=False):
+def mbem_fill_compressed(ctx, mesh, params, cluster=256, eta=2.0, eps=1e-6, rmax=128, keep_lowrank=False,
+                         band=0):
     """Block low-rank operator; returns (op, Stats, BlrStats)."""
     op = C.c_void_p()
     st, bs = Stats(), BlrStats()
-    o = BlrOpts(cluster, eta, eps, rmax, 1 if keep_lowrank else 0)
+    o = BlrOpts(cluster, eta, eps, rmax, 1 if keep_lowrank else 0, band)
     _check(lib().mbem_fill_compressed(ctx, mesh, C.byref(params), C.byref(o), C.byref(op), C.byref(st),
                                       C.byref(bs)))
     return op, st, bs

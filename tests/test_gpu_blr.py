@@ -128,6 +128,7 @@ def test_solve_far_field(case):
     dict(cluster=16, eta=3.0, eps=1e-10, rmax=2, keep_lowrank=True),    # most tiles fail: dense
     dict(cluster=1, eta=3.0, eps=1e-6, rmax=8, keep_lowrank=True),      # one node per cluster
     dict(cluster=16, eta=3.0, eps=1e-6, rmax=64, keep_lowrank=False),   # memory rule
+    dict(cluster=8, eta=3.0, eps=1e-6, rmax=64, keep_lowrank=True, band=40),   # several row bands
 ])
 def test_edge_options_match_the_oracle(opts):
     """Degenerate and limiting options on the 80-triangle sphere: the
@@ -173,7 +174,7 @@ def test_rejections(case):
     with pytest.raises(mbem.MbemError):
         S.solve_adjoint(g, 1e-8)
     for bad in (dict(cluster=0), dict(cluster=4096), dict(eps=0.0), dict(rmax=0), dict(rmax=129),
-                dict(eta=0.0)):
+                dict(eta=0.0), dict(band=-1)):
         kw = dict(OPTS)
         kw.update(bad)
         T = mbem.Solver(case["xyz"], case["tri"], 3.0, 2.25)
