@@ -2,9 +2,9 @@
 // products U V^T from adaptive cross approximation (ACA), near tiles dense.
 // The paper stops at the dense operator and names fast far-field methods as
 // future work (Sec. 8); this extends the solve to meshes whose dense blocks
-// exceed one device's memory.  The operator is filled one band of rows (one
-// row cluster) at a time into a scratch, compressed, and packed; the dense
-// blocks never exist.
+// exceed one device's memory.  The operator is filled one band of rows (a
+// run of whole row clusters) at a time into a scratch, compressed, and
+// packed; the dense blocks never exist.
 //
 // Tiles are kept in the fixed order (op, row cluster t, column cluster s),
 // so tile (op, t, s) is tiles[(op nc + t) nc + s] and the tiles of one band
