@@ -62,3 +62,28 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(mbem, "_lib", None)
     with pytest.raises(ImportError):
         mbem.lib()
+
+
+def test_argument_errors_before_any_device_call():
+    """Entry points reject null handles and out-of-range options on the host
+    (MBEM_EINVAL), before touching a device."""
+    import ctypes as C
+    from paper_2604_21181_amd import mbem
+    L = mbem.lib()
+    p = mbem.make_params(1.0, 4.0)
+    o = mbem.SolveOpts(1e-8, 100, 0, 0.0)
+    out = np.zeros(3)
+    k0 = np.array([1.0])
+    eps = np.array([4.0 + 0j])
+    kh = np.array([0.0, 0.0, 1.0])
+    pol = np.array([1.0 + 0j, 0, 0])
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    # mesh missing
+    assert L.mbem_spectrum(None, None, C.byref(p), 1, ptr(k0), ptr(eps), None, ptr(kh), ptr(pol), 100,
+                           C.byref(o), 0, ptr(out), None, None) == mbem.MBEM_EINVAL
+    opts = mbem.BlrOpts(64, 2.0, 1e-6, 64, 0, 0)
+    op = C.c_void_p()
+    assert L.mbem_fill_compressed(None, None, C.byref(p), C.byref(opts), C.byref(op), None,
+                                  None) == mbem.MBEM_EINVAL
+    assert L.mbem_fill(None, None, C.byref(p), C.byref(op), None) == mbem.MBEM_EINVAL
+    assert "null" in L.mbem_last_error().decode()
