@@ -200,6 +200,9 @@ def test_lspr_spheroid_peak_and_energy_balance():
         S.close()
     print("  C_ext", np.round(sig[:, 0]).tolist(), "iterations", it.tolist(), flush=True)
     assert st.rel_resid <= 2 * c["tol"]
+    # the paper: MBJ with clusters of 100 (123 blocks) converges in 18
+    # iterations to 1e-5 at 506 nm
+    assert abs(int(it[list(lam).index(506.0)]) - 18) <= 2
     i = int(np.argmax(sig[:, 0]))
     assert 0 < i < len(lam) - 1 and abs(lam[i] - 506.0) <= 1.0
     assert 75000.0 <= sig[i, 0] <= 85000.0
