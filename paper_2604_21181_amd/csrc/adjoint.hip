@@ -107,18 +107,33 @@ __device__ inline double2 zm(double2 a, double2 b) { return {a.x * b.x - a.y * b
 // y = Z^T lambda from the summed partials and the (symmetric) mass matrix:
 //   y_j = (i/w) K1^T l1 + K2mu^T l2 + c_mu M l2
 //   y_m = K2eps^T l1 + c_eps M l1 - (i/w) K1^T l2
-__global__ void k_combine_t(int64_t n2, int nch, const double2 *__restrict__ part,
-                            const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
-                            const double *__restrict__ mval, const double2 *__restrict__ l1,
-                            const double2 *__restrict__ l2, TCoef c, double2 *__restrict__ y) {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= n2) return;
+// A workgroup takes 64 rows; its four wavefronts sum every fourth chunk of
+// partials and the four sums are added in a fixed order through LDS.
+constexpr int kCombRows = 64;
+__global__ __launch_bounds__(256) void k_combine_t(int64_t n2, int nch, const double2 *__restrict__ part,
+                                                   const int32_t *__restrict__ mptr,
+                                                   const int32_t *__restrict__ mcol,
+                                                   const double *__restrict__ mval,
+                                                   const double2 *__restrict__ l1,
+                                                   const double2 *__restrict__ l2, TCoef c,
+                                                   double2 *__restrict__ y) {
+    __shared__ double2 s_t[4][4][kCombRows];   // [group][slot][row]
+    const int lr = threadIdx.x % kCombRows, grp = threadIdx.x / kCombRows;
+    const int64_t r = blockIdx.x * (int64_t)kCombRows + lr;
     double2 t[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    for (int ch = 0; ch < nch; ++ch)
-        for (int k = 0; k < 4; ++k) {
-            const double2 v = part[((int64_t)ch * 4 + k) * n2 + r];
-            t[k].x += v.x; t[k].y += v.y;
-        }
+    if (r < n2)
+        for (int ch = grp; ch < nch; ch += 4)
+            for (int k = 0; k < 4; ++k) {
+                const double2 v = part[((int64_t)ch * 4 + k) * n2 + r];
+                t[k].x += v.x; t[k].y += v.y;
+            }
+    for (int k = 0; k < 4; ++k) s_t[grp][k][lr] = t[k];
+    __syncthreads();
+    if (grp != 0 || r >= n2) return;
+    for (int k = 0; k < 4; ++k) {
+        t[k] = s_t[0][k][lr];
+        for (int g = 1; g < 4; ++g) { t[k].x += s_t[g][k][lr].x; t[k].y += s_t[g][k][lr].y; }
+    }
     const int64_t i = r / 2;
     const int al = (int)(r % 2);
     double2 M1 = {0, 0}, M2 = {0, 0};
@@ -145,7 +160,8 @@ int matvec_t_run(const mbem_op *op, const double2 *x, double2 *y, double2 *part,
                            (const float2 *)op->K[1], (const float2 *)op->K[2], x, x + n2, part);
     MBEM_HIP(hipGetLastError());
     const mbem_mesh *m = op->mesh;
-    hipLaunchKernelGGL(k_combine_t, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, n2, nch, part, m->d_mptr,
+    hipLaunchKernelGGL(k_combine_t, dim3((unsigned)((n2 + kCombRows - 1) / kCombRows)), dim3(256), 0, s, n2, nch,
+                       part, m->d_mptr,
                        m->d_mcol, op->d_mval, x, x + n2, TCoef{op->iw, op->ce, op->cm}, y);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
