@@ -9,8 +9,9 @@ direct form, from the paper (arXiv 2604.21181):
   core.py      C core (FP64): P2 geometry, nodal frames, kernels, pair
                quadrature (7-point rule and Sauter-Schwab), dense fill,
                single node-pair entries
-  galerkin.py  mass matrix, system assembly, plane-wave excitation,
-               far field and cross sections
+  galerkin.py  tangential basis (interpolated frame or node-attached
+               tangents), mass matrix, system assembly, plane-wave
+               excitation, far field and cross sections
   solver.py    Morton order, Morton block-Jacobi, GMRES
   mie.py       Mie series (spheres)
   spectrum.py  sweeps over wavenumber and material on one mesh
@@ -31,10 +32,11 @@ __all__ = ["blr", "core", "galerkin", "mie", "solver", "spectrum", "Problem", "s
 
 
 def solve_dense(P: Problem, khat, pol, K=None):
-    """Fill, assemble and solve by dense LU.  Returns (x[4nn, nrhs], K, M)."""
+    """Fill, assemble and solve by dense LU.  Returns (x[4nn, nrhs], K, G)
+    with G the Gram matrix of the tangential basis (galerkin.mass_blocks)."""
     if K is None:
         K = core.fill(P.xyz, P.tri6, P.phys, nss=P.nss)
-    M = galerkin.mass_matrix(P)
+    M = galerkin.mass_blocks(P)
     Z = galerkin.assemble(P, K[0], K[1], K[2], M)
     b = galerkin.planewave_rhs(P, khat, pol)
     x = np.linalg.solve(Z, b)

@@ -64,13 +64,18 @@ def _mesh(xyz, tri6):
     return xyz, tri6
 
 
-def phys_vector(k0, eps_r, mu_r=1.0, variant=0):
+def phys_vector(k0, eps_r, mu_r=1.0, variant=0, frame=0):
     """variant 0: 7-point regular rule, Sauter-Schwab on the full kernels,
     16-term series; 1: the paper's own scheme (12-point rule, Sauter-Schwab
     on the singular parts, the remainder by the 12-point rule, series
-    truncated after n = 6)."""
+    truncated after n = 6).
+    frame 0: basis N_j(y) t_beta(y) on the interpolated Gram-Schmidt frame
+    (Sec. 3.3, Sec. 4.1); 1: node-attached tangents N_j(y) P(y) t_beta,j."""
     eps_r, mu_r = complex(eps_r), complex(mu_r)
-    return np.array([k0, eps_r.real, eps_r.imag, mu_r.real, mu_r.imag, float(variant)])
+    if frame not in (0, 1):
+        raise ValueError(frame)
+    return np.array([k0, eps_r.real, eps_r.imag, mu_r.real, mu_r.imag, float(variant),
+                     float(frame)])
 
 
 def rule7():

@@ -5,6 +5,12 @@ TEST INFRASTRUCTURE ONLY.
 Unknown layout: x = [c_j ; c_jm], each of length 2 n_nodes with index
 2 * node + alpha in the caller's node order.  Units: eps_a = mu_a = 1,
 eta_a = 1, omega = k_a = k0.
+
+Tangential basis (``frame``): 0, the paper's printed construction, basis
+vector N_j(y) t_beta(y) with t_beta(y) the interpolated Gram-Schmidt frame
+(Sec. 3.3, Sec. 4.1); 1, node-attached tangents, N_j(y) P(y) t_beta,j with
+t_beta,j the nodal triad's tangents (Sec. 3.2) and P(y) = I - n(y) n(y)^T.
+The rotated test vector is (basis vector) x n in both.
 """
 from __future__ import annotations
 
@@ -17,7 +23,7 @@ from . import core
 class Problem:
     """A mesh plus material: everything the oracle's formulas need."""
 
-    def __init__(self, xyz, tri6, k0, eps_r, mu_r=1.0, nss=4, variant=0):
+    def __init__(self, xyz, tri6, k0, eps_r, mu_r=1.0, nss=4, variant=0, frame=0):
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self.tri6 = np.ascontiguousarray(tri6, dtype=np.int64)
         self.nn = self.xyz.shape[0]
@@ -29,12 +35,14 @@ class Problem:
         # variant selects the quadrature of the operator blocks (core.phys_vector);
         # mass matrix, right-hand side and far field keep the 7-point rule
         self.variant = variant
-        self.phys = core.phys_vector(k0, eps_r, mu_r, variant)
+        self.frame = frame
+        self.phys = core.phys_vector(k0, eps_r, mu_r, variant, frame)
         self.ka = self.k0
         ki = self.k0 * np.sqrt(self.eps_r * self.mu_r)
         self.ki = -ki if ki.imag < 0 else ki
         self.omega = self.k0
         self._qp = None
+        self._basis = None
 
     # quadrature-point table on the 7-point rule -------------------------
     def qp(self):
@@ -46,6 +54,25 @@ class Problem:
                                    np.tile(xi, self.nt), np.tile(eta, self.nt))
             self._qp = (elem, np.tile(w, self.nt), rows)
         return self._qp
+
+    def basis(self):
+        """V[q, k, beta, 3]: the tangent vector that multiplies N_k in the
+        basis function of local node k, component beta, at every 7-point rule
+        point q (without the N_k factor)."""
+        if self._basis is None:
+            elem, w, rows = self.qp()
+            V = np.zeros((elem.shape[0], 6, 2, 3))
+            if self.frame == 0:
+                V[:, :, 0, :] = rows[:, None, 7:10]
+                V[:, :, 1, :] = rows[:, None, 10:13]
+            else:
+                n = rows[:, 4:7]
+                _, t1n, t2n = core.nodal_frames(self.xyz, self.tri6)
+                for b, tn in enumerate((t1n, t2n)):
+                    t = tn[self.tri6[elem]]                              # q k 3
+                    V[:, :, b, :] = t - np.sum(t * n[:, None, :], axis=2)[:, :, None] * n[:, None, :]
+            self._basis = V
+        return self._basis
 
 
 def mass_matrix(P: Problem):
@@ -64,17 +91,40 @@ def mass_matrix(P: Problem):
     return M
 
 
+def mass_blocks(P: Problem):
+    """Gram matrix of the vector basis, G[2i+a, 2j+b] = int N_i N_j V_ia . V_jb
+    (eq. mass_matrix for the tangential functions), sparse 2nn x 2nn.  With
+    the interpolated frame V_ia . V_jb = delta_ab and G = M (x) I_2."""
+    if P.frame == 0:
+        return sp.kron(mass_matrix(P), sp.identity(2), format="csr")
+    elem, w, rows = P.qp()
+    WJ = w * rows[:, 3]
+    N = rows[:, 19:25]
+    V = (N[:, :, None, None] * P.basis()).reshape(-1, 12, 3)
+    dof = (2 * P.tri6[elem][:, :, None] + np.arange(2)[None, None, :]).reshape(-1, 12)
+    G = np.einsum("q,qad,qbd->qab", WJ, V, V)
+    r = np.repeat(dof[:, :, None], 12, axis=2).ravel()
+    c = np.repeat(dof[:, None, :], 12, axis=1).ravel()
+    return sp.coo_matrix((G.ravel(), (r, c)), shape=(2 * P.nn, 2 * P.nn)).tocsr()
+
+
 def coefficients(P: Problem):
     """(i/omega, c_eps = (eps_i+eps_a)/2, c_mu = (mu_i+mu_a)/2) of eq. global_system."""
     return 1j / P.omega, (P.eps_r + 1.0) / 2.0, (P.mu_r + 1.0) / 2.0
 
 
 def assemble(P: Problem, K1, K2e, K2m, M=None):
-    """Dense Z of eq. global_system from the operator blocks and M."""
+    """Dense Z of eq. global_system from the operator blocks and the mass:
+    the scalar M (interpolated frame only) or, by default, mass_blocks."""
     if M is None:
-        M = mass_matrix(P)
+        M2 = mass_blocks(P).toarray()
+    elif M.shape[0] == P.nn:
+        if P.frame != 0:
+            raise ValueError("the scalar mass matrix only serves the interpolated frame")
+        M2 = np.kron(M.toarray(), np.eye(2))
+    else:
+        M2 = M.toarray()
     iw, ce, cm = coefficients(P)
-    M2 = np.kron(M.toarray(), np.eye(2))
     return np.block([[iw * K1, ce * M2 + K2e], [cm * M2 + K2m, -iw * K1]])
 
 
@@ -87,17 +137,19 @@ def planewave_rhs(P: Problem, khat, pol):
     pol = np.atleast_2d(np.asarray(pol, dtype=np.complex128))
     elem, w, rows = P.qp()
     WJ = w * rows[:, 3]
-    x, s1, s2, N = rows[:, 0:3], rows[:, 13:16], rows[:, 16:19], rows[:, 19:25]
+    x, n, N = rows[:, 0:3], rows[:, 4:7], rows[:, 19:25]
+    S = np.cross(P.basis(), n[:, None, None, :])         # rotated test vectors
     nrhs = khat.shape[0]
     b = np.zeros((4 * P.nn, nrhs), dtype=np.complex128)
     for r in range(nrhs):
         ph = np.exp(1j * P.ka * (x @ khat[r]))
         E = ph[:, None] * pol[r][None, :]
         H = ph[:, None] * np.cross(khat[r], pol[r])[None, :]
-        for a, s in enumerate((s1, s2)):
-            sE = np.einsum("qd,qd->q", s, E)
-            sH = np.einsum("qd,qd->q", s, H)
+        for a in range(2):
             for k in range(6):
+                s = S[:, k, a, :]
+                sE = np.einsum("qd,qd->q", s, E)
+                sH = np.einsum("qd,qd->q", s, H)
                 idx = 2 * P.tri6[elem, k] + a
                 np.add.at(b[:, r], idx, -1.0 * WJ * N[:, k] * sE)
                 np.add.at(b[:, r], 2 * P.nn + idx, 1.0 * WJ * N[:, k] * sH)
@@ -107,14 +159,16 @@ def planewave_rhs(P: Problem, khat, pol):
 def surface_currents(P: Problem, x):
     """j and j_m at the 7 rule points of every element: [nt*7, 3] complex."""
     elem, w, rows = P.qp()
-    t1, t2, N = rows[:, 7:10], rows[:, 10:13], rows[:, 19:25]
+    N = rows[:, 19:25]
+    V = P.basis()
     n2 = 2 * P.nn
     cj, cm = x[:n2], x[n2:]
     j = np.zeros((elem.shape[0], 3), dtype=np.complex128)
     jm = np.zeros_like(j)
     for k in range(6):
         node = P.tri6[elem, k]
-        for b, t in enumerate((t1, t2)):
+        for b in range(2):
+            t = V[:, k, b, :]
             j += (N[:, k] * cj[2 * node + b])[:, None] * t
             jm += (N[:, k] * cm[2 * node + b])[:, None] * t
     return j, jm

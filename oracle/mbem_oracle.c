@@ -217,6 +217,7 @@ void or_nodal_frames_impl(or_mesh *m) {
 /* Everything a kernel evaluation needs at one surface point.           */
 typedef struct {
     double x[3], J, n[3], t[2][3], s[2][3], N[6];
+    int64_t elem;          /* element the point lies in            */
 } or_point;
 
 /*
@@ -229,6 +230,7 @@ static void point_data(const or_mesh *m, int64_t e, double xi, double eta,
                        or_point *P) {
     double X[6][3], a1[3], a2[3], c[3];
     elem_coords(m, e, X);
+    P->elem = e;
     p2_geom((const double(*)[3])X, xi, eta, P->x, a1, a2, P->N);
     cross3(a1, a2, c);
     P->J = norm3(c);
@@ -273,6 +275,11 @@ typedef struct {
                               remainder by the 12-point rule, series
                               truncated after n = 6                    */
     int nterms;            /* highest Taylor term n of the series  */
+    int frame;             /* tangential basis: 0 the interpolated
+                              Gram-Schmidt frame, N_j t_beta(y) (Sec. 3.3,
+                              Sec. 4.1); 1 node-attached tangents,
+                              N_j(y) P(y) t_beta,j with P(y) = I - n n^T
+                              the tangent-plane projector at y          */
 } or_phys;
 
 #define OR_SERIES_RHO 0.5
@@ -456,23 +463,54 @@ static int pair_class(const or_mesh *m, int64_t e, int64_t f, int sh_e[3],
     return n;
 }
 
-/* Accumulate w * N_i(x) N_j(y) kappa_c(x,y) into blk[i][j][c]; `which`
- * selects the full kernels, their singular parts or the remainders.      */
-static void accumulate_k(const or_phys *ph, const or_point *X, const or_point *Y,
-                         double w, int which, cplx blk[6][6][12]) {
+/*
+ * Accumulate the point pair (X, Y) into blk[i][j][c]; `which` selects the
+ * full kernels, their singular parts or the remainders.
+ * frame 0: blk[i][j][c] += w N_i(x) N_j(y) kappa_c(x,y).
+ * frame 1: the basis vector of node k at a point is P t_beta,k, whose
+ * components in the point's orthonormal frame are R_k[beta][gamma] =
+ * t_beta,k . t_gamma (the normal part drops out); the rotated test vector
+ * t_alpha,i x n has the same components on (s_1, s_2).  The kernels are
+ * linear in the test and in the trial vector, so
+ *   blk[i][j][op,a,b] += w N_i N_j sum_{g,d} R_i[a][g] kappa_{op,g,d} R_j[b][d].
+ */
+static void accumulate_k(const or_mesh *m, const or_phys *ph, const or_point *X,
+                         const or_point *Y, double w, int which, cplx blk[6][6][12]) {
     cplx k[12];
     kappa_eval(ph, X, Y, which, k);
     double ww = w * X->J * Y->J;
+    if (ph->frame == 0) {
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) {
+                double s = ww * X->N[i] * Y->N[j];
+                for (int c = 0; c < 12; ++c) blk[i][j][c] += s * k[c];
+            }
+        return;
+    }
+    double RX[6][2][2], RY[6][2][2];
+    for (int q = 0; q < 6; ++q) {
+        int64_t vx = m->tri[6 * X->elem + q], vy = m->tri[6 * Y->elem + q];
+        const double *tx[2] = {m->t1 + 3 * vx, m->t2 + 3 * vx};
+        const double *ty[2] = {m->t1 + 3 * vy, m->t2 + 3 * vy};
+        for (int a = 0; a < 2; ++a)
+            for (int g = 0; g < 2; ++g) {
+                RX[q][a][g] = dot3(tx[a], X->t[g]);
+                RY[q][a][g] = dot3(ty[a], Y->t[g]);
+            }
+    }
     for (int i = 0; i < 6; ++i)
         for (int j = 0; j < 6; ++j) {
             double s = ww * X->N[i] * Y->N[j];
-            for (int c = 0; c < 12; ++c) blk[i][j][c] += s * k[c];
+            for (int op = 0; op < 3; ++op)
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
+                        cplx acc = 0;
+                        for (int g = 0; g < 2; ++g)
+                            for (int d = 0; d < 2; ++d)
+                                acc += RX[i][a][g] * k[4 * op + 2 * g + d] * RY[j][b][d];
+                        blk[i][j][4 * op + 2 * a + b] += s * acc;
+                    }
         }
-}
-
-static void accumulate(const or_phys *ph, const or_point *X, const or_point *Y,
-                       double w, cplx blk[6][6][12]) {
-    accumulate_k(ph, X, Y, w, 0, blk);
 }
 
 /*
@@ -576,7 +614,7 @@ static void pair_block(const or_mesh *m, const or_phys *ph, int64_t e,
         if (q.mode == 0) q.mode = 1;
         for (int p = 0; p < 12; ++p)
             for (int r = 0; r < 12; ++r)
-                accumulate_k(&q, &X[p], &Y[r], w[p] * w[r], cls == 0 ? 0 : 2, blk);
+                accumulate_k(m, &q, &X[p], &Y[r], w[p] * w[r], cls == 0 ? 0 : 2, blk);
         if (cls == 0) return;
     } else if (cls == 0) {
         double xi[7], eta[7], w[7];
@@ -587,7 +625,7 @@ static void pair_block(const or_mesh *m, const or_phys *ph, int64_t e,
             point_data(m, f, xi[q], eta[q], &Y[q]);
         }
         for (int p = 0; p < 7; ++p)
-            for (int q = 0; q < 7; ++q) accumulate(ph, &X[p], &Y[q], w[p] * w[q], blk);
+            for (int q = 0; q < 7; ++q) accumulate_k(m, ph, &X[p], &Y[q], w[p] * w[q], 0, blk);
         return;
     }
     int pe[3], pf[3];
@@ -607,7 +645,7 @@ static void pair_block(const or_mesh *m, const or_phys *ph, int64_t e,
                         or_point X, Y;
                         point_data(m, e, x1, y1, &X);
                         point_data(m, f, x2, y2, &Y);
-                        accumulate_k(ph, &X, &Y, jac * gw[a] * gw[b] * gw[c] * gw[d],
+                        accumulate_k(m, ph, &X, &Y, jac * gw[a] * gw[b] * gw[c] * gw[d],
                                      ph->variant == 1 ? 1 : 0, blk);
                     }
 }
@@ -616,7 +654,7 @@ static void pair_block(const or_mesh *m, const or_phys *ph, int64_t e,
 /* exported entry points (ctypes)                                       */
 /* ------------------------------------------------------------------ */
 
-/* phys[] = {k0, Re eps_r, Im eps_r, Re mu_r, Im mu_r, variant}           */
+/* phys[] = {k0, Re eps_r, Im eps_r, Re mu_r, Im mu_r, variant, frame}    */
 static or_phys make_phys(const double *phys, int nss, int mode) {
     or_phys ph;
     cplx er = phys[1] + I * phys[2], mr = phys[3] + I * phys[4];
@@ -628,6 +666,7 @@ static or_phys make_phys(const double *phys, int nss, int mode) {
     ph.nss = nss; ph.mode = mode;
     ph.variant = (int)phys[5];
     ph.nterms = ph.variant == 1 ? 6 : OR_SERIES_TERMS;
+    ph.frame = (int)phys[6];
     return ph;
 }
 

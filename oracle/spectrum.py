@@ -16,7 +16,7 @@ from . import core, galerkin
 from .galerkin import Problem
 
 
-def spectrum(xyz, tri6, k0s, eps_rs, khat, pol, mu_rs=None, ntheta=None, variant=0):
+def spectrum(xyz, tri6, k0s, eps_rs, khat, pol, mu_rs=None, ntheta=None, variant=0, frame=0):
     """(C_ext, C_sca, C_abs)[npts, 3] for unit-amplitude incidence (khat [3],
     pol [3]) at every point; ntheta as galerkin.cross_sections (None: the
     default for each point's wavenumber)."""
@@ -29,9 +29,9 @@ def spectrum(xyz, tri6, k0s, eps_rs, khat, pol, mu_rs=None, ntheta=None, variant
     pol = np.asarray(pol, dtype=np.complex128)
     out = np.zeros((k0s.shape[0], 3))
     for i, (k0, eps, mu) in enumerate(zip(k0s, eps_rs, mu_rs)):
-        P = Problem(xyz, tri6, k0, eps, mu, variant=variant)
+        P = Problem(xyz, tri6, k0, eps, mu, variant=variant, frame=frame)
         K = core.fill(P.xyz, P.tri6, P.phys, nss=P.nss)
-        Z = galerkin.assemble(P, K[0], K[1], K[2], galerkin.mass_matrix(P))
+        Z = galerkin.assemble(P, K[0], K[1], K[2])
         x = np.linalg.solve(Z, galerkin.planewave_rhs(P, khat, pol))
         out[i] = galerkin.cross_sections(P, np.ravel(x), khat, pol, ntheta)
     return out
