@@ -82,6 +82,7 @@ typedef struct {
                                    this are computed in FP64; <= 0 selects
                                    1.89 / sqrt|k_a^2 - k_i^2|                */
     int32_t quadrature;         /* MBEM_QUAD_DEFAULT or MBEM_QUAD_PAPER      */
+    int32_t frame;              /* MBEM_FRAME_INTERPOLATED or MBEM_FRAME_NODAL */
 } mbem_params;
 
 /* Quadrature of the operator blocks.
@@ -95,6 +96,24 @@ typedef struct {
  *   on the same pair with the Taylor series truncated after n = 6.  Fill and
  *   solve only: mbem_fill_deps and mbem_grad_sigma_ext reject it.          */
 enum { MBEM_QUAD_DEFAULT = 0, MBEM_QUAD_PAPER = 1 };
+
+/* Tangential basis.
+ * MBEM_FRAME_INTERPOLATED: the basis function of node j, component beta, is
+ *   N_j(y) t_beta(y) with t_beta(y) the continuous frame of Sec. 3.3 (nodal
+ *   triads of Sec. 3.2 interpolated, projected on the tangent plane at y and
+ *   Gram-Schmidt orthonormalised); test functions alike (Sec. 4.1).  Where a
+ *   triangle's nodes took different reference axes (Sec. 3.2) this frame
+ *   turns fast inside the triangle, and far fields converge at about O(h).
+ * MBEM_FRAME_NODAL: node-attached tangents, N_j(y) P(y) t_beta,j with
+ *   t_beta,j the node's own triad tangent and P(y) = I - n(y) n(y)^T; the
+ *   rotated test vector is t_alpha,i x n(x).  Same kernels (Sec. 4), same
+ *   unknown layout; the mass matrix couples alpha and beta.  Its span does
+ *   not depend on the reference-axis choice and far fields converge at high
+ *   order.  With the default quadrature only; mbem_fill_compressed,
+ *   mbem_fill_deps and mbem_grad_sigma_ext reject it.
+ * Post-processing calls (right-hand side, far field, cross sections, far-
+ * field functional) take the same value as the fill of the solution.      */
+enum { MBEM_FRAME_INTERPOLATED = 0, MBEM_FRAME_NODAL = 1 };
 
 typedef struct {
     double tol;          /* relative residual target |b - Z x| / |b|        */

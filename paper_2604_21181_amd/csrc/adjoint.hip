@@ -18,16 +18,18 @@ namespace mbem {
 // One thread per quadrature point, added into g with atomics (each node
 // receives a few dozen contributions).
 __global__ void k_ff_functional(int64_t nt, int64_t n2, const double *__restrict__ qp,
-                                const int32_t *__restrict__ tri, dvec3 r, cx<double> e0, cx<double> e1,
-                                cx<double> e2, double ka, double2 *__restrict__ g) {
+                                const int32_t *__restrict__ tri, const double *__restrict__ frames, int frame,
+                                dvec3 r, cx<double> e0, cx<double> e1, cx<double> e2, double ka,
+                                double2 *__restrict__ g) {
     const int64_t nq = nt * kQP;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nq) return;
     const int64_t el = i / kQP;
     const int q = (int)(i % kQP);
     const dvec3 y = {qp[QX * nq + i], qp[(QX + 1) * nq + i], qp[(QX + 2) * nq + i]};
-    const dvec3 t[2] = {{qp[QT1 * nq + i], qp[(QT1 + 1) * nq + i], qp[(QT1 + 2) * nq + i]},
-                        {qp[QT2 * nq + i], qp[(QT2 + 1) * nq + i], qp[(QT2 + 2) * nq + i]}};
+    const dvec3 t0[2] = {{qp[QT1 * nq + i], qp[(QT1 + 1) * nq + i], qp[(QT1 + 2) * nq + i]},
+                         {qp[QT2 * nq + i], qp[(QT2 + 1) * nq + i], qp[(QT2 + 2) * nq + i]}};
+    const dvec3 n = {qp[QN * nq + i], qp[(QN + 1) * nq + i], qp[(QN + 2) * nq + i]};
     const double W = qp[QW * nq + i];
     double sn, cs;
     sincos(-ka * dot(r, y), &sn, &cs);
@@ -41,11 +43,13 @@ __global__ void k_ff_functional(int64_t nt, int64_t n2, const double *__restrict
     rule7(q, xi, eta, w);
     p2_shape(xi, eta, N, d1, d2);
     for (int b = 0; b < 2; ++b) {
-        const cx<double> tj = t[b].x * ep[0] + t[b].y * ep[1] + t[b].z * ep[2];
-        const cx<double> tm = t[b].x * ex[0] + t[b].y * ex[1] + t[b].z * ex[2];
-        const cx<double> vj = pre * tj, vm = pre * tm;
         for (int k = 0; k < 6; ++k) {
-            const int64_t row = 2 * (int64_t)tri[6 * el + k] + b;
+            const int64_t node = tri[6 * el + k];
+            const dvec3 t = frame == 0 ? t0[b] : project_tangent(nodal_tangent(frames, node, b), n);
+            const cx<double> tj = t.x * ep[0] + t.y * ep[1] + t.z * ep[2];
+            const cx<double> tm = t.x * ex[0] + t.y * ex[1] + t.z * ex[2];
+            const cx<double> vj = pre * tj, vm = pre * tm;
+            const int64_t row = 2 * node + b;
             const double f = W * N[k];
             unsafeAtomicAdd(&g[row].x, f * vj.re);
             unsafeAtomicAdd(&g[row].y, f * vj.im);
@@ -61,7 +65,7 @@ int ff_functional_run(const mbem_mesh *m, const mbem_params *p, const double *rh
     MBEM_HIP(hipMemsetAsync(g, 0, sizeof(double2) * 2 * n2, s));
     const int64_t nq = m->nt * kQP;
     hipLaunchKernelGGL(k_ff_functional, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, m->nt, n2, m->d_qp,
-                       m->d_tri, dvec3{rhat[0], rhat[1], rhat[2]}, cx<double>{e[0].x, e[0].y},
+                       m->d_tri, m->d_frames, p->frame, dvec3{rhat[0], rhat[1], rhat[2]}, cx<double>{e[0].x, e[0].y},
                        cx<double>{e[1].x, e[1].y}, cx<double>{e[2].x, e[2].y}, p->k0, g);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
@@ -104,7 +108,8 @@ __global__ __launch_bounds__(256) void k_gemvt_part(int64_t n2, const TS *K1, co
 struct TCoef { double2 iw, ce, cm; };
 __device__ inline double2 zm(double2 a, double2 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
-// y = Z^T lambda from the summed partials and the (symmetric) mass matrix:
+// y = Z^T lambda from the summed partials and the mass matrix (symmetric as
+// a matrix of unknowns, so M^T l = M l):
 //   y_j = (i/w) K1^T l1 + K2mu^T l2 + c_mu M l2
 //   y_m = K2eps^T l1 + c_eps M l1 - (i/w) K1^T l2
 // A workgroup takes 64 rows; its four wavefronts sum every fourth chunk of
@@ -138,10 +143,10 @@ __global__ __launch_bounds__(256) void k_combine_t(int64_t n2, int nch, const do
     const int al = (int)(r % 2);
     double2 M1 = {0, 0}, M2 = {0, 0};
     for (int32_t s = mptr[i]; s < mptr[i + 1]; ++s) {
-        const int64_t col = 2 * (int64_t)mcol[s] + al;
-        const double v = mval[s];
-        M1.x += v * l1[col].x; M1.y += v * l1[col].y;
-        M2.x += v * l2[col].x; M2.y += v * l2[col].y;
+        const int64_t col = 2 * (int64_t)mcol[s];
+        const double v0 = mval[4 * s + 2 * al], v1 = mval[4 * s + 2 * al + 1];
+        M1.x += v0 * l1[col].x + v1 * l1[col + 1].x; M1.y += v0 * l1[col].y + v1 * l1[col + 1].y;
+        M2.x += v0 * l2[col].x + v1 * l2[col + 1].x; M2.y += v0 * l2[col].y + v1 * l2[col + 1].y;
     }
     const double2 a = zm(c.iw, t[0]), b = zm(c.iw, t[1]), cm = zm(c.cm, M2), ce = zm(c.ce, M1);
     y[r] = {a.x + t[3].x + cm.x, a.y + t[3].y + cm.y};

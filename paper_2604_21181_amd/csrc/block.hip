@@ -225,11 +225,12 @@ __global__ void k_block_combine(int64_t n2, int ncol, const TT *T, const int32_t
     const int al = (int)(r % 2);
     double2 Mj = {0, 0}, Mm = {0, 0};
     for (int32_t s = mptr[i]; s < mptr[i + 1]; ++s) {
-        const int64_t col = 2 * (int64_t)mcol[s] + al;
-        const double v = mval[s];
-        const double2 xj = ld2(x, col), xm = ld2(x, n2 + col);
-        Mj.x += v * xj.x; Mj.y += v * xj.y;
-        Mm.x += v * xm.x; Mm.y += v * xm.y;
+        const int64_t col = 2 * (int64_t)mcol[s];
+        const double v0 = mval[4 * s + 2 * al], v1 = mval[4 * s + 2 * al + 1];
+        const double2 xj0 = ld2(x, col), xm0 = ld2(x, n2 + col);
+        const double2 xj1 = ld2(x, col + 1), xm1 = ld2(x, n2 + col + 1);
+        Mj.x += v0 * xj0.x + v1 * xj1.x; Mj.y += v0 * xj0.y + v1 * xj1.y;
+        Mm.x += v0 * xm0.x + v1 * xm1.x; Mm.y += v0 * xm0.y + v1 * xm1.y;
     }
     const TT *T1 = T, *T2 = T + 2 * ncol * n2, *T3 = T2 + ncol * n2;
     const double2 a = ld2(T1, (2 * c) * n2 + r), bm = ld2(T1, (2 * c + 1) * n2 + r);

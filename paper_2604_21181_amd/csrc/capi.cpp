@@ -317,6 +317,15 @@ struct CsWork {
 // C_ext by the optical theorem, C_sca by the product rule on the unit sphere
 // (Gauss-Legendre in cos theta x trapezoid in phi), C_abs by the surface
 // integral of the currents; ntheta <= 0 picks 2 k0 a_max + 20.
+// Post-processing reads the basis through p->frame: only the two frames
+static int check_frame(const mbem_params *p) {
+    if (p->frame != MBEM_FRAME_INTERPOLATED && p->frame != MBEM_FRAME_NODAL) {
+        set_error("unknown tangential frame");
+        return MBEM_EINVAL;
+    }
+    return MBEM_OK;
+}
+
 static int cross_sections_impl(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const double2 *x,
                                const double *khat, const mbem_c128 *pol, int32_t ntheta, double *out,
                                CsWork &cw) {
@@ -342,7 +351,7 @@ static int cross_sections_impl(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_
     MBEM_HIP(hipMemcpyAsync(cw.w, w.data(), sizeof(double) * ndir, hipMemcpyHostToDevice, s));
     MBEM_TRY(farfield_run(mesh, p, x, 1, cw.dirs, ndir, cw.F, s));
     MBEM_TRY(weighted_norm_run(ndir, cw.F, cw.w, cw.acc, s));
-    MBEM_TRY(absorbed_run(mesh, x, cw.acc + 1, s));
+    MBEM_TRY(absorbed_run(mesh, p, x, cw.acc + 1, s));
     double acc[2];
     double2 Ff[3];
     MBEM_HIP(hipMemcpyAsync(acc, cw.acc, sizeof(acc), hipMemcpyDeviceToHost, s));
@@ -484,6 +493,14 @@ static int op_create(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p,
         set_error("unknown quadrature scheme");
         return MBEM_EINVAL;
     }
+    if (p->frame != MBEM_FRAME_INTERPOLATED && p->frame != MBEM_FRAME_NODAL) {
+        set_error("unknown tangential frame");
+        return MBEM_EINVAL;
+    }
+    if (p->frame == MBEM_FRAME_NODAL && p->quadrature != MBEM_QUAD_DEFAULT) {
+        set_error("the node-attached frame is built for the default quadrature only");
+        return MBEM_EINVAL;
+    }
     MBEM_TRY(set_device(ctx));
     mbem_op *op = new (std::nothrow) mbem_op;
     if (!op) { set_error("host allocation"); return MBEM_ENOMEM; }
@@ -498,7 +515,7 @@ static int op_create(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p,
         hipError_t e = hipMalloc(&op->K[o], esz * op->n2 * op->n2);
         if (e != hipSuccess) { set_error(std::string("operator allocation: ") + hipGetErrorString(e)); st = MBEM_ENOMEM; }
     }
-    if (st == MBEM_OK) st = dalloc(&op->d_mval, mesh->m_col.size());
+    if (st == MBEM_OK) st = dalloc(&op->d_mval, 4 * mesh->m_col.size());   // 2 x 2 per node pair
     if (st != MBEM_OK) { op_free_device(op); delete op; return st; }
     *out = op;
     return MBEM_OK;
@@ -537,8 +554,9 @@ int mbem_fill(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_o
 int mbem_fill_compressed(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const mbem_blr_opts *o,
                          mbem_op **out, mbem_stats *stats, mbem_blr_stats *bstats) {
     if (!mesh || !p || !o || !out) { set_error("null argument"); return MBEM_EINVAL; }
-    if (p->precision != MBEM_FP64 || p->quadrature != MBEM_QUAD_DEFAULT) {
-        set_error("the block low-rank operator is built for FP64 and the default quadrature");
+    if (p->precision != MBEM_FP64 || p->quadrature != MBEM_QUAD_DEFAULT || p->frame != MBEM_FRAME_INTERPOLATED) {
+        set_error("the block low-rank operator is built for FP64, the default quadrature and the interpolated "
+                  "frame");
         return MBEM_EINVAL;
     }
     if (o->cluster < 1 || o->cluster > 2048 || !(o->eta > 0) || !(o->eps > 0 && o->eps < 1) || o->rmax < 1 ||
@@ -621,6 +639,7 @@ int mbem_precond_apply(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *v, mbe
 int mbem_rhs_planewave(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const double *khat,
                        const mbem_c128 *pol, int32_t nrhs, mbem_c128 *b) {
     if (!mesh || !p || !khat || !pol || !b || nrhs < 1) { set_error("bad argument"); return MBEM_EINVAL; }
+    MBEM_TRY(check_frame(p));
     MBEM_TRY(set_device(ctx));
     double *dk = nullptr;
     double2 *dp = nullptr;
@@ -732,8 +751,8 @@ int mbem_solve_adjoint(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *g, int32_t n
 
 int mbem_fill_deps(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_op **out, mbem_stats *stats) {
     if (!p) { set_error("null argument"); return MBEM_EINVAL; }
-    if (p->quadrature != MBEM_QUAD_DEFAULT) {
-        set_error("the eps derivative is built for the default quadrature only");
+    if (p->quadrature != MBEM_QUAD_DEFAULT || p->frame != MBEM_FRAME_INTERPOLATED) {
+        set_error("the eps derivative is built for the default quadrature and the interpolated frame only");
         return MBEM_EINVAL;
     }
     mbem_params q = *p;
@@ -751,6 +770,7 @@ int mbem_fill_deps(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, m
 int mbem_farfield_functional(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const double *rhat,
                              const mbem_c128 *e, mbem_c128 *g) {
     if (!mesh || !p || !rhat || !e || !g) { set_error("null argument"); return MBEM_EINVAL; }
+    MBEM_TRY(check_frame(p));
     MBEM_TRY(set_device(ctx));
     int st = ff_functional_run(mesh, p, rhat, (const double2 *)e, (double2 *)g, ctx->stream);
     (void)hipStreamSynchronize(ctx->stream);
@@ -763,8 +783,9 @@ int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh, const
                         mbem_stats *stats) {
     if (!op || !mesh || !p || !x || !khat || !pol || !o || !out) { set_error("null argument"); return MBEM_EINVAL; }
     if (op->blr) { set_error("the gradient needs a dense operator"); return MBEM_EINVAL; }
-    if (p->quadrature != MBEM_QUAD_DEFAULT || op->p.quadrature != MBEM_QUAD_DEFAULT) {
-        set_error("the gradient is built for the default quadrature only");
+    if (p->quadrature != MBEM_QUAD_DEFAULT || op->p.quadrature != MBEM_QUAD_DEFAULT ||
+        p->frame != MBEM_FRAME_INTERPOLATED || op->p.frame != MBEM_FRAME_INTERPOLATED) {
+        set_error("the gradient is built for the default quadrature and the interpolated frame only");
         return MBEM_EINVAL;
     }
     MBEM_TRY(set_device(ctx));
@@ -901,6 +922,7 @@ int mbem_cgemm(mbem_ctx *ctx, int32_t dtype, int32_t conj_a, int64_t M, int64_t 
 int mbem_farfield(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const mbem_c128 *x,
                   int32_t nrhs, const double *rhat, int64_t ndir, mbem_c128 *F) {
     if (!mesh || !p || !x || !rhat || !F || nrhs < 1 || ndir < 1) { set_error("bad argument"); return MBEM_EINVAL; }
+    MBEM_TRY(check_frame(p));
     MBEM_TRY(set_device(ctx));
     int st = farfield_run(mesh, p, (const double2 *)x, nrhs, rhat, ndir, (double2 *)F, ctx->stream);
     (void)hipStreamSynchronize(ctx->stream);
@@ -993,6 +1015,7 @@ int mbem_spectrum(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, in
 int mbem_cross_sections(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const mbem_c128 *x,
                         const double *khat, const mbem_c128 *pol, int32_t ntheta, double *out) {
     if (!mesh || !p || !x || !khat || !pol || !out) { set_error("null argument"); return MBEM_EINVAL; }
+    MBEM_TRY(check_frame(p));
     MBEM_TRY(set_device(ctx));
     CsWork w;
     return cross_sections_impl(ctx, mesh, p, (const double2 *)x, khat, pol, ntheta, out, w);

@@ -57,6 +57,7 @@ struct RegArgs {
     const T *qp;            // [kQPF][nt*7]
     const double *qp64;     // FP64 table (near pairs of the mixed path)
     const int32_t *tri;
+    const double *frames;   // [nn][9] nodal triads (node-attached tangents)
     const int32_t *chunks;  // kChunkRec ints per trial chunk
     const double *einfo;    // [nt][4]
     double near_r;
@@ -144,11 +145,21 @@ __host__ __device__ inline void contract7(const cx<T> v[7], cx<T> out[6]) {
 // the stride (= 1 mod 16) spreads consecutive components over the banks
 constexpr int kR1Stride = 209;
 
-template <typename T, typename TS, bool DK = false>
+// NODAL: node-attached tangents.  The kernel values stay in the point
+// frames; the trial contraction takes the 2 x 2 components of each trial
+// node's tangents in the frame of each trial point, the test contraction
+// those of each test node in the frames of the test points (the kernels are
+// linear in the test and in the trial vector).
+template <typename T, typename TS, bool DK = false, bool NODAL = false>
 __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     // point-pair kernel values; the trial-side contraction is later written
     // over them in place
     __shared__ cx<T> s_r1[12 * kR1Stride];
+    // NODAL: s_ra[p][i][alpha][gamma] = N_i(x_p) t_alpha,i . t_gamma(x_p) of
+    // the test triangle, s_rb[fs][q][j][beta][delta] likewise for the trial
+    // triangles of the chunk
+    __shared__ T s_ra[NODAL ? 168 : 1];
+    __shared__ T s_rb[NODAL ? kChunk * 168 : 1];
     // prefetched destination values.  FP32: in LDS by direct global-to-LDS
     // loads, plane (i, re / im) (i: row of the test triangle), item it.
     // FP64: in registers (pre), which keeps the LDS of a workgroup low enough
@@ -192,9 +203,24 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
         }
         s_act[tid] = kind;
     }
+    const int64_t nq = a.nt * kQP;
+    if constexpr (NODAL) {
+        for (int it = tid; it < (kChunk + 1) * 168; it += blockDim.x) {
+            const int side = it / 168, r = it % 168;          // side 0: test, 1 + fs: trial
+            const int pq = r / 24, j = (r / 4) % 6, b = (r / 2) % 2, g = r % 2;
+            const int64_t el = side == 0 ? e : ch * kChunk + side - 1;
+            T v = 0;
+            if (el < a.nt) {
+                const double *t = a.frames + 9 * (int64_t)a.tri[6 * el + j] + 3 + 3 * b;
+                const vec3<T> tg = qload(a.qp, nq, g ? QT2 : QT1, el * kQP + pq);
+                v = (T)n7(pq, j) * ((T)t[0] * tg.x + (T)t[1] * tg.y + (T)t[2] * tg.z);
+            }
+            if (side == 0) s_ra[r] = v;
+            else s_rb[(side - 1) * 168 + r] = v;
+        }
+    }
     // point data of this lane's pair, loaded before the barrier so that the
     // loads overlap those of the chunk record
-    const int64_t nq = a.nt * kQP;
     const int fsl = tid / 49, pl = (tid % 49) / 7, ql = tid % 7;
     const int64_t ix = e * kQP + pl, iy = (ch * kChunk + fsl) * kQP + ql;
     vec3<T> x = {0, 0, 0}, n = {0, 0, 0}, y = {0, 0, 0};
@@ -287,15 +313,41 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     __syncthreads();
     // B: trial side per triangle, in place: Tf[c][fs][p][j] = sum_q N_j(q) k
     // over the 7 entries (c, fs, p, q = 0..6) it replaces (j = 0..5)
-    for (int it = tid; it < 12 * kChunk * 7; it += blockDim.x) {
-        const int c = it / (kChunk * 7), fp = it % (kChunk * 7);   // fp = 7 fs + p
-        cx<T> *row = s_r1 + c * kR1Stride + 7 * fp;
-        cx<T> kv[7], tf[6];
+    if constexpr (!NODAL) {
+        for (int it = tid; it < 12 * kChunk * 7; it += blockDim.x) {
+            const int c = it / (kChunk * 7), fp = it % (kChunk * 7);   // fp = 7 fs + p
+            cx<T> *row = s_r1 + c * kR1Stride + 7 * fp;
+            cx<T> kv[7], tf[6];
 #pragma unroll
-        for (int q = 0; q < 7; ++q) kv[q] = row[q];
-        contract7(kv, tf);
+            for (int q = 0; q < 7; ++q) kv[q] = row[q];
+            contract7(kv, tf);
 #pragma unroll
-        for (int j = 0; j < 6; ++j) row[j] = tf[j];
+            for (int j = 0; j < 6; ++j) row[j] = tf[j];
+        }
+    } else {
+        // the two delta components of (op, gamma) become the two beta ones:
+        // Tf[op,gamma,beta][fs][p][j] = sum_q sum_delta s_rb[fs][q][j][beta][delta] k[op,gamma,delta]
+        for (int it = tid; it < 6 * kChunk * 7; it += blockDim.x) {
+            const int og = it / (kChunk * 7), fp = it % (kChunk * 7);   // og = 2 op + gamma
+            cx<T> *r0 = s_r1 + (2 * og) * kR1Stride + 7 * fp, *r1 = r0 + kR1Stride;
+            const T *rb = s_rb + (fp / 7) * 168;
+            cx<T> k0[7], k1[7], o0[6], o1[6];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) { k0[q] = r0[q]; k1[q] = r1[q]; }
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                o0[j] = cx<T>{0, 0};
+                o1[j] = cx<T>{0, 0};
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    const T *w = rb + (q * 6 + j) * 4;
+                    o0[j] = o0[j] + w[0] * k0[q] + w[1] * k1[q];
+                    o1[j] = o1[j] + w[2] * k0[q] + w[3] * k1[q];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 6; ++j) { r0[j] = o0[j]; r1[j] = o1[j]; }
+        }
     }
     __builtin_amdgcn_s_waitcnt(0);             // prefetched destinations have landed (FP32)
     __syncthreads();
@@ -309,20 +361,46 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
         const int g = (int)(((float)it + 0.5f) * inv_rowlen);    // g = 2 op + alpha
         const int rem = it - g * rowlen;
         const int sl = rem >> 1, be = rem & 1, op = g >> 1;
-        const int c = 2 * g + be;                                // 4 op + 2 alpha + beta
-        cx<T> tv[7];
-#pragma unroll
-        for (int p = 0; p < 7; ++p) tv[p] = cx<T>{0, 0};
         const int u1 = s_rec[26 + sl];
-        for (int u = s_rec[25 + sl]; u < u1; ++u) {
-            const int fl = s_rec[50 + u];
-            const cx<T> *src = s_r1 + c * kR1Stride + (fl >> 3) * 49 + (fl & 7);
+        cx<T> out[6];
+        if constexpr (!NODAL) {
+            const int c = 2 * g + be;                            // 4 op + 2 alpha + beta
+            cx<T> tv[7];
 #pragma unroll
-            for (int p = 0; p < 7; ++p) tv[p] = tv[p] + src[7 * p];
+            for (int p = 0; p < 7; ++p) tv[p] = cx<T>{0, 0};
+            for (int u = s_rec[25 + sl]; u < u1; ++u) {
+                const int fl = s_rec[50 + u];
+                const cx<T> *src = s_r1 + c * kR1Stride + (fl >> 3) * 49 + (fl & 7);
+#pragma unroll
+                for (int p = 0; p < 7; ++p) tv[p] = tv[p] + src[7 * p];
+            }
+            contract7(tv, out);
+        } else {
+            // components (op, gamma, beta) for gamma = 0, 1 at 4 op + beta and
+            // 4 op + 2 + beta; out[i] = sum_p sum_gamma s_ra[p][i][alpha][gamma] Ts[gamma][p]
+            const int al = g & 1;
+            const int c0 = 4 * op + be;
+            cx<T> tv0[7], tv1[7];
+#pragma unroll
+            for (int p = 0; p < 7; ++p) { tv0[p] = cx<T>{0, 0}; tv1[p] = cx<T>{0, 0}; }
+            for (int u = s_rec[25 + sl]; u < u1; ++u) {
+                const int fl = s_rec[50 + u];
+                const cx<T> *src0 = s_r1 + c0 * kR1Stride + (fl >> 3) * 49 + (fl & 7);
+                const cx<T> *src1 = src0 + 2 * kR1Stride;
+#pragma unroll
+                for (int p = 0; p < 7; ++p) { tv0[p] = tv0[p] + src0[7 * p]; tv1[p] = tv1[p] + src1[7 * p]; }
+            }
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                out[i] = cx<T>{0, 0};
+#pragma unroll
+                for (int p = 0; p < 7; ++p) {
+                    const T *w = s_ra + (p * 6 + i) * 4 + 2 * al;
+                    out[i] = out[i] + w[0] * tv0[p] + w[1] * tv1[p];
+                }
+            }
         }
         TS *Z = zblock(a.Z, op) + 2 * (2 * (int64_t)s_rec[1 + sl] + be);
-        cx<T> out[6];
-        contract7(tv, out);
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
             const cx<T> acc = out[i];
@@ -366,14 +444,27 @@ struct SsqArgs {
 constexpr int kSsqThreads = 128;
 constexpr int kStreams = 5;
 constexpr int kPtStride = 37;   // 24 kernel reals, N_i(x), N_j(y); padded
+// node-attached tangents: 24 kernel reals, then per test node i the 2 x 2
+// N_i(x) t_alpha,i . t_gamma(x) and per trial node j N_j(y) t_beta,j . t_delta(y)
+constexpr int kPtStrideNodal = 73;
 
-template <typename TS, bool DK = false>
+template <typename TS, bool DK = false, bool NODAL = false>
 __global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_ssq(SsqArgs<TS> a) {
-    __shared__ double s_pt[kSsqThreads * kPtStride];
+    constexpr int kStride = NODAL ? kPtStrideNodal : kPtStride;
+    __shared__ double s_pt[kSsqThreads * kStride];
     static_assert(kStreams * 36 * 24 <= kSsqThreads * kPtStride, "reduction buffer");
+    // NODAL: the tangents of the two triangles' nodes, s_tn[side][k][b][3]
+    __shared__ double s_tn[NODAL ? 72 : 1];
     const int tid = threadIdx.x;
     const int64_t pid = blockIdx.x;
     const int32_t e = a.pairs[4 * pid], f = a.pairs[4 * pid + 1];
+    if constexpr (NODAL) {
+        if (tid < 72) {
+            const int side = tid / 36, r = tid % 36, k = r / 6, b = (r / 3) % 2, d = r % 3;
+            s_tn[tid] = a.frames[9 * (int64_t)a.tri[6 * (side ? f : e) + k] + 3 + 3 * b + d];
+        }
+        __syncthreads();
+    }
     const int cls = a.pairs[4 * pid + 2], code = a.pairs[4 * pid + 3];
     const int n = a.order, n4 = n * n * n * n;
     const int nreg = cls == 3 ? 6 : (cls == 2 ? 5 : 2);
@@ -385,7 +476,7 @@ __global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 
     for (int k = 0; k < 36; ++k) acc[k] = 0.0;
     for (int base = 0; base < npts; base += kSsqThreads) {
         const int idx = base + tid;
-        double *pt = s_pt + tid * kPtStride;
+        double *pt = s_pt + tid * kStride;
         if (idx < npts) {
             const int r = idx / n4;
             int g = idx % n4;
@@ -407,25 +498,66 @@ __global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 
             kappa12<double, DK>(*a.K, X.x, X.n, ta, sa, Y.x, tb, wg * X.J * Y.J, k);
 #pragma unroll
             for (int q = 0; q < 12; ++q) { pt[2 * q] = k[q].re; pt[2 * q + 1] = k[q].im; }
+            if constexpr (!NODAL) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) { pt[24 + q] = X.N[q]; pt[30 + q] = Y.N[q]; }
+                for (int q = 0; q < 6; ++q) { pt[24 + q] = X.N[q]; pt[30 + q] = Y.N[q]; }
+            } else {
+                const dvec3 tx[2] = {X.t1, X.t2}, ty[2] = {Y.t1, Y.t2};
+#pragma unroll
+                for (int q = 0; q < 6; ++q)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const double *ue = s_tn + 6 * q + 3 * b, *uf = s_tn + 36 + 6 * q + 3 * b;
+                        const dvec3 te = {ue[0], ue[1], ue[2]}, tf = {uf[0], uf[1], uf[2]};
+#pragma unroll
+                        for (int g = 0; g < 2; ++g) {
+                            pt[24 + 4 * q + 2 * b + g] = X.N[q] * dot(te, tx[g]);
+                            pt[48 + 4 * q + 2 * b + g] = Y.N[q] * dot(tf, ty[g]);
+                        }
+                    }
+            }
         } else {
 #pragma unroll
-            for (int q = 0; q < 36; ++q) pt[q] = 0.0;
+            for (int q = 0; q < (NODAL ? 72 : 36); ++q) pt[q] = 0.0;
         }
         __syncthreads();
         if (consumer) {
-            for (int r = stream; r < kSsqThreads; r += kStreams) {
-                const double *row = s_pt + r * kPtStride;
-                const double kv = row[comp];
-                double u[6];
+            if constexpr (!NODAL) {
+                for (int r = stream; r < kSsqThreads; r += kStreams) {
+                    const double *row = s_pt + r * kStride;
+                    const double kv = row[comp];
+                    double u[6];
 #pragma unroll
-                for (int j = 0; j < 6; ++j) u[j] = row[30 + j] * kv;
+                    for (int j = 0; j < 6; ++j) u[j] = row[30 + j] * kv;
 #pragma unroll
-                for (int i = 0; i < 6; ++i) {
-                    const double nx = row[24 + i];
+                    for (int i = 0; i < 6; ++i) {
+                        const double nx = row[24 + i];
 #pragma unroll
-                    for (int j = 0; j < 6; ++j) acc[6 * i + j] += nx * u[j];
+                        for (int j = 0; j < 6; ++j) acc[6 * i + j] += nx * u[j];
+                    }
+                }
+            } else {
+                // lane (c = 4 op + 2 alpha + beta, re / im): acc[i][j] +=
+                // sum_{gamma,delta} A_i[alpha][gamma] B_j[beta][delta] k[op,gamma,delta]
+                const int c = comp >> 1, ri = comp & 1;
+                const int op = c >> 2, al = (c >> 1) & 1, be = c & 1;
+                for (int r = stream; r < kSsqThreads; r += kStreams) {
+                    const double *row = s_pt + r * kStride;
+                    const double k00 = row[2 * (4 * op) + ri], k01 = row[2 * (4 * op + 1) + ri];
+                    const double k10 = row[2 * (4 * op + 2) + ri], k11 = row[2 * (4 * op + 3) + ri];
+                    double u0[6], u1[6];
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) {
+                        const double b0 = row[48 + 4 * j + 2 * be], b1 = row[48 + 4 * j + 2 * be + 1];
+                        u0[j] = b0 * k00 + b1 * k01;
+                        u1[j] = b0 * k10 + b1 * k11;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) {
+                        const double a0 = row[24 + 4 * i + 2 * al], a1 = row[24 + 4 * i + 2 * al + 1];
+#pragma unroll
+                        for (int j = 0; j < 6; ++j) acc[6 * i + j] += a0 * u0[j] + a1 * u1[j];
+                    }
                 }
             }
         }
@@ -759,23 +891,48 @@ void k_ssq_paper(SsqArgs<TS> a) {
 }
 
 // ---------------------------------------------------------- mass ---
-// Element mass blocks int N_k N_l on the 7-point rule, added to the node
-// CSR values through the precomputed slot map.
-__global__ void k_mass(int64_t nt, const double *__restrict__ qp,
-                       const int32_t *__restrict__ slot, double *__restrict__ mval) {
+// Element mass blocks on the 7-point rule, added to the node CSR values
+// through the precomputed slot map; a node pair holds a 2 x 2 block, value
+// (a, b) at mval[4 slot + 2 a + b].  Interpolated frame: int N_k N_l delta_ab
+// (the frame is orthonormal at every point); node-attached tangents:
+// int N_k N_l (P t_a,k) . (P t_b,l).
+__global__ void k_mass(int64_t nt, const double *__restrict__ qp, const int32_t *__restrict__ tri,
+                       const double *__restrict__ frames, int frame, const int32_t *__restrict__ slot,
+                       double *__restrict__ mval) {
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (id >= nt * 36) return;
     const int64_t e = id / 36;
     const int k = (int)(id % 36) / 6, l = (int)(id % 6);
     const int64_t nq = nt * kQP;
-    double s = 0.0;
+    const int64_t vk = tri[6 * e + k], vl = tri[6 * e + l];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int q = 0; q < kQP; ++q) {
         double xi, eta, w, N[6], d1[6], d2[6];
         rule7(q, xi, eta, w);
         p2_shape(xi, eta, N, d1, d2);
-        s += qp[QW * nq + e * kQP + q] * N[k] * N[l];
+        const int64_t i = e * kQP + q;
+        const double wn = qp[QW * nq + i] * N[k] * N[l];
+        if (frame == 0) {
+            s[0] += wn;
+        } else {
+            const dvec3 n = {qp[QN * nq + i], qp[(QN + 1) * nq + i], qp[(QN + 2) * nq + i]};
+            const dvec3 tk[2] = {project_tangent(nodal_tangent(frames, vk, 0), n),
+                                 project_tangent(nodal_tangent(frames, vk, 1), n)};
+            const dvec3 tl[2] = {project_tangent(nodal_tangent(frames, vl, 0), n),
+                                 project_tangent(nodal_tangent(frames, vl, 1), n)};
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) s[2 * a + b] += wn * dot(tk[a], tl[b]);
+        }
     }
-    unsafeAtomicAdd(mval + slot[id], s);
+    double *dst = mval + 4 * (int64_t)slot[id];
+    if (frame == 0) {
+        unsafeAtomicAdd(dst, s[0]);
+        unsafeAtomicAdd(dst + 3, s[0]);
+    } else {
+        for (int c = 0; c < 4; ++c) unsafeAtomicAdd(dst + c, s[c]);
+    }
 }
 
 // ------------------------------------------------------------ host ---
@@ -864,7 +1021,7 @@ static KernelConst make_rem_kconst(const mbem_op *op) {
     return R;
 }
 
-template <typename T, typename TS, bool DK = false, bool P12 = false>
+template <typename T, typename TS, bool DK = false, bool P12 = false, bool NODAL = false>
 static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long *cnt,
                           hipStream_t s, const FillBand *band = nullptr) {
     const mbem_mesh *m = op->mesh;
@@ -874,6 +1031,7 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
     a.qp = qp;
     a.qp64 = P12 ? m->d_qp12 : m->d_qp;
     a.tri = m->d_tri;
+    a.frames = m->d_frames;
     a.chunks = m->d_chunks;
     a.einfo = m->d_elem;
     a.mode = mode;
@@ -899,13 +1057,13 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
             if constexpr (P12)
                 hipLaunchKernelGGL((k_regular12<T, TS>), dim3((unsigned)a.total), dim3(256), 0, s, a);
             else
-                hipLaunchKernelGGL((k_regular<T, TS, DK>), dim3((unsigned)a.total), dim3(256), 0, s, a);
+                hipLaunchKernelGGL((k_regular<T, TS, DK, NODAL>), dim3((unsigned)a.total), dim3(256), 0, s, a);
             MBEM_HIP(hipGetLastError());
         }
     return MBEM_OK;
 }
 
-template <typename TS, bool DK = false, bool PAPER = false>
+template <typename TS, bool DK = false, bool PAPER = false, bool NODAL = false>
 static int launch_ssq(mbem_op *op, hipStream_t s, const FillBand *band = nullptr) {
     const mbem_mesh *m = op->mesh;
     SsqArgs<TS> a;
@@ -930,17 +1088,17 @@ static int launch_ssq(mbem_op *op, hipStream_t s, const FillBand *band = nullptr
     if constexpr (PAPER)
         hipLaunchKernelGGL((k_ssq_paper<TS>), dim3((unsigned)a.npairs), dim3(kSsqThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_ssq<TS, DK>), dim3((unsigned)a.npairs), dim3(kSsqThreads), 0, s, a);
+        hipLaunchKernelGGL((k_ssq<TS, DK, NODAL>), dim3((unsigned)a.npairs), dim3(kSsqThreads), 0, s, a);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
 
 int mass_run(mbem_op *op, hipStream_t s) {
     const mbem_mesh *m = op->mesh;
-    MBEM_HIP(hipMemsetAsync(op->d_mval, 0, sizeof(double) * m->m_col.size(), s));
+    MBEM_HIP(hipMemsetAsync(op->d_mval, 0, sizeof(double) * 4 * m->m_col.size(), s));
     const int64_t n = m->nt * 36;
     hipLaunchKernelGGL(k_mass, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       m->nt, m->d_qp, m->d_mslot, op->d_mval);
+                       m->nt, m->d_qp, m->d_tri, m->d_frames, op->p.frame, m->d_mslot, op->d_mval);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
@@ -1001,8 +1159,8 @@ int fill_prepare(mbem_op *op, hipStream_t s, bool deriv) {
 }
 
 int fill_band_run(mbem_op *op, const FillBand &band, hipStream_t s) {
-    if (op->prec != MBEM_FP64 || op->p.quadrature != MBEM_QUAD_DEFAULT) {
-        set_error("band fills are built for the FP64 default scheme only");
+    if (op->prec != MBEM_FP64 || op->p.quadrature != MBEM_QUAD_DEFAULT || op->p.frame != MBEM_FRAME_INTERPOLATED) {
+        set_error("band fills are built for the FP64 default scheme on the interpolated frame only");
         return MBEM_EINVAL;
     }
     MBEM_TRY((launch_regular<double, double>(op, 0, op->mesh->d_qp, nullptr, s, &band)));
@@ -1015,6 +1173,11 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     const bool paper = op->p.quadrature == MBEM_QUAD_PAPER;
     if (paper && deriv) { set_error("the eps derivative is built for the default quadrature only"); return MBEM_EINVAL; }
     if (deriv && op->prec != MBEM_FP64) { set_error("derivative operators are filled in FP64"); return MBEM_EINVAL; }
+    const bool nodal = op->p.frame == MBEM_FRAME_NODAL;
+    if (nodal && (paper || deriv)) {
+        set_error("the node-attached frame is filled with the default quadrature, without derivatives");
+        return MBEM_EINVAL;
+    }
     MBEM_TRY(fill_prepare(op, s, deriv));
     FillState *f = op->fs;
     hipEvent_t *ev = f->ev;
@@ -1035,16 +1198,20 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     } else if (deriv) {
         MBEM_TRY((launch_regular<double, double, true>(op, 0, m->d_qp, nullptr, s)));
     } else if (op->prec == MBEM_FP64) {
-        MBEM_TRY((launch_regular<double, double>(op, 0, m->d_qp, nullptr, s)));
+        if (nodal) MBEM_TRY((launch_regular<double, double, false, false, true>(op, 0, m->d_qp, nullptr, s)));
+        else MBEM_TRY((launch_regular<double, double>(op, 0, m->d_qp, nullptr, s)));
     } else {
-        MBEM_TRY((launch_regular<float, float>(op, 1, m->d_qp32, cnt, s)));
+        if (nodal) MBEM_TRY((launch_regular<float, float, false, false, true>(op, 1, m->d_qp32, cnt, s)));
+        else MBEM_TRY((launch_regular<float, float>(op, 1, m->d_qp32, cnt, s)));
     }
     MBEM_HIP(hipEventRecord(ev[2], s));
     MBEM_HIP(hipEventRecord(ev[3], s));   // near pairs run inside the regular launches
     if (paper && op->prec == MBEM_FP64) MBEM_TRY((launch_ssq<double, false, true>(op, s)));
     else if (paper) MBEM_TRY((launch_ssq<float, false, true>(op, s)));
     else if (deriv) MBEM_TRY((launch_ssq<double, true>(op, s)));
+    else if (op->prec == MBEM_FP64 && nodal) MBEM_TRY((launch_ssq<double, false, false, true>(op, s)));
     else if (op->prec == MBEM_FP64) MBEM_TRY(launch_ssq<double>(op, s));
+    else if (nodal) MBEM_TRY((launch_ssq<float, false, false, true>(op, s)));
     else MBEM_TRY(launch_ssq<float>(op, s));
     MBEM_HIP(hipEventRecord(ev[4], s));
     MBEM_TRY(mass_run(op, s));

@@ -159,11 +159,12 @@ __global__ void k_combine(int64_t n2, const double2 *__restrict__ t,
     const int64_t i = r / 2;
     const int al = (int)(r % 2);
     double2 Mj = {0, 0}, Mm = {0, 0};
+    // mass: 2 x 2 block per node pair, value (al, be) at mval[4 s + 2 al + be]
     for (int32_t s = mptr[i]; s < mptr[i + 1]; ++s) {
-        const int64_t col = 2 * (int64_t)mcol[s] + al;
-        const double v = mval[s];
-        Mj.x += v * xj[col].x; Mj.y += v * xj[col].y;
-        Mm.x += v * xm[col].x; Mm.y += v * xm[col].y;
+        const int64_t col = 2 * (int64_t)mcol[s];
+        const double v0 = mval[4 * s + 2 * al], v1 = mval[4 * s + 2 * al + 1];
+        Mj.x += v0 * xj[col].x + v1 * xj[col + 1].x; Mj.y += v0 * xj[col].y + v1 * xj[col + 1].y;
+        Mm.x += v0 * xm[col].x + v1 * xm[col + 1].x; Mm.y += v0 * xm[col].y + v1 * xm[col + 1].y;
     }
     y[r] = cadd(cadd(cmul(c.iw, t[r]), t[2 * n2 + r]), cmul(c.ce, Mm));
     y[n2 + r] = csub(cadd(t[3 * n2 + r], cmul(c.cm, Mj)), cmul(c.iw, t[n2 + r]));
@@ -201,10 +202,11 @@ __device__ inline double2 kval(const void *K, int64_t idx) {
     else { const float2 v = ((const float2 *)K)[idx]; return {(double)v.x, (double)v.y}; }
 }
 
+// mass entry of unknowns (2 i + al, 2 j + be)
 __device__ inline double mass_entry(const int32_t *mptr, const int32_t *mcol, const double *mval,
-                                    int64_t i, int64_t j) {
+                                    int64_t i, int64_t j, int al, int be) {
     for (int32_t s = mptr[i]; s < mptr[i + 1]; ++s)
-        if (mcol[s] == j) return mval[s];
+        if (mcol[s] == j) return mval[4 * s + 2 * al + be];
     return 0.0;
 }
 
@@ -219,11 +221,9 @@ __device__ inline double2 z_entry(const void *const K[3], const int32_t *mptr,
     else if (ci == 1 && cc == 1) { const double2 k = cmul(c.iw, kval<TS>(K[0], idx)); z = {-k.x, -k.y}; }
     else {
         z = kval<TS>(K[ci == 0 ? 1 : 2], idx);
-        if ((r % 2) == (q % 2)) {
-            const double mv = mass_entry(mptr, mcol, mval, r / 2, q / 2);
-            const double2 cf = ci == 0 ? c.ce : c.cm;
-            z.x += cf.x * mv; z.y += cf.y * mv;
-        }
+        const double mv = mass_entry(mptr, mcol, mval, r / 2, q / 2, (int)(r % 2), (int)(q % 2));
+        const double2 cf = ci == 0 ? c.ce : c.cm;
+        z.x += cf.x * mv; z.y += cf.y * mv;
     }
     return z;
 }
@@ -315,12 +315,10 @@ __global__ void k_mbj_gather_blr(int64_t n2, int B, BlrView v, const int32_t *mp
             z = ci == 0 ? k : double2{-k.x, -k.y};
         } else {
             z = blr_entry(v, ci == 0 ? 1 : 2, gr, gq);
-            if ((gr % 2) == (gq % 2)) {
-                const double mv = mass_entry(mptr, mcol, mval, gr / 2, gq / 2);
-                const double2 cf = ci == 0 ? c.ce : c.cm;
-                z.x += cf.x * mv;
-                z.y += cf.y * mv;
-            }
+            const double mv = mass_entry(mptr, mcol, mval, gr / 2, gq / 2, (int)(gr % 2), (int)(gq % 2));
+            const double2 cf = ci == 0 ? c.ce : c.cm;
+            z.x += cf.x * mv;
+            z.y += cf.y * mv;
         }
         A[(int64_t)m * ld * ld + r * ld + q] = z;
     }

@@ -277,7 +277,7 @@ int rhs_run(const mbem_mesh *m, const mbem_params *p, const double *khat,
 int farfield_run(const mbem_mesh *m, const mbem_params *p, const double2 *x,
                  int nrhs, const double *rhat, int64_t ndir, double2 *F,
                  hipStream_t s);
-int absorbed_run(const mbem_mesh *m, const double2 *x, double *out_dev,
+int absorbed_run(const mbem_mesh *m, const mbem_params *p, const double2 *x, double *out_dev,
                  hipStream_t s);
 int weighted_norm_run(int64_t ndir, const double2 *F, const double *w,
                       double *out, hipStream_t s);

@@ -152,6 +152,17 @@ __device__ inline void p2_point(const double *__restrict__ xyz,
     P.s2 = cross(P.t2, n);
 }
 
+// Node-attached tangents (frame 1): the basis function of node v, component
+// b, is N_v(y) P(y) t_b,v with t_b,v the node's own triad tangent and
+// P(y) = I - n n^T the tangent-plane projector at y; its rotated test vector
+// is P t_b,v x n = t_b,v x n.  Frame 0 uses the interpolated frame t_b(y) of
+// p2_point for every node.
+__device__ inline dvec3 nodal_tangent(const double *__restrict__ frames, int64_t v, int b) {
+    const double *f = frames + 9 * v + 3 + 3 * b;
+    return {f[0], f[1], f[2]};
+}
+__device__ inline dvec3 project_tangent(dvec3 t, dvec3 n) { return t - dot(t, n) * n; }
+
 // ------------------------------------------------- kernel differences --
 constexpr int kSeriesTerms = 16;   // Taylor terms n = 0..16
 constexpr double kSeriesRho = 0.5; // series below max|k| R = 1/2

@@ -19,11 +19,25 @@ __device__ inline cx<double> cexpi(double ph) {
     return {c, s};
 }
 
+// Basis tangent of local node kk, component bb, at point i of the 7-point
+// table: the interpolated frame (frame 0) or the projected nodal tangent.
+__device__ inline dvec3 basis_at(int frame, const double *__restrict__ qp, int64_t nq, int64_t i,
+                                 const double *__restrict__ frames, int64_t node, int bb) {
+    if (frame == 0) {
+        const int c = bb ? QT2 : QT1;
+        return {qp[c * nq + i], qp[(c + 1) * nq + i], qp[(c + 2) * nq + i]};
+    }
+    const dvec3 n = {qp[QN * nq + i], qp[(QN + 1) * nq + i], qp[(QN + 2) * nq + i]};
+    return project_tangent(nodal_tangent(frames, node, bb), n);
+}
+
 // One thread per (quadrature point, right-hand side):
 //   b_E[2i+a] += -eps_a W N_i s_a.E,  b_H[2i+a] += mu_a W N_i s_a.H
+// with s_a the rotated test vector of node i (frame 0: of the point).
 __global__ void k_rhs(int64_t nt, int64_t n2, int nrhs, const double *__restrict__ qp,
-                      const int32_t *__restrict__ tri, const double *__restrict__ khat,
-                      const double2 *__restrict__ pol, double ka, double2 *__restrict__ b) {
+                      const int32_t *__restrict__ tri, const double *__restrict__ frames, int frame,
+                      const double *__restrict__ khat, const double2 *__restrict__ pol, double ka,
+                      double2 *__restrict__ b) {
     const int64_t nq = nt * kQP;
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (id >= nq * nrhs) return;
@@ -32,8 +46,9 @@ __global__ void k_rhs(int64_t nt, int64_t n2, int nrhs, const double *__restrict
     const int64_t e = i / kQP;
     const int q = (int)(i % kQP);
     const dvec3 x = {qp[QX * nq + i], qp[(QX + 1) * nq + i], qp[(QX + 2) * nq + i]};
-    const dvec3 s[2] = {{qp[QS1 * nq + i], qp[(QS1 + 1) * nq + i], qp[(QS1 + 2) * nq + i]},
-                        {qp[QS2 * nq + i], qp[(QS2 + 1) * nq + i], qp[(QS2 + 2) * nq + i]}};
+    const dvec3 s0[2] = {{qp[QS1 * nq + i], qp[(QS1 + 1) * nq + i], qp[(QS1 + 2) * nq + i]},
+                         {qp[QS2 * nq + i], qp[(QS2 + 1) * nq + i], qp[(QS2 + 2) * nq + i]}};
+    const dvec3 n = {qp[QN * nq + i], qp[(QN + 1) * nq + i], qp[(QN + 2) * nq + i]};
     const double W = qp[QW * nq + i];
     const dvec3 k = {khat[3 * r], khat[3 * r + 1], khat[3 * r + 2]};
     const cx<double> ph = cexpi(ka * dot(k, x));
@@ -47,10 +62,12 @@ __global__ void k_rhs(int64_t nt, int64_t n2, int nrhs, const double *__restrict
     p2_shape(xi, eta, N, d1, d2);
     double2 *bc = b + (int64_t)r * 2 * n2;
     for (int a = 0; a < 2; ++a) {
-        const cx<double> sE = s[a].x * E[0] + s[a].y * E[1] + s[a].z * E[2];
-        const cx<double> sH = s[a].x * H[0] + s[a].y * H[1] + s[a].z * H[2];
         for (int kk = 0; kk < 6; ++kk) {
-            const int64_t row = 2 * (int64_t)tri[6 * e + kk] + a;
+            const int64_t node = tri[6 * e + kk];
+            const dvec3 s = frame == 0 ? s0[a] : cross(nodal_tangent(frames, node, a), n);
+            const cx<double> sE = s.x * E[0] + s.y * E[1] + s.z * E[2];
+            const cx<double> sH = s.x * H[0] + s.y * H[1] + s.z * H[2];
+            const int64_t row = 2 * node + a;
             const double f = W * N[kk];
             unsafeAtomicAdd(&bc[row].x, -f * sE.re);
             unsafeAtomicAdd(&bc[row].y, -f * sE.im);
@@ -66,7 +83,7 @@ int rhs_run(const mbem_mesh *m, const mbem_params *p, const double *khat, const 
     MBEM_HIP(hipMemsetAsync(b, 0, sizeof(double2) * 2 * n2 * nrhs, s));
     const int64_t n = m->nt * kQP * nrhs;
     hipLaunchKernelGGL(k_rhs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, m->nt, n2, nrhs,
-                       m->d_qp, m->d_tri, khat, pol, p->k0, b);
+                       m->d_qp, m->d_tri, m->d_frames, p->frame, khat, pol, p->k0, b);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
@@ -74,15 +91,13 @@ int rhs_run(const mbem_mesh *m, const mbem_params *p, const double *khat, const 
 // Surface currents W j, W j_m at every quadrature point of one solution:
 // cur[i][0..5] = W j (3 complex), cur[i][6..11] = W j_m.
 __global__ void k_currents(int64_t nt, int64_t n2, const double *__restrict__ qp,
-                           const int32_t *__restrict__ tri, const double2 *__restrict__ x,
-                           double *__restrict__ cur) {
+                           const int32_t *__restrict__ tri, const double *__restrict__ frames, int frame,
+                           const double2 *__restrict__ x, double *__restrict__ cur) {
     const int64_t nq = nt * kQP;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nq) return;
     const int64_t e = i / kQP;
     const int q = (int)(i % kQP);
-    const dvec3 t[2] = {{qp[QT1 * nq + i], qp[(QT1 + 1) * nq + i], qp[(QT1 + 2) * nq + i]},
-                        {qp[QT2 * nq + i], qp[(QT2 + 1) * nq + i], qp[(QT2 + 2) * nq + i]}};
     const double W = qp[QW * nq + i];
     double xi, eta, w, N[6], d1[6], d2[6];
     rule7(q, xi, eta, w);
@@ -92,7 +107,8 @@ __global__ void k_currents(int64_t nt, int64_t n2, const double *__restrict__ qp
         const int64_t node = tri[6 * e + kk];
         for (int bb = 0; bb < 2; ++bb) {
             const double2 cj = x[2 * node + bb], cm = x[n2 + 2 * node + bb];
-            const double c[3] = {t[bb].x, t[bb].y, t[bb].z};
+            const dvec3 t = basis_at(frame, qp, nq, i, frames, node, bb);
+            const double c[3] = {t.x, t.y, t.z};
             for (int d = 0; d < 3; ++d) {
                 const double f = W * N[kk] * c[d];
                 J[d] = J[d] + cx<double>{f * cj.x, f * cj.y};
@@ -155,7 +171,7 @@ int farfield_run(const mbem_mesh *m, const mbem_params *p, const double2 *x, int
     MBEM_HIP(hipMallocAsync((void **)&cur, sizeof(double) * 12 * nq, s));
     for (int r = 0; r < nrhs; ++r) {
         hipLaunchKernelGGL(k_currents, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, m->nt, n2,
-                           m->d_qp, m->d_tri, x + (int64_t)r * 2 * n2, cur);
+                           m->d_qp, m->d_tri, m->d_frames, p->frame, x + (int64_t)r * 2 * n2, cur);
         MBEM_HIP(hipGetLastError());
         if (ndir > 0) {
             hipLaunchKernelGGL(k_farfield, dim3((unsigned)ndir), dim3(256), 0, s, nq, m->d_qp, cur, rhat,
@@ -170,6 +186,7 @@ int farfield_run(const mbem_mesh *m, const mbem_params *p, const double2 *x, int
 // sum_q Re n.(W j_m x conj(j)) with j from the unweighted coefficients.
 __global__ __launch_bounds__(256) void k_absorbed(int64_t nt, int64_t n2, const double *__restrict__ qp,
                                                   const int32_t *__restrict__ tri,
+                                                  const double *__restrict__ frames, int frame,
                                                   const double2 *__restrict__ x, double *out) {
     const int64_t nq = nt * kQP;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -178,8 +195,6 @@ __global__ __launch_bounds__(256) void k_absorbed(int64_t nt, int64_t n2, const 
         const int64_t e = i / kQP;
         const int q = (int)(i % kQP);
         const dvec3 n = {qp[QN * nq + i], qp[(QN + 1) * nq + i], qp[(QN + 2) * nq + i]};
-        const dvec3 t[2] = {{qp[QT1 * nq + i], qp[(QT1 + 1) * nq + i], qp[(QT1 + 2) * nq + i]},
-                            {qp[QT2 * nq + i], qp[(QT2 + 1) * nq + i], qp[(QT2 + 2) * nq + i]}};
         double xi, eta, w, N[6], d1[6], d2[6];
         rule7(q, xi, eta, w);
         p2_shape(xi, eta, N, d1, d2);
@@ -188,7 +203,8 @@ __global__ __launch_bounds__(256) void k_absorbed(int64_t nt, int64_t n2, const 
             const int64_t node = tri[6 * e + kk];
             for (int bb = 0; bb < 2; ++bb) {
                 const double2 cj = x[2 * node + bb], cm = x[n2 + 2 * node + bb];
-                const double c[3] = {t[bb].x, t[bb].y, t[bb].z};
+                const dvec3 t = basis_at(frame, qp, nq, i, frames, node, bb);
+                const double c[3] = {t.x, t.y, t.z};
                 for (int d = 0; d < 3; ++d) {
                     J[d] = J[d] + cx<double>{N[kk] * c[d] * cj.x, N[kk] * c[d] * cj.y};
                     Jm[d] = Jm[d] + cx<double>{N[kk] * c[d] * cm.x, N[kk] * c[d] * cm.y};
@@ -205,11 +221,11 @@ __global__ __launch_bounds__(256) void k_absorbed(int64_t nt, int64_t n2, const 
     if (threadIdx.x % kW2 == 0) unsafeAtomicAdd(out, v);
 }
 
-int absorbed_run(const mbem_mesh *m, const double2 *x, double *out_dev, hipStream_t s) {
+int absorbed_run(const mbem_mesh *m, const mbem_params *p, const double2 *x, double *out_dev, hipStream_t s) {
     const int64_t nq = m->nt * kQP;
     MBEM_HIP(hipMemsetAsync(out_dev, 0, sizeof(double), s));
     hipLaunchKernelGGL(k_absorbed, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, m->nt, 2 * m->nn,
-                       m->d_qp, m->d_tri, x, out_dev);
+                       m->d_qp, m->d_tri, m->d_frames, p->frame, x, out_dev);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }

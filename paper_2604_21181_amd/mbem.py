@@ -20,6 +20,7 @@ MBEM_OK, MBEM_EINVAL, MBEM_ENOMEM, MBEM_EDEVICE = 0, -1, -2, -3
 MBEM_ENOCONV, MBEM_ESINGULAR, MBEM_EMESH = -4, -5, -6
 MBEM_FP64, MBEM_MIXED = 0, 1
 MBEM_QUAD_DEFAULT, MBEM_QUAD_PAPER = 0, 1
+MBEM_FRAME_INTERPOLATED, MBEM_FRAME_NODAL = 0, 1
 
 EXPORTED = [
     "mbem_ctx_create", "mbem_ctx_destroy", "mbem_mesh_create", "mbem_mesh_destroy",
@@ -43,7 +44,8 @@ class MbemError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("k0", C.c_double), ("eps_r_re", C.c_double), ("eps_r_im", C.c_double),
                 ("mu_r_re", C.c_double), ("mu_r_im", C.c_double), ("ssq_order", C.c_int32),
-                ("precision", C.c_int32), ("near_radius", C.c_double), ("quadrature", C.c_int32)]
+                ("precision", C.c_int32), ("near_radius", C.c_double), ("quadrature", C.c_int32),
+                ("frame", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -214,9 +216,9 @@ def mbem_morton_order(xyz, tri6):
 
 
 def make_params(k0, eps_r, mu_r=1.0, precision=MBEM_FP64, ssq_order=4, near_radius=0.0,
-                quadrature=MBEM_QUAD_DEFAULT):
+                quadrature=MBEM_QUAD_DEFAULT, frame=MBEM_FRAME_INTERPOLATED):
     e, m = complex(eps_r), complex(mu_r)
-    return Params(k0, e.real, e.imag, m.real, m.imag, ssq_order, precision, near_radius, quadrature)
+    return Params(k0, e.real, e.imag, m.real, m.imag, ssq_order, precision, near_radius, quadrature, frame)
 
 
 def mbem_fill(ctx, mesh, params):
@@ -385,7 +387,7 @@ class Solver:
     Morton order (``to_morton`` / ``to_user`` map caller-ordered arrays)."""
 
     def __init__(self, xyz, tri6, k0, eps_r, mu_r=1.0, precision=MBEM_FP64, ssq_order=4,
-                 device=0, near_radius=0.0, quadrature=MBEM_QUAD_DEFAULT):
+                 device=0, near_radius=0.0, quadrature=MBEM_QUAD_DEFAULT, frame=MBEM_FRAME_INTERPOLATED):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -395,7 +397,7 @@ class Solver:
         self.nn, self.nt, self.N = int(info[0]), int(info[1]), int(info[2])
         self.n_singular = (int(info[3]), int(info[4]), int(info[5]))
         self.node_order, self.tri_order = mbem_mesh_permutation(self.mesh)
-        self.params = make_params(k0, eps_r, mu_r, precision, ssq_order, near_radius, quadrature)
+        self.params = make_params(k0, eps_r, mu_r, precision, ssq_order, near_radius, quadrature, frame)
         self.op = None
         self.fill_stats = None
 
