@@ -136,10 +136,13 @@ def parse():
                     help="skip the LSPR spectrum sweep of the silver spheroid")
     ap.add_argument("--no-blr-study", action="store_true",
                     help="skip the block low-rank operator beyond dense memory")
+    ap.add_argument("--no-frame-study", action="store_true",
+                    help="skip the comparison of the interpolated frame with node-attached tangents")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device to device once (scales the FETCH_SIZE / WRITE_SIZE "
                          "counters) and exit")
-    ap.add_argument("--only", choices=["all", "main", "mrhs", "grad", "precond", "quad", "spectrum", "blr"],
+    ap.add_argument("--only", choices=["all", "main", "mrhs", "grad", "precond", "quad", "spectrum", "blr",
+                                       "frame"],
                     default="all",
                     help="run one pass of the step only (for profiling); the JSON line is "
                          "printed for 'all' and 'main'")
@@ -310,6 +313,46 @@ def blr_study(mbem, icosphere_p2, log):
         S.close()
 
 
+def frame_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3):
+    """The interpolated frame (the paper's construction, the default) against
+    node-attached tangents on the 1280-triangle sphere, FP64 and mixed: fill
+    times, GMRES iterations to 1e-8, the energy balance
+    |C_ext - C_sca - C_abs| / C_ext of each solution (the sphere is lossless,
+    so the gap is discretisation error), and the far-field difference of the
+    two bases."""
+    c = get_config("sphere1280")
+    xyz, tri = icosphere_p2(c["n_tris"], c["axes"])
+    kh, po = planewaves("sphere1280")
+    out = {"workload": "sphere1280", "unknowns": None}
+    F = {}
+    for name, prec, frame in (("interpolated_fp64", mbem.MBEM_FP64, mbem.MBEM_FRAME_INTERPOLATED),
+                              ("nodal_fp64", mbem.MBEM_FP64, mbem.MBEM_FRAME_NODAL),
+                              ("interpolated_mixed", mbem.MBEM_MIXED, mbem.MBEM_FRAME_INTERPOLATED),
+                              ("nodal_mixed", mbem.MBEM_MIXED, mbem.MBEM_FRAME_NODAL)):
+        S = mbem.Solver(xyz, tri, c["k0"], c["eps_r"], c["mu_r"], precision=prec, frame=frame)
+        try:
+            fs = [S.fill() for _ in range(reps + 1)][1:]
+            S.precond_setup(c["mbj_block"])
+            x, st, code = S.solve(S.rhs(kh, po), tol=c["tol"], maxit=600, inner_tol=1e-4)
+            F[name] = S.farfield(x, rdirs).cpu().numpy()[0]
+            cs = S.cross_sections(x[0], kh[0], po[0])
+            out["unknowns"] = S.N
+            out[name] = {"t_fill_ms": float(np.mean([f.t_fill_ms for f in fs])),
+                         "t_regular_ms": float(np.mean([f.t_regular_ms for f in fs])),
+                         "t_singular_ms": float(np.mean([f.t_ssq_ms for f in fs])),
+                         "iters": st.iters, "converged": code == 0,
+                         "c_ext": float(cs[0]),
+                         "energy_balance": float(abs(cs[0] - cs[1] - cs[2]) / cs[0])}
+            log(f"frame study: {name} fill {out[name]['t_fill_ms']:.2f} ms, "
+                f"energy balance {out[name]['energy_balance']:.2e}")
+        finally:
+            S.close()
+    rel = lambda a, b: float(np.linalg.norm(F[a] - F[b]) / np.linalg.norm(F[b]))
+    out["farfield_nodal_vs_interpolated_fp64"] = rel("nodal_fp64", "interpolated_fp64")
+    out["farfield_nodal_mixed_vs_nodal_fp64"] = rel("nodal_mixed", "nodal_fp64")
+    return out
+
+
 def quad_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3):
     """The paper's own quadrature (12-point rule, Sauter-Schwab on the
     singular kernels, 12-point remainder) against the default on the
@@ -367,14 +410,15 @@ def main():
     if args.only != "all":
         # one pass of the step, or one study
         keep = {"mrhs": "no_mrhs", "grad": "no_grad", "precond": "no_precond_study",
-                "quad": "no_quad_study", "spectrum": "no_spectrum_study", "blr": "no_blr_study"}
+                "quad": "no_quad_study", "spectrum": "no_spectrum_study", "blr": "no_blr_study",
+                "frame": "no_frame_study"}
         for name, flag in keep.items():
             if name != args.only:
                 setattr(args, flag, True)
         if args.only != "main":
             args.paths = ""
             args.no_cpu_baseline = True
-        if args.only in ("precond", "quad", "spectrum", "blr"):
+        if args.only in ("precond", "quad", "spectrum", "blr", "frame"):
             args.steps, args.warmup = 0, 0
     cfg = get_config(args.workload)
     xyz, tri = icosphere_p2(cfg["n_tris"], cfg["axes"])
@@ -601,13 +645,17 @@ def main():
     bstudy = None
     if not args.no_blr_study:
         bstudy = blr_study(mbem, icosphere_p2, log)
+    fstudy = None
+    if not args.no_frame_study:
+        fstudy = frame_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log)
 
     if not paths:
         # profiling run of one pass: its own section only
         print(json.dumps({"pass": args.only, "steps": args.steps, "warmup": args.warmup,
                           "ms_per_step": ms_per_step, "multi_rhs": mrhs, "gradient": grad,
                           "precond_study": pstudy, "quadrature_study": qstudy,
-                          "spectrum_study": sstudy, "blr_study": bstudy}), flush=True)
+                          "spectrum_study": sstudy, "blr_study": bstudy, "frame_study": fstudy}),
+              flush=True)
         for S in (Smr, Sg):
             if S is not None:
                 S.close()
@@ -643,6 +691,7 @@ def main():
         "quadrature_study": qstudy,
         "spectrum_study": sstudy,
         "blr_study": bstudy,
+        "frame_study": fstudy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
