@@ -331,22 +331,24 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
             const int og = it / (kChunk * 7), fp = it % (kChunk * 7);   // og = 2 op + gamma
             cx<T> *r0 = s_r1 + (2 * og) * kR1Stride + 7 * fp, *r1 = r0 + kR1Stride;
             const T *rb = s_rb + (fp / 7) * 168;
-            cx<T> k0[7], k1[7], o0[6], o1[6];
+            cx<T> k0[7], k1[7];
 #pragma unroll
             for (int q = 0; q < 7; ++q) { k0[q] = r0[q]; k1[q] = r1[q]; }
-#pragma unroll
+            // every input is in registers: each output may overwrite its slot
+            // (one j at a time: unrolled, the weight loads of all j would be
+            // hoisted and the FP64 kernel would run at one wave per SIMD)
+#pragma unroll 1
             for (int j = 0; j < 6; ++j) {
-                o0[j] = cx<T>{0, 0};
-                o1[j] = cx<T>{0, 0};
+                cx<T> o0 = {0, 0}, o1 = {0, 0};
 #pragma unroll
                 for (int q = 0; q < 7; ++q) {
                     const T *w = rb + (q * 6 + j) * 4;
-                    o0[j] = o0[j] + w[0] * k0[q] + w[1] * k1[q];
-                    o1[j] = o1[j] + w[2] * k0[q] + w[3] * k1[q];
+                    o0 = o0 + w[0] * k0[q] + w[1] * k1[q];
+                    o1 = o1 + w[2] * k0[q] + w[3] * k1[q];
                 }
+                r0[j] = o0;
+                r1[j] = o1;
             }
-#pragma unroll
-            for (int j = 0; j < 6; ++j) { r0[j] = o0[j]; r1[j] = o1[j]; }
         }
     }
     __builtin_amdgcn_s_waitcnt(0);             // prefetched destinations have landed (FP32)
@@ -378,25 +380,25 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
         } else {
             // components (op, gamma, beta) for gamma = 0, 1 at 4 op + beta and
             // 4 op + 2 + beta; out[i] = sum_p sum_gamma s_ra[p][i][alpha][gamma] Ts[gamma][p]
+            // (point-major, so that only the six outputs stay live)
             const int al = g & 1;
             const int c0 = 4 * op + be;
-            cx<T> tv0[7], tv1[7];
+            const int u0 = s_rec[25 + sl];
 #pragma unroll
-            for (int p = 0; p < 7; ++p) { tv0[p] = cx<T>{0, 0}; tv1[p] = cx<T>{0, 0}; }
-            for (int u = s_rec[25 + sl]; u < u1; ++u) {
-                const int fl = s_rec[50 + u];
-                const cx<T> *src0 = s_r1 + c0 * kR1Stride + (fl >> 3) * 49 + (fl & 7);
-                const cx<T> *src1 = src0 + 2 * kR1Stride;
+            for (int i = 0; i < 6; ++i) out[i] = cx<T>{0, 0};
+#pragma unroll 1
+            for (int p = 0; p < 7; ++p) {
+                cx<T> t0 = {0, 0}, t1 = {0, 0};
+                for (int u = u0; u < u1; ++u) {
+                    const int fl = s_rec[50 + u];
+                    const cx<T> *src0 = s_r1 + c0 * kR1Stride + (fl >> 3) * 49 + (fl & 7) + 7 * p;
+                    t0 = t0 + src0[0];
+                    t1 = t1 + src0[2 * kR1Stride];
+                }
 #pragma unroll
-                for (int p = 0; p < 7; ++p) { tv0[p] = tv0[p] + src0[7 * p]; tv1[p] = tv1[p] + src1[7 * p]; }
-            }
-#pragma unroll
-            for (int i = 0; i < 6; ++i) {
-                out[i] = cx<T>{0, 0};
-#pragma unroll
-                for (int p = 0; p < 7; ++p) {
+                for (int i = 0; i < 6; ++i) {
                     const T *w = s_ra + (p * 6 + i) * 4 + 2 * al;
-                    out[i] = out[i] + w[0] * tv0[p] + w[1] * tv1[p];
+                    out[i] = out[i] + w[0] * t0 + w[1] * t1;
                 }
             }
         }
