@@ -21,10 +21,10 @@ def sigma_ext(P, x, khat, pol):
     return 4 * np.pi / P.ka * np.imag(np.vdot(np.asarray(pol, dtype=np.complex128), F))
 
 
-def solve_sigma_ext(xyz, tri, k0, eps_r, khat, pol, mu_r=1.0):
-    P = galerkin.Problem(xyz, tri, k0, eps_r, mu_r)
+def solve_sigma_ext(xyz, tri, k0, eps_r, khat, pol, mu_r=1.0, frame=0):
+    P = galerkin.Problem(xyz, tri, k0, eps_r, mu_r, frame=frame)
     K = core.fill(xyz, tri, P.phys)
-    Z = galerkin.assemble(P, *K, galerkin.mass_matrix(P))
+    Z = galerkin.assemble(P, *K)
     b = galerkin.planewave_rhs(P, np.asarray(khat)[None], np.asarray(pol)[None])[:, 0]
     x = np.linalg.solve(Z, b)
     return sigma_ext(P, x, khat, pol), x, Z, P
@@ -35,18 +35,18 @@ def richardson(f, a, h):
     return (8.0 * (f(a + h) - f(a - h)) - (f(a + 2 * h) - f(a - 2 * h))) / (12.0 * h)
 
 
-def dsigma_deps(xyz, tri, k0, eps_r, khat, pol, h=1e-3):
+def dsigma_deps(xyz, tri, k0, eps_r, khat, pol, h=1e-3, frame=0):
     """(d sigma / d Re eps_r, d sigma / d Im eps_r) by differences."""
     eps_r = complex(eps_r)
-    f_re = lambda t: solve_sigma_ext(xyz, tri, k0, eps_r + t, khat, pol)[0]
-    f_im = lambda t: solve_sigma_ext(xyz, tri, k0, eps_r + 1j * t, khat, pol)[0]
+    f_re = lambda t: solve_sigma_ext(xyz, tri, k0, eps_r + t, khat, pol, frame=frame)[0]
+    f_im = lambda t: solve_sigma_ext(xyz, tri, k0, eps_r + 1j * t, khat, pol, frame=frame)[0]
     return richardson(f_re, 0.0, h), richardson(f_im, 0.0, h)
 
 
-def dK_deps(xyz, tri, k0, eps_r, h=1e-3, mu_r=1.0):
+def dK_deps(xyz, tri, k0, eps_r, h=1e-3, mu_r=1.0, frame=0):
     """dK1, dK2eps, dK2mu / d eps_r (holomorphic) by differences of the fill."""
     def K(e):
-        return np.stack(core.fill(xyz, tri, core.phys_vector(k0, e, mu_r)))
+        return np.stack(core.fill(xyz, tri, core.phys_vector(k0, e, mu_r, frame=frame)))
     return richardson(K, complex(eps_r), h)
 
 

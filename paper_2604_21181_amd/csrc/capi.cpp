@@ -554,9 +554,8 @@ int mbem_fill(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_o
 int mbem_fill_compressed(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, const mbem_blr_opts *o,
                          mbem_op **out, mbem_stats *stats, mbem_blr_stats *bstats) {
     if (!mesh || !p || !o || !out) { set_error("null argument"); return MBEM_EINVAL; }
-    if (p->precision != MBEM_FP64 || p->quadrature != MBEM_QUAD_DEFAULT || p->frame != MBEM_FRAME_INTERPOLATED) {
-        set_error("the block low-rank operator is built for FP64, the default quadrature and the interpolated "
-                  "frame");
+    if (p->precision != MBEM_FP64 || p->quadrature != MBEM_QUAD_DEFAULT) {
+        set_error("the block low-rank operator is built for FP64 and the default quadrature");
         return MBEM_EINVAL;
     }
     if (o->cluster < 1 || o->cluster > 2048 || !(o->eta > 0) || !(o->eps > 0 && o->eps < 1) || o->rmax < 1 ||
@@ -751,8 +750,8 @@ int mbem_solve_adjoint(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *g, int32_t n
 
 int mbem_fill_deps(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p, mbem_op **out, mbem_stats *stats) {
     if (!p) { set_error("null argument"); return MBEM_EINVAL; }
-    if (p->quadrature != MBEM_QUAD_DEFAULT || p->frame != MBEM_FRAME_INTERPOLATED) {
-        set_error("the eps derivative is built for the default quadrature and the interpolated frame only");
+    if (p->quadrature != MBEM_QUAD_DEFAULT) {
+        set_error("the eps derivative is built for the default quadrature only");
         return MBEM_EINVAL;
     }
     mbem_params q = *p;
@@ -783,9 +782,13 @@ int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh, const
                         mbem_stats *stats) {
     if (!op || !mesh || !p || !x || !khat || !pol || !o || !out) { set_error("null argument"); return MBEM_EINVAL; }
     if (op->blr) { set_error("the gradient needs a dense operator"); return MBEM_EINVAL; }
-    if (p->quadrature != MBEM_QUAD_DEFAULT || op->p.quadrature != MBEM_QUAD_DEFAULT ||
-        p->frame != MBEM_FRAME_INTERPOLATED || op->p.frame != MBEM_FRAME_INTERPOLATED) {
-        set_error("the gradient is built for the default quadrature and the interpolated frame only");
+    if (p->quadrature != MBEM_QUAD_DEFAULT || op->p.quadrature != MBEM_QUAD_DEFAULT) {
+        set_error("the gradient is built for the default quadrature only");
+        return MBEM_EINVAL;
+    }
+    if (p->frame != op->p.frame) { set_error("the parameters' frame differs from the operator's"); return MBEM_EINVAL; }
+    if ((dsig_dnode || dsig_dx) && p->frame != MBEM_FRAME_INTERPOLATED) {
+        set_error("the shape gradient is built for the interpolated frame only");
         return MBEM_EINVAL;
     }
     MBEM_TRY(set_device(ctx));

@@ -1161,12 +1161,17 @@ int fill_prepare(mbem_op *op, hipStream_t s, bool deriv) {
 }
 
 int fill_band_run(mbem_op *op, const FillBand &band, hipStream_t s) {
-    if (op->prec != MBEM_FP64 || op->p.quadrature != MBEM_QUAD_DEFAULT || op->p.frame != MBEM_FRAME_INTERPOLATED) {
-        set_error("band fills are built for the FP64 default scheme on the interpolated frame only");
+    if (op->prec != MBEM_FP64 || op->p.quadrature != MBEM_QUAD_DEFAULT) {
+        set_error("band fills are built for the FP64 default scheme only");
         return MBEM_EINVAL;
     }
-    MBEM_TRY((launch_regular<double, double>(op, 0, op->mesh->d_qp, nullptr, s, &band)));
-    MBEM_TRY(launch_ssq<double>(op, s, &band));
+    if (op->p.frame == MBEM_FRAME_NODAL) {
+        MBEM_TRY((launch_regular<double, double, false, false, true>(op, 0, op->mesh->d_qp, nullptr, s, &band)));
+        MBEM_TRY((launch_ssq<double, false, false, true>(op, s, &band)));
+    } else {
+        MBEM_TRY((launch_regular<double, double>(op, 0, op->mesh->d_qp, nullptr, s, &band)));
+        MBEM_TRY(launch_ssq<double>(op, s, &band));
+    }
     return MBEM_OK;
 }
 
@@ -1176,8 +1181,8 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     if (paper && deriv) { set_error("the eps derivative is built for the default quadrature only"); return MBEM_EINVAL; }
     if (deriv && op->prec != MBEM_FP64) { set_error("derivative operators are filled in FP64"); return MBEM_EINVAL; }
     const bool nodal = op->p.frame == MBEM_FRAME_NODAL;
-    if (nodal && (paper || deriv)) {
-        set_error("the node-attached frame is filled with the default quadrature, without derivatives");
+    if (nodal && paper) {
+        set_error("the node-attached frame is filled with the default quadrature");
         return MBEM_EINVAL;
     }
     MBEM_TRY(fill_prepare(op, s, deriv));
@@ -1198,7 +1203,8 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     } else if (paper) {
         MBEM_TRY((launch_regular<float, float, false, true>(op, 1, m->d_qp12_32, cnt, s)));
     } else if (deriv) {
-        MBEM_TRY((launch_regular<double, double, true>(op, 0, m->d_qp, nullptr, s)));
+        if (nodal) MBEM_TRY((launch_regular<double, double, true, false, true>(op, 0, m->d_qp, nullptr, s)));
+        else MBEM_TRY((launch_regular<double, double, true>(op, 0, m->d_qp, nullptr, s)));
     } else if (op->prec == MBEM_FP64) {
         if (nodal) MBEM_TRY((launch_regular<double, double, false, false, true>(op, 0, m->d_qp, nullptr, s)));
         else MBEM_TRY((launch_regular<double, double>(op, 0, m->d_qp, nullptr, s)));
@@ -1210,6 +1216,7 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     MBEM_HIP(hipEventRecord(ev[3], s));   // near pairs run inside the regular launches
     if (paper && op->prec == MBEM_FP64) MBEM_TRY((launch_ssq<double, false, true>(op, s)));
     else if (paper) MBEM_TRY((launch_ssq<float, false, true>(op, s)));
+    else if (deriv && nodal) MBEM_TRY((launch_ssq<double, true, false, true>(op, s)));
     else if (deriv) MBEM_TRY((launch_ssq<double, true>(op, s)));
     else if (op->prec == MBEM_FP64 && nodal) MBEM_TRY((launch_ssq<double, false, false, true>(op, s)));
     else if (op->prec == MBEM_FP64) MBEM_TRY(launch_ssq<double>(op, s));

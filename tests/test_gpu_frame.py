@@ -10,7 +10,7 @@ high order.
 import numpy as np
 import pytest
 
-from oracle import core, galerkin, mie
+from oracle import adjoint, blr, core, galerkin, mie
 from oracle import spectrum as ospectrum
 from workloads import icosphere_p2, uv_sphere_p2
 from workloads.configs import cut_plane_directions
@@ -166,19 +166,66 @@ def test_rejections(case):
         finally:
             S.close()
     S = case["S"]
+    # the shape gradient is built for the interpolated frame only
     with pytest.raises(mbem.MbemError) as ei:
-        S.deps_blocks()
+        S.grad_sigma_ext(S.rhs(KH[None], POL[None])[0], KH, POL, shape=True)
     assert ei.value.code == mbem.MBEM_EINVAL
-    with pytest.raises(mbem.MbemError) as ei:
-        S.grad_sigma_ext(S.rhs(KH[None], POL[None])[0], KH, POL)
-    assert ei.value.code == mbem.MBEM_EINVAL
-    S2 = mbem.Solver(xyz, tri, case["k0"], case["eps"], frame=mbem.MBEM_FRAME_NODAL)
+    # an operator and parameters on different frames
+    S2 = mbem.Solver(xyz, tri, case["k0"], case["eps"])
     try:
+        S2.fill()
+        S2.params = mbem.make_params(case["k0"], case["eps"], frame=mbem.MBEM_FRAME_NODAL)
         with pytest.raises(mbem.MbemError) as ei:
-            S2.fill_compressed(cluster=64, eta=2.0, eps=1e-6, rmax=64)
+            S2.grad_sigma_ext(S2.rhs(KH[None], POL[None])[0], KH, POL)
         assert ei.value.code == mbem.MBEM_EINVAL
     finally:
         S2.close()
+
+
+def test_deps_blocks_and_eps_gradient(case):
+    """dZ/deps_r of the node-attached operator against differences of the
+    oracle's frame-1 fill, and the adjoint d sigma_ext / d eps_r against
+    differences of the oracle's whole frame-1 map."""
+    S = case["S"]
+    dK = [k.cpu().numpy() for k in S.deps_blocks()]
+    ref = adjoint.dK_deps(case["xyz"], case["tri"], case["k0"], case["eps"], frame=1)
+    p1 = S.perm[: 2 * S.nn]
+    for o in range(3):
+        r = ref[o][np.ix_(p1, p1)]
+        assert np.abs(dK[o] - r).max() < 1e-9 * np.abs(r).max(), o
+    S.precond_setup(100)
+    x, _, code = S.solve(S.rhs(KH[None], POL[None]), tol=1e-13, maxit=400)
+    assert code == 0
+    out, _, _ = S.grad_sigma_ext(x[0], KH, POL, tol=1e-13)
+    sig = adjoint.sigma_ext(case["P"], case["x"], KH, POL)
+    d_re, d_im = adjoint.dsigma_deps(case["xyz"], case["tri"], case["k0"], case["eps"], KH, POL, frame=1)
+    assert abs(out[0] - sig) < 1e-10 * abs(sig)
+    scale = max(abs(d_re), abs(d_im))
+    assert abs(out[1] - d_re) < 1e-7 * scale
+    # k_i = k0 sqrt(eps_r) takes the branch Im k_i >= 0, so on a real eps_r
+    # the difference along Im eps_r straddles the branch cut: there only the
+    # real direction is a derivative of the discrete map
+    if complex(case["eps"]).imag > 0:
+        assert abs(out[2] - d_im) < 1e-7 * scale
+
+
+def test_compressed_operator(case):
+    """Block low-rank operator on the node-attached basis: its far field
+    equals the dense node-attached solution's to the compression tolerance."""
+    mbem = _mbem()
+    S = mbem.Solver(case["xyz"], case["tri"], case["k0"], case["eps"], frame=mbem.MBEM_FRAME_NODAL)
+    try:
+        bs = S.fill_compressed(cluster=16, eta=3.0, eps=1e-8, rmax=64, keep_lowrank=True)
+        assert bs.n_admissible > 0
+        S.precond_setup(50)
+        x, _, code = S.solve(S.rhs(KH[None], POL[None]), tol=1e-12, maxit=400)
+        assert code == 0
+        r = cut_plane_directions(72)
+        F = S.farfield(x, r).cpu().numpy()[0]
+        Fo = galerkin.far_field(case["P"], case["x"], r)
+        assert np.linalg.norm(F - Fo) / np.linalg.norm(Fo) < 1e-6
+    finally:
+        S.close()
 
 
 def test_sphere1280_mie():
