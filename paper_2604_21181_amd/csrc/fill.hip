@@ -451,10 +451,17 @@ constexpr int kPtStride = 37;   // 24 kernel reals, N_i(x), N_j(y); padded
 constexpr int kPtStrideNodal = 73;
 
 template <typename TS, bool DK = false, bool NODAL = false>
-__global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_ssq(SsqArgs<TS> a) {
+__global__ __launch_bounds__(NODAL ? 2 * kSsqThreads : kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
+void k_ssq(SsqArgs<TS> a) {
+    // NODAL: rows of 73 doubles put 75 KB of LDS on a workgroup (two per
+    // compute unit), and the 2x2 contractions make the consumers the larger
+    // part: four wavefronts per workgroup, the first two producing, all of
+    // them consuming (ten streams)
+    constexpr int kThr = NODAL ? 2 * kSsqThreads : kSsqThreads;
+    constexpr int kStr = NODAL ? 2 * kStreams : kStreams;
     constexpr int kStride = NODAL ? kPtStrideNodal : kPtStride;
     __shared__ double s_pt[kSsqThreads * kStride];
-    static_assert(kStreams * 36 * 24 <= kSsqThreads * kPtStride, "reduction buffer");
+    static_assert(kStr * 36 * 24 <= kSsqThreads * kStride, "reduction buffer");
     // NODAL: the tangents of the two triangles' nodes, s_tn[side][k][b][3]
     __shared__ double s_tn[NODAL ? 72 : 1];
     const int tid = threadIdx.x;
@@ -472,14 +479,14 @@ __global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 
     const int nreg = cls == 3 ? 6 : (cls == 2 ? 5 : 2);
     const int npts = nreg * n4;
     const int comp = tid % 24, stream = tid / 24;    // consumer role
-    const bool consumer = tid < 24 * kStreams;
+    const bool consumer = tid < 24 * kStr;
     double acc[36];
 #pragma unroll
     for (int k = 0; k < 36; ++k) acc[k] = 0.0;
     for (int base = 0; base < npts; base += kSsqThreads) {
         const int idx = base + tid;
         double *pt = s_pt + tid * kStride;
-        if (idx < npts) {
+        if (tid < kSsqThreads && idx < npts) {
             const int r = idx / n4;
             int g = idx % n4;
             const int i3 = g % n; g /= n;
@@ -518,14 +525,14 @@ __global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 
                         }
                     }
             }
-        } else {
+        } else if (tid < kSsqThreads) {
 #pragma unroll
             for (int q = 0; q < (NODAL ? 72 : 36); ++q) pt[q] = 0.0;
         }
         __syncthreads();
         if (consumer) {
             if constexpr (!NODAL) {
-                for (int r = stream; r < kSsqThreads; r += kStreams) {
+                for (int r = stream; r < kSsqThreads; r += kStr) {
                     const double *row = s_pt + r * kStride;
                     const double kv = row[comp];
                     double u[6];
@@ -543,7 +550,7 @@ __global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 
                 // sum_{gamma,delta} A_i[alpha][gamma] B_j[beta][delta] k[op,gamma,delta]
                 const int c = comp >> 1, ri = comp & 1;
                 const int op = c >> 2, al = (c >> 1) & 1, be = c & 1;
-                for (int r = stream; r < kSsqThreads; r += kStreams) {
+                for (int r = stream; r < kSsqThreads; r += kStr) {
                     const double *row = s_pt + r * kStride;
                     const double k00 = row[2 * (4 * op) + ri], k01 = row[2 * (4 * op + 1) + ri];
                     const double k10 = row[2 * (4 * op + 2) + ri], k11 = row[2 * (4 * op + 3) + ri];
@@ -572,11 +579,11 @@ __global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 
     }
     __syncthreads();
     const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
-    for (int it = tid; it < 36 * 12; it += kSsqThreads) {
+    for (int it = tid; it < 36 * 12; it += kThr) {
         const int k = it / 12, cc = it % 12;
         double re = 0, im = 0;
 #pragma unroll
-        for (int s = 0; s < kStreams; ++s) {
+        for (int s = 0; s < kStr; ++s) {
             re += s_pt[(s * 36 + k) * 24 + 2 * cc];
             im += s_pt[(s * 36 + k) * 24 + 2 * cc + 1];
         }
@@ -1090,7 +1097,8 @@ static int launch_ssq(mbem_op *op, hipStream_t s, const FillBand *band = nullptr
     if constexpr (PAPER)
         hipLaunchKernelGGL((k_ssq_paper<TS>), dim3((unsigned)a.npairs), dim3(kSsqThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_ssq<TS, DK, NODAL>), dim3((unsigned)a.npairs), dim3(kSsqThreads), 0, s, a);
+        hipLaunchKernelGGL((k_ssq<TS, DK, NODAL>), dim3((unsigned)a.npairs), dim3(NODAL ? 2 * kSsqThreads : kSsqThreads),
+                           0, s, a);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
