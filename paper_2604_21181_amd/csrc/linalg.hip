@@ -150,22 +150,38 @@ __global__ __launch_bounds__(256) void k_gemv3(int64_t n2, const TS *K1, const T
 
 struct Coef { double2 iw, ce, cm; };
 
-__global__ void k_combine(int64_t n2, const double2 *__restrict__ t,
-                          const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
-                          const double *__restrict__ mval, const double2 *__restrict__ xj,
-                          const double2 *__restrict__ xm, Coef c, double2 *__restrict__ y) {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= n2) return;
-    const int64_t i = r / 2;
-    const int al = (int)(r % 2);
-    double2 Mj = {0, 0}, Mm = {0, 0};
-    // mass: 2 x 2 block per node pair, value (al, be) at mval[4 s + 2 al + be]
-    for (int32_t s = mptr[i]; s < mptr[i + 1]; ++s) {
-        const int64_t col = 2 * (int64_t)mcol[s];
-        const double v0 = mval[4 * s + 2 * al], v1 = mval[4 * s + 2 * al + 1];
-        Mj.x += v0 * xj[col].x + v1 * xj[col + 1].x; Mj.y += v0 * xj[col].y + v1 * xj[col + 1].y;
-        Mm.x += v0 * xm[col].x + v1 * xm[col + 1].x; Mm.y += v0 * xm[col].y + v1 * xm[col + 1].y;
+// kCombLanes consecutive lanes per row split the row's mass slots (a vertex
+// node has 19, each a dependent index-then-value load) and add their partial
+// sums by shuffles in a fixed order.
+constexpr int kCombLanes = 8;
+__global__ __launch_bounds__(256) void k_combine(int64_t n2, const double2 *__restrict__ t,
+                                                 const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
+                                                 const double *__restrict__ mval, const double2 *__restrict__ xj,
+                                                 const double2 *__restrict__ xm, Coef c, double2 *__restrict__ y) {
+    const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t r = gt / kCombLanes;
+    const int l = (int)(gt % kCombLanes);
+    double mj[2] = {0, 0}, mm[2] = {0, 0};
+    if (r < n2) {
+        const int64_t i = r / 2;
+        const int al = (int)(r % 2);
+        // mass: 2 x 2 block per node pair, value (al, be) at mval[4 s + 2 al + be]
+        for (int32_t s = mptr[i] + l; s < mptr[i + 1]; s += kCombLanes) {
+            const int64_t col = 2 * (int64_t)mcol[s];
+            const double v0 = mval[4 * s + 2 * al], v1 = mval[4 * s + 2 * al + 1];
+            mj[0] += v0 * xj[col].x + v1 * xj[col + 1].x; mj[1] += v0 * xj[col].y + v1 * xj[col + 1].y;
+            mm[0] += v0 * xm[col].x + v1 * xm[col + 1].x; mm[1] += v0 * xm[col].y + v1 * xm[col + 1].y;
+        }
     }
+#pragma unroll
+    for (int o = kCombLanes / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            mj[k] += __shfl_xor(mj[k], o, kCombLanes);
+            mm[k] += __shfl_xor(mm[k], o, kCombLanes);
+        }
+    if (r >= n2 || l != 0) return;
+    const double2 Mj = {mj[0], mj[1]}, Mm = {mm[0], mm[1]};
     y[r] = cadd(cadd(cmul(c.iw, t[r]), t[2 * n2 + r]), cmul(c.ce, Mm));
     y[n2 + r] = csub(cadd(t[3 * n2 + r], cmul(c.cm, Mj)), cmul(c.iw, t[n2 + r]));
 }
@@ -189,7 +205,7 @@ int matvec_run(const mbem_op *op, const double2 *x, double2 *y, double2 *tmp, hi
     MBEM_HIP(hipGetLastError());
     if (after_gemv) MBEM_HIP(hipEventRecord(after_gemv, s));
     const mbem_mesh *m = op->mesh;
-    hipLaunchKernelGGL(k_combine, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, n2, tmp,
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)((n2 * kCombLanes + 255) / 256)), dim3(256), 0, s, n2, tmp,
                        m->d_mptr, m->d_mcol, op->d_mval, x, x + n2, coef_of(op), y);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
