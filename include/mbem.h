@@ -109,8 +109,8 @@ enum { MBEM_QUAD_DEFAULT = 0, MBEM_QUAD_PAPER = 1 };
  *   rotated test vector is t_alpha,i x n(x).  Same kernels (Sec. 4), same
  *   unknown layout; the mass matrix couples alpha and beta.  Its span does
  *   not depend on the reference-axis choice and far fields converge at high
- *   order.  With the default quadrature only; mbem_grad_sigma_ext returns
- *   the eps_r derivatives for it but rejects the shape outputs.
+ *   order.  Either quadrature; mbem_grad_sigma_ext returns the eps_r
+ *   derivatives for it but rejects the shape outputs.
  * Post-processing calls (right-hand side, far field, cross sections, far-
  * field functional) take the same value as the fill of the solution.      */
 enum { MBEM_FRAME_INTERPOLATED = 0, MBEM_FRAME_NODAL = 1 };

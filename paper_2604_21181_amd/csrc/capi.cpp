@@ -497,10 +497,6 @@ static int op_create(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p,
         set_error("unknown tangential frame");
         return MBEM_EINVAL;
     }
-    if (p->frame == MBEM_FRAME_NODAL && p->quadrature != MBEM_QUAD_DEFAULT) {
-        set_error("the node-attached frame is built for the default quadrature only");
-        return MBEM_EINVAL;
-    }
     MBEM_TRY(set_device(ctx));
     mbem_op *op = new (std::nothrow) mbem_op;
     if (!op) { set_error("host allocation"); return MBEM_ENOMEM; }

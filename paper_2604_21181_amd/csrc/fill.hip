@@ -450,140 +450,118 @@ constexpr int kPtStride = 37;   // 24 kernel reals, N_i(x), N_j(y); padded
 // N_i(x) t_alpha,i . t_gamma(x) and per trial node j N_j(y) t_beta,j . t_delta(y)
 constexpr int kPtStrideNodal = 73;
 
-template <typename TS, bool DK = false, bool NODAL = false>
-__global__ __launch_bounds__(NODAL ? 2 * kSsqThreads : kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
-void k_ssq(SsqArgs<TS> a) {
-    // NODAL: rows of 73 doubles put 75 KB of LDS on a workgroup (two per
-    // compute unit), and the 2x2 contractions make the consumers the larger
-    // part: four wavefronts per workgroup, the first two producing, all of
-    // them consuming (ten streams)
-    constexpr int kThr = NODAL ? 2 * kSsqThreads : kSsqThreads;
-    constexpr int kStr = NODAL ? 2 * kStreams : kStreams;
-    constexpr int kStride = NODAL ? kPtStrideNodal : kPtStride;
-    __shared__ double s_pt[kSsqThreads * kStride];
-    static_assert(kStr * 36 * 24 <= kSsqThreads * kStride, "reduction buffer");
-    // NODAL: the tangents of the two triangles' nodes, s_tn[side][k][b][3]
-    __shared__ double s_tn[NODAL ? 72 : 1];
-    const int tid = threadIdx.x;
-    const int64_t pid = blockIdx.x;
-    const int32_t e = a.pairs[4 * pid], f = a.pairs[4 * pid + 1];
-    if constexpr (NODAL) {
-        if (tid < 72) {
-            const int side = tid / 36, r = tid % 36, k = r / 6, b = (r / 3) % 2, d = r % 3;
-            s_tn[tid] = a.frames[9 * (int64_t)a.tri[6 * (side ? f : e) + k] + 3 + 3 * b + d];
-        }
-        __syncthreads();
+// Launch shape of the singular-pair kernels.  NODAL: rows of 73 doubles put
+// 75 KB of LDS on a workgroup (two per compute unit), and the 2 x 2
+// contractions make the consumers the larger part: four wavefronts per
+// workgroup, the first two producing, all of them consuming (ten streams).
+template <bool NODAL>
+struct SsqShape {
+    static constexpr int threads = NODAL ? 2 * kSsqThreads : kSsqThreads;
+    static constexpr int streams = NODAL ? 2 * kStreams : kStreams;
+    static constexpr int stride = NODAL ? kPtStrideNodal : kPtStride;
+    static_assert(streams * 36 * 24 <= kSsqThreads * stride, "reduction buffer");
+};
+
+// NODAL: the tangents of the two triangles' nodes, s_tn[side][k][b][3]
+__device__ __forceinline__ void ssq_stage_tangents(const double *frames, const int32_t *tri, int32_t e,
+                                                   int32_t f, double *s_tn, int tid) {
+    if (tid < 72) {
+        const int side = tid / 36, r = tid % 36, k = r / 6, b = (r / 3) % 2, d = r % 3;
+        s_tn[tid] = frames[9 * (int64_t)tri[6 * (side ? f : e) + k] + 3 + 3 * b + d];
     }
-    const int cls = a.pairs[4 * pid + 2], code = a.pairs[4 * pid + 3];
-    const int n = a.order, n4 = n * n * n * n;
-    const int nreg = cls == 3 ? 6 : (cls == 2 ? 5 : 2);
-    const int npts = nreg * n4;
-    const int comp = tid % 24, stream = tid / 24;    // consumer role
-    const bool consumer = tid < 24 * kStr;
-    double acc[36];
+}
+
+// One LDS row: the twelve kernel values, then the shape data of the point
+// pair (shape functions, or with node-attached tangents their products
+// with the nodal tangents' components in the two point frames).
+template <bool NODAL>
+__device__ __forceinline__ void ssq_row(double *pt, const cx<double> k[12], const P2Point &X, const P2Point &Y,
+                                        const double *s_tn) {
 #pragma unroll
-    for (int k = 0; k < 36; ++k) acc[k] = 0.0;
-    for (int base = 0; base < npts; base += kSsqThreads) {
-        const int idx = base + tid;
-        double *pt = s_pt + tid * kStride;
-        if (tid < kSsqThreads && idx < npts) {
-            const int r = idx / n4;
-            int g = idx % n4;
-            const int i3 = g % n; g /= n;
-            const int i2 = g % n; g /= n;
-            const int i1 = g % n; g /= n;
-            const int i0 = g;
-            double s1, t1, s2, t2;
-            const double jac = ss_region(cls, r, a.glx[i0], a.glx[i1], a.glx[i2], a.glx[i3], s1, t1, s2, t2);
-            const double wg = jac * a.glw[i0] * a.glw[i1] * a.glw[i2] * a.glw[i3];
-            double xe, ye, xf, yf;
-            ss_local(code & 63, s1, t1, xe, ye);
-            ss_local(code >> 6, s2, t2, xf, yf);
-            P2Point X, Y;
-            p2_point(a.xyz, a.frames, a.tri + 6 * e, xe, ye, X);
-            p2_point(a.xyz, a.frames, a.tri + 6 * f, xf, yf, Y);
-            const dvec3 ta[2] = {X.t1, X.t2}, sa[2] = {X.s1, X.s2}, tb[2] = {Y.t1, Y.t2};
-            cx<double> k[12];
-            kappa12<double, DK>(*a.K, X.x, X.n, ta, sa, Y.x, tb, wg * X.J * Y.J, k);
+    for (int q = 0; q < 12; ++q) { pt[2 * q] = k[q].re; pt[2 * q + 1] = k[q].im; }
+    if constexpr (!NODAL) {
 #pragma unroll
-            for (int q = 0; q < 12; ++q) { pt[2 * q] = k[q].re; pt[2 * q + 1] = k[q].im; }
-            if constexpr (!NODAL) {
+        for (int q = 0; q < 6; ++q) { pt[24 + q] = X.N[q]; pt[30 + q] = Y.N[q]; }
+    } else {
+        const dvec3 tx[2] = {X.t1, X.t2}, ty[2] = {Y.t1, Y.t2};
 #pragma unroll
-                for (int q = 0; q < 6; ++q) { pt[24 + q] = X.N[q]; pt[30 + q] = Y.N[q]; }
-            } else {
-                const dvec3 tx[2] = {X.t1, X.t2}, ty[2] = {Y.t1, Y.t2};
+        for (int q = 0; q < 6; ++q)
 #pragma unroll
-                for (int q = 0; q < 6; ++q)
+            for (int b = 0; b < 2; ++b) {
+                const double *ue = s_tn + 6 * q + 3 * b, *uf = s_tn + 36 + 6 * q + 3 * b;
+                const dvec3 te = {ue[0], ue[1], ue[2]}, tf = {uf[0], uf[1], uf[2]};
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        const double *ue = s_tn + 6 * q + 3 * b, *uf = s_tn + 36 + 6 * q + 3 * b;
-                        const dvec3 te = {ue[0], ue[1], ue[2]}, tf = {uf[0], uf[1], uf[2]};
-#pragma unroll
-                        for (int g = 0; g < 2; ++g) {
-                            pt[24 + 4 * q + 2 * b + g] = X.N[q] * dot(te, tx[g]);
-                            pt[48 + 4 * q + 2 * b + g] = Y.N[q] * dot(tf, ty[g]);
-                        }
-                    }
-            }
-        } else if (tid < kSsqThreads) {
-#pragma unroll
-            for (int q = 0; q < (NODAL ? 72 : 36); ++q) pt[q] = 0.0;
-        }
-        __syncthreads();
-        if (consumer) {
-            if constexpr (!NODAL) {
-                for (int r = stream; r < kSsqThreads; r += kStr) {
-                    const double *row = s_pt + r * kStride;
-                    const double kv = row[comp];
-                    double u[6];
-#pragma unroll
-                    for (int j = 0; j < 6; ++j) u[j] = row[30 + j] * kv;
-#pragma unroll
-                    for (int i = 0; i < 6; ++i) {
-                        const double nx = row[24 + i];
-#pragma unroll
-                        for (int j = 0; j < 6; ++j) acc[6 * i + j] += nx * u[j];
-                    }
-                }
-            } else {
-                // lane (c = 4 op + 2 alpha + beta, re / im): acc[i][j] +=
-                // sum_{gamma,delta} A_i[alpha][gamma] B_j[beta][delta] k[op,gamma,delta]
-                const int c = comp >> 1, ri = comp & 1;
-                const int op = c >> 2, al = (c >> 1) & 1, be = c & 1;
-                for (int r = stream; r < kSsqThreads; r += kStr) {
-                    const double *row = s_pt + r * kStride;
-                    const double k00 = row[2 * (4 * op) + ri], k01 = row[2 * (4 * op + 1) + ri];
-                    const double k10 = row[2 * (4 * op + 2) + ri], k11 = row[2 * (4 * op + 3) + ri];
-                    double u0[6], u1[6];
-#pragma unroll
-                    for (int j = 0; j < 6; ++j) {
-                        const double b0 = row[48 + 4 * j + 2 * be], b1 = row[48 + 4 * j + 2 * be + 1];
-                        u0[j] = b0 * k00 + b1 * k01;
-                        u1[j] = b0 * k10 + b1 * k11;
-                    }
-#pragma unroll
-                    for (int i = 0; i < 6; ++i) {
-                        const double a0 = row[24 + 4 * i + 2 * al], a1 = row[24 + 4 * i + 2 * al + 1];
-#pragma unroll
-                        for (int j = 0; j < 6; ++j) acc[6 * i + j] += a0 * u0[j] + a1 * u1[j];
-                    }
+                for (int g = 0; g < 2; ++g) {
+                    pt[24 + 4 * q + 2 * b + g] = X.N[q] * dot(te, tx[g]);
+                    pt[48 + 4 * q + 2 * b + g] = Y.N[q] * dot(tf, ty[g]);
                 }
             }
-        }
-        __syncthreads();
     }
-    // stream partial sums: s_pt[(stream * 36 + k) * 24 + comp]
-    if (consumer) {
+}
+
+// Consumer lane (component comp = 2 c + re/im, stream): accumulate its
+// stream's rows of the batch into acc[i][j].
+template <bool NODAL>
+__device__ __forceinline__ void ssq_consume(const double *s_pt, int stream, int comp, double acc[36]) {
+    using Sh = SsqShape<NODAL>;
+    if constexpr (!NODAL) {
+        for (int r = stream; r < kSsqThreads; r += Sh::streams) {
+            const double *row = s_pt + r * Sh::stride;
+            const double kv = row[comp];
+            double u[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) u[j] = row[30 + j] * kv;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                const double nx = row[24 + i];
+#pragma unroll
+                for (int j = 0; j < 6; ++j) acc[6 * i + j] += nx * u[j];
+            }
+        }
+    } else {
+        // lane (c = 4 op + 2 alpha + beta, re / im): acc[i][j] +=
+        // sum_{gamma,delta} A_i[alpha][gamma] B_j[beta][delta] k[op,gamma,delta]
+        const int c = comp >> 1, ri = comp & 1;
+        const int op = c >> 2, al = (c >> 1) & 1, be = c & 1;
+        for (int r = stream; r < kSsqThreads; r += Sh::streams) {
+            const double *row = s_pt + r * Sh::stride;
+            const double k00 = row[2 * (4 * op) + ri], k01 = row[2 * (4 * op + 1) + ri];
+            const double k10 = row[2 * (4 * op + 2) + ri], k11 = row[2 * (4 * op + 3) + ri];
+            double u0[6], u1[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                const double b0 = row[48 + 4 * j + 2 * be], b1 = row[48 + 4 * j + 2 * be + 1];
+                u0[j] = b0 * k00 + b1 * k01;
+                u1[j] = b0 * k10 + b1 * k11;
+            }
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                const double a0 = row[24 + 4 * i + 2 * al], a1 = row[24 + 4 * i + 2 * al + 1];
+#pragma unroll
+                for (int j = 0; j < 6; ++j) acc[6 * i + j] += a0 * u0[j] + a1 * u1[j];
+            }
+        }
+    }
+}
+
+// Sum the consumer streams through LDS in a fixed order and add the pair's
+// 6 x 6 x 12 block to Z (atomics: a node pair collects several element pairs).
+template <typename TS, bool NODAL>
+__device__ __forceinline__ void ssq_flush(const SsqArgs<TS> &a, int32_t e, int32_t f, double *s_pt,
+                                          const double acc[36], int tid) {
+    using Sh = SsqShape<NODAL>;
+    const int comp = tid % 24, stream = tid / 24;
+    if (tid < 24 * Sh::streams) {
 #pragma unroll
         for (int k = 0; k < 36; ++k) s_pt[(stream * 36 + k) * 24 + comp] = acc[k];
     }
     __syncthreads();
     const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
-    for (int it = tid; it < 36 * 12; it += kThr) {
+    for (int it = tid; it < 36 * 12; it += Sh::threads) {
         const int k = it / 12, cc = it % 12;
         double re = 0, im = 0;
 #pragma unroll
-        for (int s = 0; s < kStr; ++s) {
+        for (int s = 0; s < Sh::streams; ++s) {
             re += s_pt[(s * 36 + k) * 24 + 2 * cc];
             im += s_pt[(s * 36 + k) * 24 + 2 * cc + 1];
         }
@@ -595,6 +573,64 @@ void k_ssq(SsqArgs<TS> a) {
         atomic_add(dst, re);
         atomic_add(dst + 1, im);
     }
+}
+
+template <typename TS, bool DK = false, bool NODAL = false>
+__global__ __launch_bounds__(SsqShape<NODAL>::threads) __attribute__((amdgpu_waves_per_eu(2, 8)))
+void k_ssq(SsqArgs<TS> a) {
+    using Sh = SsqShape<NODAL>;
+    __shared__ double s_pt[kSsqThreads * Sh::stride];
+    __shared__ double s_tn[NODAL ? 72 : 1];
+    const int tid = threadIdx.x;
+    const int64_t pid = blockIdx.x;
+    const int32_t e = a.pairs[4 * pid], f = a.pairs[4 * pid + 1];
+    if constexpr (NODAL) {
+        ssq_stage_tangents(a.frames, a.tri, e, f, s_tn, tid);
+        __syncthreads();
+    }
+    const int cls = a.pairs[4 * pid + 2], code = a.pairs[4 * pid + 3];
+    const int n = a.order, n4 = n * n * n * n;
+    const int nreg = cls == 3 ? 6 : (cls == 2 ? 5 : 2);
+    const int npts = nreg * n4;
+    const int comp = tid % 24, stream = tid / 24;    // consumer role
+    const bool consumer = tid < 24 * Sh::streams;
+    double acc[36];
+#pragma unroll
+    for (int k = 0; k < 36; ++k) acc[k] = 0.0;
+    for (int base = 0; base < npts; base += kSsqThreads) {
+        const int idx = base + tid;
+        if (tid < kSsqThreads) {
+            double *pt = s_pt + tid * Sh::stride;
+            if (idx < npts) {
+                const int r = idx / n4;
+                int g = idx % n4;
+                const int i3 = g % n; g /= n;
+                const int i2 = g % n; g /= n;
+                const int i1 = g % n; g /= n;
+                const int i0 = g;
+                double s1, t1, s2, t2;
+                const double jac = ss_region(cls, r, a.glx[i0], a.glx[i1], a.glx[i2], a.glx[i3], s1, t1, s2, t2);
+                const double wg = jac * a.glw[i0] * a.glw[i1] * a.glw[i2] * a.glw[i3];
+                double xe, ye, xf, yf;
+                ss_local(code & 63, s1, t1, xe, ye);
+                ss_local(code >> 6, s2, t2, xf, yf);
+                P2Point X, Y;
+                p2_point(a.xyz, a.frames, a.tri + 6 * e, xe, ye, X);
+                p2_point(a.xyz, a.frames, a.tri + 6 * f, xf, yf, Y);
+                const dvec3 ta[2] = {X.t1, X.t2}, sa[2] = {X.s1, X.s2}, tb[2] = {Y.t1, Y.t2};
+                cx<double> k[12];
+                kappa12<double, DK>(*a.K, X.x, X.n, ta, sa, Y.x, tb, wg * X.J * Y.J, k);
+                ssq_row<NODAL>(pt, k, X, Y, s_tn);
+            } else {
+#pragma unroll
+                for (int q = 0; q < (NODAL ? 72 : 36); ++q) pt[q] = 0.0;
+            }
+        }
+        __syncthreads();
+        if (consumer) ssq_consume<NODAL>(s_pt, stream, comp, acc);
+        __syncthreads();
+    }
+    ssq_flush<TS, NODAL>(a, e, f, s_pt, acc, tid);
 }
 
 // ------------------------------------- the paper's own scheme ---
@@ -627,10 +663,15 @@ __device__ __forceinline__ void contract12(const cx<T> v[kQP12], cx<T> out[6]) {
     }
 }
 
-template <typename T, typename TS>
+template <typename T, typename TS, bool NODAL = false>
 __global__ __launch_bounds__(256) void k_regular12(RegArgs<T, TS> a) {
     __shared__ cx<T> s_k[12 * kK12Stride];
     __shared__ cx<T> s_tf[12 * kChunk * kQP12 * 6];   // [c][fs][p][j]
+    // NODAL (node-attached tangents, as k_regular): s_ra[p][i][alpha][gamma]
+    // = N_i(x_p) t_alpha,i . t_gamma(x_p), s_rb[fs][q][j][beta][delta] likewise
+    constexpr int kR12 = kQP12 * 24;
+    __shared__ T s_ra[NODAL ? kR12 : 1];
+    __shared__ T s_rb[NODAL ? kChunk * kR12 : 1];
     constexpr bool kF64 = std::is_same<TS, double>::value;
     __shared__ __align__(16) TS s_dst[kF64 ? 1 : 2 * 6 * kItemsMax];
     constexpr int kRounds = (kItemsMax + 255) / 256;
@@ -669,6 +710,22 @@ __global__ __launch_bounds__(256) void k_regular12(RegArgs<T, TS> a) {
             }
         }
         s_act[tid] = kind;
+    }
+    if constexpr (NODAL) {
+        const int64_t nq12 = a.nt * kQP12;
+        for (int it = tid; it < (kChunk + 1) * kR12; it += blockDim.x) {
+            const int side = it / kR12, r = it % kR12;          // side 0: test, 1 + fs: trial
+            const int pq = r / 24, j = (r / 4) % 6, b = (r / 2) % 2, g = r % 2;
+            const int64_t el = side == 0 ? e : ch * kChunk + side - 1;
+            T v = 0;
+            if (el < a.nt) {
+                const double *t = a.frames + 9 * (int64_t)a.tri[6 * el + j] + 3 + 3 * b;
+                const vec3<T> tg = qload(a.qp, nq12, g ? QT2 : QT1, el * kQP12 + pq);
+                v = (T)n12(pq, j) * ((T)t[0] * tg.x + (T)t[1] * tg.y + (T)t[2] * tg.z);
+            }
+            if (side == 0) s_ra[r] = v;
+            else s_rb[(side - 1) * kR12 + r] = v;
+        }
     }
     __syncthreads();
     int any = 0;
@@ -744,14 +801,35 @@ __global__ __launch_bounds__(256) void k_regular12(RegArgs<T, TS> a) {
             for (int c = 0; c < 12; ++c) s_k[c * kK12Stride + tid] = k[c];
         }
         __syncthreads();
-        if (tid < kPP12) {
-            const int c = tid / kQP12, p = tid % kQP12;
-            cx<T> kv[kQP12], tf[6];
+        if constexpr (!NODAL) {
+            if (tid < kPP12) {
+                const int c = tid / kQP12, p = tid % kQP12;
+                cx<T> kv[kQP12], tf[6];
 #pragma unroll
-            for (int q = 0; q < kQP12; ++q) kv[q] = s_k[c * kK12Stride + p * kQP12 + q];
-            contract12(kv, tf);
+                for (int q = 0; q < kQP12; ++q) kv[q] = s_k[c * kK12Stride + p * kQP12 + q];
+                contract12(kv, tf);
 #pragma unroll
-            for (int j = 0; j < 6; ++j) s_tf[((c * kChunk + fs) * kQP12 + p) * 6 + j] = tf[j];
+                for (int j = 0; j < 6; ++j) s_tf[((c * kChunk + fs) * kQP12 + p) * 6 + j] = tf[j];
+            }
+        } else if (tid < 6 * kQP12) {
+            // the two delta components of (op, gamma) become the two beta ones
+            const int og = tid / kQP12, p = tid % kQP12;     // og = 2 op + gamma
+            const cx<T> *k0 = s_k + (2 * og) * kK12Stride + p * kQP12, *k1 = k0 + kK12Stride;
+            const T *rb = s_rb + fs * kR12;
+            cx<T> *d0 = s_tf + (((2 * og) * kChunk + fs) * kQP12 + p) * 6;
+            cx<T> *d1 = s_tf + (((2 * og + 1) * kChunk + fs) * kQP12 + p) * 6;
+#pragma unroll 1
+            for (int j = 0; j < 6; ++j) {
+                cx<T> o0 = {0, 0}, o1 = {0, 0};
+#pragma unroll
+                for (int q = 0; q < kQP12; ++q) {
+                    const T *w = rb + (q * 6 + j) * 4;
+                    o0 = o0 + w[0] * k0[q] + w[1] * k1[q];
+                    o1 = o1 + w[2] * k0[q] + w[3] * k1[q];
+                }
+                d0[j] = o0;
+                d1[j] = o1;
+            }
         }
         __syncthreads();
     }
@@ -764,20 +842,42 @@ __global__ __launch_bounds__(256) void k_regular12(RegArgs<T, TS> a) {
         const int g = (int)(((float)it + 0.5f) * inv_rowlen);
         const int rem = it - g * rowlen;
         const int sl = rem >> 1, be = rem & 1, op = g >> 1;
-        const int c = 2 * g + be;
-        cx<T> tv[kQP12];
-#pragma unroll
-        for (int p = 0; p < kQP12; ++p) tv[p] = cx<T>{0, 0};
         const int u1 = s_rec[26 + sl];
-        for (int u = s_rec[25 + sl]; u < u1; ++u) {
-            const int fl = s_rec[50 + u];
-            const cx<T> *src = s_tf + ((c * kChunk + (fl >> 3)) * kQP12) * 6 + (fl & 7);
+        cx<T> out[6];
+        if constexpr (!NODAL) {
+            const int c = 2 * g + be;
+            cx<T> tv[kQP12];
 #pragma unroll
-            for (int p = 0; p < kQP12; ++p) tv[p] = tv[p] + src[6 * p];
+            for (int p = 0; p < kQP12; ++p) tv[p] = cx<T>{0, 0};
+            for (int u = s_rec[25 + sl]; u < u1; ++u) {
+                const int fl = s_rec[50 + u];
+                const cx<T> *src = s_tf + ((c * kChunk + (fl >> 3)) * kQP12) * 6 + (fl & 7);
+#pragma unroll
+                for (int p = 0; p < kQP12; ++p) tv[p] = tv[p] + src[6 * p];
+            }
+            contract12(tv, out);
+        } else {
+            // components (op, gamma, beta), gamma = 0, 1: 4 op + beta, 4 op + 2 + beta
+            const int al = g & 1, c0 = 4 * op + be, u0 = s_rec[25 + sl];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) out[i] = cx<T>{0, 0};
+#pragma unroll 1
+            for (int p = 0; p < kQP12; ++p) {
+                cx<T> t0 = {0, 0}, t1 = {0, 0};
+                for (int u = u0; u < u1; ++u) {
+                    const int fl = s_rec[50 + u];
+                    const cx<T> *src0 = s_tf + ((c0 * kChunk + (fl >> 3)) * kQP12 + p) * 6 + (fl & 7);
+                    t0 = t0 + src0[0];
+                    t1 = t1 + src0[2 * kChunk * kQP12 * 6];
+                }
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    const T *w = s_ra + (p * 6 + i) * 4 + 2 * al;
+                    out[i] = out[i] + w[0] * t0 + w[1] * t1;
+                }
+            }
         }
         TS *Z = zblock(a.Z, op) + 2 * (2 * (int64_t)s_rec[1 + sl] + be);
-        cx<T> out[6];
-        contract12(tv, out);
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
             TS *dst = Z + s_row[g][i];
@@ -800,103 +900,73 @@ __global__ __launch_bounds__(256) void k_regular12(RegArgs<T, TS> a) {
 // of the 12-point rule with the remainders (constants a.K[0] = the kernels,
 // a.K[1] = the shifted truncated series of the remainders); the
 // accumulation into the pair's 6 x 6 x 12 block is that of k_ssq.
-template <typename TS>
-__global__ __launch_bounds__(kSsqThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
+template <typename TS, bool NODAL = false>
+__global__ __launch_bounds__(SsqShape<NODAL>::threads) __attribute__((amdgpu_waves_per_eu(2, 8)))
 void k_ssq_paper(SsqArgs<TS> a) {
-    __shared__ double s_pt[kSsqThreads * kPtStride];
+    using Sh = SsqShape<NODAL>;
+    __shared__ double s_pt[kSsqThreads * Sh::stride];
+    __shared__ double s_tn[NODAL ? 72 : 1];
     const int tid = threadIdx.x;
     const int64_t pid = blockIdx.x;
     const int32_t e = a.pairs[4 * pid], f = a.pairs[4 * pid + 1];
+    if constexpr (NODAL) {
+        ssq_stage_tangents(a.frames, a.tri, e, f, s_tn, tid);
+        __syncthreads();
+    }
     const int cls = a.pairs[4 * pid + 2], code = a.pairs[4 * pid + 3];
     const int n = a.order, n4 = n * n * n * n;
     const int nreg = cls == 3 ? 6 : (cls == 2 ? 5 : 2);
     const int nssq = nreg * n4, npts = nssq + kPP12;
     const int comp = tid % 24, stream = tid / 24;
-    const bool consumer = tid < 24 * kStreams;
+    const bool consumer = tid < 24 * Sh::streams;
     double acc[36];
 #pragma unroll
     for (int k = 0; k < 36; ++k) acc[k] = 0.0;
     for (int base = 0; base < npts; base += kSsqThreads) {
         const int idx = base + tid;
-        double *pt = s_pt + tid * kPtStride;
-        if (idx < npts) {
-            P2Point X, Y;
-            cx<double> k[12];
-            if (idx < nssq) {
-                const int r = idx / n4;
-                int g = idx % n4;
-                const int i3 = g % n; g /= n;
-                const int i2 = g % n; g /= n;
-                const int i1 = g % n; g /= n;
-                const int i0 = g;
-                double s1, t1, s2, t2;
-                const double jac = ss_region(cls, r, a.glx[i0], a.glx[i1], a.glx[i2], a.glx[i3], s1, t1, s2, t2);
-                const double wg = jac * a.glw[i0] * a.glw[i1] * a.glw[i2] * a.glw[i3];
-                double xe, ye, xf, yf;
-                ss_local(code & 63, s1, t1, xe, ye);
-                ss_local(code >> 6, s2, t2, xf, yf);
-                p2_point(a.xyz, a.frames, a.tri + 6 * e, xe, ye, X);
-                p2_point(a.xyz, a.frames, a.tri + 6 * f, xf, yf, Y);
-                const dvec3 ta[2] = {X.t1, X.t2}, sa[2] = {X.s1, X.s2}, tb[2] = {Y.t1, Y.t2};
-                kappa12_sing(a.K[0], X.x, X.n, ta, sa, Y.x, tb, wg * X.J * Y.J, k);
-            } else {
-                const int rr = idx - nssq, p = rr / kQP12, q = rr % kQP12;
-                double xe, ye, we, xf, yf, wf;
-                rule12(p, xe, ye, we);
-                rule12(q, xf, yf, wf);
-                p2_point(a.xyz, a.frames, a.tri + 6 * e, xe, ye, X);
-                p2_point(a.xyz, a.frames, a.tri + 6 * f, xf, yf, Y);
-                const dvec3 ta[2] = {X.t1, X.t2}, sa[2] = {X.s1, X.s2}, tb[2] = {Y.t1, Y.t2};
-                kappa12_rem(a.K[0], a.K[1], X.x, X.n, ta, sa, Y.x, tb, we * wf * X.J * Y.J, k);
-            }
-#pragma unroll
-            for (int q = 0; q < 12; ++q) { pt[2 * q] = k[q].re; pt[2 * q + 1] = k[q].im; }
-#pragma unroll
-            for (int q = 0; q < 6; ++q) { pt[24 + q] = X.N[q]; pt[30 + q] = Y.N[q]; }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 36; ++q) pt[q] = 0.0;
-        }
-        __syncthreads();
-        if (consumer) {
-            for (int r = stream; r < kSsqThreads; r += kStreams) {
-                const double *row = s_pt + r * kPtStride;
-                const double kv = row[comp];
-                double u[6];
-#pragma unroll
-                for (int j = 0; j < 6; ++j) u[j] = row[30 + j] * kv;
-#pragma unroll
-                for (int i = 0; i < 6; ++i) {
-                    const double nx = row[24 + i];
-#pragma unroll
-                    for (int j = 0; j < 6; ++j) acc[6 * i + j] += nx * u[j];
+        if (tid < kSsqThreads) {
+            double *pt = s_pt + tid * Sh::stride;
+            if (idx < npts) {
+                P2Point X, Y;
+                cx<double> k[12];
+                if (idx < nssq) {
+                    const int r = idx / n4;
+                    int g = idx % n4;
+                    const int i3 = g % n; g /= n;
+                    const int i2 = g % n; g /= n;
+                    const int i1 = g % n; g /= n;
+                    const int i0 = g;
+                    double s1, t1, s2, t2;
+                    const double jac = ss_region(cls, r, a.glx[i0], a.glx[i1], a.glx[i2], a.glx[i3], s1, t1, s2, t2);
+                    const double wg = jac * a.glw[i0] * a.glw[i1] * a.glw[i2] * a.glw[i3];
+                    double xe, ye, xf, yf;
+                    ss_local(code & 63, s1, t1, xe, ye);
+                    ss_local(code >> 6, s2, t2, xf, yf);
+                    p2_point(a.xyz, a.frames, a.tri + 6 * e, xe, ye, X);
+                    p2_point(a.xyz, a.frames, a.tri + 6 * f, xf, yf, Y);
+                    const dvec3 ta[2] = {X.t1, X.t2}, sa[2] = {X.s1, X.s2}, tb[2] = {Y.t1, Y.t2};
+                    kappa12_sing(a.K[0], X.x, X.n, ta, sa, Y.x, tb, wg * X.J * Y.J, k);
+                } else {
+                    const int rr = idx - nssq, p = rr / kQP12, q = rr % kQP12;
+                    double xe, ye, we, xf, yf, wf;
+                    rule12(p, xe, ye, we);
+                    rule12(q, xf, yf, wf);
+                    p2_point(a.xyz, a.frames, a.tri + 6 * e, xe, ye, X);
+                    p2_point(a.xyz, a.frames, a.tri + 6 * f, xf, yf, Y);
+                    const dvec3 ta[2] = {X.t1, X.t2}, sa[2] = {X.s1, X.s2}, tb[2] = {Y.t1, Y.t2};
+                    kappa12_rem(a.K[0], a.K[1], X.x, X.n, ta, sa, Y.x, tb, we * wf * X.J * Y.J, k);
                 }
+                ssq_row<NODAL>(pt, k, X, Y, s_tn);
+            } else {
+#pragma unroll
+                for (int q = 0; q < (NODAL ? 72 : 36); ++q) pt[q] = 0.0;
             }
         }
         __syncthreads();
+        if (consumer) ssq_consume<NODAL>(s_pt, stream, comp, acc);
+        __syncthreads();
     }
-    if (consumer) {
-#pragma unroll
-        for (int k = 0; k < 36; ++k) s_pt[(stream * 36 + k) * 24 + comp] = acc[k];
-    }
-    __syncthreads();
-    const int32_t *te = a.tri + 6 * e, *tf = a.tri + 6 * f;
-    for (int it = tid; it < 36 * 12; it += kSsqThreads) {
-        const int k = it / 12, cc = it % 12;
-        double re = 0, im = 0;
-#pragma unroll
-        for (int s = 0; s < kStreams; ++s) {
-            re += s_pt[(s * 36 + k) * 24 + 2 * cc];
-            im += s_pt[(s * 36 + k) * 24 + 2 * cc + 1];
-        }
-        const int i = k / 6, j = k % 6;
-        const int op = cc / 4, al = (cc / 2) % 2, be = cc % 2;
-        const int64_t tn = a.row_map ? a.row_map[te[i]] : te[i];
-        const int64_t row = 2 * tn + al, col = 2 * (int64_t)tf[j] + be;
-        TS *dst = zblock(a.Z, op) + 2 * (row * a.n2 + col);
-        atomic_add(dst, re);
-        atomic_add(dst + 1, im);
-    }
+    ssq_flush<TS, NODAL>(a, e, f, s_pt, acc, tid);
 }
 
 // ---------------------------------------------------------- mass ---
@@ -1064,7 +1134,7 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
             if (a.total == 0) continue;
             if (a.total > 0x7fffffffLL) { set_error("too many element pairs for one launch"); return MBEM_EINVAL; }
             if constexpr (P12)
-                hipLaunchKernelGGL((k_regular12<T, TS>), dim3((unsigned)a.total), dim3(256), 0, s, a);
+                hipLaunchKernelGGL((k_regular12<T, TS, NODAL>), dim3((unsigned)a.total), dim3(256), 0, s, a);
             else
                 hipLaunchKernelGGL((k_regular<T, TS, DK, NODAL>), dim3((unsigned)a.total), dim3(256), 0, s, a);
             MBEM_HIP(hipGetLastError());
@@ -1095,10 +1165,10 @@ static int launch_ssq(mbem_op *op, hipStream_t s, const FillBand *band = nullptr
     for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)(band ? band->Z[o] : op->K[o]);
     if (a.npairs == 0) return MBEM_OK;
     if constexpr (PAPER)
-        hipLaunchKernelGGL((k_ssq_paper<TS>), dim3((unsigned)a.npairs), dim3(kSsqThreads), 0, s, a);
+        hipLaunchKernelGGL((k_ssq_paper<TS, NODAL>), dim3((unsigned)a.npairs), dim3(SsqShape<NODAL>::threads), 0, s,
+                           a);
     else
-        hipLaunchKernelGGL((k_ssq<TS, DK, NODAL>), dim3((unsigned)a.npairs), dim3(NODAL ? 2 * kSsqThreads : kSsqThreads),
-                           0, s, a);
+        hipLaunchKernelGGL((k_ssq<TS, DK, NODAL>), dim3((unsigned)a.npairs), dim3(SsqShape<NODAL>::threads), 0, s, a);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
@@ -1189,10 +1259,6 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     if (paper && deriv) { set_error("the eps derivative is built for the default quadrature only"); return MBEM_EINVAL; }
     if (deriv && op->prec != MBEM_FP64) { set_error("derivative operators are filled in FP64"); return MBEM_EINVAL; }
     const bool nodal = op->p.frame == MBEM_FRAME_NODAL;
-    if (nodal && paper) {
-        set_error("the node-attached frame is filled with the default quadrature");
-        return MBEM_EINVAL;
-    }
     MBEM_TRY(fill_prepare(op, s, deriv));
     FillState *f = op->fs;
     hipEvent_t *ev = f->ev;
@@ -1207,9 +1273,11 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     MBEM_HIP(hipEventRecord(ev[1], s));
     unsigned long long *cnt = f->counted ? f->d_cnt : nullptr;
     if (paper && op->prec == MBEM_FP64) {
-        MBEM_TRY((launch_regular<double, double, false, true>(op, 0, m->d_qp12, nullptr, s)));
+        if (nodal) MBEM_TRY((launch_regular<double, double, false, true, true>(op, 0, m->d_qp12, nullptr, s)));
+        else MBEM_TRY((launch_regular<double, double, false, true>(op, 0, m->d_qp12, nullptr, s)));
     } else if (paper) {
-        MBEM_TRY((launch_regular<float, float, false, true>(op, 1, m->d_qp12_32, cnt, s)));
+        if (nodal) MBEM_TRY((launch_regular<float, float, false, true, true>(op, 1, m->d_qp12_32, cnt, s)));
+        else MBEM_TRY((launch_regular<float, float, false, true>(op, 1, m->d_qp12_32, cnt, s)));
     } else if (deriv) {
         if (nodal) MBEM_TRY((launch_regular<double, double, true, false, true>(op, 0, m->d_qp, nullptr, s)));
         else MBEM_TRY((launch_regular<double, double, true>(op, 0, m->d_qp, nullptr, s)));
@@ -1222,7 +1290,9 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     }
     MBEM_HIP(hipEventRecord(ev[2], s));
     MBEM_HIP(hipEventRecord(ev[3], s));   // near pairs run inside the regular launches
-    if (paper && op->prec == MBEM_FP64) MBEM_TRY((launch_ssq<double, false, true>(op, s)));
+    if (paper && op->prec == MBEM_FP64 && nodal) MBEM_TRY((launch_ssq<double, false, true, true>(op, s)));
+    else if (paper && op->prec == MBEM_FP64) MBEM_TRY((launch_ssq<double, false, true>(op, s)));
+    else if (paper && nodal) MBEM_TRY((launch_ssq<float, false, true, true>(op, s)));
     else if (paper) MBEM_TRY((launch_ssq<float, false, true>(op, s)));
     else if (deriv && nodal) MBEM_TRY((launch_ssq<double, true, false, true>(op, s)));
     else if (deriv) MBEM_TRY((launch_ssq<double, true>(op, s)));
