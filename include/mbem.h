@@ -109,8 +109,9 @@ enum { MBEM_QUAD_DEFAULT = 0, MBEM_QUAD_PAPER = 1 };
  *   rotated test vector is t_alpha,i x n(x).  Same kernels (Sec. 4), same
  *   unknown layout; the mass matrix couples alpha and beta.  Its span does
  *   not depend on the reference-axis choice and far fields converge at high
- *   order.  Either quadrature; mbem_grad_sigma_ext returns the eps_r
- *   derivatives for it but rejects the shape outputs.
+ *   order.  Either quadrature; every entry point takes it except
+ *   mbem_grad_sigma_ext's shape outputs with the paper quadrature (the
+ *   gradient is built for the default quadrature).
  * Post-processing calls (right-hand side, far field, cross sections, far-
  * field functional) take the same value as the fill of the solution.      */
 enum { MBEM_FRAME_INTERPOLATED = 0, MBEM_FRAME_NODAL = 1 };
@@ -290,8 +291,9 @@ int mbem_farfield_functional(mbem_ctx *ctx, const mbem_mesh *mesh,
  *   dsig_dx device [n_nodes*3] float64 or NULL: derivative for every
  *     coordinate of every node (Morton order);
  *   stats: the adjoint solve.
- * params and op must use the same frame; with MBEM_FRAME_NODAL the shape
- * outputs must be NULL (EINVAL otherwise).                                 */
+ * params and op must use the same frame (EINVAL otherwise).  With
+ * MBEM_FRAME_NODAL the reverse pass goes through the projections of the
+ * node-attached fields and the nodal triads instead of the point frame.    */
 int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh,
                         const mbem_params *params, const mbem_c128 *x,
                         const double *khat, const mbem_c128 *pol,

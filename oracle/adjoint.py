@@ -50,17 +50,17 @@ def dK_deps(xyz, tri, k0, eps_r, h=1e-3, mu_r=1.0, frame=0):
     return richardson(K, complex(eps_r), h)
 
 
-def dsigma_ddirs(xyz, tri, k0, eps_r, khat, pol, dirs, h=1e-4):
+def dsigma_ddirs(xyz, tri, k0, eps_r, khat, pol, dirs, h=1e-4, frame=0):
     """d sigma / dt for the node displacement x -> x + t dirs ([n_nodes, 3])."""
-    f = lambda t: solve_sigma_ext(xyz + t * dirs, tri, k0, eps_r, khat, pol)[0]
+    f = lambda t: solve_sigma_ext(xyz + t * dirs, tri, k0, eps_r, khat, pol, frame=frame)[0]
     return richardson(f, 0.0, h)
 
 
-def dsigma_dnormal(xyz, tri, k0, eps_r, khat, pol, weights, h=1e-4):
+def dsigma_dnormal(xyz, tri, k0, eps_r, khat, pol, weights, h=1e-4, frame=0):
     """d sigma / dt for the displacement x_v -> x_v + t weights_v n_v of
     every node, n_v the nodal normals of the unperturbed mesh (held fixed),
     by differences of the whole discrete map.  One node: a unit weight."""
     n0, _, _ = core.nodal_frames(xyz, tri)
     dirs = np.asarray(weights, dtype=np.float64)[:, None] * n0
-    f = lambda t: solve_sigma_ext(xyz + t * dirs, tri, k0, eps_r, khat, pol)[0]
+    f = lambda t: solve_sigma_ext(xyz + t * dirs, tri, k0, eps_r, khat, pol, frame=frame)[0]
     return richardson(f, 0.0, h)

@@ -783,10 +783,6 @@ int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh, const
         return MBEM_EINVAL;
     }
     if (p->frame != op->p.frame) { set_error("the parameters' frame differs from the operator's"); return MBEM_EINVAL; }
-    if ((dsig_dnode || dsig_dx) && p->frame != MBEM_FRAME_INTERPOLATED) {
-        set_error("the shape gradient is built for the interpolated frame only");
-        return MBEM_EINVAL;
-    }
     MBEM_TRY(set_device(ctx));
     const hipStream_t s = ctx->stream;
     const int64_t N = 2 * op->n2;

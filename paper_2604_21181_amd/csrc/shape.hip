@@ -21,6 +21,10 @@
 // Gram-Schmidt frame to node positions and nodal tangents, and through the
 // nodal triads and metric-weighted normals to node positions.  The pair
 // classes and the choice of reference vector are held fixed.
+// Node-attached tangents (NODAL): the point vectors are p = m - (m.n) n with
+// m = sum_k N_k sum_b c_kb t_b,k; their adjoints are kept as vectors and
+// carried back through that projection to the normal and to the nodal
+// tangents, which then go through the nodal triads as above.
 #include <cmath>
 
 #include "mbem_internal.h"
@@ -148,19 +152,75 @@ struct SPt {
     double W;
     cxd X[4];
 };
+// NODAL (node-attached tangents): the adjoints of the point's vectors p1, p2
+// (test) and vj, vm (trial) themselves, complex and not yet reduced to Im,
+// in place of those of the point frame.
 struct TGrad {
     dvec3 x, n, t1, t2;
     double W;
+    cv3 p1, p2;
 };
 struct SGrad {
     dvec3 y, t1, t2;
     double W;
+    cv3 vj, vm;
 };
-__device__ inline void zero(TGrad &g) { g = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}, 0.0}; }
-__device__ inline void zero(SGrad &g) { g = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, 0.0}; }
+__device__ inline cv3 czero3() { return {{0, 0}, {0, 0}, {0, 0}}; }
+__device__ inline void zero(TGrad &g) {
+    g.x = g.n = g.t1 = g.t2 = {0, 0, 0};
+    g.W = 0.0;
+    g.p1 = g.p2 = czero3();
+}
+__device__ inline void zero(SGrad &g) {
+    g.y = g.t1 = g.t2 = {0, 0, 0};
+    g.W = 0.0;
+    g.vj = g.vm = czero3();
+}
+
+// Node-attached field of the coefficients c (node v, component b at
+// c[2 v + b]) at a point with shape functions N: m = sum_k N_k sum_b c_kb t_b,k
+// (the nodal tangents, not yet projected on the point's tangent plane).
+__device__ inline cv3 nodal_field(const double *__restrict__ frames, const int32_t *t, const double N[6],
+                                  const double2 *__restrict__ c) {
+    cv3 m = czero3();
+    for (int k = 0; k < 6; ++k) {
+        const int64_t v = t[k];
+        for (int b = 0; b < 2; ++b) {
+            const double2 cf = c[2 * v + b];
+            m = m + cxd{N[k] * cf.x, N[k] * cf.y} * nodal_tangent(frames, v, b);
+        }
+    }
+    return m;
+}
+
+// Reverse of p = m - (m.n) n for the adjoint G of p (Im(G.p) is the
+// quantity): adds the normal's part to bn and returns the adjoint of m.
+__device__ inline cv3 proj_reverse(cv3 G, cv3 m, dvec3 n, dvec3 &bn) {
+    const cxd mn = cdot(m, n), Gn = cdot(G, n);
+    bn = bn - im3(Gn * m + mn * G);
+    return G - Gn * n;
+}
+
+// Node-tangent adjoints of one point: Im(N_k sum_f c_f[kb] G_f) for the
+// fields f built from the coefficient vectors c_f (nf of them).
+template <int NF>
+__device__ inline void nodal_tangent_adjoint(const int32_t *t, const double N[6], const double2 *const c[NF],
+                                             const cv3 G[NF], dvec3 gT1[6], dvec3 gT2[6]) {
+    for (int k = 0; k < 6; ++k) {
+        const int64_t v = t[k];
+        cv3 g[2] = {czero3(), czero3()};
+        for (int f = 0; f < NF; ++f)
+            for (int b = 0; b < 2; ++b) {
+                const double2 cf = c[f][2 * v + b];
+                g[b] = g[b] + cxd{N[k] * cf.x, N[k] * cf.y} * G[f];
+            }
+        gT1[k] = im3(g[0]);
+        gT2[k] = im3(g[1]);
+    }
+}
 
 // Adds d Im(c) / d(point quantities) for c = -wfac W_x W_y F.
-template <bool WT, bool WS>
+template <bool WT, bool WS, bool NODAL = false>
 __device__ void pair_adjoint(const KernelConst &K, cxd iw, const TPt &P, const SPt &Q, double wfac, TGrad &gt,
                              SGrad &gs) {
     const dvec3 Rv = P.x - Q.y;
@@ -192,28 +252,43 @@ __device__ void pair_adjoint(const KernelConst &K, cxd iw, const TPt &P, const S
         const cv3 g_p2 = s.Gm * (cxd{nR, 0.0} * vj - nv2 * Rh) + ccross(P.n, g_u2);
         const cv3 g_n = s.Ge * (pv1 * Rh - pR1 * vm) + s.Gm * (pv2 * Rh - pR2 * vj) + ccross(g_u1, p1) +
                         ccross(g_u2, p2);
-        const cv3 g_t1 = P.L[0] * g_p1 + P.L[2] * g_p2, g_t2 = P.L[1] * g_p1 + P.L[3] * g_p2;
         gt.x = gt.x + c * im3(g_Rv);
         gt.n = gt.n + c * im3(g_n);
-        gt.t1 = gt.t1 + c * im3(g_t1);
-        gt.t2 = gt.t2 + c * im3(g_t2);
+        if constexpr (NODAL) {
+            gt.p1 = gt.p1 + c * g_p1;
+            gt.p2 = gt.p2 + c * g_p2;
+        } else {
+            const cv3 g_t1 = P.L[0] * g_p1 + P.L[2] * g_p2, g_t2 = P.L[1] * g_p1 + P.L[3] * g_p2;
+            gt.t1 = gt.t1 + c * im3(g_t1);
+            gt.t2 = gt.t2 + c * im3(g_t2);
+        }
         gt.W += -wfac * Q.W * F.im;
     }
     if (WS) {
         const cv3 g_vj = iw * (s.A * u1 + (s.df * uR1) * Rh) + s.Gm * (cxd{nR, 0.0} * p2 - pR2 * P.n);
         const cv3 g_vm = cxd{-iw.re, -iw.im} * (s.A * u2 + (s.df * uR2) * Rh) +
                          s.Ge * (cxd{nR, 0.0} * p1 - pR1 * P.n);
-        const cv3 g_t1 = Q.X[0] * g_vj + Q.X[2] * g_vm, g_t2 = Q.X[1] * g_vj + Q.X[3] * g_vm;
         gs.y = gs.y - c * im3(g_Rv);
-        gs.t1 = gs.t1 + c * im3(g_t1);
-        gs.t2 = gs.t2 + c * im3(g_t2);
+        if constexpr (NODAL) {
+            gs.vj = gs.vj + c * g_vj;
+            gs.vm = gs.vm + c * g_vm;
+        } else {
+            const cv3 g_t1 = Q.X[0] * g_vj + Q.X[2] * g_vm, g_t2 = Q.X[1] * g_vj + Q.X[3] * g_vm;
+            gs.t1 = gs.t1 + c * im3(g_t1);
+            gs.t2 = gs.t2 + c * im3(g_t2);
+        }
         gs.W += -wfac * P.W * F.im;
     }
 }
 
 // --------------------------------------------------- per-point fields ---
-// fields[i][0..7]: L0..L3 (lambda), [8..15]: X0..X3 (x) at regular point i
+// fields[i][0..7]: L0..L3 (lambda), [8..15]: X0..X3 (x) at regular point i.
+// NODAL: the components in the point frame of the node-attached fields,
+// L = (m1.t1, m1.t2, m2.t1, m2.t2) with m1, m2 the fields of lambda's two
+// currents, X likewise from x, so that L0 t1 + L1 t2 = P m1 exactly.
+template <bool NODAL>
 __global__ void k_qp_fields(int64_t nt, int64_t n2, const int32_t *__restrict__ tri,
+                            const double *__restrict__ qp, const double *__restrict__ frames,
                             const double2 *__restrict__ lam, const double2 *__restrict__ x,
                             double *__restrict__ fields) {
     const int64_t nq = nt * kQP;
@@ -223,6 +298,20 @@ __global__ void k_qp_fields(int64_t nt, int64_t n2, const int32_t *__restrict__ 
     double xi, eta, w, N[6], d1[6], d2[6];
     rule7((int)(i % kQP), xi, eta, w);
     p2_shape(xi, eta, N, d1, d2);
+    if constexpr (NODAL) {
+        const dvec3 t1 = {qp[QT1 * nq + i], qp[(QT1 + 1) * nq + i], qp[(QT1 + 2) * nq + i]};
+        const dvec3 t2 = {qp[QT2 * nq + i], qp[(QT2 + 1) * nq + i], qp[(QT2 + 2) * nq + i]};
+        const double2 *c[4] = {lam, lam + n2, x, x + n2};
+        for (int f = 0; f < 4; ++f) {
+            const cv3 m = nodal_field(frames, tri + 6 * e, N, c[f]);
+            const cxd a = cdot(m, t1), b = cdot(m, t2);
+            fields[16 * i + 4 * f] = a.re;
+            fields[16 * i + 4 * f + 1] = a.im;
+            fields[16 * i + 4 * f + 2] = b.re;
+            fields[16 * i + 4 * f + 3] = b.im;
+        }
+        return;
+    }
     double acc[16];
     for (int c = 0; c < 16; ++c) acc[c] = 0.0;
     for (int k = 0; k < 6; ++k) {
@@ -261,17 +350,27 @@ __device__ inline bool share_vertex(const int32_t *te, const int32_t *tf) {
 
 // --------------------------------------------------- regular pairs ---
 // Point adjoint table qb[i][13]: x(3), W(1), n(3), t1(3), t2(3).
+// NODAL, qb[i][31]: x(3), W(1), n(3), then the complex adjoints (re, im per
+// component) of p1, p2 (test side) and vj, vm (trial side).
 constexpr int kQB = 13;
+constexpr int kQBN = 31;
+template <bool NODAL> constexpr int qb_stride() { return NODAL ? kQBN : kQB; }
 constexpr int kGroups = 36;   // 36 x 7 = 252 threads
+
+__device__ inline void put_cv3(double *o, cv3 v) {
+    o[0] = v.x.re; o[1] = v.x.im; o[2] = v.y.re; o[3] = v.y.im; o[4] = v.z.re; o[5] = v.z.im;
+}
+__device__ inline cv3 get_cv3(const double *o) { return {{o[0], o[1]}, {o[2], o[3]}, {o[4], o[5]}}; }
 
 // TEST = true: workgroup per test triangle e, its 7 points accumulate over
 // every regular trial point; TEST = false: the same with roles exchanged.
-template <bool TEST>
+template <bool TEST, bool NODAL>
 __global__ __launch_bounds__(256) void k_shape_regular(int64_t nt, const double *__restrict__ qp,
                                                        const double *__restrict__ fields,
                                                        const int32_t *__restrict__ tri, const KernelConst *Kp,
                                                        cxd iw, double *__restrict__ qb) {
-    __shared__ double s_red[kGroups][kQP][kQB];
+    constexpr int kS = qb_stride<NODAL>();
+    __shared__ double s_red[kGroups][kQP][kS];
     const int tid = threadIdx.x;
     const int64_t e = blockIdx.x;
     const int64_t nq = nt * kQP;
@@ -293,30 +392,40 @@ __global__ __launch_bounds__(256) void k_shape_regular(int64_t nt, const double 
             if (share_vertex(te, tri + 6 * f)) continue;
             if (TEST) {
                 load_spt(qp, fields, nq, idx, Q);
-                pair_adjoint<true, false>(K, iw, P, Q, 1.0, gt, gs);
+                pair_adjoint<true, false, NODAL>(K, iw, P, Q, 1.0, gt, gs);
             } else {
                 load_tpt(qp, fields, nq, idx, P);
-                pair_adjoint<false, true>(K, iw, P, Q, 1.0, gt, gs);
+                pair_adjoint<false, true, NODAL>(K, iw, P, Q, 1.0, gt, gs);
             }
         }
-        double v[kQB];
+        double v[kS];
+        for (int c = 0; c < kS; ++c) v[c] = 0.0;
         if (TEST) {
-            const double t[kQB] = {gt.x.x, gt.x.y, gt.x.z, gt.W, gt.n.x, gt.n.y, gt.n.z,
-                                   gt.t1.x, gt.t1.y, gt.t1.z, gt.t2.x, gt.t2.y, gt.t2.z};
-            for (int c = 0; c < kQB; ++c) v[c] = t[c];
+            v[0] = gt.x.x; v[1] = gt.x.y; v[2] = gt.x.z; v[3] = gt.W;
+            v[4] = gt.n.x; v[5] = gt.n.y; v[6] = gt.n.z;
+            if constexpr (NODAL) {
+                put_cv3(v + 7, gt.p1);
+                put_cv3(v + 13, gt.p2);
+            } else {
+                v[7] = gt.t1.x; v[8] = gt.t1.y; v[9] = gt.t1.z; v[10] = gt.t2.x; v[11] = gt.t2.y; v[12] = gt.t2.z;
+            }
         } else {
-            const double t[kQB] = {gs.y.x, gs.y.y, gs.y.z, gs.W, 0.0, 0.0, 0.0,
-                                   gs.t1.x, gs.t1.y, gs.t1.z, gs.t2.x, gs.t2.y, gs.t2.z};
-            for (int c = 0; c < kQB; ++c) v[c] = t[c];
+            v[0] = gs.y.x; v[1] = gs.y.y; v[2] = gs.y.z; v[3] = gs.W;
+            if constexpr (NODAL) {
+                put_cv3(v + 19, gs.vj);
+                put_cv3(v + 25, gs.vm);
+            } else {
+                v[7] = gs.t1.x; v[8] = gs.t1.y; v[9] = gs.t1.z; v[10] = gs.t2.x; v[11] = gs.t2.y; v[12] = gs.t2.z;
+            }
         }
-        for (int c = 0; c < kQB; ++c) s_red[grp][q][c] = v[c];
+        for (int c = 0; c < kS; ++c) s_red[grp][q][c] = v[c];
     }
     __syncthreads();
-    if (tid < kQP * kQB) {
-        const int qq = tid / kQB, c = tid % kQB;
+    if (tid < kQP * kS) {
+        const int qq = tid / kS, c = tid % kS;
         double acc = 0.0;
         for (int g = 0; g < kGroups; ++g) acc += s_red[g][qq][c];
-        qb[(e * kQP + qq) * kQB + c] += acc;
+        qb[(e * kQP + qq) * kS + c] += acc;
     }
 }
 
@@ -331,7 +440,8 @@ struct SingleArgs {
     cxd ce, cm;
 };
 
-__global__ void k_shape_single(int64_t nt, const double *__restrict__ qp, const double *__restrict__ fields,
+template <bool NODAL>
+__global__ __launch_bounds__(256) void k_shape_single(int64_t nt, const double *__restrict__ qp, const double *__restrict__ fields,
                                SingleArgs a, double *__restrict__ qb) {
     const int64_t nq = nt * kQP;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -344,6 +454,8 @@ __global__ void k_shape_single(int64_t nt, const double *__restrict__ qp, const 
     const double W = P.W;
     dvec3 gx = {0, 0, 0}, gn = {0, 0, 0}, gt1 = {0, 0, 0}, gt2 = {0, 0, 0};
     double gW = 0.0;
+    // NODAL: complex adjoints of the point's vectors p1, p2, vj, vm
+    cv3 gp1 = czero3(), gp2 = czero3(), gvj = czero3(), gvm = czero3();
     // far field
     {
         double sn, cs;
@@ -358,8 +470,13 @@ __global__ void k_shape_single(int64_t nt, const double *__restrict__ qp, const 
         const cxd T = pre * cxd{W * G1.re, W * G1.im};
         gx = gx + im3(cxd{0.0, -a.ka} * T * r);
         gW += (pre * G1).im;
-        gt1 = gt1 + im3((cxd{W, 0} * pre) * (Q.X[0] * ep - Q.X[2] * ex));
-        gt2 = gt2 + im3((cxd{W, 0} * pre) * (Q.X[1] * ep - Q.X[3] * ex));
+        if constexpr (NODAL) {
+            gvj = gvj + (cxd{W, 0} * pre) * ep;
+            gvm = gvm - (cxd{W, 0} * pre) * ex;
+        } else {
+            gt1 = gt1 + im3((cxd{W, 0} * pre) * (Q.X[0] * ep - Q.X[2] * ex));
+            gt2 = gt2 + im3((cxd{W, 0} * pre) * (Q.X[1] * ep - Q.X[3] * ex));
+        }
     }
     // right-hand side
     {
@@ -376,17 +493,42 @@ __global__ void k_shape_single(int64_t nt, const double *__restrict__ qp, const 
         const cv3 g_u1 = cxd{-W, 0.0} * E, g_u2 = cxd{W, 0.0} * H;
         const cv3 g_p1 = ccross(n, g_u1), g_p2 = ccross(n, g_u2);
         gn = gn + im3(ccross(g_u1, p1) + ccross(g_u2, p2));
-        gt1 = gt1 + im3(P.L[0] * g_p1 + P.L[2] * g_p2);
-        gt2 = gt2 + im3(P.L[1] * g_p1 + P.L[3] * g_p2);
+        if constexpr (NODAL) {
+            gp1 = gp1 + g_p1;
+            gp2 = gp2 + g_p2;
+        } else {
+            gt1 = gt1 + im3(P.L[0] * g_p1 + P.L[2] * g_p2);
+            gt2 = gt2 + im3(P.L[1] * g_p1 + P.L[3] * g_p2);
+        }
     }
-    // mass
+    // mass (p1 . vm = L0 X2 + L1 X3: both are expansions on the same
+    // orthonormal pair)
     {
         const cxd m = a.ce * (P.L[0] * Q.X[2] + P.L[1] * Q.X[3]) + a.cm * (P.L[2] * Q.X[0] + P.L[3] * Q.X[1]);
         gW -= m.im;
+        if constexpr (NODAL) {
+            const cv3 p1 = P.L[0] * P.t1 + P.L[1] * P.t2, p2 = P.L[2] * P.t1 + P.L[3] * P.t2;
+            const cv3 vj = Q.X[0] * P.t1 + Q.X[1] * P.t2, vm = Q.X[2] * P.t1 + Q.X[3] * P.t2;
+            const cxd we = cxd{-W, 0} * a.ce, wm = cxd{-W, 0} * a.cm;
+            gp1 = gp1 + we * vm;
+            gvm = gvm + we * p1;
+            gp2 = gp2 + wm * vj;
+            gvj = gvj + wm * p2;
+        }
     }
-    double *o = qb + i * kQB;
-    const double v[kQB] = {gx.x, gx.y, gx.z, gW, gn.x, gn.y, gn.z, gt1.x, gt1.y, gt1.z, gt2.x, gt2.y, gt2.z};
-    for (int c = 0; c < kQB; ++c) o[c] += v[c];
+    constexpr int kS = qb_stride<NODAL>();
+    double v[kS];
+    v[0] = gx.x; v[1] = gx.y; v[2] = gx.z; v[3] = gW; v[4] = gn.x; v[5] = gn.y; v[6] = gn.z;
+    if constexpr (NODAL) {
+        put_cv3(v + 7, gp1);
+        put_cv3(v + 13, gp2);
+        put_cv3(v + 19, gvj);
+        put_cv3(v + 25, gvm);
+    } else {
+        v[7] = gt1.x; v[8] = gt1.y; v[9] = gt1.z; v[10] = gt2.x; v[11] = gt2.y; v[12] = gt2.z;
+    }
+    double *o = qb + i * kS;
+    for (int c = 0; c < kS; ++c) o[c] += v[c];
 }
 
 // ------------------------------------------ P2 point: forward + reverse ---
@@ -461,9 +603,14 @@ __device__ inline void atomic_add3(double *p, dvec3 v) {
 
 // Regular points: back through the P2 map and frame of their triangle.
 // nodeb[v][9]: position (3), nodal t1 (3), nodal t2 (3) adjoints.
-__global__ void k_qp_backprop(int64_t nt, const double *__restrict__ xyz, const double *__restrict__ frames,
-                              const int32_t *__restrict__ tri, const double *__restrict__ qb,
-                              double *__restrict__ nodeb) {
+// NODAL: back through the projections p = m - (m.n) n of the four
+// node-attached fields to the normal and the nodal tangents; the point
+// frame does not enter.
+template <bool NODAL>
+__global__ __launch_bounds__(256) void k_qp_backprop(int64_t nt, int64_t n2, const double *__restrict__ xyz,
+                              const double *__restrict__ frames, const int32_t *__restrict__ tri,
+                              const double2 *__restrict__ lam, const double2 *__restrict__ x,
+                              const double *__restrict__ qb, double *__restrict__ nodeb) {
     const int64_t nq = nt * kQP;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nq) return;
@@ -472,10 +619,22 @@ __global__ void k_qp_backprop(int64_t nt, const double *__restrict__ xyz, const 
     rule7((int)(i % kQP), xi, eta, w);
     P2Fwd P;
     p2_forward(xyz, frames, tri + 6 * e, xi, eta, P);
-    const double *b = qb + i * kQB;
+    constexpr int kS = qb_stride<NODAL>();
+    const double *b = qb + i * kS;
     dvec3 gX[6], gT1[6], gT2[6];
-    p2_reverse(P, {b[0], b[1], b[2]}, w * b[3], {b[4], b[5], b[6]}, {b[7], b[8], b[9]}, {b[10], b[11], b[12]},
-               gX, gT1, gT2);
+    if constexpr (NODAL) {
+        const int32_t *t = tri + 6 * e;
+        const double2 *c[4] = {lam, lam + n2, x, x + n2};
+        dvec3 bn = {b[4], b[5], b[6]};
+        cv3 gm[4];
+        for (int f = 0; f < 4; ++f)
+            gm[f] = proj_reverse(get_cv3(b + 7 + 6 * f), nodal_field(frames, t, P.N, c[f]), P.n, bn);
+        p2_reverse(P, {b[0], b[1], b[2]}, w * b[3], bn, {0, 0, 0}, {0, 0, 0}, gX, gT1, gT2);
+        nodal_tangent_adjoint<4>(t, P.N, c, gm, gT1, gT2);
+    } else {
+        p2_reverse(P, {b[0], b[1], b[2]}, w * b[3], {b[4], b[5], b[6]}, {b[7], b[8], b[9]}, {b[10], b[11], b[12]},
+                   gX, gT1, gT2);
+    }
     for (int k = 0; k < 6; ++k) {
         double *o = nodeb + 9 * (int64_t)tri[6 * e + k];
         atomic_add3(o, gX[k]);
@@ -502,6 +661,7 @@ struct ShapeSsqArgs {
     double *nodeb;
 };
 
+template <bool NODAL>
 __global__ __launch_bounds__(64) void k_shape_ssq(ShapeSsqArgs a) {
     constexpr int kCols = 54, kStride = 55;
     __shared__ double s_buf[64 * kStride];
@@ -543,22 +703,46 @@ __global__ __launch_bounds__(64) void k_shape_ssq(ShapeSsqArgs a) {
             SPt Q;
             P.x = X.x; P.n = X.n; P.t1 = X.t1; P.t2 = X.t2; P.W = X.J;
             Q.y = Y.x; Q.t1 = Y.t1; Q.t2 = Y.t2; Q.W = Y.J;
-            for (int c = 0; c < 4; ++c) { P.L[c] = {0, 0}; Q.X[c] = {0, 0}; }
-            for (int k = 0; k < 6; ++k) {
-                const int64_t ne = te[k], nf = tf[k];
-                const double2 l[4] = {a.lam[2 * ne], a.lam[2 * ne + 1], a.lam[a.n2 + 2 * ne], a.lam[a.n2 + 2 * ne + 1]};
-                const double2 u[4] = {a.x[2 * nf], a.x[2 * nf + 1], a.x[a.n2 + 2 * nf], a.x[a.n2 + 2 * nf + 1]};
-                for (int c = 0; c < 4; ++c) {
-                    P.L[c] = P.L[c] + cxd{X.N[k] * l[c].x, X.N[k] * l[c].y};
-                    Q.X[c] = Q.X[c] + cxd{Y.N[k] * u[c].x, Y.N[k] * u[c].y};
+            if constexpr (NODAL) {
+                // components of the node-attached fields in the point frames
+                const double2 *cl[2] = {a.lam, a.lam + a.n2}, *cx_[2] = {a.x, a.x + a.n2};
+                for (int f = 0; f < 2; ++f) {
+                    const cv3 m = nodal_field(a.frames, te, X.N, cl[f]), v = nodal_field(a.frames, tf, Y.N, cx_[f]);
+                    P.L[2 * f] = cdot(m, X.t1);
+                    P.L[2 * f + 1] = cdot(m, X.t2);
+                    Q.X[2 * f] = cdot(v, Y.t1);
+                    Q.X[2 * f + 1] = cdot(v, Y.t2);
+                }
+            } else {
+                for (int c = 0; c < 4; ++c) { P.L[c] = {0, 0}; Q.X[c] = {0, 0}; }
+                for (int k = 0; k < 6; ++k) {
+                    const int64_t ne = te[k], nf = tf[k];
+                    const double2 l[4] = {a.lam[2 * ne], a.lam[2 * ne + 1], a.lam[a.n2 + 2 * ne],
+                                          a.lam[a.n2 + 2 * ne + 1]};
+                    const double2 u[4] = {a.x[2 * nf], a.x[2 * nf + 1], a.x[a.n2 + 2 * nf], a.x[a.n2 + 2 * nf + 1]};
+                    for (int c = 0; c < 4; ++c) {
+                        P.L[c] = P.L[c] + cxd{X.N[k] * l[c].x, X.N[k] * l[c].y};
+                        Q.X[c] = Q.X[c] + cxd{Y.N[k] * u[c].x, Y.N[k] * u[c].y};
+                    }
                 }
             }
-            pair_adjoint<true, true>(K, a.iw, P, Q, wg, gt, gs);
+            pair_adjoint<true, true, NODAL>(K, a.iw, P, Q, wg, gt, gs);
         }
         // test side
         {
             dvec3 gX[6], gT1[6], gT2[6];
-            if (on) p2_reverse(X, gt.x, gt.W, gt.n, gt.t1, gt.t2, gX, gT1, gT2);
+            if (on) {
+                if constexpr (NODAL) {
+                    const double2 *cl[2] = {a.lam, a.lam + a.n2};
+                    dvec3 bn = gt.n;
+                    const cv3 gm[2] = {proj_reverse(gt.p1, nodal_field(a.frames, te, X.N, cl[0]), X.n, bn),
+                                       proj_reverse(gt.p2, nodal_field(a.frames, te, X.N, cl[1]), X.n, bn)};
+                    p2_reverse(X, gt.x, gt.W, bn, {0, 0, 0}, {0, 0, 0}, gX, gT1, gT2);
+                    nodal_tangent_adjoint<2>(te, X.N, cl, gm, gT1, gT2);
+                } else {
+                    p2_reverse(X, gt.x, gt.W, gt.n, gt.t1, gt.t2, gX, gT1, gT2);
+                }
+            }
             for (int k = 0; k < 6; ++k) {
                 double *o = row + 9 * k;
                 if (on) {
@@ -577,7 +761,18 @@ __global__ __launch_bounds__(64) void k_shape_ssq(ShapeSsqArgs a) {
         // trial side
         {
             dvec3 gX[6], gT1[6], gT2[6];
-            if (on) p2_reverse(Y, gs.y, gs.W, {0, 0, 0}, gs.t1, gs.t2, gX, gT1, gT2);
+            if (on) {
+                if constexpr (NODAL) {
+                    const double2 *cx_[2] = {a.x, a.x + a.n2};
+                    dvec3 bn = {0, 0, 0};
+                    const cv3 gm[2] = {proj_reverse(gs.vj, nodal_field(a.frames, tf, Y.N, cx_[0]), Y.n, bn),
+                                       proj_reverse(gs.vm, nodal_field(a.frames, tf, Y.N, cx_[1]), Y.n, bn)};
+                    p2_reverse(Y, gs.y, gs.W, bn, {0, 0, 0}, {0, 0, 0}, gX, gT1, gT2);
+                    nodal_tangent_adjoint<2>(tf, Y.N, cx_, gm, gT1, gT2);
+                } else {
+                    p2_reverse(Y, gs.y, gs.W, {0, 0, 0}, gs.t1, gs.t2, gX, gT1, gT2);
+                }
+            }
             for (int k = 0; k < 6; ++k) {
                 double *o = row + 9 * k;
                 if (on) {
@@ -698,8 +893,10 @@ int shape_grad_run(const mbem_op *op, const mbem_params *p, const double2 *x, co
         if (nodeb) (void)hipFree(nodeb);
         if (nodeb_x) (void)hipFree(nodeb_x);
     };
+    const bool nodal = op->p.frame == MBEM_FRAME_NODAL;
+    const int kS = nodal ? kQBN : kQB;
     if (hipMalloc((void **)&fields, sizeof(double) * 16 * nq) != hipSuccess ||
-        hipMalloc((void **)&qb, sizeof(double) * kQB * nq) != hipSuccess ||
+        hipMalloc((void **)&qb, sizeof(double) * kS * nq) != hipSuccess ||
         hipMalloc((void **)&nodeb, sizeof(double) * 9 * nn) != hipSuccess ||
         hipMalloc((void **)&nodeb_x, sizeof(double) * 9 * nn) != hipSuccess) {
         cleanup();
@@ -712,20 +909,33 @@ int shape_grad_run(const mbem_op *op, const mbem_params *p, const double2 *x, co
         if (e != hipSuccess) { set_error(std::string("shape gradient launch: ") + hipGetErrorString(e)); st = MBEM_EDEVICE; }
         return st == MBEM_OK;
     };
-    (void)hipMemsetAsync(qb, 0, sizeof(double) * kQB * nq, s);
+    (void)hipMemsetAsync(qb, 0, sizeof(double) * kS * nq, s);
     (void)hipMemsetAsync(nodeb, 0, sizeof(double) * 9 * nn, s);
     (void)hipMemsetAsync(nodeb_x, 0, sizeof(double) * 9 * nn, s);
     const unsigned gq = (unsigned)((nq + 255) / 256);
     const cxd iw = {op->iw.x, op->iw.y};
-    hipLaunchKernelGGL(k_qp_fields, dim3(gq), dim3(256), 0, s, nt, op->n2, m->d_tri, lam, x, fields);
+    if (nodal)
+        hipLaunchKernelGGL(k_qp_fields<true>, dim3(gq), dim3(256), 0, s, nt, op->n2, m->d_tri, m->d_qp, m->d_frames,
+                           lam, x, fields);
+    else
+        hipLaunchKernelGGL(k_qp_fields<false>, dim3(gq), dim3(256), 0, s, nt, op->n2, m->d_tri, m->d_qp,
+                           m->d_frames, lam, x, fields);
     if (launch_ok()) {
-        hipLaunchKernelGGL(k_shape_regular<true>, dim3((unsigned)nt), dim3(256), 0, s, nt, m->d_qp, fields, m->d_tri,
-                           op->d_kconst, iw, qb);
+        if (nodal)
+            hipLaunchKernelGGL((k_shape_regular<true, true>), dim3((unsigned)nt), dim3(256), 0, s, nt, m->d_qp,
+                               fields, m->d_tri, op->d_kconst, iw, qb);
+        else
+            hipLaunchKernelGGL((k_shape_regular<true, false>), dim3((unsigned)nt), dim3(256), 0, s, nt, m->d_qp,
+                               fields, m->d_tri, op->d_kconst, iw, qb);
         launch_ok();
     }
     if (st == MBEM_OK) {
-        hipLaunchKernelGGL(k_shape_regular<false>, dim3((unsigned)nt), dim3(256), 0, s, nt, m->d_qp, fields,
-                           m->d_tri, op->d_kconst, iw, qb);
+        if (nodal)
+            hipLaunchKernelGGL((k_shape_regular<false, true>), dim3((unsigned)nt), dim3(256), 0, s, nt, m->d_qp,
+                               fields, m->d_tri, op->d_kconst, iw, qb);
+        else
+            hipLaunchKernelGGL((k_shape_regular<false, false>), dim3((unsigned)nt), dim3(256), 0, s, nt, m->d_qp,
+                               fields, m->d_tri, op->d_kconst, iw, qb);
         launch_ok();
     }
     if (st == MBEM_OK) {
@@ -735,11 +945,17 @@ int shape_grad_run(const mbem_op *op, const mbem_params *p, const double2 *x, co
         sa.ka = p->k0;
         sa.ce = {op->ce.x, op->ce.y};
         sa.cm = {op->cm.x, op->cm.y};
-        hipLaunchKernelGGL(k_shape_single, dim3(gq), dim3(256), 0, s, nt, m->d_qp, fields, sa, qb);
+        if (nodal) hipLaunchKernelGGL(k_shape_single<true>, dim3(gq), dim3(256), 0, s, nt, m->d_qp, fields, sa, qb);
+        else hipLaunchKernelGGL(k_shape_single<false>, dim3(gq), dim3(256), 0, s, nt, m->d_qp, fields, sa, qb);
         launch_ok();
     }
     if (st == MBEM_OK) {
-        hipLaunchKernelGGL(k_qp_backprop, dim3(gq), dim3(256), 0, s, nt, m->d_xyz, m->d_frames, m->d_tri, qb, nodeb);
+        if (nodal)
+            hipLaunchKernelGGL(k_qp_backprop<true>, dim3(gq), dim3(256), 0, s, nt, op->n2, m->d_xyz, m->d_frames,
+                               m->d_tri, lam, x, qb, nodeb);
+        else
+            hipLaunchKernelGGL(k_qp_backprop<false>, dim3(gq), dim3(256), 0, s, nt, op->n2, m->d_xyz, m->d_frames,
+                               m->d_tri, lam, x, qb, nodeb);
         launch_ok();
     }
     if (st == MBEM_OK && m->n_spairs > 0) {
@@ -762,7 +978,8 @@ int shape_grad_run(const mbem_op *op, const mbem_params *p, const double2 *x, co
         a.K = op->d_kconst;
         a.iw = iw;
         a.nodeb = nodeb;
-        hipLaunchKernelGGL(k_shape_ssq, dim3((unsigned)m->n_spairs), dim3(64), 0, s, a);
+        if (nodal) hipLaunchKernelGGL(k_shape_ssq<true>, dim3((unsigned)m->n_spairs), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL(k_shape_ssq<false>, dim3((unsigned)m->n_spairs), dim3(64), 0, s, a);
         launch_ok();
     }
     if (st == MBEM_OK) {
