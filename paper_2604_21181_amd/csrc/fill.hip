@@ -335,9 +335,10 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
 #pragma unroll
             for (int q = 0; q < 7; ++q) { k0[q] = r0[q]; k1[q] = r1[q]; }
             // every input is in registers: each output may overwrite its slot
-            // (one j at a time: unrolled, the weight loads of all j would be
-            // hoisted and the FP64 kernel would run at one wave per SIMD)
-#pragma unroll 1
+            // (three j at a time: unrolled fully, the weight loads of all j
+            // would be hoisted and the FP64 kernel would run at one wave per
+            // SIMD)
+#pragma unroll 3
             for (int j = 0; j < 6; ++j) {
                 cx<T> o0 = {0, 0}, o1 = {0, 0};
 #pragma unroll
