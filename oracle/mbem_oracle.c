@@ -20,7 +20,10 @@
  *    l0 = 1 - xi - eta, l1 = xi, l2 = eta, local nodes (v0 v1 v2 m01 m12 m20);
  *  - unknown index inside one current's block: 2 * node + alpha;
  *  - the 12 kernel values of one point pair are ordered
- *    c = 4 * op + 2 * alpha + beta, op = 0: K1, 1: K2^eps, 2: K2^mu.
+ *    c = 4 * op + 2 * alpha + beta, op = 0: K1, 1: K2^eps, 2: K2^mu;
+ *  - tangential basis (phys[6]): frame 0 is the printed construction,
+ *    N_j t_beta(y) with the interpolated Gram-Schmidt frame; frame 1 attaches
+ *    each basis function to its node, N_j(y) P(y) t_beta,j.
  */
 #include <complex.h>
 #include <math.h>
