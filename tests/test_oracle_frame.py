@@ -56,20 +56,21 @@ def _rotation(seed):
     return q if np.linalg.det(q) > 0 else -q
 
 
-@pytest.mark.parametrize("frame,bound", [(1, 1e-12), (0, None)])
-def test_rotation_covariance(frame, bound):
+@pytest.mark.parametrize("frame,bound,variant", [(1, 1e-12, 0), (0, None, 0), (1, 1e-12, 1)])
+def test_rotation_covariance(frame, bound, variant):
     """Rotating mesh, incidence and polarisation by Q rotates the far field
     by Q.  The reference-axis rule is tied to fixed axes, so the rotated mesh
     gets other tangent pairs.  With node-attached tangents only the tangent
     planes matter and the far field is covariant to rounding; with the
     interpolated frame the discrete space itself changes (the axis switch
-    moves), which shows as a discretisation-size difference."""
+    moves), which shows as a discretisation-size difference.  Variant 1 (the
+    paper's quadrature) on the node-attached basis is covariant as well."""
     xyz, tri = icosphere_p2(80, (1.0, 0.8, 0.6))
     Q = _rotation(5)
     r = cut_plane_directions(24)
     out = []
     for X, kh, pol, rr in ((xyz, KH, POL, r), (xyz @ Q.T, Q @ KH, (Q @ POL.real).astype(complex), r @ Q.T)):
-        P = galerkin.Problem(X, tri, 1.2, 3.0 + 0.1j, frame=frame)
+        P = galerkin.Problem(X, tri, 1.2, 3.0 + 0.1j, frame=frame, variant=variant)
         x, _, _ = oracle.solve_dense(P, kh[None], pol[None])
         out.append(galerkin.far_field(P, x[:, 0], rr))
     F0, F1 = out[0] @ Q.T, out[1]
