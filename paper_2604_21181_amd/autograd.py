@@ -29,6 +29,7 @@ class SigmaExtProblem:
     pol: np.ndarray                  # [3] complex
     mu_r: complex = 1.0
     precision: int = mbem.MBEM_FP64
+    frame: int = mbem.MBEM_FRAME_INTERPOLATED   # tangential basis (mbem.h)
     mbj_block: int = 100
     tol: float = 1e-12
     maxit: int = 600
@@ -48,7 +49,7 @@ class SigmaExtProblem:
 
 def _forward(prob: SigmaExtProblem, eps: complex, disp: np.ndarray, want_grad: bool):
     xyz = prob.xyz + disp[:, None] * prob.nodal_normals()
-    S = mbem.Solver(xyz, prob.tri6, prob.k0, eps, prob.mu_r, precision=prob.precision)
+    S = mbem.Solver(xyz, prob.tri6, prob.k0, eps, prob.mu_r, precision=prob.precision, frame=prob.frame)
     try:
         S.fill()
         S.precond_setup(prob.mbj_block)

@@ -261,6 +261,28 @@ def test_shape_gradient(case):
     assert np.abs(dxn - dnode).max() < 1e-12 * scale
 
 
+def test_autograd_function(case):
+    """SigmaExt on the node-attached basis: torch gradients against the
+    library's adjoint of the same configuration."""
+    import torch
+    mbem = _mbem()
+    from paper_2604_21181_amd.autograd import SigmaExt, SigmaExtProblem
+    xyz, tri = case["xyz"], case["tri"]
+    prob = SigmaExtProblem(xyz, tri, case["k0"], KH, POL, tol=1e-13, frame=mbem.MBEM_FRAME_NODAL)
+    eps = torch.tensor([case["eps"].real, case["eps"].imag], dtype=torch.float64, requires_grad=True)
+    disp = torch.zeros(xyz.shape[0], dtype=torch.float64, requires_grad=True)
+    sig = SigmaExt.apply(eps, disp, prob)
+    sig.backward()
+    S = case["S"]
+    S.precond_setup(100)
+    x, _, code = S.solve(S.rhs(KH[None], POL[None]), tol=1e-13, maxit=400)
+    out, _, _, dnode, _ = S.grad_sigma_ext(x[0], KH, POL, tol=1e-13, shape=True)
+    assert abs(float(sig.detach()) - out[0]) < 1e-10 * abs(out[0])
+    assert np.abs(eps.grad.numpy() - out[1:3]).max() < 1e-8 * np.abs(out[1:3]).max()
+    dn = dnode.cpu().numpy()
+    assert np.abs(disp.grad.numpy() - dn).max() < 1e-8 * np.abs(dn).max()
+
+
 def test_compressed_operator(case):
     """Block low-rank operator on the node-attached basis: its far field
     equals the dense node-attached solution's to the compression tolerance."""
