@@ -350,6 +350,39 @@ def frame_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3):
     rel = lambda a, b: float(np.linalg.norm(F[a] - F[b]) / np.linalg.norm(F[b]))
     out["farfield_nodal_vs_interpolated_fp64"] = rel("nodal_fp64", "interpolated_fp64")
     out["farfield_nodal_mixed_vs_nodal_fp64"] = rel("nodal_mixed", "nodal_fp64")
+    out["spheroid_refinement"] = frame_refinement(mbem, get_config, icosphere_p2, log)
+    return out
+
+
+def frame_refinement(mbem, get_config, icosphere_p2, log):
+    """Both bases under refinement on the plasmonic spheroid of the
+    spheroid5120 workload (semi-axes 1, 1, 2, eps_r = -10 + 1i, k_a = 4),
+    oblique incidence (45 degrees to the axis), 320 / 1280 / 5120 triangles,
+    FP64, GMRES to 1e-10: C_ext, C_abs and the energy balance per mesh.
+    There is no closed form for a spheroid; the change of C_ext between
+    consecutive meshes measures the convergence."""
+    c = get_config("spheroid5120")
+    kh = np.array([np.sqrt(0.5), 0.0, np.sqrt(0.5)])
+    po = np.array([np.sqrt(0.5), 0.0, -np.sqrt(0.5)], dtype=np.complex128)
+    out = {}
+    for name, frame in (("interpolated", mbem.MBEM_FRAME_INTERPOLATED), ("nodal", mbem.MBEM_FRAME_NODAL)):
+        rows = []
+        for nt in (320, 1280, 5120):
+            xyz, tri = icosphere_p2(nt, c["axes"])
+            S = mbem.Solver(xyz, tri, c["k0"], c["eps_r"], c["mu_r"], frame=frame)
+            try:
+                S.fill()
+                S.precond_setup(c["mbj_block"])
+                x, st, code = S.solve(S.rhs(kh[None], po[None]), tol=1e-10, maxit=800)
+                cs = S.cross_sections(x[0], kh, po)
+                rows.append({"n_tris": nt, "c_ext": float(cs[0]), "c_sca": float(cs[1]), "c_abs": float(cs[2]),
+                             "energy_balance": float(abs(cs[0] - cs[1] - cs[2]) / cs[0]), "iters": st.iters,
+                             "converged": code == 0})
+            finally:
+                S.close()
+            log(f"frame refinement: {name} {nt} C_ext {rows[-1]['c_ext']:.6f} "
+                f"balance {rows[-1]['energy_balance']:.1e}")
+        out[name] = rows
     return out
 
 
