@@ -83,6 +83,7 @@ static void op_free_device(mbem_op *op) {
     dfree(op->d_lu);
     dfree(op->d_work);
     dfree(op->d_kconst);
+    dfree(op->d_rtab);
     if (op->h_pin) (void)hipHostFree(op->h_pin);
     op->h_pin = nullptr;
     blr_free(op->blr);

@@ -58,6 +58,7 @@ struct RegArgs {
     const double *qp64;     // FP64 table (near pairs of the mixed path)
     const int32_t *tri;
     const double *frames;   // [nn][9] nodal triads (node-attached tangents)
+    const T *rtab;          // node-attached: [nt][points][6][2][2] tangent components
     const int32_t *chunks;  // kChunkRec ints per trial chunk
     const double *einfo;    // [nt][4]
     double near_r;
@@ -205,16 +206,11 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     }
     const int64_t nq = a.nt * kQP;
     if constexpr (NODAL) {
+        // the test triangle's and the chunk's rows of the precomputed table
         for (int it = tid; it < (kChunk + 1) * 168; it += blockDim.x) {
             const int side = it / 168, r = it % 168;          // side 0: test, 1 + fs: trial
-            const int pq = r / 24, j = (r / 4) % 6, b = (r / 2) % 2, g = r % 2;
             const int64_t el = side == 0 ? e : ch * kChunk + side - 1;
-            T v = 0;
-            if (el < a.nt) {
-                const double *t = a.frames + 9 * (int64_t)a.tri[6 * el + j] + 3 + 3 * b;
-                const vec3<T> tg = qload(a.qp, nq, g ? QT2 : QT1, el * kQP + pq);
-                v = (T)n7(pq, j) * ((T)t[0] * tg.x + (T)t[1] * tg.y + (T)t[2] * tg.z);
-            }
+            const T v = el < a.nt ? a.rtab[el * 168 + r] : (T)0;
             if (side == 0) s_ra[r] = v;
             else s_rb[(side - 1) * 168 + r] = v;
         }
@@ -713,17 +709,10 @@ __global__ __launch_bounds__(256) void k_regular12(RegArgs<T, TS> a) {
         s_act[tid] = kind;
     }
     if constexpr (NODAL) {
-        const int64_t nq12 = a.nt * kQP12;
         for (int it = tid; it < (kChunk + 1) * kR12; it += blockDim.x) {
             const int side = it / kR12, r = it % kR12;          // side 0: test, 1 + fs: trial
-            const int pq = r / 24, j = (r / 4) % 6, b = (r / 2) % 2, g = r % 2;
             const int64_t el = side == 0 ? e : ch * kChunk + side - 1;
-            T v = 0;
-            if (el < a.nt) {
-                const double *t = a.frames + 9 * (int64_t)a.tri[6 * el + j] + 3 + 3 * b;
-                const vec3<T> tg = qload(a.qp, nq12, g ? QT2 : QT1, el * kQP12 + pq);
-                v = (T)n12(pq, j) * ((T)t[0] * tg.x + (T)t[1] * tg.y + (T)t[2] * tg.z);
-            }
+            const T v = el < a.nt ? a.rtab[el * kR12 + r] : (T)0;
             if (side == 0) s_ra[r] = v;
             else s_rb[(side - 1) * kR12 + r] = v;
         }
@@ -1101,6 +1090,43 @@ static KernelConst make_rem_kconst(const mbem_op *op) {
     return R;
 }
 
+// Node-attached tangents: per triangle and point of the regular rule (NQ
+// points), rtab[e][p][k][b][g] = N_k(p) t_b,k . t_g(p), the components of the
+// triangle's nodal tangents in the point frame times the shape function; one
+// thread per entry, once per fill.
+template <typename T, int NQ>
+__global__ void k_nodal_table(int64_t nt, const T *__restrict__ qp, const int32_t *__restrict__ tri,
+                              const double *__restrict__ frames, T *__restrict__ rtab) {
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= nt * NQ * 24) return;
+    const int64_t e = id / (NQ * 24);
+    const int r = (int)(id % (NQ * 24));
+    const int pq = r / 24, j = (r / 4) % 6, b = (r / 2) % 2, g = r % 2;
+    const int64_t nq = nt * NQ;
+    const double *t = frames + 9 * (int64_t)tri[6 * e + j] + 3 + 3 * b;
+    const vec3<T> tg = qload(qp, nq, g ? QT2 : QT1, e * NQ + pq);
+    const double nk = NQ == kQP ? n7(pq, j) : n12(pq, j);
+    rtab[id] = (T)nk * ((T)t[0] * tg.x + (T)t[1] * tg.y + (T)t[2] * tg.z);
+}
+
+template <typename T, int NQ>
+static int nodal_table_run(mbem_op *op, const T *qp, hipStream_t s) {
+    const mbem_mesh *m = op->mesh;
+    const size_t bytes = sizeof(T) * (size_t)m->nt * NQ * 24;
+    if (op->rtab_bytes < bytes) {
+        if (op->d_rtab) MBEM_HIP(hipFree(op->d_rtab));
+        op->d_rtab = nullptr;
+        op->rtab_bytes = 0;
+        MBEM_HIP(hipMalloc(&op->d_rtab, bytes));
+        op->rtab_bytes = bytes;
+    }
+    const int64_t n = m->nt * NQ * 24;
+    hipLaunchKernelGGL((k_nodal_table<T, NQ>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, m->nt, qp,
+                       m->d_tri, m->d_frames, (T *)op->d_rtab);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
 template <typename T, typename TS, bool DK = false, bool P12 = false, bool NODAL = false>
 static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long *cnt,
                           hipStream_t s, const FillBand *band = nullptr) {
@@ -1112,6 +1138,11 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
     a.qp64 = P12 ? m->d_qp12 : m->d_qp;
     a.tri = m->d_tri;
     a.frames = m->d_frames;
+    a.rtab = nullptr;
+    if constexpr (NODAL) {
+        MBEM_TRY((nodal_table_run<T, P12 ? kQP12 : kQP>(op, qp, s)));
+        a.rtab = (const T *)op->d_rtab;
+    }
     a.chunks = m->d_chunks;
     a.einfo = m->d_elem;
     a.mode = mode;

@@ -111,6 +111,11 @@ struct mbem_op {
     int64_t n_near = 0;
     double t_phase[5] = {0, 0, 0, 0, 0};  // geom, regular, near, ssq, mass (ms)
     mbem::KernelConst *d_kconst = nullptr;   // device copy of the kernel constants
+    // node-attached tangents: per triangle and rule point the 2 x 2
+    // components of its nodes' tangents in the point frame, times N_k
+    // ([nt][points][6][2][2], in the precision of the regular-pair kernel)
+    void *d_rtab = nullptr;
+    size_t rtab_bytes = 0;
     // Morton block-Jacobi
     int32_t B = 0, nb = 0;
     double2 *d_minv = nullptr;      // [nb][2B][2B] inverses
