@@ -138,6 +138,8 @@ def parse():
                     help="skip the block low-rank operator beyond dense memory")
     ap.add_argument("--no-frame-study", action="store_true",
                     help="skip the comparison of the interpolated frame with node-attached tangents")
+    ap.add_argument("--no-frame-refinement", action="store_true",
+                    help="in the frame study, skip the spheroid refinement (320 / 1280 / 5120 triangles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device to device once (scales the FETCH_SIZE / WRITE_SIZE "
                          "counters) and exit")
@@ -313,7 +315,7 @@ def blr_study(mbem, icosphere_p2, log):
         S.close()
 
 
-def frame_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3):
+def frame_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3, refinement=True):
     """The interpolated frame (the paper's construction, the default) against
     node-attached tangents on the 1280-triangle sphere, FP64 and mixed: fill
     times, GMRES iterations to 1e-8, the energy balance
@@ -350,7 +352,7 @@ def frame_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3):
     rel = lambda a, b: float(np.linalg.norm(F[a] - F[b]) / np.linalg.norm(F[b]))
     out["farfield_nodal_vs_interpolated_fp64"] = rel("nodal_fp64", "interpolated_fp64")
     out["farfield_nodal_mixed_vs_nodal_fp64"] = rel("nodal_mixed", "nodal_fp64")
-    out["spheroid_refinement"] = frame_refinement(mbem, get_config, icosphere_p2, log)
+    out["spheroid_refinement"] = frame_refinement(mbem, get_config, icosphere_p2, log) if refinement else None
     return out
 
 
@@ -680,7 +682,8 @@ def main():
         bstudy = blr_study(mbem, icosphere_p2, log)
     fstudy = None
     if not args.no_frame_study:
-        fstudy = frame_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log)
+        fstudy = frame_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log,
+                             refinement=not args.no_frame_refinement)
 
     if not paths:
         # profiling run of one pass: its own section only
