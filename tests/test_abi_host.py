@@ -87,3 +87,60 @@ def test_argument_errors_before_any_device_call():
                                   None) == mbem.MBEM_EINVAL
     assert L.mbem_fill(None, None, C.byref(p), C.byref(op), None) == mbem.MBEM_EINVAL
     assert "null" in L.mbem_last_error().decode()
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    of its C counterpart in include/mbem.h (compiled here with the host C
+    compiler), so that a field added on one side only fails on the CPU."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    from paper_2604_21181_amd import mbem
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    pairs = [("mbem_params", mbem.Params), ("mbem_solve_opts", mbem.SolveOpts), ("mbem_stats", mbem.Stats),
+             ("mbem_blr_opts", mbem.BlrOpts), ("mbem_blr_stats", mbem.BlrStats),
+             ("mbem_block_opts", mbem.BlockOpts), ("mbem_block_stats", mbem.BlockStats)]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "mbem.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for ln in subprocess.check_output([str(exe)], text=True).splitlines():
+        a, b, v = ln.split()
+        got[(a, b)] = int(v)
+    for cname, py in pairs:
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_struct_fields_match_header():
+    """The binding's structures list exactly the header's fields, in order
+    (a trailing field that fits in padding changes no size or offset)."""
+    from paper_2604_21181_amd import mbem
+    src = open(os.path.join(ROOT, "include", "mbem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    fields = {}
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(mbem_\w+)\s*;", src, flags=re.S):
+        names = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            parts = decl.split(None, 1)[1]
+            names += [p.strip() for p in parts.split(",")]
+        fields[name] = names
+    pairs = [("mbem_params", mbem.Params), ("mbem_solve_opts", mbem.SolveOpts), ("mbem_stats", mbem.Stats),
+             ("mbem_blr_opts", mbem.BlrOpts), ("mbem_blr_stats", mbem.BlrStats),
+             ("mbem_block_opts", mbem.BlockOpts), ("mbem_block_stats", mbem.BlockStats)]
+    for cname, py in pairs:
+        assert fields[cname] == [f for f, _ in py._fields_], cname
