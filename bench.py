@@ -44,16 +44,24 @@ One step = the whole hot path, both precisions side by side:
          Schwab on the singular kernels only, 12-point remainder) against the
          default on the same sphere, FP64 and mixed: fill times and far-field
          differences.
+  SPHEROID PASS (once): the 5120-triangle plasmonic spheroid (1, 1, 2),
+         k_a = 4, eps_r = -10 + 1i, 40968 unknowns, block-Jacobi B = 256, one
+         plane wave: FP64 and mixed fill and GMRES to 1e-6 (iterations,
+         times), the mixed far field against an FP64 solve to 1e-10.
 Metric: Z-fill rate N^2 / t_fill (entries/s) of the mixed path when its far
 field is within 1e-6 of the FP64 path's, otherwise of the FP64 path; GMRES
-solve seconds of both are reported beside it.  The multi-RHS pass reports
+solve seconds of both are reported beside it, and, after the timed steps,
+the solve seconds at the loosest GMRES tolerance in 1e-4 .. 1e-12 whose far
+field is within 1e-6 of the oracle's (dense FP64 fill and LU on the host).  The multi-RHS pass reports
 its per-RHS solve time against 128 sequential single-RHS solves of the same
 operator (timed once, after the timed steps).
 
 The roofline object describes the kernel with the largest device time per
 step, timed live with HIP events on the library's stream.  Its algorithmic
 work per launch is derived below; the CPU baseline is the FP64 oracle's
-dense fill on the host cores.
+dense fill on the host cores, followed (untimed for the baseline's value,
+timed on its own) by the oracle's LU solve and far field, the reference of
+every accuracy figure of the line.
 """
 from __future__ import annotations
 
@@ -138,33 +146,136 @@ def parse():
                     help="skip the block low-rank operator beyond dense memory")
     ap.add_argument("--no-frame-study", action="store_true",
                     help="skip the comparison of the interpolated frame with node-attached tangents")
-    ap.add_argument("--no-frame-refinement", action="store_true",
-                    help="in the frame study, skip the spheroid refinement (320 / 1280 / 5120 triangles)")
+    ap.add_argument("--frame-refinement", action="store_true",
+                    help="in the frame study, also run the spheroid refinement (320 / 1280 / 5120 triangles)")
+    ap.add_argument("--no-tol-sweep", action="store_true",
+                    help="skip the search of the loosest GMRES tolerance meeting 1e-6 far-field error")
+    ap.add_argument("--no-spheroid", action="store_true",
+                    help="skip the 5120-triangle plasmonic spheroid pass (FP64 and mixed, B = 256)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device to device once (scales the FETCH_SIZE / WRITE_SIZE "
                          "counters) and exit")
     ap.add_argument("--only", choices=["all", "main", "mrhs", "grad", "precond", "quad", "spectrum", "blr",
-                                       "frame"],
+                                       "frame", "spheroid"],
                     default="all",
                     help="run one pass of the step only (for profiling); the JSON line is "
                          "printed for 'all' and 'main'")
     return ap.parse_args()
 
 
-def cpu_baseline(xyz, tri, cfg, N):
-    """FP64 oracle fill of the same mesh on the host cores."""
-    from oracle import core
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(xyz, tri, cfg, N, khat, pol, rdirs):
+    """The FP64 oracle on the host cores: its dense fill of the same mesh
+    (timed: the baseline's value), then its dense LU solve (timed) and far
+    field at the 360 cut-plane angles, the reference of the accuracy
+    figures.  Returns (baseline record, oracle far field)."""
+    from oracle import core, galerkin
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
-    phys = core.phys_vector(cfg["k0"], cfg["eps_r"], cfg["mu_r"])
+    P = galerkin.Problem(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"])
     core.lib()
     t0 = time.perf_counter()
-    K = core.fill(xyz, tri, phys, nss=4, nthreads=threads)
+    K = core.fill(xyz, tri, P.phys, nss=4, nthreads=threads)
     dt = time.perf_counter() - t0
+    Z = galerkin.assemble(P, *K, galerkin.mass_matrix(P))
     del K
-    return {"value": N * N / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
-            "sample": f"full FP64 dense fill (K1, K2eps, K2mu, all {tri.shape[0]}^2 element "
-                      f"pairs) of the same mesh, {dt:.2f} s"}
+    b = galerkin.planewave_rhs(P, khat, pol)[:, 0]
+    t0 = time.perf_counter()
+    x = np.linalg.solve(Z, b)
+    t_lu = time.perf_counter() - t0
+    del Z
+    F = galerkin.far_field(P, x, rdirs)
+    rec = {"value": N * N / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
+           "sample": f"full FP64 dense fill (K1, K2eps, K2mu, all {tri.shape[0]}^2 element "
+                     f"pairs) of the same mesh, {dt:.2f} s",
+           "t_fill_s": dt, "t_lu_solve_s": t_lu, "solve": "dense LU (numpy / LAPACK zgesv)",
+           "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
+    return rec, F
+
+
+TOL_LADDER = (1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12)
+
+
+def tol_sweep(S, khat, pol, rdirs, Fref, block, reps=3):
+    """The solve-seconds rule of the metric: the loosest GMRES tolerance of
+    the ladder whose far field is within 1e-6 of the reference, with its
+    solve time (mean of reps solves from b on the device to x), iterations
+    and error; every rung's error is listed."""
+    S.precond_setup(block)
+    b = S.rhs(khat, pol)
+    rungs = []
+    chosen = None
+    for tol in TOL_LADDER:
+        times = []
+        for _ in range(reps):
+            x, st, code = S.solve(b, tol=tol, maxit=800, inner_tol=max(tol, 1e-4))
+            times.append(st.t_solve_ms)
+        F = S.farfield(x, rdirs).cpu().numpy()[0]
+        err = float(np.linalg.norm(F - Fref) / np.linalg.norm(Fref))
+        rungs.append({"tol": tol, "err": err, "iters": int(st.iters), "sweeps": int(st.outer_iters),
+                      "t_solve_ms": float(np.mean(times)), "converged": code == 0})
+        if chosen is None and code == 0 and err <= 1e-6:
+            chosen = rungs[-1]
+            break
+    return {"rule": "loosest tol in 1e-4..1e-12 with far field within 1e-6 of the reference",
+            "tol": chosen["tol"] if chosen else None,
+            "solve_s": chosen["t_solve_ms"] * 1e-3 if chosen else None,
+            "iters": chosen["iters"] if chosen else None,
+            "err": chosen["err"] if chosen else None, "rungs": rungs}
+
+
+def spheroid_pass(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3):
+    """The 5120-triangle plasmonic spheroid (40968 unknowns, k_a = 4,
+    eps_r = -10 + 1i, block-Jacobi B = 256, one plane wave): FP64 and mixed
+    fill and solve to 1e-6 (iterations, times), the mixed far field against
+    an FP64 solve to 1e-10."""
+    c = get_config("spheroid5120")
+    xyz, tri = icosphere_p2(c["n_tris"], c["axes"])
+    kh, po = planewaves("spheroid5120")
+    out = {"workload": "spheroid5120", "n_tris": int(tri.shape[0]), "unknowns": 4 * int(xyz.shape[0]),
+           "k0": c["k0"], "eps_r": str(c["eps_r"]), "mbj_block": c["mbj_block"], "gmres_tol": c["tol"]}
+    F = {}
+    for name, prec in (("fp64", mbem.MBEM_FP64), ("mixed", mbem.MBEM_MIXED)):
+        S = mbem.Solver(xyz, tri, c["k0"], c["eps_r"], c["mu_r"], precision=prec)
+        try:
+            fs = [S.fill() for _ in range(reps)]
+            ps = S.precond_setup(c["mbj_block"])
+            b = S.rhs(kh, po)
+            sols = [S.solve(b, tol=c["tol"], maxit=1000, inner_tol=1e-4) for _ in range(reps)]
+            x, st, code = sols[-1]
+            Fp = S.farfield(x, rdirs).cpu().numpy()[0]
+            rec = {"t_fill_ms": float(np.mean([f.t_fill_ms for f in fs])),
+                   "t_regular_ms": float(np.mean([f.t_regular_ms for f in fs])),
+                   "t_singular_ms": float(np.mean([f.t_ssq_ms for f in fs])),
+                   "fill_rate": (4 * xyz.shape[0]) ** 2 / (1e-3 * float(np.mean([f.t_fill_ms for f in fs]))),
+                   "t_setup_ms": ps.t_setup_ms,
+                   "t_solve_ms": float(np.mean([s[1].t_solve_ms for s in sols])),
+                   "iters": int(st.iters), "sweeps": int(st.outer_iters), "rel_resid": float(st.rel_resid),
+                   "converged": code == 0, "n_near_pairs": int(fs[-1].n_near_pairs)}
+            if name == "fp64":
+                xr, sr, cr = S.solve(b, tol=1e-10, maxit=1000)
+                F["ref"] = S.farfield(xr, rdirs).cpu().numpy()[0]
+                rec["reference_iters"] = int(sr.iters)
+            F[name] = Fp
+            out[name] = rec
+            log(f"spheroid5120 {name}: fill {rec['t_fill_ms']:.1f} ms, solve {rec['t_solve_ms']:.1f} ms, "
+                f"{rec['iters']} iterations")
+        finally:
+            S.close()
+    rel = lambda a, b: float(np.linalg.norm(F[a] - F[b]) / np.linalg.norm(F[b]))
+    out["farfield_err_mixed_vs_fp64_ref"] = rel("mixed", "ref")
+    out["farfield_err_fp64_vs_fp64_ref"] = rel("fp64", "ref")
+    return out
 
 
 PRECOND_STUDY = (("sphere1280", (50, 100, 256, 512), 1500),
@@ -446,14 +557,15 @@ def main():
         # one pass of the step, or one study
         keep = {"mrhs": "no_mrhs", "grad": "no_grad", "precond": "no_precond_study",
                 "quad": "no_quad_study", "spectrum": "no_spectrum_study", "blr": "no_blr_study",
-                "frame": "no_frame_study"}
+                "frame": "no_frame_study", "spheroid": "no_spheroid"}
         for name, flag in keep.items():
             if name != args.only:
                 setattr(args, flag, True)
         if args.only != "main":
             args.paths = ""
             args.no_cpu_baseline = True
-        if args.only in ("precond", "quad", "spectrum", "blr", "frame"):
+            args.no_tol_sweep = True
+        if args.only in ("precond", "quad", "spectrum", "blr", "frame", "spheroid"):
             args.steps, args.warmup = 0, 0
     cfg = get_config(args.workload)
     xyz, tri = icosphere_p2(cfg["n_tris"], cfg["axes"])
@@ -606,6 +718,26 @@ def main():
         roof = dict(rooflines[0])
         roof.pop("path", None)
 
+    cpu, Foracle = None, None
+    if paths and not args.no_cpu_baseline:
+        log("timing the CPU oracle (dense fill, LU solve, far field)")
+        cpu, Foracle = cpu_baseline(xyz, tri, cfg, N, khat, pol, rdirs)
+        for p in paths:
+            info[f"farfield_err_{p}_vs_oracle"] = float(np.linalg.norm(ff[p] - Foracle) / np.linalg.norm(Foracle))
+    sweeps = None
+    if paths and not args.no_tol_sweep:
+        # reference: the oracle's LU far field, else the FP64 path at 1e-12
+        Fref, ref_name = Foracle, "oracle dense LU"
+        if Fref is None:
+            S = solvers.get("fp64") or solvers[paths[0]]
+            S.precond_setup(cfg["mbj_block"])
+            xr, _, _ = S.solve(S.rhs(khat, pol), tol=1e-12, maxit=800)
+            Fref, ref_name = S.farfield(xr, rdirs).cpu().numpy()[0], "GPU FP64 path at tol 1e-12"
+        sweeps = {"reference": ref_name}
+        for p in paths:
+            sweeps[p] = tol_sweep(solvers[p], khat, pol, rdirs, Fref, cfg["mbj_block"])
+            log(f"tolerance sweep {p}: tol {sweeps[p]['tol']}, solve {sweeps[p]['solve_s']} s")
+
     mrhs = None
     if Smr is not None:
         mr = recs[-1]["mrhs"]
@@ -680,26 +812,27 @@ def main():
     bstudy = None
     if not args.no_blr_study:
         bstudy = blr_study(mbem, icosphere_p2, log)
+    spheroid = None
+    if not args.no_spheroid:
+        spheroid = spheroid_pass(mbem, get_config, icosphere_p2, planewaves, rdirs, log)
     fstudy = None
     if not args.no_frame_study:
         fstudy = frame_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log,
-                             refinement=not args.no_frame_refinement)
+                             refinement=args.frame_refinement)
 
     if not paths:
         # profiling run of one pass: its own section only
         print(json.dumps({"pass": args.only, "steps": args.steps, "warmup": args.warmup,
                           "ms_per_step": ms_per_step, "multi_rhs": mrhs, "gradient": grad,
                           "precond_study": pstudy, "quadrature_study": qstudy,
-                          "spectrum_study": sstudy, "blr_study": bstudy, "frame_study": fstudy}),
+                          "spectrum_study": sstudy, "blr_study": bstudy, "frame_study": fstudy,
+                          "spheroid5120": spheroid}),
               flush=True)
         for S in (Smr, Sg):
             if S is not None:
                 S.close()
         return
 
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle fill")
-    cpu = None if args.no_cpu_baseline else cpu_baseline(xyz, tri, cfg, N)
     line = {
         "metric": "Z fill (entries/s) + GMRES solve s at 1e-6 far-field err; mixed vs FP64",
         "value": res[head]["fill_rate"],
@@ -718,6 +851,8 @@ def main():
                    "headline_path": head, "gmres_tol": cfg["tol"], "mbj_block": cfg["mbj_block"]},
         "paths": {p: {k: v for k, v in res[p].items()} for p in paths},
         "solve_s": {p: res[p]["t_solve_ms"] * 1e-3 for p in paths},
+        "solve_s_at_1e-6_farfield": ({p: sweeps[p]["solve_s"] for p in paths} if sweeps else None),
+        "tol_sweep": sweeps,
         "accuracy": info,
         "roofline": roof,
         "rooflines": rooflines,
@@ -728,6 +863,7 @@ def main():
         "spectrum_study": sstudy,
         "blr_study": bstudy,
         "frame_study": fstudy,
+        "spheroid5120": spheroid,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

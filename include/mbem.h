@@ -117,9 +117,14 @@ enum { MBEM_QUAD_DEFAULT = 0, MBEM_QUAD_PAPER = 1 };
 enum { MBEM_FRAME_INTERPOLATED = 0, MBEM_FRAME_NODAL = 1 };
 
 typedef struct {
-    double tol;          /* relative residual target |b - Z x| / |b|        */
+    double tol;          /* relative residual target |b - Z x| / |b|, met by
+                            the explicit FP64-accumulated residual          */
     int32_t maxit;       /* GMRES iteration limit (Krylov dimension)         */
-    int32_t max_refine;  /* MIXED: outer refinement sweeps (0 -> 8)          */
+    int32_t max_refine;  /* MIXED: outer refinement sweeps (0 -> 8); FP64:
+                            GMRES runs in all, the first on b and the others
+                            from the explicit residual when the Arnoldi
+                            estimate met tol but the explicit residual did
+                            not (0 -> 3)                                     */
     double inner_tol;    /* MIXED: inner GMRES tolerance (0 -> 1e-4)          */
 } mbem_solve_opts;
 
@@ -242,10 +247,15 @@ int mbem_rhs_planewave(mbem_ctx *ctx, const mbem_mesh *mesh,
                        const mbem_c128 *pol, int32_t nrhs, mbem_c128 *b);
 
 /* Solve Z x = b by GMRES (x0 = 0, classical Gram-Schmidt twice in FP64,
- * right-preconditioned by the Morton block-Jacobi matrix if set up).  For a
- * MIXED operator the inner GMRES applies the complex64 matrix and an outer
- * FP64-accumulated residual refines x.  b, x: device [N*nrhs] complex128.
- * MBEM_ENOCONV if the tolerance was not reached (x holds the last iterate). */
+ * right-preconditioned by the Morton block-Jacobi matrix if set up; Sec. 5).
+ * For a MIXED operator the inner GMRES applies the complex64 matrix and an
+ * outer FP64-accumulated residual refines x.  b, x: device [N*nrhs]
+ * complex128.  A column is converged when its explicit residual
+ * |b - Z x| / |b| (FP64 accumulation) is at most tol; a zero column gives
+ * x = 0.  MBEM_EINVAL if a column of b is not finite (nothing is solved);
+ * MBEM_ENOCONV if some column did not converge within maxit (and the
+ * refinement sweeps): x holds the last iterate and stats->rel_resid the
+ * worst explicit residual.                                                 */
 int mbem_solve(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrhs,
                const mbem_solve_opts *opts, mbem_c128 *x, mbem_stats *stats);
 
@@ -284,19 +294,25 @@ int mbem_farfield_functional(mbem_ctx *ctx, const mbem_mesh *mesh,
  *   (regular and Sauter-Schwab), the P2 map, the continuous frame and the
  *   nodal triads and normals (Sec. 3), with the singular-pair classes and
  *   the reference-vector choice of every node held fixed.
+ *   disp_dir host [n_nodes*3] float64 or NULL: displacement direction d_v
+ *     of every node (Morton order); NULL selects the nodal normals n_v of
+ *     this mesh (Sec. 3.1).  A caller that displaced the nodes along the
+ *     normals of an earlier mesh passes those normals here;
  *   out host [3]: sigma_ext, d/dRe eps_r, d/dIm eps_r;
  *   lambda_out device [N] or NULL;
- *   dsig_dnode device [n_nodes] float64 or NULL: derivative for a
- *     displacement of node v along its nodal normal n_v (Morton order);
+ *   dsig_dnode device [n_nodes] float64 or NULL: derivative for the
+ *     displacement x_v -> x_v + delta_v d_v of node v (Morton order);
  *   dsig_dx device [n_nodes*3] float64 or NULL: derivative for every
  *     coordinate of every node (Morton order);
  *   stats: the adjoint solve.
- * params and op must use the same frame (EINVAL otherwise).  With
+ * params and op must use the same frame and mesh must be op's mesh (EINVAL
+ * otherwise, and for non-finite disp_dir).  With
  * MBEM_FRAME_NODAL the reverse pass goes through the projections of the
  * node-attached fields and the nodal triads instead of the point frame.    */
 int mbem_grad_sigma_ext(mbem_ctx *ctx, mbem_op *op, const mbem_mesh *mesh,
                         const mbem_params *params, const mbem_c128 *x,
                         const double *khat, const mbem_c128 *pol,
+                        const double *disp_dir,
                         const mbem_solve_opts *opts, double *out,
                         mbem_c128 *lambda_out, double *dsig_dnode,
                         double *dsig_dx, mbem_stats *stats);
@@ -382,7 +398,7 @@ int mbem_cross_sections(mbem_ctx *ctx, const mbem_mesh *mesh,
 
 /* ---- block low-rank operator (compressed far interactions) ---------------- */
 
-/* The paper leaves compressed far-field interactions to future work (Sec. 8);
+/* The paper leaves compressed far-field interactions to future work (Sec. 7, Conclusion);
  * this operator stores far tiles of K1, K2^eps, K2^mu in low-rank form.
  * Clusters: the leaves of the octree of the nodes' Morton keys (Sec. 5),
  * cells of more than `cluster` nodes split into their eight children, each
@@ -434,7 +450,7 @@ int mbem_fill_compressed(mbem_ctx *ctx, const mbem_mesh *mesh,
                          mbem_op **out, mbem_stats *stats,
                          mbem_blr_stats *bstats);
 
-/* ---- spectrum sweep (Sec. 7, Benchmark II: the LSPR spectrum) ------------- */
+/* ---- spectrum sweep (Sec. 6.3, Benchmark II: the LSPR spectrum) ----------- */
 
 /* The single-frequency path repeated over npts (k0, eps_r, mu_r) points on
  * one mesh for one plane wave: at each point the operator is refilled in

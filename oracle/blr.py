@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY.
 
-The paper leaves compressed far-field interactions to future work (Sec. 8,
+The paper leaves compressed far-field interactions to future work (Sec. 7, Conclusion,
 FMM for problems beyond dense memory).  The compressed operator checked
 here is defined as follows, on the Morton-ordered nodes of Sec. 5:
 

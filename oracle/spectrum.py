@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY.
 
 A spectrum is the single-frequency path repeated on one mesh: at every
 (k0, eps_r, mu_r) point the operator is filled, the system assembled and
-solved densely, and the cross sections evaluated (Sec. 7, Benchmark II: the
+solved densely, and the cross sections evaluated (Sec. 6.3, Benchmark II: the
 LSPR spectrum of a silver spheroid, one solve per wavelength).  Nothing is
 shared between points except the mesh.
 """

@@ -57,15 +57,15 @@ def _forward(prob: SigmaExtProblem, eps: complex, disp: np.ndarray, want_grad: b
         x, st, code = S.solve(b, tol=prob.tol, maxit=prob.maxit, inner_tol=prob.inner_tol)
         if code != mbem.MBEM_OK:
             raise mbem.MbemError(code, "forward solve did not converge")
+        # the nodes moved along the undisplaced normals, so the library
+        # projects the position gradient on those, not on this mesh's normals
         res = S.grad_sigma_ext(x[0], prob.khat, prob.pol, tol=prob.tol, maxit=prob.maxit,
-                               inner_tol=prob.inner_tol, shape=want_grad)
+                               inner_tol=prob.inner_tol, shape=want_grad,
+                               disp_dir=prob.nodal_normals() if want_grad else None)
         out = res[0]
         if not want_grad:
             return out[0], None, None
-        dx = res[4].cpu().numpy()
-        # d sigma / d disp_v = (d sigma / d x_v) . n_v (undisplaced normals)
-        ddisp = np.einsum("ij,ij->i", dx, prob.nodal_normals())
-        return out[0], out[1:3].copy(), ddisp
+        return out[0], out[1:3].copy(), res[3].cpu().numpy()
     finally:
         S.close()
 

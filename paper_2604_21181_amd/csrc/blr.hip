@@ -1,7 +1,7 @@
 // Block low-rank (BLR) operator: far tiles of K1, K2^eps and K2^mu stored as
 // products U V^T from adaptive cross approximation (ACA), near tiles dense.
 // The paper stops at the dense operator and names fast far-field methods as
-// future work (Sec. 8); this extends the solve to meshes whose dense blocks
+// future work (Sec. 7, Conclusion); this extends the solve to meshes whose dense blocks
 // exceed one device's memory.  The operator is filled one band of rows (a
 // run of whole row clusters) at a time into a scratch, compressed, and
 // packed; the dense blocks never exist.

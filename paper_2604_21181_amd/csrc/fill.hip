@@ -1,10 +1,13 @@
 // Galerkin fill of K1, K2^eps, K2^mu (Sec. 4.1-4.2, fused as in Sec. 6.1)
 // and of the mass matrix (eq. mass_matrix).
 //
-//  * regular pairs: 7 x 7 quadrature-point pairs per element pair, one
-//    wavefront per pair; the twelve weighted kernel values of every point
-//    pair go to LDS and are contracted with the shape-function table in two
-//    steps (trial side, then test side) before being added to Z;
+//  * regular pairs: 7 x 7 quadrature-point pairs per element pair; one
+//    workgroup per (test triangle, chunk of 4 Morton-consecutive trial
+//    triangles), one launch per (test colour, chunk colour) so that the
+//    workgroups of a launch own disjoint rows x columns of Z; the twelve
+//    weighted kernel values of every point pair go to LDS and are contracted
+//    with the shape functions in two steps (trial side, then test side after
+//    the chunk's triangles are merged by node) before being added to Z;
 //  * singular pairs (coincident, common edge, common vertex): Sauter-Schwab
 //    quadrature, 6 / 5 / 2 regions x n^4 Gauss points, two wavefronts per
 //    pair, FP64;

@@ -50,6 +50,11 @@ std::vector<int64_t> stable_order(const std::vector<uint64_t> &key) {
 int morton_order_host(const double *xyz, int64_t nn, const int64_t *tri6,
                       int64_t nt, std::vector<int64_t> &node_order,
                       std::vector<int64_t> &tri_order, std::vector<uint64_t> *node_keys) {
+    for (int64_t i = 0; i < 3 * nn; ++i)
+        if (!std::isfinite(xyz[i])) {
+            set_error("node coordinate " + std::to_string(i) + " is not finite");
+            return MBEM_EINVAL;
+        }
     double lo[3], hi[3];
     for (int d = 0; d < 3; ++d) lo[d] = hi[d] = xyz[d];
     for (int64_t v = 0; v < nn; ++v)

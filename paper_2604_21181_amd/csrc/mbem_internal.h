@@ -268,8 +268,10 @@ int64_t matvec_t_work(const mbem_op *op);
 int mbj_transpose_run(mbem_op *op, hipStream_t s);
 int dotu_run(const double2 *a, const double2 *b, int64_t n, double2 *out, hipStream_t s);
 // shape.hip: d sigma / d(node positions) from x and lambda (Morton order)
+// dir: device [nn*3] displacement directions for dnode, or null (nodal normals)
 int shape_grad_run(const mbem_op *op, const mbem_params *p, const double2 *x, const double2 *lam,
-                   const double *khat, const double2 *pol, double *dnode, double *dx, hipStream_t s);
+                   const double *khat, const double2 *pol, const double *dir, double *dnode, double *dx,
+                   hipStream_t s);
 
 // multi-right-hand-side solve (block.hip)
 int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_opts *o, double2 *X,

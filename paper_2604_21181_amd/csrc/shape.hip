@@ -871,19 +871,22 @@ __global__ void k_frames_backprop(int64_t nn, const double *__restrict__ xyz, co
     }
 }
 
-// d sigma / d delta_v along the nodal normal, and the full position gradient
+// d sigma / d delta_v along the displacement direction of node v (dir[v],
+// or the nodal normal when dir is null), and the full position gradient
 __global__ void k_shape_out(int64_t nn, double scale, const double *__restrict__ frames,
-                            const double *__restrict__ nodeb_x, double *dnode, double *dx) {
+                            const double *__restrict__ dir, const double *__restrict__ nodeb_x, double *dnode,
+                            double *dx) {
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (v >= nn) return;
-    const double *b = nodeb_x + 9 * v, *nv = frames + 9 * v;
+    const double *b = nodeb_x + 9 * v, *nv = dir ? dir + 3 * v : frames + 9 * v;
     if (dnode) dnode[v] = scale * (b[0] * nv[0] + b[1] * nv[1] + b[2] * nv[2]);
     if (dx) for (int c = 0; c < 3; ++c) dx[3 * v + c] = scale * b[c];
 }
 
 // --------------------------------------------------------------- host ---
 int shape_grad_run(const mbem_op *op, const mbem_params *p, const double2 *x, const double2 *lam,
-                   const double *khat, const double2 *pol, double *dnode, double *dx, hipStream_t s) {
+                   const double *khat, const double2 *pol, const double *dir, double *dnode, double *dx,
+                   hipStream_t s) {
     const mbem_mesh *m = op->mesh;
     const int64_t nt = m->nt, nq = nt * kQP, nn = m->nn;
     double *fields = nullptr, *qb = nullptr, *nodeb = nullptr, *nodeb_x = nullptr;
@@ -991,7 +994,8 @@ int shape_grad_run(const mbem_op *op, const mbem_params *p, const double2 *x, co
     }
     if (st == MBEM_OK) {
         hipLaunchKernelGGL(k_shape_out, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, nn,
-                           4.0 * 3.14159265358979323846 / p->k0, m->d_frames, (const double *)nodeb_x, dnode, dx);
+                           4.0 * 3.14159265358979323846 / p->k0, m->d_frames, dir, (const double *)nodeb_x, dnode,
+                           dx);
         launch_ok();
     }
     if (hipStreamSynchronize(s) != hipSuccess && st == MBEM_OK) { set_error("shape gradient failed"); st = MBEM_EDEVICE; }

@@ -135,7 +135,7 @@ def lib():
             "mbem_solve_adjoint": ([P, P, P, i32, C.POINTER(SolveOpts), P, C.POINTER(Stats)], C.c_int),
             "mbem_fill_deps": ([P, P, C.POINTER(Params), PP, C.POINTER(Stats)], C.c_int),
             "mbem_farfield_functional": ([P, P, C.POINTER(Params), P, P, P], C.c_int),
-            "mbem_grad_sigma_ext": ([P, P, P, C.POINTER(Params), P, P, P, C.POINTER(SolveOpts), P, P,
+            "mbem_grad_sigma_ext": ([P, P, P, C.POINTER(Params), P, P, P, P, C.POINTER(SolveOpts), P, P,
                                      P, P, C.POINTER(Stats)], C.c_int),
             "mbem_spectrum": ([P, P, C.POINTER(Params), i32, P, P, P, P, P, i32,
                                C.POINTER(SolveOpts), i32, P, P, C.POINTER(Stats)], C.c_int),
@@ -162,6 +162,25 @@ def _np_ptr(a):
 
 def _t_ptr(t):
     return C.c_void_p(t.data_ptr())
+
+
+def _check_vec(t, n, device, dtype=None, name="vector"):
+    """Reject, before any library call, a tensor the kernels would read or
+    write out of bounds: it must be a contiguous complex128 (or `dtype`)
+    tensor on the solver's device with exactly n elements."""
+    import torch
+    dtype = torch.complex128 if dtype is None else dtype
+    if not isinstance(t, torch.Tensor):
+        raise MbemError(MBEM_EINVAL, f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise MbemError(MBEM_EINVAL, f"{name}: dtype {t.dtype}, expected {dtype}")
+    if t.numel() != n:
+        raise MbemError(MBEM_EINVAL, f"{name}: {t.numel()} elements, expected {n}")
+    if not t.is_contiguous():
+        raise MbemError(MBEM_EINVAL, f"{name}: not contiguous")
+    if t.device != device:
+        raise MbemError(MBEM_EINVAL, f"{name}: on {t.device}, expected {device}")
+    return t
 
 
 # ---------------------------------------------------------------- C names --
@@ -328,16 +347,23 @@ def mbem_farfield_functional(ctx, mesh, params, rhat, e, g):
 
 
 def mbem_grad_sigma_ext(ctx, op, mesh, params, x, khat, pol, tol=1e-12, maxit=500, inner_tol=0.0,
-                        lam=None, dnode=None, dx=None):
+                        lam=None, dnode=None, dx=None, disp_dir=None):
+    """disp_dir: host [n_nodes, 3] directions in Morton order, or None (nodal normals)."""
     khat = np.ascontiguousarray(khat, dtype=np.float64).ravel()
     pol = np.ascontiguousarray(pol, dtype=np.complex128).ravel()
+    if khat.shape != (3,) or pol.shape != (3,):
+        raise ValueError("khat and pol are 3-vectors")
+    if disp_dir is not None:
+        disp_dir = np.ascontiguousarray(disp_dir, dtype=np.float64)
+        if disp_dir.ndim != 2 or disp_dir.shape[1] != 3:
+            raise ValueError("disp_dir is [n_nodes, 3]")
     o = SolveOpts(tol, maxit, 0, inner_tol)
     out = np.zeros(3)
     st = Stats()
     opt = lambda t: _t_ptr(t) if t is not None else None
     _check(lib().mbem_grad_sigma_ext(ctx, op, mesh, C.byref(params), _t_ptr(x), _np_ptr(khat),
-                                     _np_ptr(pol), C.byref(o), _np_ptr(out), opt(lam), opt(dnode),
-                                     opt(dx), C.byref(st)))
+                                     _np_ptr(pol), _np_ptr(disp_dir) if disp_dir is not None else None,
+                                     C.byref(o), _np_ptr(out), opt(lam), opt(dnode), opt(dx), C.byref(st)))
     return out, st
 
 
@@ -439,17 +465,19 @@ class Solver:
         return Z
 
     def matvec(self, x):
-        y = self.torch.empty_like(x)
         nrhs = 1 if x.dim() == 1 else x.shape[0]
-        mbem_matvec(self.ctx, self.op, x.contiguous(), y, nrhs)
+        x = _check_vec(x.contiguous(), nrhs * self.N, self.device, name="x")
+        y = self.torch.empty_like(x)
+        mbem_matvec(self.ctx, self.op, x, y, nrhs)
         return y
 
     def precond_setup(self, block):
         return mbem_precond_setup(self.ctx, self.op, block)
 
     def precond_apply(self, v):
+        v = _check_vec(v.contiguous(), self.N, self.device, name="v")
         z = self.torch.empty_like(v)
-        mbem_precond_apply(self.ctx, self.op, v.contiguous(), z)
+        mbem_precond_apply(self.ctx, self.op, v, z)
         self.torch.cuda.synchronize()
         return z
 
@@ -461,22 +489,26 @@ class Solver:
 
     def solve(self, b, tol, maxit=500, max_refine=0, inner_tol=0.0):
         b = b if b.dim() == 2 else b[None]
+        b = _check_vec(b.contiguous(), b.shape[0] * self.N, self.device, name="b")
         x = self.torch.empty_like(b)
-        code, st = mbem_solve(self.ctx, self.op, b.contiguous(), x, b.shape[0], tol, maxit,
-                              max_refine, inner_tol)
+        code, st = mbem_solve(self.ctx, self.op, b, x, b.shape[0], tol, maxit, max_refine, inner_tol)
         return x, st, code
 
     def solve_block(self, b, tol, **kw):
         """b [nrhs, N] complex128 device tensor -> (x, BlockStats, code)."""
+        if b.dim() != 2:
+            raise MbemError(MBEM_EINVAL, "b: expected [nrhs, N]")
+        b = _check_vec(b.contiguous(), b.shape[0] * self.N, self.device, name="b")
         x = self.torch.empty_like(b)
-        code, st = mbem_solve_block(self.ctx, self.op, b.contiguous(), x, b.shape[0], tol, **kw)
+        code, st = mbem_solve_block(self.ctx, self.op, b, x, b.shape[0], tol, **kw)
         return x, st, code
 
     def solve_adjoint(self, g, tol, maxit=500, max_refine=0, inner_tol=0.0):
         g = g if g.dim() == 2 else g[None]
+        g = _check_vec(g.contiguous(), g.shape[0] * self.N, self.device, name="g")
         lam = self.torch.empty_like(g)
-        code, st = mbem_solve_adjoint(self.ctx, self.op, g.contiguous(), lam, g.shape[0], tol, maxit,
-                                      max_refine, inner_tol)
+        code, st = mbem_solve_adjoint(self.ctx, self.op, g, lam, g.shape[0], tol, maxit, max_refine,
+                                      inner_tol)
         return lam, st, code
 
     def deps_blocks(self):
@@ -503,17 +535,24 @@ class Solver:
         mbem_farfield_functional(self.ctx, self.mesh, self.params, rhat, e, g)
         return g
 
-    def grad_sigma_ext(self, x, khat, pol, tol=1e-12, maxit=500, inner_tol=0.0, shape=False):
+    def grad_sigma_ext(self, x, khat, pol, tol=1e-12, maxit=500, inner_tol=0.0, shape=False,
+                       disp_dir=None):
         """(sigma_ext, d/dRe eps_r, d/dIm eps_r), adjoint-solve stats, lambda and,
-        with shape=True, d sigma/d(normal displacement) [n_nodes] and
+        with shape=True, d sigma/d(node displacement) [n_nodes] along disp_dir
+        ([n_nodes, 3] in the caller's node order; None: the nodal normals) and
         d sigma/d(node coordinates) [n_nodes, 3], both in the caller's node order."""
         t = self.torch
+        x = _check_vec(x.reshape(-1).contiguous(), self.N, self.device, name="x")
+        if disp_dir is not None:
+            disp_dir = np.asarray(disp_dir, dtype=np.float64)
+            if disp_dir.shape != (self.nn, 3):
+                raise MbemError(MBEM_EINVAL, f"disp_dir: shape {disp_dir.shape}, expected ({self.nn}, 3)")
+            disp_dir = disp_dir[self.node_order]          # Morton order
         lam = t.empty(self.N, dtype=t.complex128, device=self.device)
         dnode = t.empty(self.nn, dtype=t.float64, device=self.device) if shape else None
         dx = t.empty((self.nn, 3), dtype=t.float64, device=self.device) if shape else None
-        x = x.reshape(-1)[: self.N].contiguous()
         out, st = mbem_grad_sigma_ext(self.ctx, self.op, self.mesh, self.params, x, khat, pol, tol,
-                                      maxit, inner_tol, lam, dnode, dx)
+                                      maxit, inner_tol, lam, dnode, dx, disp_dir=disp_dir)
         if not shape:
             return out, st, lam
         inv = t.as_tensor(np.argsort(self.node_order), device=self.device)
@@ -525,13 +564,15 @@ class Solver:
     def farfield(self, x, rhat):
         t = self.torch
         x = x if x.dim() == 2 else x[None]
+        x = _check_vec(x.contiguous(), x.shape[0] * self.N, self.device, name="x")
         r = t.as_tensor(np.ascontiguousarray(rhat, dtype=np.float64), device=self.device)
         F = t.empty((x.shape[0], r.shape[0], 3), dtype=t.complex128, device=self.device)
         mbem_farfield(self.ctx, self.mesh, self.params, x.contiguous(), x.shape[0], r, F)
         return F
 
     def cross_sections(self, x, khat, pol, ntheta=0):
-        return mbem_cross_sections(self.ctx, self.mesh, self.params, x.contiguous(), khat, pol, ntheta)
+        x = _check_vec(x.reshape(-1).contiguous(), self.N, self.device, name="x")
+        return mbem_cross_sections(self.ctx, self.mesh, self.params, x, khat, pol, ntheta)
 
     def spectrum(self, k0, eps_r, khat, pol, mu_r=None, block=100, tol=1e-5, **kw):
         """Sweep on this solver's mesh with its precision and quadrature (its

@@ -144,3 +144,65 @@ def test_struct_fields_match_header():
              ("mbem_block_opts", mbem.BlockOpts), ("mbem_block_stats", mbem.BlockStats)]
     for cname, py in pairs:
         assert fields[cname] == [f for f, _ in py._fields_], cname
+
+
+def test_non_finite_mesh_rejected():
+    """A NaN or infinite node coordinate is rejected on the host (EINVAL)
+    before any ordering or device work."""
+    from paper_2604_21181_amd import mbem
+    xyz, tri = icosphere_p2(80)
+    for bad_value in (np.nan, np.inf):
+        bad = xyz.copy()
+        bad[7, 1] = bad_value
+        with pytest.raises(mbem.MbemError) as e:
+            mbem.mbem_morton_order(bad, tri)
+        assert e.value.code == mbem.MBEM_EINVAL
+        assert "not finite" in str(e.value)
+
+
+def test_binding_rejects_wrong_vectors_without_a_device_call():
+    """Solver methods check dtype, device, size and layout of every tensor
+    they hand to the library and raise MBEM_EINVAL first (a wrong buffer
+    would otherwise be read or written out of bounds on the device)."""
+    import torch
+    from paper_2604_21181_amd import mbem
+    S = object.__new__(mbem.Solver)       # no context: any library call would fail differently
+    S.torch, S.device, S.N, S.nn = torch, torch.device("cuda", 0), 648, 162
+    S.ctx = S.op = S.mesh = None
+    S.node_order = np.arange(162)
+    good_cpu = torch.zeros(648, dtype=torch.complex128)
+    cases = [
+        (S.solve, (torch.zeros(648, dtype=torch.complex64), 1e-8), "dtype"),
+        (S.solve, (good_cpu, 1e-8), "expected cuda"),
+        (S.solve, (torch.zeros(600, dtype=torch.complex128), 1e-8), "elements"),
+        (S.solve_adjoint, (good_cpu, 1e-8), "expected cuda"),
+        (S.solve_block, (torch.zeros(648, dtype=torch.complex128), 1e-8), "[nrhs, N]"),
+        (S.solve_block, (torch.zeros(2, 648, dtype=torch.complex128), 1e-8), "expected cuda"),
+        (S.matvec, (torch.zeros(648, dtype=torch.float64),), "dtype"),
+        (S.precond_apply, (good_cpu,), "expected cuda"),
+        (S.farfield, (good_cpu, np.zeros((4, 3))), "expected cuda"),
+        (S.cross_sections, (good_cpu, [0, 0, 1], [1, 0, 0]), "expected cuda"),
+        (S.grad_sigma_ext, (good_cpu, [0, 0, 1], [1, 0, 0]), "expected cuda"),
+    ]
+    for fn, args, msg in cases:
+        with pytest.raises(mbem.MbemError) as e:
+            fn(*args)
+        assert e.value.code == mbem.MBEM_EINVAL, fn.__name__
+        assert msg in str(e.value), (fn.__name__, str(e.value))
+
+
+def test_non_finite_parameters_rejected():
+    """Non-finite wavenumber, materials or near radius are rejected on the
+    host (EINVAL) before the mesh or a device is looked at."""
+    import ctypes as C
+    from paper_2604_21181_amd import mbem
+    L = mbem.lib()
+    op = C.c_void_p()
+    for kw in (dict(k0=float("nan")), dict(k0=float("inf")), dict(eps_r=complex(float("nan"), 0)),
+               dict(mu_r=complex(1.0, float("inf"))), dict(near_radius=float("nan"))):
+        a = dict(k0=1.0, eps_r=4.0, mu_r=1.0, near_radius=0.0)
+        a.update(kw)
+        p = mbem.make_params(a["k0"], a["eps_r"], a["mu_r"], near_radius=a["near_radius"])
+        assert L.mbem_fill(None, None, C.byref(p), C.byref(op), None) == mbem.MBEM_EINVAL, kw
+        assert "finite" in L.mbem_last_error().decode(), kw
+        assert L.mbem_fill_deps(None, None, C.byref(p), C.byref(op), None) == mbem.MBEM_EINVAL, kw

@@ -201,3 +201,37 @@ def test_block_solve_rejects_bad_input(case):
         torch.cuda.synchronize()
     finally:
         S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_block_solve_128_rhs_full_blocks_every_tile_shape(case, prec):
+    """128 right-hand sides (64 seeded directions x 2 polarisations, the
+    shape of the multi-RHS workload) in blocks of p = 32 columns, the
+    largest block the solve stages in LDS, for every FP32 tile shape,
+    against the LU solutions of the oracle's operator."""
+    mbem = _mbem()
+    khat, pol = planewave_set(64, seed=0)
+    P = galerkin.Problem(case["xyz"], case["tri"], case["k0"], case["eps"])
+    K = core.fill(case["xyz"], case["tri"], P.phys)
+    Z = galerkin.assemble(P, *K, galerkin.mass_matrix(P))
+    X = solver.solve_columns(Z, galerkin.planewave_rhs(P, khat, pol).T)      # [128, N]
+    S = _solver(case, mbem.MBEM_FP64 if prec == "fp64" else mbem.MBEM_MIXED)
+    try:
+        S.fill()
+        S.precond_setup(100)
+        b = S.rhs(khat, pol)
+        xo = X[:, S.perm]
+        x0 = None
+        for cfg in range(mbem.GEMM_CONFIGS):
+            x, st, code = S.solve_block(b, 1e-12, block=32, gemm_config=cfg)
+            assert code == 0 and st.block == 32 and st.gemm_config == cfg and st.rel_resid <= 1e-12
+            xg = x.cpu().numpy()
+            err = np.linalg.norm(xg - xo, axis=1) / np.linalg.norm(xo, axis=1)
+            assert err.max() < (1e-9 if prec == "fp64" else 1e-5), (cfg, err.max())
+            if x0 is None:
+                x0 = xg
+            else:
+                d = np.linalg.norm(xg - x0, axis=1) / np.linalg.norm(x0, axis=1)
+                assert d.max() < 1e-10, (cfg, d.max())
+    finally:
+        S.close()

@@ -105,7 +105,7 @@ def test_sphere1280_sampled_entries_and_solve(sphere1280, prec):
         kh, pol = planewaves("sphere1280")
         b = S.rhs(kh, pol)
         xs, st, code = S.solve(b, tol=cfg["tol"], maxit=600, inner_tol=1e-4)
-        assert code == 0 and st.rel_resid <= 2 * cfg["tol"]
+        assert code == 0 and st.rel_resid <= cfg["tol"]
     finally:
         S.close()
 
@@ -165,7 +165,7 @@ def test_sphere1280_paper_scheme_sampled_entries(sphere1280):
         kh, pol = planewaves("sphere1280")
         b = S.rhs(kh, pol)
         xs, st, code = S.solve(b, tol=cfg["tol"], maxit=600)
-        assert code == 0 and st.rel_resid <= 2 * cfg["tol"]
+        assert code == 0 and st.rel_resid <= cfg["tol"]
     finally:
         S.close()
 
@@ -242,7 +242,7 @@ def test_spheroid5120_mixed_entries_and_solve():
         x, sst, code = S.solve(b, tol=cfg["tol"], maxit=800, inner_tol=1e-4)
         print(f"  iterations {sst.iters}, sweeps {sst.outer_iters}, residual {sst.rel_resid:.2e}",
               flush=True)
-        assert code == 0 and sst.rel_resid <= 2 * cfg["tol"]
+        assert code == 0 and sst.rel_resid <= cfg["tol"]
     finally:
         S.close()
 
@@ -318,3 +318,68 @@ def test_ellipsoid1280_adjoint_vs_central_differences():
     got = float(np.dot(gdisp, direction))
     print(f"  direction: adjoint {got:.8e}  FD {fd:.8e}", flush=True)
     assert abs(got - fd) < 1e-5 * abs(fd)
+
+
+def test_sphere1280_farfield_vs_oracle_lu(sphere1280):
+    """The benchmark workload against the oracle itself at full size: the
+    oracle's dense FP64 fill (every element pair on the host cores) and LU
+    solve give the reference far field at the 360 cut-plane angles; the
+    GPU's FP64 path (GMRES to 1e-12) must meet it to 1e-10 and the mixed
+    path (complex64 far pairs, FP64 refinement to 1e-10) to 1e-6."""
+    import time
+    from paper_2604_21181_amd import mbem
+    cfg, xyz, tri = sphere1280
+    kh, pol = planewaves("sphere1280")
+    r = cut_plane_directions(360)
+    t0 = time.time()
+    P = galerkin.Problem(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"])
+    K = core.fill(xyz, tri, P.phys)
+    Z = galerkin.assemble(P, *K, galerkin.mass_matrix(P))
+    del K
+    xo = np.linalg.solve(Z, galerkin.planewave_rhs(P, kh, pol)[:, 0])
+    del Z
+    Fo = galerkin.far_field(P, xo, r)
+    print(f"\n[sphere1280 oracle fill + LU: {time.time() - t0:.1f} s]", flush=True)
+    for prec, tol, bound in ((mbem.MBEM_FP64, 1e-12, 1e-10), (mbem.MBEM_MIXED, 1e-10, 1e-6)):
+        S = mbem.Solver(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"], precision=prec)
+        try:
+            S.fill()
+            S.precond_setup(cfg["mbj_block"])
+            x, st, code = S.solve(S.rhs(kh, pol), tol=tol, maxit=600, inner_tol=1e-4)
+            assert code == 0, (prec, code, st.rel_resid)
+            F = S.farfield(x, r).cpu().numpy()[0]
+            e = np.linalg.norm(F - Fo) / np.linalg.norm(Fo)
+            print(f"  precision {prec}: far field vs oracle LU {e:.3e} ({st.iters} iterations)", flush=True)
+            assert e < bound, (prec, e)
+        finally:
+            S.close()
+
+
+def test_spheroid5120_mixed_farfield_matches_fp64():
+    """The plasmonic spheroid (40968 unknowns, eps_r = -10 + i, B = 256):
+    the mixed path's far field at the 360 cut-plane angles is within 1e-6
+    of the FP64 path's (both solved to 1e-10), the bar the mixed path is
+    held to on every workload."""
+    import torch
+    from paper_2604_21181_amd import mbem
+    cfg = get_config("spheroid5120")
+    xyz, tri = icosphere_p2(cfg["n_tris"], cfg["axes"])
+    kh, pol = planewaves("spheroid5120")
+    r = cut_plane_directions(360)
+    F = {}
+    for prec in (mbem.MBEM_FP64, mbem.MBEM_MIXED):
+        print(f"\n[spheroid5120 far field, precision {prec}]", flush=True)
+        S = mbem.Solver(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"], precision=prec)
+        try:
+            S.fill()
+            S.precond_setup(cfg["mbj_block"])
+            x, st, code = S.solve(S.rhs(kh, pol), tol=1e-10, maxit=1000, inner_tol=1e-4)
+            print(f"  iterations {st.iters}, sweeps {st.outer_iters}, residual {st.rel_resid:.2e}", flush=True)
+            assert code == 0, (prec, code, st.rel_resid)
+            F[prec] = S.farfield(x, r).cpu().numpy()[0]
+        finally:
+            S.close()
+            torch.cuda.empty_cache()
+    e = np.linalg.norm(F[mbem.MBEM_MIXED] - F[mbem.MBEM_FP64]) / np.linalg.norm(F[mbem.MBEM_FP64])
+    print(f"  mixed vs FP64: {e:.3e}", flush=True)
+    assert e < 1e-6, e

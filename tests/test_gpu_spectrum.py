@@ -1,4 +1,4 @@
-"""GPU parity of the spectrum sweep (mbem_spectrum, Sec. 7 Benchmark II).
+"""GPU parity of the spectrum sweep (mbem_spectrum, Sec. 6.3 Benchmark II).
 
 Small mesh: the sweep's cross sections against the oracle's sweep, point by
 point (FP64: 1e-9 relative; MIXED with FP64 refinement: 1e-6, the far-field

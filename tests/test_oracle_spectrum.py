@@ -1,7 +1,7 @@
 """Pins of the spectrum sweep and its inputs (CPU).
 
 * The permittivity interpolation reproduces the table rows and the value the
-  paper quotes at the resonance peak (Sec. 7, Benchmark II).
+  paper quotes at the resonance peak (Sec. 6.3, Benchmark II).
 * The cubed-sphere mesh has the paper's element, node and unknown counts.
 * The Mie series for a plasmonic sphere tends to the quasi-static dipole.
 * The oracle's sweep on silver spheres matches Mie at every wavelength,

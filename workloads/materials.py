@@ -1,7 +1,7 @@
 """Optical constants of silver and the LSPR wavelength grid.
 
 The table is the paper's printed excerpt of Johnson and Christy's silver
-data (Sec. 7, Table "Optical constants of silver"): wavelength in nm,
+data (Sec. 6.3, Benchmark II, table "Optical constants of silver"): wavelength in nm,
 refractive index n and extinction coefficient kappa, with
 eps_r = (n + i kappa)^2.  Between table rows n and kappa are interpolated
 linearly in the wavelength (the paper only says that the permittivity is
