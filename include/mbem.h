@@ -63,8 +63,10 @@ typedef enum {
 typedef enum {
     MBEM_FP64 = 0,   /* all pairs in FP64, Z stored complex128             */
     MBEM_MIXED = 1   /* far regular pairs in FP32, near and singular pairs
-                        in FP64, Z stored complex64; FP64 Arnoldi and an
-                        FP64-accumulated refinement residual              */
+                        in FP64, Z stored complex64 (or, with near_store,
+                        the near and singular part in an FP64 sparse store
+                        beside it); FP64 Arnoldi and an FP64-accumulated
+                        refinement residual                               */
 } mbem_precision;
 
 typedef struct mbem_ctx mbem_ctx;    /* device ordinal + borrowed stream      */
@@ -83,7 +85,24 @@ typedef struct {
                                    1.89 / sqrt|k_a^2 - k_i^2|                */
     int32_t quadrature;         /* MBEM_QUAD_DEFAULT or MBEM_QUAD_PAPER      */
     int32_t frame;              /* MBEM_FRAME_INTERPOLATED or MBEM_FRAME_NODAL */
+    int32_t near_store;         /* MIXED, default quadrature: 1 keeps the
+                                   near and singular element pairs' part of
+                                   Z in FP64 (see below); 0 rounds it into
+                                   the complex64 blocks.  Ignored for FP64  */
 } mbem_params;
+
+/* The FP64 near store (MIXED with near_store = 1).  The kernel differences
+ * cancel as R -> 0 (Sec. 2.3), so the element pairs closer than the near
+ * radius and the singular pairs are evaluated in FP64; with the store their
+ * contributions are also accumulated and kept in FP64: for every node pair
+ * (i, j) touched by such an element pair, a 2 x 2 (alpha, beta) block of
+ * K1, K2^eps and K2^mu in complex128 on the node-pair pattern of those
+ * pairs (built on the device at every fill), while the far element pairs
+ * go to the complex64 blocks.  Z = complex64 blocks + store.  The products
+ * (mbem_matvec, the solves' residuals, the transposed product), the
+ * block-Jacobi blocks and the exports read both.  mbem_solve_block folds
+ * the store into the complex64 blocks first (its block product runs on
+ * complex64 entries).                                                      */
 
 /* Quadrature of the operator blocks.
  * MBEM_QUAD_DEFAULT: the 7-point rule on every regular element pair (closed

@@ -5,6 +5,7 @@
 #include <algorithm>
 
 #include "mbem_internal.h"
+#include "near_store.h"
 #include "p2_device.h"
 
 namespace mbem {
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(256) void k_combine_t(int64_t n2, int nch, const do
                                                    const int32_t *__restrict__ mcol,
                                                    const double *__restrict__ mval,
                                                    const double2 *__restrict__ l1,
-                                                   const double2 *__restrict__ l2, TCoef c,
+                                                   const double2 *__restrict__ l2, TCoef c, NearView nv,
                                                    double2 *__restrict__ y) {
     __shared__ double2 s_t[4][4][kCombRows];   // [group][slot][row]
     const int lr = threadIdx.x % kCombRows, grp = threadIdx.x / kCombRows;
@@ -141,6 +142,24 @@ __global__ __launch_bounds__(256) void k_combine_t(int64_t n2, int nch, const do
     }
     const int64_t i = r / 2;
     const int al = (int)(r % 2);
+    if (nv.bits) {
+        // the near store, transposed: output row 2 i + al (column of Z)
+        // takes V(k, i)[4 op + 2 a + al] of every stored pair (k, i) times l
+        // at 2 k + a; the pattern is symmetric, so row i lists every k
+        for (int32_t s = nv.rptr[i]; s < nv.rptr[i + 1]; ++s) {
+            const int64_t k = nv.col[s];
+            const int64_t sk = near_slot(nv, k, i);
+            if (sk < 0) continue;
+            const double2 *V = nv.val + 12 * sk + al;
+            const double2 a0 = l1[2 * k], a1 = l1[2 * k + 1], b0 = l2[2 * k], b1 = l2[2 * k + 1];
+            const double2 p0 = zm(V[0], a0), p1 = zm(V[2], a1), q0 = zm(V[0], b0), q1 = zm(V[2], b1);
+            const double2 e0 = zm(V[4], a0), e1 = zm(V[6], a1), m0 = zm(V[8], b0), m1 = zm(V[10], b1);
+            t[0].x += p0.x + p1.x; t[0].y += p0.y + p1.y;
+            t[1].x += q0.x + q1.x; t[1].y += q0.y + q1.y;
+            t[2].x += e0.x + e1.x; t[2].y += e0.y + e1.y;
+            t[3].x += m0.x + m1.x; t[3].y += m0.y + m1.y;
+        }
+    }
     double2 M1 = {0, 0}, M2 = {0, 0};
     for (int32_t s = mptr[i]; s < mptr[i + 1]; ++s) {
         const int64_t col = 2 * (int64_t)mcol[s];
@@ -167,7 +186,7 @@ int matvec_t_run(const mbem_op *op, const double2 *x, double2 *y, double2 *part,
     const mbem_mesh *m = op->mesh;
     hipLaunchKernelGGL(k_combine_t, dim3((unsigned)((n2 + kCombRows - 1) / kCombRows)), dim3(256), 0, s, n2, nch,
                        part, m->d_mptr,
-                       m->d_mcol, op->d_mval, x, x + n2, TCoef{op->iw, op->ce, op->cm}, y);
+                       m->d_mcol, op->d_mval, x, x + n2, TCoef{op->iw, op->ce, op->cm}, op->near_view(), y);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }

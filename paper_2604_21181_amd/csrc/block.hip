@@ -809,6 +809,9 @@ static int block_residual(const mbem_op *op, BlockWork &w, const double2 *X, con
 
 int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_opts *o, double2 *X,
                     mbem_block_stats *st, hipStream_t s) {
+    // the block product runs on complex64 entries: a near store is folded
+    // into them first
+    if (op->near_on) MBEM_TRY(near_fold_run(op, s));
     BlockWork w;
     w.n2 = op->n2;
     w.N = 2 * op->n2;

@@ -70,11 +70,12 @@ static int set_device(const mbem_ctx *ctx) {
 static void mesh_free_device(mbem_mesh *m) {
     void *ps[] = {m->d_xyz, m->d_tri, m->d_inc_ptr, m->d_inc, m->d_spairs, m->d_frames,
                   m->d_qp, m->d_qp32, m->d_elem, m->d_mptr, m->d_mcol, m->d_mslot,
-                  m->d_chunks, m->d_tcol, m->d_ccol, m->d_qp12, m->d_qp12_32};
+                  m->d_chunks, m->d_tcol, m->d_ccol, m->d_tcolour, m->d_ccolour, m->d_qp12, m->d_qp12_32};
     for (void *p : ps) dfree(p);
 }
 
 static void op_free_device(mbem_op *op) {
+    near_free(op);
     for (int o = 0; o < 3; ++o) dfree(op->K[o]);
     for (int o = 0; o < 3; ++o) dfree(op->K32[o]);
     dfree(op->d_mval);
@@ -423,7 +424,13 @@ int mbem_mesh_create(mbem_ctx *ctx, const double *xyz, int64_t n_nodes, const in
     m->tcol_list = T.tcol_list;
     m->spairs = T.spairs;
     const int64_t nq = m->nt * kQP;
-    if ((st = upload(&m->d_xyz, m->xyz, s)) || (st = upload(&m->d_tri, m->tri, s)) ||
+    std::vector<int32_t> tcolour(m->nt), ccolour(T.ccol_list.size());
+    for (size_t c = 0; c + 1 < T.tcol_off.size(); ++c)
+        for (int32_t q = T.tcol_off[c]; q < T.tcol_off[c + 1]; ++q) tcolour[T.tcol_list[q]] = (int32_t)c;
+    for (size_t c = 0; c + 1 < T.ccol_off.size(); ++c)
+        for (int32_t q = T.ccol_off[c]; q < T.ccol_off[c + 1]; ++q) ccolour[T.ccol_list[q]] = (int32_t)c;
+    if ((st = upload(&m->d_tcolour, tcolour, s)) || (st = upload(&m->d_ccolour, ccolour, s)) ||
+        (st = upload(&m->d_xyz, m->xyz, s)) || (st = upload(&m->d_tri, m->tri, s)) ||
         (st = upload(&m->d_inc_ptr, T.inc_ptr, s)) || (st = upload(&m->d_inc, T.inc, s)) ||
         (st = upload(&m->d_spairs, T.spairs, s)) || (st = upload(&m->d_mptr, T.m_ptr, s)) ||
         (st = upload(&m->d_mcol, T.m_col, s)) || (st = upload(&m->d_mslot, T.m_slot, s)) ||
@@ -503,6 +510,12 @@ static int op_create(mbem_ctx *ctx, const mbem_mesh *mesh, const mbem_params *p,
     }
     if (p->frame != MBEM_FRAME_INTERPOLATED && p->frame != MBEM_FRAME_NODAL) {
         set_error("unknown tangential frame");
+        return MBEM_EINVAL;
+    }
+    if (p->near_store != 0 && p->near_store != 1) { set_error("near_store must be 0 or 1"); return MBEM_EINVAL; }
+    if (p->near_store && p->precision == MBEM_MIXED &&
+        (p->quadrature != MBEM_QUAD_DEFAULT || p->frame != MBEM_FRAME_INTERPOLATED)) {
+        set_error("the FP64 near store is built for the default quadrature and the interpolated frame");
         return MBEM_EINVAL;
     }
     MBEM_TRY(set_device(ctx));
@@ -900,6 +913,10 @@ int mbem_solve_block(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nrh
 int mbem_gemm_autotune(mbem_ctx *ctx, mbem_op *op, int32_t nrhs, int32_t reps, float *ms, int32_t *best) {
     if (!op || nrhs < 1 || !best) { set_error("bad argument"); return MBEM_EINVAL; }
     if (op->blr) { set_error("the block product needs a dense operator"); return MBEM_EINVAL; }
+    if (op->near_on) {
+        MBEM_TRY(set_device(ctx));
+        MBEM_TRY(near_fold_run(op, ctx->stream));
+    }
     MBEM_TRY(set_device(ctx));
     const hipStream_t s = ctx->stream;
     MBEM_TRY(ensure_c64_copy(op, s));

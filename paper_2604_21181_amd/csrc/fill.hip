@@ -20,6 +20,7 @@
 
 #include "mbem_internal.h"
 #include "kappa.h"
+#include "near_store.h"
 #include "p2_device.h"
 #include "ssq_map.h"
 
@@ -66,8 +67,15 @@ struct RegArgs {
     const double *einfo;    // [nt][4]
     double near_r;
     int mode;               // 0: every regular pair in T; 1: pairs closer
-                            // than near_r in FP64, the others in T
+                            // than near_r in FP64, the others in T;
+                            // 3: the pairs the near mask leaves (far pairs);
+                            // 4: the pairs it marks (near pairs), added to
+                            // the near store
     unsigned long long *near_count;
+    const uint8_t *nmask;   // modes 3, 4: [nt][n_chunks] near bits per chunk
+    int64_t n_chunks;
+    NearView near;          // mode 4: the FP64 near store
+    const int2 *tiles;      // mode 4: this launch's (test triangle, chunk) tiles
     const KernelConst *K;   // device copy, staged in LDS by every workgroup
     const int32_t *row_map; // null, or node -> row node of a band buffer
     TS *Z[3];
@@ -154,7 +162,10 @@ constexpr int kR1Stride = 209;
 // node's tangents in the frame of each trial point, the test contraction
 // those of each test node in the frames of the test points (the kernels are
 // linear in the test and in the trial vector).
-template <typename T, typename TS, bool DK = false, bool NODAL = false>
+// STORE (mode 4): the near pairs of a MIXED operator in FP64, their blocks
+// added to the FP64 near store instead of Z (the store's slots of one
+// launch are disjoint like its rows x columns).
+template <typename T, typename TS, bool DK = false, bool NODAL = false, bool STORE = false>
 __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     // point-pair kernel values; the trial-side contraction is later written
     // over them in place
@@ -179,8 +190,8 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     const int tid = threadIdx.x;
     stage_kconst(a.K, &s_K, tid, blockDim.x);
     const int64_t tile = xcd_remap(blockIdx.x, a.total);
-    const int64_t e = a.te_list[tile / a.n_ch];
-    const int64_t ch = a.ch_list[tile % a.n_ch];
+    const int64_t e = STORE ? a.tiles[tile].x : a.te_list[tile / a.n_ch];
+    const int64_t ch = STORE ? a.tiles[tile].y : a.ch_list[tile % a.n_ch];
     for (int i = tid; i < kChunkRec; i += blockDim.x) s_rec[i] = a.chunks[ch * kChunkRec + i];
     if (tid < 36) {
         const int g = tid / 6, i = tid % 6;
@@ -204,6 +215,11 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
                 kind = 2;
                 atomicAdd(a.near_count, 1ull);
             }
+        }
+        if (act && a.mode >= 3) {
+            // one classification for both launches: the near mask
+            const bool near = (a.nmask[e * a.n_chunks + ch] >> tid) & 1;
+            kind = (a.mode == 3) != near ? 1 : 0;
         }
         s_act[tid] = kind;
     }
@@ -253,7 +269,7 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     // row i of the test triangle: Z[op][2 te_i + alpha][2 node(sl) + beta].
     // No other workgroup of this launch touches these entries (colour
     // classes), and earlier launches completed in stream order.
-    {
+    if constexpr (!STORE) {
         const int wave = tid / 64;
 #pragma unroll
         for (int k = 0; k < kRounds; ++k) {
@@ -402,6 +418,22 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
                 }
             }
         }
+        if constexpr (STORE) {
+            // only node pairs of a computed (near) element pair are in the
+            // store's pattern: skip slots whose triangles were all skipped
+            bool touched = false;
+            for (int u = s_rec[25 + sl]; u < u1; ++u) touched = touched || s_act[s_rec[50 + u] >> 3] != 0;
+            if (!touched) continue;
+            const int64_t nj = s_rec[1 + sl];
+            const int c = 4 * op + 2 * (g & 1) + be;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                double2 *v = a.near.val + 12 * near_slot(a.near, a.tri[6 * e + i], nj) + c;
+                v->x += (double)out[i].re;
+                v->y += (double)out[i].im;
+            }
+            continue;
+        }
         TS *Z = zblock(a.Z, op) + 2 * (2 * (int64_t)s_rec[1 + sl] + be);
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
@@ -435,6 +467,7 @@ struct SsqArgs {
     const KernelConst *K;   // device copy
     const int32_t *row_map; // null, or node -> row node of a band buffer
     TS *Z[3];
+    NearView near;          // MIXED with the near store: added there in FP64
 };
 
 // Two wavefronts per pair.  Every lane evaluates one quadrature point per
@@ -567,6 +600,13 @@ __device__ __forceinline__ void ssq_flush(const SsqArgs<TS> &a, int32_t e, int32
         }
         const int i = k / 6, j = k % 6;
         const int op = cc / 4, al = (cc / 2) % 2, be = cc % 2;
+        if (a.near.bits) {
+            // every node pair of a singular element pair is in the pattern
+            double *dst = (double *)(a.near.val + 12 * near_slot(a.near, te[i], tf[j]) + cc);
+            atomic_add(dst, re);
+            atomic_add(dst + 1, im);
+            continue;
+        }
         const int64_t tn = a.row_map ? a.row_map[te[i]] : te[i];
         const int64_t row = 2 * tn + al, col = 2 * (int64_t)tf[j] + be;
         TS *dst = zblock(a.Z, op) + 2 * (row * a.n2 + col);
@@ -1130,7 +1170,16 @@ static int nodal_table_run(mbem_op *op, const T *qp, hipStream_t s) {
     return MBEM_OK;
 }
 
-template <typename T, typename TS, bool DK = false, bool P12 = false, bool NODAL = false>
+// Near radius of the mixed path: params.near_radius, or 1.89 / sqrt|k_a^2 -
+// k_i^2| (the gap below which FP32 cancellation of the R^-3 terms reaches
+// about 1e-7).
+static double near_radius_of(const mbem_op *op) {
+    const std::complex<double> ka(op->ka.x, op->ka.y), ki(op->ki.x, op->ki.y);
+    const double dk2 = std::abs(ka * ka - ki * ki);
+    return op->p.near_radius > 0 ? op->p.near_radius : (dk2 > 0 ? 1.89 / std::sqrt(dk2) : 0.0);
+}
+
+template <typename T, typename TS, bool DK = false, bool P12 = false, bool NODAL = false, bool STORE = false>
 static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long *cnt,
                           hipStream_t s, const FillBand *band = nullptr) {
     const mbem_mesh *m = op->mesh;
@@ -1150,15 +1199,28 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
     a.einfo = m->d_elem;
     a.mode = mode;
     a.near_count = cnt;
+    a.nmask = op->d_nmask;
+    a.n_chunks = (m->nt + kChunk - 1) / kChunk;
+    a.near = op->near_view();
+    a.tiles = nullptr;
     a.K = op->d_kconst;
-    double dk2 = std::abs(std::complex<double>(op->ka.x, op->ka.y) * std::complex<double>(op->ka.x, op->ka.y) -
-                          std::complex<double>(op->ki.x, op->ki.y) * std::complex<double>(op->ki.x, op->ki.y));
-    a.near_r = op->p.near_radius > 0 ? op->p.near_radius : (dk2 > 0 ? 1.89 / std::sqrt(dk2) : 0.0);
+    a.near_r = near_radius_of(op);
     a.row_map = band ? band->row_map : nullptr;
     for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)(band ? band->Z[o] : op->K[o]);
     const std::vector<int32_t> &toff = band ? band->tcol_off : m->tcol_off;
     const int32_t *tlist = band ? band->tcol : m->d_tcol;
     const int ntc = (int)toff.size() - 1, ncc = (int)m->ccol_off.size() - 1;
+    if constexpr (STORE) {
+        // only the tiles with near pairs, launch by launch
+        for (int64_t L = 0; L + 1 < (int64_t)op->near_tile_off.size(); ++L) {
+            a.tiles = op->d_ntiles + op->near_tile_off[L];
+            a.total = op->near_tile_off[L + 1] - op->near_tile_off[L];
+            if (a.total == 0) continue;
+            hipLaunchKernelGGL((k_regular<T, TS, DK, NODAL, true>), dim3((unsigned)a.total), dim3(256), 0, s, a);
+            MBEM_HIP(hipGetLastError());
+        }
+        return MBEM_OK;
+    }
     for (int tc = 0; tc < ntc; ++tc)
         for (int cc = 0; cc < ncc; ++cc) {
             a.te_list = tlist + toff[tc];
@@ -1171,7 +1233,7 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
             if constexpr (P12)
                 hipLaunchKernelGGL((k_regular12<T, TS, NODAL>), dim3((unsigned)a.total), dim3(256), 0, s, a);
             else
-                hipLaunchKernelGGL((k_regular<T, TS, DK, NODAL>), dim3((unsigned)a.total), dim3(256), 0, s, a);
+                hipLaunchKernelGGL((k_regular<T, TS, DK, NODAL, STORE>), dim3((unsigned)a.total), dim3(256), 0, s, a);
             MBEM_HIP(hipGetLastError());
         }
     return MBEM_OK;
@@ -1198,6 +1260,7 @@ static int launch_ssq(mbem_op *op, hipStream_t s, const FillBand *band = nullptr
     }
     a.K = PAPER ? op->d_kconst + 1 : op->d_kconst;   // paper: the kernels, then the remainders
     for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)(band ? band->Z[o] : op->K[o]);
+    a.near = band ? NearView{} : op->near_view();
     if (a.npairs == 0) return MBEM_OK;
     if constexpr (PAPER)
         hipLaunchKernelGGL((k_ssq_paper<TS, NODAL>), dim3((unsigned)a.npairs), dim3(SsqShape<NODAL>::threads), 0, s,
@@ -1301,10 +1364,14 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     const size_t esz = op->prec == MBEM_FP64 ? 16 : 8;
     for (int o = 0; o < 3; ++o)
         MBEM_HIP(hipMemsetAsync(op->K[o], 0, esz * op->n2 * op->n2, s));
-    f->counted = op->prec != MBEM_FP64 && !deriv;
+    f->counted = op->prec != MBEM_FP64 && !deriv && !(op->p.near_store && !paper && !nodal);
     if (f->counted) MBEM_HIP(hipMemsetAsync(f->d_cnt, 0, sizeof(unsigned long long), s));
     MBEM_HIP(hipEventRecord(ev[0], s));
     if (geom) MBEM_TRY(geom_build(m, s, paper));
+    // the near store's pattern for this fill's near radius (one host wait)
+    const bool store = op->prec == MBEM_MIXED && !deriv && !paper && !nodal && op->p.near_store;
+    if (store) MBEM_TRY(near_build_run(op, near_radius_of(op), s));
+    else if (op->near_on) near_free(op);
     MBEM_HIP(hipEventRecord(ev[1], s));
     unsigned long long *cnt = f->counted ? f->d_cnt : nullptr;
     if (paper && op->prec == MBEM_FP64) {
@@ -1319,12 +1386,17 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     } else if (op->prec == MBEM_FP64) {
         if (nodal) MBEM_TRY((launch_regular<double, double, false, false, true>(op, 0, m->d_qp, nullptr, s)));
         else MBEM_TRY((launch_regular<double, double>(op, 0, m->d_qp, nullptr, s)));
+    } else if (store) {
+        MBEM_TRY((launch_regular<float, float>(op, 3, m->d_qp32, nullptr, s)));
     } else {
         if (nodal) MBEM_TRY((launch_regular<float, float, false, false, true>(op, 1, m->d_qp32, cnt, s)));
         else MBEM_TRY((launch_regular<float, float>(op, 1, m->d_qp32, cnt, s)));
     }
     MBEM_HIP(hipEventRecord(ev[2], s));
-    MBEM_HIP(hipEventRecord(ev[3], s));   // near pairs run inside the regular launches
+    // near pairs: inside the regular launches, or with the near store in a
+    // launch of their own in FP64
+    if (store) MBEM_TRY((launch_regular<double, double, false, false, false, true>(op, 4, m->d_qp, nullptr, s)));
+    MBEM_HIP(hipEventRecord(ev[3], s));
     if (paper && op->prec == MBEM_FP64 && nodal) MBEM_TRY((launch_ssq<double, false, true, true>(op, s)));
     else if (paper && op->prec == MBEM_FP64) MBEM_TRY((launch_ssq<double, false, true>(op, s)));
     else if (paper && nodal) MBEM_TRY((launch_ssq<float, false, true, true>(op, s)));
@@ -1353,7 +1425,8 @@ int fill_collect(mbem_op *op, double *t_total_ms) {
         float t = 0.f;
         return hipEventElapsedTime(&t, f->ev[a], f->ev[b]) == hipSuccess ? (double)t : 0.0;
     };
-    op->n_near = f->counted ? (int64_t)*f->h_cnt : 0;
+    if (f->counted) op->n_near = (int64_t)*f->h_cnt;
+    else if (!op->near_on) op->n_near = 0;     // with the near store: counted by its build
     op->t_phase[0] = ms(0, 1);
     op->t_phase[1] = ms(1, 2);
     op->t_phase[2] = ms(2, 3);

@@ -311,27 +311,47 @@ int build_tables(const mbem_mesh *m, MeshTables &T) {
         rec[0] = ns;
         rec[25 + ns] = ni;
     }
-    // Greedy colouring (in Morton order) so that the regular-pair fill can
-    // add to Z with plain read-modify-write: inside one colour pair no two
-    // test triangles share a node (disjoint rows) and no two trial chunks
-    // share a node (disjoint columns).
+    // Colour classes (greedy in Morton order, then balanced) so that the
+    // regular-pair fill can add to Z with plain read-modify-write: inside one
+    // launch no two test triangles share a node (disjoint rows) and no two
+    // trial chunks share a node (disjoint columns).  Balancing moves items from classes above the mean
+    // size to smaller classes they do not conflict with, so that every
+    // launch has about the same number of workgroups.
     auto colour = [&](int64_t nitems, auto nodes_of, std::vector<int32_t> &list,
                       std::vector<int32_t> &off) {
         std::vector<std::vector<int32_t>> users(nn);
+        std::vector<std::vector<int32_t>> item_nodes(nitems);
         std::vector<int32_t> col(nitems, -1);
         int ncol = 0;
-        std::vector<int32_t> nodes;
         for (int64_t it = 0; it < nitems; ++it) {
-            nodes.clear();
-            nodes_of(it, nodes);
+            nodes_of(it, item_nodes[it]);
             std::vector<char> used(ncol + 1, 0);
-            for (int32_t v : nodes)
+            for (int32_t v : item_nodes[it])
                 for (int32_t o : users[v]) used[col[o]] = 1;
             int c = 0;
             while (c < ncol && used[c]) ++c;
             col[it] = c;
             ncol = std::max(ncol, c + 1);
-            for (int32_t v : nodes) users[v].push_back((int32_t)it);
+            for (int32_t v : item_nodes[it]) users[v].push_back((int32_t)it);
+        }
+        std::vector<int64_t> size(ncol, 0);
+        for (int64_t it = 0; it < nitems; ++it) size[col[it]]++;
+        const int64_t target = (nitems + ncol - 1) / ncol;
+        for (int round = 0; round < 8; ++round) {
+            int64_t moved = 0;
+            for (int64_t it = 0; it < nitems; ++it) {
+                const int c = col[it];
+                if (size[c] <= target) continue;
+                std::vector<char> used(ncol, 0);
+                for (int32_t v : item_nodes[it])
+                    for (int32_t o : users[v])
+                        if (o != it) used[col[o]] = 1;
+                int best = -1;
+                for (int d = 0; d < ncol; ++d)
+                    if (!used[d] && size[d] < target && (best < 0 || size[d] < size[best])) best = d;
+                if (best >= 0) { col[it] = best; --size[c]; ++size[best]; ++moved; }
+            }
+            if (!moved) break;
         }
         off.assign(ncol + 1, 0);
         for (int64_t it = 0; it < nitems; ++it) off[col[it] + 1]++;

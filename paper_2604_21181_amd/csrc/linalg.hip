@@ -10,6 +10,7 @@
 #include <type_traits>
 
 #include "mbem_internal.h"
+#include "near_store.h"
 
 namespace mbem {
 
@@ -154,14 +155,19 @@ struct Coef { double2 iw, ce, cm; };
 // node has 19, each a dependent index-then-value load) and add their partial
 // sums by shuffles in a fixed order.
 constexpr int kCombLanes = 8;
+// With the FP64 near store (nv.bits non-null) its blocks are added to the
+// four products: row 2 i + al takes V[4 op + 2 al + be] of every stored
+// node pair (i, j) times x at 2 j + be.
 __global__ __launch_bounds__(256) void k_combine(int64_t n2, const double2 *__restrict__ t,
                                                  const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
                                                  const double *__restrict__ mval, const double2 *__restrict__ xj,
-                                                 const double2 *__restrict__ xm, Coef c, double2 *__restrict__ y) {
+                                                 const double2 *__restrict__ xm, Coef c, NearView nv,
+                                                 double2 *__restrict__ y) {
     const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t r = gt / kCombLanes;
     const int l = (int)(gt % kCombLanes);
     double mj[2] = {0, 0}, mm[2] = {0, 0};
+    double nq[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};   // K1 xj, K1 xm, K2e xm, K2m xj (store)
     if (r < n2) {
         const int64_t i = r / 2;
         const int al = (int)(r % 2);
@@ -172,18 +178,38 @@ __global__ __launch_bounds__(256) void k_combine(int64_t n2, const double2 *__re
             mj[0] += v0 * xj[col].x + v1 * xj[col + 1].x; mj[1] += v0 * xj[col].y + v1 * xj[col + 1].y;
             mm[0] += v0 * xm[col].x + v1 * xm[col + 1].x; mm[1] += v0 * xm[col].y + v1 * xm[col + 1].y;
         }
+        if (nv.bits)
+            for (int32_t s = nv.rptr[i] + l; s < nv.rptr[i + 1]; s += kCombLanes) {
+                const int64_t col = 2 * (int64_t)nv.col[s];
+                const double2 *V = nv.val + 12 * (int64_t)s + 2 * al;
+                const double2 a0 = xj[col], a1 = xj[col + 1], b0 = xm[col], b1 = xm[col + 1];
+                const double2 p[4] = {cadd(cmul(V[0], a0), cmul(V[1], a1)), cadd(cmul(V[0], b0), cmul(V[1], b1)),
+                                      cadd(cmul(V[4], b0), cmul(V[5], b1)), cadd(cmul(V[8], a0), cmul(V[9], a1))};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { nq[k][0] += p[k].x; nq[k][1] += p[k].y; }
+            }
     }
 #pragma unroll
-    for (int o = kCombLanes / 2; o > 0; o >>= 1)
+    for (int o = kCombLanes / 2; o > 0; o >>= 1) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             mj[k] += __shfl_xor(mj[k], o, kCombLanes);
             mm[k] += __shfl_xor(mm[k], o, kCombLanes);
         }
+        if (nv.bits)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                nq[k][0] += __shfl_xor(nq[k][0], o, kCombLanes);
+                nq[k][1] += __shfl_xor(nq[k][1], o, kCombLanes);
+            }
+    }
     if (r >= n2 || l != 0) return;
     const double2 Mj = {mj[0], mj[1]}, Mm = {mm[0], mm[1]};
-    y[r] = cadd(cadd(cmul(c.iw, t[r]), t[2 * n2 + r]), cmul(c.ce, Mm));
-    y[n2 + r] = csub(cadd(t[3 * n2 + r], cmul(c.cm, Mj)), cmul(c.iw, t[n2 + r]));
+    const double2 t0 = cadd(t[r], double2{nq[0][0], nq[0][1]}), t1 = cadd(t[n2 + r], double2{nq[1][0], nq[1][1]});
+    const double2 t2 = cadd(t[2 * n2 + r], double2{nq[2][0], nq[2][1]});
+    const double2 t3 = cadd(t[3 * n2 + r], double2{nq[3][0], nq[3][1]});
+    y[r] = cadd(cadd(cmul(c.iw, t0), t2), cmul(c.ce, Mm));
+    y[n2 + r] = csub(cadd(t3, cmul(c.cm, Mj)), cmul(c.iw, t1));
 }
 
 static Coef coef_of(const mbem_op *op) { return {op->iw, op->ce, op->cm}; }
@@ -206,7 +232,7 @@ int matvec_run(const mbem_op *op, const double2 *x, double2 *y, double2 *tmp, hi
     if (after_gemv) MBEM_HIP(hipEventRecord(after_gemv, s));
     const mbem_mesh *m = op->mesh;
     hipLaunchKernelGGL(k_combine, dim3((unsigned)((n2 * kCombLanes + 255) / 256)), dim3(256), 0, s, n2, tmp,
-                       m->d_mptr, m->d_mcol, op->d_mval, x, x + n2, coef_of(op), y);
+                       m->d_mptr, m->d_mcol, op->d_mval, x, x + n2, coef_of(op), op->near_view(), y);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
@@ -226,17 +252,23 @@ __device__ inline double mass_entry(const int32_t *mptr, const int32_t *mcol, co
     return 0.0;
 }
 
+// entry (r, q) of block op: the stored value plus the near store's
+template <typename TS>
+__device__ inline double2 kentry(const void *const K[3], const NearView &nv, int op, int64_t n2, int64_t r,
+                                 int64_t q) {
+    return cadd(kval<TS>(K[op], r * n2 + q), near_value(nv, op, r / 2, q / 2, (int)(r % 2), (int)(q % 2)));
+}
+
 // Z[(ci n2 + r), (cc n2 + q)] for current indices ci, cc in {0, 1}
 template <typename TS>
 __device__ inline double2 z_entry(const void *const K[3], const int32_t *mptr,
                                   const int32_t *mcol, const double *mval, Coef c,
-                                  int64_t n2, int ci, int64_t r, int cc, int64_t q) {
-    const int64_t idx = r * n2 + q;
+                                  int64_t n2, int ci, int64_t r, int cc, int64_t q, const NearView &nv) {
     double2 z;
-    if (ci == 0 && cc == 0) z = cmul(c.iw, kval<TS>(K[0], idx));
-    else if (ci == 1 && cc == 1) { const double2 k = cmul(c.iw, kval<TS>(K[0], idx)); z = {-k.x, -k.y}; }
+    if (ci == 0 && cc == 0) z = cmul(c.iw, kentry<TS>(K, nv, 0, n2, r, q));
+    else if (ci == 1 && cc == 1) { const double2 k = cmul(c.iw, kentry<TS>(K, nv, 0, n2, r, q)); z = {-k.x, -k.y}; }
     else {
-        z = kval<TS>(K[ci == 0 ? 1 : 2], idx);
+        z = kentry<TS>(K, nv, ci == 0 ? 1 : 2, n2, r, q);
         const double mv = mass_entry(mptr, mcol, mval, r / 2, q / 2, (int)(r % 2), (int)(q % 2));
         const double2 cf = ci == 0 ? c.ce : c.cm;
         z.x += cf.x * mv; z.y += cf.y * mv;
@@ -247,13 +279,13 @@ __device__ inline double2 z_entry(const void *const K[3], const int32_t *mptr,
 template <typename TS>
 __global__ void k_export_dense(int64_t n2, const void *K0, const void *K1, const void *K2,
                                const int32_t *mptr, const int32_t *mcol, const double *mval,
-                               Coef c, double2 *Z) {
+                               Coef c, NearView nv, double2 *Z) {
     const int64_t N = 2 * n2;
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (id >= N * N) return;
     const int64_t R = id / N, C = id % N;
     const void *K[3] = {K0, K1, K2};
-    Z[id] = z_entry<TS>(K, mptr, mcol, mval, c, n2, (int)(R / n2), R % n2, (int)(C / n2), C % n2);
+    Z[id] = z_entry<TS>(K, mptr, mcol, mval, c, n2, (int)(R / n2), R % n2, (int)(C / n2), C % n2, nv);
 }
 
 int export_dense_run(const mbem_op *op, double2 *Z, hipStream_t s) {
@@ -263,10 +295,11 @@ int export_dense_run(const mbem_op *op, double2 *Z, hipStream_t s) {
     const unsigned blocks = (unsigned)((N * N + 255) / 256);
     if (op->prec == MBEM_FP64)
         hipLaunchKernelGGL((k_export_dense<double2>), dim3(blocks), dim3(256), 0, s, op->n2,
-                           op->K[0], op->K[1], op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), Z);
+                           op->K[0], op->K[1], op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), NearView{}, Z);
     else
         hipLaunchKernelGGL((k_export_dense<float2>), dim3(blocks), dim3(256), 0, s, op->n2,
-                           op->K[0], op->K[1], op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), Z);
+                           op->K[0], op->K[1], op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op),
+                           op->near_view(), Z);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
@@ -290,6 +323,7 @@ int export_blocks_run(const mbem_op *op, double2 *K1, double2 *K2e, double2 *K2m
             MBEM_HIP(hipGetLastError());
         }
     }
+    if (op->near_on) MBEM_TRY(near_add_dense_run(op, K1, K2e, K2m, s));
     return MBEM_OK;
 }
 
@@ -300,7 +334,7 @@ int export_blocks_run(const mbem_op *op, double2 *K1, double2 *K2e, double2 *K2m
 template <typename TS>
 __global__ void k_mbj_gather(int64_t n2, int B, const void *K0, const void *K1, const void *K2,
                              const int32_t *mptr, const int32_t *mcol, const double *mval,
-                             Coef c, double2 *A) {
+                             Coef c, NearView nv, double2 *A) {
     const int m = blockIdx.y;
     const int64_t b = min((int64_t)B, n2 - (int64_t)m * B);
     const int64_t ld = 2 * B, n = 2 * b;
@@ -310,7 +344,7 @@ __global__ void k_mbj_gather(int64_t n2, int B, const void *K0, const void *K1, 
         const int64_t r = id / n, q = id % n;
         const int ci = r < b ? 0 : 1, cc = q < b ? 0 : 1;
         const int64_t gr = (int64_t)m * B + (r % b), gq = (int64_t)m * B + (q % b);
-        A[(int64_t)m * ld * ld + r * ld + q] = z_entry<TS>(K, mptr, mcol, mval, c, n2, ci, gr, cc, gq);
+        A[(int64_t)m * ld * ld + r * ld + q] = z_entry<TS>(K, mptr, mcol, mval, c, n2, ci, gr, cc, gq, nv);
     }
 }
 
@@ -591,10 +625,10 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s, bool keep) {
                            op->d_mval, coef_of(op), op->d_lu);
     else if (op->prec == MBEM_FP64)
         hipLaunchKernelGGL((k_mbj_gather<double2>), g, dim3(256), 0, s, n2, B, op->K[0], op->K[1],
-                           op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), op->d_lu);
+                           op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), NearView{}, op->d_lu);
     else
         hipLaunchKernelGGL((k_mbj_gather<float2>), g, dim3(256), 0, s, n2, B, op->K[0], op->K[1],
-                           op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), op->d_lu);
+                           op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), op->near_view(), op->d_lu);
     MBEM_HIP(hipGetLastError());
     if (ld <= 512) {
         hipLaunchKernelGGL((k_mbj_lu<512, 8>), dim3(nb), dim3(1024), 0, s, n2, B, op->d_lu, piv, info);

@@ -52,6 +52,20 @@ struct cplx {  // plain complex double for host-side bookkeeping
     double re, im;
 };
 
+// The FP64 near store of a MIXED operator (see near.hip): the node-pair
+// pattern of the near and singular element pairs as bit rows (bit j of row
+// i, nw 32-bit words per row) with the count of set bits before every word
+// of its row, and as a CSR; values [nnz][12] complex128, component
+// 4 op + 2 alpha + beta (op: K1, K2^eps, K2^mu).  bits == nullptr: no store.
+struct NearView {
+    const uint32_t *bits = nullptr;
+    const int32_t *wpre = nullptr;   // [nn][nw]
+    const int32_t *rptr = nullptr;   // [nn + 1]
+    const int32_t *col = nullptr;    // [nnz]
+    double2 *val = nullptr;          // [nnz][12]
+    int64_t nw = 0;
+};
+
 // ---------------------------------------------------------- handles --------
 }  // namespace mbem
 
@@ -91,9 +105,11 @@ struct mbem_mesh {
     std::vector<int32_t> m_ptr, m_col;
     int32_t *d_mptr = nullptr, *d_mcol = nullptr, *d_mslot = nullptr;
     int32_t *d_chunks = nullptr;   // trial-chunk records, kChunkRec ints each
-    // colour classes of the race-free regular-pair fill
+    // colour classes of the race-free regular-pair fill, and the class of
+    // every test triangle and trial chunk
     std::vector<int32_t> tcol_off, ccol_off;
     int32_t *d_tcol = nullptr, *d_ccol = nullptr;
+    int32_t *d_tcolour = nullptr, *d_ccolour = nullptr;
     // host copies for band fills: the test colour lists and singular pairs
     std::vector<int32_t> tcol_list, spairs;
 };
@@ -134,6 +150,28 @@ struct mbem_op {
     mbem::BlrOp *blr = nullptr;
     // events and staging of the last enqueued fill
     mbem::FillState *fs = nullptr;
+    // MIXED with params.near_store: the FP64 near store (near.hip) and, per
+    // (test triangle, trial chunk), the bit mask of the chunk's triangles
+    // that are near (regular) partners of the test triangle
+    bool near_on = false;
+    uint32_t *d_nbits = nullptr;
+    int32_t *d_nwpre = nullptr, *d_nrptr = nullptr, *d_ncol = nullptr;
+    double2 *d_nval = nullptr;
+    uint8_t *d_nmask = nullptr;
+    unsigned long long *d_ncount = nullptr;   // near pairs, nnz, then per launch its near tiles
+    int64_t near_nw = 0, near_nnz = 0, near_cap = 0;
+    // (test triangle, trial chunk) tiles with near pairs, grouped by the
+    // (test colour, chunk colour) launch of the regular-pair fill
+    int2 *d_ntiles = nullptr;
+    unsigned long long *d_ncursor = nullptr;
+    int64_t near_tile_cap = 0;
+    std::vector<int64_t> near_tile_off;       // host: launch -> first tile, one more
+    mbem::NearView near_view() const {
+        mbem::NearView v;
+        if (!near_on) return v;
+        v.bits = d_nbits; v.wpre = d_nwpre; v.rptr = d_nrptr; v.col = d_ncol; v.val = d_nval; v.nw = near_nw;
+        return v;
+    }
 };
 
 namespace mbem {
@@ -272,6 +310,18 @@ int dotu_run(const double2 *a, const double2 *b, int64_t n, double2 *out, hipStr
 int shape_grad_run(const mbem_op *op, const mbem_params *p, const double2 *x, const double2 *lam,
                    const double *khat, const double2 *pol, const double *dir, double *dnode, double *dx,
                    hipStream_t s);
+
+// FP64 near store (near.hip)
+// Builds the near mask and the node-pair pattern of the near and singular
+// element pairs for the op's near radius, sizes and zeroes the values (one
+// host wait for the pattern size).  MIXED ops with params.near_store only.
+int near_build_run(mbem_op *op, double near_r, hipStream_t s);
+// Adds the store into the complex64 blocks and releases it (the op then
+// holds its whole Z in complex64).
+int near_fold_run(mbem_op *op, hipStream_t s);
+void near_free(mbem_op *op);
+// K1, K2e, K2m (complex128, n2 x n2, any may be null) += the store
+int near_add_dense_run(const mbem_op *op, double2 *K1, double2 *K2e, double2 *K2m, hipStream_t s);
 
 // multi-right-hand-side solve (block.hip)
 int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_opts *o, double2 *X,

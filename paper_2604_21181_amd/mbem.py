@@ -45,7 +45,7 @@ class Params(C.Structure):
     _fields_ = [("k0", C.c_double), ("eps_r_re", C.c_double), ("eps_r_im", C.c_double),
                 ("mu_r_re", C.c_double), ("mu_r_im", C.c_double), ("ssq_order", C.c_int32),
                 ("precision", C.c_int32), ("near_radius", C.c_double), ("quadrature", C.c_int32),
-                ("frame", C.c_int32)]
+                ("frame", C.c_int32), ("near_store", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -235,9 +235,10 @@ def mbem_morton_order(xyz, tri6):
 
 
 def make_params(k0, eps_r, mu_r=1.0, precision=MBEM_FP64, ssq_order=4, near_radius=0.0,
-                quadrature=MBEM_QUAD_DEFAULT, frame=MBEM_FRAME_INTERPOLATED):
+                quadrature=MBEM_QUAD_DEFAULT, frame=MBEM_FRAME_INTERPOLATED, near_store=False):
     e, m = complex(eps_r), complex(mu_r)
-    return Params(k0, e.real, e.imag, m.real, m.imag, ssq_order, precision, near_radius, quadrature, frame)
+    return Params(k0, e.real, e.imag, m.real, m.imag, ssq_order, precision, near_radius, quadrature, frame,
+                  1 if near_store else 0)
 
 
 def mbem_fill(ctx, mesh, params):
@@ -413,7 +414,8 @@ class Solver:
     Morton order (``to_morton`` / ``to_user`` map caller-ordered arrays)."""
 
     def __init__(self, xyz, tri6, k0, eps_r, mu_r=1.0, precision=MBEM_FP64, ssq_order=4,
-                 device=0, near_radius=0.0, quadrature=MBEM_QUAD_DEFAULT, frame=MBEM_FRAME_INTERPOLATED):
+                 device=0, near_radius=0.0, quadrature=MBEM_QUAD_DEFAULT, frame=MBEM_FRAME_INTERPOLATED,
+                 near_store=False):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -423,7 +425,8 @@ class Solver:
         self.nn, self.nt, self.N = int(info[0]), int(info[1]), int(info[2])
         self.n_singular = (int(info[3]), int(info[4]), int(info[5]))
         self.node_order, self.tri_order = mbem_mesh_permutation(self.mesh)
-        self.params = make_params(k0, eps_r, mu_r, precision, ssq_order, near_radius, quadrature, frame)
+        self.params = make_params(k0, eps_r, mu_r, precision, ssq_order, near_radius, quadrature, frame,
+                                  near_store)
         self.op = None
         self.fill_stats = None
 

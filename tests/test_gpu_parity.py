@@ -291,3 +291,105 @@ def test_solve_status_codes(case, prec):
     finally:
         if prec == "mixed":
             S.close()
+
+
+def _all_near_node_pairs(xyz, tri, near_r, margin=0.9):
+    """Node pairs (user numbering) every element pair of which is singular
+    (a shared vertex) or clearly near (gap below margin * near_r, gap =
+    centroid distance minus both bounding radii, the radii as the library
+    takes them: 1.25 x the largest node distance from the vertex centroid)."""
+    c = xyz[tri[:, :3]].mean(axis=1)
+    r = 1.25 * np.linalg.norm(xyz[tri] - c[:, None], axis=2).max(axis=1)
+    gap = np.linalg.norm(c[:, None] - c[None], axis=2) - (r[:, None] + r[None])
+    sing = np.zeros(gap.shape, bool)
+    for a in range(3):
+        for b in range(3):
+            sing |= tri[:, a][:, None] == tri[:, b][None]
+    ok = sing | (gap < margin * near_r)
+    nn = xyz.shape[0]
+    bad = np.zeros((nn, nn), bool)
+    E, F = np.nonzero(~ok)
+    for a in range(6):
+        for b in range(6):
+            bad[tri[E, a], tri[F, b]] = True
+    touched = np.zeros((nn, nn), bool)
+    for a in range(6):
+        for b in range(6):
+            touched[tri[:, a][:, None], tri[:, b][None]] = True
+    return np.argwhere(touched & ~bad)
+
+
+def test_mixed_near_store(case):
+    """MIXED with the FP64 near store: far element pairs in complex64, near
+    and singular ones summed and kept in FP64 beside them.  Node pairs that
+    only near or singular element pairs touch are FP64 to 1e-12; every entry
+    is within the mixed bound; the products (forward, transposed, the
+    block-Jacobi blocks) read both parts; the far field meets the oracle's
+    LU solution to 1e-6 and the solution of the same operator without the
+    store to the store's effect; a block solve folds the store first."""
+    import torch
+    mbem = _mbem()
+    xyz, tri, k0, eps = case["xyz"], case["tri"], case["k0"], case["eps"]
+    near_r = 1.89 / np.sqrt(abs(k0 ** 2 - k0 ** 2 * complex(eps)))
+    S = mbem.Solver(xyz, tri, k0, eps, precision=mbem.MBEM_MIXED, near_store=True)
+    try:
+        st = S.fill()
+        assert st.n_near_pairs > 0
+        p1 = S.perm[: 2 * S.nn]
+        Kg = [k.cpu().numpy() for k in S.export_blocks()]
+        K = case["K"]
+        for o in range(3):
+            assert _rel(Kg[o], K[o][np.ix_(p1, p1)]) < 2e-6, o
+        rank = np.empty_like(S.node_order)
+        rank[S.node_order] = np.arange(S.nn)
+        pairs = _all_near_node_pairs(xyz, tri, near_r)
+        assert len(pairs) > 4 * S.nn, len(pairs)
+        for o in range(3):
+            scale = np.abs(K[o]).max()
+            for a in range(2):
+                for b in range(2):
+                    got = Kg[o][2 * rank[pairs[:, 0]] + a, 2 * rank[pairs[:, 1]] + b]
+                    ref = K[o][2 * pairs[:, 0] + a, 2 * pairs[:, 1] + b]
+                    assert np.abs(got - ref).max() <= 1e-12 * scale, (o, a, b)
+        # products against the exported operator
+        Zg = S.export_dense()
+        rng = np.random.default_rng(5)
+        v = torch.as_tensor(rng.normal(size=S.N) + 1j * rng.normal(size=S.N), device=S.device)
+        y = S.matvec(v)
+        ref = Zg @ v
+        assert float((y - ref).abs().max() / ref.abs().max()) < 1e-13
+        S.precond_setup(100)
+        z = S.precond_apply(v)
+        n2, B = S.N // 2, 100
+        for m in range((n2 + B - 1) // B):
+            I = torch.arange(m * B, min((m + 1) * B, n2), device=S.device)
+            idx = torch.cat([I, n2 + I])
+            A = Zg.index_select(0, idx).index_select(1, idx)
+            assert float((A @ z[idx] - v[idx]).abs().max() / v[idx].abs().max()) < 1e-10
+        # forward and transposed solves against the oracle's dense solutions
+        b = S.rhs(KH[None], POL[None])
+        x, sst, code = S.solve(b, tol=1e-12, maxit=300, inner_tol=1e-6)
+        assert code == 0
+        r = cut_plane_directions(360)
+        F = S.farfield(x, r).cpu().numpy()[0]
+        Fo = galerkin.far_field(case["P"], case["x"], r)
+        err_store = np.linalg.norm(F - Fo) / np.linalg.norm(Fo)
+        assert err_store < 1e-6, err_store
+        g = torch.as_tensor(rng.normal(size=S.N) + 1j * rng.normal(size=S.N), device=S.device)
+        lam, ast, acode = S.solve_adjoint(g, tol=1e-12, maxit=300, inner_tol=1e-6)
+        assert acode == 0
+        Zo = case["Z"]
+        pu = S.perm
+        lo = np.linalg.solve(Zo.T, g.cpu().numpy()[np.argsort(pu)])[pu]
+        assert np.linalg.norm(lam.cpu().numpy()[0] - lo) / np.linalg.norm(lo) < 1e-6
+        # the block product folds the store into complex64 and still solves
+        from workloads.configs import planewave_set
+        kh4, po4 = planewave_set(2, seed=1)
+        xb, bst, bcode = S.solve_block(S.rhs(kh4, po4), 1e-11)
+        assert bcode == 0
+        Xo = np.linalg.solve(Zo, galerkin.planewave_rhs(case["P"], kh4, po4)).T[:, S.perm]
+        errb = np.linalg.norm(xb.cpu().numpy() - Xo, axis=1) / np.linalg.norm(Xo, axis=1)
+        assert errb.max() < 1e-5, errb
+        print(f"\n  near store: {st.n_near_pairs} near pairs, far field vs oracle {err_store:.2e}", flush=True)
+    finally:
+        S.close()
