@@ -221,12 +221,14 @@ def test_sphere1280_mixed_farfield_matches_fp64_and_mie(sphere1280):
 
 
 def test_spheroid5120_mixed_entries_and_solve():
-    """The 40968-unknown plasmonic spheroid: complex64 storage, B = 256."""
+    """The 40968-unknown plasmonic spheroid: complex64 storage with the FP64
+    near store, B = 256."""
     from paper_2604_21181_amd import mbem
     cfg = get_config("spheroid5120")
     xyz, tri = icosphere_p2(cfg["n_tris"], cfg["axes"])
     print("\n[spheroid5120 mixed]", flush=True)
-    S = mbem.Solver(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"], precision=mbem.MBEM_MIXED)
+    S = mbem.Solver(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"], precision=mbem.MBEM_MIXED,
+                    near_store=cfg["near_store"])
     try:
         st = S.fill()
         assert S.N == 40968 and st.n_near_pairs > 0
@@ -357,29 +359,46 @@ def test_sphere1280_farfield_vs_oracle_lu(sphere1280):
 
 def test_spheroid5120_mixed_farfield_matches_fp64():
     """The plasmonic spheroid (40968 unknowns, eps_r = -10 + i, B = 256):
-    the mixed path's far field at the 360 cut-plane angles is within 1e-6
-    of the FP64 path's (both solved to 1e-10), the bar the mixed path is
-    held to on every workload."""
+    the mixed path's far field at the 360 cut-plane angles, with the FP64
+    near store (the workload's storage) and without it, is within 1e-6 of
+    the FP64 path's (all solved to 1e-10), the bar the mixed path is held
+    to on every workload; the store's node pairs touched only by near or
+    singular element pairs equal the FP64 operator's to 1e-12 (sampled)."""
     import torch
     from paper_2604_21181_amd import mbem
     cfg = get_config("spheroid5120")
+    assert cfg["near_store"]
     xyz, tri = icosphere_p2(cfg["n_tris"], cfg["axes"])
     kh, pol = planewaves("spheroid5120")
     r = cut_plane_directions(360)
     F = {}
-    for prec in (mbem.MBEM_FP64, mbem.MBEM_MIXED):
-        print(f"\n[spheroid5120 far field, precision {prec}]", flush=True)
-        S = mbem.Solver(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"], precision=prec)
+    for name, prec, store in (("fp64", mbem.MBEM_FP64, False), ("store", mbem.MBEM_MIXED, True),
+                              ("plain", mbem.MBEM_MIXED, False)):
+        print(f"\n[spheroid5120 far field, {name}]", flush=True)
+        S = mbem.Solver(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"], precision=prec, near_store=store)
         try:
             S.fill()
+            if name == "store":
+                # self pairs: every element pair of (i, i) shares node i's vertex
+                rng = np.random.default_rng(17)
+                I = rng.choice(S.nn, 24, replace=False)
+                K = S.export_blocks()
+                ref = core.entries(xyz, tri, core.phys_vector(cfg["k0"], cfg["eps_r"], cfg["mu_r"]), I, I)
+                got = _gpu_entries(S, K, I, I)
+                del K
+                torch.cuda.empty_cache()
+                scale = np.abs(ref).reshape(len(I), -1).max(axis=1)
+                err = np.abs(got - ref).reshape(len(I), -1).max(axis=1)
+                assert np.all(err <= 1e-12 * scale), (err / scale).max()
             S.precond_setup(cfg["mbj_block"])
             x, st, code = S.solve(S.rhs(kh, pol), tol=1e-10, maxit=1000, inner_tol=1e-4)
             print(f"  iterations {st.iters}, sweeps {st.outer_iters}, residual {st.rel_resid:.2e}", flush=True)
-            assert code == 0, (prec, code, st.rel_resid)
-            F[prec] = S.farfield(x, r).cpu().numpy()[0]
+            assert code == 0, (name, code, st.rel_resid)
+            F[name] = S.farfield(x, r).cpu().numpy()[0]
         finally:
             S.close()
             torch.cuda.empty_cache()
-    e = np.linalg.norm(F[mbem.MBEM_MIXED] - F[mbem.MBEM_FP64]) / np.linalg.norm(F[mbem.MBEM_FP64])
-    print(f"  mixed vs FP64: {e:.3e}", flush=True)
-    assert e < 1e-6, e
+    for name in ("store", "plain"):
+        e = np.linalg.norm(F[name] - F["fp64"]) / np.linalg.norm(F["fp64"])
+        print(f"  mixed ({name}) vs FP64: {e:.3e}", flush=True)
+        assert e < 1e-6, (name, e)

@@ -8,7 +8,8 @@ so the exterior wavenumber k_a equals the angular frequency.
   sphere1280   unit sphere, 1280 triangles (2562 nodes, 10248 unknowns),
                k_a = 5, eps_r = 2.25; FP64 vs mixed path, 360 far-field angles.
   spheroid5120 spheroid semi-axes (1,1,2), 5120 triangles (10242 nodes,
-               40968 unknowns), k_a = 4, eps_r = -10 + 1i; block size 256.
+               40968 unknowns), k_a = 4, eps_r = -10 + 1i; block size 256;
+               complex64 storage with FP64 near-field blocks (the near store).
   sphere1280_mrhs  the 1280-triangle sphere at k_a = 3, eps_r = 6 with 128
                right-hand sides (64 seeded directions x 2 polarisations).
   ellipsoid1280  ellipsoid semi-axes (1, 0.8, 0.6), 1280 triangles,
@@ -28,7 +29,7 @@ CONFIGS = {
                        tol=1e-8, nrhs=1),
     "spheroid5120": dict(n_tris=5120, axes=(1.0, 1.0, 2.0), k0=4.0,
                          eps_r=-10.0 + 1.0j, mu_r=1.0 + 0j, mbj_block=256,
-                         tol=1e-6, nrhs=1),
+                         tol=1e-6, nrhs=1, near_store=True),
     "sphere1280_mrhs": dict(n_tris=1280, axes=(1.0, 1.0, 1.0), k0=3.0,
                             eps_r=6.0 + 0j, mu_r=1.0 + 0j, mbj_block=100,
                             tol=1e-8, nrhs=128),
