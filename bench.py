@@ -281,6 +281,262 @@ def spheroid_pass(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3
     return out
 
 
+PRECOND_STUDY = (("sphere1280", (50, 100, 256, 512), 1500),
+                 ("spheroid5120", (50, 100, 256, 512), 2000),
+                 ("spheroid_lspr@506nm", (50, 100, 256, 512), 2000))
+PRECOND_TOL = 1e-5        # the tolerance of the paper's preconditioner comparisons
+
+
+def _precond_case(name, get_config, icosphere_p2, planewaves):
+    """(xyz, tri, k0, eps_r, mu_r, khat, pol) of a preconditioner-study case."""
+    if name == "spheroid_lspr@506nm":
+        from workloads import spectrum_workload
+        xyz, tri, _, k0, eps, kh, po, _ = spectrum_workload("spheroid_lspr", [506.0])
+        return xyz, tri, float(k0[0]), complex(eps[0]), 1.0, kh[None], po[None]
+    c = get_config(name)
+    xyz, tri = icosphere_p2(c["n_tris"], c["axes"])
+    kh, po = planewaves(name)
+    return xyz, tri, c["k0"], c["eps_r"], c["mu_r"], kh, po
+
+
+def precond_study(mbem, get_config, icosphere_p2, planewaves, log):
+    """GMRES iterations and times without a preconditioner and with Morton
+    block-Jacobi over a sweep of the cluster size, FP64 operator, one plane
+    wave, tolerance 1e-5; run once after the timed steps."""
+    out = {}
+    for wl, blocks, maxit in PRECOND_STUDY:
+        xyz, tri, k0, eps, mu, kh, po = _precond_case(wl, get_config, icosphere_p2, planewaves)
+        S = mbem.Solver(xyz, tri, k0, eps, mu, precision=mbem.MBEM_FP64)
+        try:
+            fs = S.fill()
+            b = S.rhs(kh, po)
+            n2 = S.N // 2
+            res = {"unknowns": S.N, "k0": k0, "eps_r": str(eps), "tol": PRECOND_TOL,
+                   "precision": "fp64", "t_fill_ms": fs.t_fill_ms}
+            S.precond_setup(0)
+            x, st, code = S.solve(b, tol=PRECOND_TOL, maxit=maxit)
+            base = {"iters": st.iters, "t_solve_ms": st.t_solve_ms, "converged": code == 0,
+                    "rel_resid": st.rel_resid}
+            res["none"] = base
+            log(f"precond study {wl}: no preconditioner {st.iters} iterations")
+            for B in blocks:
+                ps = S.precond_setup(B)
+                x, st, code = S.solve(b, tol=PRECOND_TOL, maxit=maxit)
+                nb = (n2 + B - 1) // B
+                res[f"B{B}"] = {"blocks": nb, "mbytes": nb * (2 * B) ** 2 * 16 / 1e6,
+                                "t_setup_ms": ps.t_setup_ms, "iters": st.iters,
+                                "t_solve_ms": st.t_solve_ms, "converged": code == 0,
+                                "rel_resid": st.rel_resid,
+                                "iter_reduction": base["iters"] / max(1, st.iters),
+                                "solve_speedup": base["t_solve_ms"] / max(1e-9, st.t_solve_ms)}
+                log(f"precond study {wl}: B = {B}, {st.iters} iterations")
+            out[wl] = res
+        finally:
+            S.close()
+    return out
+
+
+def spectrum_study(mbem, log):
+    """The LSPR spectrum of the silver spheroid in one sweep call per
+    precision (the first point includes the one geometry build)."""
+    from workloads import spectrum_workload
+    xyz, tri, lam, k0, eps, kh, po, c = spectrum_workload("spheroid_lspr")
+    out = {"workload": "spheroid_lspr", "n_tris": int(tri.shape[0]), "n_nodes": int(xyz.shape[0]),
+           "unknowns": 4 * int(xyz.shape[0]), "points": int(lam.shape[0]),
+           "lambda_nm": [float(lam[0]), float(lam[-1])], "mbj_block": c["mbj_block"],
+           "tol": c["tol"]}
+    sig = {}
+    npts = lam.shape[0]
+    for name, prec in (("fp64", mbem.MBEM_FP64), ("mixed", mbem.MBEM_MIXED)):
+        S = mbem.Solver(xyz, tri, 1.0, 1.0, precision=prec)
+        try:
+            t0 = time.perf_counter()
+            # mixed: one inner GMRES to the sweep's tolerance, then the FP64
+            # residual check
+            sg, it, st = S.spectrum(k0, eps, kh, po, block=c["mbj_block"], tol=c["tol"],
+                                    maxit=800, inner_tol=c["tol"])
+            wall = time.perf_counter() - t0
+            flops = regular_fill_flops(S, tri, st.n_regular_pairs)
+        finally:
+            S.close()
+        sig[name] = sg
+        i = int(np.argmax(sg[:, 0]))
+        t_reg = st.t_regular_ms / npts
+        gemv_ms = st.t_matvec_ms / max(1, st.n_matvec)
+        n2 = 2 * xyz.shape[0]
+        gemv_bytes = 3 * n2 * n2 * (16 if name == "fp64" else 8) + 4 * n2 * 16
+        peak = PEAK_FP64_VALU
+        out[name] = {"wall_s": wall, "points_per_s": npts / wall,
+                     # FP64: every regular pair in FP64; mixed: the FP32 kernel, which
+                     # evaluates its near pairs in FP64 (on this electrically small,
+                     # high-contrast body most pairs are near)
+                     "k_regular": ({"ms_per_point": t_reg, "tflops": flops / (t_reg * 1e-3) / 1e12,
+                                    "peak": peak, "frac": flops / (t_reg * 1e-3) / 1e12 / peak}
+                                   if name == "fp64" else
+                                   {"ms_per_point": t_reg,
+                                    "near_pair_fraction": st.n_near_pairs / npts / max(1, st.n_regular_pairs)}),
+                     "k_gemv3": {"ms_per_launch": gemv_ms,
+                                 "gbps": gemv_bytes / (gemv_ms * 1e-3) / 1e9,
+                                 "frac": gemv_bytes / (gemv_ms * 1e-3) / 1e9 / PEAK_HBM},
+                     "t_fill_ms": st.t_fill_ms, "t_setup_ms": st.t_setup_ms,
+                     "t_solve_ms": st.t_solve_ms, "t_matvec_ms": st.t_matvec_ms,
+                     "iters_total": int(st.iters), "iters_max": int(it.max()),
+                     "worst_rel_resid": st.rel_resid,
+                     "peak_lambda_nm": float(lam[i]), "peak_c_ext_nm2": float(sg[i, 0]),
+                     "energy_balance_max": float(np.abs((sg[:, 1] + sg[:, 2]) / sg[:, 0] - 1).max())}
+        log(f"spectrum study {name}: {lam.shape[0]} points in {wall:.2f} s, peak "
+            f"{sg[i, 0]:.0f} nm^2 at {lam[i]:.0f} nm")
+    out["mixed_vs_fp64_max_rel"] = float(np.abs(sig["mixed"] / sig["fp64"] - 1).max())
+    return out
+
+
+BLR_STUDY = dict(n_tris=20480, k0=5.0, eps_r=2.25,
+                 opts=dict(cluster=512, eta=2.0, eps=1e-6, rmax=128), block=100, tol=1e-8)
+
+
+def blr_study(mbem, icosphere_p2, log):
+    """Block low-rank operator beyond dense memory (see the module docstring);
+    its accuracy against the Mie series is checked by the GPU tests, here the
+    energy balance C_ext = C_sca + C_abs (a lossless sphere) is reported."""
+    c = BLR_STUDY
+    xyz, tri = icosphere_p2(c["n_tris"])
+    S = mbem.Solver(xyz, tri, c["k0"], c["eps_r"])
+    try:
+        bs = S.fill_compressed(**c["opts"])
+        ps = S.precond_setup(c["block"])
+        kh, po = np.array([0, 0, 1.0]), np.array([1.0, 0, 0], dtype=np.complex128)
+        x, st, code = S.solve(S.rhs(kh, po), c["tol"], maxit=800)
+        cs = S.cross_sections(x[0], kh, po)
+        mv = st.t_matvec_ms / max(1, st.n_matvec)
+        # bytes of one product: every stored tile once, x twice per block, t out
+        mv_bytes = bs.stored_bytes + 4 * S.N * 16
+        out = {"workload": f"sphere{c['n_tris']}", "unknowns": S.N, "k0": c["k0"], "eps_r": c["eps_r"],
+               "options": c["opts"], "t_fill_ms": bs.t_total_ms, "t_band_fill_ms": bs.t_fill_ms,
+               "t_aca_ms": bs.t_aca_ms, "stored_gb": bs.stored_bytes / 1e9,
+               "dense_gb": bs.dense_bytes / 1e9, "stored_fraction": bs.stored_bytes / bs.dense_bytes,
+               "clusters": bs.n_clusters, "lowrank_tiles": bs.n_lowrank, "tiles": bs.n_tiles,
+               "mean_rank": bs.mean_rank, "max_rank": bs.max_rank,
+               "matvec_ms": mv, "matvec_gbps": mv_bytes / (mv * 1e-3) / 1e9,
+               "matvec_hbm_frac": mv_bytes / (mv * 1e-3) / 1e9 / PEAK_HBM,
+               "t_setup_ms": ps.t_setup_ms if ps is not None else None,
+               "gmres_iters": st.iters, "t_solve_ms": st.t_solve_ms, "converged": code == 0,
+               "c_ext": cs[0], "c_sca": cs[1], "c_abs": cs[2]}
+        out["energy_balance"] = (cs[1] + cs[2]) / cs[0] - 1
+        log(f"compressed study: {S.N} unknowns, {bs.stored_bytes / 1e9:.1f} of {bs.dense_bytes / 1e9:.1f} GB, "
+            f"fill {bs.t_total_ms:.0f} ms, product {mv:.2f} ms, {st.iters} iterations")
+        return out
+    finally:
+        S.close()
+
+
+def frame_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3, refinement=True):
+    """The interpolated frame (the paper's construction, the default) against
+    node-attached tangents on the 1280-triangle sphere, FP64 and mixed: fill
+    times, GMRES iterations to 1e-8, the energy balance
+    |C_ext - C_sca - C_abs| / C_ext of each solution (the sphere is lossless,
+    so the gap is discretisation error), and the far-field difference of the
+    two bases."""
+    c = get_config("sphere1280")
+    xyz, tri = icosphere_p2(c["n_tris"], c["axes"])
+    kh, po = planewaves("sphere1280")
+    out = {"workload": "sphere1280", "unknowns": None}
+    F = {}
+    for name, prec, frame in (("interpolated_fp64", mbem.MBEM_FP64, mbem.MBEM_FRAME_INTERPOLATED),
+                              ("nodal_fp64", mbem.MBEM_FP64, mbem.MBEM_FRAME_NODAL),
+                              ("interpolated_mixed", mbem.MBEM_MIXED, mbem.MBEM_FRAME_INTERPOLATED),
+                              ("nodal_mixed", mbem.MBEM_MIXED, mbem.MBEM_FRAME_NODAL)):
+        S = mbem.Solver(xyz, tri, c["k0"], c["eps_r"], c["mu_r"], precision=prec, frame=frame)
+        try:
+            fs = [S.fill() for _ in range(reps + 1)][1:]
+            S.precond_setup(c["mbj_block"])
+            x, st, code = S.solve(S.rhs(kh, po), tol=c["tol"], maxit=600, inner_tol=1e-4)
+            F[name] = S.farfield(x, rdirs).cpu().numpy()[0]
+            cs = S.cross_sections(x[0], kh[0], po[0])
+            out["unknowns"] = S.N
+            out[name] = {"t_fill_ms": float(np.mean([f.t_fill_ms for f in fs])),
+                         "t_regular_ms": float(np.mean([f.t_regular_ms for f in fs])),
+                         "t_singular_ms": float(np.mean([f.t_ssq_ms for f in fs])),
+                         "iters": st.iters, "converged": code == 0,
+                         "c_ext": float(cs[0]),
+                         "energy_balance": float(abs(cs[0] - cs[1] - cs[2]) / cs[0])}
+            log(f"frame study: {name} fill {out[name]['t_fill_ms']:.2f} ms, "
+                f"energy balance {out[name]['energy_balance']:.2e}")
+        finally:
+            S.close()
+    rel = lambda a, b: float(np.linalg.norm(F[a] - F[b]) / np.linalg.norm(F[b]))
+    out["farfield_nodal_vs_interpolated_fp64"] = rel("nodal_fp64", "interpolated_fp64")
+    out["farfield_nodal_mixed_vs_nodal_fp64"] = rel("nodal_mixed", "nodal_fp64")
+    out["spheroid_refinement"] = frame_refinement(mbem, get_config, icosphere_p2, log) if refinement else None
+    return out
+
+
+def frame_refinement(mbem, get_config, icosphere_p2, log):
+    """Both bases under refinement on the plasmonic spheroid of the
+    spheroid5120 workload (semi-axes 1, 1, 2, eps_r = -10 + 1i, k_a = 4),
+    oblique incidence (45 degrees to the axis), 320 / 1280 / 5120 triangles,
+    FP64, GMRES to 1e-10: C_ext, C_abs and the energy balance per mesh.
+    There is no closed form for a spheroid; the change of C_ext between
+    consecutive meshes measures the convergence."""
+    c = get_config("spheroid5120")
+    kh = np.array([np.sqrt(0.5), 0.0, np.sqrt(0.5)])
+    po = np.array([np.sqrt(0.5), 0.0, -np.sqrt(0.5)], dtype=np.complex128)
+    out = {}
+    for name, frame in (("interpolated", mbem.MBEM_FRAME_INTERPOLATED), ("nodal", mbem.MBEM_FRAME_NODAL)):
+        rows = []
+        for nt in (320, 1280, 5120):
+            xyz, tri = icosphere_p2(nt, c["axes"])
+            S = mbem.Solver(xyz, tri, c["k0"], c["eps_r"], c["mu_r"], frame=frame)
+            try:
+                S.fill()
+                S.precond_setup(c["mbj_block"])
+                x, st, code = S.solve(S.rhs(kh[None], po[None]), tol=1e-10, maxit=800)
+                cs = S.cross_sections(x[0], kh, po)
+                rows.append({"n_tris": nt, "c_ext": float(cs[0]), "c_sca": float(cs[1]), "c_abs": float(cs[2]),
+                             "energy_balance": float(abs(cs[0] - cs[1] - cs[2]) / cs[0]), "iters": st.iters,
+                             "converged": code == 0})
+            finally:
+                S.close()
+            log(f"frame refinement: {name} {nt} C_ext {rows[-1]['c_ext']:.6f} "
+                f"balance {rows[-1]['energy_balance']:.1e}")
+        out[name] = rows
+    return out
+
+
+def quad_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3):
+    """The paper's own quadrature (12-point rule, Sauter-Schwab on the
+    singular kernels, 12-point remainder) against the default on the
+    1280-triangle sphere: fill times and the far-field difference of the two
+    (FP64 and mixed), GMRES to 1e-8."""
+    c = get_config("sphere1280")
+    xyz, tri = icosphere_p2(c["n_tris"], c["axes"])
+    kh, po = planewaves("sphere1280")
+    out = {"workload": "sphere1280", "unknowns": None}
+    F = {}
+    for name, prec, quad in (("default_fp64", mbem.MBEM_FP64, mbem.MBEM_QUAD_DEFAULT),
+                             ("paper_fp64", mbem.MBEM_FP64, mbem.MBEM_QUAD_PAPER),
+                             ("default_mixed", mbem.MBEM_MIXED, mbem.MBEM_QUAD_DEFAULT),
+                             ("paper_mixed", mbem.MBEM_MIXED, mbem.MBEM_QUAD_PAPER)):
+        S = mbem.Solver(xyz, tri, c["k0"], c["eps_r"], c["mu_r"], precision=prec, quadrature=quad)
+        try:
+            fs = [S.fill() for _ in range(reps + 1)][1:]
+            S.precond_setup(c["mbj_block"])
+            x, st, code = S.solve(S.rhs(kh, po), tol=c["tol"], maxit=600, inner_tol=1e-4)
+            F[name] = S.farfield(x, rdirs).cpu().numpy()[0]
+            out["unknowns"] = S.N
+            out[name] = {"t_fill_ms": float(np.mean([f.t_fill_ms for f in fs])),
+                         "t_regular_ms": float(np.mean([f.t_regular_ms for f in fs])),
+                         "t_singular_ms": float(np.mean([f.t_ssq_ms for f in fs])),
+                         "fill_rate": S.N ** 2 / (1e-3 * float(np.mean([f.t_fill_ms for f in fs]))),
+                         "iters": st.iters, "converged": code == 0}
+            log(f"quadrature study: {name} fill {out[name]['t_fill_ms']:.2f} ms")
+        finally:
+            S.close()
+    rel = lambda a, b: float(np.linalg.norm(F[a] - F[b]) / np.linalg.norm(F[b]))
+    out["farfield_paper_vs_default_fp64"] = rel("paper_fp64", "default_fp64")
+    out["farfield_paper_mixed_vs_paper_fp64"] = rel("paper_mixed", "paper_fp64")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
