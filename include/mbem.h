@@ -239,6 +239,19 @@ int mbem_op_export_dense(mbem_ctx *ctx, const mbem_op *op, mbem_c128 *Z);
 int mbem_matvec(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *x,
                 int32_t nrhs, mbem_c128 *y);
 
+/* y = Z x like mbem_matvec, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no allocation or release of any kind and no host wait -- the
+ * products are enqueued on the context's stream and the call returns; the
+ * caller synchronises before reading y.  The partial sums live in a 4 MiB
+ * array in device memory that the library holds on every device it runs
+ * on until the process ends, so op must have 2 n_nodes <= 65536 (MBEM_EINVAL
+ * otherwise, nothing enqueued).  Every call on one device uses that
+ * device's one array: calls that overlap on a device (other streams,
+ * other threads) race and must be serialised by the caller.               */
+int mbem_matvec_noalloc(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *x,
+                        int32_t nrhs, mbem_c128 *y);
+
 /* ---- preconditioner (Sec. 5, eq. precond_block) --------------------------- */
 
 /* Morton block-Jacobi: clusters of `block` consecutive indices of one

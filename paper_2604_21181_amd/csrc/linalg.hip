@@ -7,6 +7,7 @@
 //   y_j  = (i/w) K1 x_j + K2^eps x_m + c_eps (M (x) I2) x_m
 //   y_m  = K2^mu x_j + c_mu (M (x) I2) x_j - (i/w) K1 x_m
 // so every dense entry is read once per product; K1 feeds two dot products.
+#include <mutex>
 #include <type_traits>
 
 #include "mbem_internal.h"
@@ -831,3 +832,59 @@ int vec_axpy(double2 *y, const double2 *x, double2 a, int64_t n, hipStream_t s) 
 }
 
 }  // namespace mbem
+
+// ------------------------------------------------ allocation-free product --
+// mbem_matvec_noalloc: the product of mbem_matvec with its partial sums
+// (4 n2 complex values: K1 x_j, K1 x_m, K2e x_m, K2m x_j) in a file-scope
+// device array instead of a per-call allocation.  Each device holds its own
+// copy of the array; its address is looked up once per device, with that
+// device current, and the kernels receive that address (the array's name in
+// host code is not a device address).
+namespace mbem {
+constexpr int64_t kScratchN2 = 65536;                 // largest n2 = 2 n_nodes (4 MiB)
+static __device__ __align__(256) double2 scratch[4 * kScratchN2];
+namespace {
+constexpr int kScratchDevices = 64;
+void *g_scratch[kScratchDevices] = {};
+std::mutex g_scratch_mu;
+
+int scratch_of(int device, double2 **out) {
+    if (device < 0 || device >= kScratchDevices) {
+        set_error("device ordinal beyond the library's scratch table");
+        return MBEM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("scratch address: ") + hipGetErrorString(e));
+            return MBEM_EDEVICE;
+        }
+        g_scratch[device] = p;
+    }
+    *out = (double2 *)g_scratch[device];
+    return MBEM_OK;
+}
+}  // namespace
+
+}  // namespace mbem
+
+extern "C" int mbem_matvec_noalloc(mbem_ctx *ctx, const mbem_op *op, const mbem_c128 *x, int32_t nrhs,
+                                   mbem_c128 *y) {
+    using namespace mbem;
+    if (!ctx || !op || !x || !y || nrhs < 1) { set_error("bad argument"); return MBEM_EINVAL; }
+    if (op->n2 > kScratchN2) {
+        set_error("mbem_matvec_noalloc: 2 n_nodes = " + std::to_string(op->n2) + " exceeds its scratch limit of " +
+                  std::to_string(kScratchN2));
+        return MBEM_EINVAL;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) { set_error("hipSetDevice failed"); return MBEM_EDEVICE; }
+    double2 *tmp = nullptr;
+    MBEM_TRY(scratch_of(ctx->device, &tmp));
+    const int64_t N = 2 * op->n2;
+    for (int r = 0; r < nrhs; ++r)
+        MBEM_TRY(matvec_run(op, (const double2 *)x + r * N, (double2 *)y + r * N, tmp, ctx->stream));
+    return MBEM_OK;
+}
+

@@ -30,7 +30,7 @@ EXPORTED = [
     "mbem_farfield", "mbem_cross_sections", "mbem_last_error", "mbem_solve_block",
     "mbem_gemm_autotune", "mbem_cgemm", "mbem_solve_adjoint", "mbem_fill_deps",
     "mbem_farfield_functional", "mbem_grad_sigma_ext", "mbem_mesh_frames", "mbem_spectrum",
-    "mbem_fill_compressed",
+    "mbem_fill_compressed", "mbem_matvec_noalloc",
 ]
 GEMM_CONFIGS = 6   # FP32 GEMM tile shapes known to the autotuner
 
@@ -121,6 +121,7 @@ def lib():
             "mbem_op_export_blocks": ([P, P, P, P, P], C.c_int),
             "mbem_op_export_dense": ([P, P, P], C.c_int),
             "mbem_matvec": ([P, P, P, i32, P], C.c_int),
+            "mbem_matvec_noalloc": ([P, P, P, i32, P], C.c_int),
             "mbem_precond_setup": ([P, P, i32, C.POINTER(Stats)], C.c_int),
             "mbem_precond_apply": ([P, P, P, P], C.c_int),
             "mbem_rhs_planewave": ([P, P, C.POINTER(Params), P, P, i32, P], C.c_int),
@@ -274,6 +275,11 @@ def mbem_op_export_dense(ctx, op, Z):
 
 def mbem_matvec(ctx, op, x, y, nrhs=1):
     _check(lib().mbem_matvec(ctx, op, _t_ptr(x), nrhs, _t_ptr(y)))
+
+
+def mbem_matvec_noalloc(ctx, op, x, y, nrhs=1):
+    """Enqueue y = Z x without any allocation (the caller synchronises)."""
+    _check(lib().mbem_matvec_noalloc(ctx, op, _t_ptr(x), nrhs, _t_ptr(y)))
 
 
 def mbem_precond_setup(ctx, op, block):
