@@ -9,13 +9,16 @@
 //   W    = Z Zt                          (complex FP32 GEMM on MFMA for the
 //                                         dense blocks, mass in FP64, W FP64)
 //   H    = V^H W, W -= V H  (twice)      (block classical Gram-Schmidt, FP64
-//                                         MFMA for V^H W)
+//                                         MFMA for both products: V^H W from
+//                                         V, V H from a transposed copy of the
+//                                         basis kept beside it)
 //   W    = V_{k+1} R                     (Cholesky QR, twice; shifted when the
 //                                         Gram matrix is not numerically SPD)
 //   Householder QR of the new block column of the block Hessenberg matrix,
 //   applied to the least-squares right-hand side: its trailing p rows give
 //   the residual norm of every column.
-// After the sweep: Y = R^-1 g, X += P^-1 V Y; the refinement residual
+// After the sweep: Y = R^-1 g (blocked back substitution, one workgroup
+// per column), X += P^-1 V Y; the refinement residual
 // B - Z X is formed with the FP64 MFMA GEMM from the stored operator.
 #include <algorithm>
 #include <cmath>
@@ -277,7 +280,24 @@ __global__ __launch_bounds__(256) void k_nn_update(int64_t N, int ka, int p, con
         }
         __syncthreads();
         if (n < N) {
-            for (int a = 0; a < na; ++a) {
+            // eight basis entries in flight per step: the loop is otherwise
+            // bound by the latency of one load per iteration
+            int a = 0;
+            for (; a + 8 <= na; a += 8) {
+                double2 v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = V[(int64_t)(a0 + a + q) * ldv + n];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+#pragma unroll
+                    for (int u = 0; u < kCG; ++u) {
+                        const int c = grp * kCG + u;
+                        const double2 y = sY[a + q][c < p ? c : 0];
+                        re[u] += v[q].x * y.x - v[q].y * y.y;
+                        im[u] += v[q].x * y.y + v[q].y * y.x;
+                    }
+            }
+            for (; a < na; ++a) {
                 const double2 v = V[(int64_t)(a0 + a) * ldv + n];
 #pragma unroll
                 for (int u = 0; u < kCG; ++u) {
@@ -323,10 +343,9 @@ static int nn_update(int64_t N, int ka, int p, int nblk, const double2 *V, int64
 __global__ __launch_bounds__(256) void k_cholqr_small(int p, int64_t Nrows, const double2 *G, int scale,
                                                       const double2 *Rprev, double2 *Y, double2 *Rout,
                                                       int64_t ldr, int64_t sr, int *flags) {
-    __shared__ double2 sG[kMaxP][kMaxP + 1];   // sG[a][c]
+    __shared__ double2 sG[kMaxP][kMaxP + 1];   // sG[a][c]; after the factorisation R^-1, then Rprev
+    __shared__ double2 sA[kMaxP][kMaxP + 1];   // trailing matrix of the factorisation
     __shared__ double2 sR[kMaxP][kMaxP + 1];   // sR[i][c], upper
-    __shared__ double2 sX[kMaxP][kMaxP + 1];   // R^-1, or Rprev
-    __shared__ double2 sV[kMaxP];
     __shared__ double sD[kMaxP];
     __shared__ double s_fro;
     __shared__ int s_bad;
@@ -350,30 +369,37 @@ __global__ __launch_bounds__(256) void k_cholqr_small(int p, int64_t Nrows, cons
         if (tid == 0) s_fro = sqrt(f);
     }
     __syncthreads();
+    // right-looking factorisation: row j of R from the pivot row of the
+    // trailing matrix, then the rank-one update of the rows below it (all
+    // threads, two barriers per row)
     double shift = 0.0;
     for (int attempt = 0; attempt < 3; ++attempt) {
         if (tid == 0) s_bad = 0;
-        for (int t = tid; t < p * p; t += nt) sR[t % p][t / p] = {0.0, 0.0};
+        for (int t = tid; t < p * p; t += nt) {
+            const int a = t % p, c = t / p;
+            double2 v = sG[a][c];
+            if (a == c) v.x += shift;
+            sA[a][c] = v;
+            sR[a][c] = {0.0, 0.0};
+        }
         __syncthreads();
         for (int j = 0; j < p; ++j) {
-            // row j of R: v_c = G[j][c] - sum_{i<j} conj(R[i][j]) R[i][c], c >= j
-            const int c = tid;
-            double2 v = {0, 0};
-            if (c < p && c >= j) {
-                v = sG[j][c];
-                if (c == j) v.x += shift;
-                for (int i = 0; i < j; ++i) {
-                    const double2 t = zcmul(sR[i][j], sR[i][c]);
-                    v.x -= t.x; v.y -= t.y;
-                }
-                sV[c] = v;
+            if (tid >= j && tid < p) {
+                double d = sA[j][j].x;
+                if (!(d > 0.0)) { d = 1.0; if (tid == j) s_bad = 1; }
+                d = sqrt(d);
+                const double2 v = sA[j][tid];
+                sR[j][tid] = tid == j ? double2{d, 0.0} : double2{v.x / d, v.y / d};
             }
             __syncthreads();
-            if (c < p && c >= j) {
-                double d = sV[j].x;
-                if (!(d > 0.0)) { d = 1.0; if (c == j) s_bad = 1; }
-                d = sqrt(d);
-                sR[j][c] = c == j ? double2{d, 0.0} : double2{v.x / d, v.y / d};
+            const int m = p - 1 - j;
+            for (int t = tid; t < m * m; t += nt) {
+                const int a = j + 1 + t / m, c = j + 1 + t % m;
+                if (a <= c) {
+                    const double2 u = zcmul(sR[j][a], sR[j][c]);
+                    sA[a][c].x -= u.x;
+                    sA[a][c].y -= u.y;
+                }
             }
             __syncthreads();
         }
@@ -382,33 +408,41 @@ __global__ __launch_bounds__(256) void k_cholqr_small(int p, int64_t Nrows, cons
         if (tid == 0 && flags) atomicOr(flags, 1);
         __syncthreads();
     }
-    // R^-1 by columns (thread c solves R x = e_c), then Y = D^-1 R^-1
-    if (tid < p) {
-        const int c = tid;
-        for (int i = p - 1; i >= 0; --i) {
-            double2 t = {i == c ? 1.0 : 0.0, 0.0};
-            if (i <= c)
-                for (int j = i + 1; j <= c; ++j) { const double2 u = zmul(sR[i][j], sX[j][c]); t.x -= u.x; t.y -= u.y; }
-            sX[i][c] = i <= c ? double2{t.x / sR[i][i].x, t.y / sR[i][i].x} : double2{0.0, 0.0};
-        }
-    }
+    // X = R^-1 by rows from the bottom: X[i][c] = T[i][c] / R[i][i] for
+    // c >= i, then T[i'][c] -= R[i'][i] X[i][c] for the rows i' above
+    for (int t = tid; t < p * p; t += nt) sG[t % p][t / p] = {t % p == t / p ? 1.0 : 0.0, 0.0};
     __syncthreads();
+    for (int i = p - 1; i >= 0; --i) {
+        if (tid >= i && tid < p) {
+            const double d = sR[i][i].x;
+            sG[i][tid] = {sG[i][tid].x / d, sG[i][tid].y / d};
+        }
+        __syncthreads();
+        for (int t = tid; t < i * (p - i); t += nt) {
+            const int r = t % i, c = i + t / i;
+            const double2 u = zmul(sR[r][i], sG[i][c]);
+            sG[r][c].x -= u.x;
+            sG[r][c].y -= u.y;
+        }
+        __syncthreads();
+    }
     double2 *y = Y + (int64_t)blk * p * p;
     for (int t = tid; t < p * p; t += nt) {
         const int i = t % p, c = t / p;
         const double d = sD[i] > 0 ? sD[i] : 1.0;
-        y[t] = {sX[i][c].x / d, sX[i][c].y / d};
+        y[t] = {sG[i][c].x / d, sG[i][c].y / d};
     }
     __syncthreads();
     double2 *ro = Rout + (int64_t)blk * sr;
     if (Rprev) {
         const double2 *rp = Rprev + (int64_t)blk * p * p;
-        for (int t = tid; t < p * p; t += nt) sX[t % p][t / p] = rp[t];
+        for (int t = tid; t < p * p; t += nt) sG[t % p][t / p] = rp[t];
         __syncthreads();
         for (int t = tid; t < p * p; t += nt) {
             const int i = t % p, c = t / p;
             double2 acc = {0, 0};
-            for (int j = i; j <= c; ++j) { const double2 u = zmul(sR[i][j], sX[j][c]); acc.x += u.x; acc.y += u.y; }
+#pragma unroll 4
+            for (int j = i; j <= c; ++j) { const double2 u = zmul(sR[i][j], sG[j][c]); acc.x += u.x; acc.y += u.y; }
             ro[(int64_t)c * ldr + i] = acc;
         }
     } else {
@@ -593,29 +627,57 @@ __global__ __launch_bounds__(256) void k_bqr_factor(int p, int k, double2 *Hcol,
 }
 
 // Back substitution R Y = g (n x n upper triangular, column-major ldh; g
-// column-major ldg), Y overwrites g.  One workgroup per block.
+// column-major ldg, n a multiple of p), Y overwrites g.  The columns are
+// independent systems with the same R: one workgroup per (block, column),
+// blocked by p x p diagonal blocks from the bottom.  Per diagonal block:
+// the block is staged in LDS, one wavefront solves it (lane r holds row r,
+// the solution entries broadcast by shuffles), then the whole workgroup
+// subtracts R[0 : I p, block I] y_I from the rows above, which are read
+// coalesced down the columns of R.
 __global__ __launch_bounds__(256) void k_bqr_solve(int p, int n, const double2 *H, int64_t ldh, int64_t sh,
                                                    double2 *g, int64_t ldg, int64_t sg) {
+    __shared__ double2 sd[kMaxP][kMaxP + 1];   // sd[c][r] = R(r0 + r, r0 + c)
     __shared__ double2 sy[kMaxP];
-    const int blk = blockIdx.x, tid = threadIdx.x;
+    const int blk = blockIdx.x / p, col = blockIdx.x % p, tid = threadIdx.x;
     H += blk * sh;
-    g += blk * sg;
-    for (int i = n - 1; i >= 0; --i) {
-        if (tid < p) {
-            const double2 d = H[(int64_t)i * ldh + i], v = g[(int64_t)tid * ldg + i];
-            const double dd = d.x * d.x + d.y * d.y;
-            const double2 y = {(v.x * d.x + v.y * d.y) / dd, (v.y * d.x - v.x * d.y) / dd};
-            sy[tid] = y;
-            g[(int64_t)tid * ldg + i] = y;
+    double2 *gc = g + blk * sg + (int64_t)col * ldg;
+    for (int I = n / p - 1; I >= 0; --I) {
+        const int r0 = I * p;
+        for (int t = tid; t < p * p; t += blockDim.x) {
+            const int r = t % p, c = t / p;
+            sd[c][r] = H[(int64_t)(r0 + c) * ldh + r0 + r];
         }
         __syncthreads();
-        const double2 *hc = H + (int64_t)i * ldh;
-        for (int t = tid; t < i * p; t += blockDim.x) {
-            const int r = t % i, c = t / i;
-            const double2 u = zmul(hc[r], sy[c]);
-            double2 *gp = g + (int64_t)c * ldg + r;
-            gp->x -= u.x;
-            gp->y -= u.y;
+        if (tid < kWv) {
+            const int r = tid;
+            double2 acc = r < p ? gc[r0 + r] : double2{0, 0};
+            for (int i = p - 1; i >= 0; --i) {
+                const double2 v = {__shfl(acc.x, i, kWv), __shfl(acc.y, i, kWv)};
+                const double2 d = sd[i][i];
+                const double dd = d.x * d.x + d.y * d.y;
+                const double2 y = {(v.x * d.x + v.y * d.y) / dd, (v.y * d.x - v.x * d.y) / dd};
+                if (r == i) acc = y;
+                else if (r < i) {
+                    const double2 u = zmul(sd[i][r], y);
+                    acc.x -= u.x;
+                    acc.y -= u.y;
+                }
+            }
+            if (r < p) {
+                sy[r] = acc;
+                gc[r0 + r] = acc;
+            }
+        }
+        __syncthreads();
+        for (int r = tid; r < r0; r += blockDim.x) {
+            double2 a = gc[r];
+            const double2 *hc = H + (int64_t)r0 * ldh + r;
+            for (int j = 0; j < p; ++j) {
+                const double2 u = zmul(hc[(int64_t)j * ldh], sy[j]);
+                a.x -= u.x;
+                a.y -= u.y;
+            }
+            gc[r] = a;
         }
         __syncthreads();
     }
@@ -653,12 +715,34 @@ __global__ void k_c128_to_c64(const double2 *a, float2 *b, int64_t n) {
     if (i < n) b[i] = {(float)a[i].x, (float)a[i].y};
 }
 
+// VT[b][n][k p + c] = V[b][k][c][n] for the p columns of basis block k of
+// every block b, through an LDS tile (64 rows of V in, 64 rows of VT out).
+__global__ __launch_bounds__(256) void k_basis_t(int64_t N, int p, const double2 *V, int64_t sv, double2 *VT,
+                                                 int64_t ldt, int64_t svt, int col0) {
+    __shared__ double2 t[kMaxP][kWv + 1];
+    const int b = blockIdx.y, tid = threadIdx.x;
+    const int64_t n0 = (int64_t)blockIdx.x * kWv;
+    V += b * sv;
+    VT += b * svt;
+    for (int c = tid / kWv; c < p; c += blockDim.x / kWv) {
+        const int64_t n = n0 + tid % kWv;
+        t[c][tid % kWv] = n < N ? V[(int64_t)c * N + n] : double2{0, 0};
+    }
+    __syncthreads();
+    for (int e = tid; e < kWv * p; e += blockDim.x) {
+        const int nl = e / p, c = e % p;
+        const int64_t n = n0 + nl;
+        if (n < N) VT[n * ldt + col0 + c] = t[c][nl];
+    }
+}
+
 // ------------------------------------------------------------ driver ---
 namespace {
 struct BlockWork {
     int64_t N = 0, n2 = 0;
     int ncol = 0, p = 0, nblk = 0, m = 0;
     double2 *V = nullptr;      // [nblk][m+1][p][N]
+    double2 *VT = nullptr;     // [nblk][N][(m+1) p]: the basis transposed
     float2 *Zt = nullptr;      // [ncol][N]
     float2 *T32 = nullptr;     // [4 ncol][n2]
     double2 *T64 = nullptr;    // [4 ncol][n2]
@@ -686,6 +770,7 @@ struct BlockWork {
     int64_t ldh() const { return (int64_t)(m + 1) * p; }
     int64_t sV() const { return (int64_t)(m + 1) * p * N; }
     ColMap vcol(int k) const { return ColMap{V + (int64_t)k * p * N, p, sV(), N}; }
+    int64_t sVT() const { return N * ldh(); }
 };
 
 ColMap flat(void *base, int64_t ld) { return ColMap{base, 1 << 30, 0, ld}; }
@@ -721,6 +806,30 @@ static int block_project(BlockWork &w, const double2 *Vb, int64_t sVb, int ka, C
     const int splits = proj_splits(ka, w.p, w.nblk, w.N);
     if (cgemm_f64_work(L, splits) > w.split_elems) { set_error("split workspace too small"); return MBEM_EINVAL; }
     return cgemm_f64_run(L, false, true, splits, w.split, s);
+}
+
+// Basis block k of every block into the transposed copy.
+static int basis_t(BlockWork &w, int k, hipStream_t s) {
+    const dim3 g((unsigned)((w.N + kWv - 1) / kWv), (unsigned)w.nblk);
+    hipLaunchKernelGGL(k_basis_t, g, dim3(256), 0, s, w.N, w.p, (const double2 *)(w.V + (int64_t)k * w.p * w.N),
+                       w.sV(), w.VT, w.ldh(), w.sVT(), k * w.p);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+// out[c][n] (+)= alpha sum_a V[a][n] Y[c * ldy + a] over the first ka basis
+// vectors of every block, on the matrix cores from the transposed basis
+// (both operands contiguous along a).
+static int basis_update(BlockWork &w, int ka, const double2 *Y, int64_t ldy, int64_t sy, double2 *out,
+                        int64_t ldo, int64_t so, double alpha, bool accumulate, hipStream_t s) {
+    CgemmList L;
+    L.np = 1;
+    CgemmProb &P = L.p[0];
+    P.A = w.VT; P.lda = w.ldh(); P.sa = w.sVT();
+    P.B = Y; P.ldb = ldy; P.sb = sy;
+    P.C = out; P.ldc = ldo; P.sc = so;
+    P.M = w.N; P.Nb = w.p; P.K = ka; P.batch = w.nblk;
+    return cgemm_f64_run(L, false, false, 1, nullptr, s, accumulate, alpha);
 }
 
 // Cholesky QR (twice) of the p columns of every block in `W` into `out`;
@@ -830,6 +939,7 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
     const int64_t N = w.N, n2 = w.n2, ldh = w.ldh();
     MBEM_TRY(ensure_c64_copy(op, s));
     MBEM_TRY(w.get(&w.V, (size_t)w.nblk * w.sV()));
+    MBEM_TRY(w.get(&w.VT, (size_t)w.nblk * w.sVT()));
     MBEM_TRY(w.get(&w.Zt, (size_t)ncol * N));
     MBEM_TRY(w.get(&w.T32, (size_t)4 * ncol * n2));
     MBEM_TRY(w.get(&w.T64, (size_t)4 * ncol * n2));
@@ -896,6 +1006,7 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
         MBEM_TRY(zero(w.g, (int64_t)w.nblk * ldh * p, s));
         const ColMap Rm{w.R, p, (int64_t)p * N, N};
         MBEM_TRY(block_cholqr2(w, Rm, w.vcol(0), true, w.g, ldh, ldh * p, s));
+        MBEM_TRY(basis_t(w, 0, s));
         int k = 0;
         for (k = 0; k < w.m; ++k) {
             // W = Z P^-1 V_k  into the slot of V_{k+1}
@@ -912,16 +1023,15 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
             const int ka = (k + 1) * p;
             double2 *hk = w.Hs + (int64_t)k * p * ldh;
             MBEM_TRY(block_project(w, w.V, w.sV(), ka, Wk, hk, ldh, ldh * w.m * p, s));
-            MBEM_TRY(nn_update(N, ka, p, w.nblk, w.V, N, w.sV(), hk, ldh, ldh * w.m * p, (double2 *)Wk.base, N,
-                               w.sV(), -1.0, 1.0, s));
+            MBEM_TRY(basis_update(w, ka, hk, ldh, ldh * w.m * p, (double2 *)Wk.base, N, w.sV(), -1.0, true, s));
             MBEM_TRY(block_project(w, w.V, w.sV(), ka, Wk, w.Ht, ldh, ldh * p, s));
-            MBEM_TRY(nn_update(N, ka, p, w.nblk, w.V, N, w.sV(), w.Ht, ldh, ldh * p, (double2 *)Wk.base, N,
-                               w.sV(), -1.0, 1.0, s));
+            MBEM_TRY(basis_update(w, ka, w.Ht, ldh, ldh * p, (double2 *)Wk.base, N, w.sV(), -1.0, true, s));
             hipLaunchKernelGGL(k_add_blocks, dim3((unsigned)(((int64_t)ka * p * w.nblk + 255) / 256)), dim3(256),
                                0, s, hk, ldh, ldh * w.m * p, (const double2 *)w.Ht, ldh, ldh * p, ka, p, w.nblk);
             MBEM_HIP(hipGetLastError());
             // W = V_{k+1} R  (R into rows (k+1)p .. (k+2)p of the block column)
             MBEM_TRY(block_cholqr2(w, Wk, Wk, false, hk + (int64_t)(k + 1) * p, ldh, ldh * w.m * p, s));
+            MBEM_TRY(basis_t(w, k + 1, s));
             if (k > 0) {
                 hipLaunchKernelGGL(k_bqr_prev, dim3(w.nblk, (p + 7) / 8), dim3(512), 0, s, p, k, hk, ldh,
                                    ldh * w.m * p, (const double2 *)w.refl, (const double2 *)w.tau,
@@ -947,11 +1057,10 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
         total_it += k;
         // X += P^-1 V Y,  Y = R^-1 g
         const int n = k * p;
-        hipLaunchKernelGGL(k_bqr_solve, dim3(w.nblk), dim3(256), 0, s, p, n, (const double2 *)w.Hs, ldh,
+        hipLaunchKernelGGL(k_bqr_solve, dim3(w.nblk * p), dim3(256), 0, s, p, n, (const double2 *)w.Hs, ldh,
                            ldh * w.m * p, w.g, ldh, ldh * p);
         MBEM_HIP(hipGetLastError());
-        MBEM_TRY(nn_update(N, n, p, w.nblk, w.V, N, w.sV(), w.g, ldh, ldh * p, w.Q, N, (int64_t)p * N, 1.0, 0.0,
-                           s));
+        MBEM_TRY(basis_update(w, n, w.g, ldh, ldh * p, w.Q, N, (int64_t)p * N, 1.0, false, s));
         MBEM_TRY(mbj_apply_multi_mfma(op, flat(w.Q, N), flat(X, N), ncol, false, true, w.Vg, w.Og, s));
         // refinement residual in FP64
         MBEM_TRY(block_residual(op, w, X, B, w.R, s));

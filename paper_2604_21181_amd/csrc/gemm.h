@@ -35,11 +35,11 @@ int cgemm_f32_run(CgemmList L, int cfg, hipStream_t s);
 void cgemm_f32_config(int cfg, int *bm, int *bn, int *wm, int *wn);
 int cgemm_f32_autotune(const CgemmList &L, hipStream_t s, int reps, float *ms_out, int *best);
 // A complex64 (a_c64) or complex128, B and C complex128; FP64 accumulation.
-// splits > 1 divides k among workgroups (one problem only) and sums the
-// partial products from `work` (cgemm_f64_work elements); with
-// `accumulate` the sum is added to C (also staged through `work`).
+// C = alpha op(A) B, or C += alpha op(A) B with `accumulate`.  splits > 1
+// divides k among workgroups (one problem only) and sums the partial
+// products from `work` (cgemm_f64_work elements).
 int cgemm_f64_run(CgemmList L, bool a_c64, bool conj_a, int splits, double2 *work, hipStream_t s,
-                  bool accumulate = false);
+                  bool accumulate = false, double alpha = 1.0);
 int64_t cgemm_f64_work(const CgemmList &L, int splits);
 
 }  // namespace mbem

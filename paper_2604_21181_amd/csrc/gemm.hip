@@ -191,7 +191,10 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_cgemm_f32(CgemmL
 // covers complex k in [y kchunk, (y + 1) kchunk) and writes its partial
 // product at C + y * split_stride.
 template <typename TA, typename TB, bool CONJ>
-__global__ __launch_bounds__(256) void k_cgemm_f64(CgemmList L, int64_t kchunk, int64_t split_stride) {
+// The product is scaled by alpha; with rmw it is added to what C holds
+// (one split only).
+__global__ __launch_bounds__(256) void k_cgemm_f64(CgemmList L, int64_t kchunk, int64_t split_stride, double alpha,
+                                                   int rmw) {
     constexpr int BM = 64, BN = 64, WM = 32, WN = 32, NT = 256;
     constexpr int LD = 18;   // 16 real k + pad, in doubles
     __shared__ __align__(16) double sA[2][BM * LD];
@@ -311,7 +314,15 @@ __global__ __launch_bounds__(256) void k_cgemm_f64(CgemmList L, int64_t kchunk, 
                 const double w = __shfl_xor(v, 1);
                 const int64_t m = m0 + wm * WM + i * 16 + g + 4 * e;
                 const int64_t n = n0 + wn * WN + j * 16 + l16;
-                if ((l16 & 1) == 0 && m < M && (n >> 1) < Nb) C[(n >> 1) * ldc + m] = double2{v, w};
+                if ((l16 & 1) == 0 && m < M && (n >> 1) < Nb) {
+                    double2 *c = C + (n >> 1) * ldc + m;
+                    if (rmw) {
+                        const double2 o = *c;
+                        *c = double2{o.x + alpha * v, o.y + alpha * w};
+                    } else {
+                        *c = double2{alpha * v, alpha * w};
+                    }
+                }
             }
 }
 
@@ -319,7 +330,7 @@ __global__ __launch_bounds__(256) void k_cgemm_f64(CgemmList L, int64_t kchunk, 
 // the output layout; ACC adds to what the output holds.
 template <bool ACC>
 __global__ void k_split_reduce(const double2 *part, int splits, int64_t M, int64_t Nb, int64_t batch,
-                               double2 *out, int64_t ldc, int64_t sc) {
+                               double2 *out, int64_t ldc, int64_t sc, double alpha) {
     const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t per = M * Nb, stride = per * batch;
     if (id >= stride) return;
@@ -327,8 +338,8 @@ __global__ void k_split_reduce(const double2 *part, int splits, int64_t M, int64
     double2 s = {0.0, 0.0};
     for (int y = 0; y < splits; ++y) { const double2 v = part[y * stride + id]; s.x += v.x; s.y += v.y; }
     double2 *o = out + bi * sc + b * ldc + m;
-    if (ACC) { o->x += s.x; o->y += s.y; }
-    else *o = s;
+    if (ACC) { o->x += alpha * s.x; o->y += alpha * s.y; }
+    else *o = {alpha * s.x, alpha * s.y};
 }
 
 // ------------------------------------------------------------- host ----
@@ -396,7 +407,7 @@ void cgemm_f32_config(int cfg, int *bm, int *bn, int *wm, int *wn) {
 }
 
 int cgemm_f64_run(CgemmList L, bool a_c64, bool conj_a, int splits, double2 *work, hipStream_t s,
-                  bool accumulate) {
+                  bool accumulate, double alpha) {
     const int64_t total = plan(L, 64, 64);
     if (total == 0) return MBEM_OK;
     if (splits < 1) splits = 1;
@@ -404,7 +415,7 @@ int cgemm_f64_run(CgemmList L, bool a_c64, bool conj_a, int splits, double2 *wor
     for (int q = 0; q < L.np; ++q) kmax = std::max(kmax, L.p[q].K);
     const int64_t kchunk = std::max<int64_t>(8, ((kmax + splits - 1) / splits + 7) / 8 * 8);
     splits = (int)std::max<int64_t>(1, (kmax + kchunk - 1) / kchunk);
-    const bool staged = splits > 1 || accumulate;
+    const bool staged = splits > 1;
     if (staged && (L.np != 1 || !work)) { set_error("split GEMM needs one problem and a workspace"); return MBEM_EINVAL; }
     CgemmList Lw = L;
     int64_t stride = 0;
@@ -417,14 +428,18 @@ int cgemm_f64_run(CgemmList L, bool a_c64, bool conj_a, int splits, double2 *wor
         stride = P.sc * P.batch;
     }
     const dim3 grid((unsigned)total, (unsigned)splits);
+    // one split: the kernel scales (and accumulates) itself; several: the
+    // reduction does
+    const double kalpha = staged ? 1.0 : alpha;
+    const int krmw = !staged && accumulate ? 1 : 0;
     if (a_c64 && conj_a)
-        hipLaunchKernelGGL((k_cgemm_f64<float2, double2, true>), grid, dim3(256), 0, s, Lw, kchunk, stride);
+        hipLaunchKernelGGL((k_cgemm_f64<float2, double2, true>), grid, dim3(256), 0, s, Lw, kchunk, stride, kalpha, krmw);
     else if (a_c64)
-        hipLaunchKernelGGL((k_cgemm_f64<float2, double2, false>), grid, dim3(256), 0, s, Lw, kchunk, stride);
+        hipLaunchKernelGGL((k_cgemm_f64<float2, double2, false>), grid, dim3(256), 0, s, Lw, kchunk, stride, kalpha, krmw);
     else if (conj_a)
-        hipLaunchKernelGGL((k_cgemm_f64<double2, double2, true>), grid, dim3(256), 0, s, Lw, kchunk, stride);
+        hipLaunchKernelGGL((k_cgemm_f64<double2, double2, true>), grid, dim3(256), 0, s, Lw, kchunk, stride, kalpha, krmw);
     else
-        hipLaunchKernelGGL((k_cgemm_f64<double2, double2, false>), grid, dim3(256), 0, s, Lw, kchunk, stride);
+        hipLaunchKernelGGL((k_cgemm_f64<double2, double2, false>), grid, dim3(256), 0, s, Lw, kchunk, stride, kalpha, krmw);
     MBEM_HIP(hipGetLastError());
     if (staged) {
         const CgemmProb &P = L.p[0];
@@ -432,10 +447,10 @@ int cgemm_f64_run(CgemmList L, bool a_c64, bool conj_a, int splits, double2 *wor
         const unsigned g = (unsigned)((n + 255) / 256);
         if (accumulate)
             hipLaunchKernelGGL(k_split_reduce<true>, dim3(g), dim3(256), 0, s, work, splits, P.M, P.Nb,
-                               (int64_t)P.batch, (double2 *)P.C, P.ldc, P.sc);
+                               (int64_t)P.batch, (double2 *)P.C, P.ldc, P.sc, alpha);
         else
             hipLaunchKernelGGL(k_split_reduce<false>, dim3(g), dim3(256), 0, s, work, splits, P.M, P.Nb,
-                               (int64_t)P.batch, (double2 *)P.C, P.ldc, P.sc);
+                               (int64_t)P.batch, (double2 *)P.C, P.ldc, P.sc, alpha);
         MBEM_HIP(hipGetLastError());
     }
     return MBEM_OK;
