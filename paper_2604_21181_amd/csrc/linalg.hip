@@ -385,8 +385,8 @@ __global__ void k_mbj_gather_blr(int64_t n2, int B, BlrView v, const int32_t *mp
 template <int MAXN, int kPW>
 __global__ __launch_bounds__(1024) void k_mbj_lu(int64_t n2, int B, double2 *A, int32_t *piv,
                                                  int32_t *info) {
-    __shared__ double s_v[1024];
-    __shared__ int s_i[1024];
+    __shared__ double s_v[1024 / kW];
+    __shared__ int s_i[1024 / kW];
     __shared__ double2 s_L[MAXN * kPW];    // L21, rows below the panel
     __shared__ double2 s_U[kPW * MAXN];    // U12, columns right of it
     __shared__ int32_t s_pv[MAXN];         // row interchange of each step
@@ -406,19 +406,21 @@ __global__ __launch_bounds__(1024) void k_mbj_lu(int64_t n2, int B, double2 *A, 
                 const double mag = v.x * v.x + v.y * v.y;
                 if (mag > best) { best = mag; bi = i; }
             }
-            s_v[tid] = best;
-            s_i[tid] = bi;
-            __syncthreads();
-            for (int off = nth / 2; off > 0; off >>= 1) {
-                if (tid < off) {
-                    const double o = s_v[tid + off];
-                    const int oi = s_i[tid + off];
-                    if (o > s_v[tid] || (o == s_v[tid] && oi < s_i[tid])) { s_v[tid] = o; s_i[tid] = oi; }
-                }
-                __syncthreads();
+            // arg-max: within each wavefront by shuffles, then over the
+            // wavefronts' winners (largest modulus, lowest row on ties)
+#pragma unroll
+            for (int off = kW / 2; off > 0; off >>= 1) {
+                const double o = __shfl_xor(best, off, kW);
+                const int oi = __shfl_xor(bi, off, kW);
+                if (o > best || (o == best && oi < bi)) { best = o; bi = oi; }
             }
-            const int p = s_i[0];
-            const bool zero = !(s_v[0] > 0.0);
+            if (tid % kW == 0) { s_v[tid / kW] = best; s_i[tid / kW] = bi; }
+            __syncthreads();
+            double pb = s_v[0];
+            int p = s_i[0];
+            for (int q = 1; q < nth / kW; ++q)
+                if (s_v[q] > pb || (s_v[q] == pb && s_i[q] < p)) { pb = s_v[q]; p = s_i[q]; }
+            const bool zero = !(pb > 0.0);
             __syncthreads();
             if (tid == 0) { s_pv[k] = p; if (zero && *info == 0) *info = m + 1; }
             if (zero) continue;
