@@ -10,6 +10,7 @@
 #include <mutex>
 #include <type_traits>
 
+#include "gemm.h"
 #include "mbem_internal.h"
 #include "near_store.h"
 
@@ -573,6 +574,327 @@ __global__ __launch_bounds__(1024) void k_mbj_inverse(int64_t n2, int B, const d
     }
 }
 
+// ---- block-Jacobi setup for large blocks: panel kernels + FP64 MFMA GEMM --
+// For blocks of 2B >= kMbjGemmMin rows the factorisation and the inverse
+// run on every compute unit: the blocks are padded to ld x ld with the
+// identity (so that every block of the batch has one shape), each panel of
+// kMbjPW columns is factorised by one workgroup per block, the trailing
+// matrix is updated by the batched complex GEMM, and the inverse is formed
+// column-wise as X^T = (U^-1 L^-1 P)^T: per panel of 64 rows a triangular
+// solve of the diagonal block for every column (one wavefront each), then a
+// GEMM update of the remaining rows; X^T is transposed in place at the end.
+constexpr int kMbjPW = 16;
+constexpr int kMbjGemmMin = 128;
+
+// Rows and columns n .. ld-1 of the last block become the identity.
+__global__ void k_mbj_pad(int ld, int n, double2 *A) {
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= (int64_t)ld * ld) return;
+    const int r = (int)(id / ld), q = (int)(id % ld);
+    if (r >= n || q >= n) A[id] = {r == q ? 1.0 : 0.0, 0.0};
+}
+
+// Columns j0 .. j0 + kMbjPW - 1 of every block, held in registers (thread t
+// owns row j0 + t of the panel): partial pivoting over the rows below the
+// diagonal, the interchange (recorded in swp; k_mbj_laswp applies it to the
+// columns outside the panel), scaling of the column below the pivot and
+// the rank-one update of the panel's remaining columns.
+__global__ __launch_bounds__(1024) void k_mbj_panel(int ld, int j0, double2 *A, int32_t *swp, int32_t *info) {
+    __shared__ double s_v[1024 / kW];
+    __shared__ int s_i[1024 / kW];
+    __shared__ double2 s_k[kMbjPW], s_p[kMbjPW];   // rows k and p before the interchange
+    const int m = blockIdx.x, tid = threadIdx.x, nth = blockDim.x;
+    double2 *a = A + (int64_t)m * ld * ld;
+    const int jw = min(kMbjPW, ld - j0);
+    const int i = j0 + tid;
+    const bool own = i < ld;
+    double2 r[kMbjPW];
+#pragma unroll
+    for (int c = 0; c < kMbjPW; ++c) r[c] = (own && c < jw) ? a[(int64_t)i * ld + j0 + c] : double2{0, 0};
+#pragma unroll
+    for (int kk = 0; kk < kMbjPW; ++kk) {
+        if (kk < jw) {
+            const int k = j0 + kk;
+            double best = (own && i >= k) ? r[kk].x * r[kk].x + r[kk].y * r[kk].y : -1.0;
+            int bi = i;
+#pragma unroll
+            for (int off = kW / 2; off > 0; off >>= 1) {
+                const double o = __shfl_xor(best, off, kW);
+                const int oi = __shfl_xor(bi, off, kW);
+                if (o > best || (o == best && oi < bi)) { best = o; bi = oi; }
+            }
+            if (tid % kW == 0) { s_v[tid / kW] = best; s_i[tid / kW] = bi; }
+            __syncthreads();
+            double pb = s_v[0];
+            int p = s_i[0];
+            for (int q = 1; q < nth / kW; ++q)
+                if (s_v[q] > pb || (s_v[q] == pb && s_i[q] < p)) { pb = s_v[q]; p = s_i[q]; }
+            const bool zero = !(pb > 0.0);
+            if (zero) p = k;
+            if (tid == 0) {
+                swp[(int64_t)m * ld + k] = p;
+                if (zero) atomicCAS(info, 0, m + 1);
+            }
+            if (i == k) {
+#pragma unroll
+                for (int c = 0; c < kMbjPW; ++c) s_k[c] = r[c];
+            }
+            if (i == p) {
+#pragma unroll
+                for (int c = 0; c < kMbjPW; ++c) s_p[c] = r[c];
+            }
+            __syncthreads();
+            if (!zero) {
+                if (i == k && p != k) {
+#pragma unroll
+                    for (int c = 0; c < kMbjPW; ++c) r[c] = s_p[c];
+                } else if (i == p && p != k) {
+#pragma unroll
+                    for (int c = 0; c < kMbjPW; ++c) r[c] = s_k[c];
+                }
+                // the pivot row is the former row p
+                const double2 d = s_p[kk];
+                const double dn = d.x * d.x + d.y * d.y;
+                const double2 inv = {d.x / dn, -d.y / dn};
+                if (own && i > k) {
+                    const double2 l = cmul(r[kk], inv);
+                    r[kk] = l;
+#pragma unroll
+                    for (int c = kk + 1; c < kMbjPW; ++c) r[c] = csub(r[c], cmul(l, s_p[c]));
+                }
+            }
+            // s_k, s_p are rewritten only after the next step's first barrier
+        }
+    }
+    if (own)
+#pragma unroll
+        for (int c = 0; c < kMbjPW; ++c)
+            if (c < jw) a[(int64_t)i * ld + j0 + c] = r[c];
+}
+
+// The interchanges of panel j0 applied to every column outside the panel
+// (one thread per column, in the order they were chosen).
+__global__ __launch_bounds__(256) void k_mbj_laswp(int ld, int j0, double2 *A, const int32_t *swp) {
+    const int m = blockIdx.y;
+    const int jw = min(kMbjPW, ld - j0);
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ld - jw) return;
+    if (q >= j0) q += jw;                     // skip the panel's columns
+    double2 *a = A + (int64_t)m * ld * ld;
+    const int32_t *sw = swp + (int64_t)m * ld;
+    for (int k = j0; k < j0 + jw; ++k) {
+        const int p = sw[k];
+        if (p != k) {
+            const double2 t = a[(int64_t)k * ld + q];
+            a[(int64_t)k * ld + q] = a[(int64_t)p * ld + q];
+            a[(int64_t)p * ld + q] = t;
+        }
+    }
+}
+
+// U12 = L11^-1 A12 for the columns right of the panel (one thread per
+// column, L11 staged in LDS), written in place and transposed into UT
+// ([column][panel row], leading dimension kMbjPW) for the GEMM.
+__global__ __launch_bounds__(256) void k_mbj_trsm(int ld, int j0, double2 *A, double2 *UT) {
+    __shared__ double2 sL[kMbjPW][kMbjPW + 1];
+    const int m = blockIdx.y, tid = threadIdx.x;
+    const int je = min(j0 + kMbjPW, ld), jw = je - j0;
+    double2 *a = A + (int64_t)m * ld * ld;
+    for (int t = tid; t < jw * jw; t += blockDim.x) sL[t / jw][t % jw] = a[(int64_t)(j0 + t / jw) * ld + j0 + t % jw];
+    __syncthreads();
+    const int q = je + blockIdx.x * blockDim.x + tid;
+    if (q >= ld) return;
+    double2 u[kMbjPW];
+    double2 *ut = UT + (int64_t)m * ld * kMbjPW + (int64_t)(q - je) * kMbjPW;
+#pragma unroll
+    for (int r = 0; r < kMbjPW; ++r) {
+        if (r < jw) {
+            double2 t = a[(int64_t)(j0 + r) * ld + q];
+#pragma unroll
+            for (int c = 0; c < r; ++c) t = csub(t, cmul(sL[r][c], u[c]));
+            u[r] = t;
+            a[(int64_t)(j0 + r) * ld + q] = t;
+            ut[r] = t;
+        }
+    }
+}
+
+// The interchanges of every block as one gather: row i of P A is row
+// pv[i] of A (composed in LDS by one thread per block).
+__global__ __launch_bounds__(64) void k_mbj_perm(int ld, const int32_t *swp, int32_t *pv) {
+    __shared__ int32_t o[1024], sw[1024];
+    const int m = blockIdx.x;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+        o[i] = i;
+        sw[i] = swp[(int64_t)m * ld + i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < ld; ++k) {
+            const int p = sw[k];
+            const int32_t t = o[k];
+            o[k] = o[p];
+            o[p] = t;
+        }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) pv[(int64_t)m * ld + i] = o[i];
+}
+
+// X^T[j][r] = (P e_j)[r]
+__global__ void k_mbj_inv_init(int ld, int nb, const int32_t *pv, double2 *XT) {
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)ld * ld;
+    if (id >= per * nb) return;
+    const int64_t m = id / per, r = id % per;
+    const int j = (int)(r / ld), i = (int)(r % ld);
+    XT[id] = {pv[m * ld + i] == j ? 1.0 : 0.0, 0.0};
+}
+
+// Rows p0 .. p0 + pw of every column j: solve with the diagonal block of L
+// (unit, UPPER = false) or U (UPPER = true); one wavefront per two columns
+// (two independent shuffle chains), the reciprocals of U's diagonal formed
+// once per workgroup.
+template <bool UPPER>
+__global__ __launch_bounds__(1024) void k_mbj_inv_diag(int ld, int p0, int pw, const double2 *LU, double2 *XT) {
+    __shared__ double2 s_P[kW][kW + 1];
+    __shared__ double2 s_inv[kW];
+    const int m = blockIdx.y, tid = threadIdx.x, lane = tid % kW, wv = tid / kW;
+    const double2 *a = LU + (int64_t)m * ld * ld;
+    for (int id = tid; id < pw * pw; id += blockDim.x)
+        s_P[id / pw][id % pw] = a[(int64_t)(p0 + id / pw) * ld + p0 + id % pw];
+    if (UPPER && tid < pw) {
+        const double2 d = a[(int64_t)(p0 + tid) * ld + p0 + tid];
+        const double dn = d.x * d.x + d.y * d.y;
+        s_inv[tid] = {d.x / dn, -d.y / dn};
+    }
+    __syncthreads();
+    const int j = 2 * (blockIdx.x * (blockDim.x / kW) + wv);
+    if (j >= ld) return;
+    const bool two = j + 1 < ld;
+    double2 *x0 = XT + (int64_t)m * ld * ld + (int64_t)j * ld + p0;
+    double2 *x1 = x0 + ld;
+    double2 y0 = lane < pw ? x0[lane] : double2{0, 0};
+    double2 y1 = (two && lane < pw) ? x1[lane] : double2{0, 0};
+    if (!UPPER) {
+        for (int k = 0; k < pw - 1; ++k) {
+            const double2 a0 = {__shfl(y0.x, k, kW), __shfl(y0.y, k, kW)};
+            const double2 a1 = {__shfl(y1.x, k, kW), __shfl(y1.y, k, kW)};
+            if (lane > k && lane < pw) {
+                const double2 l = s_P[lane][k];
+                y0 = csub(y0, cmul(l, a0));
+                y1 = csub(y1, cmul(l, a1));
+            }
+        }
+    } else {
+        for (int k = pw - 1; k >= 0; --k) {
+            if (lane == k) {
+                y0 = cmul(y0, s_inv[k]);
+                y1 = cmul(y1, s_inv[k]);
+            }
+            const double2 a0 = {__shfl(y0.x, k, kW), __shfl(y0.y, k, kW)};
+            const double2 a1 = {__shfl(y1.x, k, kW), __shfl(y1.y, k, kW)};
+            if (lane < k) {
+                const double2 u = s_P[lane][k];
+                y0 = csub(y0, cmul(u, a0));
+                y1 = csub(y1, cmul(u, a1));
+            }
+        }
+    }
+    if (lane < pw) {
+        x0[lane] = y0;
+        if (two) x1[lane] = y1;
+    }
+}
+
+// In-place transpose of every ld x ld block, 32 x 32 tiles: the workgroup
+// of tile (ti, tj), ti <= tj, swaps it with tile (tj, ti).
+__global__ __launch_bounds__(256) void k_mbj_transpose(int ld, double2 *X) {
+    __shared__ double2 t0[32][33], t1[32][33];
+    const int nt = (ld + 31) / 32;
+    int ti = 0, rem = blockIdx.x;
+    while (rem >= nt - ti) { rem -= nt - ti; ++ti; }
+    const int tj = ti + rem;
+    double2 *x = X + (int64_t)blockIdx.y * ld * ld;
+    for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
+        const int r = e / 32, c = e % 32;
+        const int i0 = ti * 32 + r, j0 = tj * 32 + c, i1 = tj * 32 + r, j1 = ti * 32 + c;
+        if (i0 < ld && j0 < ld) t0[r][c] = x[(int64_t)i0 * ld + j0];
+        if (i1 < ld && j1 < ld) t1[r][c] = x[(int64_t)i1 * ld + j1];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
+        const int r = e / 32, c = e % 32;
+        const int i0 = ti * 32 + r, j0 = tj * 32 + c, i1 = tj * 32 + r, j1 = ti * 32 + c;
+        if (i0 < ld && j0 < ld) x[(int64_t)i0 * ld + j0] = t1[c][r];
+        if (i1 < ld && j1 < ld) x[(int64_t)i1 * ld + j1] = t0[c][r];
+    }
+}
+
+// C[b][m] += alpha sum_k A[m][k] B[b][k] over the nb blocks (strides ld^2;
+// sa overrides A's stride)
+static int mbj_gemm(const double2 *A, int64_t lda, int64_t sa, const double2 *B, int64_t ldb, double2 *C,
+                    int64_t ldc, int64_t ld, int64_t M, int64_t Nb, int64_t K, int nb, hipStream_t s) {
+    if (M <= 0 || Nb <= 0 || K <= 0) return MBEM_OK;
+    CgemmList L;
+    L.np = 1;
+    CgemmProb &P = L.p[0];
+    P.A = A; P.lda = lda; P.sa = sa;
+    P.B = B; P.ldb = ldb; P.sb = ld * ld;
+    P.C = C; P.ldc = ldc; P.sc = ld * ld;
+    P.M = M; P.Nb = Nb; P.K = K; P.batch = nb;
+    return cgemm_f64_run(L, false, false, 1, nullptr, s, true, -1.0);
+}
+
+// LU (in LUbuf, [nb][ld][ld], gathered and padded) and inverses (Minv) of
+// every block; UT: ld * kMbjPW per block; swp, pv: ld per block.
+static int mbj_factor_invert_gemm(int ld, int nb, int n_last, double2 *LUb, int32_t *swp, int32_t *pv,
+                                  int32_t *info, double2 *UT, double2 *Minv, hipStream_t s) {
+    if (n_last < ld) {
+        const int64_t tot = (int64_t)ld * ld;
+        hipLaunchKernelGGL(k_mbj_pad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, ld, n_last,
+                           LUb + (int64_t)(nb - 1) * ld * ld);
+        MBEM_HIP(hipGetLastError());
+    }
+    for (int j0 = 0; j0 < ld; j0 += kMbjPW) {
+        const int je = std::min(j0 + kMbjPW, ld);
+        hipLaunchKernelGGL(k_mbj_panel, dim3(nb), dim3(1024), 0, s, ld, j0, LUb, swp, info);
+        MBEM_HIP(hipGetLastError());
+        if (ld - (je - j0) > 0) {
+            hipLaunchKernelGGL(k_mbj_laswp, dim3((unsigned)((ld - (je - j0) + 255) / 256), nb), dim3(256), 0, s, ld,
+                               j0, LUb, (const int32_t *)swp);
+            MBEM_HIP(hipGetLastError());
+        }
+        if (je >= ld) break;
+        hipLaunchKernelGGL(k_mbj_trsm, dim3((unsigned)((ld - je + 255) / 256), nb), dim3(256), 0, s, ld, j0, LUb, UT);
+        MBEM_HIP(hipGetLastError());
+        MBEM_TRY(mbj_gemm(UT, kMbjPW, (int64_t)ld * kMbjPW, LUb + (int64_t)je * ld + j0, ld,
+                          LUb + (int64_t)je * ld + je, ld, ld, ld - je, ld - je, je - j0, nb, s));
+    }
+    hipLaunchKernelGGL(k_mbj_perm, dim3(nb), dim3(64), 0, s, ld, (const int32_t *)swp, pv);
+    MBEM_HIP(hipGetLastError());
+    const int64_t tot = (int64_t)ld * ld * nb;
+    hipLaunchKernelGGL(k_mbj_inv_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, ld, nb, pv, Minv);
+    MBEM_HIP(hipGetLastError());
+    const dim3 gd((unsigned)((ld + 31) / 32), nb);
+    for (int p0 = 0; p0 < ld; p0 += kW) {
+        const int pw = std::min(kW, ld - p0);
+        hipLaunchKernelGGL(k_mbj_inv_diag<false>, gd, dim3(1024), 0, s, ld, p0, pw, LUb, Minv);
+        MBEM_HIP(hipGetLastError());
+        MBEM_TRY(mbj_gemm(LUb + (int64_t)(p0 + pw) * ld + p0, ld, (int64_t)ld * ld, Minv + p0, ld,
+                          Minv + p0 + pw, ld, ld, ld - p0 - pw, ld, pw, nb, s));
+    }
+    for (int pe = ld; pe > 0; pe -= kW) {
+        const int p0 = std::max(0, pe - kW), pw = pe - p0;
+        hipLaunchKernelGGL(k_mbj_inv_diag<true>, gd, dim3(1024), 0, s, ld, p0, pw, LUb, Minv);
+        MBEM_HIP(hipGetLastError());
+        MBEM_TRY(mbj_gemm(LUb + p0, ld, (int64_t)ld * ld, Minv + p0, ld, Minv, ld, ld, p0, ld, pw, nb, s));
+    }
+    const int nt = (ld + 31) / 32;
+    hipLaunchKernelGGL(k_mbj_transpose, dim3((unsigned)(nt * (nt + 1) / 2), nb), dim3(256), 0, s, ld, Minv);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
 // z = blockdiag(A_m^-1) v; one wavefront per row of a block.
 __global__ __launch_bounds__(256) void k_mbj_apply(int64_t n2, int B, int nb, const double2 *Minv,
                                                    const double2 *v, double2 *z) {
@@ -633,7 +955,16 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s, bool keep) {
         hipLaunchKernelGGL((k_mbj_gather<float2>), g, dim3(256), 0, s, n2, B, op->K[0], op->K[1],
                            op->K[2], m->d_mptr, m->d_mcol, op->d_mval, coef_of(op), op->near_view(), op->d_lu);
     MBEM_HIP(hipGetLastError());
-    if (ld <= 512) {
+    double2 *UT = nullptr;
+    int32_t *swp = nullptr;
+    if (ld >= kMbjGemmMin) {
+        // panels on one workgroup per block, updates on the whole chip
+        MBEM_HIP(hipMalloc((void **)&UT, sizeof(double2) * nb * ld * kMbjPW + sizeof(int32_t) * nb * ld));
+        swp = (int32_t *)(UT + (int64_t)nb * ld * kMbjPW);
+        const int n_last = (int)(2 * (n2 - (int64_t)(nb - 1) * B));
+        const int st = mbj_factor_invert_gemm((int)ld, nb, n_last, op->d_lu, swp, piv, info, UT, op->d_minv, s);
+        if (st != MBEM_OK) { (void)hipStreamSynchronize(s); (void)hipFree(UT); return st; }
+    } else if (ld <= 512) {
         hipLaunchKernelGGL((k_mbj_lu<512, 8>), dim3(nb), dim3(1024), 0, s, n2, B, op->d_lu, piv, info);
         MBEM_HIP(hipGetLastError());
         hipLaunchKernelGGL((k_mbj_inverse<512, 8>), dim3(nb, (unsigned)((ld + 7) / 8)), dim3(1024), 0, s,
@@ -648,6 +979,7 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s, bool keep) {
     int32_t h = 0;
     MBEM_HIP(hipMemcpyAsync(&h, info, sizeof(h), hipMemcpyDeviceToHost, s));
     MBEM_HIP(hipStreamSynchronize(s));
+    if (UT) MBEM_HIP(hipFree(UT));
     if (!keep) { MBEM_HIP(hipFree(op->d_lu)); op->d_lu = nullptr; op->lu_bytes = 0; }
     if (h) {
         set_error("zero pivot in preconditioner block " + std::to_string(h - 1));
