@@ -400,9 +400,11 @@ int mbem_gemm_autotune(mbem_ctx *ctx, mbem_op *op, int32_t nrhs, int32_t reps,
 /* The complex GEMM of the block solve on its own:
  *   C[b][m] = sum_k op(A[m][k]) B[b][k],  m < M, b < Nb, k < K,
  * all row-major device arrays (leading dimensions in elements).
- *   dtype 0: complex64 A, B, C, FP32 accumulation (matrix cores), tile shape
- *            `config` (0..5), conj_a must be 0; lda, ldb even and A, B
- *            16-byte aligned;
+ *   dtype 0: complex64 A, B, C, FP32 accumulation (matrix cores; three
+ *            real products per complex one: (A_re + A_im) B_re,
+ *            A_re (B_im - B_re), A_im (B_re + B_im)), tile shape `config`
+ *            (0..5), conj_a must be 0; lda, ldb even and A, B 16-byte
+ *            aligned;
  *   dtype 1: complex128 A, B, C, FP64 accumulation (matrix cores);
  *   dtype 2: complex64 A, complex128 B and C, FP64 accumulation.
  * op = conj when conj_a (dtypes 1 and 2).                                   */

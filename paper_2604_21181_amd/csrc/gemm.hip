@@ -11,9 +11,10 @@
 //     B'  row 2b+1 = [ b_im   b_re ...]   -> Im C      (conj: [b_im -b_re])
 // B' is formed while staging B through LDS; A is used as stored.
 //
-// FP32 (complex64 operator, FP32 accumulation): v_mfma_f32_32x32x2f32, one
-// template per tile shape; the shape is chosen at run time by measuring
-// every candidate on the problem at hand (autotune below).
+// FP32 (complex64 operator, FP32 accumulation): v_mfma_f32_32x32x2f32 on
+// three real products per complex one (3M, below) instead of the doubled
+// real GEMM; one template per tile shape; the shape is chosen at run time by
+// measuring every candidate on the problem at hand (autotune below).
 // FP64 (basis projections, Gram matrices, refinement residuals):
 // v_mfma_f64_16x16x4f64 on 64 x 64 tiles with an optional split of k.
 #include <algorithm>
@@ -56,16 +57,27 @@ __device__ inline TileRef locate(const CgemmList &L, int64_t tile) {
 #define MBEM_PICK(L, q, field) ((q) == 0 ? (L).p[0].field : (q) == 1 ? (L).p[1].field : (L).p[2].field)
 
 // ------------------------------------------------------------- FP32 ----
+// Three real products per complex product (the 3M method):
+//   T1 = (A_re + A_im) B_re^T,  T2 = A_re (B_im - B_re)^T,  T3 = A_im (B_re + B_im)^T,
+//   Re C = T1 - T3,  Im C = T1 + T2,
+// so 3 instead of 4 real multiply-adds per complex one.  Per stage of 8
+// complex k the three A planes and the three B planes are formed while
+// staging through LDS, each row stored k-interleaved (position 4 h + s for
+// k = 2 s + h) so that a lane reads its four MFMA inputs with one 16-byte
+// load.  BN counts real output columns (two per complex column), as the
+// tile shapes of the autotuner are named.
 template <int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_cgemm_f32(CgemmList L) {
+    static_assert(WN >= 64 && WM >= 32, "a wavefront covers at least 32 x 32 complex outputs");
     constexpr int NWN = BN / WN;
     constexpr int NT = 64 * (BM / WM) * NWN;
-    constexpr int TM = WM / 32, TN = WN / 32;
-    constexpr int LD = 20;                        // 16 real k + pad, in floats
-    constexpr int NA = (BM * 4 + NT - 1) / NT;    // float4 loads of A per stage
-    constexpr int NB = (BN * 2 + NT - 1) / NT;    // float4 loads of B per stage
-    __shared__ __align__(16) float sA[2][BM * LD];
-    __shared__ __align__(16) float sB[2][BN * LD];
+    constexpr int BC = BN / 2, WC = WN / 2;       // complex output columns per tile / wave
+    constexpr int TM = WM / 32, TC = WC / 32;
+    constexpr int LD = 12;                        // 8 k + pad, in floats
+    constexpr int NA = (BM * 4 + NT - 1) / NT;    // float4 (two complex k) loads of A per stage
+    constexpr int NB = (BC * 4 + NT - 1) / NT;
+    __shared__ __align__(16) float sA[2][3][BM * LD];
+    __shared__ __align__(16) float sB[2][3][BC * LD];
 
     const int64_t tile = xcd_tile(blockIdx.x, L.total);
     const int q = locate(L, tile).q;
@@ -73,70 +85,73 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_cgemm_f32(CgemmL
     const int64_t per = MBEM_PICK(L, q, tiles);
     const int64_t tn_count = MBEM_PICK(L, q, tn);
     const int64_t bidx = t / per, r = t % per;
-    const int64_t m0 = (r / tn_count) * BM, n0 = (r % tn_count) * BN;
+    const int64_t m0 = (r / tn_count) * BM, b0 = (r % tn_count) * BC;
     const int64_t M = MBEM_PICK(L, q, M), Nb = MBEM_PICK(L, q, Nb), K = MBEM_PICK(L, q, K);
     const int64_t lda = MBEM_PICK(L, q, lda), ldb = MBEM_PICK(L, q, ldb), ldc = MBEM_PICK(L, q, ldc);
     const float2 *A = (const float2 *)MBEM_PICK(L, q, A) + bidx * MBEM_PICK(L, q, sa);
     const float2 *B = (const float2 *)MBEM_PICK(L, q, B) + bidx * MBEM_PICK(L, q, sb);
     float2 *C = (float2 *)MBEM_PICK(L, q, C) + bidx * MBEM_PICK(L, q, sc);
-    const int64_t b0 = n0 / 2;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / NWN, wn = wave % NWN;
     const int h = lane >> 5, l32 = lane & 31;
 
     f32x4 ra[NA], rb[NB];
+    auto ld2 = [](const float2 *src, int64_t kc, int64_t Kend) {
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};
+        if (kc + 1 < Kend) v = *(const f32x4 *)src;
+        else if (kc < Kend) { const float2 w = src[0]; v = {w.x, w.y, 0.f, 0.f}; }
+        return v;
+    };
     auto gload = [&](int64_t kc0) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int idx = tid + i * NT;
-            f32x4 v = {0.f, 0.f, 0.f, 0.f};
             const int64_t m = m0 + (idx >> 2), kc = kc0 + 2 * (idx & 3);
-            if (idx < BM * 4 && m < M) {
-                const float2 *src = A + m * lda + kc;
-                if (kc + 1 < K) v = *(const f32x4 *)src;
-                else if (kc < K) { const float2 w = src[0]; v = {w.x, w.y, 0.f, 0.f}; }
-            }
-            ra[i] = v;
+            ra[i] = (idx < BM * 4 && m < M) ? ld2(A + m * lda + kc, kc, K) : f32x4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int idx = tid + i * NT;
-            f32x4 v = {0.f, 0.f, 0.f, 0.f};
             const int64_t b = b0 + (idx >> 2), kc = kc0 + 2 * (idx & 3);
-            if (idx < BN * 2 && b < Nb) {
-                const float2 *src = B + b * ldb + kc;
-                if (kc + 1 < K) v = *(const f32x4 *)src;
-                else if (kc < K) { const float2 w = src[0]; v = {w.x, w.y, 0.f, 0.f}; }
-            }
-            rb[i] = v;
+            rb[i] = (idx < BC * 4 && b < Nb) ? ld2(B + b * ldb + kc, kc, K) : f32x4{0.f, 0.f, 0.f, 0.f};
         }
     };
+    // complex k = 2 kk + j of the pair (kk = idx & 3) -> position 4 (k & 1) + (k >> 1)
     auto sstore = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int idx = tid + i * NT;
-            if (idx < BM * 4) *(f32x4 *)&sA[buf][(idx >> 2) * LD + 4 * (idx & 3)] = ra[i];
+            if (idx < BM * 4) {
+                const f32x4 v = ra[i];
+                const int row = idx >> 2, kk = idx & 3;
+                float *s0 = &sA[buf][0][row * LD], *s1 = &sA[buf][1][row * LD], *s2 = &sA[buf][2][row * LD];
+                s0[kk] = v.x + v.y;  s1[kk] = v.x;  s2[kk] = v.y;          // k = 2 kk (even: h = 0)
+                s0[4 + kk] = v.z + v.w;  s1[4 + kk] = v.z;  s2[4 + kk] = v.w;   // k = 2 kk + 1
+            }
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int idx = tid + i * NT;
-            if (idx < BN * 2) {
+            if (idx < BC * 4) {
                 const f32x4 v = rb[i];
-                const int row = idx >> 2, k4 = 4 * (idx & 3);
-                *(f32x4 *)&sB[buf][(2 * row) * LD + k4] = f32x4{v.x, -v.y, v.z, -v.w};
-                *(f32x4 *)&sB[buf][(2 * row + 1) * LD + k4] = f32x4{v.y, v.x, v.w, v.z};
+                const int row = idx >> 2, kk = idx & 3;
+                float *s0 = &sB[buf][0][row * LD], *s1 = &sB[buf][1][row * LD], *s2 = &sB[buf][2][row * LD];
+                s0[kk] = v.x;  s1[kk] = v.y - v.x;  s2[kk] = v.x + v.y;
+                s0[4 + kk] = v.z;  s1[4 + kk] = v.w - v.z;  s2[4 + kk] = v.z + v.w;
             }
         }
     };
 
-    f32x16 acc[TM][TN];
+    f32x16 acc[3][TM][TC];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int p3 = 0; p3 < 3; ++p3)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+            for (int j = 0; j < TC; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[p3][i][j][e] = 0.f;
 
     const int64_t nst = (K + 7) / 8;   // stages of 8 complex k
     gload(0);
@@ -145,44 +160,41 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_cgemm_f32(CgemmL
     for (int64_t st = 0; st < nst; ++st) {
         const int cur = (int)(st & 1);
         if (st + 1 < nst) gload((st + 1) * 8);
-        // lane (l32, h) feeds MFMA step s with real k = 8 h + s of the stage
-        f32x4 a[TM][2], b[TN][2];
+        // lane (l32, h) feeds MFMA step s with complex k = 2 s + h
+        f32x4 a[3][TM], b[3][TC];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            const float *src = &sA[cur][(wm * WM + i * 32 + l32) * LD + 8 * h];
-            a[i][0] = *(const f32x4 *)src;
-            a[i][1] = *(const f32x4 *)(src + 4);
-        }
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const float *src = &sB[cur][(wn * WN + j * 32 + l32) * LD + 8 * h];
-            b[j][0] = *(const f32x4 *)src;
-            b[j][1] = *(const f32x4 *)(src + 4);
-        }
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
+        for (int p3 = 0; p3 < 3; ++p3) {
 #pragma unroll
             for (int i = 0; i < TM; ++i)
+                a[p3][i] = *(const f32x4 *)&sA[cur][p3][(wm * WM + i * 32 + l32) * LD + 4 * h];
 #pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][s >> 2][s & 3], b[j][s >> 2][s & 3],
-                                                                     acc[i][j], 0, 0, 0);
+            for (int j = 0; j < TC; ++j)
+                b[p3][j] = *(const f32x4 *)&sB[cur][p3][(wn * WC + j * 32 + l32) * LD + 4 * h];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int p3 = 0; p3 < 3; ++p3)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TC; ++j)
+                        acc[p3][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p3][i][s], b[p3][j][s],
+                                                                             acc[p3][i][j], 0, 0, 0);
         if (st + 1 < nst) sstore(cur ^ 1);
         __syncthreads();
     }
-    // accumulator (lane, e): column l32, row 8 (e / 4) + 4 h + e % 4; even
-    // real columns are real parts, the odd neighbour holds the imaginary part
+    // accumulator (lane, e): complex column l32, row 8 (e / 4) + 4 h + e % 4
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+        for (int j = 0; j < TC; ++j)
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const float v = acc[i][j][e];
-                const float w = __shfl_xor(v, 1);
                 const int64_t m = m0 + wm * WM + i * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
-                const int64_t n = n0 + wn * WN + j * 32 + l32;
-                if ((l32 & 1) == 0 && m < M && (n >> 1) < Nb) C[(n >> 1) * ldc + m] = float2{v, w};
+                const int64_t b = b0 + wn * WC + j * 32 + l32;
+                const float t1 = acc[0][i][j][e], t2 = acc[1][i][j][e], t3 = acc[2][i][j][e];
+                if (m < M && b < Nb) C[b * ldc + m] = float2{t1 - t3, t1 + t2};
             }
 }
 
@@ -346,7 +358,7 @@ __global__ void k_split_reduce(const double2 *part, int splits, int64_t M, int64
 namespace {
 struct F32Cfg { int BM, BN, WM, WN; };
 constexpr F32Cfg kF32Cfg[kGemmConfigs] = {
-    {128, 128, 64, 64}, {128, 64, 64, 32}, {64, 128, 32, 64}, {64, 64, 32, 32},
+    {128, 128, 64, 64}, {128, 64, 64, 64}, {64, 128, 32, 64}, {64, 64, 32, 64},
     {256, 128, 64, 64}, {128, 256, 64, 64},
 };
 
@@ -392,9 +404,9 @@ bool cgemm_list_valid(const CgemmList &L, size_t esz_a, size_t esz_b) {
 int cgemm_f32_run(CgemmList L, int cfg, hipStream_t s) {
     switch (cfg) {
         case 0: return launch_f32<128, 128, 64, 64>(L, s);
-        case 1: return launch_f32<128, 64, 64, 32>(L, s);
+        case 1: return launch_f32<128, 64, 64, 64>(L, s);
         case 2: return launch_f32<64, 128, 32, 64>(L, s);
-        case 3: return launch_f32<64, 64, 32, 32>(L, s);
+        case 3: return launch_f32<64, 64, 32, 64>(L, s);
         case 4: return launch_f32<256, 128, 64, 64>(L, s);
         case 5: return launch_f32<128, 256, 64, 64>(L, s);
         default: set_error("unknown GEMM configuration"); return MBEM_EINVAL;
