@@ -199,18 +199,19 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_cgemm_f32(CgemmL
 }
 
 // ------------------------------------------------------------- FP64 ----
-// 64 x 64 real tile, 4 waves of 32 x 32, k split over gridDim.y: split y
-// covers complex k in [y kchunk, (y + 1) kchunk) and writes its partial
-// product at C + y * split_stride.
-template <typename TA, typename TB, bool CONJ>
+// 64 rows x 32 complex columns per workgroup, 4 waves of 32 x 16, the 3M
+// method as in the FP32 kernel (op(A) = conj(A) negates the A_im plane);
+// k split over gridDim.y: split y covers complex k in [y kchunk,
+// (y + 1) kchunk) and writes its partial product at C + y * split_stride.
 // The product is scaled by alpha; with rmw it is added to what C holds
 // (one split only).
+template <typename TA, typename TB, bool CONJ>
 __global__ __launch_bounds__(256) void k_cgemm_f64(CgemmList L, int64_t kchunk, int64_t split_stride, double alpha,
                                                    int rmw) {
-    constexpr int BM = 64, BN = 64, WM = 32, WN = 32, NT = 256;
-    constexpr int LD = 18;   // 16 real k + pad, in doubles
-    __shared__ __align__(16) double sA[2][BM * LD];
-    __shared__ __align__(16) double sB[2][BN * LD];
+    constexpr int BM = 64, BC = 32, WM = 32, WC = 16;
+    constexpr int LD = 10;   // 8 complex k + pad, in doubles
+    __shared__ __align__(16) double sA[2][3][BM * LD];
+    __shared__ __align__(16) double sB[2][3][BC * LD];
 
     const int64_t tile = xcd_tile(blockIdx.x, L.total);
     const int q = locate(L, tile).q;
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(256) void k_cgemm_f64(CgemmList L, int64_t kchunk, 
     const int64_t per = MBEM_PICK(L, q, tiles);
     const int64_t tn_count = MBEM_PICK(L, q, tn);
     const int64_t bidx = t / per, r = t % per;
-    const int64_t m0 = (r / tn_count) * BM, n0 = (r % tn_count) * BN;
+    const int64_t m0 = (r / tn_count) * BM, b0 = (r % tn_count) * BC;
     const int64_t M = MBEM_PICK(L, q, M), Nb = MBEM_PICK(L, q, Nb), Kall = MBEM_PICK(L, q, K);
     const int64_t lda = MBEM_PICK(L, q, lda), ldb = MBEM_PICK(L, q, ldb), ldc = MBEM_PICK(L, q, ldc);
     const TA *A = (const TA *)MBEM_PICK(L, q, A) + bidx * MBEM_PICK(L, q, sa);
@@ -226,14 +227,13 @@ __global__ __launch_bounds__(256) void k_cgemm_f64(CgemmList L, int64_t kchunk, 
     double2 *C = (double2 *)MBEM_PICK(L, q, C) + bidx * MBEM_PICK(L, q, sc) + blockIdx.y * split_stride;
     const int64_t kbeg = blockIdx.y * kchunk;
     const int64_t K = std::min(Kall, kbeg + kchunk);
-    const int64_t b0 = n0 / 2;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int g = lane >> 4, l16 = lane & 15;
 
-    // per stage: A 64 rows x 8 complex, B 32 rows x 8 complex; a thread
-    // loads two complex numbers of A (one row, adjacent k) and one of B
+    // per stage: A 64 rows x 8 complex (two adjacent k per thread), B 32
+    // rows x 8 complex (one per thread)
     double ra[4], rb[2];
     auto ld1 = [](const auto *p, int64_t kc, int64_t Kend, double *o) {
         if (kc < Kend) { o[0] = (double)p[kc].x; o[1] = (double)p[kc].y; }
@@ -256,31 +256,36 @@ __global__ __launch_bounds__(256) void k_cgemm_f64(CgemmList L, int64_t kchunk, 
             else { rb[0] = rb[1] = 0.0; }
         }
     };
+    // complex k of the stage -> position 2 (k & 3) + (k >> 2): lane g reads
+    // the two k = g, 4 + g of its MFMA steps with one 16-byte load
+    auto pos = [](int k) { return 2 * (k & 3) + (k >> 2); };
     auto sstore = [&](int buf) {
         {
-            const int row = tid >> 2, k4 = 4 * (tid & 3);
-            double *d = &sA[buf][row * LD + k4];
-            *(f64x2 *)d = f64x2{ra[0], ra[1]};
-            *(f64x2 *)(d + 2) = f64x2{ra[2], ra[3]};
+            const int row = tid >> 2, kq = 2 * (tid & 3);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const double ar = ra[2 * u], ai = CONJ ? -ra[2 * u + 1] : ra[2 * u + 1];
+                const int o = row * LD + pos(kq + u);
+                sA[buf][0][o] = ar + ai;
+                sA[buf][1][o] = ar;
+                sA[buf][2][o] = ai;
+            }
         }
         {
-            const int row = tid >> 3, k2 = 2 * (tid & 7);
+            const int row = tid >> 3, kq = tid & 7;
+            const int o = row * LD + pos(kq);
             const double br = rb[0], bi = rb[1];
-            if (CONJ) {
-                *(f64x2 *)&sB[buf][(2 * row) * LD + k2] = f64x2{br, bi};
-                *(f64x2 *)&sB[buf][(2 * row + 1) * LD + k2] = f64x2{bi, -br};
-            } else {
-                *(f64x2 *)&sB[buf][(2 * row) * LD + k2] = f64x2{br, -bi};
-                *(f64x2 *)&sB[buf][(2 * row + 1) * LD + k2] = f64x2{bi, br};
-            }
+            sB[buf][0][o] = br;
+            sB[buf][1][o] = bi - br;
+            sB[buf][2][o] = br + bi;
         }
     };
 
-    f64x4 acc[2][2];
+    f64x4 acc[3][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int p3 = 0; p3 < 3; ++p3)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int i = 0; i < 2; ++i) acc[p3][i] = f64x4{0.0, 0.0, 0.0, 0.0};
 
     const int64_t nst = K > kbeg ? (K - kbeg + 7) / 8 : 0;
     if (nst > 0) {
@@ -291,51 +296,44 @@ __global__ __launch_bounds__(256) void k_cgemm_f64(CgemmList L, int64_t kchunk, 
     for (int64_t st = 0; st < nst; ++st) {
         const int cur = (int)(st & 1);
         if (st + 1 < nst) gload(kbeg + (st + 1) * 8);
-        // lane (l16, g) feeds MFMA step s with real k = 4 g + s of the stage
-        f64x4 a[2], b[2];
+        // lane (l16, g) feeds MFMA step s with complex k = 4 s + g of the stage
+        f64x2 a[3][2], bb[3];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const double *src = &sA[cur][(wm * WM + i * 16 + l16) * LD + 4 * g];
-            const f64x2 x0 = *(const f64x2 *)src, x1 = *(const f64x2 *)(src + 2);
-            a[i] = f64x4{x0.x, x0.y, x1.x, x1.y};
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const double *src = &sB[cur][(wn * WN + j * 16 + l16) * LD + 4 * g];
-            const f64x2 x0 = *(const f64x2 *)src, x1 = *(const f64x2 *)(src + 2);
-            b[j] = f64x4{x0.x, x0.y, x1.x, x1.y};
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int p3 = 0; p3 < 3; ++p3) {
 #pragma unroll
             for (int i = 0; i < 2; ++i)
+                a[p3][i] = *(const f64x2 *)&sA[cur][p3][(wm * WM + i * 16 + l16) * LD + 2 * g];
+            bb[p3] = *(const f64x2 *)&sB[cur][p3][(wn * WC + l16) * LD + 2 * g];
+        }
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+            for (int p3 = 0; p3 < 3; ++p3)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    acc[p3][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p3][i][s2], bb[p3][s2], acc[p3][i], 0, 0, 0);
         if (st + 1 < nst) sstore(cur ^ 1);
         __syncthreads();
     }
-    // accumulator (lane, e): column l16, row g + 4 e
+    // accumulator (lane, e): complex column l16, row g + 4 e
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const double v = acc[i][j][e];
-                const double w = __shfl_xor(v, 1);
-                const int64_t m = m0 + wm * WM + i * 16 + g + 4 * e;
-                const int64_t n = n0 + wn * WN + j * 16 + l16;
-                if ((l16 & 1) == 0 && m < M && (n >> 1) < Nb) {
-                    double2 *c = C + (n >> 1) * ldc + m;
-                    if (rmw) {
-                        const double2 o = *c;
-                        *c = double2{o.x + alpha * v, o.y + alpha * w};
-                    } else {
-                        *c = double2{alpha * v, alpha * w};
-                    }
+        for (int e = 0; e < 4; ++e) {
+            const int64_t m = m0 + wm * WM + i * 16 + g + 4 * e;
+            const int64_t b = b0 + wn * WC + l16;
+            if (m < M && b < Nb) {
+                const double t1 = acc[0][i][e], t2 = acc[1][i][e], t3 = acc[2][i][e];
+                const double v = t1 - t3, w = t1 + t2;
+                double2 *c = C + b * ldc + m;
+                if (rmw) {
+                    const double2 o = *c;
+                    *c = double2{o.x + alpha * v, o.y + alpha * w};
+                } else {
+                    *c = double2{alpha * v, alpha * w};
                 }
             }
+        }
 }
 
 // Sum of the k-split partial products (compact [split][batch][Nb][M]) into
