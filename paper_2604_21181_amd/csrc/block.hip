@@ -1025,7 +1025,17 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
     double t_gemm = 0.0;
     int n_gemm = 0;
 
-    std::vector<double> bn(ncol), rn(ncol), resh(ncol);
+    std::vector<double> bn(ncol), rn(ncol);
+    // the per-iteration residual norms come back through pinned memory
+    double *resh = nullptr;
+    MBEM_HIP(hipHostMalloc((void **)&resh, sizeof(double) * ncol, hipHostMallocDefault));
+    struct PinnedFree {
+        double *p;
+        hipStream_t st;
+        ~PinnedFree() {
+            if (p) { (void)hipStreamSynchronize(st); (void)hipHostFree(p); }
+        }
+    } resh_guard{resh, s};
     MBEM_TRY(zero(X, (int64_t)ncol * N, s));
     hipLaunchKernelGGL(k_colnorm, dim3(ncol), dim3(256), 0, s, N, flat((void *)B, N), w.res);
     MBEM_HIP(hipGetLastError());
@@ -1081,7 +1091,7 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
             hipLaunchKernelGGL(k_bqr_factor, dim3(w.nblk), dim3(256), 0, s, p, k, hk, ldh, ldh * w.m * p, w.refl,
                                w.tau, (int64_t)w.m * p * (p + 1), (int64_t)w.m * p, w.g, ldh, ldh * p, w.res);
             MBEM_HIP(hipGetLastError());
-            MBEM_HIP(hipMemcpyAsync(resh.data(), w.res, sizeof(double) * ncol, hipMemcpyDeviceToHost, s));
+            MBEM_HIP(hipMemcpyAsync(resh, w.res, sizeof(double) * ncol, hipMemcpyDeviceToHost, s));
             MBEM_HIP(hipStreamSynchronize(s));
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, ea, eb) == hipSuccess) { t_gemm += ms; ++n_gemm; }
