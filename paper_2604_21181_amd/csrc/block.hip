@@ -216,38 +216,25 @@ int mbj_apply_multi_mfma(const mbem_op *op, ColMap vin, ColMap out, int ncol, bo
 //          y_m = K2^mu x_j + c_mu M x_j - (i/w) K1 x_m.
 // RESID: y = b - Z x instead.
 struct ZCoef { double2 iw, ce, cm; };
-constexpr int kBcLanes = 8;
 template <typename TT, typename TX, bool RESID>
 __global__ void k_block_combine(int64_t n2, int ncol, const TT *T, const int32_t *__restrict__ mptr,
                                 const int32_t *__restrict__ mcol, const double *__restrict__ mval, ZCoef cf,
                                 ColMap xin, ColMap bin, ColMap yout) {
-    // kBcLanes consecutive lanes per (column, row) split the row's mass
-    // slots (each a dependent index-then-value gather) and add their
-    // partial sums by shuffles in a fixed order
-    const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t id = gt / kBcLanes;
-    const int l = (int)(gt % kBcLanes);
-    const bool on = id < n2 * ncol;
-    const int64_t c = on ? id / n2 : 0, r = on ? id % n2 : 0;
+    const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= n2 * ncol) return;
+    const int64_t c = id / n2, r = id % n2;
     const TX *x = col_ptr<const TX>(xin, c);
     const int64_t i = r / 2;
     const int al = (int)(r % 2);
     double2 Mj = {0, 0}, Mm = {0, 0};
-    if (on)
-        for (int32_t s = mptr[i] + l; s < mptr[i + 1]; s += kBcLanes) {
-            const int64_t col = 2 * (int64_t)mcol[s];
-            const double v0 = mval[4 * s + 2 * al], v1 = mval[4 * s + 2 * al + 1];
-            const double2 xj0 = ld2(x, col), xm0 = ld2(x, n2 + col);
-            const double2 xj1 = ld2(x, col + 1), xm1 = ld2(x, n2 + col + 1);
-            Mj.x += v0 * xj0.x + v1 * xj1.x; Mj.y += v0 * xj0.y + v1 * xj1.y;
-            Mm.x += v0 * xm0.x + v1 * xm1.x; Mm.y += v0 * xm0.y + v1 * xm1.y;
-        }
-#pragma unroll
-    for (int o = kBcLanes / 2; o > 0; o >>= 1) {
-        Mj.x += __shfl_xor(Mj.x, o, kBcLanes); Mj.y += __shfl_xor(Mj.y, o, kBcLanes);
-        Mm.x += __shfl_xor(Mm.x, o, kBcLanes); Mm.y += __shfl_xor(Mm.y, o, kBcLanes);
+    for (int32_t s = mptr[i]; s < mptr[i + 1]; ++s) {
+        const int64_t col = 2 * (int64_t)mcol[s];
+        const double v0 = mval[4 * s + 2 * al], v1 = mval[4 * s + 2 * al + 1];
+        const double2 xj0 = ld2(x, col), xm0 = ld2(x, n2 + col);
+        const double2 xj1 = ld2(x, col + 1), xm1 = ld2(x, n2 + col + 1);
+        Mj.x += v0 * xj0.x + v1 * xj1.x; Mj.y += v0 * xj0.y + v1 * xj1.y;
+        Mm.x += v0 * xm0.x + v1 * xm1.x; Mm.y += v0 * xm0.y + v1 * xm1.y;
     }
-    if (!on || l != 0) return;
     const TT *T1 = T, *T2 = T + 2 * ncol * n2, *T3 = T2 + ncol * n2;
     const double2 a = ld2(T1, (2 * c) * n2 + r), bm = ld2(T1, (2 * c + 1) * n2 + r);
     const double2 e = ld2(T2, c * n2 + r), u = ld2(T3, c * n2 + r);
@@ -948,10 +935,9 @@ static int block_residual(const mbem_op *op, BlockWork &w, const double2 *X, con
     MBEM_TRY(cgemm_f64_run(L, op->prec == MBEM_MIXED, false, 1, nullptr, s));
     const mbem_mesh *m = op->mesh;
     const int64_t tot = n2 * w.ncol;
-    const unsigned gb = (unsigned)((tot * kBcLanes + 255) / 256);
-    hipLaunchKernelGGL((k_block_combine<double2, double2, true>), dim3(gb), dim3(256), 0, s, n2, w.ncol,
-                       (const double2 *)w.T64, m->d_mptr, m->d_mcol, op->d_mval, zcoef(op), flat((void *)X, N),
-                       flat((void *)B, N), flat(R, N));
+    hipLaunchKernelGGL((k_block_combine<double2, double2, true>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       s, n2, w.ncol, (const double2 *)w.T64, m->d_mptr, m->d_mcol, op->d_mval, zcoef(op),
+                       flat((void *)X, N), flat((void *)B, N), flat(R, N));
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
@@ -1065,7 +1051,7 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
             MBEM_TRY(cgemm_f32_run(L32, cfg, s));
             MBEM_HIP(hipEventRecord(eb, s));
             const ColMap Wk = w.vcol(k + 1);
-            hipLaunchKernelGGL((k_block_combine<float2, float2, false>), dim3((unsigned)((tot * kBcLanes + 255) / 256)),
+            hipLaunchKernelGGL((k_block_combine<float2, float2, false>), dim3((unsigned)((tot + 255) / 256)),
                                dim3(256), 0, s, n2, ncol, (const float2 *)w.T32, mesh->d_mptr, mesh->d_mcol,
                                op->d_mval, zcoef(op), Zcols, Zcols, Wk);
             MBEM_HIP(hipGetLastError());
