@@ -259,6 +259,32 @@ def test_invalid_mesh_is_rejected():
         mbem.mbem_ctx_destroy(ctx)
 
 
+def test_singular_preconditioner_block_reports_esingular():
+    """A triangle collapsed onto one of its vertices (all six nodes at one
+    point) leaves the mesh a closed, consistently oriented P2 surface by
+    index, so validation accepts it, but that triangle has no normal and its
+    rows and columns of Z are not finite.  The block-Jacobi factorisation of
+    the block that holds its nodes then finds no usable pivot and reports
+    MBEM_ESINGULAR, on the one-workgroup path (2B < 128) and on the
+    whole-chip path (2B >= 128)."""
+    mbem = _mbem()
+    xyz, tri = icosphere_p2(80)
+    xyz = xyz.copy()
+    t = tri[0]
+    for k in range(1, 6):
+        xyz[t[k]] = xyz[t[0]]
+    S = mbem.Solver(xyz, tri, 1.0, 4.0)
+    try:
+        S.fill()
+        for B in (50, 128):
+            with pytest.raises(mbem.MbemError) as e:
+                S.precond_setup(B)
+            assert e.value.code == mbem.MBEM_ESINGULAR, (B, e.value.code)
+            assert "zero pivot" in str(e.value)
+    finally:
+        S.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_solve_status_codes(case, prec):
     """The solve accepts an iterate only when its explicit residual meets
