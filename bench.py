@@ -219,7 +219,7 @@ def tol_sweep(S, khat, pol, rdirs, Fref, block, reps=3):
     for tol in TOL_LADDER:
         times = []
         for _ in range(reps):
-            x, st, code = S.solve(b, tol=tol, maxit=800, inner_tol=max(tol, 1e-4))
+            x, st, code = S.solve(b, tol=tol, maxit=800)
             times.append(st.t_solve_ms)
         F = S.farfield(x, rdirs).cpu().numpy()[0]
         err = float(np.linalg.norm(F - Fref) / np.linalg.norm(Fref))
@@ -254,7 +254,7 @@ def spheroid_pass(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3
             fs = [S.fill() for _ in range(reps)]
             ps = S.precond_setup(c["mbj_block"])
             b = S.rhs(kh, po)
-            sols = [S.solve(b, tol=c["tol"], maxit=1000, inner_tol=1e-4) for _ in range(reps)]
+            sols = [S.solve(b, tol=c["tol"], maxit=1000) for _ in range(reps)]
             x, st, code = sols[-1]
             Fp = S.farfield(x, rdirs).cpu().numpy()[0]
             rec = {"t_fill_ms": float(np.mean([f.t_fill_ms for f in fs])),
@@ -266,7 +266,7 @@ def spheroid_pass(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3
                    "t_solve_ms": float(np.mean([s[1].t_solve_ms for s in sols])),
                    "iters": int(st.iters), "sweeps": int(st.outer_iters), "rel_resid": float(st.rel_resid),
                    "converged": code == 0, "n_near_pairs": int(fs[-1].n_near_pairs), "near_store": store}
-            xt, stt, codet = S.solve(b, tol=1e-10, maxit=1000, inner_tol=1e-4)
+            xt, stt, codet = S.solve(b, tol=1e-10, maxit=1000)
             F[name + "@1e-10"] = S.farfield(xt, rdirs).cpu().numpy()[0]
             rec["iters_at_1e-10"] = int(stt.iters)
             F[name] = Fp
@@ -449,7 +449,7 @@ def frame_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3, 
         try:
             fs = [S.fill() for _ in range(reps + 1)][1:]
             S.precond_setup(c["mbj_block"])
-            x, st, code = S.solve(S.rhs(kh, po), tol=c["tol"], maxit=600, inner_tol=1e-4)
+            x, st, code = S.solve(S.rhs(kh, po), tol=c["tol"], maxit=600)
             F[name] = S.farfield(x, rdirs).cpu().numpy()[0]
             cs = S.cross_sections(x[0], kh[0], po[0])
             out["unknowns"] = S.N
@@ -520,7 +520,7 @@ def quad_study(mbem, get_config, icosphere_p2, planewaves, rdirs, log, reps=3):
         try:
             fs = [S.fill() for _ in range(reps + 1)][1:]
             S.precond_setup(c["mbj_block"])
-            x, st, code = S.solve(S.rhs(kh, po), tol=c["tol"], maxit=600, inner_tol=1e-4)
+            x, st, code = S.solve(S.rhs(kh, po), tol=c["tol"], maxit=600)
             F[name] = S.farfield(x, rdirs).cpu().numpy()[0]
             out["unknowns"] = S.N
             out[name] = {"t_fill_ms": float(np.mean([f.t_fill_ms for f in fs])),
@@ -601,7 +601,7 @@ def main():
             fs = S.fill()
             ps = S.precond_setup(cfg["mbj_block"])
             b = S.rhs(khat, pol)
-            x, ss, code = S.solve(b, tol=cfg["tol"], maxit=600, inner_tol=1e-4)
+            x, ss, code = S.solve(b, tol=cfg["tol"], maxit=600)
             F = S.farfield(x, rdirs)
             out[p] = dict(fill=fs.as_dict(), setup_ms=ps.t_setup_ms, solve=ss.as_dict(), code=code,
                           F=F, x=x)
@@ -760,7 +760,7 @@ def main():
         t0 = time.perf_counter()
         its = 0
         for c in range(nr):
-            xs, ss, code = Smr.solve(mr["b"][c], tol=mcfg["tol"], maxit=600, inner_tol=1e-4)
+            xs, ss, code = Smr.solve(mr["b"][c], tol=mcfg["tol"], maxit=600)
             its += ss.iters
         torch.cuda.synchronize()
         t_seq = 1e3 * (time.perf_counter() - t0)

@@ -144,7 +144,7 @@ typedef struct {
                             from the explicit residual when the Arnoldi
                             estimate met tol but the explicit residual did
                             not (0 -> 3)                                     */
-    double inner_tol;    /* MIXED: inner GMRES tolerance (0 -> 1e-4)          */
+    double inner_tol;    /* MIXED: inner GMRES tolerance (0 -> max(tol, 1e-8)) */
 } mbem_solve_opts;
 
 typedef struct {

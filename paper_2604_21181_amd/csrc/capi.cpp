@@ -744,9 +744,13 @@ static int solve_impl(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nr
                 MBEM_TRY(residual(bc, xc, &rn));
             }
         } else {
-            // iterative refinement: x += GMRES(Z, b - Z x), residual in FP64
+            // iterative refinement: x += GMRES(Z, b - Z x), residual in FP64.
+            // By default the first sweep aims at tol itself (floored at 1e-8,
+            // about where the complex64 products stop reducing the Arnoldi
+            // residual): one longer Krylov space costs fewer products than
+            // restarting from the refined residual.
             const int maxref = o->max_refine > 0 ? o->max_refine : 8;
-            const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
+            const double itol = o->inner_tol > 0 ? o->inner_tol : std::max(o->tol, 1e-8);
             MBEM_HIP(hipMemsetAsync(xc, 0, sizeof(double2) * N, s));
             MBEM_HIP(hipMemcpyAsync(r, bc, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
             rn = bn;

@@ -241,7 +241,7 @@ def test_spheroid5120_mixed_entries_and_solve():
         S.precond_setup(cfg["mbj_block"])
         kh, pol = planewaves("spheroid5120")
         b = S.rhs(kh, pol)
-        x, sst, code = S.solve(b, tol=cfg["tol"], maxit=800, inner_tol=1e-4)
+        x, sst, code = S.solve(b, tol=cfg["tol"], maxit=800)
         print(f"  iterations {sst.iters}, sweeps {sst.outer_iters}, residual {sst.rel_resid:.2e}",
               flush=True)
         assert code == 0 and sst.rel_resid <= cfg["tol"]

@@ -290,7 +290,9 @@ def test_solve_status_codes(case, prec):
     """The solve accepts an iterate only when its explicit residual meets
     tol: one GMRES iteration (and one refinement sweep) cannot, so the call
     returns MBEM_ENOCONV with the residual it reached; a zero right-hand side
-    gives x = 0; a non-finite one is rejected before anything is solved."""
+    gives x = 0; a non-finite one is rejected before anything is solved.
+    The mixed path's first refinement sweep aims at tol (floored at 1e-8)
+    unless an inner tolerance is given."""
     import torch
     mbem = _mbem()
     S = case["S"] if prec == "fp64" else mbem.Solver(case["xyz"], case["tri"], case["k0"], case["eps"],
@@ -305,6 +307,15 @@ def test_solve_status_codes(case, prec):
         assert torch.isfinite(x).all()
         x, st, code = S.solve(b, tol=1e-10, maxit=300, inner_tol=1e-6)
         assert code == mbem.MBEM_OK and st.rel_resid <= 1e-10, (code, st.rel_resid)
+        if prec == "mixed":
+            # by default the first sweep aims at tol itself; a loose explicit
+            # inner tolerance is honoured and takes several sweeps
+            x6, s6, c6 = S.solve(b, tol=1e-6, maxit=300)
+            xl, sl, cl = S.solve(b, tol=1e-6, maxit=300, inner_tol=1e-2)
+            assert c6 == cl == mbem.MBEM_OK and max(s6.rel_resid, sl.rel_resid) <= 1e-6
+            assert sl.outer_iters >= 3 and s6.outer_iters < sl.outer_iters, (s6.outer_iters, sl.outer_iters)
+            x8, s8, c8 = S.solve(b, tol=1e-11, maxit=300)
+            assert c8 == mbem.MBEM_OK and s8.rel_resid <= 1e-11 and s8.outer_iters >= 2
         z = torch.zeros_like(b)
         x, st, code = S.solve(z, tol=1e-10, maxit=10)
         assert code == mbem.MBEM_OK and st.rel_resid == 0 and not x.abs().any()
