@@ -89,7 +89,7 @@ PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix cores
 # kernel changed after its counters were taken gets None here.
 MEASURED_TRAFFIC = {
     ("k_regular", "fp64"): 23.35e9,     # 15.42 GB read + 7.93 GB written per fill
-    ("k_regular", "mixed"): 15.72e9,    # 10.07 GB read + 5.65 GB written per fill
+    ("k_regular_range", "mixed"): 6.65e9,   # 3.04 GB read + 3.61 GB written per fill
     ("k_gemv3", "fp64"): 1.291e9,
     ("k_gemv3", "mixed"): 0.683e9,
 }
@@ -696,9 +696,10 @@ def main():
                 flops = regular_fill_flops(solvers[kp], tri, r["n_regular"])
                 achieved = flops / (r["t_regular_ms"] * 1e-3) / 1e12
                 peak = PEAK_FP64_VALU if kp == "fp64" else PEAK_FP32_VALU
+                kern = "k_regular" if kp == "fp64" else "k_regular_range"
                 return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                        "frac": achieved / peak, "traffic": MEASURED_TRAFFIC.get(("k_regular", kp)),
-                        "kernel": "k_regular", "path": kp,
+                        "frac": achieved / peak, "traffic": MEASURED_TRAFFIC.get((kern, kp)),
+                        "kernel": kern, "path": kp,
                         "algorithmic_flops_per_launch": flops, "launch_ms": r["t_regular_ms"]}
             S = solvers[kp]
             ncoinc, nedge, nvert = S.n_singular

@@ -1,13 +1,17 @@
 // Galerkin fill of K1, K2^eps, K2^mu (Sec. 4.1-4.2, fused as in Sec. 6.1)
 // and of the mass matrix (eq. mass_matrix).
 //
-//  * regular pairs: 7 x 7 quadrature-point pairs per element pair; one
-//    workgroup per (test triangle, chunk of 4 Morton-consecutive trial
-//    triangles), one launch per (test colour, chunk colour) so that the
-//    workgroups of a launch own disjoint rows x columns of Z; the twelve
-//    weighted kernel values of every point pair go to LDS and are contracted
-//    with the shape functions in two steps (trial side, then test side after
-//    the chunk's triangles are merged by node) before being added to Z;
+//  * regular pairs: 7 x 7 quadrature-point pairs per element pair; the
+//    twelve weighted kernel values of every point pair go to LDS and are
+//    contracted with the shape functions in two steps (trial side, then test
+//    side after the triangles are merged by node) before being added to Z.
+//    FP64 (k_regular): one workgroup per (test triangle, chunk of 4
+//    Morton-consecutive trial triangles), one launch per (test colour, chunk
+//    colour) so that the workgroups of a launch own disjoint rows x columns
+//    of Z.  complex64 (k_regular_range): one workgroup per (test triangle,
+//    range of 64 consecutive trial nodes), one launch per test colour, the
+//    node sums held in registers over all trial triangles of the range so
+//    that each entry is updated once per test triangle;
 //  * singular pairs (coincident, common edge, common vertex): Sauter-Schwab
 //    quadrature, 6 / 5 / 2 regions x n^4 Gauss points, two wavefronts per
 //    pair, FP64;
@@ -451,6 +455,226 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
             dst[1] = oim + (TS)acc.im;
         }
     }
+}
+
+// ------------------------------------ regular pairs by column range ---
+// One workgroup per (test triangle e, range J of consecutive trial nodes);
+// one launch per test colour, so that the workgroups of a launch write
+// disjoint rows (test colour) x columns (ranges) of Z.  The workgroup walks
+// the trial triangles that touch J in batches:
+//  A: one point pair per lane: twelve weighted kernel values (as k_regular);
+//  B: trial-side contraction per triangle, in place (as k_regular);
+//  C: every lane owns one (node j of J, beta) and OWN row groups
+//     g = 2 op + alpha, and adds the batch's incidences of j to its OWN x 7
+//     point sums Y[g][p] += Tf[2 g + beta][f][p][loc] (node merge);
+// after the last batch the lanes contract their sums with the test shape
+// functions and add them to Z: each entry of the workgroup's 6 x 6 rows
+// and 2 |J| columns is read and written once, in runs of 2 |J| consecutive
+// entries per row.  A triangle touching several ranges is evaluated once
+// per range (about 1.7 times on average for ranges of 64 nodes of a
+// Morton-ordered mesh); in exchange the trial chunks' colours and their
+// separate read-modify-write passes over Z are gone.
+//   mode 0: every regular pair;
+//   mode 1: complex64 operator without a near store: far pairs in FP32,
+//           near pairs evaluated in FP64 (the kernel differences cancel)
+//           and rounded, by a routine that is not inlined so that the
+//           kernel keeps the register budget of the FP32 evaluations;
+//   mode 3: the pairs the near mask leaves (the far pairs, with a store).
+template <typename T, typename TS>
+struct RngArgs {
+    int64_t nt, n2, nn, n_te, nrng, total;
+    const int32_t *te_list;     // this launch's test colour class
+    const T *qp;                // [kQPF][nt*7]
+    const double *qp64;         // FP64 table (near pairs of mode 1)
+    const int32_t *tri;
+    const int32_t *rng_off, *rng_rec;
+    const double *einfo;        // [nt][4]
+    double near_r;
+    int mode;
+    unsigned long long *near_count;
+    const uint8_t *nmask;       // mode 3: [nt][n_chunks] near bits
+    int64_t n_chunks;
+    const KernelConst *K;
+    TS *Z[3];
+};
+
+// The twelve kernel values of one near point pair in FP64 (the kernel
+// differences cancel), rounded to complex64 and stored at dst[c * stride].
+// Not inlined: the FP64 evaluation then does not set the register budget of
+// the FP32 kernel that calls it for its few near pairs.
+__device__ __attribute__((noinline)) void near_pair_values(const KernelConst &K, const double *q64, int64_t nq,
+                                                           int64_t ix, int64_t iy, cx<float> *dst, int stride) {
+    const dvec3 x = qload(q64, nq, QX, ix), n = qload(q64, nq, QN, ix);
+    const dvec3 ta[2] = {qload(q64, nq, QT1, ix), qload(q64, nq, QT2, ix)};
+    const dvec3 sa[2] = {qload(q64, nq, QS1, ix), qload(q64, nq, QS2, ix)};
+    const dvec3 y = qload(q64, nq, QX, iy);
+    const dvec3 tb[2] = {qload(q64, nq, QT1, iy), qload(q64, nq, QT2, iy)};
+    const double ww = q64[(int64_t)QW * nq + ix] * q64[(int64_t)QW * nq + iy];
+    cx<double> kd[12];
+    kappa12<double, false>(K, x, n, ta, sa, y, tb, ww, kd);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) dst[c * stride] = cx<float>{(float)kd[c].re, (float)kd[c].im};
+}
+
+template <int NB>
+struct RngStride {
+    static constexpr int v = ((49 * NB + 14) / 16) * 16 + 1;   // >= 49 NB, = 1 mod 16
+};
+
+template <typename T, typename TS, int THREADS, int WAVES, bool NEAR>
+__global__ __launch_bounds__(THREADS, WAVES) void k_regular_range(RngArgs<T, TS> a) {
+    constexpr RngLayout L = kRng;
+    constexpr int NB = L.nb, RNG = L.rng;
+    constexpr int OWN = 12 * RNG / THREADS;        // row groups per lane
+    constexpr int STR = RngStride<NB>::v;
+    static_assert(OWN * THREADS == 12 * RNG && 6 % OWN == 0, "lanes own whole row groups");
+    static_assert(!NEAR || !std::is_same<T, double>::value, "near pairs are the complex64 fill's");
+    static_assert(49 * NB <= THREADS, "one point pair per lane");
+    __shared__ cx<T> s_r1[12 * STR];
+    __shared__ T s_tp[kQPF * kQP];       // the test triangle's point table, field-major
+    __shared__ int32_t s_rec[L.rec()];
+    __shared__ int32_t s_te[6];
+    __shared__ int s_act[NB];            // 0 skip, 1 regular pair in T, 2 near pair (mode 1)
+    __shared__ KernelConst s_K;
+    const int tid = threadIdx.x;
+    const int64_t tile = xcd_remap(blockIdx.x, a.total);
+    const int64_t e = a.te_list[tile / a.nrng];
+    const int64_t r = tile % a.nrng;
+    stage_kconst(a.K, &s_K, tid, THREADS);
+    const int64_t nq = a.nt * kQP;
+    if (tid < kQPF * kQP) s_tp[tid] = a.qp[(int64_t)(tid / kQP) * nq + e * kQP + tid % kQP];
+    if (tid < 6) s_te[tid] = a.tri[6 * e + tid];
+    // C and the updates of Z: lane (jl, be) of the range, row groups g0 ..
+    const int jl = (tid % (2 * RNG)) >> 1, be = tid & 1, g0 = OWN * (tid / (2 * RNG));
+    const int64_t jglob = r * RNG + jl;
+    // A: this lane's point pair (batch-local triangle fsl, test point pl,
+    // trial point ql)
+    const int fsl = tid / 49, pl = (tid % 49) / 7, ql = tid % 7;
+    const int32_t b0 = a.rng_off[r], b1 = a.rng_off[r + 1];
+
+    // batch b into s_rec and the kind of each of its pairs into s_act;
+    // returns the number of triangles and the set of kinds present
+    auto batch = [&](int32_t b, bool count, int &kinds) -> int {
+        __syncthreads();                  // the previous batch is done with s_r1, s_rec, s_act
+        if (tid < L.rec()) s_rec[tid] = a.rng_rec[(int64_t)b * L.rec() + tid];
+        __syncthreads();
+        const int nbt = s_rec[0];
+        if (tid < nbt) {
+            const int64_t f = s_rec[1 + tid];
+            const int32_t *tf = a.tri + 6 * f;
+            bool act = true;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) act = act && (s_te[i] != tf[j]);
+            int kind = act ? 1 : 0;
+            if (act && a.mode == 1) {
+                const double *ce = a.einfo + 4 * e, *cf = a.einfo + 4 * f;
+                const double dx = ce[0] - cf[0], dy = ce[1] - cf[1], dz = ce[2] - cf[2];
+                if (sqrt(dx * dx + dy * dy + dz * dz) - ce[3] - cf[3] < a.near_r) {
+                    kind = 2;
+                    // counted once per element pair: in the range of its first vertex
+                    if (count && tf[0] / RNG == r) atomicAdd(a.near_count, 1ull);
+                }
+            }
+            if (act && a.mode == 3 && ((a.nmask[e * a.n_chunks + f / kChunk] >> (f % kChunk)) & 1)) kind = 0;
+            s_act[tid] = kind;
+        }
+        __syncthreads();
+        kinds = 0;
+        for (int k = 0; k < nbt; ++k) kinds |= 1 << s_act[k];
+        return nbt;
+    };
+    // B: Tf[c][fs][p][j] = sum_q N_j(q) k, in place over (c, fs, p)
+    auto trial_side = [&](int nbt) {
+        __syncthreads();
+        for (int it = tid; it < 12 * 7 * nbt; it += THREADS) {
+            const int c = it / (7 * nbt), fp = it % (7 * nbt);
+            cx<T> *row = s_r1 + c * STR + 7 * fp;
+            cx<T> kv[7], tfv[6];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) kv[q] = row[q];
+            contract7(kv, tfv);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) row[j] = tfv[j];
+        }
+        __syncthreads();
+    };
+    // C: the batch's incidences of this lane's node into sums v
+    auto merge = [&](cx<T> (&v)[OWN][7]) {
+        const int u1 = s_rec[L.off() + jl + 1];
+        for (int u = s_rec[L.off() + jl]; u < u1; ++u) {
+            const int fl = s_rec[L.inc() + u];
+            const cx<T> *src = s_r1 + (fl >> 3) * 49 + (fl & 7) + (2 * g0 + be) * STR;
+#pragma unroll
+            for (int k = 0; k < OWN; ++k)
+#pragma unroll
+                for (int p = 0; p < 7; ++p) v[k][p] = v[k][p] + src[2 * k * STR + 7 * p];
+        }
+    };
+    // test side: out[i] = sum_p N_i(p) v[g][p], added to row 2 te_i + alpha,
+    // column 2 j + beta of block op.  No other workgroup of this launch
+    // touches these entries; earlier launches completed in stream order.
+    auto add_to_z = [&](const cx<T> (&v)[OWN][7]) {
+#pragma unroll
+        for (int k = 0; k < OWN; ++k) {
+            const int g = g0 + k, op = g >> 1, al = g & 1;
+            cx<T> out[6];
+            contract7(v[k], out);
+            TS *Z = zblock(a.Z, op) + 2 * (2 * jglob + be);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                TS *dst = Z + 2 * (2 * (int64_t)s_te[i] + al) * a.n2;
+                dst[0] += (TS)out[i].re;
+                dst[1] += (TS)out[i].im;
+            }
+        }
+    };
+
+    cx<T> Y[OWN][7];
+#pragma unroll
+    for (int k = 0; k < OWN; ++k)
+#pragma unroll
+        for (int p = 0; p < 7; ++p) Y[k][p] = cx<T>{0, 0};
+    for (int32_t b = b0; b < b1; ++b) {
+        int kinds;
+        const int nbt = batch(b, true, kinds);
+        if (!(kinds & 6)) continue;               // uniform over the workgroup
+        if (tid < 49 * nbt) {
+            cx<T> k[12];
+            const int kind = s_act[fsl];
+            if constexpr (NEAR) {
+                if (kind == 2) {
+                    near_pair_values(s_K, a.qp64, nq, e * kQP + pl, (int64_t)s_rec[1 + fsl] * kQP + ql,
+                                     s_r1 + tid, STR);
+                }
+            }
+            if (kind == 1) {
+                const int64_t iy = (int64_t)s_rec[1 + fsl] * kQP + ql;
+                const T *tp = s_tp + pl;
+                const vec3<T> x = {tp[QX * kQP], tp[(QX + 1) * kQP], tp[(QX + 2) * kQP]};
+                const vec3<T> n = {tp[QN * kQP], tp[(QN + 1) * kQP], tp[(QN + 2) * kQP]};
+                const vec3<T> ta[2] = {{tp[QT1 * kQP], tp[(QT1 + 1) * kQP], tp[(QT1 + 2) * kQP]},
+                                       {tp[QT2 * kQP], tp[(QT2 + 1) * kQP], tp[(QT2 + 2) * kQP]}};
+                const vec3<T> sa[2] = {{tp[QS1 * kQP], tp[(QS1 + 1) * kQP], tp[(QS1 + 2) * kQP]},
+                                       {tp[QS2 * kQP], tp[(QS2 + 1) * kQP], tp[(QS2 + 2) * kQP]}};
+                const vec3<T> y = qload(a.qp, nq, QX, iy);
+                const vec3<T> tb[2] = {qload(a.qp, nq, QT1, iy), qload(a.qp, nq, QT2, iy)};
+                const T ww = tp[QW * kQP] * a.qp[(int64_t)QW * nq + iy];
+                kappa12<T, false>(s_K, x, n, ta, sa, y, tb, ww, k);
+            } else if (kind == 0) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) k[c] = cx<T>{0, 0};
+            }
+            if (kind != 2) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) s_r1[c * STR + tid] = k[c];
+            }
+        }
+        trial_side(nbt);
+        merge(Y);
+    }
+    if (jglob < a.nn) add_to_z(Y);
 }
 
 // --------------------------------------------- Sauter-Schwab pairs ---
@@ -1239,6 +1463,56 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
     return MBEM_OK;
 }
 
+// The regular pairs by column range (k_regular_range): one launch per
+// test colour.
+template <typename T, typename TS>
+static int launch_regular_range(mbem_op *op, int mode, const T *qp, unsigned long long *cnt, hipStream_t s) {
+    const mbem_mesh *m = op->mesh;
+    constexpr int threads = 12 * kRng.rng / 3;
+    // wavefronts per SIMD asked of the compiler: the FP32 kernel fits four
+    // (its FP64 near-pair routine then spills, only on the near pairs' path)
+    constexpr int waves = std::is_same<T, double>::value ? 2 : 4;
+    RngArgs<T, TS> a;
+    a.nt = m->nt;
+    a.n2 = op->n2;
+    a.nn = m->nn;
+    a.nrng = m->nrng;
+    a.qp = qp;
+    a.qp64 = m->d_qp;
+    a.tri = m->d_tri;
+    a.rng_off = m->d_rng_off;
+    a.rng_rec = m->d_rng_rec;
+    a.einfo = m->d_elem;
+    a.near_r = near_radius_of(op);
+    a.mode = mode;
+    a.near_count = cnt;
+    a.nmask = op->d_nmask;
+    a.n_chunks = (m->nt + kChunk - 1) / kChunk;
+    a.K = op->d_kconst;
+    for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)op->K[o];
+    if (mode == 3 && !a.nmask) { set_error("far-pair fill without a near mask"); return MBEM_EINVAL; }
+    if (mode == 1 && (std::is_same<T, double>::value || !cnt)) {
+        set_error("range fill: near pairs need a complex64 operator and a counter");
+        return MBEM_EINVAL;
+    }
+    const int ntc = (int)m->tcol_off.size() - 1;
+    for (int tc = 0; tc < ntc; ++tc) {
+        a.te_list = m->d_tcol + m->tcol_off[tc];
+        a.n_te = m->tcol_off[tc + 1] - m->tcol_off[tc];
+        a.total = a.n_te * a.nrng;
+        if (a.total == 0) continue;
+        if (a.total > 0x7fffffffLL) { set_error("too many workgroups for one launch"); return MBEM_EINVAL; }
+        if (mode == 1)
+            hipLaunchKernelGGL((k_regular_range<T, TS, threads, waves, !std::is_same<T, double>::value>),
+                               dim3((unsigned)a.total), dim3(threads), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_regular_range<T, TS, threads, waves, false>), dim3((unsigned)a.total),
+                               dim3(threads), 0, s, a);
+        MBEM_HIP(hipGetLastError());
+    }
+    return MBEM_OK;
+}
+
 template <typename TS, bool DK = false, bool PAPER = false, bool NODAL = false>
 static int launch_ssq(mbem_op *op, hipStream_t s, const FillBand *band = nullptr) {
     const mbem_mesh *m = op->mesh;
@@ -1387,10 +1661,11 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
         if (nodal) MBEM_TRY((launch_regular<double, double, false, false, true>(op, 0, m->d_qp, nullptr, s)));
         else MBEM_TRY((launch_regular<double, double>(op, 0, m->d_qp, nullptr, s)));
     } else if (store) {
-        MBEM_TRY((launch_regular<float, float>(op, 3, m->d_qp32, nullptr, s)));
+        MBEM_TRY((launch_regular_range<float, float>(op, 3, m->d_qp32, nullptr, s)));
+    } else if (nodal) {
+        MBEM_TRY((launch_regular<float, float, false, false, true>(op, 1, m->d_qp32, cnt, s)));
     } else {
-        if (nodal) MBEM_TRY((launch_regular<float, float, false, false, true>(op, 1, m->d_qp32, cnt, s)));
-        else MBEM_TRY((launch_regular<float, float>(op, 1, m->d_qp32, cnt, s)));
+        MBEM_TRY((launch_regular_range<float, float>(op, 1, m->d_qp32, cnt, s)));
     }
     MBEM_HIP(hipEventRecord(ev[2], s));
     // near pairs: inside the regular launches, or with the near store in a

@@ -311,6 +311,49 @@ int build_tables(const mbem_mesh *m, MeshTables &T) {
         rec[0] = ns;
         rec[25 + ns] = ni;
     }
+    // column ranges: L.rng consecutive nodes; the triangles touching a
+    // range (ascending) in batches of L.nb, and per batch the incidences of
+    // the range's nodes grouped by node
+    {
+        constexpr RngLayout L = kRng;
+        std::vector<int32_t> &off = T.rng_off, &recs = T.rng_rec;
+        const int64_t nrng = (nn + L.rng - 1) / L.rng;
+        off.assign(nrng + 1, 0);
+        recs.clear();
+        std::vector<int32_t> rtris;
+        for (int64_t r = 0; r < nrng; ++r) {
+            const int64_t j0 = r * L.rng, j1 = std::min<int64_t>(nn, j0 + L.rng);
+            rtris.clear();
+            for (int64_t j = j0; j < j1; ++j)
+                for (int32_t q = T.inc_ptr[j]; q < T.inc_ptr[j + 1]; ++q) rtris.push_back(T.inc[q] >> 3);
+            std::sort(rtris.begin(), rtris.end());
+            rtris.erase(std::unique(rtris.begin(), rtris.end()), rtris.end());
+            for (size_t b0 = 0; b0 < rtris.size(); b0 += L.nb) {
+                const size_t base = recs.size();
+                recs.resize(base + L.rec(), 0);
+                int32_t *rec = recs.data() + base;
+                const int nb = (int)std::min<size_t>(L.nb, rtris.size() - b0);
+                std::vector<std::pair<int32_t, int32_t>> uses;   // (range-local node, fb*8 + loc)
+                rec[0] = nb;
+                for (int fb = 0; fb < nb; ++fb) {
+                    const int32_t f = rtris[b0 + fb];
+                    rec[1 + fb] = f;
+                    for (int l = 0; l < 6; ++l) {
+                        const int32_t v = tri[6 * (int64_t)f + l];
+                        if (v >= j0 && v < j1) uses.push_back({(int32_t)(v - j0), fb * 8 + l});
+                    }
+                }
+                std::sort(uses.begin(), uses.end());
+                size_t u = 0;
+                for (int jl = 0; jl <= L.rng; ++jl) {
+                    while (u < uses.size() && uses[u].first < jl) ++u;
+                    rec[L.off() + jl] = (int32_t)u;
+                }
+                for (size_t k = 0; k < uses.size(); ++k) rec[L.inc() + k] = uses[k].second;
+            }
+            off[r + 1] = (int32_t)(recs.size() / L.rec());
+        }
+    }
     // Colour classes (greedy in Morton order, then balanced) so that the
     // regular-pair fill can add to Z with plain read-modify-write: inside one
     // launch no two test triangles share a node (disjoint rows) and no two

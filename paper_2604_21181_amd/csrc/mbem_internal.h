@@ -43,6 +43,18 @@ constexpr int kChunk = 4;       // trial triangles per regular-pair workgroup
 // per trial chunk: n_slots, slot nodes[24], incidence offsets[25],
 // incidences[24] (chunk-local triangle * 8 + local node)
 constexpr int kChunkRec = 1 + 24 + 25 + 24;
+// Column ranges of the regular-pair fill: rng consecutive (Morton) nodes;
+// per range the trial triangles that touch it, in batches of nb, one record
+// of rec() ints per batch: n, triangles[nb], per range-local node
+// the offsets[rng + 1] into incidences[6 nb] (batch-local triangle * 8 +
+// local node) of the nodes of the range.
+struct RngLayout {
+    int rng, nb;
+    constexpr int off() const { return 1 + nb; }
+    constexpr int inc() const { return off() + rng + 1; }
+    constexpr int rec() const { return inc() + 6 * nb; }
+};
+constexpr RngLayout kRng = {64, 5};
 // quadrature-point table fields (structure of arrays, each n_tris*7 long)
 enum QpField {
     QX = 0, QW = 3, QN = 4, QT1 = 7, QT2 = 10, QS1 = 13, QS2 = 16
@@ -105,6 +117,10 @@ struct mbem_mesh {
     std::vector<int32_t> m_ptr, m_col;
     int32_t *d_mptr = nullptr, *d_mcol = nullptr, *d_mslot = nullptr;
     int32_t *d_chunks = nullptr;   // trial-chunk records, kChunkRec ints each
+    // column ranges: batch records (kRng.rec() ints each) and, per range,
+    // the first record (one more than ranges)
+    int64_t nrng = 0;
+    int32_t *d_rng_off = nullptr, *d_rng_rec = nullptr;
     // colour classes of the race-free regular-pair fill, and the class of
     // every test triangle and trial chunk
     std::vector<int32_t> tcol_off, ccol_off;
@@ -183,6 +199,7 @@ struct MeshTables {
     int64_t n_single[4] = {0, 0, 0, 0};
     std::vector<int32_t> m_ptr, m_col, m_slot;
     std::vector<int32_t> chunks;            // kChunkRec ints per trial chunk
+    std::vector<int32_t> rng_off, rng_rec;  // column ranges: first record, records
     // colour classes: test triangles sharing no node, trial chunks sharing
     // no node (offsets into the concatenated lists, one more than classes)
     std::vector<int32_t> tcol_list, tcol_off, ccol_list, ccol_off;

@@ -6,12 +6,14 @@
 // runs mesh validation, the double Morton permutation and the table build
 // (incidence, singular pairs, mass pattern, trial chunks, colour classes),
 // checks the invariants of the colour classes (every item in exactly one
-// class; no two items of a class share a node), runs the rejection paths
+// class; no two items of a class share a node) and of the column ranges of
+// the regular-pair fill, runs the rejection paths
 // on corrupted copies, and writes node_order[nn], tri_order[nt] (int64) and
 // the four singular-pair counts to the output file.  Exit status 0 = every
 // check held.
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <limits>
 #include <set>
@@ -94,6 +96,46 @@ int main(int argc, char **argv) {
             for (int a = 0; a < 6; ++a) out.push_back(m.tri[6 * t + a]);
     };
     if (check_classes(T.ccol_list, T.ccol_off, nch, chunk_nodes, "trial-chunk colour classes")) return 1;
+    // column ranges: the batches of a range hold exactly the triangles that
+    // touch it, ascending, and every (triangle, local node) incidence of a
+    // node of the range once, under that node
+    {
+        const RngLayout L = kRng;
+        const int64_t nrng = (nn + L.rng - 1) / L.rng;
+        if ((int64_t)T.rng_off.size() != nrng + 1 || T.rng_off[0] != 0 ||
+            (int64_t)T.rng_rec.size() != (int64_t)T.rng_off.back() * L.rec())
+            return fail("column-range offsets");
+        for (int64_t r = 0; r < nrng; ++r) {
+            const int64_t j0 = r * L.rng, j1 = std::min<int64_t>(nn, j0 + L.rng);
+            std::set<int32_t> want;
+            int64_t want_inc = 0;
+            for (int64_t t = 0; t < nt; ++t)
+                for (int k = 0; k < 6; ++k)
+                    if (m.tri[6 * t + k] >= j0 && m.tri[6 * t + k] < j1) { want.insert((int32_t)t); ++want_inc; }
+            std::vector<int32_t> got;
+            int64_t got_inc = 0;
+            for (int32_t b = T.rng_off[r]; b < T.rng_off[r + 1]; ++b) {
+                const int32_t *rec = T.rng_rec.data() + (int64_t)b * L.rec();
+                const int nb = rec[0];
+                if (nb < 1 || nb > L.nb) return fail("column-range batch size");
+                for (int fb = 0; fb < nb; ++fb) got.push_back(rec[1 + fb]);
+                if (rec[L.off()] != 0) return fail("column-range incidence offsets");
+                for (int jl = 0; jl < L.rng; ++jl) {
+                    if (rec[L.off() + jl + 1] < rec[L.off() + jl] || rec[L.off() + jl + 1] > 6 * nb)
+                        return fail("column-range incidence offsets");
+                    for (int32_t u = rec[L.off() + jl]; u < rec[L.off() + jl + 1]; ++u) {
+                        const int fl = rec[L.inc() + u], fb = fl >> 3, loc = fl & 7;
+                        if (fb >= nb || loc > 5 || m.tri[6 * (int64_t)rec[1 + fb] + loc] != j0 + jl)
+                            return fail("column-range incidence");
+                        ++got_inc;
+                    }
+                }
+            }
+            if (!std::is_sorted(got.begin(), got.end()) || std::set<int32_t>(got.begin(), got.end()) != want ||
+                got.size() != want.size() || got_inc != want_inc)
+                return fail("column-range triangles");
+        }
+    }
     // mass pattern: CSR rows sorted, every column in range
     if ((int64_t)T.m_ptr.size() != nn + 1) return fail("mass pattern rows");
     for (int64_t i = 0; i < nn; ++i)
