@@ -1005,9 +1005,16 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
             ctx->tuned_cfg = cfg;
         }
     }
-    hipEvent_t ea, eb;
-    MBEM_HIP(hipEventCreate(&ea));
-    MBEM_HIP(hipEventCreate(&eb));
+    // the block product's start and end, destroyed on every way out
+    struct Events {
+        hipEvent_t e[2] = {};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } evs;
+    for (hipEvent_t &x : evs.e) MBEM_HIP(hipEventCreate(&x));
+    hipEvent_t ea = evs.e[0], eb = evs.e[1];
     double t_gemm = 0.0;
     int n_gemm = 0;
 
@@ -1110,8 +1117,6 @@ int block_solve_run(mbem_op *op, const double2 *B, int ncol, const mbem_block_op
     }
     int flags = 0;
     MBEM_HIP(hipMemcpy(&flags, w.flags, sizeof(int), hipMemcpyDeviceToHost));
-    (void)hipEventDestroy(ea);
-    (void)hipEventDestroy(eb);
     if (st) {
         st->iters = total_it;
         st->sweeps = sweeps;
