@@ -488,6 +488,7 @@ struct RngArgs {
     const double *qp64;         // FP64 table (near pairs of mode 1)
     const int32_t *tri;
     const int32_t *rng_off, *rng_rec;
+    const int32_t *row_first;   // per triangle: bit a set = first writer of node a's rows
     const double *einfo;        // [nt][4]
     double near_r;
     int mode;
@@ -613,8 +614,12 @@ __global__ __launch_bounds__(THREADS, WAVES) void k_regular_range(RngArgs<T, TS>
         }
     };
     // test side: out[i] = sum_p N_i(p) v[g][p], added to row 2 te_i + alpha,
-    // column 2 j + beta of block op.  No other workgroup of this launch
-    // touches these entries; earlier launches completed in stream order.
+    // column 2 j + beta of block op, or stored there by the first test
+    // triangle (in colour order) of node te_i: every workgroup writes all
+    // its rows x columns, so Z needs no clearing before the fill.  No other
+    // workgroup of this launch touches these entries; earlier launches
+    // completed in stream order.
+    const int first = a.row_first[e];
     auto add_to_z = [&](const cx<T> (&v)[OWN][7]) {
 #pragma unroll
         for (int k = 0; k < OWN; ++k) {
@@ -625,8 +630,13 @@ __global__ __launch_bounds__(THREADS, WAVES) void k_regular_range(RngArgs<T, TS>
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
                 TS *dst = Z + 2 * (2 * (int64_t)s_te[i] + al) * a.n2;
-                dst[0] += (TS)out[i].re;
-                dst[1] += (TS)out[i].im;
+                if ((first >> i) & 1) {
+                    dst[0] = (TS)out[i].re;
+                    dst[1] = (TS)out[i].im;
+                } else {
+                    dst[0] += (TS)out[i].re;
+                    dst[1] += (TS)out[i].im;
+                }
             }
         }
     };
@@ -1482,6 +1492,7 @@ static int launch_regular_range(mbem_op *op, int mode, const T *qp, unsigned lon
     a.tri = m->d_tri;
     a.rng_off = m->d_rng_off;
     a.rng_rec = m->d_rng_rec;
+    a.row_first = m->d_row_first;
     a.einfo = m->d_elem;
     a.near_r = near_radius_of(op);
     a.mode = mode;
@@ -1636,8 +1647,11 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     hipEvent_t *ev = f->ev;
     MBEM_HIP(hipEventRecord(ev[6], s));
     const size_t esz = op->prec == MBEM_FP64 ? 16 : 8;
-    for (int o = 0; o < 3; ++o)
-        MBEM_HIP(hipMemsetAsync(op->K[o], 0, esz * op->n2 * op->n2, s));
+    // the column-range fill (complex64, default scheme and frame) writes
+    // every entry itself; the others add to a cleared Z
+    const bool range_fill = op->prec != MBEM_FP64 && !deriv && !paper && !nodal;
+    if (!range_fill)
+        for (int o = 0; o < 3; ++o) MBEM_HIP(hipMemsetAsync(op->K[o], 0, esz * op->n2 * op->n2, s));
     f->counted = op->prec != MBEM_FP64 && !deriv && !(op->p.near_store && !paper && !nodal);
     if (f->counted) MBEM_HIP(hipMemsetAsync(f->d_cnt, 0, sizeof(unsigned long long), s));
     MBEM_HIP(hipEventRecord(ev[0], s));

@@ -406,6 +406,19 @@ int build_tables(const mbem_mesh *m, MeshTables &T) {
     colour(nt, [&](int64_t e, std::vector<int32_t> &out) {
         for (int k = 0; k < 6; ++k) out.push_back(tri[6 * e + k]);
     }, T.tcol_list, T.tcol_off);
+    {
+        // the triangles of a node have distinct test colours: the lowest one
+        // writes the node's rows first
+        std::vector<int32_t> tcolour(nt), low(nn, INT32_MAX);
+        for (size_t c = 0; c + 1 < T.tcol_off.size(); ++c)
+            for (int32_t q = T.tcol_off[c]; q < T.tcol_off[c + 1]; ++q) tcolour[T.tcol_list[q]] = (int32_t)c;
+        for (int64_t e = 0; e < nt; ++e)
+            for (int k = 0; k < 6; ++k) low[tri[6 * e + k]] = std::min(low[tri[6 * e + k]], tcolour[e]);
+        T.row_first.assign(nt, 0);
+        for (int64_t e = 0; e < nt; ++e)
+            for (int k = 0; k < 6; ++k)
+                if (tcolour[e] == low[tri[6 * e + k]]) T.row_first[e] |= 1 << k;
+    }
     colour(nch, [&](int64_t k, std::vector<int32_t> &out) {
         const int32_t *rec = T.chunks.data() + k * kChunkRec;
         for (int s2 = 0; s2 < rec[0]; ++s2) out.push_back(rec[1 + s2]);

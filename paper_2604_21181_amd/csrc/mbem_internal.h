@@ -121,6 +121,7 @@ struct mbem_mesh {
     // the first record (one more than ranges)
     int64_t nrng = 0;
     int32_t *d_rng_off = nullptr, *d_rng_rec = nullptr;
+    int32_t *d_row_first = nullptr;   // per triangle: first writer of its nodes' rows
     // colour classes of the race-free regular-pair fill, and the class of
     // every test triangle and trial chunk
     std::vector<int32_t> tcol_off, ccol_off;
@@ -200,6 +201,10 @@ struct MeshTables {
     std::vector<int32_t> m_ptr, m_col, m_slot;
     std::vector<int32_t> chunks;            // kChunkRec ints per trial chunk
     std::vector<int32_t> rng_off, rng_rec;  // column ranges: first record, records
+    // per test triangle, bit a: the triangle is the first of its colour
+    // order to write the rows of its local node a (the lowest colour among
+    // the node's triangles)
+    std::vector<int32_t> row_first;
     // colour classes: test triangles sharing no node, trial chunks sharing
     // no node (offsets into the concatenated lists, one more than classes)
     std::vector<int32_t> tcol_list, tcol_off, ccol_list, ccol_off;

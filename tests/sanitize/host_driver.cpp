@@ -136,6 +136,16 @@ int main(int argc, char **argv) {
                 return fail("column-range triangles");
         }
     }
+    // every node's rows have exactly one first writer among its triangles
+    {
+        std::vector<int> firsts(nn, 0);
+        if ((int64_t)T.row_first.size() != nt) return fail("row first writers");
+        for (int64_t e = 0; e < nt; ++e)
+            for (int k = 0; k < 6; ++k)
+                if ((T.row_first[e] >> k) & 1) firsts[m.tri[6 * e + k]]++;
+        for (int64_t v = 0; v < nn; ++v)
+            if (firsts[v] != 1) return fail("row first writers");
+    }
     // mass pattern: CSR rows sorted, every column in range
     if ((int64_t)T.m_ptr.size() != nn + 1) return fail("mass pattern rows");
     for (int64_t i = 0; i < nn; ++i)
