@@ -476,9 +476,9 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
 // separate read-modify-write passes over Z are gone.
 //   mode 0: every regular pair;
 //   mode 1: complex64 operator without a near store: far pairs in FP32,
-//           near pairs evaluated in FP64 (the kernel differences cancel)
-//           and rounded, by a routine that is not inlined so that the
-//           kernel keeps the register budget of the FP32 evaluations;
+//           near pairs with their distance and kernel scalars (where the
+//           two media's terms cancel) in FP64, rounded, and the rest of
+//           their kernel values in FP32;
 //   mode 3: the pairs the near mask leaves (the far pairs, with a store).
 template <typename T, typename TS>
 struct RngArgs {
@@ -498,24 +498,6 @@ struct RngArgs {
     const KernelConst *K;
     TS *Z[3];
 };
-
-// The twelve kernel values of one near point pair in FP64 (the kernel
-// differences cancel), rounded to complex64 and stored at dst[c * stride].
-// Not inlined: the FP64 evaluation then does not set the register budget of
-// the FP32 kernel that calls it for its few near pairs.
-__device__ __attribute__((noinline)) void near_pair_values(const KernelConst &K, const double *q64, int64_t nq,
-                                                           int64_t ix, int64_t iy, cx<float> *dst, int stride) {
-    const dvec3 x = qload(q64, nq, QX, ix), n = qload(q64, nq, QN, ix);
-    const dvec3 ta[2] = {qload(q64, nq, QT1, ix), qload(q64, nq, QT2, ix)};
-    const dvec3 sa[2] = {qload(q64, nq, QS1, ix), qload(q64, nq, QS2, ix)};
-    const dvec3 y = qload(q64, nq, QX, iy);
-    const dvec3 tb[2] = {qload(q64, nq, QT1, iy), qload(q64, nq, QT2, iy)};
-    const double ww = q64[(int64_t)QW * nq + ix] * q64[(int64_t)QW * nq + iy];
-    cx<double> kd[12];
-    kappa12<double, false>(K, x, n, ta, sa, y, tb, ww, kd);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) dst[c * stride] = cx<float>{(float)kd[c].re, (float)kd[c].im};
-}
 
 template <int NB>
 struct RngStride {
@@ -653,33 +635,43 @@ __global__ __launch_bounds__(THREADS, WAVES) void k_regular_range(RngArgs<T, TS>
         if (tid < 49 * nbt) {
             cx<T> k[12];
             const int kind = s_act[fsl];
-            if constexpr (NEAR) {
-                if (kind == 2) {
-                    near_pair_values(s_K, a.qp64, nq, e * kQP + pl, (int64_t)s_rec[1 + fsl] * kQP + ql,
-                                     s_r1 + tid, STR);
-                }
-            }
-            if (kind == 1) {
+            if (kind != 0) {
                 const int64_t iy = (int64_t)s_rec[1 + fsl] * kQP + ql;
                 const T *tp = s_tp + pl;
-                const vec3<T> x = {tp[QX * kQP], tp[(QX + 1) * kQP], tp[(QX + 2) * kQP]};
                 const vec3<T> n = {tp[QN * kQP], tp[(QN + 1) * kQP], tp[(QN + 2) * kQP]};
                 const vec3<T> ta[2] = {{tp[QT1 * kQP], tp[(QT1 + 1) * kQP], tp[(QT1 + 2) * kQP]},
                                        {tp[QT2 * kQP], tp[(QT2 + 1) * kQP], tp[(QT2 + 2) * kQP]}};
                 const vec3<T> sa[2] = {{tp[QS1 * kQP], tp[(QS1 + 1) * kQP], tp[(QS1 + 2) * kQP]},
                                        {tp[QS2 * kQP], tp[(QS2 + 1) * kQP], tp[(QS2 + 2) * kQP]}};
-                const vec3<T> y = qload(a.qp, nq, QX, iy);
                 const vec3<T> tb[2] = {qload(a.qp, nq, QT1, iy), qload(a.qp, nq, QT2, iy)};
                 const T ww = tp[QW * kQP] * a.qp[(int64_t)QW * nq + iy];
-                kappa12<T, false>(s_K, x, n, ta, sa, y, tb, ww, k);
-            } else if (kind == 0) {
+                KScal<T> sc;
+                vec3<T> Rh;
+                if (NEAR && kind == 2) {
+                    // near pair: the distance and the kernel scalars (whose
+                    // two media's terms cancel) in FP64, then rounded
+                    const dvec3 Rv = qload(a.qp64, nq, QX, e * kQP + pl) - qload(a.qp64, nq, QX, iy);
+                    const double R = sqrt(dot(Rv, Rv));
+                    const dvec3 u = (1.0 / R) * Rv;
+                    Rh = {(T)u.x, (T)u.y, (T)u.z};
+                    const KScal<double> sd = kernel_scalars<double>(s_K, R);
+                    sc = {cx<T>{(T)sd.D0.re, (T)sd.D0.im}, cx<T>{(T)sd.df.re, (T)sd.df.im},
+                          cx<T>{(T)sd.dg.re, (T)sd.dg.im}, cx<T>{(T)sd.Ge.re, (T)sd.Ge.im},
+                          cx<T>{(T)sd.Gm.re, (T)sd.Gm.im}};
+                } else {
+                    const vec3<T> x = {tp[QX * kQP], tp[(QX + 1) * kQP], tp[(QX + 2) * kQP]};
+                    const vec3<T> Rv = x - qload(a.qp, nq, QX, iy);
+                    const T R = sqrt(dot(Rv, Rv));
+                    Rh = ((T)1 / R) * Rv;
+                    sc = kernel_scalars<T>(s_K, R);
+                }
+                kappa_combine<T>(sc, Rh, n, ta, sa, tb, ww, k);
+            } else {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) k[c] = cx<T>{0, 0};
             }
-            if (kind != 2) {
 #pragma unroll
-                for (int c = 0; c < 12; ++c) s_r1[c * STR + tid] = k[c];
-            }
+            for (int c = 0; c < 12; ++c) s_r1[c * STR + tid] = k[c];
         }
         trial_side(nbt);
         merge(Y);
@@ -1480,7 +1472,6 @@ static int launch_regular_range(mbem_op *op, int mode, const T *qp, unsigned lon
     const mbem_mesh *m = op->mesh;
     constexpr int threads = 12 * kRng.rng / 3;
     // wavefronts per SIMD asked of the compiler: the FP32 kernel fits four
-    // (its FP64 near-pair routine then spills, only on the near pairs' path)
     constexpr int waves = std::is_same<T, double>::value ? 2 : 4;
     RngArgs<T, TS> a;
     a.nt = m->nt;
