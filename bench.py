@@ -89,7 +89,7 @@ PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix cores
 # kernel changed after its counters were taken gets None here.
 MEASURED_TRAFFIC = {
     ("k_regular", "fp64"): 23.35e9,     # 15.42 GB read + 7.93 GB written per fill
-    ("k_regular_range", "mixed"): 6.65e9,   # 3.04 GB read + 3.61 GB written per fill
+    ("k_regular_range", "mixed"): 3.75e9,   # 1.48 GB read + 2.27 GB written per fill
     ("k_gemv3", "fp64"): 1.291e9,
     ("k_gemv3", "mixed"): 0.683e9,
 }
