@@ -153,6 +153,8 @@ def parse():
                     help="skip the search of the loosest GMRES tolerance meeting 1e-6 far-field error")
     ap.add_argument("--no-spheroid", action="store_true",
                     help="skip the 5120-triangle plasmonic spheroid pass (FP64 and mixed, B = 256)")
+    ap.add_argument("--oracle-one-core", action="store_true",
+                    help="also time the oracle's full fill of the workload on one core (about 40 s)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device to device once (scales the FETCH_SIZE / WRITE_SIZE "
                          "counters) and exit")
@@ -175,16 +177,31 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(xyz, tri, cfg, N, khat, pol, rdirs):
+def cpu_baseline(xyz, tri, cfg, N, khat, pol, rdirs, one_core=False):
     """The FP64 oracle on the host cores: its dense fill of the same mesh
     (timed: the baseline's value), then its dense LU solve (timed) and far
     field at the 360 cut-plane angles, the reference of the accuracy
-    figures.  Returns (baseline record, oracle far field)."""
+    figures; beside it the oracle's fill of the 80-triangle sphere on all
+    threads and on one, and with one_core the workload's fill on one core.
+    Returns (baseline record, oracle far field)."""
     from oracle import core, galerkin
+    from workloads import get_config, icosphere_p2
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
     P = galerkin.Problem(xyz, tri, cfg["k0"], cfg["eps_r"], cfg["mu_r"])
     core.lib()
+    small = {}
+    c1 = get_config("sphere80")
+    x1, t1 = icosphere_p2(c1["n_tris"], c1["axes"])
+    P1 = galerkin.Problem(x1, t1, c1["k0"], c1["eps_r"], c1["mu_r"])
+    for nth in (threads, 1):
+        t0 = time.perf_counter()
+        core.fill(x1, t1, P1.phys, nss=4, nthreads=nth)
+        small[f"sphere80_fill_s_{nth}_threads"] = time.perf_counter() - t0
+    if one_core:
+        t0 = time.perf_counter()
+        core.fill(xyz, tri, P.phys, nss=4, nthreads=1)
+        small["fill_s_1_thread"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     K = core.fill(xyz, tri, P.phys, nss=4, nthreads=threads)
     dt = time.perf_counter() - t0
@@ -200,7 +217,7 @@ def cpu_baseline(xyz, tri, cfg, N, khat, pol, rdirs):
            "sample": f"full FP64 dense fill (K1, K2eps, K2mu, all {tri.shape[0]}^2 element "
                      f"pairs) of the same mesh, {dt:.2f} s",
            "t_fill_s": dt, "t_lu_solve_s": t_lu, "solve": "dense LU (numpy / LAPACK zgesv)",
-           "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
+           "nproc": os.cpu_count(), "cpu_model": _cpu_model(), **small}
     return rec, F
 
 
@@ -725,7 +742,7 @@ def main():
     cpu, Foracle = None, None
     if paths and not args.no_cpu_baseline:
         log("timing the CPU oracle (dense fill, LU solve, far field)")
-        cpu, Foracle = cpu_baseline(xyz, tri, cfg, N, khat, pol, rdirs)
+        cpu, Foracle = cpu_baseline(xyz, tri, cfg, N, khat, pol, rdirs, one_core=args.oracle_one_core)
         for p in paths:
             info[f"farfield_err_{p}_vs_oracle"] = float(np.linalg.norm(ff[p] - Foracle) / np.linalg.norm(Foracle))
     sweeps = None
