@@ -197,6 +197,48 @@ def test_mixed_fill_and_solve(case):
         S.close()
 
 
+def test_mixed_near_pairs_counted_and_forced(case):
+    """Near pairs of the complex64 fill: each regular element pair whose
+    centroid distance minus both bounding radii (1.25 x the largest node
+    distance from the vertex centroid) is below the near radius is counted
+    once, although the fill meets it in every column range its trial
+    triangle touches; a near radius covering every pair (all regular pairs
+    with their distance and kernel scalars in FP64) still gives the
+    oracle's blocks."""
+    mbem = _mbem()
+    xyz, tri = case["xyz"], case["tri"]
+    v = tri[:, :3]
+    share = (v[:, None, :, None] == v[None, :, None, :]).any(axis=(2, 3))
+    c = xyz[v].mean(axis=1)
+    rad = 1.25 * np.linalg.norm(xyz[tri] - c[:, None], axis=2).max(axis=1)
+    gap = np.linalg.norm(c[:, None] - c[None], axis=2) - rad[:, None] - rad[None]
+    near_r = 1.89 / np.sqrt(abs(case["k0"] ** 2 * (1.0 - case["eps"])))
+    lo = int(((gap < near_r * (1 - 1e-9)) & ~share).sum())
+    hi = int(((gap < near_r * (1 + 1e-9)) & ~share).sum())
+    S = mbem.Solver(xyz, tri, case["k0"], case["eps"], precision=mbem.MBEM_MIXED)
+    try:
+        st = S.fill()
+        assert lo <= st.n_near_pairs <= hi, (st.n_near_pairs, lo, hi)
+    finally:
+        S.close()
+    # a vanishing radius leaves the pairs whose bounding spheres overlap
+    S = mbem.Solver(xyz, tri, case["k0"], case["eps"], precision=mbem.MBEM_MIXED, near_radius=1e-9)
+    try:
+        assert S.fill().n_near_pairs == int(((gap < 1e-9) & ~share).sum())
+    finally:
+        S.close()
+    S = mbem.Solver(xyz, tri, case["k0"], case["eps"], precision=mbem.MBEM_MIXED, near_radius=1e3)
+    try:
+        st = S.fill()
+        assert st.n_near_pairs == int((~share).sum())
+        p1 = S.perm[: 2 * S.nn]
+        Kg = [k.cpu().numpy() for k in S.export_blocks()]
+        for o in range(3):
+            assert _rel(Kg[o], case["K"][o][np.ix_(p1, p1)]) < 2e-6, o
+    finally:
+        S.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_paper_scheme_fill_and_solve(case, prec):
     """The paper's own quadrature (12-point rule, Sauter-Schwab on kappa^s,
