@@ -71,7 +71,7 @@ static void mesh_free_device(mbem_mesh *m) {
     void *ps[] = {m->d_xyz, m->d_tri, m->d_inc_ptr, m->d_inc, m->d_spairs, m->d_frames,
                   m->d_qp, m->d_qp32, m->d_elem, m->d_mptr, m->d_mcol, m->d_mslot,
                   m->d_chunks, m->d_tcol, m->d_ccol, m->d_tcolour, m->d_ccolour, m->d_qp12, m->d_qp12_32,
-                  m->d_rng_off, m->d_rng_rec, m->d_row_first};
+                  m->d_rng_off, m->d_rng_rec, m->d_row_first, m->d_col_first};
     for (void *p : ps) dfree(p);
 }
 
@@ -439,6 +439,7 @@ int mbem_mesh_create(mbem_ctx *ctx, const double *xyz, int64_t n_nodes, const in
         (st = upload(&m->d_chunks, T.chunks, s)) || (st = upload(&m->d_tcol, T.tcol_list, s)) ||
         (st = upload(&m->d_ccol, T.ccol_list, s)) || (st = upload(&m->d_rng_off, T.rng_off, s)) ||
         (st = upload(&m->d_rng_rec, T.rng_rec, s)) || (st = upload(&m->d_row_first, T.row_first, s)) ||
+        (st = upload(&m->d_col_first, T.col_first, s)) ||
         (st = dalloc(&m->d_frames, 9 * m->nn)) || (st = dalloc(&m->d_qp, kQPF * nq)) ||
         (st = dalloc(&m->d_qp32, kQPF * nq)) || (st = dalloc(&m->d_elem, 4 * m->nt)) ||
         (st = dalloc(&m->d_qp12, kQPF * m->nt * kQP12)) || (st = dalloc(&m->d_qp12_32, kQPF * m->nt * kQP12)))

@@ -82,6 +82,11 @@ struct RegArgs {
     const int2 *tiles;      // mode 4: this launch's (test triangle, chunk) tiles
     const KernelConst *K;   // device copy, staged in LDS by every workgroup
     const int32_t *row_map; // null, or node -> row node of a band buffer
+    // FP64 dense fill: the first writer (in launch order) of an entry loads
+    // nothing and stores its sum, so Z needs no clearing; first_on = 0
+    // elsewhere
+    const int32_t *row_first, *col_first;
+    int first_on;
     TS *Z[3];
 };
 
@@ -261,7 +266,9 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
     int any = 0;
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) any |= s_act[k];
-    if (!any) return;                          // uniform over the workgroup
+    // uniform over the workgroup; a first writer still stores its zeros
+    if (!any && !a.first_on) return;
+    const int rfirst = a.first_on ? a.row_first[e] : 0, cfirst = a.first_on ? a.col_first[ch] : 0;
     const int ns = s_rec[0];
     const int rowlen = 2 * ns;
     const int nitems = 6 * rowlen;
@@ -290,7 +297,9 @@ __global__ __launch_bounds__(256) void k_regular(RegArgs<T, TS> a) {
             for (int i = 0; i < 6; ++i) {
                 const TS *src = Z + s_row[g][i];
                 if constexpr (kF64) {
-                    if (on) pre[k][i] = *(const double2 *)src;
+                    const bool first = ((rfirst >> i) & (cfirst >> sl) & 1) != 0;
+                    pre[k][i] = double2{0.0, 0.0};
+                    if (on && !first) pre[k][i] = *(const double2 *)src;
                 } else {
                     TS *dre = s_dst + (2 * i) * kItemsMax + first, *dim = s_dst + (2 * i + 1) * kItemsMax + first;
                     if (on) {
@@ -1432,6 +1441,9 @@ static int launch_regular(mbem_op *op, int mode, const T *qp, unsigned long long
     a.K = op->d_kconst;
     a.near_r = near_radius_of(op);
     a.row_map = band ? band->row_map : nullptr;
+    a.row_first = m->d_row_first;
+    a.col_first = m->d_col_first;
+    a.first_on = std::is_same<TS, double>::value && !DK && !P12 && !NODAL && !STORE && !band && mode == 0;
     for (int o = 0; o < 3; ++o) a.Z[o] = (TS *)(band ? band->Z[o] : op->K[o]);
     const std::vector<int32_t> &toff = band ? band->tcol_off : m->tcol_off;
     const int32_t *tlist = band ? band->tcol : m->d_tcol;
@@ -1638,9 +1650,9 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     hipEvent_t *ev = f->ev;
     MBEM_HIP(hipEventRecord(ev[6], s));
     const size_t esz = op->prec == MBEM_FP64 ? 16 : 8;
-    // the column-range fill (complex64, default scheme and frame) writes
-    // every entry itself; the others add to a cleared Z
-    const bool range_fill = op->prec != MBEM_FP64 && !deriv && !paper && !nodal;
+    // the default-scheme fills (FP64 by chunks, complex64 by column ranges)
+    // write every entry themselves; the others add to a cleared Z
+    const bool range_fill = !deriv && !paper && !nodal;
     if (!range_fill)
         for (int o = 0; o < 3; ++o) MBEM_HIP(hipMemsetAsync(op->K[o], 0, esz * op->n2 * op->n2, s));
     f->counted = op->prec != MBEM_FP64 && !deriv && !(op->p.near_store && !paper && !nodal);

@@ -423,6 +423,23 @@ int build_tables(const mbem_mesh *m, MeshTables &T) {
         const int32_t *rec = T.chunks.data() + k * kChunkRec;
         for (int s2 = 0; s2 < rec[0]; ++s2) out.push_back(rec[1 + s2]);
     }, T.ccol_list, T.ccol_off);
+    {
+        // likewise the chunks of a node: the lowest chunk colour writes the
+        // node's columns first
+        std::vector<int32_t> ccolour(nch), low(nn, INT32_MAX);
+        for (size_t c = 0; c + 1 < T.ccol_off.size(); ++c)
+            for (int32_t q = T.ccol_off[c]; q < T.ccol_off[c + 1]; ++q) ccolour[T.ccol_list[q]] = (int32_t)c;
+        for (int64_t k = 0; k < nch; ++k) {
+            const int32_t *rec = T.chunks.data() + k * kChunkRec;
+            for (int s2 = 0; s2 < rec[0]; ++s2) low[rec[1 + s2]] = std::min(low[rec[1 + s2]], ccolour[k]);
+        }
+        T.col_first.assign(nch, 0);
+        for (int64_t k = 0; k < nch; ++k) {
+            const int32_t *rec = T.chunks.data() + k * kChunkRec;
+            for (int s2 = 0; s2 < rec[0]; ++s2)
+                if (ccolour[k] == low[rec[1 + s2]]) T.col_first[k] |= 1 << s2;
+        }
+    }
     return MBEM_OK;
 }
 

@@ -122,6 +122,7 @@ struct mbem_mesh {
     int64_t nrng = 0;
     int32_t *d_rng_off = nullptr, *d_rng_rec = nullptr;
     int32_t *d_row_first = nullptr;   // per triangle: first writer of its nodes' rows
+    int32_t *d_col_first = nullptr;   // per trial chunk: first writer of its slots' columns
     // colour classes of the race-free regular-pair fill, and the class of
     // every test triangle and trial chunk
     std::vector<int32_t> tcol_off, ccol_off;
@@ -205,6 +206,9 @@ struct MeshTables {
     // order to write the rows of its local node a (the lowest colour among
     // the node's triangles)
     std::vector<int32_t> row_first;
+    // per trial chunk, bit sl: the chunk is the first of its colour order to
+    // write the columns of its slot node sl
+    std::vector<int32_t> col_first;
     // colour classes: test triangles sharing no node, trial chunks sharing
     // no node (offsets into the concatenated lists, one more than classes)
     std::vector<int32_t> tcol_list, tcol_off, ccol_list, ccol_off;

@@ -145,6 +145,16 @@ int main(int argc, char **argv) {
                 if ((T.row_first[e] >> k) & 1) firsts[m.tri[6 * e + k]]++;
         for (int64_t v = 0; v < nn; ++v)
             if (firsts[v] != 1) return fail("row first writers");
+        // and exactly one first chunk among the chunks of a node
+        std::vector<int> cf(nn, 0);
+        if ((int64_t)T.col_first.size() != nch) return fail("column first writers");
+        for (int64_t k = 0; k < nch; ++k) {
+            const int32_t *rec = T.chunks.data() + k * kChunkRec;
+            for (int s2 = 0; s2 < rec[0]; ++s2)
+                if ((T.col_first[k] >> s2) & 1) cf[rec[1 + s2]]++;
+        }
+        for (int64_t v = 0; v < nn; ++v)
+            if (cf[v] != 1) return fail("column first writers");
     }
     // mass pattern: CSR rows sorted, every column in range
     if ((int64_t)T.m_ptr.size() != nn + 1) return fail("mass pattern rows");
