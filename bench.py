@@ -88,7 +88,7 @@ PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix cores
 # scaled by a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  A
 # kernel changed after its counters were taken gets None here.
 MEASURED_TRAFFIC = {
-    ("k_regular", "fp64"): None,
+    ("k_regular", "fp64"): 21.77e9,    # 13.83 GB read + 7.94 GB written per fill
     ("k_regular_range", "mixed"): 3.75e9,   # 1.48 GB read + 2.27 GB written per fill
     ("k_gemv3", "fp64"): 1.291e9,
     ("k_gemv3", "mixed"): 0.683e9,
