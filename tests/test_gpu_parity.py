@@ -197,6 +197,30 @@ def test_mixed_fill_and_solve(case):
         S.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_tiny_mesh_fill(prec):
+    """A 20-triangle sphere (42 nodes: one column range, partly filled; every
+    element pair but the self pairs shares a vertex with few others): both
+    fills equal the oracle's blocks (the FP64 fill and the complex64 fill
+    write every entry themselves, without a cleared Z)."""
+    mbem = _mbem()
+    xyz, tri = icosphere_p2(20)
+    P = galerkin.Problem(xyz, tri, 1.5, 3.0 + 0.2j)
+    K = core.fill(xyz, tri, P.phys)
+    S = mbem.Solver(xyz, tri, 1.5, 3.0 + 0.2j,
+                    precision=mbem.MBEM_FP64 if prec == "fp64" else mbem.MBEM_MIXED)
+    try:
+        for _ in range(2):          # the second fill overwrites the first's values
+            S.fill()
+        p1 = S.perm[: 2 * S.nn]
+        Kg = [k.cpu().numpy() for k in S.export_blocks()]
+        tol = 1e-12 if prec == "fp64" else 2e-6
+        for o in range(3):
+            assert _rel(Kg[o], K[o][np.ix_(p1, p1)]) < tol, o
+    finally:
+        S.close()
+
+
 def test_mixed_near_pairs_counted_and_forced(case):
     """Near pairs of the complex64 fill: each regular element pair whose
     centroid distance minus both bounding radii (1.25 x the largest node
