@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "gemm.h"
+#include "wave.h"
 
 namespace mbem {
 
@@ -520,38 +521,7 @@ __device__ __forceinline__ void win_shift(int p, double2 *w) {
 // every column independently (one wavefront each, 8 per workgroup sharing
 // the reflectors of one block column through LDS).  Lane L holds row
 // j p + L of the sliding 2p-row window.
-// Sum over the 64 lanes, returned to every lane (all lanes active): within
-// each row of 16 lanes by DPP moves (quad swaps, half-row and row mirrors,
-// each pairing a lane with one of the other group), then the four row sums
-// read from lanes 0, 16, 32, 48 as wavefront-uniform values.  A dependent
-// chain of four DPP steps instead of six LDS permutes.
-__device__ __forceinline__ double dpp_move(double v, int ctrl_sel) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    int l2, h2;
-    switch (ctrl_sel) {
-        case 0: l2 = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-                h2 = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false); break;
-        case 1: l2 = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-                h2 = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false); break;
-        case 2: l2 = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);  // row_half_mirror
-                h2 = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false); break;
-        default: l2 = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false); // row_mirror
-                 h2 = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false); break;
-    }
-    return __hiloint2double(h2, l2);
-}
-__device__ __forceinline__ double lane_value(double v, int lane) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
-                            __builtin_amdgcn_readlane(__double2loint(v), lane));
-}
-__device__ __forceinline__ double wsum_all(double v) {
-    v += dpp_move(v, 0);
-    v += dpp_move(v, 1);
-    v += dpp_move(v, 2);
-    v += dpp_move(v, 3);
-    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
-}
-
+// Wavefront sums by wsum_all (four DPP steps instead of six LDS permutes).
 __global__ __launch_bounds__(512) void k_bqr_prev(int p, int k, double2 *Hcol, int64_t ldh, int64_t sh,
                                                   const double2 *refl, const double2 *taus, int64_t srefl,
                                                   int64_t staus) {

@@ -105,9 +105,10 @@ struct Gmres {
     double2 *V, *w, *z, *tmp, *hdev;
     double2 *tpart = nullptr;   // partial sums of the transposed product
     double *ndev;
-    double2 *ppart;             // per-chunk projection partials, (m + 1) x chunks
+    double2 *ppart;             // per-chunk projection partials, 2 (m + 1) x chunks
     double *npart;              // per-chunk parts of |w|^2
-    double2 *hpin[2] = {nullptr, nullptr};     // pinned copies of Hessenberg columns
+    double2 *hpin[2] = {nullptr, nullptr};     // Hessenberg column slots in pinned host memory
+    double2 *hmap[2] = {nullptr, nullptr};     // the same slots as the kernels address them
     // per column slot (two in flight): bracket the matvec, mark the column copy
     hipEvent_t ev0[2] = {nullptr, nullptr}, ev1[2] = {nullptr, nullptr}, evh[2] = {nullptr, nullptr};
     double t_matvec = 0.0;
@@ -143,12 +144,11 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
     g.s = s;
     g.N = 2 * op->n2;
     g.m = maxit;
-    // V, w, z, matvec partials (4 n2), two Hessenberg column slots, a norm,
-    // projection partials, norm partials
-    const size_t hslots = 2 * (size_t)(2 * (maxit + 1) + 1);
+    // V, w, z, matvec partials (4 n2), the coefficients y (m) and a norm,
+    // projection partials of both passes, norm partials
     const size_t nch = (size_t)arnoldi_chunks(g.N);
-    const size_t need = (size_t)(maxit + 1) * g.N + 2 * g.N + 4 * op->n2 + hslots + 1 +
-                        (size_t)(maxit + 1) * nch + nch;
+    const size_t need = (size_t)(maxit + 1) * g.N + 2 * g.N + 4 * op->n2 + (size_t)maxit + 1 +
+                        2 * (size_t)(maxit + 1) * nch + nch;
     mbem_op *mop = const_cast<mbem_op *>(op);
     if (op->work_elems < need) {
         dfree(mop->d_work);
@@ -157,24 +157,29 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
         MBEM_TRY(dalloc(&mop->d_work, need));
         mop->work_elems = need;
     }
+    // two Hessenberg column slots of 2 (maxit + 1) + 1, written by the
+    // Arnoldi kernels straight into host memory (fine-grained, so the
+    // host reads them once the slot's event has completed)
     const size_t pin = 2 * (size_t)(2 * (maxit + 1) + 1);
     if (op->pin_elems < pin) {
         if (mop->h_pin) (void)hipHostFree(mop->h_pin);
         mop->h_pin = nullptr;
         mop->pin_elems = 0;
-        MBEM_HIP(hipHostMalloc((void **)&mop->h_pin, sizeof(double2) * pin, hipHostMallocDefault));
+        MBEM_HIP(hipHostMalloc((void **)&mop->h_pin, sizeof(double2) * pin,
+                               hipHostMallocMapped | hipHostMallocCoherent));
         mop->pin_elems = pin;
     }
     g.hpin[0] = op->h_pin;
     g.hpin[1] = op->h_pin + pin / 2;
+    for (int i = 0; i < 2; ++i) MBEM_HIP(hipHostGetDevicePointer((void **)&g.hmap[i], g.hpin[i], 0));
     g.V = op->d_work;
     g.w = g.V + (size_t)(maxit + 1) * g.N;
     g.z = g.w + g.N;
     g.tmp = g.z + g.N;                 // 4 n2 for the matvec partials
-    g.hdev = g.tmp + 4 * op->n2;       // two column slots of 2 (maxit + 1) + 1
-    g.ndev = (double *)(g.hdev + hslots);
-    g.ppart = g.hdev + hslots + 1;
-    g.npart = (double *)(g.ppart + (size_t)(maxit + 1) * nch);
+    g.hdev = g.tmp + 4 * op->n2;       // the coefficients y of the final combination
+    g.ndev = (double *)(g.hdev + maxit);
+    g.ppart = g.hdev + maxit + 1;
+    g.npart = (double *)(g.ppart + 2 * (size_t)(maxit + 1) * nch);
     for (int i = 0; i < 2; ++i) {
         if (!g.ev0[i]) MBEM_HIP(hipEventCreate(&g.ev0[i]));
         if (!g.ev1[i]) MBEM_HIP(hipEventCreate(&g.ev1[i]));
@@ -215,16 +220,9 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
     auto enqueue = [&](int k) -> int {
         const int slot = k & 1;
         double2 *vk = g.V + (size_t)k * N;
-        double2 *hk = g.hdev + (size_t)slot * (2 * (m + 1) + 1);
         MBEM_TRY(mbj_apply_run(g.op, vk, g.z, s, g.trans));
         MBEM_TRY(g.timed_matvec(g.z, g.w, slot));
-        // CGS2: two projection passes, the second also yields |w|^2 by chunk
-        MBEM_TRY(arnoldi_pass(g.w, g.V, N, k + 1, N, g.ppart, hk, nullptr, s));
-        MBEM_TRY(arnoldi_pass(g.w, g.V, N, k + 1, N, g.ppart, hk + (k + 1), g.npart, s));
-        double *hn = (double *)(hk + 2 * (k + 1));
-        MBEM_TRY(scale_by_norm_parts(g.V + (size_t)(k + 1) * N, g.w, g.npart, hn, N, s));
-        MBEM_HIP(hipMemcpyAsync(g.hpin[slot], hk, sizeof(double2) * (2 * (k + 1) + 1),
-                                hipMemcpyDeviceToHost, s));
+        MBEM_TRY(arnoldi_cgs2(g.w, g.V, N, k + 1, N, g.ppart, g.npart, g.hmap[slot], s));
         MBEM_HIP(hipEventRecord(g.evh[slot], s));
         return MBEM_OK;
     };

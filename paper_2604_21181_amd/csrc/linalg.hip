@@ -13,6 +13,7 @@
 #include "gemm.h"
 #include "mbem_internal.h"
 #include "near_store.h"
+#include "wave.h"
 
 namespace mbem {
 
@@ -1006,81 +1007,129 @@ int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z, hipStream_t s
 }
 
 // ---------------------------------------------------- GMRES vectors ---
-// One Gram-Schmidt pass over k basis vectors in two launches, both with one
-// 256-element chunk of the vectors per workgroup:
-//   k_dots_part:  part[j][c] = sum over chunk c of conj(V_j) w   (j < k)
-//   k_update_red: h_j = sum_c part[j][c] (fixed order), w -= sum_j V_j h_j,
-//                 h written by workgroup 0, and optionally the chunk's part
-//                 of |w|^2 for the normalisation that follows.
-constexpr int kChunkN = 256;
-constexpr int kBatch = 64;      // basis vectors per LDS round
+// Classical Gram-Schmidt with one reorthogonalisation (CGS2) of the new
+// Krylov vector w against k orthonormal basis vectors, and its
+// normalisation, in four launches over 256-row chunks of the vectors:
+//   k_cgs_dots:           partial projections part[j][c] = (V_j^H w) over
+//                         chunk c (one workgroup per chunk and 8 vectors)
+//   k_cgs_update<true>:   h_j = sum_c part[j][c]; w -= V h over the chunk;
+//                         partial projections of the updated w
+//   k_cgs_update<false>:  the same second pass, then the chunk's |w|^2
+//   k_cgs_scale:          V_k = w / |w|
+// Every reduction runs in a fixed order and every workgroup sums the same
+// partials, so all workgroups use bit-identical coefficients.  The loads of
+// a workgroup's vectors are issued together before their wavefront sums:
+// at the sizes of a GMRES step the kernels are bound by memory latency, not
+// by bandwidth (a 10 248-row vector is 41 chunks).
+constexpr int kChunkN = 256;   // rows per workgroup: four wavefronts, one row per lane
+constexpr int kDotG = 8;       // basis vectors per workgroup of k_cgs_dots
+constexpr int kRedG = 64;      // coefficients per LDS round of k_cgs_update
+constexpr int kRedQ = kRedG / 4;   // coefficients reduced per wavefront and round
 
-__global__ __launch_bounds__(kChunkN) void k_dots_part(const double2 *V, int64_t ldv, int k,
-                                                      const double2 *w, int64_t n, double2 *part,
-                                                      int64_t nch) {
-    __shared__ double s_re[4][kBatch], s_im[4][kBatch];
-    const int64_t c = blockIdx.x, i = c * kChunkN + threadIdx.x;
-    const int wv = threadIdx.x / kW, lane = threadIdx.x % kW;
-    const double2 b = i < n ? w[i] : double2{0, 0};
-    for (int j0 = 0; j0 < k; j0 += kBatch) {
-        const int nb = k - j0 < kBatch ? k - j0 : kBatch;
-        for (int jj = 0; jj < nb; ++jj) {
-            const double2 a = i < n ? V[(int64_t)(j0 + jj) * ldv + i] : double2{0, 0};
-            const double re = wave_sum(a.x * b.x + a.y * b.y), im = wave_sum(a.x * b.y - a.y * b.x);
-            if (lane == 0) { s_re[wv][jj] = re; s_im[wv][jj] = im; }
-        }
-        __syncthreads();
-        if (threadIdx.x < nb) {
-            const int jj = threadIdx.x;
-            part[(int64_t)(j0 + jj) * nch + c] = {s_re[0][jj] + s_re[1][jj] + s_re[2][jj] + s_re[3][jj],
-                                                  s_im[0][jj] + s_im[1][jj] + s_im[2][jj] + s_im[3][jj]};
-        }
-        __syncthreads();
-    }
+__device__ inline double2 sum4(const double2 (*s)[kRedG], int g) {
+    return {(s[0][g].x + s[1][g].x) + (s[2][g].x + s[3][g].x), (s[0][g].y + s[1][g].y) + (s[2][g].y + s[3][g].y)};
 }
 
-__global__ __launch_bounds__(kChunkN) void k_update_red(double2 *w, const double2 *V, int64_t ldv, int k,
+// conj(a) b summed over the wavefront, into s[wv][g] (every lane active)
+__device__ inline void dot_to_lds(double2 a, double2 b, double2 (*s)[kRedG], int wv, int g) {
+    const double re = wsum_all(a.x * b.x + a.y * b.y), im = wsum_all(a.x * b.y - a.y * b.x);
+    if (threadIdx.x % kW == 0) s[wv][g] = {re, im};
+}
+
+__global__ __launch_bounds__(kChunkN) void k_cgs_dots(const double2 *V, int64_t ldv, int k, const double2 *w,
+                                                     int64_t n, double2 *part, int64_t nch) {
+    __shared__ double2 s[4][kRedG];
+    const int64_t c = blockIdx.x, i = c * kChunkN + threadIdx.x;
+    const int j0 = blockIdx.y * kDotG, wv = threadIdx.x / kW;
+    const bool in = i < n;
+    const double2 b = in ? w[i] : double2{0, 0};
+    double2 a[kDotG];
+#pragma unroll
+    for (int g = 0; g < kDotG; ++g) a[g] = (in && j0 + g < k) ? V[(int64_t)(j0 + g) * ldv + i] : double2{0, 0};
+#pragma unroll
+    for (int g = 0; g < kDotG; ++g)
+        if (j0 + g < k) dot_to_lds(a[g], b, s, wv, g);   // uniform over the workgroup
+    __syncthreads();
+    const int g = threadIdx.x;
+    if (g < kDotG && j0 + g < k) part[(int64_t)(j0 + g) * nch + c] = sum4(s, g);
+}
+
+// DOTS: `next` receives the partial projections of the updated w (the
+// second pass's part); otherwise npart[c] receives the chunk's |w|^2.
+// hout[j] = h_j is written by workgroup 0 (hout may be host-mapped memory).
+template <bool DOTS>
+__global__ __launch_bounds__(kChunkN) void k_cgs_update(double2 *w, const double2 *V, int64_t ldv, int k,
                                                        const double2 *part, int64_t nch, double2 *hout,
-                                                       int64_t n, double *npart) {
-    __shared__ double2 s_h[kBatch];
-    __shared__ double s_n[4];
+                                                       int64_t n, double2 *next, double *npart) {
+    __shared__ double2 s_h[kRedG];
+    __shared__ double2 s[4][kRedG];
     const int wv = threadIdx.x / kW, lane = threadIdx.x % kW;
-    const int64_t i = blockIdx.x * (int64_t)kChunkN + threadIdx.x;
-    double2 t = i < n ? w[i] : double2{0, 0};
-    for (int j0 = 0; j0 < k; j0 += kBatch) {
-        const int nb = k - j0 < kBatch ? k - j0 : kBatch;
-        for (int jj = wv; jj < nb; jj += 4) {    // wavefront wv reduces h_j over the chunks
-            const int64_t j = j0 + jj;
-            double re = 0, im = 0;
-            for (int64_t cc = lane; cc < nch; cc += kW) { re += part[j * nch + cc].x; im += part[j * nch + cc].y; }
-            re = wave_sum(re);
-            im = wave_sum(im);
-            if (lane == 0) s_h[jj] = {re, im};
+    const int64_t c = blockIdx.x, i = c * kChunkN + threadIdx.x;
+    const bool in = i < n;
+    double2 t = in ? w[i] : double2{0, 0};
+    for (int j0 = 0; j0 < k; j0 += kRedG) {
+        const int nb = k - j0 < kRedG ? k - j0 : kRedG;
+        // wavefront wv sums h_j for j = j0 + wv + 4 q over the chunks
+        double re[kRedQ], im[kRedQ];
+#pragma unroll
+        for (int q = 0; q < kRedQ; ++q) re[q] = im[q] = 0.0;
+        for (int64_t cc = lane; cc < nch; cc += kW) {
+#pragma unroll
+            for (int q = 0; q < kRedQ; ++q)
+                if (wv + 4 * q < nb) {
+                    const double2 p = part[(int64_t)(j0 + wv + 4 * q) * nch + cc];
+                    re[q] += p.x;
+                    im[q] += p.y;
+                }
         }
+#pragma unroll
+        for (int q = 0; q < kRedQ; ++q)
+            if (wv + 4 * q < nb) {   // uniform over the wavefront
+                const double a = wsum_all(re[q]), b = wsum_all(im[q]);
+                if (lane == 0) s_h[wv + 4 * q] = {a, b};
+            }
         __syncthreads();
         if (blockIdx.x == 0 && threadIdx.x < nb) hout[j0 + threadIdx.x] = s_h[threadIdx.x];
-        if (i < n)
+        if (in) {
+#pragma unroll 8
             for (int jj = 0; jj < nb; ++jj) t = csub(t, cmul(V[(int64_t)(j0 + jj) * ldv + i], s_h[jj]));
+        }
         __syncthreads();
     }
-    if (i < n) w[i] = t;
-    if (npart) {
-        const double nn = wave_sum(i < n ? t.x * t.x + t.y * t.y : 0.0);
-        if (lane == 0) s_n[wv] = nn;
+    if (in) w[i] = t;
+    if constexpr (DOTS) {
+        for (int j0 = 0; j0 < k; j0 += kRedG) {
+            const int nb = k - j0 < kRedG ? k - j0 : kRedG;
+            for (int g0 = 0; g0 < nb; g0 += 16) {
+                double2 a[16];
+#pragma unroll
+                for (int g = 0; g < 16; ++g)
+                    a[g] = (in && g0 + g < nb) ? V[(int64_t)(j0 + g0 + g) * ldv + i] : double2{0, 0};
+#pragma unroll
+                for (int g = 0; g < 16; ++g)
+                    if (g0 + g < nb) dot_to_lds(a[g], t, s, wv, g0 + g);
+            }
+            __syncthreads();
+            if (threadIdx.x < nb) next[(int64_t)(j0 + threadIdx.x) * nch + c] = sum4(s, threadIdx.x);
+            __syncthreads();
+        }
+    } else {
+        const double nn = wsum_all(in ? t.x * t.x + t.y * t.y : 0.0);
+        if (lane == 0) s[wv][0].x = nn;
         __syncthreads();
-        if (threadIdx.x == 0) npart[blockIdx.x] = s_n[0] + s_n[1] + s_n[2] + s_n[3];
+        if (threadIdx.x == 0) npart[c] = (s[0][0].x + s[1][0].x) + (s[2][0].x + s[3][0].x);
     }
 }
 
-// dst = src / h with h = sqrt(sum_c npart[c]); workgroup 0 stores h
-__global__ __launch_bounds__(kChunkN) void k_scale_norm_part(double2 *dst, const double2 *src,
-                                                            const double *npart, int64_t nch,
-                                                            double *hout, int64_t n) {
+// dst = src / h with h = sqrt(sum_c npart[c]) (0 -> dst = 0); workgroup 0
+// stores h (hout may be host-mapped memory)
+__global__ __launch_bounds__(kChunkN) void k_cgs_scale(double2 *dst, const double2 *src, const double *npart,
+                                                      int64_t nch, double *hout, int64_t n) {
     __shared__ double s_h;
     if (threadIdx.x < kW) {
         double a = 0;
         for (int64_t c = threadIdx.x; c < nch; c += kW) a += npart[c];
-        a = wave_sum(a);
+        a = wsum_all(a);
         if (threadIdx.x == 0) { s_h = sqrt(a); if (blockIdx.x == 0) *hout = s_h; }
     }
     __syncthreads();
@@ -1141,21 +1190,22 @@ int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n, hipSt
     return MBEM_OK;
 }
 int64_t arnoldi_chunks(int64_t n) { return (n + kChunkN - 1) / kChunkN; }
-int arnoldi_pass(double2 *w, const double2 *V, int64_t ldv, int k, int64_t n, double2 *part,
-                 double2 *hout, double *npart, hipStream_t s) {
+int arnoldi_cgs2(double2 *w, double2 *V, int64_t ldv, int k, int64_t n, double2 *part, double *npart,
+                 double2 *hout, hipStream_t s) {
+    if (k < 1 || n < 1) return MBEM_EINVAL;
     const int64_t nch = arnoldi_chunks(n);
-    hipLaunchKernelGGL(k_dots_part, dim3((unsigned)nch), dim3(kChunkN), 0, s, V, ldv, k, w, n, part, nch);
+    double2 *part2 = part + (int64_t)k * nch;
+    hipLaunchKernelGGL(k_cgs_dots, dim3((unsigned)nch, (unsigned)((k + kDotG - 1) / kDotG)), dim3(kChunkN), 0, s,
+                       V, ldv, k, w, n, part, nch);
     MBEM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_update_red, dim3((unsigned)nch), dim3(kChunkN), 0, s, w, V, ldv, k, part, nch,
-                       hout, n, npart);
+    hipLaunchKernelGGL(k_cgs_update<true>, dim3((unsigned)nch), dim3(kChunkN), 0, s, w, V, ldv, k, part, nch,
+                       hout, n, part2, nullptr);
     MBEM_HIP(hipGetLastError());
-    return MBEM_OK;
-}
-int scale_by_norm_parts(double2 *dst, const double2 *src, const double *npart, double *hout, int64_t n,
-                        hipStream_t s) {
-    const int64_t nch = arnoldi_chunks(n);
-    hipLaunchKernelGGL(k_scale_norm_part, dim3((unsigned)nch), dim3(kChunkN), 0, s, dst, src, npart, nch,
-                       hout, n);
+    hipLaunchKernelGGL(k_cgs_update<false>, dim3((unsigned)nch), dim3(kChunkN), 0, s, w, V, ldv, k, part2, nch,
+                       hout + k, n, nullptr, npart);
+    MBEM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_cgs_scale, dim3((unsigned)nch), dim3(kChunkN), 0, s, V + (int64_t)k * ldv, w, npart,
+                       nch, (double *)(hout + 2 * k), n);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }

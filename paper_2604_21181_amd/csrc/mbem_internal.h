@@ -307,16 +307,16 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s, bool keep = false);
 int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z,
                   hipStream_t s, bool trans = false);
 int vec_norm2(const double2 *v, int64_t n, double *out_dev, hipStream_t s);
-// One classical Gram-Schmidt pass w -= V h, h = V^H w over k basis vectors
-// (h stored to hout); with npart, the per-chunk parts of |w|^2 after the
-// pass.  part: k * arnoldi_chunks(n) complex, npart: arnoldi_chunks(n)
-// doubles (device scratch).
+// Classical Gram-Schmidt with one reorthogonalisation of w (n rows)
+// against the k orthonormal columns of V (leading dimension ldv), then
+// V_k = w / |w| (column k of V; 0 when w vanishes).  hout receives the
+// coefficients of both passes and the norm: hout[0..k) = h1,
+// hout[k..2k) = h2, ((double *)(hout + 2k))[0] = |w|; it may be
+// host-mapped memory.  part: 2 k arnoldi_chunks(n) complex and npart:
+// arnoldi_chunks(n) doubles of device scratch.
 int64_t arnoldi_chunks(int64_t n);
-int arnoldi_pass(double2 *w, const double2 *V, int64_t ldv, int k, int64_t n, double2 *part,
-                 double2 *hout, double *npart, hipStream_t s);
-// dst = src / h, h = sqrt(sum of npart) stored to *hout (0 -> dst = 0)
-int scale_by_norm_parts(double2 *dst, const double2 *src, const double *npart, double *hout, int64_t n,
-                        hipStream_t s);
+int arnoldi_cgs2(double2 *w, double2 *V, int64_t ldv, int k, int64_t n, double2 *part, double *npart,
+                 double2 *hout, hipStream_t s);
 int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n,
                    hipStream_t s);
 int vec_axpy(double2 *y, const double2 *x, double2 a, int64_t n,
