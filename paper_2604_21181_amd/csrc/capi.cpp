@@ -105,37 +105,75 @@ struct Gmres {
     double2 *V, *w, *z, *tmp, *hdev;
     double2 *tpart = nullptr;   // partial sums of the transposed product
     double *ndev;
+    double2 *hcol;              // the current step's projection coefficients (device)
     double2 *ppart;             // per-chunk projection partials, 2 (m + 1) x chunks
     double *npart;              // per-chunk parts of |w|^2
-    double2 *hpin[2] = {nullptr, nullptr};     // Hessenberg column slots in pinned host memory
-    double2 *hmap[2] = {nullptr, nullptr};     // the same slots as the kernels address them
-    // per column slot (two in flight): bracket the matvec, mark the column copy
-    hipEvent_t ev0[2] = {nullptr, nullptr}, ev1[2] = {nullptr, nullptr}, evh[2] = {nullptr, nullptr};
+    // two Hessenberg column slots in pinned host memory, each 2 (m + 1) + 1
+    // values and a completion tag, and the same slots as the kernels
+    // address them
+    double2 *hpin[2] = {nullptr, nullptr};
+    double2 *hmap[2] = {nullptr, nullptr};
+    // matvec timing: events around the products of the first kTimedSteps
+    // Arnoldi steps only (an event between two kernels costs the stream
+    // several microseconds of idle time)
+    static constexpr int kTimedSteps = 2;
+    hipEvent_t ev0[kTimedSteps] = {}, ev1[kTimedSteps] = {};
     double t_matvec = 0.0;
     int n_matvec = 0;
     ~Gmres() {
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < kTimedSteps; ++i) {
             if (ev0[i]) (void)hipEventDestroy(ev0[i]);
             if (ev1[i]) (void)hipEventDestroy(ev1[i]);
-            if (evh[i]) (void)hipEventDestroy(evh[i]);
         }
         if (tpart) (void)hipFree(tpart);
     }
     int apply(const double2 *x, double2 *y) {   // y = Z x or Z^T x
         return trans ? matvec_t_run(op, x, y, tpart, s) : matvec_run(op, x, y, tmp, s);
     }
-    int timed_matvec(const double2 *x, double2 *y, int slot) {
-        (void)hipEventRecord(ev0[slot], s);
+    int step_matvec(const double2 *x, double2 *y, int q) {
+        if (q >= kTimedSteps) return apply(x, y);
+        MBEM_HIP(hipEventRecord(ev0[q], s));
         if (trans) {
             MBEM_TRY(matvec_t_run(op, x, y, tpart, s));
-            MBEM_HIP(hipEventRecord(ev1[slot], s));
+            MBEM_HIP(hipEventRecord(ev1[q], s));
             return MBEM_OK;
         }
-        return matvec_run(op, x, y, tmp, s, ev1[slot]);   // ev1 right after the GEMV
+        return matvec_run(op, x, y, tmp, s, ev1[q]);   // ev1 right after the GEMV
     }
-    void collect(int slot) {   // after the slot's column copy has completed
+    void collect(int q) {   // once step q's column has arrived
+        if (q >= kTimedSteps) return;
         float t = 0.f;
-        if (hipEventElapsedTime(&t, ev0[slot], ev1[slot]) == hipSuccess) { t_matvec += t; ++n_matvec; }
+        if (hipEventSynchronize(ev1[q]) == hipSuccess &&
+            hipEventElapsedTime(&t, ev0[q], ev1[q]) == hipSuccess) { t_matvec += t; ++n_matvec; }
+    }
+    // Wait until the tag `seq` of step `slot` is in pinned memory.  The host
+    // spins on the tag.  Asking the stream for its state puts a marker into
+    // it, which idles the device for microseconds between two kernels, so
+    // that is done only after 20 ms without the tag (a step takes far less):
+    // a failed or drained stream ends the wait with an error, and so does a
+    // minute without the tag.
+    int wait_column(int slot, unsigned long long seq) const {
+        using clock = std::chrono::steady_clock;
+        const unsigned long long *tag = (const unsigned long long *)(hpin[slot] + 2 * (m + 1) + 1);
+        const auto t0 = clock::now();
+        auto next_query = t0 + std::chrono::milliseconds(20);
+        for (unsigned spins = 1;; ++spins) {
+            if (__atomic_load_n(tag, __ATOMIC_ACQUIRE) == seq) return MBEM_OK;
+            if (spins % 1024) continue;
+            const auto now = clock::now();
+            if (now < next_query) continue;
+            next_query = now + std::chrono::milliseconds(20);
+            const hipError_t e = hipStreamQuery(s);
+            if (e != hipSuccess && e != hipErrorNotReady) MBEM_HIP(e);
+            if (e == hipSuccess && __atomic_load_n(tag, __ATOMIC_ACQUIRE) != seq) {
+                set_error("GMRES: the stream drained without the Arnoldi column");
+                return MBEM_EDEVICE;
+            }
+            if (now - t0 > std::chrono::seconds(60)) {
+                set_error("GMRES: no Arnoldi column within a minute");
+                return MBEM_EDEVICE;
+            }
+        }
     }
 };
 
@@ -145,9 +183,10 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
     g.N = 2 * op->n2;
     g.m = maxit;
     // V, w, z, matvec partials (4 n2), the coefficients y (m) and a norm,
-    // projection partials of both passes, norm partials
+    // the step's column, projection partials of both passes, norm partials
     const size_t nch = (size_t)arnoldi_chunks(g.N);
-    const size_t need = (size_t)(maxit + 1) * g.N + 2 * g.N + 4 * op->n2 + (size_t)maxit + 1 +
+    const size_t col = 2 * (size_t)(maxit + 1) + 1;
+    const size_t need = (size_t)(maxit + 1) * g.N + 2 * g.N + 4 * op->n2 + (size_t)maxit + 1 + col +
                         2 * (size_t)(maxit + 1) * nch + nch;
     mbem_op *mop = const_cast<mbem_op *>(op);
     if (op->work_elems < need) {
@@ -157,10 +196,9 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
         MBEM_TRY(dalloc(&mop->d_work, need));
         mop->work_elems = need;
     }
-    // two Hessenberg column slots of 2 (maxit + 1) + 1, written by the
-    // Arnoldi kernels straight into host memory (fine-grained, so the
-    // host reads them once the slot's event has completed)
-    const size_t pin = 2 * (size_t)(2 * (maxit + 1) + 1);
+    // two column slots of col values and a tag, written by the Arnoldi
+    // kernels straight into fine-grained host memory
+    const size_t pin = 2 * (col + 1);
     if (op->pin_elems < pin) {
         if (mop->h_pin) (void)hipHostFree(mop->h_pin);
         mop->h_pin = nullptr;
@@ -170,7 +208,7 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
         mop->pin_elems = pin;
     }
     g.hpin[0] = op->h_pin;
-    g.hpin[1] = op->h_pin + pin / 2;
+    g.hpin[1] = op->h_pin + col + 1;
     for (int i = 0; i < 2; ++i) MBEM_HIP(hipHostGetDevicePointer((void **)&g.hmap[i], g.hpin[i], 0));
     g.V = op->d_work;
     g.w = g.V + (size_t)(maxit + 1) * g.N;
@@ -178,12 +216,12 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
     g.tmp = g.z + g.N;                 // 4 n2 for the matvec partials
     g.hdev = g.tmp + 4 * op->n2;       // the coefficients y of the final combination
     g.ndev = (double *)(g.hdev + maxit);
-    g.ppart = g.hdev + maxit + 1;
+    g.hcol = g.hdev + maxit + 1;
+    g.ppart = g.hcol + col;
     g.npart = (double *)(g.ppart + 2 * (size_t)(maxit + 1) * nch);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < Gmres::kTimedSteps; ++i) {
         if (!g.ev0[i]) MBEM_HIP(hipEventCreate(&g.ev0[i]));
         if (!g.ev1[i]) MBEM_HIP(hipEventCreate(&g.ev1[i]));
-        if (!g.evh[i]) MBEM_HIP(hipEventCreateWithFlags(&g.evh[i], hipEventDisableTiming));
     }
     if (g.trans && !g.tpart) MBEM_TRY(dalloc(&g.tpart, (size_t)matvec_t_work(op)));
     return MBEM_OK;
@@ -216,14 +254,17 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
     const int m = g.m;
     std::vector<std::complex<double>> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1);
     gv[0] = beta;
-    // queue Arnoldi step k; its column lands in hpin[k % 2]
+    // no tag of an earlier solve may match: the stream is idle here
+    for (int i = 0; i < 2; ++i) *(unsigned long long *)(g.hpin[i] + 2 * (m + 1) + 1) = 0ull;
+    // queue Arnoldi step k; its column lands in hpin[k % 2] with tag k + 1
     auto enqueue = [&](int k) -> int {
         const int slot = k & 1;
         double2 *vk = g.V + (size_t)k * N;
         MBEM_TRY(mbj_apply_run(g.op, vk, g.z, s, g.trans));
-        MBEM_TRY(g.timed_matvec(g.z, g.w, slot));
-        MBEM_TRY(arnoldi_cgs2(g.w, g.V, N, k + 1, N, g.ppart, g.npart, g.hmap[slot], s));
-        MBEM_HIP(hipEventRecord(g.evh[slot], s));
+        MBEM_TRY(g.step_matvec(g.z, g.w, k));
+        MBEM_TRY(arnoldi_cgs2(g.w, g.V, N, k + 1, N, g.ppart, g.npart, g.hcol, g.hmap[slot],
+                              (unsigned long long *)(g.hmap[slot] + 2 * (m + 1) + 1), (unsigned long long)k + 1,
+                              s));
         return MBEM_OK;
     };
     double res = 1.0;
@@ -231,8 +272,8 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
     // wait for column k and fold it into the QR factorisation of H
     auto process = [&](int k) -> int {
         const int slot = k & 1;
-        MBEM_HIP(hipEventSynchronize(g.evh[slot]));
-        g.collect(slot);
+        MBEM_TRY(g.wait_column(slot, (unsigned long long)k + 1));
+        g.collect(k);
         const double2 *hb = g.hpin[slot];
         const double hn = hb[2 * (k + 1)].x;
         auto Hc = [&](int i) -> std::complex<double> & { return H[(size_t)i * m + k]; };

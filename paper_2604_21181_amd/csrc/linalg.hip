@@ -1015,7 +1015,8 @@ int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z, hipStream_t s
 //   k_cgs_update<true>:   h_j = sum_c part[j][c]; w -= V h over the chunk;
 //                         partial projections of the updated w
 //   k_cgs_update<false>:  the same second pass, then the chunk's |w|^2
-//   k_cgs_scale:          V_k = w / |w|
+//   k_cgs_scale:          V_k = w / |w|, and the step's Hessenberg column
+//                         with a completion tag into host-mapped memory
 // Every reduction runs in a fixed order and every workgroup sums the same
 // partials, so all workgroups use bit-identical coefficients.  The loads of
 // a workgroup's vectors are issued together before their wavefront sums:
@@ -1121,21 +1122,34 @@ __global__ __launch_bounds__(kChunkN) void k_cgs_update(double2 *w, const double
     }
 }
 
-// dst = src / h with h = sqrt(sum_c npart[c]) (0 -> dst = 0); workgroup 0
-// stores h (hout may be host-mapped memory)
+// dst = src / h with h = sqrt(sum_c npart[c]) (0 -> dst = 0).  With pin
+// (host-mapped), workgroup 0 then publishes the step's Hessenberg column:
+// pin[0 .. k2) = hcol[0 .. k2), pin[k2].x = h, and last *tag = seq (also
+// host-mapped), after a system-scope fence of every store before it, so a
+// host that sees the tag reads a complete column.
 __global__ __launch_bounds__(kChunkN) void k_cgs_scale(double2 *dst, const double2 *src, const double *npart,
-                                                      int64_t nch, double *hout, int64_t n) {
+                                                      int64_t nch, int64_t n, const double2 *hcol, int k2,
+                                                      double2 *pin, unsigned long long *tag,
+                                                      unsigned long long seq) {
     __shared__ double s_h;
     if (threadIdx.x < kW) {
         double a = 0;
         for (int64_t c = threadIdx.x; c < nch; c += kW) a += npart[c];
         a = wsum_all(a);
-        if (threadIdx.x == 0) { s_h = sqrt(a); if (blockIdx.x == 0) *hout = s_h; }
+        if (threadIdx.x == 0) s_h = sqrt(a);
     }
     __syncthreads();
     const double h = s_h, inv = h > 0 ? 1.0 / h : 0.0;
     const int64_t i = blockIdx.x * (int64_t)kChunkN + threadIdx.x;
     if (i < n) dst[i] = {inv * src[i].x, inv * src[i].y};
+    if (blockIdx.x == 0 && pin) {
+        for (int t = threadIdx.x; t < k2; t += kChunkN) pin[t] = hcol[t];
+        if (threadIdx.x == 0) pin[k2] = {h, 0.0};
+        __threadfence_system();
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(tag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 // out[n] = sum_j V[j][n] y[j]
@@ -1191,7 +1205,8 @@ int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n, hipSt
 }
 int64_t arnoldi_chunks(int64_t n) { return (n + kChunkN - 1) / kChunkN; }
 int arnoldi_cgs2(double2 *w, double2 *V, int64_t ldv, int k, int64_t n, double2 *part, double *npart,
-                 double2 *hout, hipStream_t s) {
+                 double2 *hcol, double2 *pin, unsigned long long *tag, unsigned long long seq,
+                 hipStream_t s) {
     if (k < 1 || n < 1) return MBEM_EINVAL;
     const int64_t nch = arnoldi_chunks(n);
     double2 *part2 = part + (int64_t)k * nch;
@@ -1199,13 +1214,13 @@ int arnoldi_cgs2(double2 *w, double2 *V, int64_t ldv, int k, int64_t n, double2 
                        V, ldv, k, w, n, part, nch);
     MBEM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_cgs_update<true>, dim3((unsigned)nch), dim3(kChunkN), 0, s, w, V, ldv, k, part, nch,
-                       hout, n, part2, nullptr);
+                       hcol, n, part2, nullptr);
     MBEM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_cgs_update<false>, dim3((unsigned)nch), dim3(kChunkN), 0, s, w, V, ldv, k, part2, nch,
-                       hout + k, n, nullptr, npart);
+                       hcol + k, n, nullptr, npart);
     MBEM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_cgs_scale, dim3((unsigned)nch), dim3(kChunkN), 0, s, V + (int64_t)k * ldv, w, npart,
-                       nch, (double *)(hout + 2 * k), n);
+                       nch, n, (const double2 *)hcol, 2 * k, pin, tag, seq);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
