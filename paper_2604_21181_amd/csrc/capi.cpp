@@ -106,7 +106,7 @@ struct Gmres {
     double2 *tpart = nullptr;   // partial sums of the transposed product
     double *ndev;
     double2 *hcol;              // the current step's projection coefficients (device)
-    double2 *ppart;             // per-chunk projection partials, 2 (m + 1) x chunks
+    double2 *ppart;             // projection partials of both passes, 2 (m + 1) x chunks
     double *npart;              // per-chunk parts of |w|^2
     // two Hessenberg column slots in pinned host memory, each 2 (m + 1) + 1
     // values and a completion tag, and the same slots as the kernels
@@ -256,15 +256,25 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
     gv[0] = beta;
     // no tag of an earlier solve may match: the stream is idle here
     for (int i = 0; i < 2; ++i) *(unsigned long long *)(g.hpin[i] + 2 * (m + 1) + 1) = 0ull;
-    // queue Arnoldi step k; its column lands in hpin[k % 2] with tag k + 1
+    // queue Arnoldi step k; its column lands in hpin[k % 2] with tag k + 1.
+    // With a preconditioner the step's normalisation and column run as the
+    // first launch of step k + 1 (fused with its block-Jacobi product), or
+    // as arnoldi_finish after the last step.
+    const bool fuse = mbj_present(g.op);
+    auto tag_of = [&](int slot) { return (unsigned long long *)(g.hmap[slot] + 2 * (m + 1) + 1); };
     auto enqueue = [&](int k) -> int {
         const int slot = k & 1;
         double2 *vk = g.V + (size_t)k * N;
-        MBEM_TRY(mbj_apply_run(g.op, vk, g.z, s, g.trans));
+        if (fuse && k > 0) {
+            const int ps = (k - 1) & 1;
+            MBEM_TRY(mbj_scale_apply_run(g.op, g.w, g.npart, N, vk, g.z, g.hcol, k, g.hmap[ps], tag_of(ps),
+                                         (unsigned long long)k, s, g.trans));
+        } else {
+            MBEM_TRY(mbj_apply_run(g.op, vk, g.z, s, g.trans));
+        }
         MBEM_TRY(g.step_matvec(g.z, g.w, k));
-        MBEM_TRY(arnoldi_cgs2(g.w, g.V, N, k + 1, N, g.ppart, g.npart, g.hcol, g.hmap[slot],
-                              (unsigned long long *)(g.hmap[slot] + 2 * (m + 1) + 1), (unsigned long long)k + 1,
-                              s));
+        MBEM_TRY(arnoldi_cgs2(g.w, g.V, N, k + 1, N, g.ppart, g.npart, g.hcol, !fuse, g.hmap[slot], tag_of(slot),
+                              (unsigned long long)k + 1, s));
         return MBEM_OK;
     };
     double res = 1.0;
@@ -308,6 +318,9 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
         }
     }
     if (!conv) {
+        if (fuse)
+            MBEM_TRY(arnoldi_finish(g.w, g.V, N, m, N, g.npart, g.hcol, g.hmap[(m - 1) & 1], tag_of((m - 1) & 1),
+                                    (unsigned long long)m, s));
         MBEM_TRY(process(m - 1));
         k = m;
     }

@@ -1017,138 +1017,221 @@ int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z, hipStream_t s
 //   k_cgs_update<false>:  the same second pass, then the chunk's |w|^2
 //   k_cgs_scale:          V_k = w / |w|, and the step's Hessenberg column
 //                         with a completion tag into host-mapped memory
+//                         (with a preconditioner, k_mbj_scale_apply does
+//                         this as the first launch of the next step)
 // Every reduction runs in a fixed order and every workgroup sums the same
-// partials, so all workgroups use bit-identical coefficients.  The loads of
-// a workgroup's vectors are issued together before their wavefront sums:
-// at the sizes of a GMRES step the kernels are bound by memory latency, not
-// by bandwidth (a 10 248-row vector is 41 chunks).
+// partials, so all workgroups use bit-identical coefficients.  At the sizes
+// of a GMRES step (a 10 248-row vector is 41 chunks) the kernels are bound
+// by memory latency and by the cross-lane sums, not by bandwidth: the loads
+// of several vectors are issued together, and the sums over a chunk go
+// through LDS (eight vectors at a time, each summed by half a wavefront)
+// rather than one wavefront-wide sum per vector and wavefront.
 constexpr int kChunkN = 256;   // rows per workgroup: four wavefronts, one row per lane
-constexpr int kDotG = 8;       // basis vectors per workgroup of k_cgs_dots
-constexpr int kRedG = 64;      // coefficients per LDS round of k_cgs_update
-constexpr int kRedQ = kRedG / 4;   // coefficients reduced per wavefront and round
+constexpr int kDotG = 8;       // basis vectors per round of chunk sums (one per half-wavefront)
+constexpr int kRedG = 64;      // coefficients per round of k_cgs_update (one per four lanes)
+static_assert(kDotG * 32 == kChunkN && kRedG * 4 == kChunkN, "one thread group per vector");
 
-__device__ inline double2 sum4(const double2 (*s)[kRedG], int g) {
-    return {(s[0][g].x + s[1][g].x) + (s[2][g].x + s[3][g].x), (s[0][g].y + s[1][g].y) + (s[2][g].y + s[3][g].y)};
+// Sum over each row of 16 lanes, returned to every lane of the row (all
+// lanes active): the first four steps of wsum_all.
+__device__ inline double rsum16(double v) {
+    v += dpp_move(v, 0);
+    v += dpp_move(v, 1);
+    v += dpp_move(v, 2);
+    v += dpp_move(v, 3);
+    return v;
 }
 
-// conj(a) b summed over the wavefront, into s[wv][g] (every lane active)
-__device__ inline void dot_to_lds(double2 a, double2 b, double2 (*s)[kRedG], int wv, int g) {
-    const double re = wsum_all(a.x * b.x + a.y * b.y), im = wsum_all(a.x * b.y - a.y * b.x);
-    if (threadIdx.x % kW == 0) s[wv][g] = {re, im};
+// part[(j0 + g) nch + c] = sum over the workgroup's threads of conj(a[g]) b,
+// for j0 + g < k.  sp: kDotG x kChunkN complex of LDS.  Thread t sums the
+// products of vector g = t / 32 from threads t % 32 + 32 i (i < 8), then
+// each half-wavefront's two rows of 16 lanes are summed.  Every thread of
+// the workgroup calls this.
+__device__ inline void chunk_dots(const double2 (&a)[kDotG], double2 b, double2 *sp, int j0, int k,
+                                  double2 *part, int64_t nch, int64_t c) {
+    const int t = threadIdx.x, lane = t % kW, wv = t / kW;
+#pragma unroll
+    for (int g = 0; g < kDotG; ++g)
+        sp[g * kChunkN + t] = {a[g].x * b.x + a[g].y * b.y, a[g].x * b.y - a[g].y * b.x};
+    __syncthreads();
+    const int g = t / 32, q = t % 32;
+    double re = 0, im = 0;
+#pragma unroll
+    for (int i = 0; i < kChunkN / 32; ++i) {
+        const double2 v = sp[g * kChunkN + q + 32 * i];
+        re += v.x;
+        im += v.y;
+    }
+    re = rsum16(re);
+    im = rsum16(im);
+    // vector 2 wv: rows at lanes 0, 16; vector 2 wv + 1: lanes 32, 48
+    const double2 s0 = {lane_value(re, 0) + lane_value(re, 16), lane_value(im, 0) + lane_value(im, 16)};
+    const double2 s1 = {lane_value(re, 32) + lane_value(re, 48), lane_value(im, 32) + lane_value(im, 48)};
+    if (lane == 0) {
+        if (j0 + 2 * wv < k) part[(int64_t)(j0 + 2 * wv) * nch + c] = s0;
+        if (j0 + 2 * wv + 1 < k) part[(int64_t)(j0 + 2 * wv + 1) * nch + c] = s1;
+    }
+    __syncthreads();   // sp is reused
 }
 
+// a[g] = V_{j0 + g} over the thread's row, 0 outside the vectors
+__device__ inline void load_rows(double2 (&a)[kDotG], const double2 *V, int64_t ldv, int j0, int k, int64_t i,
+                                 bool in) {
+#pragma unroll
+    for (int g = 0; g < kDotG; ++g) a[g] = (in && j0 + g < k) ? V[(int64_t)(j0 + g) * ldv + i] : double2{0, 0};
+}
+
+// grid (xdim, ceil(k / kDotG)) with xdim >= nch a multiple of 8, so that
+// workgroup (c, y) runs on the same XCD as workgroup c of the update
+// kernels (workgroups are dealt to the eight XCDs in launch order)
 __global__ __launch_bounds__(kChunkN) void k_cgs_dots(const double2 *V, int64_t ldv, int k, const double2 *w,
                                                      int64_t n, double2 *part, int64_t nch) {
-    __shared__ double2 s[4][kRedG];
-    const int64_t c = blockIdx.x, i = c * kChunkN + threadIdx.x;
-    const int j0 = blockIdx.y * kDotG, wv = threadIdx.x / kW;
+    __shared__ double2 sp[kDotG * kChunkN];
+    const int64_t c = blockIdx.x;
+    if (c >= nch) return;   // the whole workgroup
+    const int64_t i = c * kChunkN + threadIdx.x;
+    const int j0 = blockIdx.y * kDotG;
     const bool in = i < n;
     const double2 b = in ? w[i] : double2{0, 0};
     double2 a[kDotG];
-#pragma unroll
-    for (int g = 0; g < kDotG; ++g) a[g] = (in && j0 + g < k) ? V[(int64_t)(j0 + g) * ldv + i] : double2{0, 0};
-#pragma unroll
-    for (int g = 0; g < kDotG; ++g)
-        if (j0 + g < k) dot_to_lds(a[g], b, s, wv, g);   // uniform over the workgroup
-    __syncthreads();
-    const int g = threadIdx.x;
-    if (g < kDotG && j0 + g < k) part[(int64_t)(j0 + g) * nch + c] = sum4(s, g);
+    load_rows(a, V, ldv, j0, k, i, in);
+    chunk_dots(a, b, sp, j0, k, part, nch, c);
 }
 
-// DOTS: `next` receives the partial projections of the updated w (the
-// second pass's part); otherwise npart[c] receives the chunk's |w|^2.
-// hout[j] = h_j is written by workgroup 0 (hout may be host-mapped memory).
+// h_j sums part[j][0 .. npin).  DOTS: `next` receives the partial
+// projections of the updated w (the second pass's part, one per chunk);
+// otherwise npart[c] receives the chunk's |w|^2.  hout[j] = h_j is written
+// by workgroup 0.  One workgroup per chunk.
 template <bool DOTS>
 __global__ __launch_bounds__(kChunkN) void k_cgs_update(double2 *w, const double2 *V, int64_t ldv, int k,
-                                                       const double2 *part, int64_t nch, double2 *hout,
+                                                       const double2 *part, int64_t npin, double2 *hout,
                                                        int64_t n, double2 *next, double *npart) {
     __shared__ double2 s_h[kRedG];
-    __shared__ double2 s[4][kRedG];
+    __shared__ double2 sp[kDotG * kChunkN];
     const int wv = threadIdx.x / kW, lane = threadIdx.x % kW;
-    const int64_t c = blockIdx.x, i = c * kChunkN + threadIdx.x;
+    const int64_t c = blockIdx.x, nch = gridDim.x, i = c * kChunkN + threadIdx.x;
     const bool in = i < n;
     double2 t = in ? w[i] : double2{0, 0};
     for (int j0 = 0; j0 < k; j0 += kRedG) {
         const int nb = k - j0 < kRedG ? k - j0 : kRedG;
-        // wavefront wv sums h_j for j = j0 + wv + 4 q over the chunks
-        double re[kRedQ], im[kRedQ];
-#pragma unroll
-        for (int q = 0; q < kRedQ; ++q) re[q] = im[q] = 0.0;
-        for (int64_t cc = lane; cc < nch; cc += kW) {
-#pragma unroll
-            for (int q = 0; q < kRedQ; ++q)
-                if (wv + 4 * q < nb) {
-                    const double2 p = part[(int64_t)(j0 + wv + 4 * q) * nch + cc];
-                    re[q] += p.x;
-                    im[q] += p.y;
+        {   // h_{j0 + jj}, jj = thread / 4: each of four lanes sums every fourth chunk
+            const int jj = threadIdx.x / 4, q = threadIdx.x % 4;
+            double re = 0, im = 0;
+            if (jj < nb) {
+                const double2 *pj = part + (int64_t)(j0 + jj) * npin;
+#pragma unroll 8
+                for (int64_t cc = q; cc < npin; cc += 4) {
+                    const double2 p = pj[cc];
+                    re += p.x;
+                    im += p.y;
                 }
-        }
-#pragma unroll
-        for (int q = 0; q < kRedQ; ++q)
-            if (wv + 4 * q < nb) {   // uniform over the wavefront
-                const double a = wsum_all(re[q]), b = wsum_all(im[q]);
-                if (lane == 0) s_h[wv + 4 * q] = {a, b};
             }
+            re += dpp_move(re, 0);
+            re += dpp_move(re, 1);
+            im += dpp_move(im, 0);
+            im += dpp_move(im, 1);
+            if (q == 0 && jj < nb) s_h[jj] = {re, im};
+        }
         __syncthreads();
         if (blockIdx.x == 0 && threadIdx.x < nb) hout[j0 + threadIdx.x] = s_h[threadIdx.x];
         if (in) {
-#pragma unroll 8
+#pragma unroll 16
             for (int jj = 0; jj < nb; ++jj) t = csub(t, cmul(V[(int64_t)(j0 + jj) * ldv + i], s_h[jj]));
         }
         __syncthreads();
     }
     if (in) w[i] = t;
     if constexpr (DOTS) {
-        for (int j0 = 0; j0 < k; j0 += kRedG) {
-            const int nb = k - j0 < kRedG ? k - j0 : kRedG;
-            for (int g0 = 0; g0 < nb; g0 += 16) {
-                double2 a[16];
+        // the next batch's rows load while the current batch is summed
+        double2 a[kDotG], an[kDotG];
+        load_rows(a, V, ldv, 0, k, i, in);
+        for (int j0 = 0; j0 < k; j0 += kDotG) {
+            if (j0 + kDotG < k) load_rows(an, V, ldv, j0 + kDotG, k, i, in);
+            chunk_dots(a, t, sp, j0, k, next, nch, c);
 #pragma unroll
-                for (int g = 0; g < 16; ++g)
-                    a[g] = (in && g0 + g < nb) ? V[(int64_t)(j0 + g0 + g) * ldv + i] : double2{0, 0};
-#pragma unroll
-                for (int g = 0; g < 16; ++g)
-                    if (g0 + g < nb) dot_to_lds(a[g], t, s, wv, g0 + g);
-            }
-            __syncthreads();
-            if (threadIdx.x < nb) next[(int64_t)(j0 + threadIdx.x) * nch + c] = sum4(s, threadIdx.x);
-            __syncthreads();
+            for (int g = 0; g < kDotG; ++g) a[g] = an[g];
         }
     } else {
         const double nn = wsum_all(in ? t.x * t.x + t.y * t.y : 0.0);
-        if (lane == 0) s[wv][0].x = nn;
+        if (lane == 0) sp[wv].x = nn;
         __syncthreads();
-        if (threadIdx.x == 0) npart[c] = (s[0][0].x + s[1][0].x) + (s[2][0].x + s[3][0].x);
+        if (threadIdx.x == 0) npart[c] = (sp[0].x + sp[1].x) + (sp[2].x + sp[3].x);
     }
 }
 
-// dst = src / h with h = sqrt(sum_c npart[c]) (0 -> dst = 0).  With pin
-// (host-mapped), workgroup 0 then publishes the step's Hessenberg column:
-// pin[0 .. k2) = hcol[0 .. k2), pin[k2].x = h, and last *tag = seq (also
-// host-mapped), after a system-scope fence of every store before it, so a
-// host that sees the tag reads a complete column.
+// Publication of a step's Hessenberg column by one workgroup (every thread
+// of it calls this): pin[0 .. k2) = hcol[0 .. k2), pin[k2].x = h, and last
+// *tag = seq, after a system-scope fence of every store before it, so a
+// host that sees the tag reads a complete column (pin and tag host-mapped).
+__device__ inline void publish_column(const double2 *hcol, int k2, double h, double2 *pin,
+                                      unsigned long long *tag, unsigned long long seq) {
+    for (int t = threadIdx.x; t < k2; t += blockDim.x) pin[t] = hcol[t];
+    if (threadIdx.x == 0) pin[k2] = {h, 0.0};
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(tag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// |w| from the chunks' parts of |w|^2, the same sum in every wavefront
+__device__ inline double norm_from_parts(const double *npart, int64_t nch) {
+    double a = 0;
+    for (int64_t c = threadIdx.x % kW; c < nch; c += kW) a += npart[c];
+    return sqrt(wsum_all(a));
+}
+
+// dst = src / h with h = sqrt(sum_c npart[c]) (0 -> dst = 0); with pin,
+// workgroup 0 publishes the step's column (publish_column).
 __global__ __launch_bounds__(kChunkN) void k_cgs_scale(double2 *dst, const double2 *src, const double *npart,
                                                       int64_t nch, int64_t n, const double2 *hcol, int k2,
                                                       double2 *pin, unsigned long long *tag,
                                                       unsigned long long seq) {
-    __shared__ double s_h;
-    if (threadIdx.x < kW) {
-        double a = 0;
-        for (int64_t c = threadIdx.x; c < nch; c += kW) a += npart[c];
-        a = wsum_all(a);
-        if (threadIdx.x == 0) s_h = sqrt(a);
-    }
-    __syncthreads();
-    const double h = s_h, inv = h > 0 ? 1.0 / h : 0.0;
+    const double h = norm_from_parts(npart, nch), inv = h > 0 ? 1.0 / h : 0.0;
     const int64_t i = blockIdx.x * (int64_t)kChunkN + threadIdx.x;
     if (i < n) dst[i] = {inv * src[i].x, inv * src[i].y};
-    if (blockIdx.x == 0 && pin) {
-        for (int t = threadIdx.x; t < k2; t += kChunkN) pin[t] = hcol[t];
-        if (threadIdx.x == 0) pin[k2] = {h, 0.0};
-        __threadfence_system();
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_store(tag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (blockIdx.x == 0 && pin) publish_column(hcol, k2, h, pin, tag, seq);
+}
+
+// The normalisation that ends an Arnoldi step fused with the block-Jacobi
+// product that starts the next: V_k = w / |w| and z = P^-1 V_k, one
+// wavefront per row of a diagonal block as in k_mbj_apply; the row's sum
+// is formed from w and scaled once (z = (P^-1 w) / |w|).  One extra
+// workgroup, the first, publishes the finished step's column meanwhile.
+__global__ __launch_bounds__(256) void k_mbj_scale_apply(int64_t n2, int B, int nb, const double2 *Minv,
+                                                         const double2 *w, const double *npart, int64_t nch,
+                                                         double2 *vk, double2 *z, const double2 *hcol, int k2,
+                                                         double2 *pin, unsigned long long *tag,
+                                                         unsigned long long seq) {
+    if (blockIdx.x == 0) {   // the extra first workgroup publishes
+        publish_column(hcol, k2, norm_from_parts(npart, nch), pin, tag, seq);
+        return;
+    }
+    const int64_t wid = ((blockIdx.x - 1) * (int64_t)blockDim.x + threadIdx.x) / kW;
+    const int lane = threadIdx.x % kW;
+    const int64_t ld = 2 * B;
+    const int64_t m = wid / ld, r = wid % ld;
+    const int64_t b = m < nb ? min((int64_t)B, n2 - m * B) : 0;
+    const int64_t n = 2 * b;
+    const bool ok = r < n;   // uniform over the wavefront
+    // the loads of the norm's parts and of the row are issued together
+    double a = 0;
+    for (int64_t c = lane; c < nch; c += kW) a += npart[c];
+    double re = 0, im = 0;
+    if (ok) {
+        const double2 *row = Minv + m * ld * ld + r * ld;
+        for (int64_t q = lane; q < n; q += kW) {
+            const int64_t g = (q < b ? 0 : n2) + m * B + (q % b);
+            const double2 e = row[q], x = w[g];
+            re += e.x * x.x - e.y * x.y;
+            im += e.x * x.y + e.y * x.x;
+        }
+    }
+    const double h = sqrt(wsum_all(a)), inv = h > 0 ? 1.0 / h : 0.0;   // as norm_from_parts
+    re = wsum_all(re);
+    im = wsum_all(im);
+    if (ok && lane == 0) {
+        const int64_t go = (r < b ? 0 : n2) + m * B + (r % b);
+        const double2 x = w[go];
+        z[go] = {inv * re, inv * im};
+        vk[go] = {inv * x.x, inv * x.y};
     }
 }
 
@@ -1205,13 +1288,13 @@ int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n, hipSt
 }
 int64_t arnoldi_chunks(int64_t n) { return (n + kChunkN - 1) / kChunkN; }
 int arnoldi_cgs2(double2 *w, double2 *V, int64_t ldv, int k, int64_t n, double2 *part, double *npart,
-                 double2 *hcol, double2 *pin, unsigned long long *tag, unsigned long long seq,
+                 double2 *hcol, bool finish, double2 *pin, unsigned long long *tag, unsigned long long seq,
                  hipStream_t s) {
     if (k < 1 || n < 1) return MBEM_EINVAL;
     const int64_t nch = arnoldi_chunks(n);
     double2 *part2 = part + (int64_t)k * nch;
-    hipLaunchKernelGGL(k_cgs_dots, dim3((unsigned)nch, (unsigned)((k + kDotG - 1) / kDotG)), dim3(kChunkN), 0, s,
-                       V, ldv, k, w, n, part, nch);
+    hipLaunchKernelGGL(k_cgs_dots, dim3((unsigned)((nch + 7) / 8 * 8), (unsigned)((k + kDotG - 1) / kDotG)),
+                       dim3(kChunkN), 0, s, V, ldv, k, w, n, part, nch);
     MBEM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_cgs_update<true>, dim3((unsigned)nch), dim3(kChunkN), 0, s, w, V, ldv, k, part, nch,
                        hcol, n, part2, nullptr);
@@ -1219,8 +1302,27 @@ int arnoldi_cgs2(double2 *w, double2 *V, int64_t ldv, int k, int64_t n, double2 
     hipLaunchKernelGGL(k_cgs_update<false>, dim3((unsigned)nch), dim3(kChunkN), 0, s, w, V, ldv, k, part2, nch,
                        hcol + k, n, nullptr, npart);
     MBEM_HIP(hipGetLastError());
+    if (finish) MBEM_TRY(arnoldi_finish(w, V, ldv, k, n, npart, hcol, pin, tag, seq, s));
+    return MBEM_OK;
+}
+int arnoldi_finish(const double2 *w, double2 *V, int64_t ldv, int k, int64_t n, const double *npart,
+                   const double2 *hcol, double2 *pin, unsigned long long *tag, unsigned long long seq,
+                   hipStream_t s) {
+    const int64_t nch = arnoldi_chunks(n);
     hipLaunchKernelGGL(k_cgs_scale, dim3((unsigned)nch), dim3(kChunkN), 0, s, V + (int64_t)k * ldv, w, npart,
-                       nch, n, (const double2 *)hcol, 2 * k, pin, tag, seq);
+                       nch, n, hcol, 2 * k, pin, tag, seq);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+bool mbj_present(const mbem_op *op) { return op->d_minv && op->nb > 0; }
+int mbj_scale_apply_run(const mbem_op *op, const double2 *w, const double *npart, int64_t n, double2 *vk,
+                        double2 *z, const double2 *hcol, int k, double2 *pin, unsigned long long *tag,
+                        unsigned long long seq, hipStream_t s, bool trans) {
+    if (!mbj_present(op) || n != 2 * op->n2 || !pin || !tag) return MBEM_EINVAL;
+    const int64_t rows = (int64_t)op->nb * 2 * op->B;
+    hipLaunchKernelGGL(k_mbj_scale_apply, dim3((unsigned)((rows * kW + 255) / 256 + 1)), dim3(256), 0, s, op->n2,
+                       op->B, op->nb, trans ? op->d_minv_t : op->d_minv, w, npart, arnoldi_chunks(n), vk, z,
+                       hcol, 2 * k, pin, tag, seq);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }

@@ -308,18 +308,30 @@ int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z,
                   hipStream_t s, bool trans = false);
 int vec_norm2(const double2 *v, int64_t n, double *out_dev, hipStream_t s);
 // Classical Gram-Schmidt with one reorthogonalisation of w (n rows)
-// against the k orthonormal columns of V (leading dimension ldv), then
-// V_k = w / |w| (column k of V; 0 when w vanishes).  The coefficients of
-// both passes go to the device column hcol[0..k) = h1, hcol[k..2k) = h2.
-// With pin (host-mapped memory of 2k + 1 complex), the last kernel also
-// writes pin[0..2k) = hcol, pin[2k].x = |w| and then, after a system-scope
-// fence, *tag = seq (host-mapped): a host that reads the tag reads the
-// whole column.  part: 2 k arnoldi_chunks(n) complex and npart:
+// against the k orthonormal columns of V (leading dimension ldv).  The
+// coefficients of both passes go to the device column hcol[0..k) = h1,
+// hcol[k..2k) = h2, and the chunks' parts of |w|^2 to npart.  With finish,
+// arnoldi_finish follows.  part: 2 k arnoldi_chunks(n) complex and npart:
 // arnoldi_chunks(n) doubles of device scratch.
 int64_t arnoldi_chunks(int64_t n);
 int arnoldi_cgs2(double2 *w, double2 *V, int64_t ldv, int k, int64_t n, double2 *part, double *npart,
-                 double2 *hcol, double2 *pin, unsigned long long *tag, unsigned long long seq,
+                 double2 *hcol, bool finish, double2 *pin, unsigned long long *tag, unsigned long long seq,
                  hipStream_t s);
+// V_k = w / |w| (column k of V; 0 when w vanishes), |w| from npart; then
+// the step's column is published to host-mapped memory: pin[0..2k) = hcol,
+// pin[2k].x = |w| and, after a system-scope fence, *tag = seq, so a host
+// that reads the tag reads the whole column.
+int arnoldi_finish(const double2 *w, double2 *V, int64_t ldv, int k, int64_t n, const double *npart,
+                   const double2 *hcol, double2 *pin, unsigned long long *tag, unsigned long long seq,
+                   hipStream_t s);
+// arnoldi_finish fused with the block-Jacobi product of the next step:
+// vk = w / |w|, z = P^-1 vk (P^-T with trans), and the finished step's
+// column (k coefficients per pass) published as by arnoldi_finish.  Needs
+// a preconditioner (mbj_present).
+bool mbj_present(const mbem_op *op);
+int mbj_scale_apply_run(const mbem_op *op, const double2 *w, const double *npart, int64_t n, double2 *vk,
+                        double2 *z, const double2 *hcol, int k, double2 *pin, unsigned long long *tag,
+                        unsigned long long seq, hipStream_t s, bool trans);
 int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n,
                    hipStream_t s);
 int vec_axpy(double2 *y, const double2 *x, double2 a, int64_t n,
