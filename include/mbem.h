@@ -163,8 +163,9 @@ typedef struct {
     double t_ssq_ms;      /* Sauter-Schwab kernel                            */
     double t_mass_ms;     /* mass matrix                                     */
     double t_matvec_ms;   /* solve: sum of the timed dense GEMV kernel times
-                             (the products of the first two Arnoldi steps of
-                             every GMRES run: a sample, not the total)       */
+                             (the products of the third and fourth Arnoldi
+                             steps of every GMRES run: a sample, not the
+                             total)                                          */
     int32_t n_matvec;     /* solve: number of GEMV launches timed             */
     int64_t n_regular_pairs; /* regular element pairs (all launches)          */
     /* mbem_grad_sigma_ext: wall times of its phases                          */

@@ -113,10 +113,12 @@ struct Gmres {
     // address them
     double2 *hpin[2] = {nullptr, nullptr};
     double2 *hmap[2] = {nullptr, nullptr};
-    // matvec timing: events around the products of the first kTimedSteps
-    // Arnoldi steps only (an event between two kernels costs the stream
-    // several microseconds of idle time)
-    static constexpr int kTimedSteps = 2;
+    // matvec timing: events around the products of Arnoldi steps kTimed0 ..
+    // kTimed0 + kTimedSteps - 1 only.  An event between two kernels costs
+    // the stream several microseconds of idle time, and the first steps'
+    // products start on an idle stream, so their events would also time
+    // the host's launches.
+    static constexpr int kTimed0 = 2, kTimedSteps = 2;
     hipEvent_t ev0[kTimedSteps] = {}, ev1[kTimedSteps] = {};
     double t_matvec = 0.0;
     int n_matvec = 0;
@@ -130,21 +132,24 @@ struct Gmres {
     int apply(const double2 *x, double2 *y) {   // y = Z x or Z^T x
         return trans ? matvec_t_run(op, x, y, tpart, s) : matvec_run(op, x, y, tmp, s);
     }
+    static bool timed(int q) { return q >= kTimed0 && q < kTimed0 + kTimedSteps; }
     int step_matvec(const double2 *x, double2 *y, int q) {
-        if (q >= kTimedSteps) return apply(x, y);
-        MBEM_HIP(hipEventRecord(ev0[q], s));
+        if (!timed(q)) return apply(x, y);
+        const int e = q - kTimed0;
+        MBEM_HIP(hipEventRecord(ev0[e], s));
         if (trans) {
             MBEM_TRY(matvec_t_run(op, x, y, tpart, s));
-            MBEM_HIP(hipEventRecord(ev1[q], s));
+            MBEM_HIP(hipEventRecord(ev1[e], s));
             return MBEM_OK;
         }
-        return matvec_run(op, x, y, tmp, s, ev1[q]);   // ev1 right after the GEMV
+        return matvec_run(op, x, y, tmp, s, ev1[e]);   // ev1 right after the GEMV
     }
     void collect(int q) {   // once step q's column has arrived
-        if (q >= kTimedSteps) return;
+        if (!timed(q)) return;
+        const int e = q - kTimed0;
         float t = 0.f;
-        if (hipEventSynchronize(ev1[q]) == hipSuccess &&
-            hipEventElapsedTime(&t, ev0[q], ev1[q]) == hipSuccess) { t_matvec += t; ++n_matvec; }
+        if (hipEventSynchronize(ev1[e]) == hipSuccess &&
+            hipEventElapsedTime(&t, ev0[e], ev1[e]) == hipSuccess) { t_matvec += t; ++n_matvec; }
     }
     // Wait until the tag `seq` of step `slot` is in pinned memory.  The host
     // spins on the tag.  Asking the stream for its state puts a marker into

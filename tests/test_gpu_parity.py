@@ -146,6 +146,40 @@ def test_solve_fp64_and_farfield(case):
     assert np.allclose(cs, co, rtol=1e-10, atol=1e-12 * abs(co[0]))
 
 
+def test_gmres_iterates_match_oracle(case):
+    """A GMRES run cut off after m Arnoldi steps returns the m-step iterate
+    of right-preconditioned GMRES: the oracle's GMRES (Sec. 5, classical
+    Gram-Schmidt twice) on the dense Morton-ordered Z with the same
+    block-Jacobi blocks, stopped after m steps, gives the same x, and the
+    explicit residual does not grow with m.  With a preconditioner each
+    step's column is published by the next step's first launch and the
+    last one by the separate normalisation; without one every step ends
+    with its own normalisation: both orders are covered."""
+    mbem = _mbem()
+    S = case["S"]
+    p = S.perm
+    Zm = case["Z"][np.ix_(p, p)]
+    b = S.rhs(KH[None], POL[None])
+    bn = b.cpu().numpy()[0]
+    try:
+        for B in (100, 0):
+            S.precond_setup(B)
+            blocks = solver.mbj_matrices(Zm, B) if B else None
+            pre = (lambda v: solver.mbj_apply(blocks, v, B)) if B else None
+            prev = np.inf
+            for m in (1, 2, 5, 9):
+                x, st, code = S.solve(b, tol=1e-15, maxit=m)
+                assert code == mbem.MBEM_ENOCONV and st.iters == m, (B, m, code, st.iters)
+                xo, ko, _ = solver.gmres(lambda v: Zm @ v, bn, precond=pre, tol=0.0, maxit=m)
+                assert ko == m
+                err = _rel(x.cpu().numpy()[0], xo)
+                assert err < 1e-10, (B, m, err)
+                assert st.rel_resid <= prev * (1 + 1e-12), (B, m, st.rel_resid, prev)
+                prev = st.rel_resid
+    finally:
+        S.precond_setup(100)
+
+
 def test_solve_unpreconditioned_and_whole_block(case):
     """GMRES without the preconditioner reaches the oracle's LU solution; a
     single block covering the whole system makes P = Z, so GMRES converges
