@@ -211,6 +211,7 @@ int mbj_transpose_run(mbem_op *op, hipStream_t s) {
     hipLaunchKernelGGL(k_transpose_blocks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (int64_t)op->nb, ld,
                        (const double2 *)op->d_minv, op->d_minv_t);
     MBEM_HIP(hipGetLastError());
+    if (op->prec == MBEM_MIXED) MBEM_TRY(mbj_copy_c64(op->d_minv_t, &op->d_minv_t32, n, s));
     return MBEM_OK;
 }
 

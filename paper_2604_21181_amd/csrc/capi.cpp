@@ -82,6 +82,8 @@ static void op_free_device(mbem_op *op) {
     dfree(op->d_mval);
     dfree(op->d_minv);
     dfree(op->d_minv_t);
+    dfree(op->d_minv32);
+    dfree(op->d_minv_t32);
     dfree(op->d_lu);
     dfree(op->d_work);
     dfree(op->d_kconst);
@@ -102,6 +104,7 @@ struct Gmres {
     int64_t N;
     int m;              // Krylov dimension limit
     bool trans = false;
+    bool lowp = false;          // MIXED: the complex64 copy of the block-Jacobi inverses
     double2 *V, *w, *z, *tmp, *hdev;
     double2 *tpart = nullptr;   // partial sums of the transposed product
     double *ndev;
@@ -185,6 +188,7 @@ struct Gmres {
 static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
     g.op = op;
     g.s = s;
+    g.lowp = op->prec == MBEM_MIXED;
     g.N = 2 * op->n2;
     g.m = maxit;
     // V, w, z, matvec partials (4 n2), the coefficients y (m) and a norm,
@@ -273,9 +277,9 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
         if (fuse && k > 0) {
             const int ps = (k - 1) & 1;
             MBEM_TRY(mbj_scale_apply_run(g.op, g.w, g.npart, N, vk, g.z, g.hcol, k, g.hmap[ps], tag_of(ps),
-                                         (unsigned long long)k, s, g.trans));
+                                         (unsigned long long)k, s, g.trans, g.lowp));
         } else {
-            MBEM_TRY(mbj_apply_run(g.op, vk, g.z, s, g.trans));
+            MBEM_TRY(mbj_apply_run(g.op, vk, g.z, s, g.trans, g.lowp));
         }
         MBEM_TRY(g.step_matvec(g.z, g.w, k));
         MBEM_TRY(arnoldi_cgs2(g.w, g.V, N, k + 1, N, g.ppart, g.npart, g.hcol, !fuse, g.hmap[slot], tag_of(slot),
@@ -341,7 +345,7 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
     for (int i = 0; i < k; ++i) yd[i] = {y[i].real(), y[i].imag()};
     MBEM_HIP(hipMemcpyAsync(g.hdev, yd.data(), sizeof(double2) * k, hipMemcpyHostToDevice, s));
     MBEM_TRY(vec_combine(g.w, g.V, N, k, g.hdev, N, s));
-    MBEM_TRY(mbj_apply_run(g.op, g.w, x, s, g.trans));
+    MBEM_TRY(mbj_apply_run(g.op, g.w, x, s, g.trans, g.lowp));
     MBEM_HIP(hipStreamSynchronize(s));
     *iters = k;
     *est = res;

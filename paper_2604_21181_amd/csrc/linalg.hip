@@ -896,8 +896,13 @@ static int mbj_factor_invert_gemm(int ld, int nb, int n_last, double2 *LUb, int3
     return MBEM_OK;
 }
 
-// z = blockdiag(A_m^-1) v; one wavefront per row of a block.
-__global__ __launch_bounds__(256) void k_mbj_apply(int64_t n2, int B, int nb, const double2 *Minv,
+__device__ inline double2 ld_c(const double2 *p) { return *p; }
+__device__ inline double2 ld_c(const float2 *p) { const float2 v = *p; return {(double)v.x, (double)v.y}; }
+
+// z = blockdiag(A_m^-1) v; one wavefront per row of a block.  TM: the
+// stored inverses' type (complex128, or the complex64 copy); FP64 sums.
+template <typename TM>
+__global__ __launch_bounds__(256) void k_mbj_apply(int64_t n2, int B, int nb, const TM *Minv,
                                                    const double2 *v, double2 *z) {
     const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kW;
     const int lane = threadIdx.x % kW;
@@ -907,11 +912,11 @@ __global__ __launch_bounds__(256) void k_mbj_apply(int64_t n2, int B, int nb, co
     const int64_t b = min((int64_t)B, n2 - m * B);
     const int64_t n = 2 * b;
     if (r >= n) return;
-    const double2 *row = Minv + m * ld * ld + r * ld;
+    const TM *row = Minv + m * ld * ld + r * ld;
     double re = 0, im = 0;
     for (int64_t q = lane; q < n; q += kW) {
         const int64_t g = (q < b ? 0 : n2) + m * B + (q % b);
-        const double2 a = row[q], x = v[g];
+        const double2 a = ld_c(row + q), x = v[g];
         re += a.x * x.x - a.y * x.y;
         im += a.x * x.y + a.y * x.x;
     }
@@ -921,8 +926,11 @@ __global__ __launch_bounds__(256) void k_mbj_apply(int64_t n2, int B, int nb, co
 }
 
 int mbj_setup_run(mbem_op *op, int B, hipStream_t s, bool keep) {
-    // the transposed inverses belong to the previous blocks
+    // the transposed inverses belong to the previous blocks (and so does the
+    // complex64 copy, which is rewritten below; its allocation is kept when
+    // the size matches)
     if (op->d_minv_t) { MBEM_HIP(hipFree(op->d_minv_t)); op->d_minv_t = nullptr; }
+    if (op->d_minv_t32) { MBEM_HIP(hipFree(op->d_minv_t32)); op->d_minv_t32 = nullptr; }
     op->B = 0; op->nb = 0;
     if (B > kMaxBlock) { set_error("preconditioner block above 512 is not supported"); return MBEM_EINVAL; }
     const int64_t n2 = op->n2;
@@ -934,6 +942,7 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s, bool keep) {
     const size_t lu_bytes = B > 0 ? bytes + sizeof(int32_t) * (nb * ld + 1) : 0;
     if (op->d_minv && op->minv_bytes != bytes) {
         MBEM_HIP(hipFree(op->d_minv)); op->d_minv = nullptr; op->minv_bytes = 0;
+        if (op->d_minv32) { MBEM_HIP(hipFree(op->d_minv32)); op->d_minv32 = nullptr; }
     }
     if (op->d_lu && op->lu_bytes != lu_bytes) {
         MBEM_HIP(hipFree(op->d_lu)); op->d_lu = nullptr; op->lu_bytes = 0;
@@ -987,21 +996,43 @@ int mbj_setup_run(mbem_op *op, int B, hipStream_t s, bool keep) {
         MBEM_HIP(hipFree(op->d_minv));
         op->d_minv = nullptr;
         op->minv_bytes = 0;
+        if (op->d_minv32) { MBEM_HIP(hipFree(op->d_minv32)); op->d_minv32 = nullptr; }
         return MBEM_ESINGULAR;
     }
     op->B = B;
     op->nb = nb;
+    if (op->prec == MBEM_MIXED) MBEM_TRY(mbj_copy_c64(op->d_minv, &op->d_minv32, (int64_t)nb * ld * ld, s));
     return MBEM_OK;
 }
 
-int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z, hipStream_t s, bool trans) {
+// The GMRES steps of a MIXED operator apply the inverses rounded to
+// complex64 (half the bytes of the product that starts every step); right
+// preconditioning takes any fixed P^-1, and the solution is formed with the
+// same copy, so only the preconditioner changes, not the system solved.
+__global__ void k_round_c64(const double2 *a, float2 *b, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = {(float)a[i].x, (float)a[i].y};
+}
+int mbj_copy_c64(const double2 *src, float2 **dst, int64_t n, hipStream_t s) {
+    if (!*dst) MBEM_HIP(hipMalloc((void **)dst, sizeof(float2) * n));
+    hipLaunchKernelGGL(k_round_c64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, *dst, n);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
+
+int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z, hipStream_t s, bool trans, bool lowp) {
     if (!op->d_minv || op->nb == 0) {
         MBEM_HIP(hipMemcpyAsync(z, v, sizeof(double2) * 2 * op->n2, hipMemcpyDeviceToDevice, s));
         return MBEM_OK;
     }
     const int64_t rows = (int64_t)op->nb * 2 * op->B;
-    hipLaunchKernelGGL(k_mbj_apply, dim3((unsigned)((rows * kW + 255) / 256)), dim3(256), 0, s,
-                       op->n2, op->B, op->nb, trans ? op->d_minv_t : op->d_minv, v, z);
+    const dim3 grid((unsigned)((rows * kW + 255) / 256));
+    const float2 *m32 = lowp ? (trans ? op->d_minv_t32 : op->d_minv32) : nullptr;
+    if (m32)
+        hipLaunchKernelGGL(k_mbj_apply<float2>, grid, dim3(256), 0, s, op->n2, op->B, op->nb, m32, v, z);
+    else
+        hipLaunchKernelGGL(k_mbj_apply<double2>, grid, dim3(256), 0, s, op->n2, op->B, op->nb,
+                           (const double2 *)(trans ? op->d_minv_t : op->d_minv), v, z);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
@@ -1195,7 +1226,8 @@ __global__ __launch_bounds__(kChunkN) void k_cgs_scale(double2 *dst, const doubl
 // wavefront per row of a diagonal block as in k_mbj_apply; the row's sum
 // is formed from w and scaled once (z = (P^-1 w) / |w|).  One extra
 // workgroup, the first, publishes the finished step's column meanwhile.
-__global__ __launch_bounds__(256) void k_mbj_scale_apply(int64_t n2, int B, int nb, const double2 *Minv,
+template <typename TM>
+__global__ __launch_bounds__(256) void k_mbj_scale_apply(int64_t n2, int B, int nb, const TM *Minv,
                                                          const double2 *w, const double *npart, int64_t nch,
                                                          double2 *vk, double2 *z, const double2 *hcol, int k2,
                                                          double2 *pin, unsigned long long *tag,
@@ -1216,10 +1248,10 @@ __global__ __launch_bounds__(256) void k_mbj_scale_apply(int64_t n2, int B, int 
     for (int64_t c = lane; c < nch; c += kW) a += npart[c];
     double re = 0, im = 0;
     if (ok) {
-        const double2 *row = Minv + m * ld * ld + r * ld;
+        const TM *row = Minv + m * ld * ld + r * ld;
         for (int64_t q = lane; q < n; q += kW) {
             const int64_t g = (q < b ? 0 : n2) + m * B + (q % b);
-            const double2 e = row[q], x = w[g];
+            const double2 e = ld_c(row + q), x = w[g];
             re += e.x * x.x - e.y * x.y;
             im += e.x * x.y + e.y * x.x;
         }
@@ -1317,12 +1349,18 @@ int arnoldi_finish(const double2 *w, double2 *V, int64_t ldv, int k, int64_t n, 
 bool mbj_present(const mbem_op *op) { return op->d_minv && op->nb > 0; }
 int mbj_scale_apply_run(const mbem_op *op, const double2 *w, const double *npart, int64_t n, double2 *vk,
                         double2 *z, const double2 *hcol, int k, double2 *pin, unsigned long long *tag,
-                        unsigned long long seq, hipStream_t s, bool trans) {
+                        unsigned long long seq, hipStream_t s, bool trans, bool lowp) {
     if (!mbj_present(op) || n != 2 * op->n2 || !pin || !tag) return MBEM_EINVAL;
     const int64_t rows = (int64_t)op->nb * 2 * op->B;
-    hipLaunchKernelGGL(k_mbj_scale_apply, dim3((unsigned)((rows * kW + 255) / 256 + 1)), dim3(256), 0, s, op->n2,
-                       op->B, op->nb, trans ? op->d_minv_t : op->d_minv, w, npart, arnoldi_chunks(n), vk, z,
-                       hcol, 2 * k, pin, tag, seq);
+    const dim3 grid((unsigned)((rows * kW + 255) / 256 + 1));
+    const float2 *m32 = lowp ? (trans ? op->d_minv_t32 : op->d_minv32) : nullptr;
+    if (m32)
+        hipLaunchKernelGGL(k_mbj_scale_apply<float2>, grid, dim3(256), 0, s, op->n2, op->B, op->nb, m32, w, npart,
+                           arnoldi_chunks(n), vk, z, hcol, 2 * k, pin, tag, seq);
+    else
+        hipLaunchKernelGGL(k_mbj_scale_apply<double2>, grid, dim3(256), 0, s, op->n2, op->B, op->nb,
+                           (const double2 *)(trans ? op->d_minv_t : op->d_minv), w, npart, arnoldi_chunks(n), vk,
+                           z, hcol, 2 * k, pin, tag, seq);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }

@@ -154,6 +154,9 @@ struct mbem_op {
     int32_t B = 0, nb = 0;
     double2 *d_minv = nullptr;      // [nb][2B][2B] inverses
     double2 *d_minv_t = nullptr;    // their transposes (adjoint solves)
+    // complex64 copies of both for the GMRES steps of a MIXED operator
+    // (made with the inverses and with their transposes)
+    float2 *d_minv32 = nullptr, *d_minv_t32 = nullptr;
     double2 *d_lu = nullptr;        // scratch of the factorisation
     size_t minv_bytes = 0, lu_bytes = 0;   // sizes of d_minv and d_lu
     // solver workspace
@@ -304,8 +307,12 @@ int export_blocks_run(const mbem_op *op, double2 *K1, double2 *K2e,
 // matches
 int mbj_setup_run(mbem_op *op, int B, hipStream_t s, bool keep = false);
 // trans: apply P^-T (mbj_transpose_run must have run)
+// *dst (allocated when null) = src rounded to complex64, n elements
+int mbj_copy_c64(const double2 *src, float2 **dst, int64_t n, hipStream_t s);
+// lowp: with the complex64 copy of the inverses when there is one (the
+// GMRES steps of a MIXED operator, which apply the same copy throughout)
 int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z,
-                  hipStream_t s, bool trans = false);
+                  hipStream_t s, bool trans = false, bool lowp = false);
 int vec_norm2(const double2 *v, int64_t n, double *out_dev, hipStream_t s);
 // Classical Gram-Schmidt with one reorthogonalisation of w (n rows)
 // against the k orthonormal columns of V (leading dimension ldv).  The
@@ -331,7 +338,7 @@ int arnoldi_finish(const double2 *w, double2 *V, int64_t ldv, int k, int64_t n, 
 bool mbj_present(const mbem_op *op);
 int mbj_scale_apply_run(const mbem_op *op, const double2 *w, const double *npart, int64_t n, double2 *vk,
                         double2 *z, const double2 *hcol, int k, double2 *pin, unsigned long long *tag,
-                        unsigned long long seq, hipStream_t s, bool trans);
+                        unsigned long long seq, hipStream_t s, bool trans, bool lowp);
 int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n,
                    hipStream_t s);
 int vec_axpy(double2 *y, const double2 *x, double2 a, int64_t n,
