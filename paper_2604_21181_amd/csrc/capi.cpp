@@ -116,6 +116,7 @@ struct Gmres {
     // address them
     double2 *hpin[2] = {nullptr, nullptr};
     double2 *hmap[2] = {nullptr, nullptr};
+    double2 *ypin = nullptr;    // the final coefficients y (pinned host memory)
     // matvec timing: events around the products of Arnoldi steps kTimed0 ..
     // kTimed0 + kTimedSteps - 1 only.  An event between two kernels costs
     // the stream several microseconds of idle time, and the first steps'
@@ -206,8 +207,8 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
         mop->work_elems = need;
     }
     // two column slots of col values and a tag, written by the Arnoldi
-    // kernels straight into fine-grained host memory
-    const size_t pin = 2 * (col + 1);
+    // kernels straight into fine-grained host memory, then y
+    const size_t pin = 2 * (col + 1) + (size_t)maxit;
     if (op->pin_elems < pin) {
         if (mop->h_pin) (void)hipHostFree(mop->h_pin);
         mop->h_pin = nullptr;
@@ -218,6 +219,7 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
     }
     g.hpin[0] = op->h_pin;
     g.hpin[1] = op->h_pin + col + 1;
+    g.ypin = op->h_pin + 2 * (col + 1);
     for (int i = 0; i < 2; ++i) MBEM_HIP(hipHostGetDevicePointer((void **)&g.hmap[i], g.hpin[i], 0));
     g.V = op->d_work;
     g.w = g.V + (size_t)(maxit + 1) * g.N;
@@ -239,32 +241,31 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
 static inline std::complex<double> C(double2 v) { return {v.x, v.y}; }
 
 // Right-preconditioned GMRES on Z P^-1, x0 = 0, CGS2 Arnoldi in FP64.
-// Solves Z x = b to |r_k| <= tol |b| (Arnoldi estimate).  x, b device.
+// Solves Z x = b to |r_k| <= tol |b| (Arnoldi estimate); beta = |b| is the
+// caller's (it has just computed it).  x, b device.
 // The host lags the device by one column: Arnoldi step k (preconditioner,
 // matvec, two projection passes, norm, and V_{k+1} = w / h_{k+1,k} with the
 // norm read on the device) is queued before the host waits for column k-1
 // and applies its Givens rotation, so the stream never drains between
 // steps.  When column k-1 meets the tolerance the queued step k is unused.
-static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *iters,
+// Returns with x's last kernels queued, not finished.
+static int gmres_solve(Gmres &g, const double2 *b, double beta, double tol, double2 *x, int *iters,
                        double *est) {
     const hipStream_t s = g.s;
     const int64_t N = g.N;
-    MBEM_TRY(vec_norm2(b, N, g.ndev, s));
-    double beta = 0;
-    MBEM_HIP(hipMemcpyAsync(&beta, g.ndev, sizeof(double), hipMemcpyDeviceToHost, s));
-    MBEM_HIP(hipStreamSynchronize(s));
     if (!(beta > 0)) {
         MBEM_HIP(hipMemsetAsync(x, 0, sizeof(double2) * N, s));
         *iters = 0;
         *est = 0;
         return MBEM_OK;
     }
-    MBEM_TRY(vec_scale_copy(g.V, b, double2{1.0 / beta, 0.0}, N, s));
     const int m = g.m;
+    // no tag of an earlier solve may match; no Arnoldi kernel of one is
+    // pending (the caller synchronises between solves)
+    for (int i = 0; i < 2; ++i) *(unsigned long long *)(g.hpin[i] + 2 * (m + 1) + 1) = 0ull;
+    MBEM_TRY(vec_scale_copy(g.V, b, double2{1.0 / beta, 0.0}, N, s));
     std::vector<std::complex<double>> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1);
     gv[0] = beta;
-    // no tag of an earlier solve may match: the stream is idle here
-    for (int i = 0; i < 2; ++i) *(unsigned long long *)(g.hpin[i] + 2 * (m + 1) + 1) = 0ull;
     // queue Arnoldi step k; its column lands in hpin[k % 2] with tag k + 1.
     // With a preconditioner the step's normalisation and column run as the
     // first launch of step k + 1 (fused with its block-Jacobi product), or
@@ -341,12 +342,12 @@ static int gmres_solve(Gmres &g, const double2 *b, double tol, double2 *x, int *
         for (int j = i + 1; j < k; ++j) t -= H[(size_t)i * m + j] * y[j];
         y[i] = t / H[(size_t)i * m + i];
     }
-    std::vector<double2> yd(k);
-    for (int i = 0; i < k; ++i) yd[i] = {y[i].real(), y[i].imag()};
-    MBEM_HIP(hipMemcpyAsync(g.hdev, yd.data(), sizeof(double2) * k, hipMemcpyHostToDevice, s));
+    // y through pinned memory: no earlier copy from it is pending (the
+    // caller synchronises between solves), so the host needs no wait here
+    for (int i = 0; i < k; ++i) g.ypin[i] = {y[i].real(), y[i].imag()};
+    MBEM_HIP(hipMemcpyAsync(g.hdev, g.ypin, sizeof(double2) * k, hipMemcpyHostToDevice, s));
     MBEM_TRY(vec_combine(g.w, g.V, N, k, g.hdev, N, s));
     MBEM_TRY(mbj_apply_run(g.op, g.w, x, s, g.trans, g.lowp));
-    MBEM_HIP(hipStreamSynchronize(s));
     *iters = k;
     *est = res;
     return conv ? MBEM_OK : MBEM_ENOCONV;
@@ -794,14 +795,14 @@ static int solve_impl(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nr
             // residual (rounding drift of the long recurrence) did not, one
             // more GMRES from the explicit residual corrects x
             const int maxref = o->max_refine > 0 ? o->max_refine : 3;
-            int st = gmres_solve(g, bc, o->tol, xc, &it, &est);
+            int st = gmres_solve(g, bc, bn, o->tol, xc, &it, &est);
             if (st != MBEM_OK && st != MBEM_ENOCONV) return st;
             total_it += it;
             sweeps += 1;
             MBEM_TRY(residual(bc, xc, &rn));
             for (int sw = 1; sw < maxref && st == MBEM_OK && bn > 0 && !(rn <= o->tol * bn) &&
                              std::isfinite(rn); ++sw) {
-                st = gmres_solve(g, r, o->tol * bn / rn, d, &it, &est);
+                st = gmres_solve(g, r, rn, o->tol * bn / rn, d, &it, &est);
                 if (st != MBEM_OK && st != MBEM_ENOCONV) return st;
                 total_it += it;
                 sweeps += 1;
@@ -820,7 +821,7 @@ static int solve_impl(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nr
             MBEM_HIP(hipMemcpyAsync(r, bc, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
             rn = bn;
             for (int sw = 0; sw < maxref && bn > 0 && !(rn <= o->tol * bn) && std::isfinite(rn); ++sw) {
-                int st = gmres_solve(g, r, std::max(itol, o->tol * bn / rn), d, &it, &est);
+                int st = gmres_solve(g, r, rn, std::max(itol, o->tol * bn / rn), d, &it, &est);
                 if (st != MBEM_OK && st != MBEM_ENOCONV) return st;
                 total_it += it;
                 sweeps += 1;
