@@ -526,7 +526,6 @@ __global__ __launch_bounds__(THREADS, WAVES) void k_regular_range(RngArgs<T, TS>
     __shared__ T s_tp[kQPF * kQP];       // the test triangle's point table, field-major
     __shared__ int32_t s_rec[L.rec()];
     __shared__ int32_t s_te[6];
-    __shared__ int s_act[NB];            // 0 skip, 1 regular pair in T, 2 near pair (mode 1)
     __shared__ KernelConst s_K;
     const int tid = threadIdx.x;
     const int64_t tile = xcd_remap(blockIdx.x, a.total);
@@ -544,38 +543,35 @@ __global__ __launch_bounds__(THREADS, WAVES) void k_regular_range(RngArgs<T, TS>
     const int fsl = tid / 49, pl = (tid % 49) / 7, ql = tid % 7;
     const int32_t b0 = a.rng_off[r], b1 = a.rng_off[r + 1];
 
-    // batch b into s_rec and the kind of each of its pairs into s_act;
-    // returns the number of triangles and the set of kinds present
-    auto batch = [&](int32_t b, bool count, int &kinds) -> int {
-        __syncthreads();                  // the previous batch is done with s_r1, s_rec, s_act
+    // batch b into s_rec; returns its number of triangles
+    auto batch = [&](int32_t b) -> int {
+        __syncthreads();                  // the previous batch is done with s_r1 and s_rec
         if (tid < L.rec()) s_rec[tid] = a.rng_rec[(int64_t)b * L.rec() + tid];
         __syncthreads();
-        const int nbt = s_rec[0];
-        if (tid < nbt) {
-            const int64_t f = s_rec[1 + tid];
-            const int32_t *tf = a.tri + 6 * f;
-            bool act = true;
+        return s_rec[0];
+    };
+    // kind of the pair (e, f), evaluated by each of its 49 lanes: 0 skip
+    // (shares a vertex with e, or mode 3 and near), 1 regular pair in T,
+    // 2 near pair (mode 1; counted once, by the lane `count`, in the range
+    // of f's first vertex)
+    auto pair_kind = [&](int64_t f, bool count) -> int {
+        const int32_t *tf = a.tri + 6 * f;
+        bool act = true;
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) act = act && (s_te[i] != tf[j]);
-            int kind = act ? 1 : 0;
-            if (act && a.mode == 1) {
-                const double *ce = a.einfo + 4 * e, *cf = a.einfo + 4 * f;
-                const double dx = ce[0] - cf[0], dy = ce[1] - cf[1], dz = ce[2] - cf[2];
-                if (sqrt(dx * dx + dy * dy + dz * dz) - ce[3] - cf[3] < a.near_r) {
-                    kind = 2;
-                    // counted once per element pair: in the range of its first vertex
-                    if (count && tf[0] / RNG == r) atomicAdd(a.near_count, 1ull);
-                }
+            for (int j = 0; j < 3; ++j) act = act && (s_te[i] != tf[j]);
+        if (!act) return 0;
+        if (a.mode == 1) {
+            const double *ce = a.einfo + 4 * e, *cf = a.einfo + 4 * f;
+            const double dx = ce[0] - cf[0], dy = ce[1] - cf[1], dz = ce[2] - cf[2];
+            if (sqrt(dx * dx + dy * dy + dz * dz) - ce[3] - cf[3] < a.near_r) {
+                if (count && tf[0] / RNG == r) atomicAdd(a.near_count, 1ull);
+                return 2;
             }
-            if (act && a.mode == 3 && ((a.nmask[e * a.n_chunks + f / kChunk] >> (f % kChunk)) & 1)) kind = 0;
-            s_act[tid] = kind;
         }
-        __syncthreads();
-        kinds = 0;
-        for (int k = 0; k < nbt; ++k) kinds |= 1 << s_act[k];
-        return nbt;
+        if (a.mode == 3 && ((a.nmask[e * a.n_chunks + f / kChunk] >> (f % kChunk)) & 1)) return 0;
+        return 1;
     };
     // B: Tf[c][fs][p][j] = sum_q N_j(q) k, in place over (c, fs, p)
     auto trial_side = [&](int nbt) {
@@ -638,14 +634,13 @@ __global__ __launch_bounds__(THREADS, WAVES) void k_regular_range(RngArgs<T, TS>
 #pragma unroll
         for (int p = 0; p < 7; ++p) Y[k][p] = cx<T>{0, 0};
     for (int32_t b = b0; b < b1; ++b) {
-        int kinds;
-        const int nbt = batch(b, true, kinds);
-        if (!(kinds & 6)) continue;               // uniform over the workgroup
+        const int nbt = batch(b);
         if (tid < 49 * nbt) {
             cx<T> k[12];
-            const int kind = s_act[fsl];
+            const int64_t f = s_rec[1 + fsl];
+            const int kind = pair_kind(f, pl == 0 && ql == 0);
             if (kind != 0) {
-                const int64_t iy = (int64_t)s_rec[1 + fsl] * kQP + ql;
+                const int64_t iy = f * kQP + ql;
                 const T *tp = s_tp + pl;
                 const vec3<T> n = {tp[QN * kQP], tp[(QN + 1) * kQP], tp[(QN + 2) * kQP]};
                 const vec3<T> ta[2] = {{tp[QT1 * kQP], tp[(QT1 + 1) * kQP], tp[(QT1 + 2) * kQP]},
