@@ -318,12 +318,35 @@ static int gmres_solve(Gmres &g, const double2 *b, double beta, double tol, doub
         conv = res <= tol || breakdown;
         return MBEM_OK;
     };
+    // The column that meets the tolerance normally finds the next step
+    // already queued, and that step is wasted.  When the last two residual
+    // estimates extrapolate (at their ratio) to the tolerance at column
+    // q - 1, the host instead waits for that column before queueing step q:
+    // a short drain of the stream if the guess is wrong, one step saved if
+    // it is right.  With the fused start the column is published by step
+    // q's first launch, so it is published here by arnoldi_finish (step q
+    // then recomputes the same V_q and publishes the column once more).
+    double r_prev = 0.0, r_last = 0.0;   // estimates after the last two columns
     int k = 0;       // columns folded into H
     for (int q = 0; q < m; ++q) {
+        if (q >= 3 && r_prev > 0 && r_last * (r_last / r_prev) <= tol) {
+            if (fuse)
+                MBEM_TRY(arnoldi_finish(g.w, g.V, N, q, N, g.npart, g.hcol, g.hmap[(q - 1) & 1],
+                                        tag_of((q - 1) & 1), (unsigned long long)q, s));
+            MBEM_TRY(process(q - 1));
+            k = q;
+            r_prev = r_last;
+            r_last = res;
+            if (conv) break;
+            MBEM_TRY(enqueue(q));
+            continue;
+        }
         MBEM_TRY(enqueue(q));
         if (q >= 1) {
             MBEM_TRY(process(q - 1));
             k = q;
+            r_prev = r_last;
+            r_last = res;
             if (conv) break;
         }
     }
