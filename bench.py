@@ -89,7 +89,7 @@ PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix cores
 # kernel changed after its counters were taken gets None here.
 MEASURED_TRAFFIC = {
     ("k_regular", "fp64"): 21.77e9,    # 13.83 GB read + 7.94 GB written per fill
-    ("k_regular_range", "mixed"): 3.75e9,   # 1.48 GB read + 2.27 GB written per fill
+    ("k_regular_range", "mixed"): 3.52e9,   # 1.42 GB read + 2.10 GB written per fill
     ("k_gemv3", "fp64"): 1.291e9,
     ("k_gemv3", "mixed"): 0.683e9,
 }
