@@ -154,35 +154,38 @@ __global__ __launch_bounds__(256) void k_gemv3(int64_t n2, const TS *K1, const T
 
 struct Coef { double2 iw, ce, cm; };
 
-// kCombLanes consecutive lanes per row split the row's mass slots (a vertex
-// node has 19, each a dependent index-then-value load) and add their partial
-// sums by shuffles in a fixed order.
-constexpr int kCombLanes = 8;
+// LANES consecutive lanes per row split the row's mass slots (a vertex
+// node has 19, each a dependent index-then-value load) and, with the near
+// store, its stored node pairs (about 70 per node on the 5120-triangle
+// spheroid: sixteen lanes then), and add their partial sums by shuffles in a
+// fixed order.
+constexpr int kCombLanes = 8, kCombLanesNear = 16;
 // With the FP64 near store (nv.bits non-null) its blocks are added to the
 // four products: row 2 i + al takes V[4 op + 2 al + be] of every stored
 // node pair (i, j) times x at 2 j + be.
+template <int LANES>
 __global__ __launch_bounds__(256) void k_combine(int64_t n2, const double2 *__restrict__ t,
                                                  const int32_t *__restrict__ mptr, const int32_t *__restrict__ mcol,
                                                  const double *__restrict__ mval, const double2 *__restrict__ xj,
                                                  const double2 *__restrict__ xm, Coef c, NearView nv,
                                                  double2 *__restrict__ y) {
     const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t r = gt / kCombLanes;
-    const int l = (int)(gt % kCombLanes);
+    const int64_t r = gt / LANES;
+    const int l = (int)(gt % LANES);
     double mj[2] = {0, 0}, mm[2] = {0, 0};
     double nq[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};   // K1 xj, K1 xm, K2e xm, K2m xj (store)
     if (r < n2) {
         const int64_t i = r / 2;
         const int al = (int)(r % 2);
         // mass: 2 x 2 block per node pair, value (al, be) at mval[4 s + 2 al + be]
-        for (int32_t s = mptr[i] + l; s < mptr[i + 1]; s += kCombLanes) {
+        for (int32_t s = mptr[i] + l; s < mptr[i + 1]; s += LANES) {
             const int64_t col = 2 * (int64_t)mcol[s];
             const double v0 = mval[4 * s + 2 * al], v1 = mval[4 * s + 2 * al + 1];
             mj[0] += v0 * xj[col].x + v1 * xj[col + 1].x; mj[1] += v0 * xj[col].y + v1 * xj[col + 1].y;
             mm[0] += v0 * xm[col].x + v1 * xm[col + 1].x; mm[1] += v0 * xm[col].y + v1 * xm[col + 1].y;
         }
         if (nv.bits)
-            for (int32_t s = nv.rptr[i] + l; s < nv.rptr[i + 1]; s += kCombLanes) {
+            for (int32_t s = nv.rptr[i] + l; s < nv.rptr[i + 1]; s += LANES) {
                 const int64_t col = 2 * (int64_t)nv.col[s];
                 const double2 *V = nv.val + 12 * (int64_t)s + 2 * al;
                 const double2 a0 = xj[col], a1 = xj[col + 1], b0 = xm[col], b1 = xm[col + 1];
@@ -193,17 +196,17 @@ __global__ __launch_bounds__(256) void k_combine(int64_t n2, const double2 *__re
             }
     }
 #pragma unroll
-    for (int o = kCombLanes / 2; o > 0; o >>= 1) {
+    for (int o = LANES / 2; o > 0; o >>= 1) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            mj[k] += __shfl_xor(mj[k], o, kCombLanes);
-            mm[k] += __shfl_xor(mm[k], o, kCombLanes);
+            mj[k] += __shfl_xor(mj[k], o, LANES);
+            mm[k] += __shfl_xor(mm[k], o, LANES);
         }
         if (nv.bits)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                nq[k][0] += __shfl_xor(nq[k][0], o, kCombLanes);
-                nq[k][1] += __shfl_xor(nq[k][1], o, kCombLanes);
+                nq[k][0] += __shfl_xor(nq[k][0], o, LANES);
+                nq[k][1] += __shfl_xor(nq[k][1], o, LANES);
             }
     }
     if (r >= n2 || l != 0) return;
@@ -234,8 +237,13 @@ int matvec_run(const mbem_op *op, const double2 *x, double2 *y, double2 *tmp, hi
     MBEM_HIP(hipGetLastError());
     if (after_gemv) MBEM_HIP(hipEventRecord(after_gemv, s));
     const mbem_mesh *m = op->mesh;
-    hipLaunchKernelGGL(k_combine, dim3((unsigned)((n2 * kCombLanes + 255) / 256)), dim3(256), 0, s, n2, tmp,
-                       m->d_mptr, m->d_mcol, op->d_mval, x, x + n2, coef_of(op), op->near_view(), y);
+    const NearView nv = op->near_view();
+    if (nv.bits)
+        hipLaunchKernelGGL(k_combine<kCombLanesNear>, dim3((unsigned)((n2 * kCombLanesNear + 255) / 256)), dim3(256),
+                           0, s, n2, tmp, m->d_mptr, m->d_mcol, op->d_mval, x, x + n2, coef_of(op), nv, y);
+    else
+        hipLaunchKernelGGL(k_combine<kCombLanes>, dim3((unsigned)((n2 * kCombLanes + 255) / 256)), dim3(256), 0, s,
+                           n2, tmp, m->d_mptr, m->d_mcol, op->d_mval, x, x + n2, coef_of(op), nv, y);
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
