@@ -154,7 +154,8 @@ def test_gmres_iterates_match_oracle(case):
     explicit residual does not grow with m.  With a preconditioner each
     step's column is published by the next step's first launch and the
     last one by the separate normalisation; without one every step ends
-    with its own normalisation: both orders are covered."""
+    with its own normalisation: both orders are covered, and so is a run
+    stopped one step before it would converge."""
     mbem = _mbem()
     S = case["S"]
     p = S.perm
@@ -176,6 +177,16 @@ def test_gmres_iterates_match_oracle(case):
                 assert err < 1e-10, (B, m, err)
                 assert st.rel_resid <= prev * (1 + 1e-12), (B, m, st.rel_resid, prev)
                 prev = st.rel_resid
+            # near convergence the host waits for the column it expects to
+            # meet the tolerance before queueing another step; cut off one
+            # step short of convergence, the iterate is still the oracle's
+            _, n, _ = solver.gmres(lambda v: Zm @ v, bn, precond=pre, tol=1e-10, maxit=400)
+            x, st, code = S.solve(b, tol=1e-10, maxit=n - 1, max_refine=1)
+            assert code == mbem.MBEM_ENOCONV and st.iters == n - 1, (B, n, code, st.iters)
+            xo, ko, _ = solver.gmres(lambda v: Zm @ v, bn, precond=pre, tol=1e-10, maxit=n - 1)
+            assert ko == n - 1
+            err = _rel(x.cpu().numpy()[0], xo)
+            assert err < 1e-10, (B, n, err)
     finally:
         S.precond_setup(100)
 
