@@ -15,6 +15,34 @@ namespace mbem {
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 
+// The host spins on the tag.  Asking the stream for its state puts a marker
+// into it, which idles the device for microseconds between two kernels, so
+// that is done only after 20 ms without the tag (the steps that publish
+// tags take far less): a failed or drained stream ends the wait with an
+// error, and so does a minute without the tag.
+int wait_host_tag(const unsigned long long *tag, unsigned long long seq, hipStream_t s, const char *what) {
+    using clock = std::chrono::steady_clock;
+    const auto t0 = clock::now();
+    auto next_query = t0 + std::chrono::milliseconds(20);
+    for (unsigned spins = 1;; ++spins) {
+        if (__atomic_load_n(tag, __ATOMIC_ACQUIRE) == seq) return MBEM_OK;
+        if (spins % 1024) continue;
+        const auto now = clock::now();
+        if (now < next_query) continue;
+        next_query = now + std::chrono::milliseconds(20);
+        const hipError_t e = hipStreamQuery(s);
+        if (e != hipSuccess && e != hipErrorNotReady) MBEM_HIP(e);
+        if (e == hipSuccess && __atomic_load_n(tag, __ATOMIC_ACQUIRE) != seq) {
+            set_error(std::string("the stream drained without the ") + what);
+            return MBEM_EDEVICE;
+        }
+        if (now - t0 > std::chrono::seconds(60)) {
+            set_error(std::string("no ") + what + " within a minute");
+            return MBEM_EDEVICE;
+        }
+    }
+}
+
 template <typename T>
 static int dalloc(T **p, size_t n) {
     if (n == 0) n = 1;
@@ -155,34 +183,10 @@ struct Gmres {
         if (hipEventSynchronize(ev1[e]) == hipSuccess &&
             hipEventElapsedTime(&t, ev0[e], ev1[e]) == hipSuccess) { t_matvec += t; ++n_matvec; }
     }
-    // Wait until the tag `seq` of step `slot` is in pinned memory.  The host
-    // spins on the tag.  Asking the stream for its state puts a marker into
-    // it, which idles the device for microseconds between two kernels, so
-    // that is done only after 20 ms without the tag (a step takes far less):
-    // a failed or drained stream ends the wait with an error, and so does a
-    // minute without the tag.
+    // Wait until the tag `seq` of step `slot` is in pinned memory.
     int wait_column(int slot, unsigned long long seq) const {
-        using clock = std::chrono::steady_clock;
-        const unsigned long long *tag = (const unsigned long long *)(hpin[slot] + 2 * (m + 1) + 1);
-        const auto t0 = clock::now();
-        auto next_query = t0 + std::chrono::milliseconds(20);
-        for (unsigned spins = 1;; ++spins) {
-            if (__atomic_load_n(tag, __ATOMIC_ACQUIRE) == seq) return MBEM_OK;
-            if (spins % 1024) continue;
-            const auto now = clock::now();
-            if (now < next_query) continue;
-            next_query = now + std::chrono::milliseconds(20);
-            const hipError_t e = hipStreamQuery(s);
-            if (e != hipSuccess && e != hipErrorNotReady) MBEM_HIP(e);
-            if (e == hipSuccess && __atomic_load_n(tag, __ATOMIC_ACQUIRE) != seq) {
-                set_error("GMRES: the stream drained without the Arnoldi column");
-                return MBEM_EDEVICE;
-            }
-            if (now - t0 > std::chrono::seconds(60)) {
-                set_error("GMRES: no Arnoldi column within a minute");
-                return MBEM_EDEVICE;
-            }
-        }
+        return wait_host_tag((const unsigned long long *)(hpin[slot] + 2 * (m + 1) + 1), seq, s,
+                             "GMRES Arnoldi column");
     }
 };
 

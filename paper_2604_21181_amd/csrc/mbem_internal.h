@@ -16,6 +16,10 @@ struct FillState;
 
 // ---------------------------------------------------------------- errors --
 void set_error(const std::string &msg);
+// Wait until *tag (pinned host memory written by a kernel on stream s after
+// a system-scope fence) equals seq; MBEM_EDEVICE with a message naming
+// `what` if the stream fails or drains without it, or after a minute.
+int wait_host_tag(const unsigned long long *tag, unsigned long long seq, hipStream_t s, const char *what);
 
 #define MBEM_HIP(call)                                                       \
     do {                                                                     \
