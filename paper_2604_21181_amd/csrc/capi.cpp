@@ -134,6 +134,7 @@ struct Gmres {
     bool trans = false;
     bool lowp = false;          // MIXED: the complex64 copy of the block-Jacobi inverses
     double2 *V, *w, *z, *tmp, *hdev;
+    double2 *W;                 // the products Z z_j of the steps, (m + 1) x N
     double2 *tpart = nullptr;   // partial sums of the transposed product
     double *ndev;
     double2 *hcol;              // the current step's projection coefficients (device)
@@ -201,7 +202,7 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
     const size_t nch = (size_t)arnoldi_chunks(g.N);
     const size_t col = 2 * (size_t)(maxit + 1) + 1;
     const size_t need = (size_t)(maxit + 1) * g.N + 2 * g.N + 4 * op->n2 + (size_t)maxit + 1 + col +
-                        2 * (size_t)(maxit + 1) * nch + nch;
+                        2 * (size_t)(maxit + 1) * nch + nch + 1 + (size_t)(maxit + 1) * g.N;
     mbem_op *mop = const_cast<mbem_op *>(op);
     if (op->work_elems < need) {
         dfree(mop->d_work);
@@ -234,6 +235,7 @@ static int gmres_alloc(Gmres &g, const mbem_op *op, int maxit, hipStream_t s) {
     g.hcol = g.hdev + maxit + 1;
     g.ppart = g.hcol + col;
     g.npart = (double *)(g.ppart + 2 * (size_t)(maxit + 1) * nch);
+    g.W = g.ppart + 2 * (size_t)(maxit + 1) * nch + (nch + 1) / 2 + 1;   // after the nch doubles of npart
     for (int i = 0; i < Gmres::kTimedSteps; ++i) {
         if (!g.ev0[i]) MBEM_HIP(hipEventCreate(&g.ev0[i]));
         if (!g.ev1[i]) MBEM_HIP(hipEventCreate(&g.ev1[i]));
@@ -286,9 +288,10 @@ static int gmres_solve(Gmres &g, const double2 *b, double beta, double tol, doub
         } else {
             MBEM_TRY(mbj_apply_run(g.op, vk, g.z, s, g.trans, g.lowp));
         }
-        MBEM_TRY(g.step_matvec(g.z, g.w, k));
-        MBEM_TRY(arnoldi_cgs2(g.w, g.V, N, k + 1, N, g.ppart, g.npart, g.hcol, !fuse, g.hmap[slot], tag_of(slot),
-                              (unsigned long long)k + 1, s));
+        double2 *wk = g.W + (size_t)k * N;   // Z z_k, kept for the residual of the solution
+        MBEM_TRY(g.step_matvec(g.z, wk, k));
+        MBEM_TRY(arnoldi_cgs2(wk, g.w, g.V, N, k + 1, N, g.ppart, g.npart, g.hcol, !fuse, g.hmap[slot],
+                              tag_of(slot), (unsigned long long)k + 1, s));
         return MBEM_OK;
     };
     double res = 1.0;
@@ -800,11 +803,13 @@ static int solve_impl(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nr
             set_error("right-hand side column " + std::to_string(c) + " is not finite");
             return MBEM_EINVAL;
         }
-    // explicit residual r = b - Z x of column c (FP64 accumulation); returns |r|
-    auto residual = [&](const double2 *bc, const double2 *xc, double *rn) -> int {
-        MBEM_TRY(g.apply(xc, r));
-        MBEM_TRY(vec_scale_copy(r, r, double2{-1.0, 0.0}, N, s));
-        MBEM_TRY(vec_axpy(r, bc, double2{1.0, 0.0}, N, s));
+    // Residual of the solution of the GMRES run just made on right-hand side
+    // rhs with it steps: r = rhs - Z u for its solution u = P^-1 V y, formed
+    // as rhs - sum_j y_j (Z z_j) from the steps' products Z z_j (z_j =
+    // P^-1 V_j; r may be rhs), which are products with the operator, not
+    // the Arnoldi recurrence, in place of one more product.  Returns |r|.
+    auto residual = [&](const double2 *rhs, int it, double *rn) -> int {
+        MBEM_TRY(vec_resid_products(r, rhs, g.W, N, it, g.hdev, N, s));
         MBEM_TRY(vec_norm2(r, N, g.ndev, s));
         MBEM_HIP(hipMemcpyAsync(rn, g.ndev, sizeof(double), hipMemcpyDeviceToHost, s));
         MBEM_HIP(hipStreamSynchronize(s));
@@ -826,7 +831,7 @@ static int solve_impl(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nr
             if (st != MBEM_OK && st != MBEM_ENOCONV) return st;
             total_it += it;
             sweeps += 1;
-            MBEM_TRY(residual(bc, xc, &rn));
+            MBEM_TRY(residual(bc, it, &rn));
             for (int sw = 1; sw < maxref && st == MBEM_OK && bn > 0 && !(rn <= o->tol * bn) &&
                              std::isfinite(rn); ++sw) {
                 st = gmres_solve(g, r, rn, o->tol * bn / rn, d, &it, &est);
@@ -834,7 +839,7 @@ static int solve_impl(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nr
                 total_it += it;
                 sweeps += 1;
                 MBEM_TRY(vec_axpy(xc, d, double2{1.0, 0.0}, N, s));
-                MBEM_TRY(residual(bc, xc, &rn));
+                MBEM_TRY(residual(r, it, &rn));   // r - Z d
             }
         } else {
             // iterative refinement: x += GMRES(Z, b - Z x), residual in FP64.
@@ -853,7 +858,7 @@ static int solve_impl(mbem_ctx *ctx, mbem_op *op, const mbem_c128 *b, int32_t nr
                 total_it += it;
                 sweeps += 1;
                 MBEM_TRY(vec_axpy(xc, d, double2{1.0, 0.0}, N, s));
-                MBEM_TRY(residual(bc, xc, &rn));
+                MBEM_TRY(residual(r, it, &rn));   // r - Z d
             }
         }
         // the iterate is accepted only if its explicit residual meets tol

@@ -1136,20 +1136,20 @@ __global__ __launch_bounds__(kChunkN) void k_cgs_dots(const double2 *V, int64_t 
     chunk_dots(a, b, sp, j0, k, part, nch, c);
 }
 
-// h_j sums part[j][0 .. npin).  DOTS: `next` receives the partial
+// h_j sums part[j][0 .. npin); w = win - V h (win may be w).  DOTS: `next` receives the partial
 // projections of the updated w (the second pass's part, one per chunk);
 // otherwise npart[c] receives the chunk's |w|^2.  hout[j] = h_j is written
 // by workgroup 0.  One workgroup per chunk.
 template <bool DOTS>
-__global__ __launch_bounds__(kChunkN) void k_cgs_update(double2 *w, const double2 *V, int64_t ldv, int k,
-                                                       const double2 *part, int64_t npin, double2 *hout,
-                                                       int64_t n, double2 *next, double *npart) {
+__global__ __launch_bounds__(kChunkN) void k_cgs_update(const double2 *win, double2 *w, const double2 *V,
+                                                       int64_t ldv, int k, const double2 *part, int64_t npin,
+                                                       double2 *hout, int64_t n, double2 *next, double *npart) {
     __shared__ double2 s_h[kRedG];
     __shared__ double2 sp[kDotG * kChunkN];
     const int wv = threadIdx.x / kW, lane = threadIdx.x % kW;
     const int64_t c = blockIdx.x, nch = gridDim.x, i = c * kChunkN + threadIdx.x;
     const bool in = i < n;
-    double2 t = in ? w[i] : double2{0, 0};
+    double2 t = in ? win[i] : double2{0, 0};
     for (int j0 = 0; j0 < k; j0 += kRedG) {
         const int nb = k - j0 < kRedG ? k - j0 : kRedG;
         {   // h_{j0 + jj}, jj = thread / 4: each of four lanes sums every fourth chunk
@@ -1275,6 +1275,16 @@ __global__ __launch_bounds__(256) void k_mbj_scale_apply(int64_t n2, int B, int 
     }
 }
 
+// r[n] = b[n] - sum_j W[j][n] y[j] (r may be b)
+__global__ void k_resid_products(double2 *r, const double2 *b, const double2 *W, int64_t ldw, int k,
+                                 const double2 *y, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 s = b[i];
+    for (int j = 0; j < k; ++j) s = csub(s, cmul(W[(int64_t)j * ldw + i], y[j]));
+    r[i] = s;
+}
+
 // out[n] = sum_j V[j][n] y[j]
 __global__ void k_combine_basis(double2 *out, const double2 *V, int64_t ldv, int k, const double2 *y,
                                 int64_t n) {
@@ -1316,6 +1326,12 @@ int vec_combine(double2 *out, const double2 *V, int64_t ldv, int k, const double
     MBEM_HIP(hipGetLastError());
     return MBEM_OK;
 }
+int vec_resid_products(double2 *r, const double2 *b, const double2 *W, int64_t ldw, int k, const double2 *y,
+                       int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_resid_products, dim3(nblk(n)), dim3(256), 0, s, r, b, W, ldw, k, y, n);
+    MBEM_HIP(hipGetLastError());
+    return MBEM_OK;
+}
 int vec_norm2(const double2 *v, int64_t n, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, s, v, n, out);
     MBEM_HIP(hipGetLastError());
@@ -1327,20 +1343,20 @@ int vec_scale_copy(double2 *dst, const double2 *src, double2 a, int64_t n, hipSt
     return MBEM_OK;
 }
 int64_t arnoldi_chunks(int64_t n) { return (n + kChunkN - 1) / kChunkN; }
-int arnoldi_cgs2(double2 *w, double2 *V, int64_t ldv, int k, int64_t n, double2 *part, double *npart,
-                 double2 *hcol, bool finish, double2 *pin, unsigned long long *tag, unsigned long long seq,
-                 hipStream_t s) {
+int arnoldi_cgs2(const double2 *win, double2 *w, double2 *V, int64_t ldv, int k, int64_t n, double2 *part,
+                 double *npart, double2 *hcol, bool finish, double2 *pin, unsigned long long *tag,
+                 unsigned long long seq, hipStream_t s) {
     if (k < 1 || n < 1) return MBEM_EINVAL;
     const int64_t nch = arnoldi_chunks(n);
     double2 *part2 = part + (int64_t)k * nch;
     hipLaunchKernelGGL(k_cgs_dots, dim3((unsigned)((nch + 7) / 8 * 8), (unsigned)((k + kDotG - 1) / kDotG)),
-                       dim3(kChunkN), 0, s, V, ldv, k, w, n, part, nch);
+                       dim3(kChunkN), 0, s, V, ldv, k, win, n, part, nch);
     MBEM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_cgs_update<true>, dim3((unsigned)nch), dim3(kChunkN), 0, s, w, V, ldv, k, part, nch,
+    hipLaunchKernelGGL(k_cgs_update<true>, dim3((unsigned)nch), dim3(kChunkN), 0, s, win, w, V, ldv, k, part, nch,
                        hcol, n, part2, nullptr);
     MBEM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_cgs_update<false>, dim3((unsigned)nch), dim3(kChunkN), 0, s, w, V, ldv, k, part2, nch,
-                       hcol + k, n, nullptr, npart);
+    hipLaunchKernelGGL(k_cgs_update<false>, dim3((unsigned)nch), dim3(kChunkN), 0, s, (const double2 *)w, w, V, ldv,
+                       k, part2, nch, hcol + k, n, nullptr, npart);
     MBEM_HIP(hipGetLastError());
     if (finish) MBEM_TRY(arnoldi_finish(w, V, ldv, k, n, npart, hcol, pin, tag, seq, s));
     return MBEM_OK;

@@ -318,16 +318,17 @@ int mbj_copy_c64(const double2 *src, float2 **dst, int64_t n, hipStream_t s);
 int mbj_apply_run(const mbem_op *op, const double2 *v, double2 *z,
                   hipStream_t s, bool trans = false, bool lowp = false);
 int vec_norm2(const double2 *v, int64_t n, double *out_dev, hipStream_t s);
-// Classical Gram-Schmidt with one reorthogonalisation of w (n rows)
-// against the k orthonormal columns of V (leading dimension ldv).  The
+// Classical Gram-Schmidt with one reorthogonalisation of win (n rows; the
+// result goes to w, which may be win) against the k orthonormal columns of
+// V (leading dimension ldv).  The
 // coefficients of both passes go to the device column hcol[0..k) = h1,
 // hcol[k..2k) = h2, and the chunks' parts of |w|^2 to npart.  With finish,
 // arnoldi_finish follows.  part: 2 k arnoldi_chunks(n) complex and npart:
 // arnoldi_chunks(n) doubles of device scratch.
 int64_t arnoldi_chunks(int64_t n);
-int arnoldi_cgs2(double2 *w, double2 *V, int64_t ldv, int k, int64_t n, double2 *part, double *npart,
-                 double2 *hcol, bool finish, double2 *pin, unsigned long long *tag, unsigned long long seq,
-                 hipStream_t s);
+int arnoldi_cgs2(const double2 *win, double2 *w, double2 *V, int64_t ldv, int k, int64_t n, double2 *part,
+                 double *npart, double2 *hcol, bool finish, double2 *pin, unsigned long long *tag,
+                 unsigned long long seq, hipStream_t s);
 // V_k = w / |w| (column k of V; 0 when w vanishes), |w| from npart; then
 // the step's column is published to host-mapped memory: pin[0..2k) = hcol,
 // pin[2k].x = |w| and, after a system-scope fence, *tag = seq, so a host
@@ -349,6 +350,10 @@ int vec_axpy(double2 *y, const double2 *x, double2 a, int64_t n,
              hipStream_t s);
 int vec_combine(double2 *out, const double2 *V, int64_t ldv, int k,
                 const double2 *y_dev, int64_t n, hipStream_t s);
+// r = b - sum_{j<k} W_j y_j (columns of W with leading dimension ldw; r may
+// be b)
+int vec_resid_products(double2 *r, const double2 *b, const double2 *W, int64_t ldw, int k, const double2 *y_dev,
+                       int64_t n, hipStream_t s);
 
 // adjoint (adjoint.hip)
 int ff_functional_run(const mbem_mesh *m, const mbem_params *p, const double *rhat, const double2 *e,
