@@ -266,12 +266,19 @@ static int gmres_solve(Gmres &g, const double2 *b, double beta, double tol, doub
         return MBEM_OK;
     }
     const int m = g.m;
+    // The Hessenberg matrix, column-major (column k holds rows 0..k+1),
+    // kept across solves: allocating and zeroing (m + 1) m entries for every
+    // solve, and releasing them, left the stream idle for about 0.1 ms at
+    // each end of a solve; every entry read has been written first.
+    static thread_local std::vector<std::complex<double>> Hbuf;
+    if (Hbuf.size() < (size_t)(m + 1) * m) Hbuf.resize((size_t)(m + 1) * m);
+    std::complex<double> *const H = Hbuf.data();
+    std::vector<std::complex<double>> cs(m), sn(m), gv(m + 1);
+    gv[0] = beta;
     // no tag of an earlier solve may match; no Arnoldi kernel of one is
     // pending (the caller synchronises between solves)
     for (int i = 0; i < 2; ++i) *(unsigned long long *)(g.hpin[i] + 2 * (m + 1) + 1) = 0ull;
     MBEM_TRY(vec_scale_copy(g.V, b, double2{1.0 / beta, 0.0}, N, s));
-    std::vector<std::complex<double>> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1);
-    gv[0] = beta;
     // queue Arnoldi step k; its column lands in hpin[k % 2] with tag k + 1.
     // With a preconditioner the step's normalisation and column run as the
     // first launch of step k + 1 (fused with its block-Jacobi product), or
@@ -303,7 +310,7 @@ static int gmres_solve(Gmres &g, const double2 *b, double beta, double tol, doub
         g.collect(k);
         const double2 *hb = g.hpin[slot];
         const double hn = hb[2 * (k + 1)].x;
-        auto Hc = [&](int i) -> std::complex<double> & { return H[(size_t)i * m + k]; };
+        auto Hc = [&](int i) -> std::complex<double> & { return H[(size_t)k * (m + 1) + i]; };
         for (int i = 0; i <= k; ++i) Hc(i) = C(hb[i]) + C(hb[k + 1 + i]);
         Hc(k + 1) = hn;
         for (int i = 0; i < k; ++i) {
@@ -369,8 +376,8 @@ static int gmres_solve(Gmres &g, const double2 *b, double beta, double tol, doub
     std::vector<std::complex<double>> y(k);
     for (int i = k - 1; i >= 0; --i) {
         std::complex<double> t = gv[i];
-        for (int j = i + 1; j < k; ++j) t -= H[(size_t)i * m + j] * y[j];
-        y[i] = t / H[(size_t)i * m + i];
+        for (int j = i + 1; j < k; ++j) t -= H[(size_t)j * (m + 1) + i] * y[j];
+        y[i] = t / H[(size_t)i * (m + 1) + i];
     }
     // y through pinned memory: no earlier copy from it is pending (the
     // caller synchronises between solves), so the host needs no wait here
