@@ -1645,9 +1645,17 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
     hipEvent_t *ev = f->ev;
     MBEM_HIP(hipEventRecord(ev[6], s));
     const size_t esz = op->prec == MBEM_FP64 ? 16 : 8;
+    // The complex64 regular pairs go by column ranges, unless the previous
+    // fill of this operator found most of them near: a near pair's FP64
+    // evaluation is repeated for every range its trial triangle touches
+    // (about 1.75 times), which made the column-range fill twice as slow as
+    // the chunk kernel on a body whose pairs are 78 % near.
+    const int64_t n_reg = m->nt * m->nt - m->n_spairs;
+    const bool mixed_chunks = op->prec == MBEM_MIXED && !deriv && !paper && !nodal && !op->p.near_store &&
+                              n_reg > 0 && op->n_near > 0.3 * (double)n_reg;
     // the default-scheme fills (FP64 by chunks, complex64 by column ranges)
     // write every entry themselves; the others add to a cleared Z
-    const bool range_fill = !deriv && !paper && !nodal;
+    const bool range_fill = !deriv && !paper && !nodal && !mixed_chunks;
     if (!range_fill)
         for (int o = 0; o < 3; ++o) MBEM_HIP(hipMemsetAsync(op->K[o], 0, esz * op->n2 * op->n2, s));
     f->counted = op->prec != MBEM_FP64 && !deriv && !(op->p.near_store && !paper && !nodal);
@@ -1676,6 +1684,8 @@ int fill_enqueue(mbem_op *op, hipStream_t s, bool deriv, bool geom) {
         MBEM_TRY((launch_regular_range<float, float>(op, 3, m->d_qp32, nullptr, s)));
     } else if (nodal) {
         MBEM_TRY((launch_regular<float, float, false, false, true>(op, 1, m->d_qp32, cnt, s)));
+    } else if (mixed_chunks) {
+        MBEM_TRY((launch_regular<float, float>(op, 1, m->d_qp32, cnt, s)));
     } else {
         MBEM_TRY((launch_regular_range<float, float>(op, 1, m->d_qp32, cnt, s)));
     }
